@@ -1,0 +1,84 @@
+/*
+ * rxo.h -- FP64 CPU oracle of the software-defined receiver's two DSP chains.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or constant generator with the GPU library; the two meet only
+ * at the seeded synthetic inputs.
+ *
+ * Everything is computed in double precision, single-threaded, in the order
+ * the chain is defined (no blocking or fusion beyond what a definition states).
+ */
+#ifndef RXO_H
+#define RXO_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { RXO_PAM2 = 1, RXO_PAM4, RXO_PAM8, RXO_KK_QPSK, RXO_KK_16QAM };
+
+typedef struct {
+  int32_t fmt;           /* RXO_* */
+  int32_t mf_taps;       /* matched RRC length: 33 (PAM, 2 sps) / 65 (KK, 4 sps) */
+  int32_t ffe_taps;      /* T/2-spaced FFE length: 15 (PAM) / 21 (KK) */
+  int32_t prefix;        /* known training/sync symbols at the buffer start */
+  int32_t hilbert_taps;  /* odd: V+1 */
+  int32_t os_log2;       /* FFT size of the oracle's own overlap-save (any >= log2(2V)) */
+  int32_t form;          /* 0: block-parallel DD-LMS FFE; 1: FFE frozen at the prefix taps */
+  int32_t rounding;      /* 0: none; 1: BF16; 2: FP16 operands (MF + FFE, or the MLP) */
+  int32_t equalizer;     /* 0: LMS FFE; 1: MLP (PAM only) */
+  int32_t pad0;
+  double rolloff, mu, mu_cma, fc_over_fs;
+  uint64_t seed;         /* reference sequence: bits of symbol k = top bits of SplitMix64(seed, k) */
+  const double *mlp;     /* RXO_MLP_PARAMS packed parameters when equalizer == 1 */
+} rxo_cfg;
+
+/* Optional outputs: any pointer may be NULL. */
+typedef struct {
+  double *field;     /* KK: reconstructed field E (2*L doubles, re/im) before carrier removal */
+  double *shifted;   /* KK: (E - mean) * exp(-j 2 pi frac(r n)) (2*L doubles) */
+  double *mf;        /* PAM: AGC'd MF output (L); KK: AGC'd decimated MF output (2*(L/2)) */
+  double *timing;    /* PAM: timing shift delta_b in samples per 512-sample block (L/512) */
+  double *xr;        /* PAM: timing-corrected 2-sps samples (L) */
+  double *soft;      /* soft symbols in odd-integer units: PAM nsym, KK 2*nsym (after VV) */
+  double *taps;      /* prefix taps w0 as complex pairs (2*ffe_taps) */
+  double *phase;     /* KK: unwrapped per-block carrier phase (nsym/128) */
+  uint8_t *bits;     /* packed hard decisions, ceil(nsym*bps/8) bytes */
+  double mean_re, mean_im;   /* KK: carrier mean; PAM: mean of v */
+  double agc, theta0;
+  int32_t lag, rot, fallback, pad1;
+  int64_t nsym, nbits, counted_syms, sym_errors, counted_bits, bit_errors;
+} rxo_out;
+
+#define RXO_MLP_IN 31
+#define RXO_MLP_H 64
+#define RXO_MLP_PARAMS (RXO_MLP_H * RXO_MLP_IN + RXO_MLP_H + RXO_MLP_H * RXO_MLP_H + RXO_MLP_H + RXO_MLP_H + 1)
+
+int rxo_process(const rxo_cfg *cfg, const uint8_t *packed, int64_t n_samples, rxo_out *out);
+
+/* building blocks, exported for the pins */
+uint64_t rxo_splitmix64(uint64_t seed, uint64_t k);
+void rxo_unpack12(const uint8_t *in, int64_t n, int32_t *codes);
+void rxo_fft(double *x, int64_t n, int inverse);
+void rxo_rrc_taps(int32_t k, double sps, double beta, double *h);
+void rxo_hilbert_taps(int32_t ntaps, double *h);
+void rxo_fir_same(const double *x, int64_t n, const double *h, int32_t k, double *y);
+void rxo_fir_same_dec2_cplx(const double *x, int64_t n, const double *h, int32_t k, double *y);
+void rxo_hilbert_direct(const double *l, int64_t n, const double *h, int32_t ntaps, double *phi);
+void rxo_hilbert_os(const double *l, int64_t n, const double *h, int32_t ntaps, int32_t log2n, double *phi);
+void rxo_gardner(const double *x, int64_t n, double *delta);
+void rxo_farrow(const double *x, int64_t n, const double *delta, double *xr);
+int32_t rxo_decide(double v, int32_t m_axis);
+double rxo_round_bf16(double v);
+double rxo_round_fp16(double v);
+void rxo_mlp_forward(const double *p, const double *x, int64_t nb, int32_t rounding, double *y);
+double rxo_mlp_grad(const double *p, const double *x, const double *t, int64_t nb, double *g);
+void rxo_adam(double *p, double *m, double *v, const double *g, int64_t n, int64_t step,
+              double lr, double b1, double b2, double eps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
