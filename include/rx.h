@@ -1,0 +1,151 @@
+/*
+ * rx.h -- C ABI of the MI355X receiver library (librx.so).
+ *
+ * The library implements the per-buffer DSP hot path of a software-defined,
+ * GPU-based optical receiver (van der Heide et al., ECOC 2020): a buffer of
+ * 12-bit ADC samples in device memory goes in, hard-decision bits and error
+ * counts come out.  Two chains, selected at create time ("format switching
+ * by updating the GPU software", Sec. 1, second paragraph):
+ *
+ *   - PAM-2/4/8 at 2 samples/symbol: DC removal, matched filter, blockwise
+ *     clock-phase estimation + unwrapping + clock recovery, FFE, decision,
+ *     demapping (Sec. 2, first paragraph);
+ *   - Kramers-Kronig QPSK/16QAM at 4 samples/symbol: sqrt/log, FFT
+ *     Hilbert transform, field recovery and frequency downshift (Fig. 1d),
+ *     filtering and decimation to 2 samples/symbol, adaptive FFE with clock-
+ *     and symbol-phase recovery, decision, demapping (Sec. 2, second
+ *     paragraph).
+ *
+ * Conventions shared by every entry point
+ *   - Return value: 0 on success, a negative RX_E_* code on error, or the
+ *     positive warning RX_W_FALLBACK.  No C++ exception crosses the ABI.
+ *   - Pointers named dev_* are device (HBM) pointers owned by the caller; they
+ *     must stay valid until the handle's stream has passed the enqueued work
+ *     (rx_errors() or a stream synchronisation).  The library owns every
+ *     workspace it allocates and frees it in rx_destroy().
+ *   - Work is enqueued asynchronously on the handle's stream.  Handles are not
+ *     thread-safe: use one handle per host thread.
+ *   - Input layout: n_samples unsigned 12-bit codes, two per three bytes,
+ *     little-endian (byte0 = s0 & 0xFF, byte1 = (s0 >> 8) | ((s1 & 0xF) << 4),
+ *     byte2 = s1 >> 4); n_samples is a multiple of 1024.  Code c is read as
+ *     the photocurrent c + 0.5 (Sec. 2, first paragraph: 2^22 12-bit samples
+ *     per buffer at 4 Gs/s).
+ *   - Output bits: symbol-major, Gray bits MSB-first within a symbol; stream
+ *     bit t lives in byte t >> 3 at bit position t & 7 (LSB first).
+ */
+#ifndef RX_H
+#define RX_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rx_ctx *rx_handle;
+
+typedef enum { RX_PAM2 = 1, RX_PAM4 = 2, RX_PAM8 = 3, RX_KK_QPSK = 4, RX_KK_16QAM = 5 } rx_format;
+typedef enum { RX_FP32 = 0, RX_BF16 = 1, RX_FP16 = 2 } rx_precision;
+typedef enum { RX_EQ_LMS = 0, RX_EQ_MLP = 1 } rx_equalizer;
+
+enum {
+  RX_OK = 0,
+  RX_E_INVALID = -1,      /* bad argument or unsupported size / rate */
+  RX_E_UNSUPPORTED = -2,  /* combination not provided (e.g. MLP on a KK format) */
+  RX_E_NOMEM = -3,        /* device allocation failed */
+  RX_E_HIP = -4,          /* a HIP call failed; rx_strerror() gives the HIP text */
+  RX_E_STATE = -5,        /* call-order violation (e.g. MLP inference before weights) */
+  RX_W_FALLBACK = 1       /* warning: the MLP lost to LMS on the known prefix; LMS ran */
+};
+
+/* Flags */
+#define RX_DEBUG_KEEP 0x1u   /* keep intermediate arrays for rx_debug_fetch() */
+
+typedef struct {
+  uint32_t struct_size;     /* sizeof(rx_params), for ABI evolution */
+  int32_t mf_taps;          /* matched RRC length: 33 (PAM, 2 sps), 65 (KK, 4 sps); odd, <= 65 */
+  int32_t ffe_taps;         /* T/2-spaced FFE length: 15 (PAM), 21 (KK); odd, <= 31 */
+  int32_t prefix_symbols;   /* known training/sync symbols at each buffer start: 4096 */
+  int32_t hilbert_taps;     /* KK Hilbert FIR length V+1: 4097 */
+  int32_t fft_log2;         /* KK overlap-save FFT size: 0 = library choice, else 13 or 14 */
+  int32_t precision;        /* rx_precision: RX_FP32 plain chain; BF16/FP16 precision form (KK) */
+  int32_t equalizer;        /* rx_equalizer (MLP: PAM only) */
+  double rolloff;           /* RRC roll-off: 0.1 */
+  double mu;                /* LMS / DD-LMS step: 1e-3 */
+  double mu_cma;            /* CMA step (KK): 1e-3 */
+  double carrier_hz;        /* KK tone offset, signed: +0.55e9 = signal above the carrier */
+  uint64_t seed;            /* reference sequence: bits of symbol k are the top log2(M) bits
+                               of the k-th SplitMix64 output seeded with `seed` */
+  uint64_t max_samples;     /* largest n_samples a call may pass (sizes the workspace) */
+  void *stream;             /* hipStream_t for all work of this handle; NULL = null stream */
+  uint32_t flags;           /* RX_DEBUG_KEEP */
+  uint32_t reserved;
+} rx_params;
+
+/* Cumulative counters since create / rx_errors_reset.  Symbols counted are
+ * those in [prefix + 64, n_symbols - 64) of each buffer (Sec. 3, second
+ * paragraph: Q-factor estimated from the error rate). */
+typedef struct {
+  uint64_t buffers, symbols, bits, bit_errors, symbol_errors, fallbacks;
+} rx_stats;
+
+/* Debug stages for rx_debug_fetch (the handle needs RX_DEBUG_KEEP for FIELD). */
+enum {
+  RX_STAGE_FIELD = 1,   /* KK: reconstructed field E, float2[n] (needs RX_DEBUG_KEEP) */
+  RX_STAGE_MF = 2,      /* KK: AGC'd decimated MF output float2[n/2]; PAM: AGC'd MF output float[n] */
+  RX_STAGE_XR = 3,      /* PAM: timing-corrected samples float[n] */
+  RX_STAGE_TIMING = 4,  /* PAM: timing shift (samples) per 512-sample block, float[n/512] */
+  RX_STAGE_SOFT = 5,    /* soft symbols after carrier phase (KK float2, PAM float) [n_sym] */
+  RX_STAGE_TAPS = 6,    /* prefix FFE taps w0, float2[ffe_taps] */
+  RX_STAGE_PHASE = 7,   /* KK: unwrapped carrier phase per 128-symbol block, float[n_sym/128] */
+  RX_STAGE_SCALARS = 8  /* double[8]: mean re, mean im, agc, theta0, lag, rot, fallback, 0 */
+};
+
+/* Fill *p with the defaults of `fmt` (values in the comments above).
+ * Returns RX_E_INVALID for an unknown format or NULL p. */
+int rx_params_default(rx_format fmt, rx_params *p);
+
+/* Create a receiver for one format (Sec. 1, second paragraph: the format is
+ * selected in software).  baud/fs must be 2e9/4e9 (PAM) or 1e9/4e9 (KK),
+ * i.e. 2 and 4 samples per symbol.  Designs the filters in FP64 on the host,
+ * rounds them once, allocates the workspace for p->max_samples.
+ * p may be NULL (defaults).  On success *out owns device memory. */
+int rx_create(rx_format fmt, double baud, double fs, const rx_params *p, rx_handle *out);
+
+/* Process one buffer (Fig. 1a: buffer in, bits out).  dev_buffer holds
+ * n_samples packed 12-bit codes (1.5 * n_samples bytes); dev_bits receives
+ * ceil(n_sym * log2(M) / 8) bytes, n_sym = n_samples / sps.  *n_bits_out (may
+ * be NULL) is set on the host without synchronising.  Asynchronous on the
+ * handle's stream.  Errors: RX_E_INVALID if n_samples is not a positive
+ * multiple of 1024, exceeds max_samples, or leaves fewer than prefix + 128
+ * symbols; RX_E_HIP on a launch failure. */
+int rx_process(rx_handle h, const void *dev_buffer, size_t n_samples, void *dev_bits,
+               size_t *n_bits_out);
+
+/* Process `count` buffers (1..64) with distinct handles, mixed formats
+ * allowed, as one batched launch sequence on the FIRST handle's stream (the
+ * paper overlaps 5 buffers on 5 streams, Sec. 2, first paragraph; here all
+ * buffers share every kernel launch).  With graph != 0 the launch sequence
+ * is captured once into a hipGraph per (handles, buffers, sizes) and replayed.
+ * Arguments as for rx_process, one entry per buffer.  Errors: RX_E_INVALID
+ * for count outside 1..64, a repeated handle or handles on different
+ * streams. */
+int rx_process_batch(const rx_handle *hs, const void *const *dev_buffers, const size_t *n_samples,
+                     void *const *dev_bits, int count, int graph);
+
+/* Synchronise the handle's stream and copy the cumulative counters. */
+int rx_errors(rx_handle h, rx_stats *out);
+int rx_errors_reset(rx_handle h);
+
+/* Copy an intermediate array of the most recent buffer to host memory
+ * (synchronises).  bytes must equal the stage's size for that buffer.
+ * RX_E_STATE if nothing was processed or the stage needs RX_DEBUG_KEEP. */
+int rx_debug_fetch(rx_handle h, int stage, void *host_dst, size_t bytes);
+
+void rx_destroy(rx_handle h);
+const char *rx_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

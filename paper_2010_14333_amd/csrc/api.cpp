@@ -1,0 +1,457 @@
+// Host side of librx.so: the C ABI of include/rx.h, filter design in FP64,
+// workspace management and launch sequencing (single buffers, batches and
+// hipGraph replay of batches).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstddef>
+#include <cstring>
+#include <vector>
+
+#include "../../include/rx.h"
+#include "rx_shared.h"
+
+namespace {
+
+thread_local char g_err[256] = "";
+
+int fail_hip(hipError_t e, const char *what) {
+  snprintf(g_err, sizeof(g_err), "%s: %s", what, hipGetErrorString(e));
+  return RX_E_HIP;
+}
+
+bool is_kk(int fmt) { return fmt == RX_KK_QPSK || fmt == RX_KK_16QAM; }
+int bps_of(int fmt) { return fmt == RX_PAM2 ? 1 : fmt == RX_PAM4 ? 2 : fmt == RX_PAM8 ? 3 : fmt == RX_KK_QPSK ? 2 : 4; }
+int axis_levels(int fmt) { return fmt == RX_PAM2 ? 2 : fmt == RX_PAM4 ? 4 : fmt == RX_PAM8 ? 8 : fmt == RX_KK_QPSK ? 2 : 4; }
+
+// ---- FP64 designs, rounded once to FP32 ----------------------------------
+// Root-raised-cosine taps at `sps` samples/symbol, closed form including the
+// limits at t = 0 and |t| = 1/(4 beta), unit energy.
+std::vector<double> design_rrc(int k, double sps, double beta) {
+  std::vector<double> h(k);
+  double e = 0.0;
+  for (int i = 0; i < k; i++) {
+    const double t = (i - 0.5 * (k - 1)) / sps;
+    double v;
+    if (std::fabs(t) < 1e-12) {
+      v = 1.0 - beta + 4.0 * beta / M_PI;
+    } else if (beta > 0 && std::fabs(std::fabs(t) - 0.25 / beta) < 1e-12) {
+      const double a = M_PI / (4.0 * beta);
+      v = beta / std::sqrt(2.0) * ((1.0 + 2.0 / M_PI) * std::sin(a) + (1.0 - 2.0 / M_PI) * std::cos(a));
+    } else {
+      const double q = 4.0 * beta * t;
+      v = (std::sin(M_PI * t * (1.0 - beta)) + q * std::cos(M_PI * t * (1.0 + beta))) / (M_PI * t * (1.0 - q * q));
+    }
+    h[i] = v;
+    e += v * v;
+  }
+  for (auto &v : h) v /= std::sqrt(e);
+  return h;
+}
+
+// Hilbert FIR h(m), |m| <= V/2: (2/(pi m)) Blackman(m) for odd m, else 0;
+// returned for m = 1..V/2 (odd symmetric).  Its N-point DFT is -j S[k] with
+// S[k] = 2 sum_{m>0} h(m) sin(2 pi k m / N).
+std::vector<float> design_hilbert_spectrum(int ntaps, int log2n) {
+  const int v = ntaps - 1, half = v / 2, n = 1 << log2n;
+  std::vector<double> h(half + 1, 0.0);
+  for (int m = 1; m <= half; m += 2) {
+    const double w = 0.42 + 0.5 * std::cos(2.0 * M_PI * m / v) + 0.08 * std::cos(4.0 * M_PI * m / v);
+    h[m] = 2.0 / (M_PI * m) * w;
+  }
+  std::vector<double> sn(n);
+  for (int i = 0; i < n; i++) sn[i] = std::sin(2.0 * M_PI * i / n);
+  std::vector<float> s(n);
+  for (int k = 0; k < n; k++) {
+    double acc = 0.0;
+    for (int m = 1; m <= half; m += 2) acc += h[m] * sn[(int)(((int64_t)k * m) % n)];
+    s[k] = (float)(2.0 * acc / n);
+  }
+  return s;
+}
+
+std::vector<float2> design_twiddles(int log2n) {
+  const int n = 1 << log2n;
+  std::vector<float2> t(n);
+  for (int k = 0; k < n; k++) t[k] = make_float2((float)std::cos(2.0 * M_PI * k / n), (float)-std::sin(2.0 * M_PI * k / n));
+  return t;
+}
+
+struct Alloc {
+  std::vector<void *> ptrs;
+  template <class T>
+  T *get(size_t count) {
+    void *p = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) return nullptr;
+    ptrs.push_back(p);
+    return static_cast<T *>(p);
+  }
+  ~Alloc() {
+    for (void *p : ptrs) hipFree(p);
+  }
+};
+
+struct GraphCache {
+  std::vector<const void *> key;
+  hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
+struct rx_ctx {
+  rx_format fmt;
+  rx_params p;
+  int kk = 0, sps = 2, bps = 1, log2n = 14;
+  hipStream_t stream = nullptr;
+  RxJob hj{};
+  RxJob *dj = nullptr;
+  RxScalars *dsc = nullptr;
+  Alloc mem;
+  int64_t last_n = 0;
+  GraphCache graph;
+};
+
+extern "C" {
+
+int rx_params_default(rx_format fmt, rx_params *p) {
+  if (!p || fmt < RX_PAM2 || fmt > RX_KK_16QAM) return RX_E_INVALID;
+  std::memset(p, 0, sizeof(*p));
+  const bool kk = is_kk(fmt);
+  p->struct_size = sizeof(rx_params);
+  p->mf_taps = kk ? 65 : 33;
+  p->ffe_taps = kk ? 21 : 15;
+  p->prefix_symbols = 4096;
+  p->hilbert_taps = 4097;
+  p->fft_log2 = 0;
+  p->precision = RX_FP32;
+  p->equalizer = RX_EQ_LMS;
+  p->rolloff = 0.1;
+  p->mu = 1e-3;
+  p->mu_cma = 1e-3;
+  p->carrier_hz = kk ? 0.55e9 : 0.0;
+  p->seed = 0;
+  p->max_samples = (uint64_t)1 << 22;
+  p->stream = nullptr;
+  p->flags = 0;
+  return RX_OK;
+}
+
+const char *rx_strerror(int code) {
+  switch (code) {
+    case RX_OK: return "ok";
+    case RX_E_INVALID: return "invalid argument";
+    case RX_E_UNSUPPORTED: return "unsupported configuration";
+    case RX_E_NOMEM: return "device allocation failed";
+    case RX_E_HIP: return g_err[0] ? g_err : "HIP error";
+    case RX_E_STATE: return "call-order violation";
+    case RX_W_FALLBACK: return "warning: LMS fallback used";
+    default: return "unknown status";
+  }
+}
+
+int rx_create(rx_format fmt, double baud, double fs, const rx_params *pin, rx_handle *out) {
+  if (!out) return RX_E_INVALID;
+  *out = nullptr;
+  rx_params p;
+  if (rx_params_default(fmt, &p) != RX_OK) return RX_E_INVALID;
+  if (pin) {
+    if (pin->struct_size != sizeof(rx_params)) return RX_E_INVALID;
+    p = *pin;
+  }
+  const bool kk = is_kk(fmt);
+  const double sps = fs / baud;
+  if (!(baud > 0) || !(fs > 0) || std::fabs(sps - (kk ? 4.0 : 2.0)) > 1e-9) return RX_E_UNSUPPORTED;
+  if (p.mf_taps < 1 || p.mf_taps % 2 == 0 || p.mf_taps > (kk ? 65 : 33)) return RX_E_INVALID;
+  if (p.ffe_taps != 15 && p.ffe_taps != 21) return RX_E_UNSUPPORTED;
+  if (p.prefix_symbols < 2048 || p.prefix_symbols > RX_PREFIX_MAX) return RX_E_INVALID;
+  if (kk && (p.hilbert_taps < 3 || p.hilbert_taps > 4097 || p.hilbert_taps % 2 == 0)) return RX_E_INVALID;
+  if (p.fft_log2 != 0 && p.fft_log2 != 13 && p.fft_log2 != 14) return RX_E_INVALID;
+  if (!(p.rolloff > 0 && p.rolloff <= 1) || !(p.mu > 0) || !(p.mu_cma > 0)) return RX_E_INVALID;
+  if (p.precision != RX_FP32) return RX_E_UNSUPPORTED;
+  if (p.equalizer != RX_EQ_LMS) return RX_E_UNSUPPORTED;
+  if (kk && !(std::fabs(p.carrier_hz) < fs / 2)) return RX_E_INVALID;
+  if (p.max_samples < 65536 || p.max_samples > ((uint64_t)1 << 26) || p.max_samples % 1024) return RX_E_INVALID;
+
+  rx_ctx *h = new rx_ctx();
+  h->fmt = fmt;
+  h->p = p;
+  h->kk = kk;
+  h->sps = kk ? 4 : 2;
+  h->bps = bps_of(fmt);
+  h->log2n = p.fft_log2 ? p.fft_log2 : 14;
+  h->stream = static_cast<hipStream_t>(p.stream);
+  const int64_t L = (int64_t)p.max_samples;
+  Alloc &A = h->mem;
+  RxJob &J = h->hj;
+  J.fmt = fmt;
+  J.kk = kk;
+  J.bps = h->bps;
+  J.m_axis = axis_levels(fmt);
+  J.mf_taps = p.mf_taps;
+  J.ffe_taps = p.ffe_taps;
+  J.prefix = p.prefix_symbols;
+  J.precision = p.precision;
+  J.fft_log2 = h->log2n;
+  J.hop = rx_kk_hop(h->log2n);
+  J.blk = kk ? 128 : 256;
+  J.equalizer = p.equalizer;
+  J.mu = (float)p.mu;
+  J.mu_cma = (float)p.mu_cma;
+  J.r2 = fmt == RX_KK_16QAM ? 1.32f : 1.0f;
+  const int m = J.m_axis;
+  J.ea2_sqrt = (float)std::sqrt((m * m - 1) / 3.0 * (kk ? 2.0 : 1.0));
+  J.r = kk ? p.carrier_hz / fs : 0.0;
+  J.sgn = p.carrier_hz >= 0 ? 1.0f : -1.0f;
+  J.debug = (p.flags & RX_DEBUG_KEEP) ? 1 : 0;
+  J.seed = p.seed;
+
+  // matched filter: KK taps centred in 65 slots (zero padded)
+  std::vector<double> hm = design_rrc(p.mf_taps, h->sps, p.rolloff);
+  const int slots = kk ? 65 : 33;
+  std::vector<float> hf(slots, 0.0f);
+  std::vector<double> hd(slots, 0.0);
+  for (int i = 0; i < p.mf_taps; i++) {
+    hd[(slots - p.mf_taps) / 2 + i] = hm[i];
+    hf[(slots - p.mf_taps) / 2 + i] = (float)hm[i];
+  }
+  float *dmf = A.get<float>(slots);
+  bool ok = dmf != nullptr;
+  if (ok) ok = hipMemcpy(dmf, hf.data(), slots * sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
+  J.mf = dmf;
+  if (kk && ok) {
+    // interior value of MF(exp(-j 2 pi r n)) at n = 2m, divided by exp(-j 2 pi r 2m)
+    std::complex<double> c0 = 0.0;
+    for (int i = 0; i < 65; i++) c0 += (double)hf[i] * std::exp(std::complex<double>(0.0, -2.0 * M_PI * J.r * (32 - i)));
+    J.c0 = make_float2((float)c0.real(), (float)c0.imag());
+    const int n = 1 << h->log2n;
+    std::vector<float> hs = design_hilbert_spectrum(p.hilbert_taps, h->log2n);
+    std::vector<float2> tw = design_twiddles(h->log2n);
+    float *dhs = A.get<float>(n);
+    float2 *dtw = A.get<float2>(n);
+    ok = dhs && dtw && hipMemcpy(dhs, hs.data(), n * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(dtw, tw.data(), n * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess;
+    J.hspec = dhs;
+    J.twid = dtw;
+    const int64_t nd = L / 2;
+    const int hop = J.hop;
+    J.z = A.get<float2>(nd);
+    J.part = A.get<double2>(((L + hop - 1) / hop + 1) / 2 + 1);
+    J.part2 = A.get<double>((nd + 1023) / 1024 + 1);
+    J.soft = A.get<float2>(L / 4);
+    J.s4 = A.get<float2>(L / 4 / 128);
+    J.theta = A.get<float>(L / 4 / 128);
+    J.field = J.debug ? A.get<float2>(L) : nullptr;
+    ok = ok && J.z && J.part && J.part2 && J.soft && J.s4 && J.theta && (!J.debug || J.field);
+  } else if (ok) {
+    J.y = A.get<float>(L);
+    J.xr = A.get<float>(L);
+    J.upart = A.get<uint32_t>(L / 16384 + 1);
+    J.part2 = A.get<double>(L / 4096 + 1);
+    J.gard = A.get<float2>(L / 512);
+    J.delta = A.get<float>(2 * (L / 512));
+    J.soft = A.get<float2>(L / 2);
+    ok = J.y && J.xr && J.upart && J.part2 && J.gard && J.delta && J.soft;
+  }
+  h->dsc = ok ? A.get<RxScalars>(1) : nullptr;
+  h->dj = ok && h->dsc ? A.get<RxJob>(1) : nullptr;
+  if (!h->dj) {
+    delete h;
+    return RX_E_NOMEM;
+  }
+  J.sc = h->dsc;
+  RxScalars zero{};
+  if (hipMemcpy(h->dsc, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h->dj, &J, sizeof(J), hipMemcpyHostToDevice) != hipSuccess) {
+    delete h;
+    return fail_hip(hipGetLastError(), "rx_create upload");
+  }
+  *out = h;
+  return RX_OK;
+}
+
+static int check_n(rx_handle h, size_t n) {
+  if (n == 0 || n % 1024 || n > h->p.max_samples) return RX_E_INVALID;
+  const int64_t nsym = (int64_t)n / h->sps;
+  if (nsym < h->p.prefix_symbols + 2 * RX_GUARD + 128) return RX_E_INVALID;
+  return RX_OK;
+}
+
+// Launch the chains of one batch: jobs grouped by (chain, FFT size, taps).
+static int enqueue(rx_handle const *hs, const void *const *bufs, const size_t *ns, void *const *bits, int count,
+                   hipStream_t s) {
+  bool done[RX_MAXB] = {false};
+  for (int i = 0; i < count; i++) {
+    if (done[i]) continue;
+    RxLaunch L{};
+    int64_t maxn = 0;
+    const rx_ctx *a = hs[i];
+    for (int j = i; j < count; j++) {
+      const rx_ctx *b = hs[j];
+      if (done[j] || b->kk != a->kk || b->log2n != a->log2n || b->p.ffe_taps != a->p.ffe_taps) continue;
+      done[j] = true;
+      L.job[L.count] = b->dj;
+      L.in[L.count] = static_cast<const uint8_t *>(bufs[j]);
+      L.bits[L.count] = static_cast<uint8_t *>(bits[j]);
+      L.n[L.count] = (int64_t)ns[j];
+      L.count++;
+      if ((int64_t)ns[j] > maxn) maxn = (int64_t)ns[j];
+    }
+    if (a->kk) rx_launch_kk(L, maxn, a->log2n, s);
+    else rx_launch_pam(L, maxn, s);
+    rx_launch_tail(L, maxn, a->kk, a->p.ffe_taps, s);
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? RX_OK : fail_hip(e, "kernel launch");
+}
+
+int rx_process(rx_handle h, const void *dev_buffer, size_t n_samples, void *dev_bits, size_t *n_bits_out) {
+  if (!h || !dev_buffer || !dev_bits) return RX_E_INVALID;
+  int rc = check_n(h, n_samples);
+  if (rc) return rc;
+  rc = enqueue(&h, &dev_buffer, &n_samples, &dev_bits, 1, h->stream);
+  if (rc) return rc;
+  h->last_n = (int64_t)n_samples;
+  if (n_bits_out) *n_bits_out = n_samples / h->sps * h->bps;
+  return RX_OK;
+}
+
+int rx_process_batch(const rx_handle *hs, const void *const *bufs, const size_t *ns, void *const *bits, int count,
+                     int graph) {
+  if (!hs || !bufs || !ns || !bits || count < 1 || count > RX_MAXB) return RX_E_INVALID;
+  for (int i = 0; i < count; i++) {
+    if (!hs[i] || !bufs[i] || !bits[i]) return RX_E_INVALID;
+    if (hs[i]->stream != hs[0]->stream) return RX_E_INVALID;
+    for (int j = 0; j < i; j++)
+      if (hs[j] == hs[i]) return RX_E_INVALID;
+    int rc = check_n(hs[i], ns[i]);
+    if (rc) return rc;
+  }
+  hipStream_t s = hs[0]->stream;
+  int rc = RX_OK;
+  if (!graph) {
+    rc = enqueue(hs, bufs, ns, bits, count, s);
+  } else {
+    GraphCache &gc = hs[0]->graph;
+    std::vector<const void *> key;
+    for (int i = 0; i < count; i++) {
+      key.push_back(hs[i]);
+      key.push_back(bufs[i]);
+      key.push_back(bits[i]);
+      key.push_back(reinterpret_cast<const void *>(ns[i]));
+    }
+    if (!gc.exec || gc.key != key) {
+      if (gc.exec) {
+        hipGraphExecDestroy(gc.exec);
+        gc.exec = nullptr;
+      }
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return fail_hip(e, "hipStreamBeginCapture");
+      rc = enqueue(hs, bufs, ns, bits, count, s);
+      e = hipStreamEndCapture(s, &g);
+      if (rc) {
+        if (g) hipGraphDestroy(g);
+        return rc;
+      }
+      if (e != hipSuccess) return fail_hip(e, "hipStreamEndCapture");
+      e = hipGraphInstantiate(&gc.exec, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        gc.exec = nullptr;
+        return fail_hip(e, "hipGraphInstantiate");
+      }
+      gc.key = key;
+    }
+    hipError_t e = hipGraphLaunch(gc.exec, s);
+    if (e != hipSuccess) return fail_hip(e, "hipGraphLaunch");
+  }
+  if (rc == RX_OK)
+    for (int i = 0; i < count; i++) hs[i]->last_n = (int64_t)ns[i];
+  return rc;
+}
+
+int rx_errors(rx_handle h, rx_stats *out) {
+  if (!h || !out) return RX_E_INVALID;
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
+  unsigned long long st[6];
+  e = hipMemcpy(st, h->dsc->stats, sizeof(st), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail_hip(e, "hipMemcpy stats");
+  out->buffers = st[0];
+  out->symbols = st[1];
+  out->bits = st[2];
+  out->bit_errors = st[3];
+  out->symbol_errors = st[4];
+  out->fallbacks = st[5];
+  return RX_OK;
+}
+
+int rx_errors_reset(rx_handle h) {
+  if (!h) return RX_E_INVALID;
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
+  unsigned long long z[6] = {0, 0, 0, 0, 0, 0};
+  e = hipMemcpy(h->dsc->stats, z, sizeof(z), hipMemcpyHostToDevice);
+  return e == hipSuccess ? RX_OK : fail_hip(e, "hipMemcpy stats");
+}
+
+int rx_debug_fetch(rx_handle h, int stage, void *dst, size_t bytes) {
+  if (!h || !dst) return RX_E_INVALID;
+  if (h->last_n == 0) return RX_E_STATE;
+  const int64_t n = h->last_n, nsym = n / h->sps;
+  const RxJob &J = h->hj;
+  const void *src = nullptr;
+  size_t need = 0;
+  std::vector<double> scal;
+  RxScalars sc;
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
+  switch (stage) {
+    case RX_STAGE_FIELD:
+      if (!h->kk) return RX_E_INVALID;
+      if (!J.field) return RX_E_STATE;
+      src = J.field; need = n * sizeof(float2); break;
+    case RX_STAGE_MF:
+      src = h->kk ? (const void *)J.z : (const void *)J.y;
+      need = h->kk ? (n / 2) * sizeof(float2) : n * sizeof(float); break;
+    case RX_STAGE_XR:
+      if (h->kk) return RX_E_INVALID;
+      src = J.xr; need = n * sizeof(float); break;
+    case RX_STAGE_TIMING:
+      if (h->kk) return RX_E_INVALID;
+      src = J.delta; need = (n / 512) * sizeof(float); break;
+    case RX_STAGE_SOFT:
+      if (h->kk && !J.debug) return RX_E_STATE;
+      src = J.soft; need = nsym * sizeof(float2); break;
+    case RX_STAGE_TAPS:
+      src = reinterpret_cast<const char *>(h->dsc) + offsetof(RxScalars, w0);
+      need = h->p.ffe_taps * sizeof(float2); break;
+    case RX_STAGE_PHASE:
+      if (!h->kk) return RX_E_INVALID;
+      src = J.theta; need = (nsym / 128) * sizeof(float); break;
+    case RX_STAGE_SCALARS: {
+      if (bytes != 8 * sizeof(double)) return RX_E_INVALID;
+      e = hipMemcpy(&sc, h->dsc, sizeof(sc), hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return fail_hip(e, "hipMemcpy scalars");
+      double v[8] = {sc.mean_re, sc.mean_im, sc.agc, sc.theta0, (double)sc.lag, (double)sc.rot, (double)sc.fallback, 0.0};
+      std::memcpy(dst, v, sizeof(v));
+      return RX_OK;
+    }
+    default: return RX_E_INVALID;
+  }
+  if (bytes != need) return RX_E_INVALID;
+  e = hipMemcpy(dst, src, need, hipMemcpyDeviceToHost);
+  return e == hipSuccess ? RX_OK : fail_hip(e, "hipMemcpy debug");
+}
+
+void rx_destroy(rx_handle h) {
+  if (!h) return;
+  hipStreamSynchronize(h->stream);
+  if (h->graph.exec) hipGraphExecDestroy(h->graph.exec);
+  delete h;
+}
+
+}  // extern "C"

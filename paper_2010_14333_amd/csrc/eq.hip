@@ -1,0 +1,295 @@
+// Equaliser tail of both chains: prefix adaptation (one wavefront per
+// buffer), block-parallel DD-LMS FFE (one lane per block, Sec. 2, second
+// paragraph: "8192 data blocks per buffer in parallel"), decisions, Gray
+// demapping, bit packing and error counting (Sec. 3, second paragraph).
+#include "rx_dev.hpp"
+
+// Sum over lanes 0..31 of a wavefront, returned in every lane: DPP within
+// rows of 16 (quad swaps, half-row and row mirrors), then two row values.
+#define DPP(v, ctrl) __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xF, 0xF, false))
+__device__ __forceinline__ float tap_sum(float v) {
+  v += DPP(v, 0xB1);    // quad_perm [1,0,3,2]
+  v += DPP(v, 0x4E);    // quad_perm [2,3,0,1]
+  v += DPP(v, 0x141);   // row_half_mirror
+  v += DPP(v, 0x140);   // row_mirror
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0)) +
+         __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+}
+#undef DPP
+
+#define PFX_OFF (2 * RX_LAG + RX_KMAX / 2)
+#define PFX_UL (2 * RX_PREFIX_MAX + 2 * RX_LAG + 2 * PFX_OFF)
+
+// Prefix stage, one workgroup (4 wavefronts) per buffer.
+//  KK : CMA over the prefix (centre-tap start), static Viterbi-Viterbi phase
+//       of the last 2048 CMA outputs, taps rotated and scaled to odd-integer
+//       units;
+//  both: delay search over [-64, 64] symbols on the known prefix (KK also
+//       picks the quadrant), then data-aided LMS over the prefix -> w0.
+__global__ __launch_bounds__(256) void rx_prefix(RxLaunch L) {
+  __shared__ float2 u[PFX_UL];
+  __shared__ float2 zp[RX_PREFIX_MAX + 2 * RX_LAG];
+  __shared__ float2 ar[RX_PREFIX_MAX];
+  __shared__ float2 cs[2 * RX_LAG + 1];
+  __shared__ float2 w[RX_KMAX];
+  __shared__ double red[4];
+  __shared__ int sel[2];
+  __shared__ float th0s;
+
+  const int jb = blockIdx.y;
+  const RxJob &J = *L.job[jb];
+  const int64_t n = L.n[jb];
+  const int kk = J.kk, K = J.ffe_taps, c = (K - 1) / 2, P = J.prefix;
+  const int64_t nx = kk ? n / 2 : n;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+
+  // AGC gain: KK reduces the power partials of the carrier-removal pass;
+  // the PAM samples arrive already scaled.
+  float g = 1.0f;
+  if (kk) {
+    const int64_t nfin = (nx + 1023) / 1024;
+    double p = 0.0;
+    for (int64_t i = threadIdx.x; i < nfin; i += 256) p += J.part2[i];
+    p = block_sum(p, red);
+    const double gd = 1.0 / sqrt(p / (double)nx);
+    g = (float)gd;
+    if (threadIdx.x == 0) J.sc->agc = gd;
+  }
+  for (int idx = threadIdx.x; idx < PFX_UL; idx += 256) {
+    const int64_t j = (int64_t)idx - PFX_OFF;
+    float2 v = make_float2(0.0f, 0.0f);
+    if (j >= 0 && j < nx) v = kk ? cscale(J.z[j], g) : make_float2(J.xr[j], 0.0f);
+    u[idx] = v;
+  }
+  for (int k = threadIdx.x; k < P; k += 256) ar[k] = ref_symbol(J, k);
+  __syncthreads();
+
+  if (wv == 0) {
+    float2 wi = make_float2(0.0f, 0.0f);
+    if (lane == c) wi.x = kk ? 1.0f : J.ea2_sqrt;
+    float th0 = 0.0f;
+    if (kk) {
+      float s4r = 0.0f, s4i = 0.0f;
+      const float r2 = J.r2, mu = J.mu_cma;
+      for (int k = 0; k < P; k++) {
+        const float2 xi = lane < K ? u[PFX_OFF + 2 * k + c - lane] : make_float2(0.0f, 0.0f);
+        const float2 pr = cmul(wi, xi);
+        const float zr = tap_sum(pr.x), zi = tap_sum(pr.y);
+        if (k >= P - 2048) {
+          const float ar2 = zr * zr - zi * zi, ai2 = 2.0f * zr * zi;
+          s4r += ar2 * ar2 - ai2 * ai2;
+          s4i += 2.0f * ar2 * ai2;
+        }
+        const float f = mu * (r2 - (zr * zr + zi * zi));
+        const float2 e = make_float2(zr * f, zi * f);
+        wi = cadd(wi, cmulc(e, xi));
+      }
+      th0 = 0.25f * atan2f(-s4i, -s4r);
+      float sn, cn;
+      sincosf(-th0, &sn, &cn);
+      wi = cscale(cmul(wi, make_float2(cn, sn)), J.ea2_sqrt);
+    }
+    if (lane < RX_KMAX) w[lane] = lane < K ? wi : make_float2(0.0f, 0.0f);
+    if (lane == 0) th0s = th0;
+  }
+  __syncthreads();
+
+  // FFE outputs with the start taps for every candidate delay
+  for (int jj = threadIdx.x; jj < P + 2 * RX_LAG; jj += 256) {
+    const int j = jj - RX_LAG;
+    float2 z = make_float2(0.0f, 0.0f);
+    for (int i = 0; i < K; i++) z = cadd(z, cmul(w[i], u[PFX_OFF + 2 * j + c - i]));
+    zp[jj] = z;
+  }
+  __syncthreads();
+  // correlation with the known prefix, candidates in preference order
+  // s = 0, -1, 1, -2, 2, ...
+  for (int t = wv; t <= 2 * RX_LAG; t += 4) {
+    const int s = (t == 0) ? 0 : ((t & 1) ? -((t + 1) / 2) : t / 2);
+    float cr = 0.0f, ci = 0.0f;
+    for (int k = lane; k < P; k += 64) {
+      const float2 p = cmulc(zp[k + s + RX_LAG], ar[k]);
+      cr += p.x;
+      ci += p.y;
+    }
+    cr = wave_sum(cr);
+    ci = wave_sum(ci);
+    if (lane == 0) cs[t] = make_float2(cr, ci);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float best = -INFINITY;
+    int bt = 0;
+    for (int t = 0; t <= 2 * RX_LAG; t++) {
+      const float2 v = cs[t];
+      const float sc = kk ? (v.x * v.x + v.y * v.y) : v.x;
+      if (sc > best) { best = sc; bt = t; }
+    }
+    const int s = (bt == 0) ? 0 : ((bt & 1) ? -((bt + 1) / 2) : bt / 2);
+    int q = 0;
+    if (kk) {
+      const float2 v = cs[bt];
+      const int qq = (int)lrintf(-atan2f(v.y, v.x) / 1.5707963267948966f);
+      q = ((qq % 4) + 4) % 4;
+    }
+    sel[0] = s;
+    sel[1] = q;
+  }
+  __syncthreads();
+
+  if (wv == 0) {
+    const int s = sel[0], q = sel[1];
+    float2 wi = lane < K ? w[lane] : make_float2(0.0f, 0.0f);
+    const float2 jq = q == 0 ? make_float2(1, 0) : q == 1 ? make_float2(0, 1) : q == 2 ? make_float2(-1, 0) : make_float2(0, -1);
+    wi = cmul(wi, jq);
+    const float mu = J.mu;
+    for (int k = 0; k < P; k++) {
+      const float2 xi = lane < K ? u[PFX_OFF + 2 * (k + s) + c - lane] : make_float2(0.0f, 0.0f);
+      const float2 pr = cmul(wi, xi);
+      const float zr = tap_sum(pr.x), zi = tap_sum(pr.y);
+      const float2 a = ar[k];
+      const float2 e = make_float2(mu * (a.x - zr), mu * (a.y - zi));
+      wi = cadd(wi, cmulc(e, xi));
+    }
+    if (lane < RX_KMAX) J.sc->w0[lane] = lane < K ? wi : make_float2(0.0f, 0.0f);
+    if (lane == 0) {
+      J.sc->lag = s;
+      J.sc->rot = q;
+      J.sc->theta0 = th0s;
+      J.sc->fallback = 0;
+    }
+  }
+}
+
+// Block-parallel DD-LMS: each lane adapts one block of `blk` symbols from w0
+// independently (a decision feedback error cannot leave its block).
+template <bool CPLX, int K>
+__global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
+  const int jb = blockIdx.y;
+  const RxJob &J = *L.job[jb];
+  const int64_t n = L.n[jb];
+  const int64_t nx = CPLX ? n / 2 : n;
+  const int blk = J.blk;
+  const int64_t nsym = n / (CPLX ? 4 : 2);
+  const int64_t nb = nsym / blk;
+  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (b >= nb) return;
+  constexpr int C = (K - 1) / 2;
+  const float mu = J.mu;
+  const int m = J.m_axis;
+  const float g = CPLX ? (float)J.sc->agc : 1.0f;
+  const int s = J.sc->lag;
+  float2 w[K], x[K];
+#pragma unroll
+  for (int i = 0; i < K; i++) w[i] = J.sc->w0[i];
+  const int64_t k0 = b * blk;
+  int64_t p = 2 * (k0 + s);
+  auto load = [&](int64_t j) -> float2 {
+    if (j < 0 || j >= nx) return make_float2(0.0f, 0.0f);
+    if (CPLX) return cscale(J.z[j], g);
+    return make_float2(J.xr[j], 0.0f);
+  };
+#pragma unroll
+  for (int i = 0; i < K; i++) x[i] = load(p + C - i);
+  float s4r = 0.0f, s4i = 0.0f;
+  for (int k = 0; k < blk; k++) {
+    float2 z = make_float2(0.0f, 0.0f);
+    if (CPLX) {
+#pragma unroll
+      for (int i = 0; i < K; i++) z = cadd(z, cmul(w[i], x[i]));
+      const float2 e = make_float2(mu * (decide_level(z.x, m) - z.x), mu * (decide_level(z.y, m) - z.y));
+#pragma unroll
+      for (int i = 0; i < K; i++) w[i] = cadd(w[i], cmulc(e, x[i]));
+      const float a2 = z.x * z.x - z.y * z.y, b2 = 2.0f * z.x * z.y;
+      s4r += a2 * a2 - b2 * b2;
+      s4i += 2.0f * a2 * b2;
+      J.soft[k0 + k] = z;
+    } else {
+#pragma unroll
+      for (int i = 0; i < K; i++) z.x = fmaf(w[i].x, x[i].x, z.x);
+      const float e = mu * (decide_level(z.x, m) - z.x);
+#pragma unroll
+      for (int i = 0; i < K; i++) w[i].x = fmaf(e, x[i].x, w[i].x);
+      J.soft[k0 + k] = z;
+    }
+#pragma unroll
+    for (int i = K - 1; i >= 2; i--) x[i] = x[i - 2];
+    x[0] = load(p + 2 + C);
+    x[1] = load(p + 1 + C);
+    p += 2;
+  }
+  if (CPLX) J.s4[b] = make_float2(s4r, s4i);
+}
+
+// Decisions, Gray demapping, packing and error counting: one thread per 32
+// symbols, i.e. bps whole 32-bit words of the bit stream.
+__global__ __launch_bounds__(256) void rx_decide(RxLaunch L) {
+  const int jb = blockIdx.y;
+  const RxJob &J = *L.job[jb];
+  const int64_t n = L.n[jb];
+  const int kk = J.kk, bps = J.bps, m = J.m_axis, P = J.prefix;
+  const int64_t nsym = n / (kk ? 4 : 2);
+  const int64_t grp = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  unsigned long long cs = 0, se = 0, be = 0;
+  if (grp < nsym / 32) {
+    uint32_t words[4] = {0u, 0u, 0u, 0u};
+    const int half = bps >> 1;
+    for (int e = 0; e < 32; e++) {
+      const int64_t k = grp * 32 + e;
+      float2 z = J.soft[k];
+      uint32_t sym;
+      if (kk) {
+        z = cmul(z, cis_rev(-J.theta[k / J.blk] * 0.15915494309189535f));
+        if (J.debug) J.soft[k] = z;
+        const uint32_t gi = (uint32_t)decide_index(z.x, m), gq = (uint32_t)decide_index(z.y, m);
+        sym = ((gi ^ (gi >> 1)) << half) | (gq ^ (gq >> 1));
+      } else {
+        const uint32_t gi = (uint32_t)decide_index(z.x, m);
+        sym = gi ^ (gi >> 1);
+      }
+      for (int j = 0; j < bps; j++) {
+        const int l = e * bps + j;
+        words[l >> 5] |= ((sym >> (bps - 1 - j)) & 1u) << (l & 31);
+      }
+      if (k >= P + RX_GUARD && k < nsym - RX_GUARD) {
+        const uint32_t ref = (uint32_t)(splitmix64(J.seed, (uint64_t)k) >> (64 - bps));
+        const int ne = __popc(ref ^ sym);
+        cs++;
+        be += ne;
+        se += ne > 0;
+      }
+    }
+    uint32_t *out = reinterpret_cast<uint32_t *>(L.bits[jb]) + grp * bps;
+    for (int i = 0; i < bps; i++) out[i] = words[i];
+  }
+  cs = wave_sum(cs);
+  se = wave_sum(se);
+  be = wave_sum(be);
+  if ((threadIdx.x & 63) == 0 && cs) {
+    atomicAdd(&J.sc->stats[1], cs);
+    atomicAdd(&J.sc->stats[2], cs * (unsigned long long)bps);
+    atomicAdd(&J.sc->stats[3], be);
+    atomicAdd(&J.sc->stats[4], se);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    atomicAdd(&J.sc->stats[0], 1ull);
+    if (J.sc->fallback) atomicAdd(&J.sc->stats[5], 1ull);
+  }
+}
+
+void rx_launch_tail(const RxLaunch &L, int64_t maxn, int kk, int ffe_taps, hipStream_t s) {
+  const unsigned cnt = (unsigned)L.count;
+  hipLaunchKernelGGL(rx_prefix, dim3(1, cnt), dim3(256), 0, s, L);
+  const int64_t nsym = maxn / (kk ? 4 : 2);
+  const int64_t nb = nsym / (kk ? 128 : 256);
+  dim3 gb((unsigned)((nb + 255) / 256), cnt);
+  if (kk) {
+    if (ffe_taps == 21) hipLaunchKernelGGL((rx_blocks<true, 21>), gb, dim3(256), 0, s, L);
+    else hipLaunchKernelGGL((rx_blocks<true, 15>), gb, dim3(256), 0, s, L);
+    rx_launch_kk_vv(L, s);
+  } else {
+    if (ffe_taps == 21) hipLaunchKernelGGL((rx_blocks<false, 21>), gb, dim3(256), 0, s, L);
+    else hipLaunchKernelGGL((rx_blocks<false, 15>), gb, dim3(256), 0, s, L);
+  }
+  hipLaunchKernelGGL(rx_decide, dim3((unsigned)((nsym / 32 + 255) / 256), cnt), dim3(256), 0, s, L);
+}

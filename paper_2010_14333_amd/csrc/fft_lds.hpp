@@ -1,0 +1,131 @@
+// In-LDS complex FFT for one workgroup: Stockham auto-sort, radix-16 passes
+// followed by one radix-2/4/8 pass, N = 16 * blockDim.x.  Each thread holds
+// exactly 16 values per pass: read all, barrier, butterfly, write, barrier,
+// so the transform runs in place in one padded LDS buffer.
+#pragma once
+#include "rx_dev.hpp"
+
+// LDS index with one float2 of padding every 16: stride-16 writes of the
+// first pass then spread over all banks.
+__device__ __forceinline__ int fpad(int p) { return p + (p >> 4); }
+
+__device__ __forceinline__ float2 mul_mj(float2 a) { return make_float2(a.y, -a.x); }  // -j * a
+
+__device__ __forceinline__ void dft2(float2 &a, float2 &b) {
+  const float2 t = a;
+  a = cadd(t, b);
+  b = csub(t, b);
+}
+
+// 4-point forward DFT (kernel exp(-j 2 pi kn/4)), natural order in and out.
+__device__ __forceinline__ void dft4(float2 &x0, float2 &x1, float2 &x2, float2 &x3) {
+  const float2 t0 = cadd(x0, x2), t1 = csub(x0, x2), t2 = cadd(x1, x3), t3 = mul_mj(csub(x1, x3));
+  x0 = cadd(t0, t2);
+  x2 = csub(t0, t2);
+  x1 = cadd(t1, t3);
+  x3 = csub(t1, t3);
+}
+
+// 8-point forward DFT as 2 x 4 (natural order in and out).
+__device__ __forceinline__ void dft8(float2 *v) {
+  const float h = 0.70710678118654752f;
+  float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4(e0, e1, e2, e3);
+  dft4(o0, o1, o2, o3);
+  o1 = make_float2(h * (o1.x + o1.y), h * (o1.y - o1.x));   // * exp(-j pi/4)
+  o2 = mul_mj(o2);                                          // * exp(-j pi/2)
+  o3 = make_float2(h * (o3.y - o3.x), -h * (o3.x + o3.y));  // * exp(-j 3pi/4)
+  v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
+  v[1] = cadd(e1, o1); v[5] = csub(e1, o1);
+  v[2] = cadd(e2, o2); v[6] = csub(e2, o2);
+  v[3] = cadd(e3, o3); v[7] = csub(e3, o3);
+}
+
+// 16-point forward DFT as 4 x 4: X[k1 + 4 k2] = sum_n2 W16^(n2 k1) W4^(n2 k2)
+// sum_n1 x[4 n1 + n2] W4^(n1 k1).
+__device__ __forceinline__ void dft16(float2 *v) {
+  const float c1 = 0.92387953251128674f, s1 = 0.38268343236508977f, h = 0.70710678118654752f;
+  float2 a[16];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; n2++) {
+    float2 x0 = v[n2], x1 = v[4 + n2], x2 = v[8 + n2], x3 = v[12 + n2];
+    dft4(x0, x1, x2, x3);
+    a[n2 * 4 + 0] = x0; a[n2 * 4 + 1] = x1; a[n2 * 4 + 2] = x2; a[n2 * 4 + 3] = x3;
+  }
+  // twiddles W16^(n2 k1): (n2,k1) = (1,1) -pi/8, (1,2) -pi/4, (1,3) -3pi/8,
+  // (2,1) -pi/4, (2,2) -pi/2, (2,3) -3pi/4, (3,1) -3pi/8, (3,2) -3pi/4, (3,3) -9pi/8
+  auto rot = [](float2 x, float c, float s) { return make_float2(x.x * c + x.y * s, x.y * c - x.x * s); };
+  a[5] = rot(a[5], c1, s1);
+  a[6] = rot(a[6], h, h);
+  a[7] = rot(a[7], s1, c1);
+  a[9] = rot(a[9], h, h);
+  a[10] = mul_mj(a[10]);
+  a[11] = rot(a[11], -h, h);
+  a[13] = rot(a[13], s1, c1);
+  a[14] = rot(a[14], -h, h);
+  a[15] = rot(a[15], -c1, -s1);
+#pragma unroll
+  for (int k1 = 0; k1 < 4; k1++) {
+    float2 x0 = a[k1], x1 = a[4 + k1], x2 = a[8 + k1], x3 = a[12 + k1];
+    dft4(x0, x1, x2, x3);
+    v[k1] = x0; v[k1 + 4] = x1; v[k1 + 8] = x2; v[k1 + 12] = x3;
+  }
+}
+
+template <int R>
+__device__ __forceinline__ void dft_r(float2 *v) {
+  if constexpr (R == 16) dft16(v);
+  else if constexpr (R == 8) dft8(v);
+  else if constexpr (R == 4) dft4(v[0], v[1], v[2], v[3]);
+  else dft2(v[0], v[1]);
+}
+
+// One Stockham pass of radix R with Ns = product of the previous radices.
+// Butterfly j reads x[j + r N/R], twiddles by W_{Ns R}^{r (j mod Ns)}, and
+// writes to (j / Ns) Ns R + (j mod Ns) + r Ns.
+template <int N, int R>
+__device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *__restrict__ tw, int ns) {
+  constexpr int T = N / 16;
+  constexpr int NB = (N / R) / T;  // butterflies per thread
+  float2 v[NB][R];
+#pragma unroll
+  for (int b = 0; b < NB; b++) {
+    const int j = threadIdx.x + b * T;
+#pragma unroll
+    for (int r = 0; r < R; r++) v[b][r] = buf[fpad(j + r * (N / R))];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < NB; b++) {
+    const int j = threadIdx.x + b * T;
+    const int k = j & (ns - 1);
+    if (ns > 1) {
+      const int step = k * (N / (ns * R));
+#pragma unroll
+      for (int r = 1; r < R; r++) v[b][r] = cmul(v[b][r], tw[r * step]);
+    }
+    dft_r<R>(v[b]);
+    const int base = (j / ns) * ns * R + k;
+#pragma unroll
+    for (int r = 0; r < R; r++) buf[fpad(base + r * ns)] = v[b][r];
+  }
+  __syncthreads();
+}
+
+// Forward FFT of N = 2^LOGN points held in buf (padded layout), natural
+// order in and out.  tw[k] = exp(-j 2 pi k / N).
+template <int LOGN>
+__device__ __forceinline__ void fft_forward(float2 *buf, const float2 *__restrict__ tw) {
+  constexpr int N = 1 << LOGN;
+  int ns = 1;
+#pragma unroll
+  for (int p = 0; p < LOGN / 4; p++) {
+    stockham_pass<N, 16>(buf, tw, ns);
+    ns *= 16;
+  }
+  constexpr int REM = LOGN % 4;
+  if constexpr (REM == 1) stockham_pass<N, 2>(buf, tw, ns);
+  else if constexpr (REM == 2) stockham_pass<N, 4>(buf, tw, ns);
+  else if constexpr (REM == 3) stockham_pass<N, 8>(buf, tw, ns);
+}

@@ -1,0 +1,259 @@
+// Kramers-Kronig front end for gfx950 (Sec. 2, second paragraph; Fig. 1d).
+//
+// kk_front: one workgroup per pair of overlap-save blocks.  Two real blocks
+// of l = ln(sqrt(v)) share one complex N-point FFT (block A in the real
+// part, block B in the imaginary part: the Hilbert filter is real, so the
+// two stay separate).  The spectrum is multiplied by the Hilbert response,
+// transformed back in LDS, and each sample becomes
+//     E = sqrt(v) exp(j phi),  y' = E exp(-j 2 pi frac(r n))
+// with the downshift phase accumulated in FP64.  The decimating matched
+// filter runs on y' straight from LDS and writes the 2-sample/symbol
+// output; only packed codes come in and half-rate complex samples go out.
+// The carrier mean m is not known inside one workgroup, so the filter runs
+// on y' = y + m exp(-j 2 pi r n) and kk_finalize subtracts m * MF(exp(...))
+// afterwards (the filter is linear).
+#include "fft_lds.hpp"
+
+__device__ __forceinline__ int64_t clamp64(int64_t v, int64_t lo, int64_t hi) {
+  return v < lo ? lo : (v > hi ? hi : v);
+}
+
+// Codes of samples s0 .. s0+7 of a frame, replicated beyond the buffer edges.
+__device__ __forceinline__ void frame_codes8(const uint8_t *in, int64_t n, int64_t s0, int c[8]) {
+  if (s0 >= 0 && s0 + 8 <= n) {
+    read_codes8(in, s0 >> 3, c);
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; e++) c[e] = read_code(in, clamp64(s0 + e, 0, n - 1));
+  }
+}
+
+__device__ __forceinline__ int ypad(int q) { return q + (q >> 5); }
+
+template <int LOGN>
+__global__ __launch_bounds__((1 << LOGN) / 16) void kk_front(RxLaunch L) {
+  constexpr int N = 1 << LOGN, T = N / 16;
+  constexpr int HOP = (N - RX_KK_HALFV - RX_KK_EDGE - RX_KK_CMF) & ~15;
+  constexpr int QN = HOP + 2 * RX_KK_CMF;   // y' samples each block needs
+  constexpr int QPT = (QN + T - 1) / T;
+  constexpr float INV2PI = 0.15915494309189535f;
+  __shared__ float2 lds[N + N / 16];
+  __shared__ double red[T / 64];
+
+  const int jb = blockIdx.y;
+  const RxJob &J = *L.job[jb];
+  const int64_t n = L.n[jb];
+  const uint8_t *in = L.in[jb];
+  const int64_t nrb = (n + HOP - 1) / HOP;
+  const int64_t blk[2] = {2 * (int64_t)blockIdx.x, 2 * (int64_t)blockIdx.x + 1};
+  if (blk[0] >= nrb) return;
+  const int64_t F[2] = {blk[0] * HOP - RX_KK_EDGE, blk[1] * HOP - RX_KK_EDGE};
+
+  // 1. l - l_ref for both frames (l_ref: the frame's centre sample; the
+  //    Hilbert response is zero at DC, so any offset leaves phi unchanged and
+  //    a small one keeps the FP32 transform accurate).
+  const float off0 = 0.5f * __logf((float)read_code(in, clamp64(F[0] + N / 2, 0, n - 1)) + 0.5f);
+  const float off1 = 0.5f * __logf((float)read_code(in, clamp64(F[1] + N / 2, 0, n - 1)) + 0.5f);
+  for (int g = threadIdx.x; g < N / 8; g += T) {
+    int ca[8], cb[8];
+    frame_codes8(in, n, F[0] + 8 * g, ca);
+    frame_codes8(in, n, F[1] + 8 * g, cb);
+#pragma unroll
+    for (int e = 0; e < 8; e++)
+      lds[fpad(8 * g + e)] = make_float2(0.5f * __logf((float)ca[e] + 0.5f) - off0,
+                                         0.5f * __logf((float)cb[e] + 0.5f) - off1);
+  }
+  __syncthreads();
+
+  // 2. Hilbert filtering: Y = Z H, H = -j S; the inverse transform is done as
+  //    conj(FFT(conj(Y)/N)), so the second pass leaves phiA - j phiB.
+  fft_forward<LOGN>(lds, J.twid);
+  for (int k = threadIdx.x; k < N; k += T) {
+    const float2 zv = lds[fpad(k)];
+    const float s = J.hspec[k];
+    lds[fpad(k)] = make_float2(zv.y * s, zv.x * s);
+  }
+  __syncthreads();
+  fft_forward<LOGN>(lds, J.twid);
+
+  float ph[2][QPT];
+#pragma unroll
+  for (int i = 0; i < QPT; i++) {
+    const int q = threadIdx.x + i * T;
+    if (q < QN) {
+      const float2 v = lds[fpad(q + RX_KK_EDGE - RX_KK_CMF)];
+      ph[0][i] = v.x * J.sgn * INV2PI;
+      ph[1][i] = -v.y * J.sgn * INV2PI;
+    }
+  }
+  __syncthreads();
+
+  double se_re = 0.0, se_im = 0.0;
+#pragma unroll
+  for (int x = 0; x < 2; x++) {
+    // 3. field, carrier mean partials, downshifted field y' into LDS
+    const int64_t nq0 = F[x] + RX_KK_EDGE - RX_KK_CMF;   // sample index of q = 0
+#pragma unroll
+    for (int i = 0; i < QPT; i++) {
+      const int q = threadIdx.x + i * T;
+      if (q < QN) {
+        const int64_t t = nq0 + q;
+        float2 yv = make_float2(0.0f, 0.0f);
+        if (t >= 0 && t < n) {
+          const float mag = sqrtf((float)read_code(in, t) + 0.5f);
+          const float u = downshift_rev(J.r, t);
+          yv = cscale(cis_rev(ph[x][i] - u), mag);
+          if (q >= RX_KK_CMF && q < RX_KK_CMF + HOP) {
+            const float2 e = cscale(cis_rev(ph[x][i]), mag);
+            se_re += e.x;
+            se_im += e.y;
+            if (J.field) J.field[t] = e;
+          }
+        }
+        lds[ypad(q)] = yv;
+      }
+    }
+    __syncthreads();
+    // 4. decimating matched filter: Z[m] = sum_i h[i] y'[2m + 32 - i],
+    //    eight consecutive outputs per thread from 79 inputs in registers.
+    const int64_t m0 = blk[x] * (HOP / 2);
+    for (int t8 = threadIdx.x; t8 < HOP / 16; t8 += T) {
+      float2 acc[8];
+#pragma unroll
+      for (int o = 0; o < 8; o++) acc[o] = make_float2(0.0f, 0.0f);
+      // not unrolled over the inputs: an unrolled form keeps too many
+      // taps and inputs live at 1024 threads per workgroup
+#pragma unroll 1
+      for (int d = 0; d < 79; d++) {
+        const float2 v = lds[ypad(16 * t8 + d)];
+#pragma unroll
+        for (int o = 0; o < 8; o++) {
+          const int tap = 2 * o + 64 - d;
+          const float h = (tap >= 0 && tap <= 64) ? J.mf[tap] : 0.0f;
+          acc[o].x = fmaf(h, v.x, acc[o].x);
+          acc[o].y = fmaf(h, v.y, acc[o].y);
+        }
+      }
+#pragma unroll
+      for (int o = 0; o < 8; o++) {
+        const int64_t m = m0 + 8 * t8 + o;
+        if (2 * m < n) J.z[m] = acc[o];
+      }
+    }
+    __syncthreads();
+  }
+  const double sr = block_sum(se_re, red);
+  const double si = block_sum(se_im, red);
+  if (threadIdx.x == 0) J.part[blockIdx.x] = make_double2(sr, si);
+}
+
+// Carrier removal after the filter: u'[m] = Z[m] - mean * MF(exp(-j2 pi r n))[2m].
+// In the interior MF(exp)[2m] = c0 exp(-j 2 pi r 2m); the 16 outputs at each
+// edge sum the in-range taps directly.  Also the partial power sums for AGC.
+__global__ __launch_bounds__(256) void kk_finalize(RxLaunch L) {
+  __shared__ double red[4];
+  const int jb = blockIdx.y;
+  const RxJob &J = *L.job[jb];
+  const int64_t n = L.n[jb], nd = n / 2;
+  const int64_t m0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  if ((int64_t)blockIdx.x * 1024 >= nd) return;
+  const int64_t npairs = ((n + J.hop - 1) / J.hop + 1) / 2;
+  double sr = 0.0, si = 0.0;
+  for (int64_t i = threadIdx.x; i < npairs; i += 256) {
+    sr += J.part[i].x;
+    si += J.part[i].y;
+  }
+  sr = block_sum(sr, red) / (double)n;
+  si = block_sum(si, red) / (double)n;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    J.sc->mean_re = sr;
+    J.sc->mean_im = si;
+  }
+  const float2 mean = make_float2((float)sr, (float)si);
+  double p2 = 0.0;
+#pragma unroll
+  for (int o = 0; o < 4; o++) {
+    const int64_t m = m0 + o;
+    if (m >= nd) break;
+    float2 tc;
+    if (m >= 16 && 2 * m + 32 < n) {
+      tc = cmul(J.c0, cis_rev(-downshift_rev(J.r, 2 * m)));
+    } else {
+      tc = make_float2(0.0f, 0.0f);
+      for (int i = 0; i < 65; i++) {
+        const int64_t t = 2 * m + 32 - i;
+        if (t >= 0 && t < n) tc = cadd(tc, cscale(cis_rev(-downshift_rev(J.r, t)), J.mf[i]));
+      }
+    }
+    const float2 u = csub(J.z[m], cmul(mean, tc));
+    J.z[m] = u;
+    p2 += (double)u.x * u.x + (double)u.y * u.y;
+  }
+  p2 = block_sum(p2, red);
+  if (threadIdx.x == 0) J.part2[blockIdx.x] = p2;
+}
+
+// Viterbi-Viterbi carrier phase per DD-LMS block over blocks b-1..b+1,
+// unwrapped in multiples of pi/2 (wrapped differences, then a workgroup
+// prefix sum), one workgroup per buffer.
+__global__ __launch_bounds__(1024) void kk_vv(RxLaunch L) {
+  __shared__ double scan[1024];
+  const int jb = blockIdx.y;
+  const RxJob &J = *L.job[jb];
+  const int64_t nsym = L.n[jb] / 4;
+  const int nb = (int)(nsym / J.blk);
+  const int per = (nb + 1023) / 1024;
+  const int b0 = threadIdx.x * per;
+  constexpr float Q = 1.5707963267948966f;
+  auto raw = [&](int b) {
+    float2 s = J.s4[b];
+    if (b > 0) s = cadd(s, J.s4[b - 1]);
+    if (b + 1 < nb) s = cadd(s, J.s4[b + 1]);
+    return 0.25f * atan2f(-s.y, -s.x);
+  };
+  auto wrapq = [&](float d) { return d - Q * floorf(d / Q + 0.5f); };
+  double local = 0.0;
+  float prev = (b0 > 0 && b0 < nb) ? raw(b0 - 1) : 0.0f;
+  for (int b = b0; b < b0 + per && b < nb; b++) {
+    const float r = raw(b);
+    local += (b == 0) ? r : wrapq(r - prev);
+    prev = r;
+  }
+  scan[threadIdx.x] = local;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const double v = threadIdx.x >= o ? scan[threadIdx.x - o] : 0.0;
+    __syncthreads();
+    scan[threadIdx.x] += v;
+    __syncthreads();
+  }
+  double th = scan[threadIdx.x] - local;   // exclusive prefix
+  prev = (b0 > 0 && b0 < nb) ? raw(b0 - 1) : 0.0f;
+  for (int b = b0; b < b0 + per && b < nb; b++) {
+    const float r = raw(b);
+    th += (b == 0) ? r : wrapq(r - prev);
+    prev = r;
+    J.theta[b] = (float)th;
+  }
+}
+
+template <int LOGN>
+static void launch_front(const RxLaunch &L, int64_t maxn, hipStream_t s) {
+  constexpr int N = 1 << LOGN;
+  const int hop = rx_kk_hop(LOGN);
+  const int64_t nrb = (maxn + hop - 1) / hop;
+  dim3 grid((unsigned)((nrb + 1) / 2), (unsigned)L.count);
+  hipLaunchKernelGGL(kk_front<LOGN>, grid, dim3(N / 16), 0, s, L);
+}
+
+void rx_launch_kk(const RxLaunch &L, int64_t maxn, int log2n, hipStream_t s) {
+  if (log2n == 13) launch_front<13>(L, maxn, s);
+  else launch_front<14>(L, maxn, s);
+  const int64_t nd = maxn / 2;
+  hipLaunchKernelGGL(kk_finalize, dim3((unsigned)((nd + 1023) / 1024), (unsigned)L.count), dim3(256), 0,
+                     s, L);
+}
+
+void rx_launch_kk_vv(const RxLaunch &L, hipStream_t s) {
+  hipLaunchKernelGGL(kk_vv, dim3(1, (unsigned)L.count), dim3(1024), 0, s, L);
+}

@@ -1,0 +1,220 @@
+// PAM front end for gfx950 (Sec. 2, first paragraph): DC removal, matched
+// filter, blockwise clock-phase estimation, unwrapping and clock recovery.
+#include "rx_dev.hpp"
+
+#define PAM_TS 4096      // matched-filter outputs per workgroup (8 timing blocks)
+#define PAM_SUMW 16384   // samples per code-sum workgroup
+
+// Exact integer sum of the codes (the buffer mean is then exact in FP64).
+__global__ __launch_bounds__(256) void pam_sum(RxLaunch L) {
+  __shared__ uint32_t red[4];
+  const int jb = blockIdx.y;
+  const RxJob &J = *L.job[jb];
+  const int64_t n = L.n[jb];
+  const int64_t base = (int64_t)blockIdx.x * PAM_SUMW;
+  if (base >= n) return;
+  uint32_t s = 0;
+  for (int g = threadIdx.x; g < PAM_SUMW / 8; g += 256) {
+    const int64_t s0 = base + 8 * g;
+    if (s0 + 8 <= n) {
+      int c[8];
+      read_codes8(L.in[jb], s0 >> 3, c);
+#pragma unroll
+      for (int e = 0; e < 8; e++) s += (uint32_t)c[e];
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) J.upart[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__device__ __forceinline__ int xpad(int i) { return i + (i >> 4); }
+
+// x0 = v - mean(v); y = MF(x0) (33 taps, centred, zero outside); partial
+// sums of y^2; Gardner detector sums per 512-sample block on y (the AGC gain
+// does not change the angle of the sums).
+__global__ __launch_bounds__(256) void pam_mf(RxLaunch L) {
+  constexpr int XN = PAM_TS + 40;   // x0 over [t0-20, t0+TS+20)
+  constexpr int YN = PAM_TS + 8;    // y over [t0-4, t0+TS+4)
+  __shared__ float xs[XN + XN / 16 + 1];
+  __shared__ float ys[YN];
+  __shared__ double red[4];
+  __shared__ double mean_s;
+  const int jb = blockIdx.y;
+  const RxJob &J = *L.job[jb];
+  const int64_t n = L.n[jb];
+  const uint8_t *in = L.in[jb];
+  const int64_t t0 = (int64_t)blockIdx.x * PAM_TS;
+  if (t0 >= n) return;
+  {
+    const int64_t np = (n + PAM_SUMW - 1) / PAM_SUMW;
+    unsigned long long s = 0;
+    for (int64_t i = threadIdx.x; i < np; i += 256) s += J.upart[i];
+    s = wave_sum(s);
+    __shared__ unsigned long long rs[4];
+    if ((threadIdx.x & 63) == 0) rs[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const unsigned long long tot = rs[0] + rs[1] + rs[2] + rs[3];
+      mean_s = (double)tot / (double)n + 0.5;
+      if (blockIdx.x == 0) {
+        J.sc->mean_re = mean_s;
+        J.sc->mean_im = 0.0;
+      }
+    }
+    __syncthreads();
+  }
+  const double mv = mean_s;
+  for (int i = threadIdx.x; i < XN; i += 256) {
+    const int64_t t = t0 - 20 + i;
+    xs[xpad(i)] = (t >= 0 && t < n) ? (float)((double)read_code(in, t) + 0.5 - mv) : 0.0f;
+  }
+  __syncthreads();
+  // 16 consecutive outputs per thread: y[t0 + 16 tid + o] from 48 inputs
+  double p2 = 0.0;
+  {
+    float acc[16];
+#pragma unroll
+    for (int o = 0; o < 16; o++) acc[o] = 0.0f;
+    const int ib = 16 * threadIdx.x + 4;
+#pragma unroll
+    for (int d = 0; d < 48; d++) {
+      const float v = xs[xpad(ib + d)];
+#pragma unroll
+      for (int o = 0; o < 16; o++) {
+        const int tap = o + 32 - d;
+        if (tap >= 0 && tap <= 32) acc[o] = fmaf(J.mf[tap], v, acc[o]);
+      }
+    }
+#pragma unroll
+    for (int o = 0; o < 16; o++) {
+      const int64_t t = t0 + 16 * threadIdx.x + o;
+      const float yv = (t < n) ? acc[o] : 0.0f;
+      ys[16 * threadIdx.x + o + 4] = yv;
+      if (t < n) {
+        J.y[t] = yv;
+        p2 += (double)yv * yv;
+      }
+    }
+  }
+  if (threadIdx.x < 8) {   // the 4 outputs either side of the tile
+    const int l = threadIdx.x < 4 ? (int)threadIdx.x - 4 : PAM_TS + (int)threadIdx.x - 4;
+    const int64_t t = t0 + l;
+    float a = 0.0f;
+    for (int i = 0; i < 33; i++) a = fmaf(J.mf[i], xs[xpad(l + 36 - i)], a);
+    ys[l + 4] = (t >= 0 && t < n) ? a : 0.0f;
+  }
+  p2 = block_sum(p2, red);
+  if (threadIdx.x == 0) J.part2[blockIdx.x] = p2;
+  __syncthreads();
+  // Gardner sums: 8 blocks of 256 symbols, 32 threads x 8 symbols each.
+  const int bl = threadIdx.x >> 5, sub = threadIdx.x & 31;
+  float g0 = 0.0f, g1 = 0.0f;
+  for (int e = 0; e < 8; e++) {
+    const int s = 2 * (256 * bl + 8 * sub + e) + 4;   // ys index of the symbol sample
+    const float y0 = ys[s], y1 = ys[s + 1], y2 = ys[s + 2];
+    g0 += y1 * (y0 - y2);
+    const float ym = ys[s - 1], y3 = ys[s + 3], y4 = ys[s + 4];
+    const float h0 = (-ym + 9.0f * y0 + 9.0f * y1 - y2) * 0.0625f;
+    const float h1 = (-y0 + 9.0f * y1 + 9.0f * y2 - y3) * 0.0625f;
+    const float h2 = (-y1 + 9.0f * y2 + 9.0f * y3 - y4) * 0.0625f;
+    g1 += h1 * (h0 - h2);
+  }
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) {
+    g0 += __shfl_xor(g0, o, 32);
+    g1 += __shfl_xor(g1, o, 32);
+  }
+  const int64_t gb = t0 / 512 + bl;
+  if (sub == 0 && gb * 512 < n) J.gard[gb] = make_float2(g0, g1);
+}
+
+// Angle of the detector sums averaged over blocks b-16 .. b+16.
+__global__ __launch_bounds__(256) void pam_gavg(RxLaunch L) {
+  const int jb = blockIdx.y;
+  const RxJob &J = *L.job[jb];
+  const int64_t nb = L.n[jb] / 512;
+  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (b >= nb) return;
+  double re = 0.0, im = 0.0;
+  const int64_t lo = b - 16 < 0 ? 0 : b - 16, hi = b + 16 >= nb ? nb - 1 : b + 16;
+  for (int64_t j = lo; j <= hi; j++) {
+    re += J.gard[j].x;
+    im += J.gard[j].y;
+  }
+  J.delta[nb + b] = (float)atan2(im, re);   // raw angle, second half of the array
+}
+
+// Unwrap (wrapped differences + workgroup prefix sum), timing shift
+// delta_b = 1/2 + psi_b / pi samples, and the AGC gain.
+__global__ __launch_bounds__(1024) void pam_unwrap(RxLaunch L) {
+  __shared__ double scan[1024];
+  __shared__ double red[16];
+  const int jb = blockIdx.y;
+  const RxJob &J = *L.job[jb];
+  const int64_t n = L.n[jb];
+  const int nb = (int)(n / 512);
+  const float *raw = J.delta + nb;
+  {
+    const int64_t np = (n + PAM_TS - 1) / PAM_TS;
+    double p = 0.0;
+    for (int64_t i = threadIdx.x; i < np; i += 1024) p += J.part2[i];
+    p = block_sum(p, red);
+    if (threadIdx.x == 0) J.sc->agc = 1.0 / sqrt(p / (double)n);
+  }
+  const int per = (nb + 1023) / 1024;
+  const int b0 = threadIdx.x * per;
+  constexpr double TWO_PI = 6.283185307179586;
+  auto wrap = [&](double d) { return d - TWO_PI * floor(d / TWO_PI + 0.5); };
+  double local = 0.0;
+  for (int b = b0; b < b0 + per && b < nb; b++) local += (b == 0) ? raw[0] : wrap((double)raw[b] - raw[b - 1]);
+  scan[threadIdx.x] = local;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const double v = threadIdx.x >= o ? scan[threadIdx.x - o] : 0.0;
+    __syncthreads();
+    scan[threadIdx.x] += v;
+    __syncthreads();
+  }
+  double acc = scan[threadIdx.x] - local;   // exclusive prefix
+  // raw angles live in the second half of the array, shifts in the first
+  for (int b = b0; b < b0 + per && b < nb; b++) {
+    acc += (b == 0) ? raw[0] : wrap((double)raw[b] - raw[b - 1]);
+    J.delta[b] = (float)(0.5 + acc / 3.141592653589793);
+  }
+}
+
+// Cubic-Lagrange (Farrow) interpolation with the AGC gain:
+// xr[t] = g * y(t + delta_b), t in block b.
+__global__ __launch_bounds__(256) void pam_farrow(RxLaunch L) {
+  const int jb = blockIdx.y;
+  const RxJob &J = *L.job[jb];
+  const int64_t n = L.n[jb];
+  const float g = (float)J.sc->agc;
+  const int64_t t00 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  for (int o = 0; o < 4; o++) {
+    const int64_t t = t00 + o;
+    if (t >= n) return;
+    const float d = J.delta[t / 512];
+    const float fl = floorf(d), mu = d - fl;
+    const int64_t i0 = t + (int64_t)fl;
+    const float lm1 = -mu * (mu - 1.0f) * (mu - 2.0f) * (1.0f / 6.0f);
+    const float l0 = (mu + 1.0f) * (mu - 1.0f) * (mu - 2.0f) * 0.5f;
+    const float l1 = -(mu + 1.0f) * mu * (mu - 2.0f) * 0.5f;
+    const float l2 = (mu + 1.0f) * mu * (mu - 1.0f) * (1.0f / 6.0f);
+    auto yat = [&](int64_t j) { return (j >= 0 && j < n) ? J.y[j] : 0.0f; };
+    J.xr[t] = g * (lm1 * yat(i0 - 1) + l0 * yat(i0) + l1 * yat(i0 + 1) + l2 * yat(i0 + 2));
+  }
+}
+
+void rx_launch_pam(const RxLaunch &L, int64_t maxn, hipStream_t s) {
+  const unsigned cnt = (unsigned)L.count;
+  hipLaunchKernelGGL(pam_sum, dim3((unsigned)((maxn + PAM_SUMW - 1) / PAM_SUMW), cnt), dim3(256), 0, s, L);
+  hipLaunchKernelGGL(pam_mf, dim3((unsigned)((maxn + PAM_TS - 1) / PAM_TS), cnt), dim3(256), 0, s, L);
+  const int64_t nb = maxn / 512;
+  hipLaunchKernelGGL(pam_gavg, dim3((unsigned)((nb + 255) / 256), cnt), dim3(256), 0, s, L);
+  hipLaunchKernelGGL(pam_unwrap, dim3(1, cnt), dim3(1024), 0, s, L);
+  hipLaunchKernelGGL(pam_farrow, dim3((unsigned)((maxn + 1023) / 1024), cnt), dim3(256), 0, s, L);
+}

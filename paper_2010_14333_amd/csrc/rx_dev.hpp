@@ -1,0 +1,116 @@
+// Device helpers for the gfx950 receiver kernels (wave64).
+#pragma once
+#include "rx_shared.h"
+
+#define RX_WAVE 64
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {  // a * conj(b)
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// ---- wave / workgroup reductions ---------------------------------------
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, RX_WAVE);
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, RX_WAVE);
+  return v;
+}
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, RX_WAVE);
+  return v;
+}
+
+// Sum of a double over the workgroup; every thread gets the result.
+// `scratch` holds at least blockDim.x / 64 doubles.
+__device__ __forceinline__ double block_sum(double v, double *scratch) {
+  v = wave_sum(v);
+  const int w = threadIdx.x / RX_WAVE, nw = blockDim.x / RX_WAVE;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) scratch[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < nw; i++) s += scratch[i];
+  __syncthreads();
+  return s;
+}
+
+// ---- reference sequence (SplitMix64, Steele, Lea & Flood 2014) -----------
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint32_t gray_inverse(uint32_t g) {
+  uint32_t i = g;
+  for (uint32_t s = g >> 1; s; s >>= 1) i ^= s;
+  return i;
+}
+
+// Transmitted symbol k in odd-integer units (QAM: I bits first).
+__device__ __forceinline__ float2 ref_symbol(const RxJob &J, int64_t k) {
+  const uint32_t b = (uint32_t)(splitmix64(J.seed, (uint64_t)k) >> (64 - J.bps));
+  const int m = J.m_axis;
+  if (J.kk) {
+    const int half = J.bps >> 1;
+    const uint32_t bi = b >> half, bq = b & (uint32_t)(m - 1);
+    return make_float2((float)(2 * (int)gray_inverse(bi) - (m - 1)),
+                       (float)(2 * (int)gray_inverse(bq) - (m - 1)));
+  }
+  return make_float2((float)(2 * (int)gray_inverse(b) - (m - 1)), 0.0f);
+}
+
+// ---- decisions: levels 2i-(M-1), thresholds at even integers, tie -> up ---
+__device__ __forceinline__ int decide_index(float v, int m) {
+  float f = floorf((v + (float)m) * 0.5f);
+  f = fminf(fmaxf(f, 0.0f), (float)(m - 1));
+  return (int)f;
+}
+__device__ __forceinline__ float decide_level(float v, int m) {
+  return (float)(2 * decide_index(v, m) - (m - 1));
+}
+
+// ---- 12-bit packed input -------------------------------------------------
+// Code of sample i (any i in range), from the three bytes holding its pair.
+__device__ __forceinline__ int read_code(const uint8_t *in, int64_t i) {
+  const uint8_t *b = in + 3 * (i >> 1);
+  return (i & 1) ? ((int)(b[1] >> 4) | ((int)b[2] << 4)) : ((int)b[0] | ((int)(b[1] & 0x0F) << 8));
+}
+
+// Eight codes of samples 8g .. 8g+7 from three aligned 32-bit words.
+__device__ __forceinline__ void read_codes8(const uint8_t *in, int64_t g, int c[8]) {
+  const uint32_t *p = reinterpret_cast<const uint32_t *>(in + 12 * g);
+  const uint32_t w0 = p[0], w1 = p[1], w2 = p[2];
+  c[0] = w0 & 0xFFF;
+  c[1] = (w0 >> 12) & 0xFFF;
+  c[2] = (w0 >> 24) | ((w1 & 0xF) << 8);
+  c[3] = (w1 >> 4) & 0xFFF;
+  c[4] = (w1 >> 16) & 0xFFF;
+  c[5] = (w1 >> 28) | ((w2 & 0xFF) << 4);
+  c[6] = (w2 >> 8) & 0xFFF;
+  c[7] = w2 >> 20;
+}
+
+// exp(-j 2 pi frac(r n)) with the phase accumulator in FP64.
+__device__ __forceinline__ float downshift_rev(double r, int64_t n) {
+  double u = r * (double)n;
+  u -= floor(u);
+  return (float)u;
+}
+// exp(+j 2 pi rev) from the hardware sine/cosine, whose argument is in
+// revolutions (valid for |rev| < 256).
+__device__ __forceinline__ float2 cis_rev(float rev) {
+  return make_float2(__builtin_amdgcn_cosf(rev), __builtin_amdgcn_sinf(rev));
+}

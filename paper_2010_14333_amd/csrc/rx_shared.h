@@ -1,0 +1,76 @@
+// Declarations shared by the host library and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define RX_MAXB 64          // buffers per batched launch
+#define RX_PREFIX_MAX 4096  // longest known prefix the prefix kernel holds in LDS
+#define RX_GUARD 64         // symbols excluded at each end of the error-count window
+#define RX_LAG 64           // delay search range [-RX_LAG, RX_LAG] symbols
+#define RX_KMAX 32          // tap storage per handle
+
+// Per-buffer scalars written by the kernels (device memory, one per handle).
+struct RxScalars {
+  double mean_re, mean_im;  // KK carrier mean / PAM mean of v
+  double agc;               // unit-power gain
+  double theta0;            // static carrier phase of the CMA taps (KK)
+  int32_t lag, rot, fallback, pad;
+  float2 w0[RX_KMAX];       // prefix FFE taps
+  unsigned long long stats[6];  // buffers, symbols, bits, bit errors, symbol errors, fallbacks
+};
+
+// Everything a kernel needs about one handle (device memory, written once).
+struct RxJob {
+  int32_t fmt, kk, bps, m_axis;     // format, KK flag, bits/symbol, levels per real axis
+  int32_t mf_taps, ffe_taps, prefix, precision;
+  int32_t fft_log2, hop, blk, equalizer;  // KK OS geometry, DD-LMS block length
+  float mu, mu_cma, r2, ea2_sqrt;   // steps, CMA radius, sqrt(E|a|^2)
+  double r;                         // carrier offset / fs (signed)
+  float sgn;                        // Hilbert sign (+1: signal above the carrier)
+  int32_t debug;                    // keep derotated soft symbols
+  uint64_t seed;
+  float2 c0;                        // interior value of MF(exp(-j 2 pi r n)) / exp(-j 2 pi r 2m)
+  const float *mf;                  // matched filter taps (65 centred for KK, 33 for PAM)
+  const float *hspec;               // KK: Hilbert spectrum S[k]/N (H = -j S), N entries
+  const float2 *twid;               // KK: exp(-j 2 pi k / N), N entries
+  float2 *z;                        // KK: MF output / carrier-free field at 2 sps [n/2]
+  float *y;                         // PAM: MF output [n]
+  float *xr;                        // PAM: timing-corrected samples [n]
+  double2 *part;                    // per-workgroup partial sums (stage 1)
+  double *part2;                    // per-workgroup partial sums (stage 2)
+  uint32_t *upart;                  // PAM code-sum partials
+  float2 *gard;                     // PAM: Gardner sums per 512-sample block
+  float *delta;                     // PAM: timing shift per block (samples)
+  float2 *soft;                     // soft symbols (PAM uses .x)
+  float2 *s4;                       // KK: sum z^4 per DD-LMS block
+  float *theta;                     // KK: carrier phase per block
+  float2 *field;                    // KK debug: reconstructed field [n] or null
+  RxScalars *sc;
+};
+
+// By-value launch description of one batch (kernel argument, < 4 KiB).
+struct RxLaunch {
+  const RxJob *job[RX_MAXB];
+  const uint8_t *in[RX_MAXB];
+  uint8_t *bits[RX_MAXB];
+  int64_t n[RX_MAXB];
+  int32_t count;
+  int32_t pad;
+};
+
+// KK overlap-save geometry: a frame of N samples starts RX_KK_EDGE samples
+// before its hop, the Hilbert FIR reaches 2048 samples either side and the
+// matched filter 32 more; hop is what remains, rounded down to 16 samples.
+#define RX_KK_HALFV 2048
+#define RX_KK_CMF 32
+#define RX_KK_EDGE 2080
+static inline int rx_kk_hop(int log2n) {
+  int h = (1 << log2n) - RX_KK_HALFV - RX_KK_EDGE - RX_KK_CMF;
+  return h & ~15;
+}
+
+// Host-side launchers (defined with their kernels).
+void rx_launch_kk(const RxLaunch &L, int64_t maxn, int log2n, hipStream_t s);
+void rx_launch_pam(const RxLaunch &L, int64_t maxn, hipStream_t s);
+void rx_launch_tail(const RxLaunch &L, int64_t maxn, int kk, int ffe_taps, hipStream_t s);
+void rx_launch_kk_vv(const RxLaunch &L, hipStream_t s);

@@ -1,0 +1,143 @@
+"""HIP path vs FP64 oracle, element by element, through the C ABI.
+
+Bars: reconstructed KK field relative RMS <= 1e-5; decisions bit-exact except
+symbols within 1e-3 (odd-integer level units) of a threshold in the oracle
+(plus the DD-LMS cascade rule of parity.compare_decisions); error counts
+differ by at most the tolerated bits; integer results (delay, quadrant)
+exact."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import parity
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2010_14333_amd as rx
+    rx.lib()
+    return rx
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(rx, fmt, g, n, debug=True, **over):
+    import torch
+    dev = torch.device("cuda:0")
+    r = rx.Receiver(fmt, g["seed"], max_samples=max(n, 1 << 16), debug=debug, **over)
+    buf = torch.from_numpy(g["packed"]).to(dev)
+    bits = r.process(buf, n)
+    torch.cuda.synchronize()
+    out = {"bits": bits.cpu().numpy(), "err": r.errors(), "r": r}
+    return out
+
+
+def check_chain(rx, fmt, n, seed, snr, **gen):
+    _log(f"[parity] fmt={fmt} n={n} seed={seed} snr={snr} {gen}")
+    g = synth.generate(fmt, n, seed, snr, **gen)
+    kk = fmt >= 4
+    want = ("bits", "soft", "taps", "mf") + (("field",) if kk else ("timing", "xr"))
+    o = oracle.process(fmt, g["packed"], n, g["seed"], want=want)
+    res = run_gpu(rx, fmt, g, n)
+    r = res["r"]
+    sc = r.fetch(rx.RX_STAGE_SCALARS, n)
+    report = {}
+    if kk:
+        field = r.fetch(rx.RX_STAGE_FIELD, n)
+        report["field"] = parity.rel_rms(field, o["field"])
+        assert report["field"] <= 1e-5, report
+        mf = r.fetch(rx.RX_STAGE_MF, n) * sc[2]
+        report["mf"] = parity.rel_rms(mf, o["mf"])
+        assert report["mf"] <= 2e-5, report
+        assert abs(complex(sc[0], sc[1]) - complex(o["mean_re"], o["mean_im"])) <= 1e-5 * abs(
+            complex(o["mean_re"], o["mean_im"]))
+    else:
+        mf = r.fetch(rx.RX_STAGE_MF, n) * sc[2]
+        report["mf"] = parity.rel_rms(mf, o["mf"])
+        assert report["mf"] <= 1e-5, report
+        d = r.fetch(rx.RX_STAGE_TIMING, n)
+        report["timing"] = float(np.max(np.abs(d - o["timing"])))
+        assert report["timing"] <= 2e-4, report
+        xr = r.fetch(rx.RX_STAGE_XR, n)
+        report["xr"] = parity.rel_rms(xr, o["xr"])
+        assert report["xr"] <= 1e-4, report
+        assert sc[0] == pytest.approx(o["mean_re"], rel=1e-15)
+    assert int(sc[4]) == o["lag"] and int(sc[5]) == o["rot"], (sc, o["lag"], o["rot"])
+    taps = r.fetch(rx.RX_STAGE_TAPS, n)
+    report["taps"] = parity.rel_rms(taps, o["taps"])
+    assert report["taps"] <= 1e-3, report
+    nsym = n // (4 if kk else 2)
+    blk = 128 if kk else 256
+    nbad, tol_bits, untol = parity.compare_decisions(fmt, res["bits"], o["bits"], o["soft"], nsym, blk)
+    report.update(mismatch=nbad, tolerated_bits=tol_bits, bit_errors=(res["err"]["bit_errors"], o["bit_errors"]))
+    _log(f"[parity]   {report}")
+    assert not untol, (untol[:10], report)
+    e = res["err"]
+    assert e["buffers"] == 1 and e["symbols"] == o["counted_syms"] and e["bits"] == o["counted_bits"]
+    assert abs(e["bit_errors"] - o["bit_errors"]) <= tol_bits
+    r.close()
+    return report
+
+
+SMALL = [
+    (5, 1 << 18, 11, 22.0, {}),
+    (5, 1 << 18, 12, 16.0, {}),
+    (4, 1 << 18, 13, 22.0, {}),
+    (4, 1 << 18, 14, None, {"theta_c": 2.0}),
+    (2, 1 << 18, 21, 20.0, {}),
+    (1, 1 << 18, 22, 16.0, {}),
+    (3, 1 << 18, 23, 24.0, {}),
+    (3, 1 << 18, 24, None, {"drive": 0.1}),
+]
+
+
+@pytest.mark.parametrize("fmt,n,seed,snr,gen", SMALL)
+def test_parity_small(rx, fmt, n, seed, snr, gen):
+    check_chain(rx, fmt, n, seed, snr, **gen)
+
+
+@pytest.mark.parametrize("fmt,n,seed,snr", [
+    (5, (1 << 18) + 3 * 1024, 31, 22.0),   # ragged: not a multiple of the OS hop or block pair
+    (2, (1 << 18) + 5 * 1024, 32, 20.0),
+    (5, 17408, 33, 22.0),                  # smallest buffer the KK chain accepts
+    (2, 9216, 34, 20.0),                   # smallest PAM buffer
+])
+def test_parity_ragged_and_minimum(rx, fmt, n, seed, snr):
+    check_chain(rx, fmt, n, seed, snr)
+
+
+def test_parity_kk16qam_full_buffer(rx):
+    """KK-16QAM, one 2^22-sample buffer, CSPR 10 dB, 22 dB SNR."""
+    g = synth.kk_2e22(synth.KK_16QAM)
+    check_chain(rx, 5, 1 << 22, g["seed"], 22.0)
+
+
+def test_parity_kkqpsk_full_buffer(rx):
+    g = synth.kk_2e22(synth.KK_QPSK)
+    check_chain(rx, 4, 1 << 22, g["seed"], 22.0)
+
+
+def test_parity_pam4_2e20(rx):
+    """PAM-4, one 2^20-sample buffer at 20 dB SNR."""
+    check_chain(rx, 2, 1 << 20, synth.derive_seed(101, 0), 20.0)
+
+
+def test_invalid_sizes_rejected(rx):
+    import torch
+    r = rx.Receiver(5, 1, max_samples=1 << 18)
+    buf = torch.zeros(3 << 17, dtype=torch.uint8, device="cuda:0")
+    out = torch.zeros(1 << 16, dtype=torch.uint8, device="cuda:0")
+    for n in (1000, (1 << 18) + 1024, 0, 16384):
+        with pytest.raises(rx.RxError):
+            rx.rx_process(r.h, buf.data_ptr(), n, out.data_ptr())
+    r.close()
