@@ -1,0 +1,150 @@
+#!/usr/bin/env python3
+"""Sustained throughput of the KK-16QAM receiver chain on one MI355X.
+
+One step = one batched pass of the whole KK chain (unpack .. error count)
+over `--batch` buffers of 2^22 packed 12-bit samples (KK-16QAM, 1 GBaud,
+CSPR 10 dB, 22 dB SNR; `--distinct` seeded buffers, reused round-robin by
+distinct receiver handles), inputs resident in HBM.  Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N = 1 << 22
+# Algorithmic work per input sample of the fused KK front end (two complex
+# N-point FFTs per 2*hop samples at 5 N log2 N flop, Hilbert product, 65-tap
+# decimating matched filter on complex samples = 130 flop), and its bytes.
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_VALU_TFLOPS = 78.6   # 256 CU x 64 FMA/clk x 2 x 2.4 GHz (no packed FP32)
+
+
+def front_flop_per_sample(log2n):
+    n = 1 << log2n
+    hop = (n - 2048 - 2080 - 32) & ~15
+    return (5.0 * n * log2n + 2.0 * n) / hop + 130.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--distinct", type=int, default=8)
+    ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--cpu-buffers", type=int, default=8)
+    ap.add_argument("--copy-probe", type=int, default=1, help="run a 256 MiB device copy (counter scale)")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the receiver path is "
+              "single-GPU in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2010_14333_amd as rx
+    import synth
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    gens = [synth.kk_2e22(synth.KK_16QAM, index=i) for i in range(a.distinct)]
+    log(f"[bench] generated {a.distinct} KK-16QAM buffers in {time.time() - t0:.1f}s")
+    bufs = [torch.from_numpy(g["packed"]).to(dev) for g in gens]
+    recs = [rx.Receiver(rx.RX_KK_16QAM, gens[i % a.distinct]["seed"], max_samples=N,
+                        flags=rx.RX_PROFILE if i == 0 else 0) for i in range(a.batch)]
+    outs = [torch.empty(r.bits_bytes(N), dtype=torch.uint8, device=dev) for r in recs]
+    hs = [r.h for r in recs]
+    bp = [bufs[i % a.distinct].data_ptr() for i in range(a.batch)]
+    op = [o.data_ptr() for o in outs]
+    ns = [N] * a.batch
+
+    def step():
+        rx.rx_process_batch(hs, bp, ns, op, graph=bool(a.graph))
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    rx.rx_stage_times(hs[0], reset=True)
+    for r in recs:
+        r.reset()
+    log(f"[bench] warmup done ({a.warmup} steps x {a.batch} buffers)")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(a.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    log(f"[bench] timed {a.steps} steps in {wall:.3f}s")
+    stages = rx.rx_stage_times(hs[0])
+    errs = [r.errors() for r in recs]
+    bits = sum(e["bits"] for e in errs)
+    berr = sum(e["bit_errors"] for e in errs)
+
+    ms_step = wall * 1e3 / a.steps
+    samples = a.batch * N
+    gsps = samples / (ms_step * 1e-3) / 1e9
+
+    # dominant kernel: the stage with the largest total time
+    dom = max(stages, key=lambda k: stages[k][0])
+    dom_ms = stages[dom][0] / stages[dom][1]
+    per_stage_us_per_buffer = {k: round(v[0] / v[1] * 1e3 / a.batch, 3) for k, v in stages.items()}
+    if dom == "kk_front":
+        flop = front_flop_per_sample(14) * samples
+        achieved = flop / (dom_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_FP32_VALU_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4), "traffic": None,
+                "kernel": "kk_front<14>", "flop_per_sample": round(front_flop_per_sample(14), 2)}
+    else:
+        roof = {"bound": "latency", "achieved": None, "peak": None, "unit": None, "frac": None,
+                "traffic": None, "kernel": dom}
+
+    if a.copy_probe:
+        src = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    cpu = None
+    if a.cpu_buffers > 0:
+        import oracle
+        t2 = time.perf_counter()
+        k = min(a.cpu_buffers, a.distinct)
+        for g in gens[:k]:
+            oracle.process(synth.KK_16QAM, g["packed"], N, g["seed"], want=("bits",))
+        ct = time.perf_counter() - t2
+        cpu = {"value": round(k * N / ct / 1e9, 5), "unit": "Gsamples/s", "cores": 1, "kind": "oracle",
+               "sample": f"{k} x 2^22-sample KK-16QAM buffers (22 dB), FP64 oracle, one thread, "
+                         f"{ct:.1f} s"}
+        log(f"[bench] cpu baseline {cpu['value']} Gs/s")
+
+    out = {
+        "metric": "sustained Gsamples/s for KK-16QAM chain, plain vs BF16/MLP at matched BER",
+        "value": round(gsps, 3), "unit": "Gsamples/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "KK-16QAM receiver chain, plain FP32, 2^22-sample 12-bit buffers "
+                               "at 4 Gs/s (1 GBaud, CSPR 10 dB, 22 dB SNR)",
+                   "buffers_per_step": a.batch, "samples_per_buffer": N, "graph": bool(a.graph)},
+        "realtime_factor": round(gsps / 4.0, 2),
+        "ber": berr / bits if bits else None,
+        "stage_us_per_buffer": per_stage_us_per_buffer,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    for r in recs:
+        r.close()
+
+
+if __name__ == "__main__":
+    main()

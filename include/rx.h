@@ -60,6 +60,23 @@ enum {
 
 /* Flags */
 #define RX_DEBUG_KEEP 0x1u   /* keep intermediate arrays for rx_debug_fetch() */
+#define RX_PROFILE 0x2u      /* time every kernel stage with HIP events (see rx_stage_times) */
+
+/* Kernel stages reported by rx_stage_times (index into its arrays). */
+enum {
+  RX_ST_KK_FRONT = 0,   /* unpack, ln, FFT Hilbert, field, FP64 downshift, decimating MF */
+  RX_ST_KK_FINALIZE,    /* carrier removal after the filter, power partials */
+  RX_ST_PAM_SUM,        /* exact code sum (DC) */
+  RX_ST_PAM_MF,         /* DC removal, matched filter, timing-detector sums */
+  RX_ST_PAM_GAVG,       /* timing-detector averaging and angle */
+  RX_ST_PAM_UNWRAP,     /* timing unwrap, AGC gain */
+  RX_ST_PAM_FARROW,     /* cubic interpolation onto the recovered clock */
+  RX_ST_PREFIX,         /* (CMA,) delay search, LMS training on the known prefix */
+  RX_ST_BLOCKS,         /* block-parallel DD-LMS FFE */
+  RX_ST_KK_VV,          /* Viterbi-Viterbi block phase, unwrap */
+  RX_ST_DECIDE,         /* decisions, demapping, packing, error counting */
+  RX_NSTAGES
+};
 
 typedef struct {
   uint32_t struct_size;     /* sizeof(rx_params), for ABI evolution */
@@ -141,6 +158,13 @@ int rx_errors_reset(rx_handle h);
  * (synchronises).  bytes must equal the stage's size for that buffer.
  * RX_E_STATE if nothing was processed or the stage needs RX_DEBUG_KEEP. */
 int rx_debug_fetch(rx_handle h, int stage, void *host_dst, size_t bytes);
+
+/* Stage timing of handles created with RX_PROFILE: synchronises the stream
+ * and returns, per stage, the accumulated milliseconds and launch count of
+ * every launch this handle led (it was the first handle of its batch) since
+ * the last reset.  ms == NULL resets.  Returns RX_NSTAGES.  Graph replays are
+ * not timed. */
+int rx_stage_times(rx_handle h, double *ms, uint64_t *launches, int max_stages);
 
 void rx_destroy(rx_handle h);
 const char *rx_strerror(int code);

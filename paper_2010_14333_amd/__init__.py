@@ -23,8 +23,11 @@ RX_DEBUG_KEEP = 0x1
 (RX_STAGE_FIELD, RX_STAGE_MF, RX_STAGE_XR, RX_STAGE_TIMING, RX_STAGE_SOFT, RX_STAGE_TAPS,
  RX_STAGE_PHASE, RX_STAGE_SCALARS) = range(1, 9)
 
+RX_PROFILE = 0x2
+STAGES = ("kk_front", "kk_finalize", "pam_sum", "pam_mf", "pam_gavg", "pam_unwrap", "pam_farrow",
+          "prefix", "blocks", "kk_vv", "decide")
 EXPORTS = ("rx_params_default", "rx_create", "rx_process", "rx_process_batch", "rx_errors",
-           "rx_errors_reset", "rx_debug_fetch", "rx_destroy", "rx_strerror")
+           "rx_errors_reset", "rx_debug_fetch", "rx_stage_times", "rx_destroy", "rx_strerror")
 
 
 class rx_params(ctypes.Structure):
@@ -68,6 +71,8 @@ def lib() -> ctypes.CDLL:
         L.rx_errors.argtypes = [vp, ctypes.POINTER(rx_stats)]
         L.rx_errors_reset.argtypes = [vp]
         L.rx_debug_fetch.argtypes = [vp, i32, vp, sz]
+        L.rx_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_uint64), i32]
         L.rx_destroy.argtypes = [vp]
         L.rx_destroy.restype = None
         L.rx_strerror.argtypes = [i32]
@@ -131,6 +136,18 @@ def rx_debug_fetch(h: int, stage: int, nbytes: int) -> bytes:
     buf = ctypes.create_string_buffer(nbytes)
     _check(lib().rx_debug_fetch(h, stage, buf, nbytes), "rx_debug_fetch")
     return buf.raw
+
+
+def rx_stage_times(h: int, reset: bool = False) -> dict:
+    """{stage name: (total ms, launches)} since the last reset."""
+    n = len(STAGES)
+    if reset:
+        _check(lib().rx_stage_times(h, None, None, n), "rx_stage_times")
+        return {}
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_uint64 * n)()
+    _check(lib().rx_stage_times(h, ms, cnt, n), "rx_stage_times")
+    return {STAGES[i]: (ms[i], cnt[i]) for i in range(n) if cnt[i]}
 
 
 def rx_destroy(h: int) -> None:

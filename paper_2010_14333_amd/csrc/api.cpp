@@ -112,6 +112,26 @@ struct rx_ctx {
   Alloc mem;
   int64_t last_n = 0;
   GraphCache graph;
+  // stage timing (RX_PROFILE): events recorded around every stage launch
+  struct Pending { int stage; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  double stage_ms[ST_COUNT] = {0};
+  uint64_t stage_n[ST_COUNT] = {0};
+  hipEvent_t event() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    hipEventCreate(&e);
+    return e;
+  }
+  ~rx_ctx() {
+    for (auto &p : pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
+    for (auto e : pool) hipEventDestroy(e);
+  }
 };
 
 extern "C" {
@@ -279,10 +299,17 @@ static int check_n(rx_handle h, size_t n) {
   return RX_OK;
 }
 
-// Launch the chains of one batch: jobs grouped by (chain, FFT size, taps).
+static const int KK_STAGES[] = {ST_KK_FRONT, ST_KK_FINALIZE, ST_PREFIX, ST_BLOCKS, ST_KK_VV, ST_DECIDE};
+static const int PAM_STAGES[] = {ST_PAM_SUM, ST_PAM_MF, ST_PAM_GAVG, ST_PAM_UNWRAP, ST_PAM_FARROW,
+                                 ST_PREFIX, ST_BLOCKS, ST_DECIDE};
+
+// Launch the chains of one batch: jobs grouped by (chain, FFT size, taps),
+// each group one launch per stage.  With RX_PROFILE on the first handle
+// (and not under graph capture) every stage is bracketed by events.
 static int enqueue(rx_handle const *hs, const void *const *bufs, const size_t *ns, void *const *bits, int count,
-                   hipStream_t s) {
+                   hipStream_t s, bool capturing) {
   bool done[RX_MAXB] = {false};
+  rx_ctx *prof = (!capturing && (hs[0]->p.flags & RX_PROFILE)) ? hs[0] : nullptr;
   for (int i = 0; i < count; i++) {
     if (done[i]) continue;
     RxLaunch L{};
@@ -299,9 +326,26 @@ static int enqueue(rx_handle const *hs, const void *const *bufs, const size_t *n
       L.count++;
       if ((int64_t)ns[j] > maxn) maxn = (int64_t)ns[j];
     }
-    if (a->kk) rx_launch_kk(L, maxn, a->log2n, s);
-    else rx_launch_pam(L, maxn, s);
-    rx_launch_tail(L, maxn, a->kk, a->p.ffe_taps, s);
+    const int *st = a->kk ? KK_STAGES : PAM_STAGES;
+    const int nst = a->kk ? 6 : 8;
+    for (int k = 0; k < nst; k++) {
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (prof) {
+        e0 = prof->event();
+        hipEventRecord(e0, s);
+      }
+      if (st[k] == ST_KK_FRONT || st[k] == ST_KK_FINALIZE || st[k] == ST_KK_VV)
+        rx_launch_kk_stage(st[k], L, maxn, a->log2n, s);
+      else if (st[k] >= ST_PAM_SUM && st[k] <= ST_PAM_FARROW)
+        rx_launch_pam_stage(st[k], L, maxn, s);
+      else
+        rx_launch_eq_stage(st[k], L, maxn, a->kk, a->p.ffe_taps, s);
+      if (prof) {
+        e1 = prof->event();
+        hipEventRecord(e1, s);
+        prof->pending.push_back({st[k], e0, e1});
+      }
+    }
   }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? RX_OK : fail_hip(e, "kernel launch");
@@ -311,7 +355,7 @@ int rx_process(rx_handle h, const void *dev_buffer, size_t n_samples, void *dev_
   if (!h || !dev_buffer || !dev_bits) return RX_E_INVALID;
   int rc = check_n(h, n_samples);
   if (rc) return rc;
-  rc = enqueue(&h, &dev_buffer, &n_samples, &dev_bits, 1, h->stream);
+  rc = enqueue(&h, &dev_buffer, &n_samples, &dev_bits, 1, h->stream, false);
   if (rc) return rc;
   h->last_n = (int64_t)n_samples;
   if (n_bits_out) *n_bits_out = n_samples / h->sps * h->bps;
@@ -332,7 +376,7 @@ int rx_process_batch(const rx_handle *hs, const void *const *bufs, const size_t 
   hipStream_t s = hs[0]->stream;
   int rc = RX_OK;
   if (!graph) {
-    rc = enqueue(hs, bufs, ns, bits, count, s);
+    rc = enqueue(hs, bufs, ns, bits, count, s, false);
   } else {
     GraphCache &gc = hs[0]->graph;
     std::vector<const void *> key;
@@ -350,7 +394,7 @@ int rx_process_batch(const rx_handle *hs, const void *const *bufs, const size_t 
       hipGraph_t g = nullptr;
       hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) return fail_hip(e, "hipStreamBeginCapture");
-      rc = enqueue(hs, bufs, ns, bits, count, s);
+      rc = enqueue(hs, bufs, ns, bits, count, s, true);
       e = hipStreamEndCapture(s, &g);
       if (rc) {
         if (g) hipGraphDestroy(g);
@@ -445,6 +489,31 @@ int rx_debug_fetch(rx_handle h, int stage, void *dst, size_t bytes) {
   if (bytes != need) return RX_E_INVALID;
   e = hipMemcpy(dst, src, need, hipMemcpyDeviceToHost);
   return e == hipSuccess ? RX_OK : fail_hip(e, "hipMemcpy debug");
+}
+
+int rx_stage_times(rx_handle h, double *ms, uint64_t *launches, int max_stages) {
+  if (!h || max_stages < 0) return RX_E_INVALID;
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
+  for (auto &p : h->pending) {
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
+      h->stage_ms[p.stage] += t;
+      h->stage_n[p.stage] += 1;
+    }
+    h->pool.push_back(p.a);
+    h->pool.push_back(p.b);
+  }
+  h->pending.clear();
+  if (!ms) {
+    for (int i = 0; i < ST_COUNT; i++) { h->stage_ms[i] = 0.0; h->stage_n[i] = 0; }
+    return ST_COUNT;
+  }
+  for (int i = 0; i < ST_COUNT && i < max_stages; i++) {
+    ms[i] = h->stage_ms[i];
+    if (launches) launches[i] = h->stage_n[i];
+  }
+  return ST_COUNT;
 }
 
 void rx_destroy(rx_handle h) {

@@ -37,7 +37,7 @@ __global__ __launch_bounds__(256) void rx_prefix(RxLaunch L) {
   __shared__ float th0s;
 
   const int jb = blockIdx.y;
-  const RxJob &J = *L.job[jb];
+  const RxJob J = *L.job[jb];
   const int64_t n = L.n[jb];
   const int kk = J.kk, K = J.ffe_taps, c = (K - 1) / 2, P = J.prefix;
   const int64_t nx = kk ? n / 2 : n;
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(256) void rx_prefix(RxLaunch L) {
 template <bool CPLX, int K>
 __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
   const int jb = blockIdx.y;
-  const RxJob &J = *L.job[jb];
+  const RxJob J = *L.job[jb];
   const int64_t n = L.n[jb];
   const int64_t nx = CPLX ? n / 2 : n;
   const int blk = J.blk;
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
 // symbols, i.e. bps whole 32-bit words of the bit stream.
 __global__ __launch_bounds__(256) void rx_decide(RxLaunch L) {
   const int jb = blockIdx.y;
-  const RxJob &J = *L.job[jb];
+  const RxJob J = *L.job[jb];
   const int64_t n = L.n[jb];
   const int kk = J.kk, bps = J.bps, m = J.m_axis, P = J.prefix;
   const int64_t nsym = n / (kk ? 4 : 2);
@@ -277,19 +277,22 @@ __global__ __launch_bounds__(256) void rx_decide(RxLaunch L) {
   }
 }
 
-void rx_launch_tail(const RxLaunch &L, int64_t maxn, int kk, int ffe_taps, hipStream_t s) {
+void rx_launch_eq_stage(int stage, const RxLaunch &L, int64_t maxn, int kk, int ffe_taps, hipStream_t s) {
   const unsigned cnt = (unsigned)L.count;
-  hipLaunchKernelGGL(rx_prefix, dim3(1, cnt), dim3(256), 0, s, L);
   const int64_t nsym = maxn / (kk ? 4 : 2);
-  const int64_t nb = nsym / (kk ? 128 : 256);
-  dim3 gb((unsigned)((nb + 255) / 256), cnt);
-  if (kk) {
-    if (ffe_taps == 21) hipLaunchKernelGGL((rx_blocks<true, 21>), gb, dim3(256), 0, s, L);
-    else hipLaunchKernelGGL((rx_blocks<true, 15>), gb, dim3(256), 0, s, L);
-    rx_launch_kk_vv(L, s);
-  } else {
-    if (ffe_taps == 21) hipLaunchKernelGGL((rx_blocks<false, 21>), gb, dim3(256), 0, s, L);
-    else hipLaunchKernelGGL((rx_blocks<false, 15>), gb, dim3(256), 0, s, L);
+  if (stage == ST_PREFIX) {
+    hipLaunchKernelGGL(rx_prefix, dim3(1, cnt), dim3(256), 0, s, L);
+  } else if (stage == ST_BLOCKS) {
+    const int64_t nb = nsym / (kk ? 128 : 256);
+    dim3 gb((unsigned)((nb + 255) / 256), cnt);
+    if (kk) {
+      if (ffe_taps == 21) hipLaunchKernelGGL((rx_blocks<true, 21>), gb, dim3(256), 0, s, L);
+      else hipLaunchKernelGGL((rx_blocks<true, 15>), gb, dim3(256), 0, s, L);
+    } else {
+      if (ffe_taps == 21) hipLaunchKernelGGL((rx_blocks<false, 21>), gb, dim3(256), 0, s, L);
+      else hipLaunchKernelGGL((rx_blocks<false, 15>), gb, dim3(256), 0, s, L);
+    }
+  } else if (stage == ST_DECIDE) {
+    hipLaunchKernelGGL(rx_decide, dim3((unsigned)((nsym / 32 + 255) / 256), cnt), dim3(256), 0, s, L);
   }
-  hipLaunchKernelGGL(rx_decide, dim3((unsigned)((nsym / 32 + 255) / 256), cnt), dim3(256), 0, s, L);
 }

@@ -81,11 +81,33 @@ __device__ __forceinline__ void dft_r(float2 *v) {
   else dft2(v[0], v[1]);
 }
 
-// One Stockham pass of radix R with Ns = product of the previous radices.
-// Butterfly j reads x[j + r N/R], twiddles by W_{Ns R}^{r (j mod Ns)}, and
-// writes to (j / Ns) Ns R + (j mod Ns) + r Ns.
-template <int N, int R>
-__device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *__restrict__ tw, int ns) {
+// Twiddle W^r (r < 16) from the table powers W, W^2, W^4, W^8: at most three
+// products deep, so the error stays a few ulp.
+template <int r>
+__device__ __forceinline__ float2 twid_pow(float2 w1, float2 w2, float2 w4, float2 w8) {
+  float2 w = make_float2(1.0f, 0.0f);
+  bool first = true;
+  if constexpr ((r & 1) != 0) { w = w1; first = false; }
+  if constexpr ((r & 2) != 0) { w = first ? w2 : cmul(w, w2); first = false; }
+  if constexpr ((r & 4) != 0) { w = first ? w4 : cmul(w, w4); first = false; }
+  if constexpr ((r & 8) != 0) { w = first ? w8 : cmul(w, w8); }
+  return w;
+}
+
+template <int R, int I>
+__device__ __forceinline__ void apply_twiddles(float2 *v, float2 w1, float2 w2, float2 w4, float2 w8) {
+  if constexpr (I < R) {
+    v[I] = cmul(v[I], twid_pow<I>(w1, w2, w4, w8));
+    apply_twiddles<R, I + 1>(v, w1, w2, w4, w8);
+  }
+}
+
+// One Stockham pass of radix R with NS = product of the previous radices.
+// Butterfly j reads x[j + r N/R], twiddles by W_{NS R}^{r (j mod NS)}, and
+// writes to (j / NS) NS R + (j mod NS) + r NS.  NS is a compile-time
+// constant so the padded LDS offsets of the 16 accesses fold to immediates.
+template <int N, int R, int NS>
+__device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *__restrict__ tw) {
   constexpr int T = N / 16;
   constexpr int NB = (N / R) / T;  // butterflies per thread
   float2 v[NB][R];
@@ -99,33 +121,40 @@ __device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *__restr
 #pragma unroll
   for (int b = 0; b < NB; b++) {
     const int j = threadIdx.x + b * T;
-    const int k = j & (ns - 1);
-    if (ns > 1) {
-      const int step = k * (N / (ns * R));
-#pragma unroll
-      for (int r = 1; r < R; r++) v[b][r] = cmul(v[b][r], tw[r * step]);
+    const int k = j & (NS - 1);
+    if constexpr (NS > 1) {
+      const int step = k * (N / (NS * R));
+      const float2 w1 = tw[step];
+      const float2 w2 = R > 2 ? tw[2 * step] : w1;
+      const float2 w4 = R > 4 ? tw[4 * step] : w1;
+      const float2 w8 = R > 8 ? tw[8 * step] : w1;
+      apply_twiddles<R, 1>(v[b], w1, w2, w4, w8);
     }
     dft_r<R>(v[b]);
-    const int base = (j / ns) * ns * R + k;
+    const int base = (j / NS) * NS * R + k;
 #pragma unroll
-    for (int r = 0; r < R; r++) buf[fpad(base + r * ns)] = v[b][r];
+    for (int r = 0; r < R; r++) buf[fpad(base + r * NS)] = v[b][r];
   }
   __syncthreads();
+}
+
+template <int N, int NS>
+__device__ __forceinline__ void fft_passes(float2 *buf, const float2 *__restrict__ tw) {
+  if constexpr (NS * 16 <= N) {
+    stockham_pass<N, 16, NS>(buf, tw);
+    fft_passes<N, NS * 16>(buf, tw);
+  } else if constexpr (NS * 8 == N) {
+    stockham_pass<N, 8, NS>(buf, tw);
+  } else if constexpr (NS * 4 == N) {
+    stockham_pass<N, 4, NS>(buf, tw);
+  } else if constexpr (NS * 2 == N) {
+    stockham_pass<N, 2, NS>(buf, tw);
+  }
 }
 
 // Forward FFT of N = 2^LOGN points held in buf (padded layout), natural
 // order in and out.  tw[k] = exp(-j 2 pi k / N).
 template <int LOGN>
 __device__ __forceinline__ void fft_forward(float2 *buf, const float2 *__restrict__ tw) {
-  constexpr int N = 1 << LOGN;
-  int ns = 1;
-#pragma unroll
-  for (int p = 0; p < LOGN / 4; p++) {
-    stockham_pass<N, 16>(buf, tw, ns);
-    ns *= 16;
-  }
-  constexpr int REM = LOGN % 4;
-  if constexpr (REM == 1) stockham_pass<N, 2>(buf, tw, ns);
-  else if constexpr (REM == 2) stockham_pass<N, 4>(buf, tw, ns);
-  else if constexpr (REM == 3) stockham_pass<N, 8>(buf, tw, ns);
+  fft_passes<(1 << LOGN), 1>(buf, tw);
 }

@@ -39,15 +39,22 @@ __global__ __launch_bounds__((1 << LOGN) / 16) void kk_front(RxLaunch L) {
   constexpr float INV2PI = 0.15915494309189535f;
   __shared__ float2 lds[N + N / 16];
   __shared__ double red[T / 64];
+  __shared__ float hev[48], hod[48];   // h[2q], h[2q-1] at index q+8, zero outside the filter
 
   const int jb = blockIdx.y;
-  const RxJob &J = *L.job[jb];
+  const RxJob J = *L.job[jb];
   const int64_t n = L.n[jb];
   const uint8_t *in = L.in[jb];
   const int64_t nrb = (n + HOP - 1) / HOP;
   const int64_t blk[2] = {2 * (int64_t)blockIdx.x, 2 * (int64_t)blockIdx.x + 1};
   if (blk[0] >= nrb) return;
   const int64_t F[2] = {blk[0] * HOP - RX_KK_EDGE, blk[1] * HOP - RX_KK_EDGE};
+
+  if (threadIdx.x < 48) {
+    const int q = (int)threadIdx.x - 8;
+    hev[threadIdx.x] = (q >= 0 && 2 * q <= 64) ? J.mf[2 * q] : 0.0f;
+    hod[threadIdx.x] = (q >= 1 && 2 * q - 1 <= 64) ? J.mf[2 * q - 1] : 0.0f;
+  }
 
   // 1. l - l_ref for both frames (l_ref: the frame's centre sample; the
   //    Hilbert response is zero at DC, so any offset leaves phi unchanged and
@@ -114,24 +121,41 @@ __global__ __launch_bounds__((1 << LOGN) / 16) void kk_front(RxLaunch L) {
       }
     }
     __syncthreads();
-    // 4. decimating matched filter: Z[m] = sum_i h[i] y'[2m + 32 - i],
-    //    eight consecutive outputs per thread from 79 inputs in registers.
+    // 4. decimating matched filter Z[m] = sum_i h[i] y'[2m + 32 - i], eight
+    //    consecutive outputs per thread.  Polyphase form: at step e the input
+    //    pair y'(2e), y'(2e+1) meets the even taps h[2(o+32-e)] and the odd
+    //    taps h[2(o+32-e)-1] of outputs o = 0..7; those taps form an 8-wide
+    //    window that slides by one per step, so each step loads one even and
+    //    one odd tap (zero-padded tables in LDS) and two inputs.
     const int64_t m0 = blk[x] * (HOP / 2);
     for (int t8 = threadIdx.x; t8 < HOP / 16; t8 += T) {
       float2 acc[8];
+      float we[8], wo[8];
 #pragma unroll
-      for (int o = 0; o < 8; o++) acc[o] = make_float2(0.0f, 0.0f);
-      // not unrolled over the inputs: an unrolled form keeps too many
-      // taps and inputs live at 1024 threads per workgroup
+      for (int o = 0; o < 8; o++) {
+        acc[o] = make_float2(0.0f, 0.0f);
+        we[o] = hev[32 + o + 8];
+        wo[o] = hod[32 + o + 8];
+      }
+      const int qb = 16 * t8;
 #pragma unroll 1
-      for (int d = 0; d < 79; d++) {
-        const float2 v = lds[ypad(16 * t8 + d)];
+      for (int eb = 0; eb < 40; eb += 8) {
 #pragma unroll
-        for (int o = 0; o < 8; o++) {
-          const int tap = 2 * o + 64 - d;
-          const float h = (tap >= 0 && tap <= 64) ? J.mf[tap] : 0.0f;
-          acc[o].x = fmaf(h, v.x, acc[o].x);
-          acc[o].y = fmaf(h, v.y, acc[o].y);
+        for (int ee = 0; ee < 8; ee++) {
+          const int e = eb + ee;
+          const float2 y0 = lds[ypad(qb + 2 * e)];
+          const float2 y1 = lds[ypad(qb + 2 * e + 1)];
+#pragma unroll
+          for (int o = 0; o < 8; o++) {
+            const int slot = (o - ee + 8) & 7;
+            acc[o].x = fmaf(we[slot], y0.x, acc[o].x);
+            acc[o].y = fmaf(we[slot], y0.y, acc[o].y);
+            acc[o].x = fmaf(wo[slot], y1.x, acc[o].x);
+            acc[o].y = fmaf(wo[slot], y1.y, acc[o].y);
+          }
+          // next step's window: slot (-e-1) mod 8 takes h(31 - e)
+          we[(7 - ee) & 7] = hev[31 - e + 8];
+          wo[(7 - ee) & 7] = hod[31 - e + 8];
         }
       }
 #pragma unroll
@@ -153,7 +177,7 @@ __global__ __launch_bounds__((1 << LOGN) / 16) void kk_front(RxLaunch L) {
 __global__ __launch_bounds__(256) void kk_finalize(RxLaunch L) {
   __shared__ double red[4];
   const int jb = blockIdx.y;
-  const RxJob &J = *L.job[jb];
+  const RxJob J = *L.job[jb];
   const int64_t n = L.n[jb], nd = n / 2;
   const int64_t m0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
   if ((int64_t)blockIdx.x * 1024 >= nd) return;
@@ -199,7 +223,7 @@ __global__ __launch_bounds__(256) void kk_finalize(RxLaunch L) {
 __global__ __launch_bounds__(1024) void kk_vv(RxLaunch L) {
   __shared__ double scan[1024];
   const int jb = blockIdx.y;
-  const RxJob &J = *L.job[jb];
+  const RxJob J = *L.job[jb];
   const int64_t nsym = L.n[jb] / 4;
   const int nb = (int)(nsym / J.blk);
   const int per = (nb + 1023) / 1024;
@@ -246,14 +270,15 @@ static void launch_front(const RxLaunch &L, int64_t maxn, hipStream_t s) {
   hipLaunchKernelGGL(kk_front<LOGN>, grid, dim3(N / 16), 0, s, L);
 }
 
-void rx_launch_kk(const RxLaunch &L, int64_t maxn, int log2n, hipStream_t s) {
-  if (log2n == 13) launch_front<13>(L, maxn, s);
-  else launch_front<14>(L, maxn, s);
-  const int64_t nd = maxn / 2;
-  hipLaunchKernelGGL(kk_finalize, dim3((unsigned)((nd + 1023) / 1024), (unsigned)L.count), dim3(256), 0,
-                     s, L);
-}
-
-void rx_launch_kk_vv(const RxLaunch &L, hipStream_t s) {
-  hipLaunchKernelGGL(kk_vv, dim3(1, (unsigned)L.count), dim3(1024), 0, s, L);
+void rx_launch_kk_stage(int stage, const RxLaunch &L, int64_t maxn, int log2n, hipStream_t s) {
+  const unsigned cnt = (unsigned)L.count;
+  if (stage == ST_KK_FRONT) {
+    if (log2n == 13) launch_front<13>(L, maxn, s);
+    else launch_front<14>(L, maxn, s);
+  } else if (stage == ST_KK_FINALIZE) {
+    const int64_t nd = maxn / 2;
+    hipLaunchKernelGGL(kk_finalize, dim3((unsigned)((nd + 1023) / 1024), cnt), dim3(256), 0, s, L);
+  } else if (stage == ST_KK_VV) {
+    hipLaunchKernelGGL(kk_vv, dim3(1, cnt), dim3(1024), 0, s, L);
+  }
 }

@@ -9,7 +9,7 @@
 __global__ __launch_bounds__(256) void pam_sum(RxLaunch L) {
   __shared__ uint32_t red[4];
   const int jb = blockIdx.y;
-  const RxJob &J = *L.job[jb];
+  const RxJob J = *L.job[jb];
   const int64_t n = L.n[jb];
   const int64_t base = (int64_t)blockIdx.x * PAM_SUMW;
   if (base >= n) return;
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(256) void pam_mf(RxLaunch L) {
   __shared__ double red[4];
   __shared__ double mean_s;
   const int jb = blockIdx.y;
-  const RxJob &J = *L.job[jb];
+  const RxJob J = *L.job[jb];
   const int64_t n = L.n[jb];
   const uint8_t *in = L.in[jb];
   const int64_t t0 = (int64_t)blockIdx.x * PAM_TS;
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(256) void pam_mf(RxLaunch L) {
 // Angle of the detector sums averaged over blocks b-16 .. b+16.
 __global__ __launch_bounds__(256) void pam_gavg(RxLaunch L) {
   const int jb = blockIdx.y;
-  const RxJob &J = *L.job[jb];
+  const RxJob J = *L.job[jb];
   const int64_t nb = L.n[jb] / 512;
   const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (b >= nb) return;
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(1024) void pam_unwrap(RxLaunch L) {
   __shared__ double scan[1024];
   __shared__ double red[16];
   const int jb = blockIdx.y;
-  const RxJob &J = *L.job[jb];
+  const RxJob J = *L.job[jb];
   const int64_t n = L.n[jb];
   const int nb = (int)(n / 512);
   const float *raw = J.delta + nb;
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(1024) void pam_unwrap(RxLaunch L) {
 // xr[t] = g * y(t + delta_b), t in block b.
 __global__ __launch_bounds__(256) void pam_farrow(RxLaunch L) {
   const int jb = blockIdx.y;
-  const RxJob &J = *L.job[jb];
+  const RxJob J = *L.job[jb];
   const int64_t n = L.n[jb];
   const float g = (float)J.sc->agc;
   const int64_t t00 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
@@ -209,12 +209,24 @@ __global__ __launch_bounds__(256) void pam_farrow(RxLaunch L) {
   }
 }
 
-void rx_launch_pam(const RxLaunch &L, int64_t maxn, hipStream_t s) {
+void rx_launch_pam_stage(int stage, const RxLaunch &L, int64_t maxn, hipStream_t s) {
   const unsigned cnt = (unsigned)L.count;
-  hipLaunchKernelGGL(pam_sum, dim3((unsigned)((maxn + PAM_SUMW - 1) / PAM_SUMW), cnt), dim3(256), 0, s, L);
-  hipLaunchKernelGGL(pam_mf, dim3((unsigned)((maxn + PAM_TS - 1) / PAM_TS), cnt), dim3(256), 0, s, L);
   const int64_t nb = maxn / 512;
-  hipLaunchKernelGGL(pam_gavg, dim3((unsigned)((nb + 255) / 256), cnt), dim3(256), 0, s, L);
-  hipLaunchKernelGGL(pam_unwrap, dim3(1, cnt), dim3(1024), 0, s, L);
-  hipLaunchKernelGGL(pam_farrow, dim3((unsigned)((maxn + 1023) / 1024), cnt), dim3(256), 0, s, L);
+  switch (stage) {
+    case ST_PAM_SUM:
+      hipLaunchKernelGGL(pam_sum, dim3((unsigned)((maxn + PAM_SUMW - 1) / PAM_SUMW), cnt), dim3(256), 0, s, L);
+      break;
+    case ST_PAM_MF:
+      hipLaunchKernelGGL(pam_mf, dim3((unsigned)((maxn + PAM_TS - 1) / PAM_TS), cnt), dim3(256), 0, s, L);
+      break;
+    case ST_PAM_GAVG:
+      hipLaunchKernelGGL(pam_gavg, dim3((unsigned)((nb + 255) / 256), cnt), dim3(256), 0, s, L);
+      break;
+    case ST_PAM_UNWRAP:
+      hipLaunchKernelGGL(pam_unwrap, dim3(1, cnt), dim3(1024), 0, s, L);
+      break;
+    case ST_PAM_FARROW:
+      hipLaunchKernelGGL(pam_farrow, dim3((unsigned)((maxn + 1023) / 1024), cnt), dim3(256), 0, s, L);
+      break;
+  }
 }

@@ -83,10 +83,12 @@ __device__ __forceinline__ float decide_level(float v, int m) {
 }
 
 // ---- 12-bit packed input -------------------------------------------------
-// Code of sample i (any i in range), from the three bytes holding its pair.
+// Code of sample i (any i in range): the 16 bits at byte 3i/2 hold it in
+// their low 12 bits (even i) or high 12 bits (odd i).
 __device__ __forceinline__ int read_code(const uint8_t *in, int64_t i) {
-  const uint8_t *b = in + 3 * (i >> 1);
-  return (i & 1) ? ((int)(b[1] >> 4) | ((int)b[2] << 4)) : ((int)b[0] | ((int)(b[1] & 0x0F) << 8));
+  const uint8_t *b = in + ((3 * i) >> 1);
+  const int v = (int)b[0] | ((int)b[1] << 8);
+  return (v >> ((int)(i & 1) << 2)) & 0xFFF;
 }
 
 // Eight codes of samples 8g .. 8g+7 from three aligned 32-bit words.

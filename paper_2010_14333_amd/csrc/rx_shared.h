@@ -69,8 +69,11 @@ static inline int rx_kk_hop(int log2n) {
   return h & ~15;
 }
 
-// Host-side launchers (defined with their kernels).
-void rx_launch_kk(const RxLaunch &L, int64_t maxn, int log2n, hipStream_t s);
-void rx_launch_pam(const RxLaunch &L, int64_t maxn, hipStream_t s);
-void rx_launch_tail(const RxLaunch &L, int64_t maxn, int kk, int ffe_taps, hipStream_t s);
-void rx_launch_kk_vv(const RxLaunch &L, hipStream_t s);
+// Kernel stages (host-side launchers are defined with their kernels).
+enum RxStage {
+  ST_KK_FRONT = 0, ST_KK_FINALIZE, ST_PAM_SUM, ST_PAM_MF, ST_PAM_GAVG, ST_PAM_UNWRAP, ST_PAM_FARROW,
+  ST_PREFIX, ST_BLOCKS, ST_KK_VV, ST_DECIDE, ST_COUNT
+};
+void rx_launch_kk_stage(int stage, const RxLaunch &L, int64_t maxn, int log2n, hipStream_t s);
+void rx_launch_pam_stage(int stage, const RxLaunch &L, int64_t maxn, hipStream_t s);
+void rx_launch_eq_stage(int stage, const RxLaunch &L, int64_t maxn, int kk, int ffe_taps, hipStream_t s);
