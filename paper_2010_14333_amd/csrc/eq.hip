@@ -2,6 +2,8 @@
 // buffer), block-parallel DD-LMS FFE (one lane per block, Sec. 2, second
 // paragraph: "8192 data blocks per buffer in parallel"), decisions, Gray
 // demapping, bit packing and error counting (Sec. 3, second paragraph).
+#include <type_traits>
+
 #include "rx_dev.hpp"
 
 // Sum over lanes 0..31 of a wavefront, returned in every lane: DPP within
@@ -55,6 +57,7 @@ __global__ __launch_bounds__(256) void rx_prefix(RxLaunch L) {
     g = (float)gd;
     if (threadIdx.x == 0) J.sc->agc = gd;
   }
+#pragma unroll 8
   for (int idx = threadIdx.x; idx < PFX_UL; idx += 256) {
     const int64_t j = (int64_t)idx - PFX_OFF;
     float2 v = make_float2(0.0f, 0.0f);
@@ -71,8 +74,11 @@ __global__ __launch_bounds__(256) void rx_prefix(RxLaunch L) {
     if (kk) {
       float s4r = 0.0f, s4i = 0.0f;
       const float r2 = J.r2, mu = J.mu_cma;
+      const float2 zero = make_float2(0.0f, 0.0f);
+      float2 xn = lane < K ? u[PFX_OFF + c - lane] : zero;
       for (int k = 0; k < P; k++) {
-        const float2 xi = lane < K ? u[PFX_OFF + 2 * k + c - lane] : make_float2(0.0f, 0.0f);
+        const float2 xi = xn;   // the next step's input is read one step ahead
+        if (k + 1 < P) xn = lane < K ? u[PFX_OFF + 2 * (k + 1) + c - lane] : zero;
         const float2 pr = cmul(wi, xi);
         const float zr = tap_sum(pr.x), zi = tap_sum(pr.y);
         if (k >= P - 2048) {
@@ -143,11 +149,17 @@ __global__ __launch_bounds__(256) void rx_prefix(RxLaunch L) {
     const float2 jq = q == 0 ? make_float2(1, 0) : q == 1 ? make_float2(0, 1) : q == 2 ? make_float2(-1, 0) : make_float2(0, -1);
     wi = cmul(wi, jq);
     const float mu = J.mu;
+    const float2 zero = make_float2(0.0f, 0.0f);
+    float2 xn = lane < K ? u[PFX_OFF + 2 * s + c - lane] : zero;
+    float2 an = ar[0];
     for (int k = 0; k < P; k++) {
-      const float2 xi = lane < K ? u[PFX_OFF + 2 * (k + s) + c - lane] : make_float2(0.0f, 0.0f);
+      const float2 xi = xn, a = an;   // next step's input and symbol read one step ahead
+      if (k + 1 < P) {
+        xn = lane < K ? u[PFX_OFF + 2 * (k + 1 + s) + c - lane] : zero;
+        an = ar[k + 1];
+      }
       const float2 pr = cmul(wi, xi);
       const float zr = tap_sum(pr.x), zi = tap_sum(pr.y);
-      const float2 a = ar[k];
       const float2 e = make_float2(mu * (a.x - zr), mu * (a.y - zi));
       wi = cadd(wi, cmulc(e, xi));
     }
@@ -162,9 +174,17 @@ __global__ __launch_bounds__(256) void rx_prefix(RxLaunch L) {
 }
 
 // Block-parallel DD-LMS: each lane adapts one block of `blk` symbols from w0
-// independently (a decision feedback error cannot leave its block).
+// independently (a decision feedback error cannot leave its block).  Lane
+// streams are 2*blk samples apart, so they are staged through LDS in chunks
+// of BC steps: the workgroup loads every lane's next 2*BC samples with
+// coalesced reads, each lane runs BC steps from registers, and the soft
+// outputs go back out the same way.
+#define BC 8
 template <bool CPLX, int K>
 __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
+  using T = typename std::conditional<CPLX, float2, float>::type;
+  __shared__ T sin_[256 * (2 * BC + 1)];
+  __shared__ T sout[256 * (BC + 1)];
   const int jb = blockIdx.y;
   const RxJob J = *L.job[jb];
   const int64_t n = L.n[jb];
@@ -172,108 +192,157 @@ __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
   const int blk = J.blk;
   const int64_t nsym = n / (CPLX ? 4 : 2);
   const int64_t nb = nsym / blk;
-  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (b >= nb) return;
+  const int64_t b0 = (int64_t)blockIdx.x * 256;
+  if (b0 >= nb) return;
+  const int64_t b = b0 + threadIdx.x;
+  const bool active = b < nb;
   constexpr int C = (K - 1) / 2;
   const float mu = J.mu;
   const int m = J.m_axis;
   const float g = CPLX ? (float)J.sc->agc : 1.0f;
   const int s = J.sc->lag;
-  float2 w[K], x[K];
+  const float2 *__restrict__ zin = J.z;
+  const float *__restrict__ xin = J.xr;
+  float2 *__restrict__ soft = J.soft;
+  auto load = [&](int64_t j) -> T {
+    if constexpr (CPLX) {
+      return (j >= 0 && j < nx) ? cscale(zin[j], g) : make_float2(0.0f, 0.0f);
+    } else {
+      return (j >= 0 && j < nx) ? xin[j] : 0.0f;
+    }
+  };
+  float2 w[K];
+  T xs[K + 2 * BC];   // xs[t] = sample p0 - C + t (+ 2 BC per chunk)
 #pragma unroll
   for (int i = 0; i < K; i++) w[i] = J.sc->w0[i];
-  const int64_t k0 = b * blk;
-  int64_t p = 2 * (k0 + s);
-  auto load = [&](int64_t j) -> float2 {
-    if (j < 0 || j >= nx) return make_float2(0.0f, 0.0f);
-    if (CPLX) return cscale(J.z[j], g);
-    return make_float2(J.xr[j], 0.0f);
-  };
+  const int64_t p0 = 2 * (b * blk + s);
 #pragma unroll
-  for (int i = 0; i < K; i++) x[i] = load(p + C - i);
+  for (int t = 0; t < K; t++) xs[t] = load(p0 - C + t);
   float s4r = 0.0f, s4i = 0.0f;
-  for (int k = 0; k < blk; k++) {
-    float2 z = make_float2(0.0f, 0.0f);
-    if (CPLX) {
+  const int nch = blk / BC;
+  for (int ch = 0; ch < nch; ch++) {
+    // lane l's next 2*BC samples start at p0_l + C + 1 + 2*BC*ch
+    for (int e = threadIdx.x; e < 256 * 2 * BC; e += 256) {
+      const int l = e / (2 * BC), jj = e % (2 * BC);
+      const int64_t pl = 2 * ((b0 + l) * blk + s) + C + 1 + 2 * BC * ch + jj;
+      sin_[l * (2 * BC + 1) + jj] = load(pl);
+    }
+    __syncthreads();
 #pragma unroll
-      for (int i = 0; i < K; i++) z = cadd(z, cmul(w[i], x[i]));
-      const float2 e = make_float2(mu * (decide_level(z.x, m) - z.x), mu * (decide_level(z.y, m) - z.y));
+    for (int t = 0; t < 2 * BC; t++) xs[K + t] = sin_[threadIdx.x * (2 * BC + 1) + t];
 #pragma unroll
-      for (int i = 0; i < K; i++) w[i] = cadd(w[i], cmulc(e, x[i]));
-      const float a2 = z.x * z.x - z.y * z.y, b2 = 2.0f * z.x * z.y;
-      s4r += a2 * a2 - b2 * b2;
-      s4i += 2.0f * a2 * b2;
-      J.soft[k0 + k] = z;
-    } else {
+    for (int kk = 0; kk < BC; kk++) {
+      // tap i sees xs[2 kk + K - 1 - i]
+      if constexpr (CPLX) {
+        float2 z = make_float2(0.0f, 0.0f);
 #pragma unroll
-      for (int i = 0; i < K; i++) z.x = fmaf(w[i].x, x[i].x, z.x);
-      const float e = mu * (decide_level(z.x, m) - z.x);
+        for (int i = 0; i < K; i++) z = cadd(z, cmul(w[i], xs[2 * kk + K - 1 - i]));
+        const float2 e = make_float2(mu * (decide_level(z.x, m) - z.x), mu * (decide_level(z.y, m) - z.y));
 #pragma unroll
-      for (int i = 0; i < K; i++) w[i].x = fmaf(e, x[i].x, w[i].x);
-      J.soft[k0 + k] = z;
+        for (int i = 0; i < K; i++) w[i] = cadd(w[i], cmulc(e, xs[2 * kk + K - 1 - i]));
+        const float a2 = z.x * z.x - z.y * z.y, b2 = 2.0f * z.x * z.y;
+        s4r += a2 * a2 - b2 * b2;
+        s4i += 2.0f * a2 * b2;
+        sout[threadIdx.x * (BC + 1) + kk] = z;
+      } else {
+        float z = 0.0f;
+#pragma unroll
+        for (int i = 0; i < K; i++) z = fmaf(w[i].x, xs[2 * kk + K - 1 - i], z);
+        const float e = mu * (decide_level(z, m) - z);
+#pragma unroll
+        for (int i = 0; i < K; i++) w[i].x = fmaf(e, xs[2 * kk + K - 1 - i], w[i].x);
+        sout[threadIdx.x * (BC + 1) + kk] = z;
+      }
     }
 #pragma unroll
-    for (int i = K - 1; i >= 2; i--) x[i] = x[i - 2];
-    x[0] = load(p + 2 + C);
-    x[1] = load(p + 1 + C);
-    p += 2;
+    for (int t = 0; t < K; t++) xs[t] = xs[t + 2 * BC];
+    __syncthreads();
+    for (int e = threadIdx.x; e < 256 * BC; e += 256) {
+      const int l = e / BC, kk = e % BC;
+      if (b0 + l < nb) {
+        const T v = sout[l * (BC + 1) + kk];
+        if constexpr (CPLX) soft[(b0 + l) * blk + BC * ch + kk] = v;
+        else soft[(b0 + l) * blk + BC * ch + kk] = make_float2(v, 0.0f);
+      }
+    }
   }
-  if (CPLX) J.s4[b] = make_float2(s4r, s4i);
+  if (CPLX && active) J.s4[b] = make_float2(s4r, s4i);
 }
+#undef BC
 
-// Decisions, Gray demapping, packing and error counting: one thread per 32
-// symbols, i.e. bps whole 32-bit words of the bit stream.
+// Decisions, Gray demapping, packing and error counting: one lane per
+// symbol (coalesced soft reads); each pass of 256 symbols fills exactly
+// 8*bps words of the bit stream, assembled in LDS.  A workgroup covers
+// DEC_SYMS symbols and adds its error counts with one set of atomics.
+#define DEC_SYMS 2048
 __global__ __launch_bounds__(256) void rx_decide(RxLaunch L) {
+  __shared__ uint32_t wb[32];
+  __shared__ unsigned long long red[3][4];
   const int jb = blockIdx.y;
   const RxJob J = *L.job[jb];
   const int64_t n = L.n[jb];
   const int kk = J.kk, bps = J.bps, m = J.m_axis, P = J.prefix;
   const int64_t nsym = n / (kk ? 4 : 2);
-  const int64_t grp = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t kbase = (int64_t)blockIdx.x * DEC_SYMS;
+  if (kbase >= nsym) return;   // nsym is a multiple of 256
+  uint32_t *__restrict__ out = reinterpret_cast<uint32_t *>(L.bits[jb]);
+  float2 *__restrict__ soft = J.soft;
   unsigned long long cs = 0, se = 0, be = 0;
-  if (grp < nsym / 32) {
-    uint32_t words[4] = {0u, 0u, 0u, 0u};
-    const int half = bps >> 1;
-    for (int e = 0; e < 32; e++) {
-      const int64_t k = grp * 32 + e;
-      float2 z = J.soft[k];
-      uint32_t sym;
-      if (kk) {
-        z = cmul(z, cis_rev(-J.theta[k / J.blk] * 0.15915494309189535f));
-        if (J.debug) J.soft[k] = z;
-        const uint32_t gi = (uint32_t)decide_index(z.x, m), gq = (uint32_t)decide_index(z.y, m);
-        sym = ((gi ^ (gi >> 1)) << half) | (gq ^ (gq >> 1));
-      } else {
-        const uint32_t gi = (uint32_t)decide_index(z.x, m);
-        sym = gi ^ (gi >> 1);
-      }
-      for (int j = 0; j < bps; j++) {
-        const int l = e * bps + j;
-        words[l >> 5] |= ((sym >> (bps - 1 - j)) & 1u) << (l & 31);
-      }
-      if (k >= P + RX_GUARD && k < nsym - RX_GUARD) {
-        const uint32_t ref = (uint32_t)(splitmix64(J.seed, (uint64_t)k) >> (64 - bps));
-        const int ne = __popc(ref ^ sym);
-        cs++;
-        be += ne;
-        se += ne > 0;
-      }
+  for (int64_t k0 = kbase; k0 < kbase + DEC_SYMS && k0 < nsym; k0 += 256) {
+    if (threadIdx.x < 32) wb[threadIdx.x] = 0u;
+    __syncthreads();
+    const int64_t k = k0 + threadIdx.x;
+    float2 z = soft[k];
+    uint32_t sym;
+    if (kk) {
+      z = cmul(z, cis_rev(-J.theta[k / J.blk] * 0.15915494309189535f));
+      if (J.debug) soft[k] = z;
+      const uint32_t gi = (uint32_t)decide_index(z.x, m), gq = (uint32_t)decide_index(z.y, m);
+      sym = ((gi ^ (gi >> 1)) << (bps >> 1)) | (gq ^ (gq >> 1));
+    } else {
+      const uint32_t gi = (uint32_t)decide_index(z.x, m);
+      sym = gi ^ (gi >> 1);
     }
-    uint32_t *out = reinterpret_cast<uint32_t *>(L.bits[jb]) + grp * bps;
-    for (int i = 0; i < bps; i++) out[i] = words[i];
+    // stream order: the symbol's MSB first
+    uint32_t rev = 0;
+    for (int j = 0; j < bps; j++) rev |= ((sym >> (bps - 1 - j)) & 1u) << j;
+    const int lb = threadIdx.x * bps, wi = lb >> 5, off = lb & 31;
+    atomicOr(&wb[wi], rev << off);
+    if (off + bps > 32) atomicOr(&wb[wi + 1], rev >> (32 - off));
+    if (k >= P + RX_GUARD && k < nsym - RX_GUARD) {
+      const uint32_t ref = (uint32_t)(splitmix64(J.seed, (uint64_t)k) >> (64 - bps));
+      const int ne = __popc(ref ^ sym);
+      cs += 1;
+      be += (unsigned long long)ne;
+      se += ne > 0;
+    }
+    __syncthreads();
+    if (threadIdx.x < 8 * bps) out[(k0 / 256) * 8 * bps + threadIdx.x] = wb[threadIdx.x];
+    __syncthreads();
   }
   cs = wave_sum(cs);
   se = wave_sum(se);
   be = wave_sum(be);
-  if ((threadIdx.x & 63) == 0 && cs) {
-    atomicAdd(&J.sc->stats[1], cs);
-    atomicAdd(&J.sc->stats[2], cs * (unsigned long long)bps);
-    atomicAdd(&J.sc->stats[3], be);
-    atomicAdd(&J.sc->stats[4], se);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = cs;
+    red[1][threadIdx.x >> 6] = se;
+    red[2][threadIdx.x >> 6] = be;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    atomicAdd(&J.sc->stats[0], 1ull);
-    if (J.sc->fallback) atomicAdd(&J.sc->stats[5], 1ull);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    cs = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    se = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    be = red[2][0] + red[2][1] + red[2][2] + red[2][3];
+    if (cs) {
+      atomicAdd(&J.sc->stats[1], cs);
+      atomicAdd(&J.sc->stats[2], cs * (unsigned long long)bps);
+      atomicAdd(&J.sc->stats[3], be);
+      atomicAdd(&J.sc->stats[4], se);
+    }
+    if (blockIdx.x == 0) {
+      atomicAdd(&J.sc->stats[0], 1ull);
+      if (J.sc->fallback) atomicAdd(&J.sc->stats[5], 1ull);
+    }
   }
 }
 
@@ -293,6 +362,6 @@ void rx_launch_eq_stage(int stage, const RxLaunch &L, int64_t maxn, int kk, int 
       else hipLaunchKernelGGL((rx_blocks<false, 15>), gb, dim3(256), 0, s, L);
     }
   } else if (stage == ST_DECIDE) {
-    hipLaunchKernelGGL(rx_decide, dim3((unsigned)((nsym / 32 + 255) / 256), cnt), dim3(256), 0, s, L);
+    hipLaunchKernelGGL(rx_decide, dim3((unsigned)((nsym + DEC_SYMS - 1) / DEC_SYMS), cnt), dim3(256), 0, s, L);
   }
 }
