@@ -143,7 +143,8 @@ int rx_process(rx_handle h, const void *dev_buffer, size_t n_samples, void *dev_
  * allowed, as one batched launch sequence on the FIRST handle's stream (the
  * paper overlaps 5 buffers on 5 streams, Sec. 2, first paragraph; here all
  * buffers share every kernel launch).  With graph != 0 the launch sequence
- * is captured once into a hipGraph per (handles, buffers, sizes) and replayed.
+ * is captured once (on a library-owned stream) into a hipGraph per (handles,
+ * buffers, sizes) and replayed on the first handle's stream.
  * Arguments as for rx_process, one entry per buffer.  Errors: RX_E_INVALID
  * for count outside 1..64, a repeated handle or handles on different
  * streams. */

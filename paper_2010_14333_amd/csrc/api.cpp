@@ -97,6 +97,7 @@ struct Alloc {
 struct GraphCache {
   std::vector<const void *> key;
   hipGraphExec_t exec = nullptr;
+  hipStream_t capture = nullptr;   // library stream used only for capture (the null stream cannot be captured)
 };
 
 }  // namespace
@@ -190,7 +191,8 @@ int rx_create(rx_format fmt, double baud, double fs, const rx_params *pin, rx_ha
   if (kk && (p.hilbert_taps < 3 || p.hilbert_taps > 4097 || p.hilbert_taps % 2 == 0)) return RX_E_INVALID;
   if (p.fft_log2 != 0 && p.fft_log2 != 13 && p.fft_log2 != 14) return RX_E_INVALID;
   if (!(p.rolloff > 0 && p.rolloff <= 1) || !(p.mu > 0) || !(p.mu_cma > 0)) return RX_E_INVALID;
-  if (p.precision != RX_FP32) return RX_E_UNSUPPORTED;
+  if (p.precision != RX_FP32 && p.precision != RX_BF16 && p.precision != RX_FP16) return RX_E_INVALID;
+  if (p.precision != RX_FP32 && (!kk || p.ffe_taps != 21)) return RX_E_UNSUPPORTED;
   if (p.equalizer != RX_EQ_LMS) return RX_E_UNSUPPORTED;
   if (kk && !(std::fabs(p.carrier_hz) < fs / 2)) return RX_E_INVALID;
   if (p.max_samples < 65536 || p.max_samples > ((uint64_t)1 << 26) || p.max_samples % 1024) return RX_E_INVALID;
@@ -236,6 +238,12 @@ int rx_create(rx_format fmt, double baud, double fs, const rx_params *pin, rx_ha
   for (int i = 0; i < p.mf_taps; i++) {
     hd[(slots - p.mf_taps) / 2 + i] = hm[i];
     hf[(slots - p.mf_taps) / 2 + i] = (float)hm[i];
+  }
+  // precision form: the filter is the narrow-rounded taps (the carrier term
+  // removed after it uses the same filter)
+  for (int i = 0; i < slots; i++) {
+    if (p.precision == RX_BF16) hf[i] = (float)(__bf16)hf[i];
+    else if (p.precision == RX_FP16) hf[i] = (float)(_Float16)hf[i];
   }
   float *dmf = A.get<float>(slots);
   bool ok = dmf != nullptr;
@@ -317,7 +325,9 @@ static int enqueue(rx_handle const *hs, const void *const *bufs, const size_t *n
     const rx_ctx *a = hs[i];
     for (int j = i; j < count; j++) {
       const rx_ctx *b = hs[j];
-      if (done[j] || b->kk != a->kk || b->log2n != a->log2n || b->p.ffe_taps != a->p.ffe_taps) continue;
+      if (done[j] || b->kk != a->kk || b->log2n != a->log2n || b->p.ffe_taps != a->p.ffe_taps ||
+          b->p.precision != a->p.precision)
+        continue;
       done[j] = true;
       L.job[L.count] = b->dj;
       L.in[L.count] = static_cast<const uint8_t *>(bufs[j]);
@@ -335,11 +345,11 @@ static int enqueue(rx_handle const *hs, const void *const *bufs, const size_t *n
         hipEventRecord(e0, s);
       }
       if (st[k] == ST_KK_FRONT || st[k] == ST_KK_FINALIZE || st[k] == ST_KK_VV)
-        rx_launch_kk_stage(st[k], L, maxn, a->log2n, s);
+        rx_launch_kk_stage(st[k], L, maxn, a->log2n, a->p.precision, s);
       else if (st[k] >= ST_PAM_SUM && st[k] <= ST_PAM_FARROW)
         rx_launch_pam_stage(st[k], L, maxn, s);
       else
-        rx_launch_eq_stage(st[k], L, maxn, a->kk, a->p.ffe_taps, s);
+        rx_launch_eq_stage(st[k], L, maxn, a->kk, a->p.ffe_taps, a->p.precision, s);
       if (prof) {
         e1 = prof->event();
         hipEventRecord(e1, s);
@@ -392,10 +402,15 @@ int rx_process_batch(const rx_handle *hs, const void *const *bufs, const size_t 
         gc.exec = nullptr;
       }
       hipGraph_t g = nullptr;
-      hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+      hipError_t e = hipSuccess;
+      if (!gc.capture) {
+        e = hipStreamCreateWithFlags(&gc.capture, hipStreamNonBlocking);
+        if (e != hipSuccess) return fail_hip(e, "hipStreamCreateWithFlags");
+      }
+      e = hipStreamBeginCapture(gc.capture, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) return fail_hip(e, "hipStreamBeginCapture");
-      rc = enqueue(hs, bufs, ns, bits, count, s, true);
-      e = hipStreamEndCapture(s, &g);
+      rc = enqueue(hs, bufs, ns, bits, count, gc.capture, true);
+      e = hipStreamEndCapture(gc.capture, &g);
       if (rc) {
         if (g) hipGraphDestroy(g);
         return rc;
@@ -520,6 +535,7 @@ void rx_destroy(rx_handle h) {
   if (!h) return;
   hipStreamSynchronize(h->stream);
   if (h->graph.exec) hipGraphExecDestroy(h->graph.exec);
+  if (h->graph.capture) hipStreamDestroy(h->graph.capture);
   delete h;
 }
 

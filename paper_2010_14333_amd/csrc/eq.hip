@@ -270,6 +270,83 @@ __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
 }
 #undef BC
 
+// Precision form of the FFE (KK): the prefix taps w0 frozen for the buffer
+// and applied as a Toeplitz GEMM on MFMA with narrow operands and FP32
+// accumulation.  A row = [Re x | Im x] of the 64-sample window of a tile of
+// 16 symbols (x = AGC'd 2-sps samples from 2(k0+s)-C), B = [[Wr, Wi],
+// [-Wi, Wr]] with W[t][q] = w0[2C + 2q - t]; 4 K-steps x 2 column tiles.
+// One wavefront per 16 tiles (256 symbols = two VV blocks), whose z^4 sums
+// it also forms.
+template <int PREC>
+__global__ __launch_bounds__(256) void rx_ffe_mfma(RxLaunch L) {
+  using NT = NarrowT<PREC>;
+  const int jb = blockIdx.y;
+  const RxJob J = *L.job[jb];
+  const int64_t n = L.n[jb], nx = n / 2, nsym = n / 4;
+  const int lane = threadIdx.x & 63;
+  const int64_t grp = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (grp * 256 >= nsym) return;
+  const int K = J.ffe_taps, C = (K - 1) / 2;
+  const int s = J.sc->lag;
+  const float g = (float)J.sc->agc;
+  const int row = lane & 15, kq = lane >> 4;
+  // B fragments: kk = 32 ks + 8 kq + j (t = kk % 64, part = kk / 64),
+  // column q = row of output tile ct (0: Re z, 1: Im z)
+  typename NT::vec bw[4][2];
+#pragma unroll
+  for (int ks = 0; ks < 4; ks++)
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      const int kk = 32 * ks + 8 * kq + j, t = kk & 63, part = kk >> 6;
+      const int i = 2 * C + 2 * row - t;
+      float2 w = make_float2(0.0f, 0.0f);
+      if (i >= 0 && i < K) w = J.sc->w0[i];
+      const float wr = NT::cvt(w.x), wi = NT::cvt(w.y);   // operands rounded once
+      bw[ks][0][j] = NT::cvt(part == 0 ? wr : -wi);
+      bw[ks][1][j] = NT::cvt(part == 0 ? wi : wr);
+    }
+  const int64_t tile = grp * 16 + row;
+  const int64_t base = 2 * (tile * 16 + s) - C;
+  const float2 *__restrict__ zin = J.z;
+  float2 xv[16];
+#pragma unroll
+  for (int h = 0; h < 2; h++)
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      const int64_t q = base + 32 * h + 8 * kq + j;
+      xv[8 * h + j] = (q >= 0 && q < nx) ? cscale(zin[q], g) : make_float2(0.0f, 0.0f);
+    }
+  rx_f32x4 zr = {0.0f, 0.0f, 0.0f, 0.0f}, zi = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int ks = 0; ks < 4; ks++) {
+    typename NT::vec a;
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      const float2 v = xv[8 * (ks & 1) + j];
+      a[j] = NT::cvt(ks < 2 ? v.x : v.y);
+    }
+    zr = NT::mfma(a, bw[ks][0], zr);
+    zi = NT::mfma(a, bw[ks][1], zi);
+  }
+  float s4r = 0.0f, s4i = 0.0f;
+#pragma unroll
+  for (int j = 0; j < 4; j++) {
+    const int64_t k = (grp * 16 + 4 * kq + j) * 16 + row;
+    const float2 z = make_float2(zr[j], zi[j]);
+    J.soft[k] = z;
+    const float a2 = z.x * z.x - z.y * z.y, b2 = 2.0f * z.x * z.y;
+    s4r += a2 * a2 - b2 * b2;
+    s4i += 2.0f * a2 * b2;
+  }
+  // lanes 0..31 hold tiles 0..7 (block 2 grp), lanes 32..63 tiles 8..15
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) {
+    s4r += __shfl_xor(s4r, o, 64);
+    s4i += __shfl_xor(s4i, o, 64);
+  }
+  if ((lane & 31) == 0) J.s4[2 * grp + (lane >> 5)] = make_float2(s4r, s4i);
+}
+
 // Decisions, Gray demapping, packing and error counting: one lane per
 // symbol (coalesced soft reads); each pass of 256 symbols fills exactly
 // 8*bps words of the bit stream, assembled in LDS.  A workgroup covers
@@ -346,11 +423,15 @@ __global__ __launch_bounds__(256) void rx_decide(RxLaunch L) {
   }
 }
 
-void rx_launch_eq_stage(int stage, const RxLaunch &L, int64_t maxn, int kk, int ffe_taps, hipStream_t s) {
+void rx_launch_eq_stage(int stage, const RxLaunch &L, int64_t maxn, int kk, int ffe_taps, int prec, hipStream_t s) {
   const unsigned cnt = (unsigned)L.count;
   const int64_t nsym = maxn / (kk ? 4 : 2);
   if (stage == ST_PREFIX) {
     hipLaunchKernelGGL(rx_prefix, dim3(1, cnt), dim3(256), 0, s, L);
+  } else if (stage == ST_BLOCKS && kk && prec != 0) {
+    dim3 gf((unsigned)((nsym / 256 + 3) / 4), cnt);
+    if (prec == 1) hipLaunchKernelGGL(rx_ffe_mfma<1>, gf, dim3(256), 0, s, L);
+    else hipLaunchKernelGGL(rx_ffe_mfma<2>, gf, dim3(256), 0, s, L);
   } else if (stage == ST_BLOCKS) {
     const int64_t nb = nsym / (kk ? 128 : 256);
     dim3 gb((unsigned)((nb + 255) / 256), cnt);

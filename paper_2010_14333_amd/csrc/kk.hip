@@ -12,6 +12,8 @@
 // The carrier mean m is not known inside one workgroup, so the filter runs
 // on y' = y + m exp(-j 2 pi r n) and kk_finalize subtracts m * MF(exp(...))
 // afterwards (the filter is linear).
+#include <type_traits>
+
 #include "fft_lds.hpp"
 
 __device__ __forceinline__ int64_t clamp64(int64_t v, int64_t lo, int64_t hi) {
@@ -30,7 +32,7 @@ __device__ __forceinline__ void frame_codes8(const uint8_t *in, int64_t n, int64
 
 __device__ __forceinline__ int ypad(int q) { return q + (q >> 5); }
 
-template <int LOGN>
+template <int LOGN, int PREC>
 __global__ __launch_bounds__((1 << LOGN) / 16) void kk_front(RxLaunch L) {
   constexpr int N = 1 << LOGN, T = N / 16;
   constexpr int HOP = (N - RX_KK_HALFV - RX_KK_EDGE - RX_KK_CMF) & ~15;
@@ -121,47 +123,88 @@ __global__ __launch_bounds__((1 << LOGN) / 16) void kk_front(RxLaunch L) {
       }
     }
     __syncthreads();
-    // 4. decimating matched filter Z[m] = sum_i h[i] y'[2m + 32 - i], eight
-    //    consecutive outputs per thread.  Polyphase form: at step e the input
-    //    pair y'(2e), y'(2e+1) meets the even taps h[2(o+32-e)] and the odd
-    //    taps h[2(o+32-e)-1] of outputs o = 0..7; those taps form an 8-wide
-    //    window that slides by one per step, so each step loads one even and
-    //    one odd tap (zero-padded tables in LDS) and two inputs.
     const int64_t m0 = blk[x] * (HOP / 2);
-    for (int t8 = threadIdx.x; t8 < HOP / 16; t8 += T) {
-      float2 acc[8];
-      float we[8], wo[8];
-#pragma unroll
-      for (int o = 0; o < 8; o++) {
-        acc[o] = make_float2(0.0f, 0.0f);
-        we[o] = hev[32 + o + 8];
-        wo[o] = hod[32 + o + 8];
-      }
-      const int qb = 16 * t8;
-#pragma unroll 1
-      for (int eb = 0; eb < 40; eb += 8) {
-#pragma unroll
-        for (int ee = 0; ee < 8; ee++) {
-          const int e = eb + ee;
-          const float2 y0 = lds[ypad(qb + 2 * e)];
-          const float2 y1 = lds[ypad(qb + 2 * e + 1)];
-#pragma unroll
-          for (int o = 0; o < 8; o++) {
-            const int slot = (o - ee + 8) & 7;
-            acc[o].x = fmaf(we[slot], y0.x, acc[o].x);
-            acc[o].y = fmaf(we[slot], y0.y, acc[o].y);
-            acc[o].x = fmaf(wo[slot], y1.x, acc[o].x);
-            acc[o].y = fmaf(wo[slot], y1.y, acc[o].y);
+    if constexpr (PREC == 0) {
+      // 4. decimating matched filter Z[m] = sum_i h[i] y'[2m + 32 - i], eight
+      //    consecutive outputs per thread.  Polyphase form: at step e the input
+      //    pair y'(2e), y'(2e+1) meets the even taps h[2(o+32-e)] and the odd
+      //    taps h[2(o+32-e)-1] of outputs o = 0..7; those taps form an 8-wide
+      //    window that slides by one per step, so each step loads one even and
+      //    one odd tap (zero-padded tables in LDS) and two inputs.
+      for (int t8 = threadIdx.x; t8 < HOP / 16; t8 += T) {
+        float2 acc[8];
+        float we[8], wo[8];
+  #pragma unroll
+        for (int o = 0; o < 8; o++) {
+          acc[o] = make_float2(0.0f, 0.0f);
+          we[o] = hev[32 + o + 8];
+          wo[o] = hod[32 + o + 8];
+        }
+        const int qb = 16 * t8;
+  #pragma unroll 1
+        for (int eb = 0; eb < 40; eb += 8) {
+  #pragma unroll
+          for (int ee = 0; ee < 8; ee++) {
+            const int e = eb + ee;
+            const float2 y0 = lds[ypad(qb + 2 * e)];
+            const float2 y1 = lds[ypad(qb + 2 * e + 1)];
+  #pragma unroll
+            for (int o = 0; o < 8; o++) {
+              const int slot = (o - ee + 8) & 7;
+              acc[o].x = fmaf(we[slot], y0.x, acc[o].x);
+              acc[o].y = fmaf(we[slot], y0.y, acc[o].y);
+              acc[o].x = fmaf(wo[slot], y1.x, acc[o].x);
+              acc[o].y = fmaf(wo[slot], y1.y, acc[o].y);
+            }
+            // next step's window: slot (-e-1) mod 8 takes h(31 - e)
+            we[(7 - ee) & 7] = hev[31 - e + 8];
+            wo[(7 - ee) & 7] = hod[31 - e + 8];
           }
-          // next step's window: slot (-e-1) mod 8 takes h(31 - e)
-          we[(7 - ee) & 7] = hev[31 - e + 8];
-          wo[(7 - ee) & 7] = hod[31 - e + 8];
+        }
+  #pragma unroll
+        for (int o = 0; o < 8; o++) {
+          const int64_t m = m0 + 8 * t8 + o;
+          if (2 * m < n) J.z[m] = acc[o];
         }
       }
+
+    } else {
+      // 4'. precision form: the same filter as a Toeplitz GEMM on MFMA with
+      //     narrow operands and FP32 accumulation.  A row = one real
+      //     component (re or im) of the 96-sample window of a tile of 16
+      //     outputs, B[t][q] = h[2q + 64 - t]; one 16x16x32 step per 32
+      //     window samples, eight tiles (16 rows) per wavefront pass.
+      using NT = NarrowT<PREC>;
+      const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+      constexpr int NTILE = HOP / 32;
+      const int row = lane & 15, kq = lane >> 4;
+      typename NT::vec bmf[3];   // B fragments of the tap matrix
 #pragma unroll
-      for (int o = 0; o < 8; o++) {
-        const int64_t m = m0 + 8 * t8 + o;
-        if (2 * m < n) J.z[m] = acc[o];
+      for (int ks = 0; ks < 3; ks++)
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+          const int t = 32 * ks + 8 * kq + j, tap = 2 * row + 64 - t;
+          bmf[ks][j] = NT::cvt((tap >= 0 && tap <= 64) ? J.mf[tap] : 0.0f);
+        }
+      for (int grp = wv; grp < (NTILE + 7) / 8; grp += T / 64) {
+        const int tile = grp * 8 + (row >> 1);
+        rx_f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int ks = 0; ks < 3; ks++) {
+          typename NT::vec a;
+#pragma unroll
+          for (int j = 0; j < 8; j++) {
+            const float2 v = lds[ypad(32 * tile + 32 * ks + 8 * kq + j)];
+            a[j] = NT::cvt((row & 1) ? v.y : v.x);
+          }
+          acc = NT::mfma(a, bmf[ks], acc);
+        }
+#pragma unroll
+        for (int jj = 0; jj < 2; jj++) {
+          const int t2 = grp * 8 + 2 * kq + jj;
+          const int64_t m = m0 + 16 * t2 + row;
+          if (t2 < NTILE && 2 * m < n) J.z[m] = make_float2(acc[2 * jj], acc[2 * jj + 1]);
+        }
       }
     }
     __syncthreads();
@@ -261,20 +304,27 @@ __global__ __launch_bounds__(1024) void kk_vv(RxLaunch L) {
   }
 }
 
-template <int LOGN>
+template <int LOGN, int PREC>
 static void launch_front(const RxLaunch &L, int64_t maxn, hipStream_t s) {
   constexpr int N = 1 << LOGN;
   const int hop = rx_kk_hop(LOGN);
   const int64_t nrb = (maxn + hop - 1) / hop;
   dim3 grid((unsigned)((nrb + 1) / 2), (unsigned)L.count);
-  hipLaunchKernelGGL(kk_front<LOGN>, grid, dim3(N / 16), 0, s, L);
+  hipLaunchKernelGGL((kk_front<LOGN, PREC>), grid, dim3(N / 16), 0, s, L);
 }
 
-void rx_launch_kk_stage(int stage, const RxLaunch &L, int64_t maxn, int log2n, hipStream_t s) {
+void rx_launch_kk_stage(int stage, const RxLaunch &L, int64_t maxn, int log2n, int prec, hipStream_t s) {
   const unsigned cnt = (unsigned)L.count;
   if (stage == ST_KK_FRONT) {
-    if (log2n == 13) launch_front<13>(L, maxn, s);
-    else launch_front<14>(L, maxn, s);
+    if (log2n == 13) {
+      if (prec == 1) launch_front<13, 1>(L, maxn, s);
+      else if (prec == 2) launch_front<13, 2>(L, maxn, s);
+      else launch_front<13, 0>(L, maxn, s);
+    } else {
+      if (prec == 1) launch_front<14, 1>(L, maxn, s);
+      else if (prec == 2) launch_front<14, 2>(L, maxn, s);
+      else launch_front<14, 0>(L, maxn, s);
+    }
   } else if (stage == ST_KK_FINALIZE) {
     const int64_t nd = maxn / 2;
     hipLaunchKernelGGL(kk_finalize, dim3((unsigned)((nd + 1023) / 1024), cnt), dim3(256), 0, s, L);

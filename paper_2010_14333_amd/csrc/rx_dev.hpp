@@ -4,6 +4,31 @@
 
 #define RX_WAVE 64
 
+typedef __bf16 rx_bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 rx_f16x8 __attribute__((ext_vector_type(8)));
+typedef float rx_f32x4 __attribute__((ext_vector_type(4)));
+
+// Narrow operand type of the precision form (PREC 1: BF16, 2: FP16), with
+// round-to-nearest-even conversion from FP32.
+template <int PREC> struct NarrowT;
+template <> struct NarrowT<1> {
+  using vec = rx_bf16x8;
+  __device__ static __bf16 cvt(float v) { return (__bf16)v; }
+  __device__ static rx_f32x4 mfma(vec a, vec b, rx_f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct NarrowT<2> {
+  using vec = rx_f16x8;
+  __device__ static _Float16 cvt(float v) { return (_Float16)v; }
+  __device__ static rx_f32x4 mfma(vec a, vec b, rx_f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
+// Operand layout of v_mfma_f32_16x16x32_{bf16,f16}: lane l supplies
+// A[l % 16][8 (l / 16) + j] and B[8 (l / 16) + j][l % 16], j = 0..7, and
+// receives D[4 (l / 16) + j][l % 16], j = 0..3.
+
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }

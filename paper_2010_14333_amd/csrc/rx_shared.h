@@ -74,6 +74,6 @@ enum RxStage {
   ST_KK_FRONT = 0, ST_KK_FINALIZE, ST_PAM_SUM, ST_PAM_MF, ST_PAM_GAVG, ST_PAM_UNWRAP, ST_PAM_FARROW,
   ST_PREFIX, ST_BLOCKS, ST_KK_VV, ST_DECIDE, ST_COUNT
 };
-void rx_launch_kk_stage(int stage, const RxLaunch &L, int64_t maxn, int log2n, hipStream_t s);
+void rx_launch_kk_stage(int stage, const RxLaunch &L, int64_t maxn, int log2n, int prec, hipStream_t s);
 void rx_launch_pam_stage(int stage, const RxLaunch &L, int64_t maxn, hipStream_t s);
-void rx_launch_eq_stage(int stage, const RxLaunch &L, int64_t maxn, int kk, int ffe_taps, hipStream_t s);
+void rx_launch_eq_stage(int stage, const RxLaunch &L, int64_t maxn, int kk, int ffe_taps, int prec, hipStream_t s);
