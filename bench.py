@@ -43,6 +43,7 @@ def main():
     ap.add_argument("--graph", type=int, default=0)
     ap.add_argument("--cpu-buffers", type=int, default=8)
     ap.add_argument("--copy-probe", type=int, default=1, help="run a 256 MiB device copy (counter scale)")
+    ap.add_argument("--forms", default="bf16,fp16", help="precision forms timed beside the plain chain")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the receiver path is "
@@ -60,35 +61,49 @@ def main():
     gens = [synth.kk_2e22(synth.KK_16QAM, index=i) for i in range(a.distinct)]
     log(f"[bench] generated {a.distinct} KK-16QAM buffers in {time.time() - t0:.1f}s")
     bufs = [torch.from_numpy(g["packed"]).to(dev) for g in gens]
-    recs = [rx.Receiver(rx.RX_KK_16QAM, gens[i % a.distinct]["seed"], max_samples=N,
-                        flags=rx.RX_PROFILE if i == 0 else 0) for i in range(a.batch)]
-    outs = [torch.empty(r.bits_bytes(N), dtype=torch.uint8, device=dev) for r in recs]
-    hs = [r.h for r in recs]
-    bp = [bufs[i % a.distinct].data_ptr() for i in range(a.batch)]
-    op = [o.data_ptr() for o in outs]
-    ns = [N] * a.batch
+    def run_form(precision, profile):
+        recs = [rx.Receiver(rx.RX_KK_16QAM, gens[i % a.distinct]["seed"], max_samples=N,
+                            flags=rx.RX_PROFILE if (i == 0 and profile) else 0, precision=precision)
+                for i in range(a.batch)]
+        outs = [torch.empty(r.bits_bytes(N), dtype=torch.uint8, device=dev) for r in recs]
+        hs = [r.h for r in recs]
+        bp = [bufs[i % a.distinct].data_ptr() for i in range(a.batch)]
+        op = [o.data_ptr() for o in outs]
+        ns = [N] * a.batch
 
-    def step():
-        rx.rx_process_batch(hs, bp, ns, op, graph=bool(a.graph))
+        def step():
+            rx.rx_process_batch(hs, bp, ns, op, graph=bool(a.graph))
 
-    for _ in range(a.warmup):
-        step()
-    torch.cuda.synchronize()
-    rx.rx_stage_times(hs[0], reset=True)
-    for r in recs:
-        r.reset()
-    log(f"[bench] warmup done ({a.warmup} steps x {a.batch} buffers)")
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(a.steps):
-        step()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t1
-    log(f"[bench] timed {a.steps} steps in {wall:.3f}s")
-    stages = rx.rx_stage_times(hs[0])
-    errs = [r.errors() for r in recs]
-    bits = sum(e["bits"] for e in errs)
-    berr = sum(e["bit_errors"] for e in errs)
+        for _ in range(a.warmup):
+            step()
+        torch.cuda.synchronize()
+        if profile:
+            rx.rx_stage_times(hs[0], reset=True)
+        for r in recs:
+            r.reset()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(a.steps):
+            step()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t1
+        stages = rx.rx_stage_times(hs[0]) if profile else {}
+        errs = [r.errors() for r in recs]
+        for r in recs:
+            r.close()
+        bits = sum(e["bits"] for e in errs)
+        berr = sum(e["bit_errors"] for e in errs)
+        return wall, stages, (berr / bits if bits else None)
+
+    wall, stages, ber = run_form(rx.RX_FP32, True)
+    log(f"[bench] plain chain: {a.steps} steps x {a.batch} buffers in {wall:.3f}s")
+    forms = {}
+    for name in [f for f in a.forms.split(",") if f]:
+        prec = {"bf16": rx.RX_BF16, "fp16": rx.RX_FP16}[name]
+        w2, _, b2 = run_form(prec, False)
+        forms[name] = {"value": round(a.batch * N / (w2 / a.steps) / 1e9, 3), "unit": "Gsamples/s",
+                       "ms_per_step": round(w2 * 1e3 / a.steps, 4), "ber": b2}
+        log(f"[bench] {name} form: {forms[name]['value']} Gs/s, BER {b2}")
 
     ms_step = wall * 1e3 / a.steps
     samples = a.batch * N
@@ -136,14 +151,13 @@ def main():
                                "at 4 Gs/s (1 GBaud, CSPR 10 dB, 22 dB SNR)",
                    "buffers_per_step": a.batch, "samples_per_buffer": N, "graph": bool(a.graph)},
         "realtime_factor": round(gsps / 4.0, 2),
-        "ber": berr / bits if bits else None,
+        "ber": ber,
+        "forms": forms,
         "stage_us_per_buffer": per_stage_us_per_buffer,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-    for r in recs:
-        r.close()
 
 
 if __name__ == "__main__":

@@ -75,6 +75,8 @@ enum {
   RX_ST_BLOCKS,         /* block-parallel DD-LMS FFE */
   RX_ST_KK_VV,          /* Viterbi-Viterbi block phase, unwrap */
   RX_ST_DECIDE,         /* decisions, demapping, packing, error counting */
+  RX_ST_MLP_INFER,      /* learned equaliser, BF16 MFMA inference */
+  RX_ST_MLP_JUDGE,      /* MLP vs LMS errors on the known prefix (sets the fallback) */
   RX_NSTAGES
 };
 
@@ -159,6 +161,60 @@ int rx_errors_reset(rx_handle h);
  * (synchronises).  bytes must equal the stage's size for that buffer.
  * RX_E_STATE if nothing was processed or the stage needs RX_DEBUG_KEEP. */
 int rx_debug_fetch(rx_handle h, int stage, void *host_dst, size_t bytes);
+
+/* ---- Learned equaliser (PAM formats, equalizer = RX_EQ_MLP) ------------
+ * A 31 -> 64 ReLU -> 64 ReLU -> 1 network over the 31 timing-corrected
+ * samples centred on each symbol replaces the block DD-LMS FFE (the paper's
+ * PAM chain equalises with an LMS FFE, Sec. 2, first paragraph).  It is
+ * trained in FP32 by the library's own forward/backward/Adam kernels and
+ * runs as BF16 MFMA inference.  LMS stays the fallback and the judge: per
+ * buffer, if the network makes more decision errors than the LMS taps on
+ * the known prefix, the block DD-LMS runs instead (counted in
+ * rx_stats.fallbacks).  rx_process on an MLP handle without weights runs
+ * LMS and returns RX_W_FALLBACK.
+ * Parameters: RX_MLP_PARAMS floats packed W1[64][31], b1[64], W2[64][64],
+ * b2[64], W3[64], b3. */
+#define RX_MLP_PARAMS 6273
+
+typedef struct {
+  uint32_t struct_size;   /* sizeof(rx_train_cfg) */
+  int32_t epochs;         /* 2 */
+  int32_t batch;          /* minibatch: 1024 */
+  int32_t max_steps;      /* 0 = epochs * floor(n / batch) steps, else at most this many */
+  double lr, beta1, beta2, eps;   /* Adam: 1e-3, 0.9, 0.999, 1e-8 */
+  uint64_t init_seed;     /* Kaiming-uniform start drawn from SplitMix64(init_seed) if init is NULL */
+  const float *init;      /* host pointer to RX_MLP_PARAMS start values, or NULL */
+} rx_train_cfg;
+
+int rx_train_cfg_default(rx_train_cfg *c);
+int rx_mlp_param_count(void);
+/* Row order of training: step t uses rows (mult * (t * batch + e)) mod n,
+ * e < batch, mult = this value (the first odd number >= 1000003 coprime to n). */
+int rx_mlp_order_multiplier(int64_t n);
+
+/* Train on training buffers whose reference sequences have seeds[i]: each
+ * buffer runs the PAM front end and prefix stage, every symbol in
+ * [64, n_sym - 64) becomes one (window, level) row, then Adam on all rows.
+ * Synchronous.  *final_loss (may be NULL) = last minibatch MSE.
+ * RX_E_UNSUPPORTED on KK handles. */
+int rx_train_mlp(rx_handle h, const void *const *dev_buffers, const size_t *n_samples, const uint64_t *seeds,
+                 int count, const rx_train_cfg *c, double *final_loss);
+/* Train on a given set: dev_x = n rows of 32 floats (31 samples + 0),
+ * dev_t = n target levels (device memory).  Synchronous. */
+int rx_train_mlp_data(rx_handle h, const float *dev_x, const float *dev_t, size_t n, const rx_train_cfg *c,
+                      double *final_loss);
+/* Gradient of (1/n) sum (y - t)^2 at the handle's weights over n <= 65536
+ * rows (device x, t as above) into dev_grad[RX_MLP_PARAMS].  Synchronous. */
+int rx_mlp_grad(rx_handle h, const float *dev_x, const float *dev_t, size_t n, float *dev_grad, double *loss);
+/* BF16 MFMA inference (the kernel of the chain's MLP stage) on given rows:
+ * dev_x = n rows of 32 floats, dev_y = n outputs.  Asynchronous. */
+int rx_mlp_infer(rx_handle h, const float *dev_x, size_t n, float *dev_y);
+/* Copy weights in/out (host memory), or to/from a file ("RXMLP001", uint32
+ * count, float32 little-endian). */
+int rx_set_mlp(rx_handle h, const float *host_params);
+int rx_get_mlp(rx_handle h, float *host_params);
+int rx_save_weights(rx_handle h, const char *path);
+int rx_load_weights(rx_handle h, const char *path);
 
 /* Stage timing of handles created with RX_PROFILE: synchronises the stream
  * and returns, per stage, the accumulated milliseconds and launch count of

@@ -25,9 +25,13 @@ RX_DEBUG_KEEP = 0x1
 
 RX_PROFILE = 0x2
 STAGES = ("kk_front", "kk_finalize", "pam_sum", "pam_mf", "pam_gavg", "pam_unwrap", "pam_farrow",
-          "prefix", "blocks", "kk_vv", "decide")
+          "prefix", "blocks", "kk_vv", "decide", "mlp_infer", "mlp_judge")
+RX_MLP_PARAMS = 6273
 EXPORTS = ("rx_params_default", "rx_create", "rx_process", "rx_process_batch", "rx_errors",
-           "rx_errors_reset", "rx_debug_fetch", "rx_stage_times", "rx_destroy", "rx_strerror")
+           "rx_errors_reset", "rx_debug_fetch", "rx_train_cfg_default", "rx_mlp_param_count",
+           "rx_mlp_order_multiplier", "rx_train_mlp", "rx_train_mlp_data", "rx_mlp_grad", "rx_mlp_infer",
+           "rx_set_mlp", "rx_get_mlp", "rx_save_weights", "rx_load_weights", "rx_stage_times",
+           "rx_destroy", "rx_strerror")
 
 
 class rx_params(ctypes.Structure):
@@ -44,6 +48,13 @@ class rx_params(ctypes.Structure):
 class rx_stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in
                 ("buffers", "symbols", "bits", "bit_errors", "symbol_errors", "fallbacks")]
+
+
+class rx_train_cfg(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("epochs", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("max_steps", ctypes.c_int32), ("lr", ctypes.c_double), ("beta1", ctypes.c_double),
+                ("beta2", ctypes.c_double), ("eps", ctypes.c_double), ("init_seed", ctypes.c_uint64),
+                ("init", ctypes.POINTER(ctypes.c_float))]
 
 
 class RxError(RuntimeError):
@@ -73,6 +84,20 @@ def lib() -> ctypes.CDLL:
         L.rx_debug_fetch.argtypes = [vp, i32, vp, sz]
         L.rx_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_uint64), i32]
+        fp = ctypes.POINTER(ctypes.c_float)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.rx_train_cfg_default.argtypes = [ctypes.POINTER(rx_train_cfg)]
+        L.rx_mlp_param_count.argtypes = []
+        L.rx_mlp_order_multiplier.argtypes = [ctypes.c_int64]
+        L.rx_train_mlp.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(sz), ctypes.POINTER(ctypes.c_uint64),
+                                   i32, ctypes.POINTER(rx_train_cfg), dp]
+        L.rx_train_mlp_data.argtypes = [vp, vp, vp, sz, ctypes.POINTER(rx_train_cfg), dp]
+        L.rx_mlp_grad.argtypes = [vp, vp, vp, sz, vp, dp]
+        L.rx_mlp_infer.argtypes = [vp, vp, sz, vp]
+        L.rx_set_mlp.argtypes = [vp, fp]
+        L.rx_get_mlp.argtypes = [vp, fp]
+        L.rx_save_weights.argtypes = [vp, ctypes.c_char_p]
+        L.rx_load_weights.argtypes = [vp, ctypes.c_char_p]
         L.rx_destroy.argtypes = [vp]
         L.rx_destroy.restype = None
         L.rx_strerror.argtypes = [i32]
@@ -138,6 +163,76 @@ def rx_debug_fetch(h: int, stage: int, nbytes: int) -> bytes:
     return buf.raw
 
 
+def rx_train_cfg_default() -> rx_train_cfg:
+    c = rx_train_cfg()
+    _check(lib().rx_train_cfg_default(ctypes.byref(c)), "rx_train_cfg_default")
+    return c
+
+
+def rx_mlp_order_multiplier(n: int) -> int:
+    return int(lib().rx_mlp_order_multiplier(n))
+
+
+def _cfg(cfg, init):
+    c = cfg if cfg is not None else rx_train_cfg_default()
+    keep = None
+    if init is not None:
+        keep = np.ascontiguousarray(init, dtype=np.float32)
+        assert keep.size == RX_MLP_PARAMS
+        c.init = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    return c, keep
+
+
+def rx_train_mlp(h: int, dev_buffers, n_samples, seeds, cfg=None, init=None) -> float:
+    c, keep = _cfg(cfg, init)
+    k = len(dev_buffers)
+    B = (ctypes.c_void_p * k)(*dev_buffers)
+    N = (ctypes.c_size_t * k)(*n_samples)
+    S = (ctypes.c_uint64 * k)(*seeds)
+    loss = ctypes.c_double()
+    _check(lib().rx_train_mlp(h, B, N, S, k, ctypes.byref(c), ctypes.byref(loss)), "rx_train_mlp")
+    del keep
+    return loss.value
+
+
+def rx_train_mlp_data(h: int, dev_x: int, dev_t: int, n: int, cfg=None, init=None) -> float:
+    c, keep = _cfg(cfg, init)
+    loss = ctypes.c_double()
+    _check(lib().rx_train_mlp_data(h, dev_x, dev_t, n, ctypes.byref(c), ctypes.byref(loss)), "rx_train_mlp_data")
+    del keep
+    return loss.value
+
+
+def rx_mlp_grad(h: int, dev_x: int, dev_t: int, n: int, dev_grad: int) -> float:
+    loss = ctypes.c_double()
+    _check(lib().rx_mlp_grad(h, dev_x, dev_t, n, dev_grad, ctypes.byref(loss)), "rx_mlp_grad")
+    return loss.value
+
+
+def rx_mlp_infer(h: int, dev_x: int, n: int, dev_y: int) -> None:
+    _check(lib().rx_mlp_infer(h, dev_x, n, dev_y), "rx_mlp_infer")
+
+
+def rx_set_mlp(h: int, params) -> None:
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    assert a.size == RX_MLP_PARAMS
+    _check(lib().rx_set_mlp(h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))), "rx_set_mlp")
+
+
+def rx_get_mlp(h: int) -> np.ndarray:
+    a = np.zeros(RX_MLP_PARAMS, dtype=np.float32)
+    _check(lib().rx_get_mlp(h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))), "rx_get_mlp")
+    return a
+
+
+def rx_save_weights(h: int, path: str) -> None:
+    _check(lib().rx_save_weights(h, path.encode()), "rx_save_weights")
+
+
+def rx_load_weights(h: int, path: str) -> None:
+    _check(lib().rx_load_weights(h, path.encode()), "rx_load_weights")
+
+
 def rx_stage_times(h: int, reset: bool = False) -> dict:
     """{stage name: (total ms, launches)} since the last reset."""
     n = len(STAGES)
@@ -184,7 +279,9 @@ class Receiver:
         import torch
         if out is None:
             out = torch.empty(self.bits_bytes(n_samples), dtype=torch.uint8, device=buf.device)
-        rx_process(self.h, buf.data_ptr(), n_samples, out.data_ptr())
+        nb = ctypes.c_size_t()
+        self.last_status = _check(lib().rx_process(self.h, buf.data_ptr(), n_samples, out.data_ptr(),
+                                                   ctypes.byref(nb)), "rx_process")
         return out
 
     def errors(self) -> dict:

@@ -113,6 +113,8 @@ struct rx_ctx {
   Alloc mem;
   int64_t last_n = 0;
   GraphCache graph;
+  float *mlp = nullptr;   // learned-equaliser parameters (device), allocated with the handle
+  bool mlp_ready = false;
   // stage timing (RX_PROFILE): events recorded around every stage launch
   struct Pending { int stage; hipEvent_t a, b; };
   std::vector<Pending> pending;
@@ -193,7 +195,8 @@ int rx_create(rx_format fmt, double baud, double fs, const rx_params *pin, rx_ha
   if (!(p.rolloff > 0 && p.rolloff <= 1) || !(p.mu > 0) || !(p.mu_cma > 0)) return RX_E_INVALID;
   if (p.precision != RX_FP32 && p.precision != RX_BF16 && p.precision != RX_FP16) return RX_E_INVALID;
   if (p.precision != RX_FP32 && (!kk || p.ffe_taps != 21)) return RX_E_UNSUPPORTED;
-  if (p.equalizer != RX_EQ_LMS) return RX_E_UNSUPPORTED;
+  if (p.equalizer != RX_EQ_LMS && p.equalizer != RX_EQ_MLP) return RX_E_INVALID;
+  if (p.equalizer == RX_EQ_MLP && kk) return RX_E_UNSUPPORTED;
   if (kk && !(std::fabs(p.carrier_hz) < fs / 2)) return RX_E_INVALID;
   if (p.max_samples < 65536 || p.max_samples > ((uint64_t)1 << 26) || p.max_samples % 1024) return RX_E_INVALID;
 
@@ -283,6 +286,10 @@ int rx_create(rx_format fmt, double baud, double fs, const rx_params *pin, rx_ha
     J.soft = A.get<float2>(L / 2);
     ok = J.y && J.xr && J.upart && J.part2 && J.gard && J.delta && J.soft;
   }
+  if (ok && !kk) {
+    h->mlp = A.get<float>(rx_mlp_params());
+    ok = h->mlp != nullptr;
+  }
   h->dsc = ok ? A.get<RxScalars>(1) : nullptr;
   h->dj = ok && h->dsc ? A.get<RxJob>(1) : nullptr;
   if (!h->dj) {
@@ -310,6 +317,10 @@ static int check_n(rx_handle h, size_t n) {
 static const int KK_STAGES[] = {ST_KK_FRONT, ST_KK_FINALIZE, ST_PREFIX, ST_BLOCKS, ST_KK_VV, ST_DECIDE};
 static const int PAM_STAGES[] = {ST_PAM_SUM, ST_PAM_MF, ST_PAM_GAVG, ST_PAM_UNWRAP, ST_PAM_FARROW,
                                  ST_PREFIX, ST_BLOCKS, ST_DECIDE};
+static const int PAM_MLP_STAGES[] = {ST_PAM_SUM, ST_PAM_MF, ST_PAM_GAVG, ST_PAM_UNWRAP, ST_PAM_FARROW,
+                                     ST_PREFIX, ST_MLP_INFER, ST_MLP_JUDGE, ST_BLOCKS, ST_DECIDE};
+
+static bool uses_mlp(const rx_ctx *h) { return h->p.equalizer == RX_EQ_MLP && h->mlp_ready; }
 
 // Launch the chains of one batch: jobs grouped by (chain, FFT size, taps),
 // each group one launch per stage.  With RX_PROFILE on the first handle
@@ -326,7 +337,7 @@ static int enqueue(rx_handle const *hs, const void *const *bufs, const size_t *n
     for (int j = i; j < count; j++) {
       const rx_ctx *b = hs[j];
       if (done[j] || b->kk != a->kk || b->log2n != a->log2n || b->p.ffe_taps != a->p.ffe_taps ||
-          b->p.precision != a->p.precision)
+          b->p.precision != a->p.precision || uses_mlp(b) != uses_mlp(a))
         continue;
       done[j] = true;
       L.job[L.count] = b->dj;
@@ -336,8 +347,8 @@ static int enqueue(rx_handle const *hs, const void *const *bufs, const size_t *n
       L.count++;
       if ((int64_t)ns[j] > maxn) maxn = (int64_t)ns[j];
     }
-    const int *st = a->kk ? KK_STAGES : PAM_STAGES;
-    const int nst = a->kk ? 6 : 8;
+    const int *st = a->kk ? KK_STAGES : (uses_mlp(a) ? PAM_MLP_STAGES : PAM_STAGES);
+    const int nst = a->kk ? 6 : (uses_mlp(a) ? 10 : 8);
     for (int k = 0; k < nst; k++) {
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (prof) {
@@ -348,6 +359,8 @@ static int enqueue(rx_handle const *hs, const void *const *bufs, const size_t *n
         rx_launch_kk_stage(st[k], L, maxn, a->log2n, a->p.precision, s);
       else if (st[k] >= ST_PAM_SUM && st[k] <= ST_PAM_FARROW)
         rx_launch_pam_stage(st[k], L, maxn, s);
+      else if (st[k] == ST_MLP_INFER || st[k] == ST_MLP_JUDGE)
+        rx_launch_mlp_stage(st[k], L, maxn, s);
       else
         rx_launch_eq_stage(st[k], L, maxn, a->kk, a->p.ffe_taps, a->p.precision, s);
       if (prof) {
@@ -369,7 +382,7 @@ int rx_process(rx_handle h, const void *dev_buffer, size_t n_samples, void *dev_
   if (rc) return rc;
   h->last_n = (int64_t)n_samples;
   if (n_bits_out) *n_bits_out = n_samples / h->sps * h->bps;
-  return RX_OK;
+  return (h->p.equalizer == RX_EQ_MLP && !h->mlp_ready) ? RX_W_FALLBACK : RX_OK;
 }
 
 int rx_process_batch(const rx_handle *hs, const void *const *bufs, const size_t *ns, void *const *bits, int count,
@@ -504,6 +517,252 @@ int rx_debug_fetch(rx_handle h, int stage, void *dst, size_t bytes) {
   if (bytes != need) return RX_E_INVALID;
   e = hipMemcpy(dst, src, need, hipMemcpyDeviceToHost);
   return e == hipSuccess ? RX_OK : fail_hip(e, "hipMemcpy debug");
+}
+
+
+// ---- learned equaliser ----------------------------------------------------
+static int upload_job(rx_handle h) {
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess) e = hipMemcpy(h->dj, &h->hj, sizeof(RxJob), hipMemcpyHostToDevice);
+  return e == hipSuccess ? RX_OK : fail_hip(e, "job upload");
+}
+
+int rx_train_cfg_default(rx_train_cfg *c) {
+  if (!c) return RX_E_INVALID;
+  std::memset(c, 0, sizeof(*c));
+  c->struct_size = sizeof(rx_train_cfg);
+  c->epochs = 2;
+  c->batch = 1024;
+  c->max_steps = 0;
+  c->lr = 1e-3;
+  c->beta1 = 0.9;
+  c->beta2 = 0.999;
+  c->eps = 1e-8;
+  c->init_seed = 1;
+  c->init = nullptr;
+  return RX_OK;
+}
+
+int rx_mlp_param_count(void) { return rx_mlp_params(); }
+
+int rx_set_mlp(rx_handle h, const float *host) {
+  if (!h || !host) return RX_E_INVALID;
+  if (!h->mlp) return RX_E_UNSUPPORTED;
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess) e = hipMemcpy(h->mlp, host, rx_mlp_params() * sizeof(float), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail_hip(e, "rx_set_mlp");
+  h->mlp_ready = true;
+  h->hj.mlp = h->p.equalizer == RX_EQ_MLP ? h->mlp : nullptr;
+  return upload_job(h);
+}
+
+int rx_get_mlp(rx_handle h, float *host) {
+  if (!h || !host) return RX_E_INVALID;
+  if (!h->mlp) return RX_E_UNSUPPORTED;
+  if (!h->mlp_ready) return RX_E_STATE;
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess) e = hipMemcpy(host, h->mlp, rx_mlp_params() * sizeof(float), hipMemcpyDeviceToHost);
+  return e == hipSuccess ? RX_OK : fail_hip(e, "rx_get_mlp");
+}
+
+static uint64_t mix64(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + (k + 1u) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Kaiming-uniform weights U(-sqrt(6/fan_in), +sqrt(6/fan_in)), zero biases.
+static std::vector<float> mlp_init(uint64_t seed) {
+  const int np = rx_mlp_params();
+  std::vector<float> w(np, 0.0f);
+  auto fill = [&](int off, int count, int fan_in) {
+    const double b = std::sqrt(6.0 / fan_in);
+    for (int i = 0; i < count; i++) {
+      const double u = (double)(mix64(seed, (uint64_t)(off + i)) >> 11) * (1.0 / 9007199254740992.0);
+      w[off + i] = (float)((2.0 * u - 1.0) * b);
+    }
+  };
+  fill(0, 64 * 31, 31);
+  fill(64 * 31 + 64, 64 * 64, 64);
+  fill(64 * 31 + 64 + 64 * 64 + 64, 64, 64);
+  return w;
+}
+
+static int64_t gcd64(int64_t a, int64_t b) { return b ? gcd64(b, a % b) : a; }
+
+int rx_mlp_order_multiplier(int64_t ntrain) {
+  int64_t m = 1000003;
+  while (gcd64(m, ntrain) != 1) m += 2;
+  return (int)m;
+}
+
+int rx_train_mlp_data(rx_handle h, const float *dev_x, const float *dev_t, size_t ntrain, const rx_train_cfg *cin,
+                      double *final_loss) {
+  if (!h || !dev_x || !dev_t || ntrain == 0) return RX_E_INVALID;
+  if (!h->mlp) return RX_E_UNSUPPORTED;
+  rx_train_cfg c;
+  rx_train_cfg_default(&c);
+  if (cin) {
+    if (cin->struct_size != sizeof(rx_train_cfg)) return RX_E_INVALID;
+    c = *cin;
+  }
+  if (c.batch < 1 || c.batch > 65536 || c.epochs < 1 || !(c.lr > 0)) return RX_E_INVALID;
+  const int np = rx_mlp_params();
+  std::vector<float> w0 = c.init ? std::vector<float>(c.init, c.init + np) : mlp_init(c.init_seed);
+  const int nwg = (c.batch + 63) / 64;
+  float *m = nullptr, *v = nullptr, *part = nullptr;
+  double *loss = nullptr;
+  hipError_t e = hipMalloc(&m, np * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&v, np * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&part, (size_t)nwg * np * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&loss, nwg * sizeof(double));
+  if (e == hipSuccess) e = hipMemcpy(h->mlp, w0.data(), np * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(m, 0, np * sizeof(float));
+  if (e == hipSuccess) e = hipMemset(v, 0, np * sizeof(float));
+  int64_t steps = (int64_t)c.epochs * ((int64_t)ntrain / c.batch);
+  if (steps < 1) steps = 1;
+  if (c.max_steps > 0 && c.max_steps < steps) steps = c.max_steps;
+  const int64_t mult = rx_mlp_order_multiplier((int64_t)ntrain);
+  for (int64_t t = 0; t < steps && e == hipSuccess; t++) {
+    const double c1 = 1.0 - std::pow(c.beta1, (double)(t + 1)), c2 = 1.0 - std::pow(c.beta2, (double)(t + 1));
+    rx_mlp_step(dev_x, dev_t, (int64_t)ntrain, t * c.batch, c.batch, mult, h->mlp, m, v, part, loss, nullptr, 1,
+                (float)c.lr, (float)c.beta1, (float)c.beta2, (float)c.eps, (float)c1, (float)c2, h->stream);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess && final_loss) {
+    std::vector<double> lp(nwg);
+    e = hipMemcpy(lp.data(), loss, nwg * sizeof(double), hipMemcpyDeviceToHost);
+    double acc = 0.0;
+    for (double x : lp) acc += x;
+    *final_loss = acc / c.batch;
+  }
+  hipFree(m);
+  hipFree(v);
+  hipFree(part);
+  hipFree(loss);
+  if (e != hipSuccess) return fail_hip(e, "rx_train_mlp_data");
+  h->mlp_ready = true;
+  h->hj.mlp = h->p.equalizer == RX_EQ_MLP ? h->mlp : nullptr;
+  return upload_job(h);
+}
+
+int rx_train_mlp(rx_handle h, const void *const *dev_buffers, const size_t *n_samples, const uint64_t *seeds,
+                 int count, const rx_train_cfg *c, double *final_loss) {
+  if (!h || !dev_buffers || !n_samples || !seeds || count < 1) return RX_E_INVALID;
+  if (h->kk || !h->mlp) return RX_E_UNSUPPORTED;
+  int64_t rows = 0;
+  for (int i = 0; i < count; i++) {
+    int rc = check_n(h, n_samples[i]);
+    if (rc) return rc;
+    rows += (int64_t)n_samples[i] / 2 - 2 * RX_GUARD;
+  }
+  float *X = nullptr, *T = nullptr;
+  hipError_t e = hipMalloc(&X, (size_t)rows * 32 * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&T, (size_t)rows * sizeof(float));
+  if (e != hipSuccess) {
+    hipFree(X);
+    return RX_E_NOMEM;
+  }
+  const uint64_t seed0 = h->hj.seed;
+  const float *mlp0 = h->hj.mlp;
+  h->hj.mlp = nullptr;   // training buffers run the plain front end and prefix
+  int rc = RX_OK;
+  int64_t row0 = 0;
+  for (int i = 0; i < count && rc == RX_OK; i++) {
+    h->hj.seed = seeds[i];
+    rc = upload_job(h);
+    if (rc) break;
+    RxLaunch L{};
+    L.job[0] = h->dj;
+    L.in[0] = static_cast<const uint8_t *>(dev_buffers[i]);
+    L.n[0] = (int64_t)n_samples[i];
+    L.count = 1;
+    for (int st = ST_PAM_SUM; st <= ST_PAM_FARROW; st++) rx_launch_pam_stage(st, L, L.n[0], h->stream);
+    rx_launch_eq_stage(ST_PREFIX, L, L.n[0], 0, h->p.ffe_taps, 0, h->stream);
+    rx_mlp_windows(L, X, T, row0, h->stream);
+    row0 += L.n[0] / 2 - 2 * RX_GUARD;
+    e = hipGetLastError();
+    if (e != hipSuccess) rc = fail_hip(e, "rx_train_mlp windows");
+  }
+  if (rc == RX_OK) e = hipStreamSynchronize(h->stream);
+  h->hj.seed = seed0;
+  h->hj.mlp = mlp0;
+  int rc2 = upload_job(h);
+  if (rc == RX_OK) rc = rc2;
+  if (rc == RX_OK) rc = rx_train_mlp_data(h, X, T, (size_t)rows, c, final_loss);
+  hipFree(X);
+  hipFree(T);
+  return rc;
+}
+
+int rx_mlp_grad(rx_handle h, const float *dev_x, const float *dev_t, size_t n, float *dev_grad, double *loss_out) {
+  if (!h || !dev_x || !dev_t || !dev_grad || n == 0 || n > 65536) return RX_E_INVALID;
+  if (!h->mlp) return RX_E_UNSUPPORTED;
+  if (!h->mlp_ready) return RX_E_STATE;
+  const int np = rx_mlp_params();
+  const int nwg = ((int)n + 63) / 64;
+  float *part = nullptr;
+  double *loss = nullptr;
+  hipError_t e = hipMalloc(&part, (size_t)nwg * np * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&loss, nwg * sizeof(double));
+  if (e == hipSuccess) {
+    rx_mlp_step(dev_x, dev_t, (int64_t)n, 0, (int)n, 0, h->mlp, nullptr, nullptr, part, loss, dev_grad, 0, 0.f, 0.f,
+                0.f, 0.f, 1.f, 1.f, h->stream);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess && loss_out) {
+    std::vector<double> lp(nwg);
+    e = hipMemcpy(lp.data(), loss, nwg * sizeof(double), hipMemcpyDeviceToHost);
+    double acc = 0.0;
+    for (double x : lp) acc += x;
+    *loss_out = acc / (double)n;
+  }
+  hipFree(part);
+  hipFree(loss);
+  return e == hipSuccess ? RX_OK : fail_hip(e, "rx_mlp_grad");
+}
+
+int rx_mlp_infer(rx_handle h, const float *dev_x, size_t n, float *dev_y) {
+  if (!h || !dev_x || !dev_y || n == 0) return RX_E_INVALID;
+  if (!h->mlp) return RX_E_UNSUPPORTED;
+  if (!h->mlp_ready) return RX_E_STATE;
+  rx_mlp_infer_rows(h->mlp, dev_x, (int64_t)n, dev_y, h->stream);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? RX_OK : fail_hip(e, "rx_mlp_infer");
+}
+
+// Weights file: "RXMLP001", uint32 parameter count, float32 parameters (LE).
+int rx_save_weights(rx_handle h, const char *path) {
+  if (!h || !path) return RX_E_INVALID;
+  const int np = rx_mlp_params();
+  std::vector<float> w(np);
+  int rc = rx_get_mlp(h, w.data());
+  if (rc) return rc;
+  FILE *f = std::fopen(path, "wb");
+  if (!f) return RX_E_INVALID;
+  const uint32_t cnt = (uint32_t)np;
+  bool ok = std::fwrite("RXMLP001", 1, 8, f) == 8 && std::fwrite(&cnt, 4, 1, f) == 1 &&
+            std::fwrite(w.data(), 4, np, f) == (size_t)np;
+  ok = (std::fclose(f) == 0) && ok;
+  return ok ? RX_OK : RX_E_INVALID;
+}
+
+int rx_load_weights(rx_handle h, const char *path) {
+  if (!h || !path) return RX_E_INVALID;
+  const int np = rx_mlp_params();
+  FILE *f = std::fopen(path, "rb");
+  if (!f) return RX_E_INVALID;
+  char magic[8];
+  uint32_t cnt = 0;
+  std::vector<float> w(np);
+  bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "RXMLP001", 8) == 0 &&
+            std::fread(&cnt, 4, 1, f) == 1 && cnt == (uint32_t)np && std::fread(w.data(), 4, np, f) == (size_t)np;
+  std::fclose(f);
+  if (!ok) return RX_E_INVALID;
+  return rx_set_mlp(h, w.data());
 }
 
 int rx_stage_times(rx_handle h, double *ms, uint64_t *launches, int max_stages) {

@@ -194,6 +194,7 @@ __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
   const int64_t nb = nsym / blk;
   const int64_t b0 = (int64_t)blockIdx.x * 256;
   if (b0 >= nb) return;
+  if (J.mlp && !J.sc->fallback) return;   // the learned equaliser's output stands
   const int64_t b = b0 + threadIdx.x;
   const bool active = b < nb;
   constexpr int C = (K - 1) / 2;

@@ -1,0 +1,338 @@
+// Learned equaliser for the PAM chain: an MLP 31 -> 64 ReLU -> 64 ReLU -> 1
+// over 31 timing-corrected samples centred on each symbol, used in place of
+// the block DD-LMS FFE (the paper equalises with an LMS FFE, Sec. 2 ¶1; the
+// network replaces it on nonlinear links).  Training: FP32 forward,
+// backward and Adam (Kingma & Ba 2015) kernels.  Inference: BF16 operands on
+// MFMA with FP32 accumulation.  Parameters are packed W1[64][31], b1[64],
+// W2[64][64], b2[64], W3[64], b3.
+#include "rx_dev.hpp"
+
+#define MI 31
+#define MH 64
+#define MP (MH * MI + MH + MH * MH + MH + MH + 1)
+#define OFF_B1 (MH * MI)
+#define OFF_W2 (OFF_B1 + MH)
+#define OFF_B2 (OFF_W2 + MH * MH)
+#define OFF_W3 (OFF_B2 + MH)
+#define OFF_B3 (OFF_W3 + MH)
+#define SPW 64   // samples per workgroup in the training kernels
+
+// ---- training -------------------------------------------------------------
+// Partial gradient of the minibatch loss (1/B) sum (y - t)^2 over the SPW
+// samples of this workgroup.  Sample e of the minibatch is row
+// (mult * (i0 + e)) mod ntrain of the training set (mult coprime to ntrain:
+// a permutation per epoch), or row e when mult == 0.
+__global__ __launch_bounds__(256) void mlp_grad_partial(const float *__restrict__ p, const float *__restrict__ X,
+                                                        const float *__restrict__ Tg, int64_t ntrain, int64_t i0,
+                                                        int batch, int64_t mult, float *__restrict__ part,
+                                                        double *__restrict__ loss_part) {
+  __shared__ float w[MP];
+  __shared__ float xs[SPW][32];
+  __shared__ float h1[SPW][MH + 1], h2[SPW][MH + 1], d1[SPW][MH + 1], d2[SPW][MH + 1];
+  __shared__ float dy[SPW], tt[SPW];
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < MP; i += 256) w[i] = p[i];
+  const int e0 = blockIdx.x * SPW;
+  for (int i = tid; i < SPW * 32; i += 256) {
+    const int sidx = i / 32, c = i % 32, e = e0 + sidx;
+    float v = 0.0f;
+    if (e < batch && c < MI) {
+      const int64_t row = mult ? (int64_t)(((uint64_t)mult * (uint64_t)(i0 + e)) % (uint64_t)ntrain) : e;
+      v = X[row * 32 + c];
+    }
+    xs[sidx][c] = v;
+  }
+  if (tid < SPW) {
+    const int e = e0 + tid;
+    const int64_t row = (e < batch) ? (mult ? (int64_t)(((uint64_t)mult * (uint64_t)(i0 + e)) % (uint64_t)ntrain) : e) : 0;
+    tt[tid] = (e < batch) ? Tg[row] : 0.0f;
+  }
+  __syncthreads();
+  // layer 1 and 2 forward: thread -> 16 (sample, unit) pairs
+  for (int q = tid; q < SPW * MH; q += 256) {
+    const int sidx = q / MH, o = q % MH;
+    float a = 0.0f;
+    for (int i = 0; i < MI; i++) a = fmaf(w[o * MI + i], xs[sidx][i], a);
+    a += w[OFF_B1 + o];
+    h1[sidx][o] = a > 0.0f ? a : 0.0f;
+  }
+  __syncthreads();
+  for (int q = tid; q < SPW * MH; q += 256) {
+    const int sidx = q / MH, o = q % MH;
+    float a = 0.0f;
+    for (int i = 0; i < MH; i++) a = fmaf(w[OFF_W2 + o * MH + i], h1[sidx][i], a);
+    a += w[OFF_B2 + o];
+    h2[sidx][o] = a > 0.0f ? a : 0.0f;
+  }
+  __syncthreads();
+  double lp = 0.0;
+  if (tid < SPW) {
+    float a = w[OFF_B3];
+    for (int i = 0; i < MH; i++) a = fmaf(w[OFF_W3 + i], h2[tid][i], a);
+    const bool live = e0 + tid < batch;
+    const float r = live ? a - tt[tid] : 0.0f;
+    lp = (double)r * r;
+    dy[tid] = 2.0f * r / (float)batch;
+  }
+  __syncthreads();
+  for (int q = tid; q < SPW * MH; q += 256) {
+    const int sidx = q / MH, o = q % MH;
+    d2[sidx][o] = h2[sidx][o] > 0.0f ? dy[sidx] * w[OFF_W3 + o] : 0.0f;
+  }
+  __syncthreads();
+  for (int q = tid; q < SPW * MH; q += 256) {
+    const int sidx = q / MH, i = q % MH;
+    float a = 0.0f;
+    for (int o = 0; o < MH; o++) a = fmaf(w[OFF_W2 + o * MH + i], d2[sidx][o], a);
+    d1[sidx][i] = h1[sidx][i] > 0.0f ? a : 0.0f;
+  }
+  __syncthreads();
+  // parameter gradients summed over this workgroup's samples
+  float *out = part + (int64_t)blockIdx.x * MP;
+  for (int q = tid; q < MP; q += 256) {
+    float g = 0.0f;
+    if (q < OFF_B1) {
+      const int o = q / MI, i = q % MI;
+      for (int sidx = 0; sidx < SPW; sidx++) g = fmaf(d1[sidx][o], xs[sidx][i], g);
+    } else if (q < OFF_W2) {
+      for (int sidx = 0; sidx < SPW; sidx++) g += d1[sidx][q - OFF_B1];
+    } else if (q < OFF_B2) {
+      const int o = (q - OFF_W2) / MH, i = (q - OFF_W2) % MH;
+      for (int sidx = 0; sidx < SPW; sidx++) g = fmaf(d2[sidx][o], h1[sidx][i], g);
+    } else if (q < OFF_W3) {
+      for (int sidx = 0; sidx < SPW; sidx++) g += d2[sidx][q - OFF_B2];
+    } else if (q < OFF_B3) {
+      for (int sidx = 0; sidx < SPW; sidx++) g = fmaf(dy[sidx], h2[sidx][q - OFF_W3], g);
+    } else {
+      for (int sidx = 0; sidx < SPW; sidx++) g += dy[sidx];
+    }
+    out[q] = g;
+  }
+  lp = block_sum(lp, red);
+  if (tid == 0) loss_part[blockIdx.x] = lp;
+}
+
+// Sum of the partial gradients; with adam != 0 also the Adam update
+// (bias corrections c1 = 1 - beta1^t, c2 = 1 - beta2^t from the host).
+__global__ __launch_bounds__(256) void mlp_reduce_adam(float *__restrict__ p, float *__restrict__ m, float *__restrict__ v,
+                                                       const float *__restrict__ part, int nparts, float *__restrict__ grad,
+                                                       int adam, float lr, float b1, float b2, float eps, float c1,
+                                                       float c2) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= MP) return;
+  float g = 0.0f;
+  for (int i = 0; i < nparts; i++) g += part[(int64_t)i * MP + q];
+  if (grad) grad[q] = g;
+  if (adam) {
+    const float mm = b1 * m[q] + (1.0f - b1) * g;
+    const float vv = b2 * v[q] + (1.0f - b2) * g * g;
+    m[q] = mm;
+    v[q] = vv;
+    p[q] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+  }
+}
+
+// Training rows of one processed buffer: for symbols k in [64, nsym - 64),
+// X = xr[2(k+s) - 15 .. 2(k+s) + 15] (zero outside, column 31 zero) and
+// T = the transmitted level of symbol k.
+__global__ __launch_bounds__(256) void mlp_windows(RxLaunch L, float *__restrict__ X, float *__restrict__ Tg,
+                                                   int64_t row0) {
+  const RxJob J = *L.job[0];
+  const int64_t n = L.n[0], nsym = n / 2;
+  const int64_t k = RX_GUARD + (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= nsym - RX_GUARD) return;
+  const int s = J.sc->lag;
+  const int64_t row = row0 + (k - RX_GUARD);
+  const int64_t c = 2 * (k + s) - 15;
+  for (int i = 0; i < 32; i++) {
+    const int64_t j = c + i;
+    X[row * 32 + i] = (i < MI && j >= 0 && j < n) ? J.xr[j] : 0.0f;
+  }
+  Tg[row] = ref_symbol(J, k).x;
+}
+
+// ---- inference (BF16 MFMA) -----------------------------------------------
+// Per wavefront, tiles of 16 symbols:
+//   layer 1: H1^T (64 x 16) = W1 (64 x 32) X^T (32 x 16): 4 MFMA 16x16x32
+//   layer 2: H2^T = W2 (64 x 64) H1^T: 8 MFMA (H1 through LDS for the B layout)
+//   layer 3: y = W3 . H2 + b3 in FP32 (lane partials + two shuffles).
+#define TILES_PER_WAVE 8
+using MNT = NarrowT<1>;
+
+struct MlpFrag {
+  MNT::vec a1[4], a2[4][2];            // A fragments of W1 (4 row tiles) and W2 (4 x 2 K-steps)
+  float bb1[4][4], bb2[4][4], ww3[4][4];  // b1, b2, W3 of the hidden units this lane's D rows hold
+  float b3;
+};
+
+__device__ __forceinline__ void mlp_load_frag(const float *__restrict__ P, int row, int kq, MlpFrag &f) {
+#pragma unroll
+  for (int t = 0; t < 4; t++)
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      const int i = 8 * kq + j;
+      f.a1[t][j] = MNT::cvt(i < MI ? P[(16 * t + row) * MI + i] : 0.0f);
+      f.a2[t][0][j] = MNT::cvt(P[OFF_W2 + (16 * t + row) * MH + 8 * kq + j]);
+      f.a2[t][1][j] = MNT::cvt(P[OFF_W2 + (16 * t + row) * MH + 32 + 8 * kq + j]);
+    }
+#pragma unroll
+  for (int t = 0; t < 4; t++)
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      f.bb1[t][j] = P[OFF_B1 + 16 * t + 4 * kq + j];
+      f.bb2[t][j] = P[OFF_B2 + 16 * t + 4 * kq + j];
+      f.ww3[t][j] = P[OFF_W3 + 16 * t + 4 * kq + j];
+    }
+  f.b3 = P[OFF_B3];
+}
+
+// One tile of 16 symbols; bx = this lane's B fragment of layer 1 (window
+// samples 8 kq .. 8 kq + 7 of symbol `row`).  Every lane returns the output
+// of symbol `row`.  Contains workgroup barriers: all waves call it together.
+__device__ __forceinline__ float mlp_tile(const MlpFrag &f, MNT::vec bx, __bf16 (*hs)[MH + 8], int row, int kq) {
+#pragma unroll
+  for (int t = 0; t < 4; t++) {
+    rx_f32x4 d = MNT::mfma(f.a1[t], bx, rx_f32x4{0.0f, 0.0f, 0.0f, 0.0f});
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const float h = d[j] + f.bb1[t][j];
+      hs[row][16 * t + 4 * kq + j] = MNT::cvt(h > 0.0f ? h : 0.0f);
+    }
+  }
+  __syncthreads();
+  MNT::vec bh[2];
+#pragma unroll
+  for (int ks = 0; ks < 2; ks++)
+#pragma unroll
+    for (int j = 0; j < 8; j++) bh[ks][j] = hs[row][32 * ks + 8 * kq + j];
+  __syncthreads();
+  float y = 0.0f;
+#pragma unroll
+  for (int t = 0; t < 4; t++) {
+    rx_f32x4 d = MNT::mfma(f.a2[t][0], bh[0], rx_f32x4{0.0f, 0.0f, 0.0f, 0.0f});
+    d = MNT::mfma(f.a2[t][1], bh[1], d);
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const float h = d[j] + f.bb2[t][j];
+      y = fmaf(f.ww3[t][j], h > 0.0f ? h : 0.0f, y);
+    }
+  }
+  y += __shfl_xor(y, 16, 64);
+  y += __shfl_xor(y, 32, 64);
+  return y + f.b3;
+}
+
+// Per wavefront, tiles of 16 symbols:
+//   layer 1: H1^T (64 x 16) = W1 (64 x 32) X^T (32 x 16): 4 MFMA 16x16x32
+//   layer 2: H2^T = W2 (64 x 64) H1^T: 8 MFMA (H1 through LDS for the B layout)
+//   layer 3: y = W3 . H2 + b3 in FP32 (lane partials + two shuffles).
+__global__ __launch_bounds__(256) void mlp_infer(RxLaunch L) {
+  __shared__ __bf16 hs[4][16][MH + 8];
+  const int jb = blockIdx.y;
+  const RxJob J = *L.job[jb];
+  if (!J.mlp) return;
+  const int64_t n = L.n[jb], nsym = n / 2;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int row = lane & 15, kq = lane >> 4;
+  const int s = J.sc->lag;
+  const float *__restrict__ xr = J.xr;
+  MlpFrag f;
+  mlp_load_frag(J.mlp, row, kq, f);
+  const int64_t tile0 = ((int64_t)blockIdx.x * 4 + wv) * TILES_PER_WAVE;
+  for (int tt = 0; tt < TILES_PER_WAVE; tt++) {
+    const int64_t k0 = (tile0 + tt) * 16;
+    MNT::vec bx;
+    const int64_t c = 2 * (k0 + row + s) - 15 + 8 * kq;
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      const int64_t q = c + j;
+      bx[j] = MNT::cvt((8 * kq + j < MI && q >= 0 && q < n) ? xr[q] : 0.0f);
+    }
+    const float y = mlp_tile(f, bx, hs[wv], row, kq);
+    if (kq == 0 && k0 + row < nsym) J.soft[k0 + row] = make_float2(y, 0.0f);
+  }
+}
+
+// The same inference on given rows X[n][32] (column 31 ignored) -> Y[n].
+__global__ __launch_bounds__(256) void mlp_infer_rows(const float *__restrict__ P, const float *__restrict__ X,
+                                                      int64_t nrows, float *__restrict__ Y) {
+  __shared__ __bf16 hs[4][16][MH + 8];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int row = lane & 15, kq = lane >> 4;
+  MlpFrag f;
+  mlp_load_frag(P, row, kq, f);
+  const int64_t tile0 = ((int64_t)blockIdx.x * 4 + wv) * TILES_PER_WAVE;
+  for (int tt = 0; tt < TILES_PER_WAVE; tt++) {
+    const int64_t r = (tile0 + tt) * 16 + row;
+    MNT::vec bx;
+#pragma unroll
+    for (int j = 0; j < 8; j++) bx[j] = MNT::cvt((8 * kq + j < MI && r < nrows) ? X[r * 32 + 8 * kq + j] : 0.0f);
+    const float y = mlp_tile(f, bx, hs[wv], row, kq);
+    if (kq == 0 && r < nrows) Y[r] = y;
+  }
+}
+
+// LMS stays the fallback and the judge: on the known prefix symbols
+// [64, prefix) count the MLP's decision errors and those of the FFE with the
+// trained prefix taps w0; the block DD-LMS runs (and overwrites the MLP's
+// soft symbols) when the MLP makes more errors.
+__global__ __launch_bounds__(256) void mlp_judge(RxLaunch L) {
+  __shared__ double red[4];
+  const int jb = blockIdx.y;
+  const RxJob J = *L.job[jb];
+  const int64_t n = L.n[jb];
+  const int K = J.ffe_taps, C = (K - 1) / 2, P = J.prefix, m = J.m_axis;
+  const int s = J.sc->lag;
+  double em = 0.0, el = 0.0;
+  for (int k = RX_GUARD + threadIdx.x; k < P; k += 256) {
+    const float a = ref_symbol(J, k).x;
+    em += decide_level(J.soft[k].x, m) != a;
+    float z = 0.0f;
+    for (int i = 0; i < K; i++) {
+      const int64_t j = 2 * ((int64_t)k + s) + C - i;
+      z = fmaf(J.sc->w0[i].x, (j >= 0 && j < n) ? J.xr[j] : 0.0f, z);
+    }
+    el += decide_level(z, m) != a;
+  }
+  em = block_sum(em, red);
+  el = block_sum(el, red);
+  if (threadIdx.x == 0) J.sc->fallback = em > el ? 1 : 0;
+}
+
+// ---- host-side launchers ---------------------------------------------------
+void rx_launch_mlp_stage(int stage, const RxLaunch &L, int64_t maxn, hipStream_t s) {
+  const unsigned cnt = (unsigned)L.count;
+  const int64_t nsym = maxn / 2;
+  if (stage == ST_MLP_INFER) {
+    const int64_t tiles = (nsym + 15) / 16;
+    const int64_t wgs = (tiles + 4 * TILES_PER_WAVE - 1) / (4 * TILES_PER_WAVE);
+    hipLaunchKernelGGL(mlp_infer, dim3((unsigned)wgs, cnt), dim3(256), 0, s, L);
+  } else if (stage == ST_MLP_JUDGE) {
+    hipLaunchKernelGGL(mlp_judge, dim3(1, cnt), dim3(256), 0, s, L);
+  }
+}
+
+void rx_mlp_windows(const RxLaunch &L, float *X, float *T, int64_t row0, hipStream_t s) {
+  const int64_t nsym = L.n[0] / 2;
+  const int64_t rows = nsym - 2 * RX_GUARD;
+  hipLaunchKernelGGL(mlp_windows, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, L, X, T, row0);
+}
+
+int rx_mlp_params(void) { return MP; }
+
+void rx_mlp_infer_rows(const float *P, const float *X, int64_t n, float *Y, hipStream_t s) {
+  const int64_t tiles = (n + 15) / 16;
+  const int64_t wgs = (tiles + 4 * TILES_PER_WAVE - 1) / (4 * TILES_PER_WAVE);
+  hipLaunchKernelGGL(mlp_infer_rows, dim3((unsigned)wgs), dim3(256), 0, s, P, X, n, Y);
+}
+
+void rx_mlp_step(const float *X, const float *T, int64_t ntrain, int64_t i0, int batch, int64_t mult, float *p,
+                 float *m, float *v, float *part, double *loss_part, float *grad, int adam, float lr, float b1,
+                 float b2, float eps, float c1, float c2, hipStream_t s) {
+  const int nwg = (batch + SPW - 1) / SPW;
+  hipLaunchKernelGGL(mlp_grad_partial, dim3(nwg), dim3(256), 0, s, p, X, T, ntrain, i0, batch, mult, part,
+                     loss_part);
+  hipLaunchKernelGGL(mlp_reduce_adam, dim3((MP + 255) / 256), dim3(256), 0, s, p, m, v, part, nwg, grad, adam, lr,
+                     b1, b2, eps, c1, c2);
+}

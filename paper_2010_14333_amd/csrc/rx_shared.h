@@ -45,6 +45,7 @@ struct RxJob {
   float2 *s4;                       // KK: sum z^4 per DD-LMS block
   float *theta;                     // KK: carrier phase per block
   float2 *field;                    // KK debug: reconstructed field [n] or null
+  const float *mlp;                 // PAM learned equaliser parameters (FP32) or null
   RxScalars *sc;
 };
 
@@ -72,8 +73,15 @@ static inline int rx_kk_hop(int log2n) {
 // Kernel stages (host-side launchers are defined with their kernels).
 enum RxStage {
   ST_KK_FRONT = 0, ST_KK_FINALIZE, ST_PAM_SUM, ST_PAM_MF, ST_PAM_GAVG, ST_PAM_UNWRAP, ST_PAM_FARROW,
-  ST_PREFIX, ST_BLOCKS, ST_KK_VV, ST_DECIDE, ST_COUNT
+  ST_PREFIX, ST_BLOCKS, ST_KK_VV, ST_DECIDE, ST_MLP_INFER, ST_MLP_JUDGE, ST_COUNT
 };
 void rx_launch_kk_stage(int stage, const RxLaunch &L, int64_t maxn, int log2n, int prec, hipStream_t s);
 void rx_launch_pam_stage(int stage, const RxLaunch &L, int64_t maxn, hipStream_t s);
 void rx_launch_eq_stage(int stage, const RxLaunch &L, int64_t maxn, int kk, int ffe_taps, int prec, hipStream_t s);
+void rx_launch_mlp_stage(int stage, const RxLaunch &L, int64_t maxn, hipStream_t s);
+void rx_mlp_windows(const RxLaunch &L, float *X, float *T, int64_t row0, hipStream_t s);
+int rx_mlp_params(void);
+void rx_mlp_step(const float *X, const float *T, int64_t ntrain, int64_t i0, int batch, int64_t mult, float *p,
+                 float *m, float *v, float *part, double *loss_part, float *grad, int adam, float lr, float b1,
+                 float b2, float eps, float c1, float c2, hipStream_t s);
+void rx_mlp_infer_rows(const float *P, const float *X, int64_t n, float *Y, hipStream_t s);

@@ -1,0 +1,246 @@
+"""Learned equaliser: gradient, Adam and BF16 inference kernels against the
+oracle, the MLP stage inside the PAM chain (with its LMS fallback), weights
+I/O, and the gain of the trained network over LMS on the nonlinear PAM-8
+link (91 km SSMF, tanh driver, 24 dB)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import parity
+import synth
+
+pytestmark = pytest.mark.gpu
+NP = oracle.MLP_PARAMS
+
+
+@pytest.fixture(scope="module")
+def rx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2010_14333_amd as rx
+    rx.lib()
+    return rx
+
+
+def _t(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to("cuda:0")
+
+
+def _params(seed, scale=1.0):
+    """Kaiming-uniform weights, small random biases (seeded, numpy)."""
+    r = np.random.default_rng(seed)
+    p = np.zeros(NP)
+    p[:64 * 31] = r.uniform(-1, 1, 64 * 31) * math.sqrt(6 / 31) * scale
+    p[64 * 31:64 * 31 + 64] = r.uniform(-0.1, 0.1, 64)
+    o = 64 * 31 + 64
+    p[o:o + 4096] = r.uniform(-1, 1, 4096) * math.sqrt(6 / 64) * scale
+    p[o + 4096:o + 4096 + 64] = r.uniform(-0.1, 0.1, 64)
+    o += 4096 + 64
+    p[o:o + 64] = r.uniform(-1, 1, 64) * math.sqrt(6 / 64)
+    p[-1] = 0.05
+    return p.astype(np.float32).astype(np.float64)   # exactly representable in FP32
+
+
+def _rows(seed, n):
+    r = np.random.default_rng(seed)
+    x = r.standard_normal((n, 31))
+    t = (2 * r.integers(0, 8, n) - 7).astype(np.float64)
+    x32 = np.zeros((n, 32), dtype=np.float32)
+    x32[:, :31] = x
+    return x32[:, :31].astype(np.float64), t, x32, t.astype(np.float32)
+
+
+def _slices():
+    o1 = 64 * 31
+    o2 = o1 + 64
+    o3 = o2 + 4096
+    o4 = o3 + 64
+    o5 = o4 + 64
+    return {"W1": slice(0, o1), "b1": slice(o1, o2), "W2": slice(o2, o3), "b2": slice(o3, o4),
+            "W3": slice(o4, o5), "b3": slice(o5, NP)}
+
+
+def test_mlp_gradient_matches_oracle(rx):
+    import torch
+    p = _params(1)
+    x, t, x32, t32 = _rows(2, 4096)
+    r = rx.Receiver(rx.RX_PAM8, 1, max_samples=1 << 16, equalizer=rx.RX_EQ_MLP)
+    rx.rx_set_mlp(r.h, p)
+    gx, gt = _t(x32), _t(t32)
+    g = torch.zeros(NP, dtype=torch.float32, device="cuda:0")
+    loss = rx.rx_mlp_grad(r.h, gx.data_ptr(), gt.data_ptr(), 4096, g.data_ptr())
+    lo, go = oracle.mlp_grad(p, x, t)
+    g = g.cpu().numpy().astype(np.float64)
+    assert abs(loss - lo) <= 1e-6 * lo
+    for name, sl in _slices().items():
+        rel = np.linalg.norm(g[sl] - go[sl]) / np.linalg.norm(go[sl])
+        assert rel <= 1e-5, (name, rel)
+    r.close()
+
+
+def _order_multiplier(n):
+    m = 1000003
+    while math.gcd(m, n) != 1:
+        m += 2
+    return m
+
+
+def test_mlp_adam_steps_match_oracle(rx):
+    n, batch, steps = 4096, 256, 5
+    p0 = _params(3)
+    x, t, x32, t32 = _rows(4, n)
+    r = rx.Receiver(rx.RX_PAM8, 1, max_samples=1 << 16, equalizer=rx.RX_EQ_MLP)
+    cfg = rx.rx_train_cfg_default()
+    cfg.batch, cfg.max_steps = batch, steps
+    gx, gt = _t(x32), _t(t32)
+    rx.rx_train_mlp_data(r.h, gx.data_ptr(), gt.data_ptr(), n, cfg=cfg, init=p0)
+    pg = rx.rx_get_mlp(r.h).astype(np.float64)
+    assert rx.rx_mlp_order_multiplier(n) == _order_multiplier(n)
+    # oracle: the same rows in the same order, FP64 gradient and Adam
+    mult = _order_multiplier(n)
+    po, m, v = p0.copy(), np.zeros(NP), np.zeros(NP)
+    for s in range(steps):
+        rows = (mult * (s * batch + np.arange(batch))) % n
+        _, g = oracle.mlp_grad(po, x[rows], t[rows])
+        oracle.adam(po, m, v, g, s + 1)
+    d = np.abs(pg - po)
+    assert np.quantile(d, 0.999) < 1e-6 and d.max() <= 2.2 * 1e-3 * steps, (np.quantile(d, 0.999), d.max())
+    assert np.max(np.abs(po - p0)) > 1e-3      # the steps moved the weights
+    r.close()
+
+
+def test_mlp_bf16_inference_matches_oracle(rx):
+    import torch
+    p = _params(5)
+    x, _, x32, _ = _rows(6, 10000)
+    r = rx.Receiver(rx.RX_PAM8, 1, max_samples=1 << 16, equalizer=rx.RX_EQ_MLP)
+    rx.rx_set_mlp(r.h, p)
+    y = torch.zeros(10000, dtype=torch.float32, device="cuda:0")
+    rx.rx_mlp_infer(r.h, _t(x32).data_ptr(), 10000, y.data_ptr())
+    torch.cuda.synchronize()
+    y = y.cpu().numpy().astype(np.float64)
+    yo = oracle.mlp_forward(p, x, rounding=1)
+    rel = parity.rel_rms(y, yo)
+    print(f"[mlp] bf16 inference rel-RMS vs oracle (same rounding) {rel:.2e}; "
+          f"vs unrounded {parity.rel_rms(y, oracle.mlp_forward(p, x)):.2e}", flush=True)
+    assert rel <= 1e-4
+    r.close()
+
+
+def _linear_net():
+    """y = sqrt(21) * centre sample: two ReLU paths carry +x and -x."""
+    p = np.zeros(NP)
+    p[0 * 31 + 15] = 1.0
+    p[1 * 31 + 15] = -1.0
+    o = 64 * 31 + 64
+    p[o + 0 * 64 + 0] = 1.0
+    p[o + 1 * 64 + 1] = 1.0
+    o += 4096 + 64
+    p[o + 0] = math.sqrt(21.0)
+    p[o + 1] = -math.sqrt(21.0)
+    return p.astype(np.float32).astype(np.float64)
+
+
+MLP_NEAR = 1e-1   # a one-ulp BF16 disagreement of the centre sample moves y by up to ~5e-2
+
+
+@pytest.mark.parametrize("kind", ["linear", "zero"])
+def test_mlp_stage_in_chain(rx, kind):
+    """PAM-8 chain with the MLP stage: the hand-built linear network wins on
+    the noiseless prefix (no fallback); the all-zero network loses and the
+    block DD-LMS takes over.  Both against the oracle's chain."""
+    import torch
+    n = 1 << 18
+    g = synth.generate(synth.PAM8, n, 909, None, drive=0.1)
+    p = _linear_net() if kind == "linear" else np.zeros(NP)
+    o = oracle.process(3, g["packed"], n, g["seed"], want=("bits", "soft"), equalizer=1, mlp=p, rounding=1)
+    r = rx.Receiver(rx.RX_PAM8, g["seed"], max_samples=n, equalizer=rx.RX_EQ_MLP)
+    rx.rx_set_mlp(r.h, p)
+    bits = r.process(_t(g["packed"]), n).cpu().numpy()
+    sc = r.fetch(rx.RX_STAGE_SCALARS, n)
+    e = r.errors()
+    r.close()
+    assert int(sc[6]) == o["fallback"] == (0 if kind == "linear" else 1)
+    assert e["fallbacks"] == o["fallback"]
+    nsym = n // 2
+    if kind == "linear":
+        gs = parity.symbols_from_bits(bits, 3, nsym)
+        os_ = parity.symbols_from_bits(o["bits"], 3, nsym)
+        dist = parity.threshold_distance(o["soft"], 3)
+        bad = np.nonzero(gs != os_)[0]
+        assert np.all(dist[bad] <= MLP_NEAR), dist[bad][:10]
+        assert abs(e["bit_errors"] - o["bit_errors"]) <= 3 * bad.size
+    else:
+        _, tol, untol = parity.compare_decisions(3, bits, o["bits"], o["soft"], nsym, 256)
+        assert not untol and abs(e["bit_errors"] - o["bit_errors"]) <= tol
+
+
+def test_untrained_mlp_runs_lms_with_warning(rx):
+    import torch
+    n = 1 << 17
+    g = synth.generate(synth.PAM8, n, 910, 24.0)
+    r = rx.Receiver(rx.RX_PAM8, g["seed"], max_samples=n, equalizer=rx.RX_EQ_MLP)
+    bits = r.process(_t(g["packed"]), n).cpu().numpy()
+    assert r.last_status == rx.RX_W_FALLBACK
+    r.close()
+    r2 = rx.Receiver(rx.RX_PAM8, g["seed"], max_samples=n)
+    bits2 = r2.process(_t(g["packed"]), n).cpu().numpy()
+    r2.close()
+    assert np.array_equal(bits, bits2)
+
+
+def test_weights_save_load_roundtrip(rx, tmp_path):
+    p = _params(7)
+    r = rx.Receiver(rx.RX_PAM8, 1, max_samples=1 << 16, equalizer=rx.RX_EQ_MLP)
+    rx.rx_set_mlp(r.h, p)
+    path = str(tmp_path / "w.bin")
+    rx.rx_save_weights(r.h, path)
+    r2 = rx.Receiver(rx.RX_PAM8, 1, max_samples=1 << 16, equalizer=rx.RX_EQ_MLP)
+    rx.rx_load_weights(r2.h, path)
+    assert np.array_equal(rx.rx_get_mlp(r2.h), p.astype(np.float32))
+    with pytest.raises(rx.RxError):
+        rx.rx_load_weights(r2.h, str(tmp_path / "missing.bin"))
+    r.close()
+    r2.close()
+
+
+def test_trained_mlp_beats_lms_on_nonlinear_pam8(rx):
+    """Train on 4 x 2^22 chain-processed PAM-8 buffers (91 km, tanh driver,
+    24 dB; 2^24 samples), test on 4 fresh buffers: the BF16 MLP must make
+    fewer bit errors than the LMS chain on the same buffers."""
+    import torch
+    n = 1 << 22
+    train = [synth.pam8_91km(i, seed=501) for i in range(4)]
+    test = [synth.pam8_91km(i, seed=502) for i in range(4)]
+    r = rx.Receiver(rx.RX_PAM8, 0, max_samples=n, equalizer=rx.RX_EQ_MLP)
+    tb = [_t(g["packed"]) for g in train]
+    loss = rx.rx_train_mlp(r.h, [b.data_ptr() for b in tb], [n] * 4, [g["seed"] for g in train])
+    del tb
+    errs = {"mlp": 0, "lms": 0, "bits": 0, "fallbacks": 0}
+    for g in test:
+        buf = _t(g["packed"])
+        m = rx.Receiver(rx.RX_PAM8, g["seed"], max_samples=n, equalizer=rx.RX_EQ_MLP)
+        rx.rx_set_mlp(m.h, rx.rx_get_mlp(r.h))
+        m.process(buf, n)
+        em = m.errors()
+        m.close()
+        lms = rx.Receiver(rx.RX_PAM8, g["seed"], max_samples=n)
+        lms.process(buf, n)
+        el = lms.errors()
+        lms.close()
+        errs["mlp"] += em["bit_errors"]
+        errs["lms"] += el["bit_errors"]
+        errs["bits"] += em["bits"]
+        errs["fallbacks"] += em["fallbacks"]
+    r.close()
+    ber_m, ber_l = errs["mlp"] / errs["bits"], errs["lms"] / errs["bits"]
+    print(f"[mlp] final train loss {loss:.4f}; test BER MLP {ber_m:.3e} vs LMS {ber_l:.3e} "
+          f"(gain x{ber_l / max(ber_m, 1e-12):.2f}), fallbacks {errs['fallbacks']}", flush=True)
+    assert errs["fallbacks"] == 0
+    assert ber_m < 0.8 * ber_l
