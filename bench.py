@@ -44,6 +44,8 @@ def main():
     ap.add_argument("--cpu-buffers", type=int, default=8)
     ap.add_argument("--copy-probe", type=int, default=1, help="run a 256 MiB device copy (counter scale)")
     ap.add_argument("--forms", default="bf16,fp16", help="precision forms timed beside the plain chain")
+    ap.add_argument("--mlp", type=int, default=1, help="train and time the PAM-8 learned-equaliser form")
+    ap.add_argument("--mixed", type=int, default=1, help="time a 64-buffer mixed-format batch (graph replay)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the receiver path is "
@@ -109,6 +111,99 @@ def main():
     samples = a.batch * N
     gsps = samples / (ms_step * 1e-3) / 1e9
 
+    def time_handles(recs, bp, steps, graph, lat=False):
+        outs = [torch.empty(r.bits_bytes(N), dtype=torch.uint8, device=dev) for r in recs]
+        hs = [r.h for r in recs]
+        op = [o.data_ptr() for o in outs]
+        ns = [N] * len(recs)
+        for _ in range(a.warmup):
+            rx.rx_process_batch(hs, bp, ns, op, graph=graph)
+        torch.cuda.synchronize()
+        for r in recs:
+            r.reset()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)] if lat else []
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for i in range(steps):
+            if lat:
+                evs[i][0].record()
+            rx.rx_process_batch(hs, bp, ns, op, graph=graph)
+            if lat:
+                evs[i][1].record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t1
+        errs = [r.errors() for r in recs]
+        bits = sum(e["bits"] for e in errs)
+        ber = sum(e["bit_errors"] for e in errs) / bits if bits else None
+        ms = sorted(e0.elapsed_time(e1) for e0, e1 in evs)
+        return wall, ber, ms, errs
+
+    mlp_form = None
+    if a.mlp:
+        t0 = time.time()
+        train = [synth.pam8_91km(i, seed=501) for i in range(4)]
+        testg = [synth.pam8_91km(i, seed=502) for i in range(4)]
+        log(f"[bench] generated PAM-8 91 km buffers in {time.time() - t0:.1f}s")
+        trainer = rx.Receiver(rx.RX_PAM8, 0, max_samples=N, equalizer=rx.RX_EQ_MLP)
+        tb = [torch.from_numpy(g["packed"]).to(dev) for g in train]
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        loss = rx.rx_train_mlp(trainer.h, [b.data_ptr() for b in tb], [N] * 4, [g["seed"] for g in train])
+        train_s = time.perf_counter() - t2
+        w = rx.rx_get_mlp(trainer.h)
+        trainer.close()
+        del tb
+        pb = [torch.from_numpy(g["packed"]).to(dev) for g in testg]
+        pbp = [pb[i % 4].data_ptr() for i in range(a.batch)]
+        res = {}
+        for eq in ("mlp", "lms"):
+            recs = [rx.Receiver(rx.RX_PAM8, testg[i % 4]["seed"], max_samples=N,
+                                equalizer=rx.RX_EQ_MLP if eq == "mlp" else rx.RX_EQ_LMS)
+                    for i in range(a.batch)]
+            if eq == "mlp":
+                for r in recs:
+                    rx.rx_set_mlp(r.h, w)
+            wl, ber_f, _, errs = time_handles(recs, pbp, a.steps, bool(a.graph))
+            res[eq] = (a.batch * N / (wl / a.steps) / 1e9, ber_f, sum(e["fallbacks"] for e in errs))
+            for r in recs:
+                r.close()
+        mlp_form = {"workload": "PAM-8, 2 GBaud, 91 km SSMF, tanh driver, 24 dB; 2^22-sample buffers",
+                    "value": round(res["mlp"][0], 3), "unit": "Gsamples/s", "ber": res["mlp"][1],
+                    "fallbacks": res["mlp"][2], "lms_value": round(res["lms"][0], 3), "lms_ber": res["lms"][1],
+                    "train_samples": 4 * N, "train_s": round(train_s, 3), "final_loss": round(loss, 5)}
+        log(f"[bench] MLP form {mlp_form}")
+
+    mixed = None
+    if a.mixed:
+        plan = synth.mixed_batch_formats(a.batch, seed=301)
+        per_fmt = {}
+        t0 = time.time()
+        for i, (f, snr) in enumerate(plan):
+            if len(per_fmt.setdefault(f, [])) < 2:
+                per_fmt[f].append(synth.generate(f, N, synth.derive_seed(301, i), snr))
+        log(f"[bench] generated mixed-format buffers in {time.time() - t0:.1f}s")
+        dbuf = {f: [torch.from_numpy(g["packed"]).to(dev) for g in gl] for f, gl in per_fmt.items()}
+        cnt = {}
+        recs, mbp = [], []
+        for f, _ in plan:
+            j = cnt.get(f, 0) % len(per_fmt[f])
+            cnt[f] = cnt.get(f, 0) + 1
+            recs.append(rx.Receiver(f, per_fmt[f][j]["seed"], max_samples=N))
+            mbp.append(dbuf[f][j].data_ptr())
+        wl, ber_m, ms, _ = time_handles(recs, mbp, a.steps, True, lat=True)
+        for r in recs:
+            r.close()
+        p50 = ms[len(ms) // 2]
+        p99 = ms[min(len(ms) - 1, int(round(0.99 * (len(ms) - 1))))]
+        mixed = {"workload": f"{a.batch} x 2^22 buffers, formats mixed per buffer (SplitMix64 % 5), "
+                             "SNR U[14, 26] dB, one hipGraph replay per batch",
+                 "value": round(a.batch * N / (wl / a.steps) / 1e9, 3), "unit": "Gsamples/s",
+                 "formats": {synth.FORMAT_NAMES[f]: c for f, c in sorted(cnt.items())},
+                 "batch_latency_ms_p50": round(p50, 3), "batch_latency_ms_p99": round(p99, 3),
+                 "realtime_budget_ms_per_batch": round(a.batch * N / 4e9 * 1e3, 3), "ber": ber_m}
+        log(f"[bench] mixed batch {mixed}")
+
     # dominant kernel: the stage with the largest total time
     dom = max(stages, key=lambda k: stages[k][0])
     dom_ms = stages[dom][0] / stages[dom][1]
@@ -153,6 +248,8 @@ def main():
         "realtime_factor": round(gsps / 4.0, 2),
         "ber": ber,
         "forms": forms,
+        "mlp_form": mlp_form,
+        "mixed_batch": mixed,
         "stage_us_per_buffer": per_stage_us_per_buffer,
         "roofline": roof,
         "cpu_baseline": cpu,
