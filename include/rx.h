@@ -65,7 +65,7 @@ enum {
 /* Kernel stages reported by rx_stage_times (index into its arrays). */
 enum {
   RX_ST_KK_FRONT = 0,   /* unpack, ln, FFT Hilbert, field, FP64 downshift, decimating MF */
-  RX_ST_KK_FINALIZE,    /* carrier removal after the filter, power partials */
+  RX_ST_KK_DEBUG,       /* (RX_DEBUG_KEEP only) materialises the AGC'd carrier-free MF output */
   RX_ST_PAM_SUM,        /* exact code sum (DC) */
   RX_ST_PAM_MF,         /* DC removal, matched filter, timing-detector sums */
   RX_ST_PAM_GAVG,       /* timing-detector averaging and angle */
@@ -111,7 +111,8 @@ typedef struct {
 /* Debug stages for rx_debug_fetch (the handle needs RX_DEBUG_KEEP for FIELD). */
 enum {
   RX_STAGE_FIELD = 1,   /* KK: reconstructed field E, float2[n] (needs RX_DEBUG_KEEP) */
-  RX_STAGE_MF = 2,      /* KK: AGC'd decimated MF output float2[n/2]; PAM: AGC'd MF output float[n] */
+  RX_STAGE_MF = 2,      /* KK: AGC'd carrier-free decimated MF output float2[n/2] (needs RX_DEBUG_KEEP);
+                           PAM: MF output before the AGC gain, float[n] */
   RX_STAGE_XR = 3,      /* PAM: timing-corrected samples float[n] */
   RX_STAGE_TIMING = 4,  /* PAM: timing shift (samples) per 512-sample block, float[n/512] */
   RX_STAGE_SOFT = 5,    /* soft symbols after carrier phase (KK float2, PAM float) [n_sym] */

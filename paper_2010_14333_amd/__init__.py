@@ -24,7 +24,7 @@ RX_DEBUG_KEEP = 0x1
  RX_STAGE_PHASE, RX_STAGE_SCALARS) = range(1, 9)
 
 RX_PROFILE = 0x2
-STAGES = ("kk_front", "kk_finalize", "pam_sum", "pam_mf", "pam_gavg", "pam_unwrap", "pam_farrow",
+STAGES = ("kk_front", "kk_debug", "pam_sum", "pam_mf", "pam_gavg", "pam_unwrap", "pam_farrow",
           "prefix", "blocks", "kk_vv", "decide", "mlp_infer", "mlp_judge")
 RX_MLP_PARAMS = 6273
 EXPORTS = ("rx_params_default", "rx_create", "rx_process", "rx_process_batch", "rx_errors",

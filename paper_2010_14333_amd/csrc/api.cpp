@@ -269,13 +269,13 @@ int rx_create(rx_format fmt, double baud, double fs, const rx_params *pin, rx_ha
     const int64_t nd = L / 2;
     const int hop = J.hop;
     J.z = A.get<float2>(nd);
-    J.part = A.get<double2>(((L + hop - 1) / hop + 1) / 2 + 1);
-    J.part2 = A.get<double>((nd + 1023) / 1024 + 1);
+    J.part = A.get<double2>(3 * (((L + hop - 1) / hop + 1) / 2 + 1));
     J.soft = A.get<float2>(L / 4);
     J.s4 = A.get<float2>(L / 4 / 128);
     J.theta = A.get<float>(L / 4 / 128);
     J.field = J.debug ? A.get<float2>(L) : nullptr;
-    ok = ok && J.z && J.part && J.part2 && J.soft && J.s4 && J.theta && (!J.debug || J.field);
+    J.udbg = J.debug ? A.get<float2>(nd) : nullptr;
+    ok = ok && J.z && J.part && J.soft && J.s4 && J.theta && (!J.debug || (J.field && J.udbg));
   } else if (ok) {
     J.y = A.get<float>(L);
     J.xr = A.get<float>(L);
@@ -314,7 +314,7 @@ static int check_n(rx_handle h, size_t n) {
   return RX_OK;
 }
 
-static const int KK_STAGES[] = {ST_KK_FRONT, ST_KK_FINALIZE, ST_PREFIX, ST_BLOCKS, ST_KK_VV, ST_DECIDE};
+static const int KK_STAGES[] = {ST_KK_FRONT, ST_PREFIX, ST_BLOCKS, ST_KK_VV, ST_DECIDE, ST_KK_DEBUG};
 static const int PAM_STAGES[] = {ST_PAM_SUM, ST_PAM_MF, ST_PAM_GAVG, ST_PAM_UNWRAP, ST_PAM_FARROW,
                                  ST_PREFIX, ST_BLOCKS, ST_DECIDE};
 static const int PAM_MLP_STAGES[] = {ST_PAM_SUM, ST_PAM_MF, ST_PAM_GAVG, ST_PAM_UNWRAP, ST_PAM_FARROW,
@@ -348,14 +348,14 @@ static int enqueue(rx_handle const *hs, const void *const *bufs, const size_t *n
       if ((int64_t)ns[j] > maxn) maxn = (int64_t)ns[j];
     }
     const int *st = a->kk ? KK_STAGES : (uses_mlp(a) ? PAM_MLP_STAGES : PAM_STAGES);
-    const int nst = a->kk ? 6 : (uses_mlp(a) ? 10 : 8);
+    const int nst = a->kk ? (a->hj.debug ? 6 : 5) : (uses_mlp(a) ? 10 : 8);
     for (int k = 0; k < nst; k++) {
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (prof) {
         e0 = prof->event();
         hipEventRecord(e0, s);
       }
-      if (st[k] == ST_KK_FRONT || st[k] == ST_KK_FINALIZE || st[k] == ST_KK_VV)
+      if (st[k] == ST_KK_FRONT || st[k] == ST_KK_DEBUG || st[k] == ST_KK_VV)
         rx_launch_kk_stage(st[k], L, maxn, a->log2n, a->p.precision, s);
       else if (st[k] >= ST_PAM_SUM && st[k] <= ST_PAM_FARROW)
         rx_launch_pam_stage(st[k], L, maxn, s);
@@ -487,7 +487,8 @@ int rx_debug_fetch(rx_handle h, int stage, void *dst, size_t bytes) {
       if (!J.field) return RX_E_STATE;
       src = J.field; need = n * sizeof(float2); break;
     case RX_STAGE_MF:
-      src = h->kk ? (const void *)J.z : (const void *)J.y;
+      if (h->kk && !J.udbg) return RX_E_STATE;
+      src = h->kk ? (const void *)J.udbg : (const void *)J.y;
       need = h->kk ? (n / 2) * sizeof(float2) : n * sizeof(float); break;
     case RX_STAGE_XR:
       if (h->kk) return RX_E_INVALID;

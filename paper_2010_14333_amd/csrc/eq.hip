@@ -45,23 +45,36 @@ __global__ __launch_bounds__(256) void rx_prefix(RxLaunch L) {
   const int64_t nx = kk ? n / 2 : n;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 
-  // AGC gain: KK reduces the power partials of the carrier-removal pass;
-  // the PAM samples arrive already scaled.
+  // KK: carrier mean and AGC gain from the front end's per-workgroup sums:
+  // sum |Z - m T|^2 = sum|Z|^2 - 2 Re(conj(m) sum Z conj(T)) + |m|^2 sum|T|^2.
+  // The PAM samples arrive already scaled.
   float g = 1.0f;
+  float2 mean = make_float2(0.0f, 0.0f);
   if (kk) {
-    const int64_t nfin = (nx + 1023) / 1024;
-    double p = 0.0;
-    for (int64_t i = threadIdx.x; i < nfin; i += 256) p += J.part2[i];
-    p = block_sum(p, red);
-    const double gd = 1.0 / sqrt(p / (double)nx);
+    const int64_t npairs = ((n + J.hop - 1) / J.hop + 1) / 2;
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t i = threadIdx.x; i < npairs; i += 256) {
+      const double2 a = J.part[3 * i], b = J.part[3 * i + 1], c2 = J.part[3 * i + 2];
+      v[0] += a.x; v[1] += a.y; v[2] += b.x; v[3] += b.y; v[4] += c2.x; v[5] += c2.y;
+    }
+    for (int q = 0; q < 6; q++) v[q] = block_sum(v[q], red);
+    const double mr = v[0] / (double)n, mi = v[1] / (double)n;
+    const double pw = v[2] - 2.0 * (mr * v[4] + mi * v[5]) + (mr * mr + mi * mi) * v[3];
+    const double gd = 1.0 / sqrt(pw / (double)nx);
     g = (float)gd;
-    if (threadIdx.x == 0) J.sc->agc = gd;
+    mean = make_float2((float)mr, (float)mi);
+    if (threadIdx.x == 0) {
+      J.sc->agc = gd;
+      J.sc->mean_re = mr;
+      J.sc->mean_im = mi;
+    }
   }
+  const float2 *__restrict__ zin = J.z;
 #pragma unroll 8
   for (int idx = threadIdx.x; idx < PFX_UL; idx += 256) {
     const int64_t j = (int64_t)idx - PFX_OFF;
     float2 v = make_float2(0.0f, 0.0f);
-    if (j >= 0 && j < nx) v = kk ? cscale(J.z[j], g) : make_float2(J.xr[j], 0.0f);
+    if (j >= 0 && j < nx) v = kk ? kk_sample(J, zin, j, n, mean, g) : make_float2(J.xr[j], 0.0f);
     u[idx] = v;
   }
   for (int k = threadIdx.x; k < P; k += 256) ar[k] = ref_symbol(J, k);
@@ -201,13 +214,14 @@ __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
   const float mu = J.mu;
   const int m = J.m_axis;
   const float g = CPLX ? (float)J.sc->agc : 1.0f;
+  const float2 mean = make_float2((float)J.sc->mean_re, (float)J.sc->mean_im);
   const int s = J.sc->lag;
   const float2 *__restrict__ zin = J.z;
   const float *__restrict__ xin = J.xr;
   float2 *__restrict__ soft = J.soft;
   auto load = [&](int64_t j) -> T {
     if constexpr (CPLX) {
-      return (j >= 0 && j < nx) ? cscale(zin[j], g) : make_float2(0.0f, 0.0f);
+      return kk_sample(J, zin, j, n, mean, g);
     } else {
       return (j >= 0 && j < nx) ? xin[j] : 0.0f;
     }
@@ -290,6 +304,7 @@ __global__ __launch_bounds__(256) void rx_ffe_mfma(RxLaunch L) {
   const int K = J.ffe_taps, C = (K - 1) / 2;
   const int s = J.sc->lag;
   const float g = (float)J.sc->agc;
+  const float2 mean = make_float2((float)J.sc->mean_re, (float)J.sc->mean_im);
   const int row = lane & 15, kq = lane >> 4;
   // B fragments: kk = 32 ks + 8 kq + j (t = kk % 64, part = kk / 64),
   // column q = row of output tile ct (0: Re z, 1: Im z)
@@ -315,7 +330,7 @@ __global__ __launch_bounds__(256) void rx_ffe_mfma(RxLaunch L) {
 #pragma unroll
     for (int j = 0; j < 8; j++) {
       const int64_t q = base + 32 * h + 8 * kq + j;
-      xv[8 * h + j] = (q >= 0 && q < nx) ? cscale(zin[q], g) : make_float2(0.0f, 0.0f);
+      xv[8 * h + j] = kk_sample(J, zin, q, n, mean, g);
     }
   rx_f32x4 zr = {0.0f, 0.0f, 0.0f, 0.0f}, zi = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll

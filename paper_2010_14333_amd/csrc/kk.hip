@@ -10,8 +10,9 @@
 // filter runs on y' straight from LDS and writes the 2-sample/symbol
 // output; only packed codes come in and half-rate complex samples go out.
 // The carrier mean m is not known inside one workgroup, so the filter runs
-// on y' = y + m exp(-j 2 pi r n) and kk_finalize subtracts m * MF(exp(...))
-// afterwards (the filter is linear).
+// on y' = y + m exp(-j 2 pi r n); since the filter is linear its consumers
+// subtract m * MF(exp(...)) on load, and the AGC power of the carrier-free
+// output follows from per-workgroup sums of |Z|^2, |T|^2 and Z conj(T).
 #include <type_traits>
 
 #include "fft_lds.hpp"
@@ -98,6 +99,15 @@ __global__ __launch_bounds__((1 << LOGN) / 16) void kk_front(RxLaunch L) {
   __syncthreads();
 
   double se_re = 0.0, se_im = 0.0;
+  double zz = 0.0, tt = 0.0, ztr = 0.0, zti = 0.0;   // sum |Z|^2, |T|^2, Z conj(T)
+  auto zstat = [&](int64_t m, float2 zv) {
+    const float2 tc = kk_carrier_term(J, m, n);
+    zz += (double)zv.x * zv.x + (double)zv.y * zv.y;
+    tt += (double)tc.x * tc.x + (double)tc.y * tc.y;
+    const float2 p = cmulc(zv, tc);
+    ztr += p.x;
+    zti += p.y;
+  };
 #pragma unroll
   for (int x = 0; x < 2; x++) {
     // 3. field, carrier mean partials, downshifted field y' into LDS
@@ -164,7 +174,10 @@ __global__ __launch_bounds__((1 << LOGN) / 16) void kk_front(RxLaunch L) {
   #pragma unroll
         for (int o = 0; o < 8; o++) {
           const int64_t m = m0 + 8 * t8 + o;
-          if (2 * m < n) J.z[m] = acc[o];
+          if (2 * m < n) {
+          J.z[m] = acc[o];
+          zstat(m, acc[o]);
+        }
         }
       }
 
@@ -203,61 +216,37 @@ __global__ __launch_bounds__((1 << LOGN) / 16) void kk_front(RxLaunch L) {
         for (int jj = 0; jj < 2; jj++) {
           const int t2 = grp * 8 + 2 * kq + jj;
           const int64_t m = m0 + 16 * t2 + row;
-          if (t2 < NTILE && 2 * m < n) J.z[m] = make_float2(acc[2 * jj], acc[2 * jj + 1]);
+          if (t2 < NTILE && 2 * m < n) {
+            const float2 zv = make_float2(acc[2 * jj], acc[2 * jj + 1]);
+            J.z[m] = zv;
+            zstat(m, zv);
+          }
         }
       }
     }
     __syncthreads();
   }
-  const double sr = block_sum(se_re, red);
-  const double si = block_sum(se_im, red);
-  if (threadIdx.x == 0) J.part[blockIdx.x] = make_double2(sr, si);
+  const double sr = block_sum(se_re, red), si = block_sum(se_im, red);
+  const double szz = block_sum(zz, red), stt = block_sum(tt, red);
+  const double szr = block_sum(ztr, red), szi = block_sum(zti, red);
+  if (threadIdx.x == 0) {
+    J.part[3 * blockIdx.x] = make_double2(sr, si);          // sum of the field E
+    J.part[3 * blockIdx.x + 1] = make_double2(szz, stt);    // sum |Z|^2, sum |T|^2
+    J.part[3 * blockIdx.x + 2] = make_double2(szr, szi);    // sum Z conj(T)
+  }
 }
 
-// Carrier removal after the filter: u'[m] = Z[m] - mean * MF(exp(-j2 pi r n))[2m].
-// In the interior MF(exp)[2m] = c0 exp(-j 2 pi r 2m); the 16 outputs at each
-// edge sum the in-range taps directly.  Also the partial power sums for AGC.
-__global__ __launch_bounds__(256) void kk_finalize(RxLaunch L) {
-  __shared__ double red[4];
+// Debug only (RX_DEBUG_KEEP): materialise u[m] = g (Z[m] - mean T[m]) exactly
+// as the consumers form it on load.
+__global__ __launch_bounds__(256) void kk_debug_u(RxLaunch L) {
   const int jb = blockIdx.y;
   const RxJob J = *L.job[jb];
-  const int64_t n = L.n[jb], nd = n / 2;
-  const int64_t m0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
-  if ((int64_t)blockIdx.x * 1024 >= nd) return;
-  const int64_t npairs = ((n + J.hop - 1) / J.hop + 1) / 2;
-  double sr = 0.0, si = 0.0;
-  for (int64_t i = threadIdx.x; i < npairs; i += 256) {
-    sr += J.part[i].x;
-    si += J.part[i].y;
-  }
-  sr = block_sum(sr, red) / (double)n;
-  si = block_sum(si, red) / (double)n;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    J.sc->mean_re = sr;
-    J.sc->mean_im = si;
-  }
-  const float2 mean = make_float2((float)sr, (float)si);
-  double p2 = 0.0;
-#pragma unroll
-  for (int o = 0; o < 4; o++) {
-    const int64_t m = m0 + o;
-    if (m >= nd) break;
-    float2 tc;
-    if (m >= 16 && 2 * m + 32 < n) {
-      tc = cmul(J.c0, cis_rev(-downshift_rev(J.r, 2 * m)));
-    } else {
-      tc = make_float2(0.0f, 0.0f);
-      for (int i = 0; i < 65; i++) {
-        const int64_t t = 2 * m + 32 - i;
-        if (t >= 0 && t < n) tc = cadd(tc, cscale(cis_rev(-downshift_rev(J.r, t)), J.mf[i]));
-      }
-    }
-    const float2 u = csub(J.z[m], cmul(mean, tc));
-    J.z[m] = u;
-    p2 += (double)u.x * u.x + (double)u.y * u.y;
-  }
-  p2 = block_sum(p2, red);
-  if (threadIdx.x == 0) J.part2[blockIdx.x] = p2;
+  if (!J.udbg) return;
+  const int64_t n = L.n[jb];
+  const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (m >= n / 2) return;
+  const float2 mean = make_float2((float)J.sc->mean_re, (float)J.sc->mean_im);
+  J.udbg[m] = kk_sample(J, J.z, m, n, mean, (float)J.sc->agc);
 }
 
 // Viterbi-Viterbi carrier phase per DD-LMS block over blocks b-1..b+1,
@@ -325,9 +314,9 @@ void rx_launch_kk_stage(int stage, const RxLaunch &L, int64_t maxn, int log2n, i
       else if (prec == 2) launch_front<14, 2>(L, maxn, s);
       else launch_front<14, 0>(L, maxn, s);
     }
-  } else if (stage == ST_KK_FINALIZE) {
+  } else if (stage == ST_KK_DEBUG) {
     const int64_t nd = maxn / 2;
-    hipLaunchKernelGGL(kk_finalize, dim3((unsigned)((nd + 1023) / 1024), cnt), dim3(256), 0, s, L);
+    hipLaunchKernelGGL(kk_debug_u, dim3((unsigned)((nd + 255) / 256), cnt), dim3(256), 0, s, L);
   } else if (stage == ST_KK_VV) {
     hipLaunchKernelGGL(kk_vv, dim3(1, cnt), dim3(1024), 0, s, L);
   }

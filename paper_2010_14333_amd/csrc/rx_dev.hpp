@@ -141,3 +141,23 @@ __device__ __forceinline__ float downshift_rev(double r, int64_t n) {
 __device__ __forceinline__ float2 cis_rev(float rev) {
   return make_float2(__builtin_amdgcn_cosf(rev), __builtin_amdgcn_sinf(rev));
 }
+
+// KK: the matched filter's response to the downshifted carrier,
+// T[m] = sum_i h[i] exp(-j 2 pi frac(r (2m + 32 - i))) over in-range samples;
+// in the interior it is c0 exp(-j 2 pi frac(2 r m)).
+__device__ __forceinline__ float2 kk_carrier_term(const RxJob &J, int64_t m, int64_t n) {
+  if (m >= 16 && 2 * m + 32 < n) return cmul(J.c0, cis_rev(-downshift_rev(J.r, 2 * m)));
+  float2 tc = make_float2(0.0f, 0.0f);
+  for (int i = 0; i < 65; i++) {
+    const int64_t t = 2 * m + 32 - i;
+    if (t >= 0 && t < n) tc = cadd(tc, cscale(cis_rev(-downshift_rev(J.r, t)), J.mf[i]));
+  }
+  return tc;
+}
+
+// KK: AGC'd carrier-free 2-sps sample u[m] = g (Z[m] - mean T[m]) (zero outside).
+__device__ __forceinline__ float2 kk_sample(const RxJob &J, const float2 *__restrict__ z, int64_t m, int64_t n,
+                                            float2 mean, float g) {
+  if (m < 0 || m >= n / 2) return make_float2(0.0f, 0.0f);
+  return cscale(csub(z[m], cmul(mean, kk_carrier_term(J, m, n))), g);
+}

@@ -36,7 +36,7 @@ struct RxJob {
   float2 *z;                        // KK: MF output / carrier-free field at 2 sps [n/2]
   float *y;                         // PAM: MF output [n]
   float *xr;                        // PAM: timing-corrected samples [n]
-  double2 *part;                    // per-workgroup partial sums (stage 1)
+  double2 *part;                    // per-workgroup partial sums (KK: 3 per workgroup, see kk_front)
   double *part2;                    // per-workgroup partial sums (stage 2)
   uint32_t *upart;                  // PAM code-sum partials
   float2 *gard;                     // PAM: Gardner sums per 512-sample block
@@ -45,6 +45,7 @@ struct RxJob {
   float2 *s4;                       // KK: sum z^4 per DD-LMS block
   float *theta;                     // KK: carrier phase per block
   float2 *field;                    // KK debug: reconstructed field [n] or null
+  float2 *udbg;                     // KK debug: AGC'd carrier-free MF output [n/2] or null
   const float *mlp;                 // PAM learned equaliser parameters (FP32) or null
   RxScalars *sc;
 };
@@ -72,7 +73,7 @@ static inline int rx_kk_hop(int log2n) {
 
 // Kernel stages (host-side launchers are defined with their kernels).
 enum RxStage {
-  ST_KK_FRONT = 0, ST_KK_FINALIZE, ST_PAM_SUM, ST_PAM_MF, ST_PAM_GAVG, ST_PAM_UNWRAP, ST_PAM_FARROW,
+  ST_KK_FRONT = 0, ST_KK_DEBUG, ST_PAM_SUM, ST_PAM_MF, ST_PAM_GAVG, ST_PAM_UNWRAP, ST_PAM_FARROW,
   ST_PREFIX, ST_BLOCKS, ST_KK_VV, ST_DECIDE, ST_MLP_INFER, ST_MLP_JUDGE, ST_COUNT
 };
 void rx_launch_kk_stage(int stage, const RxLaunch &L, int64_t maxn, int log2n, int prec, hipStream_t s);

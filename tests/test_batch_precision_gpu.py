@@ -107,7 +107,7 @@ def test_precision_form(rx, prec, n, seed):
     r = rx.Receiver(5, s, max_samples=n, debug=True, precision=prec)
     bits = r.process(_dev(g["packed"]), n).cpu().numpy()
     sc = r.fetch(rx.RX_STAGE_SCALARS, n)
-    mf = r.fetch(rx.RX_STAGE_MF, n) * sc[2]
+    mf = r.fetch(rx.RX_STAGE_MF, n)   # already AGC'd
     soft = r.fetch(rx.RX_STAGE_SOFT, n)
     err = r.errors()
     r.close()

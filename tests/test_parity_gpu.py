@@ -56,7 +56,7 @@ def check_chain(rx, fmt, n, seed, snr, **gen):
         field = r.fetch(rx.RX_STAGE_FIELD, n)
         report["field"] = parity.rel_rms(field, o["field"])
         assert report["field"] <= 1e-5, report
-        mf = r.fetch(rx.RX_STAGE_MF, n) * sc[2]
+        mf = r.fetch(rx.RX_STAGE_MF, n)   # already AGC'd
         report["mf"] = parity.rel_rms(mf, o["mf"])
         assert report["mf"] <= 2e-5, report
         assert abs(complex(sc[0], sc[1]) - complex(o["mean_re"], o["mean_im"])) <= 1e-5 * abs(
