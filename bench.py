@@ -41,6 +41,8 @@ def main():
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--distinct", type=int, default=8)
     ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--streams", type=int, default=2,
+                    help="consecutive batches alternate over this many HIP streams (batch pipelining)")
     ap.add_argument("--cpu-buffers", type=int, default=8)
     ap.add_argument("--copy-probe", type=int, default=1, help="run a 256 MiB device copy (counter scale)")
     ap.add_argument("--forms", default="bf16,fp16", help="precision forms timed beside the plain chain")
@@ -63,42 +65,52 @@ def main():
     gens = [synth.kk_2e22(synth.KK_16QAM, index=i) for i in range(a.distinct)]
     log(f"[bench] generated {a.distinct} KK-16QAM buffers in {time.time() - t0:.1f}s")
     bufs = [torch.from_numpy(g["packed"]).to(dev) for g in gens]
-    def run_form(precision, profile):
-        recs = [rx.Receiver(rx.RX_KK_16QAM, gens[i % a.distinct]["seed"], max_samples=N,
-                            flags=rx.RX_PROFILE if (i == 0 and profile) else 0, precision=precision)
-                for i in range(a.batch)]
-        outs = [torch.empty(r.bits_bytes(N), dtype=torch.uint8, device=dev) for r in recs]
-        hs = [r.h for r in recs]
+    streams = [torch.cuda.Stream(device=dev) for _ in range(max(1, a.streams))]   # default priority
+
+    def run_form(precision, profile, nstreams=a.streams, steps=a.steps):
+        sets = []
+        for si, st in enumerate(streams[:max(1, nstreams)]):
+            recs = [rx.Receiver(rx.RX_KK_16QAM, gens[i % a.distinct]["seed"], max_samples=N, stream=st,
+                                flags=rx.RX_PROFILE if (i == 0 and si == 0 and profile) else 0,
+                                precision=precision) for i in range(a.batch)]
+            outs = [torch.empty(r.bits_bytes(N), dtype=torch.uint8, device=dev) for r in recs]
+            sets.append((recs, outs, [r.h for r in recs], [o.data_ptr() for o in outs]))
         bp = [bufs[i % a.distinct].data_ptr() for i in range(a.batch)]
-        op = [o.data_ptr() for o in outs]
         ns = [N] * a.batch
 
-        def step():
+        def step(i):
+            _, _, hs, op = sets[i % len(sets)]
             rx.rx_process_batch(hs, bp, ns, op, graph=bool(a.graph))
 
-        for _ in range(a.warmup):
-            step()
+        for i in range(a.warmup * len(sets)):
+            step(i)
         torch.cuda.synchronize()
+        h0 = sets[0][2][0]
         if profile:
-            rx.rx_stage_times(hs[0], reset=True)
-        for r in recs:
-            r.reset()
+            rx.rx_stage_times(h0, reset=True)
+        for recs, _, _, _ in sets:
+            for r in recs:
+                r.reset()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        for _ in range(a.steps):
-            step()
+        for i in range(steps):
+            step(i)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t1
-        stages = rx.rx_stage_times(hs[0]) if profile else {}
-        errs = [r.errors() for r in recs]
-        for r in recs:
-            r.close()
+        stages = rx.rx_stage_times(h0) if profile else {}
+        errs = [r.errors() for recs, _, _, _ in sets for r in recs]
+        for recs, _, _, _ in sets:
+            for r in recs:
+                r.close()
         bits = sum(e["bits"] for e in errs)
         berr = sum(e["bit_errors"] for e in errs)
         return wall, stages, (berr / bits if bits else None)
 
     wall, stages, ber = run_form(rx.RX_FP32, True)
     log(f"[bench] plain chain: {a.steps} steps x {a.batch} buffers in {wall:.3f}s")
+    # the same chain on one stream, so that each stage's launch owns the chip
+    wall1, stages1, _ = run_form(rx.RX_FP32, True, nstreams=1)
+    log(f"[bench] plain chain, one stream: {a.steps} steps in {wall1:.3f}s")
     forms = {}
     for name in [f for f in a.forms.split(",") if f]:
         prec = {"bf16": rx.RX_BF16, "fp16": rx.RX_FP16}[name]
@@ -204,19 +216,26 @@ def main():
                  "realtime_budget_ms_per_batch": round(a.batch * N / 4e9 * 1e3, 3), "ber": ber_m}
         log(f"[bench] mixed batch {mixed}")
 
-    # dominant kernel: the stage with the largest total time
-    dom = max(stages, key=lambda k: stages[k][0])
-    dom_ms = stages[dom][0] / stages[dom][1]
-    per_stage_us_per_buffer = {k: round(v[0] / v[1] * 1e3 / a.batch, 3) for k, v in stages.items()}
-    if dom == "kk_front":
+    def roofline(st):
+        # dominant kernel: the stage with the largest total time
+        dom = max(st, key=lambda k: st[k][0])
+        dom_ms = st[dom][0] / st[dom][1]
+        if dom != "kk_front":
+            return {"bound": "latency", "achieved": None, "peak": None, "unit": None, "frac": None,
+                    "traffic": None, "kernel": dom}
         flop = front_flop_per_sample(14) * samples
         achieved = flop / (dom_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_FP32_VALU_TFLOPS,
+        return {"bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_FP32_VALU_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4), "traffic": None,
-                "kernel": "kk_front<14>", "flop_per_sample": round(front_flop_per_sample(14), 2)}
-    else:
-        roof = {"bound": "latency", "achieved": None, "peak": None, "unit": None, "frac": None,
-                "traffic": None, "kernel": dom}
+                "kernel": "kk_front<14>", "flop_per_sample": round(front_flop_per_sample(14), 2),
+                "launch_us": round(dom_ms * 1e3, 2)}
+
+    def per_buffer(st):
+        return {k: round(v[0] / v[1] * 1e3 / a.batch, 3) for k, v in st.items()}
+
+    roof = roofline(stages)
+    roof1 = roofline(stages1)
+    roof1["value"] = round(samples / (wall1 / a.steps) / 1e9, 3)
 
     if a.copy_probe:
         src = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
@@ -244,14 +263,16 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "KK-16QAM receiver chain, plain FP32, 2^22-sample 12-bit buffers "
                                "at 4 Gs/s (1 GBaud, CSPR 10 dB, 22 dB SNR)",
-                   "buffers_per_step": a.batch, "samples_per_buffer": N, "graph": bool(a.graph)},
+                   "buffers_per_step": a.batch, "samples_per_buffer": N, "graph": bool(a.graph),
+                   "streams": a.streams},
         "realtime_factor": round(gsps / 4.0, 2),
         "ber": ber,
         "forms": forms,
         "mlp_form": mlp_form,
         "mixed_batch": mixed,
-        "stage_us_per_buffer": per_stage_us_per_buffer,
+        "stage_us_per_buffer": per_buffer(stages),
         "roofline": roof,
+        "one_stream": {"stage_us_per_buffer": per_buffer(stages1), "roofline": roof1},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

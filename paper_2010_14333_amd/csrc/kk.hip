@@ -100,8 +100,7 @@ __global__ __launch_bounds__((1 << LOGN) / 16) void kk_front(RxLaunch L) {
 
   double se_re = 0.0, se_im = 0.0;
   double zz = 0.0, tt = 0.0, ztr = 0.0, zti = 0.0;   // sum |Z|^2, |T|^2, Z conj(T)
-  auto zstat = [&](int64_t m, float2 zv) {
-    const float2 tc = kk_carrier_term(J, m, n);
+  auto zstat = [&](int64_t m, float2 zv, float2 tc) {
     zz += (double)zv.x * zv.x + (double)zv.y * zv.y;
     tt += (double)tc.x * tc.x + (double)tc.y * tc.y;
     const float2 p = cmulc(zv, tc);
@@ -171,13 +170,18 @@ __global__ __launch_bounds__((1 << LOGN) / 16) void kk_front(RxLaunch L) {
             wo[(7 - ee) & 7] = hod[31 - e + 8];
           }
         }
-  #pragma unroll
+        // carrier term of the 8 outputs: exact at the first, then rotated by
+        // exp(-j 4 pi r) (it enters only the AGC power sums)
+        const int64_t mb = m0 + 8 * t8;
+        float2 tc = kk_carrier_term(J, mb, n);
+#pragma unroll
         for (int o = 0; o < 8; o++) {
-          const int64_t m = m0 + 8 * t8 + o;
+          const int64_t m = mb + o;
           if (2 * m < n) {
-          J.z[m] = acc[o];
-          zstat(m, acc[o]);
-        }
+            J.z[m] = acc[o];
+            if (o > 0) tc = kk_interior(m, n) ? cmul(tc, J.rot2) : kk_carrier_term(J, m, n);
+            zstat(m, acc[o], tc);
+          }
         }
       }
 
@@ -219,7 +223,7 @@ __global__ __launch_bounds__((1 << LOGN) / 16) void kk_front(RxLaunch L) {
           if (t2 < NTILE && 2 * m < n) {
             const float2 zv = make_float2(acc[2 * jj], acc[2 * jj + 1]);
             J.z[m] = zv;
-            zstat(m, zv);
+            zstat(m, zv, kk_carrier_term(J, m, n));
           }
         }
       }

@@ -144,15 +144,20 @@ __device__ __forceinline__ float2 cis_rev(float rev) {
 
 // KK: the matched filter's response to the downshifted carrier,
 // T[m] = sum_i h[i] exp(-j 2 pi frac(r (2m + 32 - i))) over in-range samples;
-// in the interior it is c0 exp(-j 2 pi frac(2 r m)).
-__device__ __forceinline__ float2 kk_carrier_term(const RxJob &J, int64_t m, int64_t n) {
-  if (m >= 16 && 2 * m + 32 < n) return cmul(J.c0, cis_rev(-downshift_rev(J.r, 2 * m)));
+// in the interior it is c0 exp(-j 2 pi frac(2 r m)).  The 16 outputs at each
+// edge take the direct sum, kept out of line so callers stay compact.
+__device__ __noinline__ float2 kk_carrier_edge(const float *__restrict__ mf, double r, int64_t m, int64_t n) {
   float2 tc = make_float2(0.0f, 0.0f);
   for (int i = 0; i < 65; i++) {
     const int64_t t = 2 * m + 32 - i;
-    if (t >= 0 && t < n) tc = cadd(tc, cscale(cis_rev(-downshift_rev(J.r, t)), J.mf[i]));
+    if (t >= 0 && t < n) tc = cadd(tc, cscale(cis_rev(-downshift_rev(r, t)), mf[i]));
   }
   return tc;
+}
+__device__ __forceinline__ bool kk_interior(int64_t m, int64_t n) { return m >= 16 && 2 * m + 32 < n; }
+__device__ __forceinline__ float2 kk_carrier_term(const RxJob &J, int64_t m, int64_t n) {
+  if (kk_interior(m, n)) return cmul(J.c0, cis_rev(-downshift_rev(J.r, 2 * m)));
+  return kk_carrier_edge(J.mf, J.r, m, n);
 }
 
 // KK: AGC'd carrier-free 2-sps sample u[m] = g (Z[m] - mean T[m]) (zero outside).
