@@ -31,7 +31,63 @@ __device__ __forceinline__ void frame_codes8(const uint8_t *in, int64_t n, int64
   }
 }
 
-__device__ __forceinline__ int ypad(int q) { return q + (q >> 5); }
+// LDS slot of y' sample q.  The filter's A operand reads, per instruction,
+// one component of 16 rows (8 tiles 32 samples apart) x 4 (PREC 0) or 4 x 8
+// (PREC 1, 2) window positions; the padding spreads them over distinct banks:
+// 4 float2 per 32 for FP32 (tile stride 72 dwords), 1 per 32 for the narrow
+// forms (66 dwords).
+template <int PREC>
+__device__ __forceinline__ int yidx(int q) { return PREC == 0 ? q + 4 * (q >> 5) : q + (q >> 5); }
+
+// Matched-filter B operand (the tap matrix) and one wavefront pass of eight
+// 16-output tiles.  Lane l holds column q = l % 16 and K-row group l / 16.
+template <int PREC> struct MfB;
+template <> struct MfB<0> {
+  // v_mfma_f32_16x16x4_f32: lane l supplies A[l % 16][l / 16], B[l / 16][l % 16].
+  // B[t][q] = htab[2 q + 95 - t] from a zero-padded copy of the taps in LDS
+  // (h[i] at index i + 31), read per step rather than held in registers.
+  const float *hb;
+  __device__ void load(const float *__restrict__ htab, int row, int kq) { hb = htab + 2 * row + 95 - kq; }
+  __device__ rx_f32x4 apply(const float *__restrict__ ly, int tile, int comp, int kq) const {
+    // A[row][4 ks + kq] = component of y'[32 tile + 4 ks + kq]; 4 ks + kq stays
+    // inside one 32-sample group, so the padded offset is 36 tile + kq + 4 ks +
+    // 4 (ks / 8) float2.
+    const float *a = ly + 2 * (36 * tile + kq) + comp;
+    rx_f32x4 c0 = {0.0f, 0.0f, 0.0f, 0.0f}, c1 = c0;
+#pragma unroll
+    for (int ks = 0; ks < 24; ks += 2) {
+      c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2 * (4 * ks + 4 * (ks >> 3))], hb[-4 * ks], c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2 * (4 * ks + 4 + 4 * ((ks + 1) >> 3))], hb[-4 * ks - 4], c1,
+                                                0, 0, 0);
+    }
+    return c0 + c1;
+  }
+};
+template <int PREC> struct MfB {
+  // v_mfma_f32_16x16x32_{bf16,f16}: operands rounded once to the narrow type
+  using NT = NarrowT<PREC>;
+  typename NT::vec b[3];
+  __device__ void load(const float *__restrict__ mf, int row, int kq) {
+#pragma unroll
+    for (int ks = 0; ks < 3; ks++)
+#pragma unroll
+      for (int j = 0; j < 8; j++) {
+        const int t = 32 * ks + 8 * kq + j, tap = 2 * row + 64 - t;
+        b[ks][j] = NT::cvt((tap >= 0 && tap <= 64) ? mf[tap] : 0.0f);
+      }
+  }
+  __device__ rx_f32x4 apply(const float *__restrict__ ly, int tile, int comp, int kq) const {
+    rx_f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int ks = 0; ks < 3; ks++) {
+      typename NT::vec a;
+#pragma unroll
+      for (int j = 0; j < 8; j++) a[j] = NT::cvt(ly[2 * yidx<PREC>(32 * tile + 32 * ks + 8 * kq + j) + comp]);
+      acc = NT::mfma(a, b[ks], acc);
+    }
+    return acc;
+  }
+};
 
 template <int LOGN, int PREC>
 __global__ __launch_bounds__((1 << LOGN) / 16) void kk_front(RxLaunch L) {
@@ -41,8 +97,8 @@ __global__ __launch_bounds__((1 << LOGN) / 16) void kk_front(RxLaunch L) {
   constexpr int QPT = (QN + T - 1) / T;
   constexpr float INV2PI = 0.15915494309189535f;
   __shared__ float2 lds[N + N / 16];
-  __shared__ double red[T / 64];
-  __shared__ float hev[48], hod[48];   // h[2q], h[2q-1] at index q+8, zero outside the filter
+  __shared__ double red[9 * (T / 64)];
+  __shared__ float htab[128];   // matched-filter taps h[i] at i + 31, zero elsewhere
 
   const int jb = blockIdx.y;
   const RxJob J = *L.job[jb];
@@ -53,10 +109,9 @@ __global__ __launch_bounds__((1 << LOGN) / 16) void kk_front(RxLaunch L) {
   if (blk[0] >= nrb) return;
   const int64_t F[2] = {blk[0] * HOP - RX_KK_EDGE, blk[1] * HOP - RX_KK_EDGE};
 
-  if (threadIdx.x < 48) {
-    const int q = (int)threadIdx.x - 8;
-    hev[threadIdx.x] = (q >= 0 && 2 * q <= 64) ? J.mf[2 * q] : 0.0f;
-    hod[threadIdx.x] = (q >= 1 && 2 * q - 1 <= 64) ? J.mf[2 * q - 1] : 0.0f;
+  if (threadIdx.x < 128) {
+    const int i = (int)threadIdx.x - 31;
+    htab[threadIdx.x] = (i >= 0 && i <= 64) ? J.mf[i] : 0.0f;
   }
 
   // 1. l - l_ref for both frames (l_ref: the frame's centre sample; the
@@ -98,15 +153,24 @@ __global__ __launch_bounds__((1 << LOGN) / 16) void kk_front(RxLaunch L) {
   }
   __syncthreads();
 
-  double se_re = 0.0, se_im = 0.0;
-  double zz = 0.0, tt = 0.0, ztr = 0.0, zti = 0.0;   // sum |Z|^2, |T|^2, Z conj(T)
-  auto zstat = [&](int64_t m, float2 zv, float2 tc) {
-    zz += (double)zv.x * zv.x + (double)zv.y * zv.y;
-    tt += (double)tc.x * tc.x + (double)tc.y * tc.y;
-    const float2 p = cmulc(zv, tc);
-    ztr += p.x;
-    zti += p.y;
-  };
+  // Workgroup partial sums: the field E (carrier mean), |Z|^2, and the
+  // carrier terms.  In the interior T[m] = c0 P(m)^*, P(m) = exp(+j 2 pi
+  // frac(2 r m)), so sum Z conj(T) = conj(c0) sum Z P and sum |T|^2 = |c0|^2
+  // per output; the edge outputs take the exact T.  Per-thread sums are in
+  // FP32 (at most a few dozen terms), the workgroup sums in FP64.
+  float se_re = 0.0f, se_im = 0.0f, zz = 0.0f;
+  float2 sp = make_float2(0.0f, 0.0f), sedge = make_float2(0.0f, 0.0f);
+  float tedge = 0.0f;
+  int nint = 0;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int row = lane & 15, kq = lane >> 4;
+  constexpr int NTILE = HOP / 32;          // 16-output tiles per block
+  constexpr int NG = (NTILE + 7) / 8;      // eight tiles per wavefront pass
+  constexpr int NW = T / 64;
+  // rotations of P between this lane's outputs: +16 (second tile) and
+  // +16 * 8 * NW (next pass)
+  const float2 r16 = cis_rev(downshift_rev(J.r, 2 * 16));
+  const float2 rpass = cis_rev(downshift_rev(J.r, 2 * 16 * 8 * NW));
 #pragma unroll
   for (int x = 0; x < 2; x++) {
     // 3. field, carrier mean partials, downshifted field y' into LDS
@@ -128,115 +192,58 @@ __global__ __launch_bounds__((1 << LOGN) / 16) void kk_front(RxLaunch L) {
             if (J.field) J.field[t] = e;
           }
         }
-        lds[ypad(q)] = yv;
+        lds[yidx<PREC>(q)] = yv;
       }
     }
     __syncthreads();
+    // 4. decimating matched filter Z[m] = sum_i h[i] y'[2m + 32 - i] as a
+    //    Toeplitz GEMM on MFMA: a row of A is one real component (re or im)
+    //    of the 96-sample window of a tile of 16 outputs, B[t][q] =
+    //    h[2q + 64 - t]; eight tiles (16 rows) per wavefront pass.  PREC 0
+    //    takes FP32 operands (16x16x4 steps), the precision form narrow ones
+    //    (16x16x32 steps), both with FP32 accumulation.
     const int64_t m0 = blk[x] * (HOP / 2);
-    if constexpr (PREC == 0) {
-      // 4. decimating matched filter Z[m] = sum_i h[i] y'[2m + 32 - i], eight
-      //    consecutive outputs per thread.  Polyphase form: at step e the input
-      //    pair y'(2e), y'(2e+1) meets the even taps h[2(o+32-e)] and the odd
-      //    taps h[2(o+32-e)-1] of outputs o = 0..7; those taps form an 8-wide
-      //    window that slides by one per step, so each step loads one even and
-      //    one odd tap (zero-padded tables in LDS) and two inputs.
-      for (int t8 = threadIdx.x; t8 < HOP / 16; t8 += T) {
-        float2 acc[8];
-        float we[8], wo[8];
-  #pragma unroll
-        for (int o = 0; o < 8; o++) {
-          acc[o] = make_float2(0.0f, 0.0f);
-          we[o] = hev[32 + o + 8];
-          wo[o] = hod[32 + o + 8];
-        }
-        const int qb = 16 * t8;
-  #pragma unroll 1
-        for (int eb = 0; eb < 40; eb += 8) {
-  #pragma unroll
-          for (int ee = 0; ee < 8; ee++) {
-            const int e = eb + ee;
-            const float2 y0 = lds[ypad(qb + 2 * e)];
-            const float2 y1 = lds[ypad(qb + 2 * e + 1)];
-  #pragma unroll
-            for (int o = 0; o < 8; o++) {
-              const int slot = (o - ee + 8) & 7;
-              acc[o].x = fmaf(we[slot], y0.x, acc[o].x);
-              acc[o].y = fmaf(we[slot], y0.y, acc[o].y);
-              acc[o].x = fmaf(wo[slot], y1.x, acc[o].x);
-              acc[o].y = fmaf(wo[slot], y1.y, acc[o].y);
-            }
-            // next step's window: slot (-e-1) mod 8 takes h(31 - e)
-            we[(7 - ee) & 7] = hev[31 - e + 8];
-            wo[(7 - ee) & 7] = hod[31 - e + 8];
-          }
-        }
-        // carrier term of the 8 outputs: exact at the first, then rotated by
-        // exp(-j 4 pi r) (it enters only the AGC power sums)
-        const int64_t mb = m0 + 8 * t8;
-        float2 tc = kk_carrier_term(J, mb, n);
+    MfB<PREC> bmf;
+    if constexpr (PREC == 0) bmf.load(htab, row, kq);
+    else bmf.load(J.mf, row, kq);
+    const float *ly = reinterpret_cast<const float *>(lds);
+    // P at this lane's first output of the block, exact from the FP64 phase
+    const int64_t mfirst = m0 + 16 * (8 * wv + 2 * kq) + row;
+    float2 pp = cis_rev(downshift_rev(J.r, 2 * mfirst));
+    for (int grp = wv; grp < NG; grp += NW) {
+      const int tile = grp * 8 + (row >> 1);
+      const rx_f32x4 acc = bmf.apply(ly, tile, row & 1, kq);
 #pragma unroll
-        for (int o = 0; o < 8; o++) {
-          const int64_t m = mb + o;
-          if (2 * m < n) {
-            J.z[m] = acc[o];
-            if (o > 0) tc = kk_interior(m, n) ? cmul(tc, J.rot2) : kk_carrier_term(J, m, n);
-            zstat(m, acc[o], tc);
+      for (int jj = 0; jj < 2; jj++) {
+        const int t2 = grp * 8 + 2 * kq + jj;
+        const int64_t m = m0 + 16 * t2 + row;
+        const float2 p = jj ? cmul(pp, r16) : pp;
+        if (t2 < NTILE && 2 * m < n) {
+          const float2 zv = make_float2(acc[2 * jj], acc[2 * jj + 1]);
+          J.z[m] = zv;
+          zz = fmaf(zv.x, zv.x, fmaf(zv.y, zv.y, zz));
+          if (kk_interior(m, n)) {
+            sp = cadd(sp, cmul(zv, p));
+            nint++;
+          } else {
+            const float2 te = kk_carrier_edge(J.mf, J.r, m, n);
+            sedge = cadd(sedge, cmulc(zv, te));
+            tedge = fmaf(te.x, te.x, fmaf(te.y, te.y, tedge));
           }
         }
       }
-
-    } else {
-      // 4'. precision form: the same filter as a Toeplitz GEMM on MFMA with
-      //     narrow operands and FP32 accumulation.  A row = one real
-      //     component (re or im) of the 96-sample window of a tile of 16
-      //     outputs, B[t][q] = h[2q + 64 - t]; one 16x16x32 step per 32
-      //     window samples, eight tiles (16 rows) per wavefront pass.
-      using NT = NarrowT<PREC>;
-      const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-      constexpr int NTILE = HOP / 32;
-      const int row = lane & 15, kq = lane >> 4;
-      typename NT::vec bmf[3];   // B fragments of the tap matrix
-#pragma unroll
-      for (int ks = 0; ks < 3; ks++)
-#pragma unroll
-        for (int j = 0; j < 8; j++) {
-          const int t = 32 * ks + 8 * kq + j, tap = 2 * row + 64 - t;
-          bmf[ks][j] = NT::cvt((tap >= 0 && tap <= 64) ? J.mf[tap] : 0.0f);
-        }
-      for (int grp = wv; grp < (NTILE + 7) / 8; grp += T / 64) {
-        const int tile = grp * 8 + (row >> 1);
-        rx_f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int ks = 0; ks < 3; ks++) {
-          typename NT::vec a;
-#pragma unroll
-          for (int j = 0; j < 8; j++) {
-            const float2 v = lds[ypad(32 * tile + 32 * ks + 8 * kq + j)];
-            a[j] = NT::cvt((row & 1) ? v.y : v.x);
-          }
-          acc = NT::mfma(a, bmf[ks], acc);
-        }
-#pragma unroll
-        for (int jj = 0; jj < 2; jj++) {
-          const int t2 = grp * 8 + 2 * kq + jj;
-          const int64_t m = m0 + 16 * t2 + row;
-          if (t2 < NTILE && 2 * m < n) {
-            const float2 zv = make_float2(acc[2 * jj], acc[2 * jj + 1]);
-            J.z[m] = zv;
-            zstat(m, zv, kk_carrier_term(J, m, n));
-          }
-        }
-      }
+      pp = cmul(pp, rpass);
     }
     __syncthreads();
   }
-  const double sr = block_sum(se_re, red), si = block_sum(se_im, red);
-  const double szz = block_sum(zz, red), stt = block_sum(tt, red);
-  const double szr = block_sum(ztr, red), szi = block_sum(zti, red);
+  double v[9] = {se_re, se_im, zz, tedge, (double)nint, sp.x, sp.y, sedge.x, sedge.y};
+  block_sum_n<9>(v, red);
   if (threadIdx.x == 0) {
-    J.part[3 * blockIdx.x] = make_double2(sr, si);          // sum of the field E
-    J.part[3 * blockIdx.x + 1] = make_double2(szz, stt);    // sum |Z|^2, sum |T|^2
-    J.part[3 * blockIdx.x + 2] = make_double2(szr, szi);    // sum Z conj(T)
+    const double c0r = J.c0.x, c0i = J.c0.y;
+    J.part[3 * blockIdx.x] = make_double2(v[0], v[1]);                          // sum of the field E
+    J.part[3 * blockIdx.x + 1] = make_double2(v[2], v[3] + v[4] * (c0r * c0r + c0i * c0i));  // |Z|^2, |T|^2
+    J.part[3 * blockIdx.x + 2] = make_double2(c0r * v[5] + c0i * v[6] + v[7],    // sum Z conj(T)
+                                              c0r * v[6] - c0i * v[5] + v[8]);
   }
 }
 

@@ -70,6 +70,28 @@ __device__ __forceinline__ double block_sum(double v, double *scratch) {
   return s;
 }
 
+// Sums of K doubles over the workgroup, in place (every thread gets them).
+// `scratch` holds at least K * blockDim.x / 64 doubles.
+template <int K>
+__device__ __forceinline__ void block_sum_n(double *v, double *scratch) {
+  const int w = threadIdx.x / RX_WAVE, nw = blockDim.x / RX_WAVE;
+#pragma unroll
+  for (int k = 0; k < K; k++) v[k] = wave_sum(v[k]);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < K; k++) scratch[k * nw + w] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    double s = 0.0;
+    for (int i = 0; i < nw; i++) s += scratch[k * nw + i];
+    v[k] = s;
+  }
+  __syncthreads();
+}
+
 // ---- reference sequence (SplitMix64, Steele, Lea & Flood 2014) -----------
 __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
   uint64_t z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
