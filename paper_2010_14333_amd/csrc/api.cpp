@@ -257,14 +257,13 @@ int rx_create(rx_format fmt, double baud, double fs, const rx_params *pin, rx_ha
     std::complex<double> c0 = 0.0;
     for (int i = 0; i < 65; i++) c0 += (double)hf[i] * std::exp(std::complex<double>(0.0, -2.0 * M_PI * J.r * (32 - i)));
     J.c0 = make_float2((float)c0.real(), (float)c0.imag());
-    J.rot2 = make_float2((float)std::cos(4.0 * M_PI * J.r), (float)-std::sin(4.0 * M_PI * J.r));
     const int n = 1 << h->log2n;
     std::vector<float> hs = design_hilbert_spectrum(p.hilbert_taps, h->log2n);
     std::vector<float2> tw = design_twiddles(h->log2n);
     float *dhs = A.get<float>(n);
-    float2 *dtw = A.get<float2>(n);
+    float2 *dtw = A.get<float2>(tw.size());
     ok = dhs && dtw && hipMemcpy(dhs, hs.data(), n * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
-         hipMemcpy(dtw, tw.data(), n * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess;
+         hipMemcpy(dtw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess;
     J.hspec = dhs;
     J.twid = dtw;
     const int64_t nd = L / 2;

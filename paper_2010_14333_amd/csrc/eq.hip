@@ -226,6 +226,9 @@ __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
       return (j >= 0 && j < nx) ? xin[j] : 0.0f;
     }
   };
+  static_assert(256 % (2 * BC) == 0, "staging assumes whole lanes per pass");
+  const float2 Mc = cscale(cmul(mean, J.c0), g);
+  const float2 rstep = cis_rev(-downshift_rev(J.r, 2 * 2 * (256 / (2 * BC)) * (int64_t)blk));
   float2 w[K];
   T xs[K + 2 * BC];   // xs[t] = sample p0 - C + t (+ 2 BC per chunk)
 #pragma unroll
@@ -237,10 +240,30 @@ __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
   const int nch = blk / BC;
   for (int ch = 0; ch < nch; ch++) {
     // lane l's next 2*BC samples start at p0_l + C + 1 + 2*BC*ch
-    for (int e = threadIdx.x; e < 256 * 2 * BC; e += 256) {
-      const int l = e / (2 * BC), jj = e % (2 * BC);
-      const int64_t pl = 2 * ((b0 + l) * blk + s) + C + 1 + 2 * BC * ch + jj;
-      sin_[l * (2 * BC + 1) + jj] = load(pl);
+    if constexpr (CPLX) {
+      // thread: stream position jj of lanes l0 + LPP i, whose samples are
+      // 2 LPP blk apart, so the carrier phasor P(p) = exp(-j 2 pi frac(2 r p))
+      // advances by one fixed rotation from an FP64 anchor per chunk; the
+      // interior sample is then u = g z - (g mean c0) P (the edge samples
+      // take the exact form).
+      constexpr int LPP = 256 / (2 * BC);
+      const int l0 = threadIdx.x / (2 * BC), jj = threadIdx.x % (2 * BC);
+      const int64_t pa = 2 * ((b0 + l0) * blk + s) + C + 1 + 2 * BC * ch + jj;
+      float2 P = cis_rev(-downshift_rev(J.r, 2 * pa));
+#pragma unroll 4
+      for (int i = 0; i < 2 * BC; i++) {
+        const int64_t pl = pa + (int64_t)i * 2 * LPP * blk;
+        const float2 v = (pl >= 16 && 2 * pl + 32 < n) ? csub(cscale(zin[pl], g), cmul(Mc, P))
+                                                       : load(pl);
+        sin_[(l0 + LPP * i) * (2 * BC + 1) + jj] = v;
+        P = cmul(P, rstep);
+      }
+    } else {
+      for (int e = threadIdx.x; e < 256 * 2 * BC; e += 256) {
+        const int l = e / (2 * BC), jj = e % (2 * BC);
+        const int64_t pl = 2 * ((b0 + l) * blk + s) + C + 1 + 2 * BC * ch + jj;
+        sin_[l * (2 * BC + 1) + jj] = load(pl);
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -249,12 +272,25 @@ __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
     for (int kk = 0; kk < BC; kk++) {
       // tap i sees xs[2 kk + K - 1 - i]
       if constexpr (CPLX) {
+        // z = sum_i w_i x_i and w_i += e conj(x_i), four FMAs per tap each
         float2 z = make_float2(0.0f, 0.0f);
 #pragma unroll
-        for (int i = 0; i < K; i++) z = cadd(z, cmul(w[i], xs[2 * kk + K - 1 - i]));
+        for (int i = 0; i < K; i++) {
+          const float2 xv = xs[2 * kk + K - 1 - i];
+          z.x = fmaf(w[i].x, xv.x, z.x);
+          z.x = fmaf(-w[i].y, xv.y, z.x);
+          z.y = fmaf(w[i].x, xv.y, z.y);
+          z.y = fmaf(w[i].y, xv.x, z.y);
+        }
         const float2 e = make_float2(mu * (decide_level(z.x, m) - z.x), mu * (decide_level(z.y, m) - z.y));
 #pragma unroll
-        for (int i = 0; i < K; i++) w[i] = cadd(w[i], cmulc(e, xs[2 * kk + K - 1 - i]));
+        for (int i = 0; i < K; i++) {
+          const float2 xv = xs[2 * kk + K - 1 - i];
+          w[i].x = fmaf(e.x, xv.x, w[i].x);
+          w[i].x = fmaf(e.y, xv.y, w[i].x);
+          w[i].y = fmaf(e.y, xv.x, w[i].y);
+          w[i].y = fmaf(-e.x, xv.y, w[i].y);
+        }
         const float a2 = z.x * z.x - z.y * z.y, b2 = 2.0f * z.x * z.y;
         s4r += a2 * a2 - b2 * b2;
         s4i += 2.0f * a2 * b2;

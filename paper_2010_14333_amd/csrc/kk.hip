@@ -171,29 +171,39 @@ __global__ __launch_bounds__((1 << LOGN) / 16) void kk_front(RxLaunch L) {
   // +16 * 8 * NW (next pass)
   const float2 r16 = cis_rev(downshift_rev(J.r, 2 * 16));
   const float2 rpass = cis_rev(downshift_rev(J.r, 2 * 16 * 8 * NW));
+  const float2 drot = cis_rev(-downshift_rev(J.r, T));   // downshift phasor step over T samples
 #pragma unroll
   for (int x = 0; x < 2; x++) {
-    // 3. field, carrier mean partials, downshifted field y' into LDS
+    // 3. field, carrier mean partials, downshifted field y' = E D into LDS.
+    //    This thread's samples t = nq0 + q, q = threadIdx + i T, are T apart,
+    //    so the downshift phasor D(t) = exp(-j 2 pi frac(r t)) starts from an
+    //    FP64 anchor and advances by the fixed rotation D(T) per sample.
+    //    Codes: t = nq0 + q sits at byte 3t/2 = base + 3(q + e)/2 with
+    //    e = nq0 mod 2 and base = 3(nq0 - e)/2, all offsets 32-bit.
     const int64_t nq0 = F[x] + RX_KK_EDGE - RX_KK_CMF;   // sample index of q = 0
+    const int e = (int)(nq0 & 1);
+    const uint8_t *cb = in + 3 * ((nq0 - e) / 2);
+    const int qlo = (int)clamp64(-nq0, 0, QN), qhi = (int)clamp64(n - nq0, 0, QN);   // t in [0, n)
+    float2 dph = cis_rev(-downshift_rev(J.r, nq0 + threadIdx.x));
 #pragma unroll
     for (int i = 0; i < QPT; i++) {
       const int q = threadIdx.x + i * T;
       if (q < QN) {
-        const int64_t t = nq0 + q;
         float2 yv = make_float2(0.0f, 0.0f);
-        if (t >= 0 && t < n) {
-          const float mag = sqrtf((float)read_code(in, t) + 0.5f);
-          const float u = downshift_rev(J.r, t);
-          yv = cscale(cis_rev(ph[x][i] - u), mag);
+        if (q >= qlo && q < qhi) {
+          const int o = 3 * (q + e);
+          const int c = (((int)cb[o >> 1] | ((int)cb[(o >> 1) + 1] << 8)) >> (((q + e) & 1) << 2)) & 0xFFF;
+          const float2 ev = cscale(cis_rev(ph[x][i]), sqrtf((float)c + 0.5f));
+          yv = cmul(ev, dph);
           if (q >= RX_KK_CMF && q < RX_KK_CMF + HOP) {
-            const float2 e = cscale(cis_rev(ph[x][i]), mag);
-            se_re += e.x;
-            se_im += e.y;
-            if (J.field) J.field[t] = e;
+            se_re += ev.x;
+            se_im += ev.y;
+            if (J.field) J.field[nq0 + q] = ev;
           }
         }
         lds[yidx<PREC>(q)] = yv;
       }
+      dph = cmul(dph, drot);
     }
     __syncthreads();
     // 4. decimating matched filter Z[m] = sum_i h[i] y'[2m + 32 - i] as a

@@ -30,7 +30,6 @@ struct RxJob {
   int32_t debug;                    // keep derotated soft symbols
   uint64_t seed;
   float2 c0;                        // interior value of MF(exp(-j 2 pi r n)) / exp(-j 2 pi r 2m)
-  float2 rot2;                      // exp(-j 4 pi r): step of that term from m to m+1
   const float *mf;                  // matched filter taps (65 centred for KK, 33 for PAM)
   const float *hspec;               // KK: Hilbert spectrum S[k]/N (H = -j S), N entries
   const float2 *twid;               // KK: exp(-j 2 pi k / N), N entries
