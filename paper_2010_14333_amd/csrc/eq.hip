@@ -6,18 +6,33 @@
 
 #include "rx_dev.hpp"
 
-// Sum over lanes 0..31 of a wavefront, returned in every lane: DPP within
-// rows of 16 (quad swaps, half-row and row mirrors), then two row values.
-#define DPP(v, ctrl) __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xF, 0xF, false))
-__device__ __forceinline__ float tap_sum(float v) {
-  v += DPP(v, 0xB1);    // quad_perm [1,0,3,2]
-  v += DPP(v, 0x4E);    // quad_perm [2,3,0,1]
-  v += DPP(v, 0x141);   // row_half_mirror
-  v += DPP(v, 0x140);   // row_mirror
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0)) +
-         __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+// Serial adaptive filters of the prefix stage, one wavefront: lane l holds
+// tap t = l mod 32 (zero beyond K); lanes 0..31 form the real parts of the
+// products w_t x_t, lanes 32..63 the imaginary parts, so one reduction
+// within each half gives Re z (lane 31) and Im z (lane 63): DPP within rows
+// of 16 (quad swaps, half-row and row mirrors), then row_bcast:15 adds row 0
+// into row 1 and row 2 into row 3.
+#define DPP(v, ctrl, rm) __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, rm, 0xF, false))
+__device__ __forceinline__ float2 split_sum(float v) {
+  v += DPP(v, 0xB1, 0xF);    // quad_perm [1,0,3,2]
+  v += DPP(v, 0x4E, 0xF);    // quad_perm [2,3,0,1]
+  v += DPP(v, 0x141, 0xF);   // row_half_mirror
+  v += DPP(v, 0x140, 0xF);   // row_mirror
+  v += DPP(v, 0x142, 0xA);   // row_bcast:15 into rows 1 and 3
+  return make_float2(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 31)),
+                     __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63)));
 }
 #undef DPP
+
+// One lane's view of the input sample of its tap: products w x split by half.
+struct PfxLane {
+  bool hi;    // lane >= 32: imaginary part of the product
+  __device__ float part(float2 w, float2 x) const {
+    // lanes 0..31: wr xr - wi xi; lanes 32..63: wr xi + wi xr
+    const float xa = hi ? x.y : x.x, xb = hi ? x.x : -x.y;
+    return fmaf(w.y, xb, w.x * xa);
+  }
+};
 
 #define PFX_OFF (2 * RX_LAG + RX_KMAX / 2)
 #define PFX_UL (2 * RX_PREFIX_MAX + 2 * RX_LAG + 2 * PFX_OFF)
@@ -80,29 +95,38 @@ __global__ __launch_bounds__(256) void rx_prefix(RxLaunch L) {
   for (int k = threadIdx.x; k < P; k += 256) ar[k] = ref_symbol(J, k);
   __syncthreads();
 
+  const int tap = lane & 31;
+  const PfxLane pl{lane >= 32};
+  // LDS slot of this lane's input at step k: u[PFX_OFF + 2 k + c - tap]; taps
+  // beyond K read slot 0, which holds a zero (a sample before the buffer)
+  const int xbase = tap < K ? PFX_OFF + c - tap : 0, xstep = tap < K ? 2 : 0;
   if (wv == 0) {
     float2 wi = make_float2(0.0f, 0.0f);
-    if (lane == c) wi.x = kk ? 1.0f : J.ea2_sqrt;
+    if (tap == c) wi.x = kk ? 1.0f : J.ea2_sqrt;
     float th0 = 0.0f;
     if (kk) {
+      // CMA: e = mu (R2 - |z|^2) z, w += e conj(x); static Viterbi-Viterbi
+      // sum of z^4 over the last 2048 outputs
       float s4r = 0.0f, s4i = 0.0f;
-      const float r2 = J.r2, mu = J.mu_cma;
-      const float2 zero = make_float2(0.0f, 0.0f);
-      float2 xn = lane < K ? u[PFX_OFF + c - lane] : zero;
-      for (int k = 0; k < P; k++) {
-        const float2 xi = xn;   // the next step's input is read one step ahead
-        if (k + 1 < P) xn = lane < K ? u[PFX_OFF + 2 * (k + 1) + c - lane] : zero;
-        const float2 pr = cmul(wi, xi);
-        const float zr = tap_sum(pr.x), zi = tap_sum(pr.y);
-        if (k >= P - 2048) {
-          const float ar2 = zr * zr - zi * zi, ai2 = 2.0f * zr * zi;
+      const float mur2 = J.mu_cma * J.r2, mu = J.mu_cma;
+      float2 xn = u[xbase];
+      auto cma_step = [&](int k, bool vv) {
+        const float2 xi = xn;
+        xn = u[xbase + xstep * (k + 1)];   // in range: u extends past the prefix
+        const float2 z = split_sum(pl.part(wi, xi));
+        if (vv) {
+          const float ar2 = z.x * z.x - z.y * z.y, ai2 = 2.0f * z.x * z.y;
           s4r += ar2 * ar2 - ai2 * ai2;
           s4i += 2.0f * ar2 * ai2;
         }
-        const float f = mu * (r2 - (zr * zr + zi * zi));
-        const float2 e = make_float2(zr * f, zi * f);
-        wi = cadd(wi, cmulc(e, xi));
-      }
+        const float f = fmaf(-mu, fmaf(z.y, z.y, z.x * z.x), mur2);
+        const float er = z.x * f, ei = z.y * f;
+        wi.x = fmaf(er, xi.x, fmaf(ei, xi.y, wi.x));
+        wi.y = fmaf(ei, xi.x, fmaf(-er, xi.y, wi.y));
+      };
+      const int k1 = P > 2048 ? P - 2048 : 0;
+      for (int k = 0; k < k1; k++) cma_step(k, false);
+      for (int k = k1; k < P; k++) cma_step(k, true);
       th0 = 0.25f * atan2f(-s4i, -s4r);
       float sn, cn;
       sincosf(-th0, &sn, &cn);
@@ -157,24 +181,23 @@ __global__ __launch_bounds__(256) void rx_prefix(RxLaunch L) {
   __syncthreads();
 
   if (wv == 0) {
+    // data-aided LMS over the prefix at the chosen delay: e = mu (a - z)
     const int s = sel[0], q = sel[1];
-    float2 wi = lane < K ? w[lane] : make_float2(0.0f, 0.0f);
+    float2 wi = tap < K ? w[tap] : make_float2(0.0f, 0.0f);
     const float2 jq = q == 0 ? make_float2(1, 0) : q == 1 ? make_float2(0, 1) : q == 2 ? make_float2(-1, 0) : make_float2(0, -1);
     wi = cmul(wi, jq);
     const float mu = J.mu;
-    const float2 zero = make_float2(0.0f, 0.0f);
-    float2 xn = lane < K ? u[PFX_OFF + 2 * s + c - lane] : zero;
+    const int xb2 = tap < K ? xbase + 2 * s : 0;
+    float2 xn = u[xb2];
     float2 an = ar[0];
     for (int k = 0; k < P; k++) {
       const float2 xi = xn, a = an;   // next step's input and symbol read one step ahead
-      if (k + 1 < P) {
-        xn = lane < K ? u[PFX_OFF + 2 * (k + 1 + s) + c - lane] : zero;
-        an = ar[k + 1];
-      }
-      const float2 pr = cmul(wi, xi);
-      const float zr = tap_sum(pr.x), zi = tap_sum(pr.y);
-      const float2 e = make_float2(mu * (a.x - zr), mu * (a.y - zi));
-      wi = cadd(wi, cmulc(e, xi));
+      xn = u[xb2 + xstep * (k + 1)];
+      an = ar[k + 1 < P ? k + 1 : k];
+      const float2 z = split_sum(pl.part(wi, xi));
+      const float er = mu * (a.x - z.x), ei = mu * (a.y - z.y);
+      wi.x = fmaf(er, xi.x, fmaf(ei, xi.y, wi.x));
+      wi.y = fmaf(ei, xi.x, fmaf(-er, xi.y, wi.y));
     }
     if (lane < RX_KMAX) J.sc->w0[lane] = lane < K ? wi : make_float2(0.0f, 0.0f);
     if (lane == 0) {
