@@ -24,6 +24,11 @@ __device__ __forceinline__ float2 split_sum(float v) {
 }
 #undef DPP
 
+// The value of the other lane of an even/odd lane pair (DPP quad_perm [1,0,3,2]).
+__device__ __forceinline__ float pair_swap(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+
 // One lane's view of the input sample of its tap: products w x split by half.
 struct PfxLane {
   bool hi;    // lane >= 32: imaginary part of the product
@@ -209,18 +214,24 @@ __global__ __launch_bounds__(256) void rx_prefix(RxLaunch L) {
   }
 }
 
-// Block-parallel DD-LMS: each lane adapts one block of `blk` symbols from w0
-// independently (a decision feedback error cannot leave its block).  Lane
-// streams are 2*blk samples apart, so they are staged through LDS in chunks
-// of BC steps: the workgroup loads every lane's next 2*BC samples with
-// coalesced reads, each lane runs BC steps from registers, and the soft
-// outputs go back out the same way.
+// Block-parallel DD-LMS: each block of `blk` symbols is adapted from w0
+// independently (a decision feedback error cannot leave its block).  A block
+// runs on a lane pair split by polyphase: at 2 samples per symbol tap i of the
+// FFE meets only samples of the parity of i, so lane h of the pair holds the
+// taps i = 2a + h and every other sample, xe[j] = x[2j - h]; tap a of either
+// lane sees xe[kk + C - a] at step kk, and one DPP swap adds the two partial
+// outputs.  Half the taps and half the window per lane keep the kernel at
+// four wavefronts per SIMD.  Block streams are 2*blk samples apart, so they
+// are staged through LDS in chunks of BC steps: the workgroup loads every
+// block's next 2*BC samples with coalesced reads, each lane runs BC steps
+// from registers, and the soft outputs go back out the same way.
 #define BC 8
 template <bool CPLX, int K>
 __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
   using T = typename std::conditional<CPLX, float2, float>::type;
-  __shared__ T sin_[256 * (2 * BC + 1)];
-  __shared__ T sout[256 * (BC + 1)];
+  constexpr int NBW = 128;   // blocks per workgroup (one lane pair each)
+  __shared__ T sin_[NBW * (2 * BC + 1)];
+  __shared__ T sout[NBW * (BC + 1)];
   const int jb = blockIdx.y;
   const RxJob J = *L.job[jb];
   const int64_t n = L.n[jb];
@@ -228,10 +239,11 @@ __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
   const int blk = J.blk;
   const int64_t nsym = n / (CPLX ? 4 : 2);
   const int64_t nb = nsym / blk;
-  const int64_t b0 = (int64_t)blockIdx.x * 256;
+  const int64_t b0 = (int64_t)blockIdx.x * NBW;
   if (b0 >= nb) return;
   if (J.mlp && !J.sc->fallback) return;   // the learned equaliser's output stands
-  const int64_t b = b0 + threadIdx.x;
+  const int lb = threadIdx.x >> 1, h = threadIdx.x & 1;
+  const int64_t b = b0 + lb;
   const bool active = b < nb;
   constexpr int C = (K - 1) / 2;
   const float mu = J.mu;
@@ -244,37 +256,39 @@ __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
   float2 *__restrict__ soft = J.soft;
   auto load = [&](int64_t j) -> T {
     if constexpr (CPLX) {
-      return kk_sample(J, zin, j, n, mean, g);
+      return kk_sample<true>(J, zin, j, n, mean, g);
     } else {
       return (j >= 0 && j < nx) ? xin[j] : 0.0f;
     }
   };
-  static_assert(256 % (2 * BC) == 0, "staging assumes whole lanes per pass");
+  constexpr int LPP = 256 / (2 * BC);          // blocks staged per pass of the workgroup
+  static_assert(256 % (2 * BC) == 0 && NBW % LPP == 0, "staging assumes whole blocks per pass");
   const float2 Mc = cscale(cmul(mean, J.c0), g);
-  const float2 rstep = cis_rev(-downshift_rev(J.r, 2 * 2 * (256 / (2 * BC)) * (int64_t)blk));
-  float2 w[K];
-  T xs[K + 2 * BC];   // xs[t] = sample p0 - C + t (+ 2 BC per chunk)
+  const float2 rstep = cis_rev(-downshift_rev(J.r, 2 * 2 * LPP * (int64_t)blk));
+  // taps 2a + h; lane 1's extra tap a = C (index K) stays zero: its update is masked
+  float2 w[C + 1];
 #pragma unroll
-  for (int i = 0; i < K; i++) w[i] = J.sc->w0[i];
+  for (int a = 0; a <= C; a++) w[a] = (2 * a + h < K) ? J.sc->w0[2 * a + h] : make_float2(0.0f, 0.0f);
+  const float umask = h == 0 ? 1.0f : 0.0f;
+  T xe[C + 1 + BC];   // xe[j] = sample p0 - C + 2 j - h (+ 2 BC per chunk)
   const int64_t p0 = 2 * (b * blk + s);
 #pragma unroll
-  for (int t = 0; t < K; t++) xs[t] = load(p0 - C + t);
+  for (int j = 0; j <= C; j++) xe[j] = load(p0 - C + 2 * j - h);
   float s4r = 0.0f, s4i = 0.0f;
   const int nch = blk / BC;
   for (int ch = 0; ch < nch; ch++) {
-    // lane l's next 2*BC samples start at p0_l + C + 1 + 2*BC*ch
+    // block l's next 2*BC samples start at p0_l + C + 1 + 2*BC*ch
     if constexpr (CPLX) {
-      // thread: stream position jj of lanes l0 + LPP i, whose samples are
+      // thread: stream position jj of blocks l0 + LPP i, whose samples are
       // 2 LPP blk apart, so the carrier phasor P(p) = exp(-j 2 pi frac(2 r p))
       // advances by one fixed rotation from an FP64 anchor per chunk; the
       // interior sample is then u = g z - (g mean c0) P (the edge samples
       // take the exact form).
-      constexpr int LPP = 256 / (2 * BC);
       const int l0 = threadIdx.x / (2 * BC), jj = threadIdx.x % (2 * BC);
       const int64_t pa = 2 * ((b0 + l0) * blk + s) + C + 1 + 2 * BC * ch + jj;
       float2 P = cis_rev(-downshift_rev(J.r, 2 * pa));
 #pragma unroll 4
-      for (int i = 0; i < 2 * BC; i++) {
+      for (int i = 0; i < NBW / LPP; i++) {
         const int64_t pl = pa + (int64_t)i * 2 * LPP * blk;
         const float2 v = (pl >= 16 && 2 * pl + 32 < n) ? csub(cscale(zin[pl], g), cmul(Mc, P))
                                                        : load(pl);
@@ -282,56 +296,60 @@ __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
         P = cmul(P, rstep);
       }
     } else {
-      for (int e = threadIdx.x; e < 256 * 2 * BC; e += 256) {
+      for (int e = threadIdx.x; e < NBW * 2 * BC; e += 256) {
         const int l = e / (2 * BC), jj = e % (2 * BC);
         const int64_t pl = 2 * ((b0 + l) * blk + s) + C + 1 + 2 * BC * ch + jj;
         sin_[l * (2 * BC + 1) + jj] = load(pl);
       }
     }
     __syncthreads();
+    // xe[C + 1 + t] = staged position 2 t + 1 - h of this block
 #pragma unroll
-    for (int t = 0; t < 2 * BC; t++) xs[K + t] = sin_[threadIdx.x * (2 * BC + 1) + t];
+    for (int t = 0; t < BC; t++) xe[C + 1 + t] = sin_[lb * (2 * BC + 1) + 2 * t + 1 - h];
 #pragma unroll
     for (int kk = 0; kk < BC; kk++) {
-      // tap i sees xs[2 kk + K - 1 - i]
       if constexpr (CPLX) {
         // z = sum_i w_i x_i and w_i += e conj(x_i), four FMAs per tap each
         float2 z = make_float2(0.0f, 0.0f);
 #pragma unroll
-        for (int i = 0; i < K; i++) {
-          const float2 xv = xs[2 * kk + K - 1 - i];
-          z.x = fmaf(w[i].x, xv.x, z.x);
-          z.x = fmaf(-w[i].y, xv.y, z.x);
-          z.y = fmaf(w[i].x, xv.y, z.y);
-          z.y = fmaf(w[i].y, xv.x, z.y);
+        for (int a = 0; a <= C; a++) {
+          const float2 xv = xe[kk + C - a];
+          z.x = fmaf(w[a].x, xv.x, z.x);
+          z.x = fmaf(-w[a].y, xv.y, z.x);
+          z.y = fmaf(w[a].x, xv.y, z.y);
+          z.y = fmaf(w[a].y, xv.x, z.y);
         }
+        z.x += pair_swap(z.x);
+        z.y += pair_swap(z.y);
         const float2 e = make_float2(mu * (decide_level(z.x, m) - z.x), mu * (decide_level(z.y, m) - z.y));
 #pragma unroll
-        for (int i = 0; i < K; i++) {
-          const float2 xv = xs[2 * kk + K - 1 - i];
-          w[i].x = fmaf(e.x, xv.x, w[i].x);
-          w[i].x = fmaf(e.y, xv.y, w[i].x);
-          w[i].y = fmaf(e.y, xv.x, w[i].y);
-          w[i].y = fmaf(-e.x, xv.y, w[i].y);
+        for (int a = 0; a <= C; a++) {
+          const float2 xv = xe[kk + C - a];
+          const float2 ea = a == C ? cscale(e, umask) : e;
+          w[a].x = fmaf(ea.x, xv.x, w[a].x);
+          w[a].x = fmaf(ea.y, xv.y, w[a].x);
+          w[a].y = fmaf(ea.y, xv.x, w[a].y);
+          w[a].y = fmaf(-ea.x, xv.y, w[a].y);
         }
         const float a2 = z.x * z.x - z.y * z.y, b2 = 2.0f * z.x * z.y;
         s4r += a2 * a2 - b2 * b2;
         s4i += 2.0f * a2 * b2;
-        sout[threadIdx.x * (BC + 1) + kk] = z;
+        if (h == 0) sout[lb * (BC + 1) + kk] = z;
       } else {
         float z = 0.0f;
 #pragma unroll
-        for (int i = 0; i < K; i++) z = fmaf(w[i].x, xs[2 * kk + K - 1 - i], z);
+        for (int a = 0; a <= C; a++) z = fmaf(w[a].x, xe[kk + C - a], z);
+        z += pair_swap(z);
         const float e = mu * (decide_level(z, m) - z);
 #pragma unroll
-        for (int i = 0; i < K; i++) w[i].x = fmaf(e, xs[2 * kk + K - 1 - i], w[i].x);
-        sout[threadIdx.x * (BC + 1) + kk] = z;
+        for (int a = 0; a <= C; a++) w[a].x = fmaf(a == C ? e * umask : e, xe[kk + C - a], w[a].x);
+        if (h == 0) sout[lb * (BC + 1) + kk] = z;
       }
     }
 #pragma unroll
-    for (int t = 0; t < K; t++) xs[t] = xs[t + 2 * BC];
+    for (int j = 0; j <= C; j++) xe[j] = xe[j + BC];
     __syncthreads();
-    for (int e = threadIdx.x; e < 256 * BC; e += 256) {
+    for (int e = threadIdx.x; e < NBW * BC; e += 256) {
       const int l = e / BC, kk = e % BC;
       if (b0 + l < nb) {
         const T v = sout[l * (BC + 1) + kk];
@@ -340,7 +358,7 @@ __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
       }
     }
   }
-  if (CPLX && active) J.s4[b] = make_float2(s4r, s4i);
+  if (CPLX && active && h == 0) J.s4[b] = make_float2(s4r, s4i);
 }
 #undef BC
 
@@ -389,7 +407,7 @@ __global__ __launch_bounds__(256) void rx_ffe_mfma(RxLaunch L) {
 #pragma unroll
     for (int j = 0; j < 8; j++) {
       const int64_t q = base + 32 * h + 8 * kq + j;
-      xv[8 * h + j] = kk_sample(J, zin, q, n, mean, g);
+      xv[8 * h + j] = kk_sample<true>(J, zin, q, n, mean, g);
     }
   rx_f32x4 zr = {0.0f, 0.0f, 0.0f, 0.0f}, zi = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -509,7 +527,7 @@ void rx_launch_eq_stage(int stage, const RxLaunch &L, int64_t maxn, int kk, int 
     else hipLaunchKernelGGL(rx_ffe_mfma<2>, gf, dim3(256), 0, s, L);
   } else if (stage == ST_BLOCKS) {
     const int64_t nb = nsym / (kk ? 128 : 256);
-    dim3 gb((unsigned)((nb + 255) / 256), cnt);
+    dim3 gb((unsigned)((nb + 127) / 128), cnt);   // 128 blocks (lane pairs) per workgroup
     if (kk) {
       if (ffe_taps == 21) hipLaunchKernelGGL((rx_blocks<true, 21>), gb, dim3(256), 0, s, L);
       else hipLaunchKernelGGL((rx_blocks<true, 15>), gb, dim3(256), 0, s, L);

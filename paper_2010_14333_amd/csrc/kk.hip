@@ -236,7 +236,7 @@ __global__ __launch_bounds__((1 << LOGN) / 16) void kk_front(RxLaunch L) {
             sp = cadd(sp, cmul(zv, p));
             nint++;
           } else {
-            const float2 te = kk_carrier_edge(J.mf, J.r, m, n);
+            const float2 te = kk_carrier_edge_inl(J.mf, J.r, m, n);
             sedge = cadd(sedge, cmulc(zv, te));
             tedge = fmaf(te.x, te.x, fmaf(te.y, te.y, tedge));
           }

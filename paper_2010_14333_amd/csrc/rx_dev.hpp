@@ -167,24 +167,32 @@ __device__ __forceinline__ float2 cis_rev(float rev) {
 // KK: the matched filter's response to the downshifted carrier,
 // T[m] = sum_i h[i] exp(-j 2 pi frac(r (2m + 32 - i))) over in-range samples;
 // in the interior it is c0 exp(-j 2 pi frac(2 r m)).  The 16 outputs at each
-// edge take the direct sum, kept out of line so callers stay compact.
-__device__ __noinline__ float2 kk_carrier_edge(const float *__restrict__ mf, double r, int64_t m, int64_t n) {
+// edge take the direct sum: inline where the caller has registers to spare,
+// out of line (kk_carrier_edge) where it has not.
+__device__ __forceinline__ float2 kk_carrier_edge_inl(const float *__restrict__ mf, double r, int64_t m,
+                                                      int64_t n) {
   float2 tc = make_float2(0.0f, 0.0f);
+#pragma unroll 1
   for (int i = 0; i < 65; i++) {
     const int64_t t = 2 * m + 32 - i;
     if (t >= 0 && t < n) tc = cadd(tc, cscale(cis_rev(-downshift_rev(r, t)), mf[i]));
   }
   return tc;
 }
+__device__ __noinline__ float2 kk_carrier_edge(const float *__restrict__ mf, double r, int64_t m, int64_t n) {
+  return kk_carrier_edge_inl(mf, r, m, n);
+}
 __device__ __forceinline__ bool kk_interior(int64_t m, int64_t n) { return m >= 16 && 2 * m + 32 < n; }
+template <bool INL = false>
 __device__ __forceinline__ float2 kk_carrier_term(const RxJob &J, int64_t m, int64_t n) {
   if (kk_interior(m, n)) return cmul(J.c0, cis_rev(-downshift_rev(J.r, 2 * m)));
-  return kk_carrier_edge(J.mf, J.r, m, n);
+  return INL ? kk_carrier_edge_inl(J.mf, J.r, m, n) : kk_carrier_edge(J.mf, J.r, m, n);
 }
 
 // KK: AGC'd carrier-free 2-sps sample u[m] = g (Z[m] - mean T[m]) (zero outside).
+template <bool INL = false>
 __device__ __forceinline__ float2 kk_sample(const RxJob &J, const float2 *__restrict__ z, int64_t m, int64_t n,
                                             float2 mean, float g) {
   if (m < 0 || m >= n / 2) return make_float2(0.0f, 0.0f);
-  return cscale(csub(z[m], cmul(mean, kk_carrier_term(J, m, n))), g);
+  return cscale(csub(z[m], cmul(mean, kk_carrier_term<INL>(J, m, n))), g);
 }
