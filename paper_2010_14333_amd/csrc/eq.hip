@@ -89,12 +89,13 @@ __global__ __launch_bounds__(256) void rx_prefix(RxLaunch L) {
       J.sc->mean_im = mi;
     }
   }
-  const float2 *__restrict__ zin = J.z;
+  const auto zin = gview(J.z);
+  const auto xin = gptr(J.xr);
 #pragma unroll 8
   for (int idx = threadIdx.x; idx < PFX_UL; idx += 256) {
     const int64_t j = (int64_t)idx - PFX_OFF;
     float2 v = make_float2(0.0f, 0.0f);
-    if (j >= 0 && j < nx) v = kk ? kk_sample(J, zin, j, n, mean, g) : make_float2(J.xr[j], 0.0f);
+    if (j >= 0 && j < nx) v = kk ? kk_sample(J, zin, j, n, mean, g) : make_float2(xin[j], 0.0f);
     u[idx] = v;
   }
   for (int k = threadIdx.x; k < P; k += 256) ar[k] = ref_symbol(J, k);
@@ -251,9 +252,9 @@ __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
   const float g = CPLX ? (float)J.sc->agc : 1.0f;
   const float2 mean = make_float2((float)J.sc->mean_re, (float)J.sc->mean_im);
   const int s = J.sc->lag;
-  const float2 *__restrict__ zin = J.z;
-  const float *__restrict__ xin = J.xr;
-  float2 *__restrict__ soft = J.soft;
+  const auto zin = gview(J.z);
+  const auto xin = gptr(J.xr);
+  float2 *const soft = J.soft;
   auto load = [&](int64_t j) -> T {
     if constexpr (CPLX) {
       return kk_sample<true>(J, zin, j, n, mean, g);
@@ -353,12 +354,12 @@ __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
       const int l = e / BC, kk = e % BC;
       if (b0 + l < nb) {
         const T v = sout[l * (BC + 1) + kk];
-        if constexpr (CPLX) soft[(b0 + l) * blk + BC * ch + kk] = v;
-        else soft[(b0 + l) * blk + BC * ch + kk] = make_float2(v, 0.0f);
+        if constexpr (CPLX) gstore(soft, (b0 + l) * blk + BC * ch + kk, v);
+        else gstore(soft, (b0 + l) * blk + BC * ch + kk, make_float2(v, 0.0f));
       }
     }
   }
-  if (CPLX && active && h == 0) J.s4[b] = make_float2(s4r, s4i);
+  if (CPLX && active && h == 0) gstore(J.s4, b, make_float2(s4r, s4i));
 }
 #undef BC
 
@@ -400,7 +401,7 @@ __global__ __launch_bounds__(256) void rx_ffe_mfma(RxLaunch L) {
     }
   const int64_t tile = grp * 16 + row;
   const int64_t base = 2 * (tile * 16 + s) - C;
-  const float2 *__restrict__ zin = J.z;
+  const auto zin = gview(J.z);
   float2 xv[16];
 #pragma unroll
   for (int h = 0; h < 2; h++)
@@ -426,7 +427,7 @@ __global__ __launch_bounds__(256) void rx_ffe_mfma(RxLaunch L) {
   for (int j = 0; j < 4; j++) {
     const int64_t k = (grp * 16 + 4 * kq + j) * 16 + row;
     const float2 z = make_float2(zr[j], zi[j]);
-    J.soft[k] = z;
+    gstore(J.soft, k, z);
     const float a2 = z.x * z.x - z.y * z.y, b2 = 2.0f * z.x * z.y;
     s4r += a2 * a2 - b2 * b2;
     s4i += 2.0f * a2 * b2;
@@ -437,16 +438,16 @@ __global__ __launch_bounds__(256) void rx_ffe_mfma(RxLaunch L) {
     s4r += __shfl_xor(s4r, o, 64);
     s4i += __shfl_xor(s4i, o, 64);
   }
-  if ((lane & 31) == 0) J.s4[2 * grp + (lane >> 5)] = make_float2(s4r, s4i);
+  if ((lane & 31) == 0) gstore(J.s4, 2 * grp + (lane >> 5), make_float2(s4r, s4i));
 }
 
-// Decisions, Gray demapping, packing and error counting: one lane per
-// symbol (coalesced soft reads); each pass of 256 symbols fills exactly
-// 8*bps words of the bit stream, assembled in LDS.  A workgroup covers
-// DEC_SYMS symbols and adds its error counts with one set of atomics.
+// Decisions, Gray demapping, packing and error counting: eight consecutive
+// symbols per lane (one derotation phase, one 8*bps-bit chunk of the stream);
+// the workgroup's DEC_SYMS symbols are packed in LDS, written out as whole
+// words, and its error counts added with one set of atomics.
 #define DEC_SYMS 2048
 __global__ __launch_bounds__(256) void rx_decide(RxLaunch L) {
-  __shared__ uint32_t wb[32];
+  __shared__ uint32_t wb[DEC_SYMS * 4 / 32];   // the workgroup's packed bits (up to 4 per symbol)
   __shared__ unsigned long long red[3][4];
   const int jb = blockIdx.y;
   const RxJob J = *L.job[jb];
@@ -455,41 +456,58 @@ __global__ __launch_bounds__(256) void rx_decide(RxLaunch L) {
   const int64_t nsym = n / (kk ? 4 : 2);
   const int64_t kbase = (int64_t)blockIdx.x * DEC_SYMS;
   if (kbase >= nsym) return;   // nsym is a multiple of 256
-  uint32_t *__restrict__ out = reinterpret_cast<uint32_t *>(L.bits[jb]);
-  float2 *__restrict__ soft = J.soft;
+  const auto out = gptr(reinterpret_cast<uint32_t *>(L.bits[jb]));
+  float2 *const soft = J.soft;
+  const int nw = DEC_SYMS * bps / 32;
+  for (int i = threadIdx.x; i < nw; i += 256) wb[i] = 0u;
+  // this thread: symbols k0 .. k0 + 7 (one DD-LMS block, so one phase)
+  const int64_t k0 = kbase + 8 * threadIdx.x;
+  const bool valid = k0 < nsym;   // then k0 + 8 <= nsym
   unsigned long long cs = 0, se = 0, be = 0;
-  for (int64_t k0 = kbase; k0 < kbase + DEC_SYMS && k0 < nsym; k0 += 256) {
-    if (threadIdx.x < 32) wb[threadIdx.x] = 0u;
-    __syncthreads();
-    const int64_t k = k0 + threadIdx.x;
-    float2 z = soft[k];
-    uint32_t sym;
-    if (kk) {
-      z = cmul(z, cis_rev(-J.theta[k / J.blk] * 0.15915494309189535f));
-      if (J.debug) soft[k] = z;
-      const uint32_t gi = (uint32_t)decide_index(z.x, m), gq = (uint32_t)decide_index(z.y, m);
-      sym = ((gi ^ (gi >> 1)) << (bps >> 1)) | (gq ^ (gq >> 1));
-    } else {
-      const uint32_t gi = (uint32_t)decide_index(z.x, m);
-      sym = gi ^ (gi >> 1);
+  uint32_t chunk = 0;   // symbol k0 + i at bits [bps i, bps (i + 1)), MSB of the symbol first
+  if (valid) {
+    float2 zv[8];
+#pragma unroll
+    for (int h = 0; h < 4; h++) {
+      const float4 q = gload4(soft + k0, h);
+      zv[2 * h] = make_float2(q.x, q.y);
+      zv[2 * h + 1] = make_float2(q.z, q.w);
     }
-    // stream order: the symbol's MSB first
-    uint32_t rev = 0;
-    for (int j = 0; j < bps; j++) rev |= ((sym >> (bps - 1 - j)) & 1u) << j;
-    const int lb = threadIdx.x * bps, wi = lb >> 5, off = lb & 31;
-    atomicOr(&wb[wi], rev << off);
-    if (off + bps > 32) atomicOr(&wb[wi + 1], rev >> (32 - off));
-    if (k >= P + RX_GUARD && k < nsym - RX_GUARD) {
-      const uint32_t ref = (uint32_t)(splitmix64(J.seed, (uint64_t)k) >> (64 - bps));
-      const int ne = __popc(ref ^ sym);
-      cs += 1;
-      be += (unsigned long long)ne;
-      se += ne > 0;
+    const float2 rot = kk ? cis_rev(-gptr(J.theta)[k0 / J.blk] * 0.15915494309189535f) : make_float2(1.0f, 0.0f);
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+      const int64_t k = k0 + i;
+      uint32_t sym;
+      if (kk) {
+        const float2 z = cmul(zv[i], rot);
+        if (J.debug) gstore(soft, k, z);
+        const uint32_t gi = (uint32_t)decide_index(z.x, m), gq = (uint32_t)decide_index(z.y, m);
+        sym = ((gi ^ (gi >> 1)) << (bps >> 1)) | (gq ^ (gq >> 1));
+      } else {
+        const uint32_t gi = (uint32_t)decide_index(zv[i].x, m);
+        sym = gi ^ (gi >> 1);
+      }
+      uint32_t rev = 0;
+      for (int j = 0; j < bps; j++) rev |= ((sym >> (bps - 1 - j)) & 1u) << j;
+      chunk |= rev << (bps * i);
+      if (k >= P + RX_GUARD && k < nsym - RX_GUARD) {
+        const uint32_t ref = (uint32_t)(splitmix64(J.seed, (uint64_t)k) >> (64 - bps));
+        const int ne = __popc(ref ^ sym);
+        cs += 1;
+        be += (unsigned long long)ne;
+        se += ne > 0;
+      }
     }
-    __syncthreads();
-    if (threadIdx.x < 8 * bps) out[(k0 / 256) * 8 * bps + threadIdx.x] = wb[threadIdx.x];
-    __syncthreads();
   }
+  __syncthreads();
+  if (valid) {
+    const int lb = 8 * bps * threadIdx.x, wi = lb >> 5, off = lb & 31;
+    atomicOr(&wb[wi], chunk << off);
+    if (off + 8 * bps > 32) atomicOr(&wb[wi + 1], chunk >> (32 - off));
+  }
+  __syncthreads();
+  const int64_t nsw = (nsym - kbase < DEC_SYMS ? nsym - kbase : DEC_SYMS) * bps / 32;
+  for (int i = threadIdx.x; i < nsw; i += 256) out[kbase * bps / 32 + i] = wb[i];
   cs = wave_sum(cs);
   se = wave_sum(se);
   be = wave_sum(be);

@@ -153,82 +153,87 @@ __global__ __launch_bounds__(256) void mlp_windows(RxLaunch L, float *__restrict
 }
 
 // ---- inference (BF16 MFMA) -----------------------------------------------
-// Per wavefront, tiles of 16 symbols:
-//   layer 1: H1^T (64 x 16) = W1 (64 x 32) X^T (32 x 16): 4 MFMA 16x16x32
-//   layer 2: H2^T = W2 (64 x 64) H1^T: 8 MFMA (H1 through LDS for the B layout)
+// Per wavefront, tiles of 16 symbols (v_mfma_f32_16x16x32_bf16: lane l
+// supplies A[l % 16][8 (l / 16) + j] and B[8 (l / 16) + j][l % 16] and
+// receives D[4 (l / 16) + j][l % 16]):
+//   layer 1: H1^T (64 x 16) = W1 (64 x 32) X^T (32 x 16) + b1: 4 MFMA, the
+//            bias as the accumulator input;
+//   layer 2: H2^T = W2 (64 x 64) H1^T + b2: 8 MFMA.  Lane l holds after layer
+//            1 the units 16 t + 4 kq + j (kq = l / 16, t, j < 4) of symbol
+//            l % 16, so layer 2 takes its K index in the order
+//            u(ks, kq, jj) = 16 (2 ks + jj / 4) + 4 kq + jj % 4 (W2's columns
+//            permuted to match) and the ReLU'd layer-1 outputs become its B
+//            operand without leaving the registers;
 //   layer 3: y = W3 . H2 + b3 in FP32 (lane partials + two shuffles).
-#define TILES_PER_WAVE 8
+#define TILES_PER_WAVE 64   // amortises loading the network into registers
 using MNT = NarrowT<1>;
 
 struct MlpFrag {
-  MNT::vec a1[4], a2[4][2];            // A fragments of W1 (4 row tiles) and W2 (4 x 2 K-steps)
-  float bb1[4][4], bb2[4][4], ww3[4][4];  // b1, b2, W3 of the hidden units this lane's D rows hold
+  MNT::vec a1[4], a2[4][2];   // A fragments: W1 row tiles, W2 row tiles x 2 K-steps (permuted)
+  const float *cv;            // LDS: b1[64], b2[64], W3[64] (per-unit vectors read per tile)
   float b3;
 };
 
-__device__ __forceinline__ void mlp_load_frag(const float *__restrict__ P, int row, int kq, MlpFrag &f) {
+// Every thread of the workgroup calls this (it fills the LDS vectors).
+__device__ __forceinline__ void mlp_load_frag(const float *__restrict__ P, int row, int kq, float *cv, MlpFrag &f) {
 #pragma unroll
   for (int t = 0; t < 4; t++)
 #pragma unroll
-    for (int j = 0; j < 8; j++) {
-      const int i = 8 * kq + j;
-      f.a1[t][j] = MNT::cvt(i < MI ? P[(16 * t + row) * MI + i] : 0.0f);
-      f.a2[t][0][j] = MNT::cvt(P[OFF_W2 + (16 * t + row) * MH + 8 * kq + j]);
-      f.a2[t][1][j] = MNT::cvt(P[OFF_W2 + (16 * t + row) * MH + 32 + 8 * kq + j]);
-    }
+    for (int jj = 0; jj < 8; jj++) {
+      const int i = 8 * kq + jj;
+      f.a1[t][jj] = MNT::cvt(i < MI ? P[(16 * t + row) * MI + i] : 0.0f);
 #pragma unroll
-  for (int t = 0; t < 4; t++)
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-      f.bb1[t][j] = P[OFF_B1 + 16 * t + 4 * kq + j];
-      f.bb2[t][j] = P[OFF_B2 + 16 * t + 4 * kq + j];
-      f.ww3[t][j] = P[OFF_W3 + 16 * t + 4 * kq + j];
+      for (int ks = 0; ks < 2; ks++) {
+        const int u = 16 * (2 * ks + jj / 4) + 4 * kq + jj % 4;
+        f.a2[t][ks][jj] = MNT::cvt(P[OFF_W2 + (16 * t + row) * MH + u]);
+      }
     }
+  for (int i = threadIdx.x; i < 3 * MH; i += blockDim.x)
+    cv[i] = P[i < MH ? OFF_B1 + i : i < 2 * MH ? OFF_B2 + i - MH : OFF_W3 + i - 2 * MH];
+  f.cv = cv;
   f.b3 = P[OFF_B3];
+  __syncthreads();
 }
+
+// ReLU on the bit pattern: a float with the sign bit clear compares as a
+// non-negative int32 in the same order, one with it set as a negative one,
+// so max(bits, 0) is max(x, +0) in one integer instruction.
+__device__ __forceinline__ float relu_bits(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
 
 // One tile of 16 symbols; bx = this lane's B fragment of layer 1 (window
 // samples 8 kq .. 8 kq + 7 of symbol `row`).  Every lane returns the output
-// of symbol `row`.  Contains workgroup barriers: all waves call it together.
-__device__ __forceinline__ float mlp_tile(const MlpFrag &f, MNT::vec bx, __bf16 (*hs)[MH + 8], int row, int kq) {
+// of symbol `row`.  Registers, LDS reads of the per-unit vectors and two
+// cross-lane shuffles only.
+__device__ __forceinline__ float mlp_tile(const MlpFrag &f, MNT::vec bx, int kq) {
+  const float4 *cv4 = reinterpret_cast<const float4 *>(f.cv) + kq;   // units 16 t + 4 kq .. + 3
+  rx_f32x4 d1[4];
 #pragma unroll
   for (int t = 0; t < 4; t++) {
-    rx_f32x4 d = MNT::mfma(f.a1[t], bx, rx_f32x4{0.0f, 0.0f, 0.0f, 0.0f});
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-      const float h = d[j] + f.bb1[t][j];
-      hs[row][16 * t + 4 * kq + j] = MNT::cvt(h > 0.0f ? h : 0.0f);
-    }
+    const float4 b = cv4[4 * t];
+    d1[t] = MNT::mfma(f.a1[t], bx, rx_f32x4{b.x, b.y, b.z, b.w});
   }
-  __syncthreads();
   MNT::vec bh[2];
 #pragma unroll
   for (int ks = 0; ks < 2; ks++)
 #pragma unroll
-    for (int j = 0; j < 8; j++) bh[ks][j] = hs[row][32 * ks + 8 * kq + j];
-  __syncthreads();
+    for (int jj = 0; jj < 8; jj++) bh[ks][jj] = MNT::cvt(relu_bits(d1[2 * ks + jj / 4][jj % 4]));
   float y = 0.0f;
 #pragma unroll
   for (int t = 0; t < 4; t++) {
-    rx_f32x4 d = MNT::mfma(f.a2[t][0], bh[0], rx_f32x4{0.0f, 0.0f, 0.0f, 0.0f});
+    const float4 b = cv4[16 + 4 * t], w3 = cv4[32 + 4 * t];
+    rx_f32x4 d = MNT::mfma(f.a2[t][0], bh[0], rx_f32x4{b.x, b.y, b.z, b.w});
     d = MNT::mfma(f.a2[t][1], bh[1], d);
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-      const float h = d[j] + f.bb2[t][j];
-      y = fmaf(f.ww3[t][j], h > 0.0f ? h : 0.0f, y);
-    }
+    y = fmaf(w3.x, relu_bits(d[0]), y);
+    y = fmaf(w3.y, relu_bits(d[1]), y);
+    y = fmaf(w3.z, relu_bits(d[2]), y);
+    y = fmaf(w3.w, relu_bits(d[3]), y);
   }
   y += __shfl_xor(y, 16, 64);
   y += __shfl_xor(y, 32, 64);
   return y + f.b3;
 }
 
-// Per wavefront, tiles of 16 symbols:
-//   layer 1: H1^T (64 x 16) = W1 (64 x 32) X^T (32 x 16): 4 MFMA 16x16x32
-//   layer 2: H2^T = W2 (64 x 64) H1^T: 8 MFMA (H1 through LDS for the B layout)
-//   layer 3: y = W3 . H2 + b3 in FP32 (lane partials + two shuffles).
 __global__ __launch_bounds__(256) void mlp_infer(RxLaunch L) {
-  __shared__ __bf16 hs[4][16][MH + 8];
   const int jb = blockIdx.y;
   const RxJob J = *L.job[jb];
   if (!J.mlp) return;
@@ -236,39 +241,56 @@ __global__ __launch_bounds__(256) void mlp_infer(RxLaunch L) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int row = lane & 15, kq = lane >> 4;
   const int s = J.sc->lag;
-  const float *__restrict__ xr = J.xr;
+  const auto xr = gptr(J.xr);
+  __shared__ __attribute__((aligned(16))) float cv[3 * MH];
   MlpFrag f;
-  mlp_load_frag(J.mlp, row, kq, f);
+  mlp_load_frag(J.mlp, row, kq, cv, f);
   const int64_t tile0 = ((int64_t)blockIdx.x * 4 + wv) * TILES_PER_WAVE;
+  // window sample 8 kq + j of symbol k0 + row: x[2 (k0 + row + s) - 15 + 8 kq + j];
+  // the next tile's samples are loaded while this tile runs
+  auto load_x = [&](int64_t k0, float xv[8]) {
+    const int64_t c = 2 * (k0 + row + s) - 15 + 8 * kq;
+    if (2 * (k0 + s) - 15 >= 0 && 2 * (k0 + 15 + s) + 16 < n) {   // whole tile window inside the buffer
+#pragma unroll
+      for (int j = 0; j < 8; j++) xv[j] = 8 * kq + j < MI ? xr[c + j] : 0.0f;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; j++) {
+        const int64_t q = c + j;
+        xv[j] = (8 * kq + j < MI && q >= 0 && q < n) ? xr[q] : 0.0f;
+      }
+    }
+  };
+  float xn[8];
+  load_x(tile0 * 16, xn);
   for (int tt = 0; tt < TILES_PER_WAVE; tt++) {
     const int64_t k0 = (tile0 + tt) * 16;
+    if (k0 >= nsym) break;
     MNT::vec bx;
-    const int64_t c = 2 * (k0 + row + s) - 15 + 8 * kq;
 #pragma unroll
-    for (int j = 0; j < 8; j++) {
-      const int64_t q = c + j;
-      bx[j] = MNT::cvt((8 * kq + j < MI && q >= 0 && q < n) ? xr[q] : 0.0f);
-    }
-    const float y = mlp_tile(f, bx, hs[wv], row, kq);
-    if (kq == 0 && k0 + row < nsym) J.soft[k0 + row] = make_float2(y, 0.0f);
+    for (int j = 0; j < 8; j++) bx[j] = MNT::cvt(xn[j]);
+    if (tt + 1 < TILES_PER_WAVE) load_x(k0 + 16, xn);
+    const float y = mlp_tile(f, bx, kq);
+    if (kq == 0 && k0 + row < nsym) gstore(J.soft, k0 + row, make_float2(y, 0.0f));
   }
 }
 
 // The same inference on given rows X[n][32] (column 31 ignored) -> Y[n].
 __global__ __launch_bounds__(256) void mlp_infer_rows(const float *__restrict__ P, const float *__restrict__ X,
                                                       int64_t nrows, float *__restrict__ Y) {
-  __shared__ __bf16 hs[4][16][MH + 8];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int row = lane & 15, kq = lane >> 4;
+  __shared__ __attribute__((aligned(16))) float cv[3 * MH];
   MlpFrag f;
-  mlp_load_frag(P, row, kq, f);
+  mlp_load_frag(P, row, kq, cv, f);
   const int64_t tile0 = ((int64_t)blockIdx.x * 4 + wv) * TILES_PER_WAVE;
   for (int tt = 0; tt < TILES_PER_WAVE; tt++) {
     const int64_t r = (tile0 + tt) * 16 + row;
+    if ((tile0 + tt) * 16 >= nrows) break;
     MNT::vec bx;
 #pragma unroll
     for (int j = 0; j < 8; j++) bx[j] = MNT::cvt((8 * kq + j < MI && r < nrows) ? X[r * 32 + 8 * kq + j] : 0.0f);
-    const float y = mlp_tile(f, bx, hs[wv], row, kq);
+    const float y = mlp_tile(f, bx, kq);
     if (kq == 0 && r < nrows) Y[r] = y;
   }
 }

@@ -67,9 +67,22 @@ __global__ __launch_bounds__(256) void pam_mf(RxLaunch L) {
     __syncthreads();
   }
   const double mv = mean_s;
-  for (int i = threadIdx.x; i < XN; i += 256) {
-    const int64_t t = t0 - 20 + i;
-    xs[xpad(i)] = (t >= 0 && t < n) ? (float)((double)read_code(in, t) + 0.5 - mv) : 0.0f;
+  // codes of [t0 - 24, t0 + TS + 24) in aligned groups of eight (t0 is a
+  // multiple of 8); xs[i] holds sample t0 - 20 + i
+  for (int g = threadIdx.x; g < (PAM_TS + 48) / 8; g += 256) {
+    const int64_t s0 = t0 - 24 + 8 * g;
+    int c[8];
+    if (s0 >= 0 && s0 + 8 <= n) {
+      read_codes8(in, s0 >> 3, c);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; e++) c[e] = (s0 + e >= 0 && s0 + e < n) ? read_code(in, s0 + e) : -1;
+    }
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+      const int i = 8 * g + e - 4;
+      if (i >= 0 && i < XN) xs[xpad(i)] = c[e] >= 0 ? (float)((double)c[e] + 0.5 - mv) : 0.0f;
+    }
   }
   __syncthreads();
   // 16 consecutive outputs per thread: y[t0 + 16 tid + o] from 48 inputs
@@ -88,16 +101,15 @@ __global__ __launch_bounds__(256) void pam_mf(RxLaunch L) {
         if (tap >= 0 && tap <= 32) acc[o] = fmaf(J.mf[tap], v, acc[o]);
       }
     }
+    float q2 = 0.0f;   // 16 squares in FP32, then one FP64 add
 #pragma unroll
     for (int o = 0; o < 16; o++) {
       const int64_t t = t0 + 16 * threadIdx.x + o;
       const float yv = (t < n) ? acc[o] : 0.0f;
       ys[16 * threadIdx.x + o + 4] = yv;
-      if (t < n) {
-        J.y[t] = yv;
-        p2 += (double)yv * yv;
-      }
+      q2 = fmaf(yv, yv, q2);
     }
+    p2 = q2;
   }
   if (threadIdx.x < 8) {   // the 4 outputs either side of the tile
     const int l = threadIdx.x < 4 ? (int)threadIdx.x - 4 : PAM_TS + (int)threadIdx.x - 4;
@@ -106,9 +118,12 @@ __global__ __launch_bounds__(256) void pam_mf(RxLaunch L) {
     for (int i = 0; i < 33; i++) a = fmaf(J.mf[i], xs[xpad(l + 36 - i)], a);
     ys[l + 4] = (t >= 0 && t < n) ? a : 0.0f;
   }
-  p2 = block_sum(p2, red);
+  p2 = block_sum(p2, red);   // (its barriers also publish ys)
   if (threadIdx.x == 0) J.part2[blockIdx.x] = p2;
-  __syncthreads();
+  for (int i = threadIdx.x; i < PAM_TS; i += 256) {   // coalesced copy-out of the tile
+    const int64_t t = t0 + i;
+    if (t < n) gptr(J.y)[t] = ys[i + 4];
+  }
   // Gardner sums: 8 blocks of 256 symbols, 32 threads x 8 symbols each.
   const int bl = threadIdx.x >> 5, sub = threadIdx.x & 31;
   float g0 = 0.0f, g1 = 0.0f;
@@ -187,25 +202,35 @@ __global__ __launch_bounds__(1024) void pam_unwrap(RxLaunch L) {
 }
 
 // Cubic-Lagrange (Farrow) interpolation with the AGC gain:
-// xr[t] = g * y(t + delta_b), t in block b.
+// xr[t] = g * y(t + delta_b), t in block b.  A workgroup covers 1024
+// consecutive samples (two 512-sample timing blocks), one per thread and pass.
 __global__ __launch_bounds__(256) void pam_farrow(RxLaunch L) {
   const int jb = blockIdx.y;
   const RxJob J = *L.job[jb];
   const int64_t n = L.n[jb];
   const float g = (float)J.sc->agc;
-  const int64_t t00 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  const auto y = gptr(J.y);
+  const auto xr = gptr(J.xr);
+  const auto dl = gptr(J.delta);
+#pragma unroll
   for (int o = 0; o < 4; o++) {
-    const int64_t t = t00 + o;
+    const int64_t t = (int64_t)blockIdx.x * 1024 + 256 * o + threadIdx.x;
     if (t >= n) return;
-    const float d = J.delta[t / 512];
+    const float d = dl[t / 512];
     const float fl = floorf(d), mu = d - fl;
     const int64_t i0 = t + (int64_t)fl;
     const float lm1 = -mu * (mu - 1.0f) * (mu - 2.0f) * (1.0f / 6.0f);
     const float l0 = (mu + 1.0f) * (mu - 1.0f) * (mu - 2.0f) * 0.5f;
     const float l1 = -(mu + 1.0f) * mu * (mu - 2.0f) * 0.5f;
     const float l2 = (mu + 1.0f) * mu * (mu - 1.0f) * (1.0f / 6.0f);
-    auto yat = [&](int64_t j) { return (j >= 0 && j < n) ? J.y[j] : 0.0f; };
-    J.xr[t] = g * (lm1 * yat(i0 - 1) + l0 * yat(i0) + l1 * yat(i0 + 1) + l2 * yat(i0 + 2));
+    float v;
+    if (i0 >= 1 && i0 + 2 < n) {
+      v = lm1 * y[i0 - 1] + l0 * y[i0] + l1 * y[i0 + 1] + l2 * y[i0 + 2];
+    } else {
+      auto yat = [&](int64_t j) { return (j >= 0 && j < n) ? y[j] : 0.0f; };
+      v = lm1 * yat(i0 - 1) + l0 * yat(i0) + l1 * yat(i0 + 1) + l2 * yat(i0 + 2);
+    }
+    xr[t] = g * v;
   }
 }
 

@@ -29,6 +29,33 @@ template <> struct NarrowT<2> {
 // A[l % 16][8 (l / 16) + j] and B[8 (l / 16) + j][l % 16], j = 0..7, and
 // receives D[4 (l / 16) + j][l % 16], j = 0..3.
 
+// Global-memory view of a pointer.  Pointers read out of the job descriptor
+// are generic to the compiler, which then emits flat accesses; those also
+// count against the LDS wait counter, so every wait for an LDS read would
+// wait for outstanding HBM loads too.  Hot paths access through this view.
+// (HIP's float2/float4 classes do not bind to address-space-qualified
+// references, so complex and 4-wide accesses go through native vectors.)
+#define RX_GLOBAL __attribute__((address_space(1)))
+typedef float rx_v2 __attribute__((ext_vector_type(2)));
+typedef float rx_v4 __attribute__((ext_vector_type(4)));
+template <class T>
+__device__ __forceinline__ RX_GLOBAL T *gptr(T *p) { return (RX_GLOBAL T *)p; }
+struct GView2 {   // read-only global view of a float2 array
+  const RX_GLOBAL rx_v2 *p;
+  __device__ float2 operator[](int64_t i) const {
+    const rx_v2 v = p[i];
+    return make_float2(v.x, v.y);
+  }
+};
+__device__ __forceinline__ GView2 gview(const float2 *p) { return GView2{(const RX_GLOBAL rx_v2 *)p}; }
+__device__ __forceinline__ void gstore(float2 *p, int64_t i, float2 v) {
+  ((RX_GLOBAL rx_v2 *)p)[i] = rx_v2{v.x, v.y};
+}
+__device__ __forceinline__ float4 gload4(const void *p, int64_t i) {   // i-th 16-byte element
+  const rx_v4 v = ((const RX_GLOBAL rx_v4 *)p)[i];
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -190,9 +217,8 @@ __device__ __forceinline__ float2 kk_carrier_term(const RxJob &J, int64_t m, int
 }
 
 // KK: AGC'd carrier-free 2-sps sample u[m] = g (Z[m] - mean T[m]) (zero outside).
-template <bool INL = false>
-__device__ __forceinline__ float2 kk_sample(const RxJob &J, const float2 *__restrict__ z, int64_t m, int64_t n,
-                                            float2 mean, float g) {
+template <bool INL = false, class ZP>
+__device__ __forceinline__ float2 kk_sample(const RxJob &J, ZP z, int64_t m, int64_t n, float2 mean, float g) {
   if (m < 0 || m >= n / 2) return make_float2(0.0f, 0.0f);
   return cscale(csub(z[m], cmul(mean, kk_carrier_term<INL>(J, m, n))), g);
 }
