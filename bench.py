@@ -29,6 +29,27 @@ def front_flop_per_sample(log2n):
     return (5.0 * n * log2n + 2.0 * n) / hop + 130.0
 
 
+KERNEL_SOURCES = ["kk.hip", "fft_lds.hpp", "rx_dev.hpp", "rx_shared.h"]
+
+
+def front_traffic(batch):
+    """HBM bytes per kk_front launch from the committed counter summary, if it
+    was taken on the kernel sources as they are now (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "kk_front_kk16qam_2e22_b64_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2010_14333_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    if t.get("source_sha256") != h.hexdigest() or t.get("buffers_per_launch") != batch:
+        return None
+    return {"bytes_per_launch": t["bytes_per_launch"], "source": os.path.relpath(path, ROOT)}
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -43,6 +64,7 @@ def main():
     ap.add_argument("--graph", type=int, default=0)
     ap.add_argument("--streams", type=int, default=2,
                     help="consecutive batches alternate over this many HIP streams (batch pipelining)")
+    ap.add_argument("--one-stream", type=int, default=1, help="also time the chain on one stream (isolated stages)")
     ap.add_argument("--cpu-buffers", type=int, default=8)
     ap.add_argument("--copy-probe", type=int, default=1, help="run a 256 MiB device copy (counter scale)")
     ap.add_argument("--forms", default="bf16,fp16", help="precision forms timed beside the plain chain")
@@ -71,7 +93,7 @@ def main():
         sets = []
         for si, st in enumerate(streams[:max(1, nstreams)]):
             recs = [rx.Receiver(rx.RX_KK_16QAM, gens[i % a.distinct]["seed"], max_samples=N, stream=st,
-                                flags=rx.RX_PROFILE if (i == 0 and si == 0 and profile) else 0,
+                                flags=rx.RX_PROFILE if (i == 0 and profile) else 0,
                                 precision=precision) for i in range(a.batch)]
             outs = [torch.empty(r.bits_bytes(N), dtype=torch.uint8, device=dev) for r in recs]
             sets.append((recs, outs, [r.h for r in recs], [o.data_ptr() for o in outs]))
@@ -85,9 +107,10 @@ def main():
         for i in range(a.warmup * len(sets)):
             step(i)
         torch.cuda.synchronize()
-        h0 = sets[0][2][0]
+        heads = [hs[0] for _, _, hs, _ in sets]   # the profiled handle of each stream
         if profile:
-            rx.rx_stage_times(h0, reset=True)
+            for h in heads:
+                rx.rx_stage_times(h, reset=True)
         for recs, _, _, _ in sets:
             for r in recs:
                 r.reset()
@@ -97,7 +120,12 @@ def main():
             step(i)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t1
-        stages = rx.rx_stage_times(h0) if profile else {}
+        stages = {}
+        if profile:   # every timed launch, whichever stream it ran on
+            for h in heads:
+                for k, (ms, cnt) in rx.rx_stage_times(h).items():
+                    a0, c0 = stages.get(k, (0.0, 0))
+                    stages[k] = (a0 + ms, c0 + cnt)
         errs = [r.errors() for recs, _, _, _ in sets for r in recs]
         for recs, _, _, _ in sets:
             for r in recs:
@@ -109,8 +137,9 @@ def main():
     wall, stages, ber = run_form(rx.RX_FP32, True)
     log(f"[bench] plain chain: {a.steps} steps x {a.batch} buffers in {wall:.3f}s")
     # the same chain on one stream, so that each stage's launch owns the chip
-    wall1, stages1, _ = run_form(rx.RX_FP32, True, nstreams=1)
-    log(f"[bench] plain chain, one stream: {a.steps} steps in {wall1:.3f}s")
+    if a.one_stream:
+        wall1, stages1, _ = run_form(rx.RX_FP32, True, nstreams=1)
+        log(f"[bench] plain chain, one stream: {a.steps} steps in {wall1:.3f}s")
     forms = {}
     for name in [f for f in a.forms.split(",") if f]:
         prec = {"bf16": rx.RX_BF16, "fp16": rx.RX_FP16}[name]
@@ -234,8 +263,15 @@ def main():
         return {k: round(v[0] / v[1] * 1e3 / a.batch, 3) for k, v in st.items()}
 
     roof = roofline(stages)
-    roof1 = roofline(stages1)
-    roof1["value"] = round(samples / (wall1 / a.steps) / 1e9, 3)
+    traffic = front_traffic(a.batch)
+    if traffic is not None and roof.get("kernel") == "kk_front<14>":
+        roof["traffic"] = traffic["bytes_per_launch"]
+        roof["traffic_source"] = traffic["source"]
+    one = None
+    if a.one_stream:
+        roof1 = roofline(stages1)
+        roof1["value"] = round(samples / (wall1 / a.steps) / 1e9, 3)
+        one = {"stage_us_per_buffer": per_buffer(stages1), "roofline": roof1}
 
     if a.copy_probe:
         src = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
@@ -272,7 +308,10 @@ def main():
         "mixed_batch": mixed,
         "stage_us_per_buffer": per_buffer(stages),
         "roofline": roof,
-        "one_stream": {"stage_us_per_buffer": per_buffer(stages1), "roofline": roof1},
+        "one_stream": one,
+        # algorithmic HBM fraction of the whole chain: 1.5 B in + 0.125 B of bits out per
+        # sample (KK-16QAM: 4 bits per 4 samples) at the sustained rate, over 8 TB/s
+        "algorithmic_hbm_frac": round(1.625 * gsps / PEAK_HBM_GBS, 5),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

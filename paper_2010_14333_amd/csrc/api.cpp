@@ -8,6 +8,9 @@
 #include <cstdio>
 #include <cstddef>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "../../include/rx.h"
@@ -175,6 +178,113 @@ const char *rx_strerror(int code) {
   }
 }
 
+// Hilbert spectrum and FFT twiddles depend only on (N, Hilbert taps): one
+// copy per device serves every handle, so a batch of many buffers reads one
+// L2-resident set of tables.  They are kept until the process ends.
+struct SharedTables {
+  float *hspec;
+  float2 *twid;
+};
+static const SharedTables *shared_tables(int log2n, int htaps) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, int>, SharedTables> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  const auto key = std::make_tuple(dev, log2n, htaps);
+  auto it = cache.find(key);
+  if (it != cache.end()) return &it->second;
+  const int n = 1 << log2n;
+  std::vector<float> hs = design_hilbert_spectrum(htaps, log2n);
+  std::vector<float2> tw = design_twiddles(log2n);
+  SharedTables t{nullptr, nullptr};
+  if (hipMalloc((void **)&t.hspec, n * sizeof(float)) != hipSuccess) return nullptr;
+  if (hipMalloc((void **)&t.twid, tw.size() * sizeof(float2)) != hipSuccess ||
+      hipMemcpy(t.hspec, hs.data(), n * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(t.twid, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) {
+    hipFree(t.hspec);
+    if (t.twid) hipFree(t.twid);
+    return nullptr;
+  }
+  return &(cache[key] = t);
+}
+
+// FFT-size autotuner (fft_log2 = 0 on a KK handle): a batch of 16 buffers of
+// 2^22 pseudo-random codes (the work does not depend on the values; the
+// batch fills the chip the way a streaming batch does, at the real buffer
+// size) is run through the chain at each supported overlap-save size, once
+// per device and process; the fastest of three runs counts, and the smaller
+// size must win by more than 3 % to replace 2^14.  The overlap is fixed by the
+// Hilbert kernel, so the size decides the hop (N - 4160) and how many
+// workgroups share a CU.
+static int autotune_log2n(rx_format fmt, double baud, double fs, const rx_params &p) {
+  static std::mutex mu;
+  static std::map<int, int> chosen;   // device -> log2 N
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 14;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = chosen.find(dev);
+  if (it != chosen.end()) return it->second;
+  constexpr int NB = 16;
+  const size_t n = (size_t)1 << 22, nbits = n / 4;   // >= n/sps * bps / 8 for every KK format
+  std::vector<uint8_t> host(3 * n / 2);
+  uint64_t x = 0x2545F4914F6CDD1Dull;
+  for (auto &b : host) {
+    x ^= x << 13; x ^= x >> 7; x ^= x << 17;
+    b = (uint8_t)(x >> 24);
+  }
+  void *dbuf = nullptr;
+  uint8_t *dbits = nullptr;
+  int best = 14;
+  if (hipMalloc(&dbuf, host.size()) == hipSuccess && hipMalloc((void **)&dbits, NB * nbits) == hipSuccess &&
+      hipMemcpy(dbuf, host.data(), host.size(), hipMemcpyHostToDevice) == hipSuccess) {
+    float best_ms = 0.0f;
+    for (int lg : {14, 13}) {   // incumbent first
+      rx_params q = p;
+      q.fft_log2 = lg;
+      q.max_samples = n;
+      q.flags = 0;
+      q.stream = nullptr;
+      std::vector<rx_handle> hs;
+      for (int i = 0; i < NB; i++) {
+        rx_handle h = nullptr;
+        if (rx_create(fmt, baud, fs, &q, &h) != RX_OK) break;
+        hs.push_back(h);
+      }
+      float ms = -1.0f;
+      hipEvent_t e0, e1;
+      if ((int)hs.size() == NB && hipEventCreate(&e0) == hipSuccess) {
+        if (hipEventCreate(&e1) == hipSuccess) {
+          std::vector<const void *> bufs(NB, dbuf);
+          std::vector<size_t> ns(NB, n);
+          std::vector<void *> outs(NB);
+          for (int i = 0; i < NB; i++) outs[i] = dbits + i * nbits;
+          rx_process_batch(hs.data(), bufs.data(), ns.data(), outs.data(), NB, 0);   // warm-up
+          for (int r = 0; r < 3; r++) {
+            float t = -1.0f;
+            hipEventRecord(e0, nullptr);
+            rx_process_batch(hs.data(), bufs.data(), ns.data(), outs.data(), NB, 0);
+            hipEventRecord(e1, nullptr);
+            if (hipEventSynchronize(e1) == hipSuccess) hipEventElapsedTime(&t, e0, e1);
+            if (t > 0.0f && (ms < 0.0f || t < ms)) ms = t;
+          }
+          hipEventDestroy(e1);
+        }
+        hipEventDestroy(e0);
+      }
+      for (rx_handle h : hs) rx_destroy(h);
+      if (ms > 0.0f && (best_ms == 0.0f || ms < 0.97f * best_ms)) {
+        best_ms = ms;
+        best = lg;
+      }
+    }
+  }
+  if (dbuf) hipFree(dbuf);
+  if (dbits) hipFree(dbits);
+  chosen[dev] = best;
+  return best;
+}
+
 int rx_create(rx_format fmt, double baud, double fs, const rx_params *pin, rx_handle *out) {
   if (!out) return RX_E_INVALID;
   *out = nullptr;
@@ -206,7 +316,7 @@ int rx_create(rx_format fmt, double baud, double fs, const rx_params *pin, rx_ha
   h->kk = kk;
   h->sps = kk ? 4 : 2;
   h->bps = bps_of(fmt);
-  h->log2n = p.fft_log2 ? p.fft_log2 : 14;
+  h->log2n = p.fft_log2 ? p.fft_log2 : (kk ? autotune_log2n(fmt, baud, fs, p) : 14);
   h->stream = static_cast<hipStream_t>(p.stream);
   const int64_t L = (int64_t)p.max_samples;
   Alloc &A = h->mem;
@@ -257,15 +367,12 @@ int rx_create(rx_format fmt, double baud, double fs, const rx_params *pin, rx_ha
     std::complex<double> c0 = 0.0;
     for (int i = 0; i < 65; i++) c0 += (double)hf[i] * std::exp(std::complex<double>(0.0, -2.0 * M_PI * J.r * (32 - i)));
     J.c0 = make_float2((float)c0.real(), (float)c0.imag());
-    const int n = 1 << h->log2n;
-    std::vector<float> hs = design_hilbert_spectrum(p.hilbert_taps, h->log2n);
-    std::vector<float2> tw = design_twiddles(h->log2n);
-    float *dhs = A.get<float>(n);
-    float2 *dtw = A.get<float2>(tw.size());
-    ok = dhs && dtw && hipMemcpy(dhs, hs.data(), n * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
-         hipMemcpy(dtw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess;
-    J.hspec = dhs;
-    J.twid = dtw;
+    const SharedTables *t = shared_tables(h->log2n, p.hilbert_taps);
+    ok = t != nullptr;
+    if (ok) {
+      J.hspec = t->hspec;
+      J.twid = t->twid;
+    }
     const int64_t nd = L / 2;
     const int hop = J.hop;
     J.z = A.get<float2>(nd);

@@ -139,7 +139,11 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
     lds[fpad(k)] = make_float2(zv.y * s, zv.x * s);
   }
   __syncthreads();
-  fft_forward<LOGN>(lds, J.twid);
+  // the second transform recomputes its twiddle addresses: kept live from the
+  // first they would be spilled across the Hilbert product
+  const float2 *tw2 = J.twid;
+  asm volatile("" : "+s"(tw2));
+  fft_forward<LOGN>(lds, tw2);
 
   float ph[2][QPT];
 #pragma unroll
