@@ -4,8 +4,8 @@
  * The library implements the per-buffer DSP hot path of a software-defined,
  * GPU-based optical receiver (van der Heide et al., ECOC 2020): a buffer of
  * 12-bit ADC samples in device memory goes in, hard-decision bits and error
- * counts come out.  Two chains, selected at create time ("format switching
- * by updating the GPU software", Sec. 1, second paragraph):
+ * counts come out.  Two chains, selected at create time (the paper switches
+ * formats by changing only the GPU software, Sec. 1, second paragraph):
  *
  *   - PAM-2/4/8 at 2 samples/symbol: DC removal, matched filter, blockwise
  *     clock-phase estimation + unwrapping + clock recovery, FFE, decision,

@@ -241,7 +241,7 @@ static double rnd(int mode, double v)
 static cplx rndc(int mode, cplx v) { return rnd(mode, creal(v)) + I * rnd(mode, cimag(v)); }
 
 /* ------------------------------------------------------------------ */
-/* Decisions and Gray demapping (Sec. 2, "symbol decision, demapping"). */
+/* Decisions and Gray demapping (Sec. 2, first and second paragraphs). */
 /* Levels 2i-(M-1) per real axis, thresholds at the even integers, an    */
 /* exact tie goes to the higher level; bits = i xor (i >> 1), MSB first. */
 /* ------------------------------------------------------------------ */

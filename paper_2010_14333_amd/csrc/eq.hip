@@ -1,7 +1,8 @@
 // Equaliser tail of both chains: prefix adaptation (one wavefront per
-// buffer), block-parallel DD-LMS FFE (one lane per block, Sec. 2, second
-// paragraph: "8192 data blocks per buffer in parallel"), decisions, Gray
-// demapping, bit packing and error counting (Sec. 3, second paragraph).
+// buffer), block-parallel DD-LMS FFE (one lane pair per block; the paper
+// runs the 8192 blocks of a buffer in parallel, Sec. 2, second paragraph),
+// decisions, Gray demapping, bit packing and error counting (Sec. 3, second
+// paragraph).
 #include <type_traits>
 
 #include "rx_dev.hpp"
