@@ -311,16 +311,20 @@ __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
 #pragma unroll
     for (int kk = 0; kk < BC; kk++) {
       if constexpr (CPLX) {
-        // z = sum_i w_i x_i and w_i += e conj(x_i), four FMAs per tap each
-        float2 z = make_float2(0.0f, 0.0f);
+        // z = sum_i w_i x_i and w_i += e conj(x_i), four FMAs per tap each;
+        // the dot product in two interleaved partial sums per component (even
+        // and odd a) so four independent FMA chains are in flight
+        float2 z0 = make_float2(0.0f, 0.0f), z1 = z0;
 #pragma unroll
         for (int a = 0; a <= C; a++) {
           const float2 xv = xe[kk + C - a];
-          z.x = fmaf(w[a].x, xv.x, z.x);
-          z.x = fmaf(-w[a].y, xv.y, z.x);
-          z.y = fmaf(w[a].x, xv.y, z.y);
-          z.y = fmaf(w[a].y, xv.x, z.y);
+          float2 &zz = (a & 1) ? z1 : z0;
+          zz.x = fmaf(w[a].x, xv.x, zz.x);
+          zz.x = fmaf(-w[a].y, xv.y, zz.x);
+          zz.y = fmaf(w[a].x, xv.y, zz.y);
+          zz.y = fmaf(w[a].y, xv.x, zz.y);
         }
+        float2 z = cadd(z0, z1);
         z.x += pair_swap(z.x);
         z.y += pair_swap(z.y);
         const float2 e = make_float2(mu * (decide_level(z.x, m) - z.x), mu * (decide_level(z.y, m) - z.y));

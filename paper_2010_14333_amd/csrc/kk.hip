@@ -31,34 +31,44 @@ __device__ __forceinline__ void frame_codes8(const uint8_t *in, int64_t n, int64
   }
 }
 
-// LDS slot of y' sample q.  The filter's A operand reads, per instruction,
-// one component of 16 rows (8 tiles 32 samples apart) x 4 (PREC 0) or 4 x 8
-// (PREC 1, 2) window positions; the padding spreads them over distinct banks:
-// 4 float2 per 32 for FP32 (tile stride 72 dwords), 1 per 32 for the narrow
-// forms (66 dwords).
+// LDS layout of the downshifted field y' for the matched filter.
+//  PREC 0: two planes of floats, re at [0, YPL) and im at [YPL, 2 YPL), no
+//    padding: a lane reads 24 consecutive window samples of one component
+//    as six 16-byte reads.
+//  PREC 1, 2: interleaved float2 with one float2 of padding per 32, so the
+//    8-wide A reads of one instruction (8 tiles 32 samples apart) fall on
+//    distinct banks (tile stride 66 dwords).
 template <int PREC>
-__device__ __forceinline__ int yidx(int q) { return PREC == 0 ? q + 4 * (q >> 5) : q + (q >> 5); }
+__device__ __forceinline__ int yidx(int q) { return q + (q >> 5); }
 
 // Matched-filter B operand (the tap matrix) and one wavefront pass of eight
 // 16-output tiles.  Lane l holds column q = l % 16 and K-row group l / 16.
 template <int PREC> struct MfB;
 template <> struct MfB<0> {
   // v_mfma_f32_16x16x4_f32: lane l supplies A[l % 16][l / 16], B[l / 16][l % 16].
-  // B[t][q] = htab[2 q + 95 - t] from a zero-padded copy of the taps in LDS
-  // (h[i] at index i + 31), read per step rather than held in registers.
+  // The GEMM's K index is taken as k = 24 kq + ks (step ks, lane group kq), so
+  // lane group kq covers window samples 24 kq .. 24 kq + 23 in order.
+  // B[k][q] = h[2 q + 64 - k] = htab[2 q + 95 - k] from a zero-padded copy of
+  // the taps in LDS (h[i] at index i + 31).
   const float *hb;
-  __device__ void load(const float *__restrict__ htab, int row, int kq) { hb = htab + 2 * row + 95 - kq; }
-  __device__ rx_f32x4 apply(const float *__restrict__ ly, int tile, int comp, int kq) const {
-    // A[row][4 ks + kq] = component of y'[32 tile + 4 ks + kq]; 4 ks + kq stays
-    // inside one 32-sample group, so the padded offset is 36 tile + kq + 4 ks +
-    // 4 (ks / 8) float2.
-    const float *a = ly + 2 * (36 * tile + kq) + comp;
+  __device__ void load(const float *__restrict__ htab, int row, int kq) { hb = htab + 2 * row + 95 - 24 * kq; }
+  // yp: this lane's component plane; A[row][k] = plane[32 tile + k]
+  __device__ rx_f32x4 apply(const float *__restrict__ yp, int tile, int kq) const {
+    const float4 *a4 = reinterpret_cast<const float4 *>(yp + 32 * tile + 24 * kq);   // 16-byte aligned
+    float av[24];
+#pragma unroll
+    for (int h = 0; h < 6; h++) {
+      const float4 v = a4[h];
+      av[4 * h] = v.x;
+      av[4 * h + 1] = v.y;
+      av[4 * h + 2] = v.z;
+      av[4 * h + 3] = v.w;
+    }
     rx_f32x4 c0 = {0.0f, 0.0f, 0.0f, 0.0f}, c1 = c0;
 #pragma unroll
     for (int ks = 0; ks < 24; ks += 2) {
-      c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2 * (4 * ks + 4 * (ks >> 3))], hb[-4 * ks], c0, 0, 0, 0);
-      c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2 * (4 * ks + 4 + 4 * ((ks + 1) >> 3))], hb[-4 * ks - 4], c1,
-                                                0, 0, 0);
+      c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks], hb[-ks], c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks + 1], hb[-ks - 1], c1, 0, 0, 0);
     }
     return c0 + c1;
   }
@@ -95,8 +105,13 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
   constexpr int HOP = (N - RX_KK_HALFV - RX_KK_EDGE - RX_KK_CMF) & ~15;
   constexpr int QN = HOP + 2 * RX_KK_CMF;   // y' samples each block needs
   constexpr int QPT = (QN + T - 1) / T;
+  constexpr int NTILE = HOP / 32;          // 16-output matched-filter tiles per block
+  constexpr int NG = (NTILE + 7) / 8;      // eight tiles per wavefront pass
+  constexpr int YPL = 32 * (8 * NG) + 64;  // y' plane length (PREC 0): every window a pass reads
+  static_assert(2 * YPL <= 2 * (N + N / 16) && QN <= YPL && YPL % 4 == 0, "y' planes fit the LDS buffer");
   constexpr float INV2PI = 0.15915494309189535f;
   __shared__ float2 lds[N + N / 16];
+  float *const ypl = reinterpret_cast<float *>(lds);   // y' planes of the FP32 filter
   __shared__ double red[9 * (T / 64)];
   __shared__ float htab[128];   // matched-filter taps h[i] at i + 31, zero elsewhere
 
@@ -168,8 +183,6 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
   int nint = 0;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int row = lane & 15, kq = lane >> 4;
-  constexpr int NTILE = HOP / 32;          // 16-output tiles per block
-  constexpr int NG = (NTILE + 7) / 8;      // eight tiles per wavefront pass
   constexpr int NW = T / 64;
   // rotations of P between this lane's outputs: +16 (second tile) and
   // +16 * 8 * NW (next pass)
@@ -205,7 +218,12 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
             if (J.field) J.field[nq0 + q] = ev;
           }
         }
-        lds[yidx<PREC>(q)] = yv;
+        if constexpr (PREC == 0) {
+          ypl[q] = yv.x;
+          ypl[YPL + q] = yv.y;
+        } else {
+          lds[yidx<PREC>(q)] = yv;
+        }
       }
       dph = cmul(dph, drot);
     }
@@ -226,7 +244,9 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
     float2 pp = cis_rev(downshift_rev(J.r, 2 * mfirst));
     for (int grp = wv; grp < NG; grp += NW) {
       const int tile = grp * 8 + (row >> 1);
-      const rx_f32x4 acc = bmf.apply(ly, tile, row & 1, kq);
+      rx_f32x4 acc;
+      if constexpr (PREC == 0) acc = bmf.apply(ypl + (row & 1) * YPL, tile, kq);
+      else acc = bmf.apply(ly, tile, row & 1, kq);
 #pragma unroll
       for (int jj = 0; jj < 2; jj++) {
         const int t2 = grp * 8 + 2 * kq + jj;
