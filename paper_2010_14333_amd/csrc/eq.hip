@@ -227,9 +227,9 @@ __global__ __launch_bounds__(256) void rx_prefix(RxLaunch L) {
 // are staged through LDS in chunks of BC steps: the workgroup loads every
 // block's next 2*BC samples with coalesced reads, each lane runs BC steps
 // from registers, and the soft outputs go back out the same way.
-#define BC 8
 template <bool CPLX, int K>
 __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
+  constexpr int BC = 8;   // steps per staged chunk (16 measured no faster on the real chain)
   using T = typename std::conditional<CPLX, float2, float>::type;
   constexpr int NBW = 128;   // blocks per workgroup (one lane pair each)
   __shared__ T sin_[NBW * (2 * BC + 1)];
@@ -366,7 +366,6 @@ __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
   }
   if (CPLX && active && h == 0) gstore(J.s4, b, make_float2(s4r, s4i));
 }
-#undef BC
 
 // Precision form of the FFE (KK): the prefix taps w0 frozen for the buffer
 // and applied as a Toeplitz GEMM on MFMA with narrow operands and FP32

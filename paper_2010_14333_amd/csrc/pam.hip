@@ -2,7 +2,8 @@
 // filter, blockwise clock-phase estimation, unwrapping and clock recovery.
 #include "rx_dev.hpp"
 
-#define PAM_TS 4096      // matched-filter outputs per workgroup (8 timing blocks)
+#define PAM_TS 4096      // matched-filter outputs per tile (8 timing blocks)
+#define PAM_MF_SUB 1     // tiles per workgroup (more serialises the tiles and loses parallel slack)
 #define PAM_SUMW 16384   // samples per code-sum workgroup
 
 // Exact integer sum of the codes (the buffer mean is then exact in FP64).
@@ -46,8 +47,7 @@ __global__ __launch_bounds__(256) void pam_mf(RxLaunch L) {
   const RxJob J = *L.job[jb];
   const int64_t n = L.n[jb];
   const uint8_t *in = L.in[jb];
-  const int64_t t0 = (int64_t)blockIdx.x * PAM_TS;
-  if (t0 >= n) return;
+  if ((int64_t)blockIdx.x * PAM_MF_SUB * PAM_TS >= n) return;
   {
     const int64_t np = (n + PAM_SUMW - 1) / PAM_SUMW;
     unsigned long long s = 0;
@@ -59,7 +59,7 @@ __global__ __launch_bounds__(256) void pam_mf(RxLaunch L) {
     if (threadIdx.x == 0) {
       const unsigned long long tot = rs[0] + rs[1] + rs[2] + rs[3];
       mean_s = (double)tot / (double)n + 0.5;
-      if (blockIdx.x == 0) {
+      if (blockIdx.x == 0) {   // the workgroup of tile 0
         J.sc->mean_re = mean_s;
         J.sc->mean_im = 0.0;
       }
@@ -67,83 +67,92 @@ __global__ __launch_bounds__(256) void pam_mf(RxLaunch L) {
     __syncthreads();
   }
   const double mv = mean_s;
-  // codes of [t0 - 24, t0 + TS + 24) in aligned groups of eight (t0 is a
-  // multiple of 8); xs[i] holds sample t0 - 20 + i
-  for (int g = threadIdx.x; g < (PAM_TS + 48) / 8; g += 256) {
-    const int64_t s0 = t0 - 24 + 8 * g;
-    int c[8];
-    if (s0 >= 0 && s0 + 8 <= n) {
-      read_codes8(in, s0 >> 3, c);
-    } else {
+  for (int sub = 0; sub < PAM_MF_SUB; sub++) {
+    const int64_t tile = (int64_t)blockIdx.x * PAM_MF_SUB + sub;
+    const int64_t t0 = tile * PAM_TS;
+    if (t0 >= n) break;
+    __syncthreads();   // the previous tile's readers of xs and ys are done
+    // codes of [t0 - 24, t0 + TS + 24) in aligned groups of eight (t0 is a
+    // multiple of 8); xs[i] holds sample t0 - 20 + i
+    for (int g = threadIdx.x; g < (PAM_TS + 48) / 8; g += 256) {
+      const int64_t s0 = t0 - 24 + 8 * g;
+      int c[8];
+      if (s0 >= 0 && s0 + 8 <= n) {
+        read_codes8(in, s0 >> 3, c);
+      } else {
 #pragma unroll
-      for (int e = 0; e < 8; e++) c[e] = (s0 + e >= 0 && s0 + e < n) ? read_code(in, s0 + e) : -1;
-    }
+        for (int e = 0; e < 8; e++) c[e] = (s0 + e >= 0 && s0 + e < n) ? read_code(in, s0 + e) : -1;
+      }
 #pragma unroll
-    for (int e = 0; e < 8; e++) {
-      const int i = 8 * g + e - 4;
-      if (i >= 0 && i < XN) xs[xpad(i)] = c[e] >= 0 ? (float)((double)c[e] + 0.5 - mv) : 0.0f;
-    }
-  }
-  __syncthreads();
-  // 16 consecutive outputs per thread: y[t0 + 16 tid + o] from 48 inputs
-  double p2 = 0.0;
-  {
-    float acc[16];
-#pragma unroll
-    for (int o = 0; o < 16; o++) acc[o] = 0.0f;
-    const int ib = 16 * threadIdx.x + 4;
-#pragma unroll
-    for (int d = 0; d < 48; d++) {
-      const float v = xs[xpad(ib + d)];
-#pragma unroll
-      for (int o = 0; o < 16; o++) {
-        const int tap = o + 32 - d;
-        if (tap >= 0 && tap <= 32) acc[o] = fmaf(J.mf[tap], v, acc[o]);
+      for (int e = 0; e < 8; e++) {
+        const int i = 8 * g + e - 4;
+        if (i >= 0 && i < XN) xs[xpad(i)] = c[e] >= 0 ? (float)((double)c[e] + 0.5 - mv) : 0.0f;
       }
     }
-    float q2 = 0.0f;   // 16 squares in FP32, then one FP64 add
+    __syncthreads();
+    // 16 consecutive outputs per thread: y[t0 + 16 tid + o] from 48 inputs
+    double p2 = 0.0;
+    {
+      float acc[16];
 #pragma unroll
-    for (int o = 0; o < 16; o++) {
-      const int64_t t = t0 + 16 * threadIdx.x + o;
-      const float yv = (t < n) ? acc[o] : 0.0f;
-      ys[16 * threadIdx.x + o + 4] = yv;
-      q2 = fmaf(yv, yv, q2);
+      for (int o = 0; o < 16; o++) acc[o] = 0.0f;
+      // xpad(16 tid + 4 + d) = 17 tid + (4 + d) + (4 + d) / 16: a per-thread base and
+      // immediate offsets
+      const float *xb = xs + 17 * threadIdx.x;
+#pragma unroll
+      for (int d = 0; d < 48; d++) {
+        const float v = xb[(4 + d) + ((4 + d) >> 4)];
+#pragma unroll
+        for (int o = 0; o < 16; o++) {
+          const int tap = o + 32 - d;
+          if (tap >= 0 && tap <= 32) acc[o] = fmaf(J.mf[tap], v, acc[o]);
+        }
+      }
+      float q2 = 0.0f;   // 16 squares in FP32, then one FP64 add
+#pragma unroll
+      for (int o = 0; o < 16; o++) {
+        const int64_t t = t0 + 16 * threadIdx.x + o;
+        const float yv = (t < n) ? acc[o] : 0.0f;
+        ys[16 * threadIdx.x + o + 4] = yv;
+        q2 = fmaf(yv, yv, q2);
+      }
+      p2 = q2;
     }
-    p2 = q2;
-  }
-  if (threadIdx.x < 8) {   // the 4 outputs either side of the tile
-    const int l = threadIdx.x < 4 ? (int)threadIdx.x - 4 : PAM_TS + (int)threadIdx.x - 4;
-    const int64_t t = t0 + l;
-    float a = 0.0f;
-    for (int i = 0; i < 33; i++) a = fmaf(J.mf[i], xs[xpad(l + 36 - i)], a);
-    ys[l + 4] = (t >= 0 && t < n) ? a : 0.0f;
-  }
-  p2 = block_sum(p2, red);   // (its barriers also publish ys)
-  if (threadIdx.x == 0) J.part2[blockIdx.x] = p2;
-  for (int i = threadIdx.x; i < PAM_TS; i += 256) {   // coalesced copy-out of the tile
-    const int64_t t = t0 + i;
-    if (t < n) gptr(J.y)[t] = ys[i + 4];
-  }
-  // Gardner sums: 8 blocks of 256 symbols, 32 threads x 8 symbols each.
-  const int bl = threadIdx.x >> 5, sub = threadIdx.x & 31;
-  float g0 = 0.0f, g1 = 0.0f;
-  for (int e = 0; e < 8; e++) {
-    const int s = 2 * (256 * bl + 8 * sub + e) + 4;   // ys index of the symbol sample
-    const float y0 = ys[s], y1 = ys[s + 1], y2 = ys[s + 2];
-    g0 += y1 * (y0 - y2);
-    const float ym = ys[s - 1], y3 = ys[s + 3], y4 = ys[s + 4];
-    const float h0 = (-ym + 9.0f * y0 + 9.0f * y1 - y2) * 0.0625f;
-    const float h1 = (-y0 + 9.0f * y1 + 9.0f * y2 - y3) * 0.0625f;
-    const float h2 = (-y1 + 9.0f * y2 + 9.0f * y3 - y4) * 0.0625f;
-    g1 += h1 * (h0 - h2);
-  }
+    if (threadIdx.x < 8) {   // the 4 outputs either side of the tile
+      const int l = threadIdx.x < 4 ? (int)threadIdx.x - 4 : PAM_TS + (int)threadIdx.x - 4;
+      const int64_t t = t0 + l;
+      float a = 0.0f;
+      for (int i = 0; i < 33; i++) a = fmaf(J.mf[i], xs[xpad(l + 36 - i)], a);
+      ys[l + 4] = (t >= 0 && t < n) ? a : 0.0f;
+    }
+    p2 = block_sum(p2, red);   // (its barriers also publish ys)
+    if (threadIdx.x == 0) J.part2[tile] = p2;
+    {   // coalesced copy-out of the tile (32-bit offsets from its start)
+      const auto yo = gptr(J.y) + t0;
+      const int cnt = (int)(n - t0 < PAM_TS ? n - t0 : PAM_TS);
+      for (int i = threadIdx.x; i < cnt; i += 256) yo[i] = ys[i + 4];
+    }
+    // Gardner sums: 8 blocks of 256 symbols, 32 threads x 8 symbols each.
+    const int bl = threadIdx.x >> 5, gsub = threadIdx.x & 31;
+    float g0 = 0.0f, g1 = 0.0f;
+    for (int e = 0; e < 8; e++) {
+      const int s = 2 * (256 * bl + 8 * gsub + e) + 4;   // ys index of the symbol sample
+      const float y0 = ys[s], y1 = ys[s + 1], y2 = ys[s + 2];
+      g0 += y1 * (y0 - y2);
+      const float ym = ys[s - 1], y3 = ys[s + 3], y4 = ys[s + 4];
+      const float h0 = (-ym + 9.0f * y0 + 9.0f * y1 - y2) * 0.0625f;
+      const float h1 = (-y0 + 9.0f * y1 + 9.0f * y2 - y3) * 0.0625f;
+      const float h2 = (-y1 + 9.0f * y2 + 9.0f * y3 - y4) * 0.0625f;
+      g1 += h1 * (h0 - h2);
+    }
 #pragma unroll
-  for (int o = 16; o > 0; o >>= 1) {
-    g0 += __shfl_xor(g0, o, 32);
-    g1 += __shfl_xor(g1, o, 32);
+    for (int o = 16; o > 0; o >>= 1) {
+      g0 += __shfl_xor(g0, o, 32);
+      g1 += __shfl_xor(g1, o, 32);
+    }
+    const int64_t gb = t0 / 512 + bl;
+    if (gsub == 0 && gb * 512 < n) J.gard[gb] = make_float2(g0, g1);
   }
-  const int64_t gb = t0 / 512 + bl;
-  if (sub == 0 && gb * 512 < n) J.gard[gb] = make_float2(g0, g1);
 }
 
 // Angle of the detector sums averaged over blocks b-16 .. b+16.
@@ -202,35 +211,46 @@ __global__ __launch_bounds__(1024) void pam_unwrap(RxLaunch L) {
 }
 
 // Cubic-Lagrange (Farrow) interpolation with the AGC gain:
-// xr[t] = g * y(t + delta_b), t in block b.  A workgroup covers 1024
-// consecutive samples (two 512-sample timing blocks), one per thread and pass.
+// xr[t] = g * y(t + delta_b), t in block b.  A workgroup covers FAR_SPAN
+// consecutive samples (FAR_SPAN / 512 timing blocks), one sample per thread
+// and pass; the four Lagrange weights are formed once per block (each pair of
+// passes stays in one block), offsets are 32-bit from the span's start.
+#define FAR_SPAN 8192
 __global__ __launch_bounds__(256) void pam_farrow(RxLaunch L) {
   const int jb = blockIdx.y;
   const RxJob J = *L.job[jb];
   const int64_t n = L.n[jb];
+  const int64_t base = (int64_t)blockIdx.x * FAR_SPAN;
+  if (base >= n) return;
   const float g = (float)J.sc->agc;
-  const auto y = gptr(J.y);
-  const auto xr = gptr(J.xr);
-  const auto dl = gptr(J.delta);
-#pragma unroll
-  for (int o = 0; o < 4; o++) {
-    const int64_t t = (int64_t)blockIdx.x * 1024 + 256 * o + threadIdx.x;
-    if (t >= n) return;
-    const float d = dl[t / 512];
+  const auto y = gptr(J.y) + base;
+  const auto xr = gptr(J.xr) + base;
+  const auto dl = gptr(J.delta) + base / 512;
+  const int span = (int)(n - base < FAR_SPAN ? n - base : FAR_SPAN);   // multiple of 1024
+  const int lo = (int)(base < 4 ? -base : -4), hi = (int)(n - base < FAR_SPAN + 4 ? n - base : FAR_SPAN + 4);
+  for (int o2 = 0; 512 * o2 < span; o2++) {   // block o2 of the span: passes 2 o2, 2 o2 + 1
+    const float d = dl[o2];
     const float fl = floorf(d), mu = d - fl;
-    const int64_t i0 = t + (int64_t)fl;
+    const int sh = (int)fl;
     const float lm1 = -mu * (mu - 1.0f) * (mu - 2.0f) * (1.0f / 6.0f);
     const float l0 = (mu + 1.0f) * (mu - 1.0f) * (mu - 2.0f) * 0.5f;
     const float l1 = -(mu + 1.0f) * mu * (mu - 2.0f) * 0.5f;
     const float l2 = (mu + 1.0f) * mu * (mu - 1.0f) * (1.0f / 6.0f);
-    float v;
-    if (i0 >= 1 && i0 + 2 < n) {
-      v = lm1 * y[i0 - 1] + l0 * y[i0] + l1 * y[i0 + 1] + l2 * y[i0 + 2];
-    } else {
-      auto yat = [&](int64_t j) { return (j >= 0 && j < n) ? y[j] : 0.0f; };
-      v = lm1 * yat(i0 - 1) + l0 * yat(i0) + l1 * yat(i0 + 1) + l2 * yat(i0 + 2);
+    // taps i0 - 1 .. i0 + 2 of the whole block inside the buffer, relative to base: [lo, hi)
+    const bool inside = 512 * o2 + sh - 1 >= lo && 512 * o2 + 511 + sh + 2 < hi;
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+      const int t = 512 * o2 + 256 * h + threadIdx.x;
+      const int i0 = t + sh;
+      float v;
+      if (inside) {
+        v = lm1 * y[i0 - 1] + l0 * y[i0] + l1 * y[i0 + 1] + l2 * y[i0 + 2];
+      } else {
+        auto yat = [&](int j) { return (base + j >= 0 && base + j < n) ? y[j] : 0.0f; };
+        v = lm1 * yat(i0 - 1) + l0 * yat(i0) + l1 * yat(i0 + 1) + l2 * yat(i0 + 2);
+      }
+      xr[t] = g * v;
     }
-    xr[t] = g * v;
   }
 }
 
@@ -242,7 +262,8 @@ void rx_launch_pam_stage(int stage, const RxLaunch &L, int64_t maxn, hipStream_t
       hipLaunchKernelGGL(pam_sum, dim3((unsigned)((maxn + PAM_SUMW - 1) / PAM_SUMW), cnt), dim3(256), 0, s, L);
       break;
     case ST_PAM_MF:
-      hipLaunchKernelGGL(pam_mf, dim3((unsigned)((maxn + PAM_TS - 1) / PAM_TS), cnt), dim3(256), 0, s, L);
+      hipLaunchKernelGGL(pam_mf, dim3((unsigned)((maxn + PAM_MF_SUB * PAM_TS - 1) / (PAM_MF_SUB * PAM_TS)), cnt),
+                         dim3(256), 0, s, L);
       break;
     case ST_PAM_GAVG:
       hipLaunchKernelGGL(pam_gavg, dim3((unsigned)((nb + 255) / 256), cnt), dim3(256), 0, s, L);
@@ -251,7 +272,7 @@ void rx_launch_pam_stage(int stage, const RxLaunch &L, int64_t maxn, hipStream_t
       hipLaunchKernelGGL(pam_unwrap, dim3(1, cnt), dim3(1024), 0, s, L);
       break;
     case ST_PAM_FARROW:
-      hipLaunchKernelGGL(pam_farrow, dim3((unsigned)((maxn + 1023) / 1024), cnt), dim3(256), 0, s, L);
+      hipLaunchKernelGGL(pam_farrow, dim3((unsigned)((maxn + FAR_SPAN - 1) / FAR_SPAN), cnt), dim3(256), 0, s, L);
       break;
   }
 }
