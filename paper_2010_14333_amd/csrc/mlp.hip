@@ -212,11 +212,26 @@ __device__ __forceinline__ float mlp_tile(const MlpFrag &f, MNT::vec bx, int kq)
     const float4 b = cv4[4 * t];
     d1[t] = MNT::mfma(f.a1[t], bx, rx_f32x4{b.x, b.y, b.z, b.w});
   }
+  // layer-1 activations: round pairs to BF16, then ReLU as a packed 16-bit
+  // integer max with 0 (a BF16 with the sign bit set is a negative int16;
+  // rounding and ReLU commute)
   MNT::vec bh[2];
 #pragma unroll
-  for (int ks = 0; ks < 2; ks++)
+  for (int ks = 0; ks < 2; ks++) {
+    typedef short s16x2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 #pragma unroll
-    for (int jj = 0; jj < 8; jj++) bh[ks][jj] = MNT::cvt(relu_bits(d1[2 * ks + jj / 4][jj % 4]));
+    for (int jp = 0; jp < 4; jp++) {
+      const int t = 2 * ks + (2 * jp) / 4, j = (2 * jp) % 4;
+      typedef float f32x2 __attribute__((ext_vector_type(2)));
+      bf16x2 pr = __builtin_convertvector((f32x2){d1[t][j], d1[t][j + 1]}, bf16x2);
+      s16x2 bits = __builtin_bit_cast(s16x2, pr);
+      bits = __builtin_elementwise_max(bits, (s16x2){0, 0});
+      pr = __builtin_bit_cast(bf16x2, bits);
+      bh[ks][2 * jp] = pr[0];
+      bh[ks][2 * jp + 1] = pr[1];
+    }
+  }
   float y = 0.0f;
 #pragma unroll
   for (int t = 0; t < 4; t++) {
