@@ -152,29 +152,44 @@ def main():
     samples = a.batch * N
     gsps = samples / (ms_step * 1e-3) / 1e9
 
-    def time_handles(recs, bp, steps, graph, lat=False):
-        outs = [torch.empty(r.bits_bytes(N), dtype=torch.uint8, device=dev) for r in recs]
-        hs = [r.h for r in recs]
-        op = [o.data_ptr() for o in outs]
-        ns = [N] * len(recs)
-        for _ in range(a.warmup):
+    def time_handles(make_recs, bp, steps, graph, lat=False):
+        """Time `steps` batches, consecutive batches alternating over the
+        streams (one set of handles per stream, made by make_recs(stream));
+        with lat, each batch's latency from events on its own stream."""
+        sets = []
+        for st in streams:
+            recs = make_recs(st)
+            outs = [torch.empty(r.bits_bytes(N), dtype=torch.uint8, device=dev) for r in recs]
+            sets.append((st, recs, outs, [r.h for r in recs], [o.data_ptr() for o in outs]))
+        ns = [N] * len(bp)
+
+        def step(i):
+            _, _, _, hs, op = sets[i % len(sets)]
             rx.rx_process_batch(hs, bp, ns, op, graph=graph)
+
+        for i in range(a.warmup * len(sets)):
+            step(i)
         torch.cuda.synchronize()
-        for r in recs:
-            r.reset()
+        for _, recs, _, _, _ in sets:
+            for r in recs:
+                r.reset()
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                for _ in range(steps)] if lat else []
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for i in range(steps):
+            st = sets[i % len(sets)][0]
             if lat:
-                evs[i][0].record()
-            rx.rx_process_batch(hs, bp, ns, op, graph=graph)
+                evs[i][0].record(st)
+            step(i)
             if lat:
-                evs[i][1].record()
+                evs[i][1].record(st)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t1
-        errs = [r.errors() for r in recs]
+        errs = [r.errors() for _, recs, _, _, _ in sets for r in recs]
+        for _, recs, _, _, _ in sets:
+            for r in recs:
+                r.close()
         bits = sum(e["bits"] for e in errs)
         ber = sum(e["bit_errors"] for e in errs) / bits if bits else None
         ms = sorted(e0.elapsed_time(e1) for e0, e1 in evs)
@@ -199,16 +214,16 @@ def main():
         pbp = [pb[i % 4].data_ptr() for i in range(a.batch)]
         res = {}
         for eq in ("mlp", "lms"):
-            recs = [rx.Receiver(rx.RX_PAM8, testg[i % 4]["seed"], max_samples=N,
-                                equalizer=rx.RX_EQ_MLP if eq == "mlp" else rx.RX_EQ_LMS)
-                    for i in range(a.batch)]
-            if eq == "mlp":
-                for r in recs:
-                    rx.rx_set_mlp(r.h, w)
-            wl, ber_f, _, errs = time_handles(recs, pbp, a.steps, bool(a.graph))
+            def make(st, eq=eq):
+                recs = [rx.Receiver(rx.RX_PAM8, testg[i % 4]["seed"], max_samples=N, stream=st,
+                                    equalizer=rx.RX_EQ_MLP if eq == "mlp" else rx.RX_EQ_LMS)
+                        for i in range(a.batch)]
+                if eq == "mlp":
+                    for r in recs:
+                        rx.rx_set_mlp(r.h, w)
+                return recs
+            wl, ber_f, _, errs = time_handles(make, pbp, a.steps, bool(a.graph))
             res[eq] = (a.batch * N / (wl / a.steps) / 1e9, ber_f, sum(e["fallbacks"] for e in errs))
-            for r in recs:
-                r.close()
         mlp_form = {"workload": "PAM-8, 2 GBaud, 91 km SSMF, tanh driver, 24 dB; 2^22-sample buffers",
                     "value": round(res["mlp"][0], 3), "unit": "Gsamples/s", "ber": res["mlp"][1],
                     "fallbacks": res["mlp"][2], "lms_value": round(res["lms"][0], 3), "lms_ber": res["lms"][1],
@@ -225,20 +240,21 @@ def main():
                 per_fmt[f].append(synth.generate(f, N, synth.derive_seed(301, i), snr))
         log(f"[bench] generated mixed-format buffers in {time.time() - t0:.1f}s")
         dbuf = {f: [torch.from_numpy(g["packed"]).to(dev) for g in gl] for f, gl in per_fmt.items()}
-        cnt = {}
-        recs, mbp = [], []
+        cnt, slot, mbp = {}, [], []
         for f, _ in plan:
             j = cnt.get(f, 0) % len(per_fmt[f])
             cnt[f] = cnt.get(f, 0) + 1
-            recs.append(rx.Receiver(f, per_fmt[f][j]["seed"], max_samples=N))
+            slot.append((f, j))
             mbp.append(dbuf[f][j].data_ptr())
-        wl, ber_m, ms, _ = time_handles(recs, mbp, a.steps, True, lat=True)
-        for r in recs:
-            r.close()
+
+        def make_mixed(st):
+            return [rx.Receiver(f, per_fmt[f][j]["seed"], max_samples=N, stream=st) for f, j in slot]
+        wl, ber_m, ms, _ = time_handles(make_mixed, mbp, a.steps, True, lat=True)
         p50 = ms[len(ms) // 2]
         p99 = ms[min(len(ms) - 1, int(round(0.99 * (len(ms) - 1))))]
         mixed = {"workload": f"{a.batch} x 2^22 buffers, formats mixed per buffer (SplitMix64 % 5), "
-                             "SNR U[14, 26] dB, one hipGraph replay per batch",
+                             f"SNR U[14, 26] dB, one hipGraph replay per batch, consecutive batches over "
+                             f"{len(streams)} streams",
                  "value": round(a.batch * N / (wl / a.steps) / 1e9, 3), "unit": "Gsamples/s",
                  "formats": {synth.FORMAT_NAMES[f]: c for f, c in sorted(cnt.items())},
                  "batch_latency_ms_p50": round(p50, 3), "batch_latency_ms_p99": round(p99, 3),
