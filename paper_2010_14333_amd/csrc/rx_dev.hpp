@@ -147,13 +147,16 @@ __device__ __forceinline__ float2 ref_symbol(const RxJob &J, int64_t k) {
 }
 
 // ---- decisions: levels 2i-(M-1), thresholds at even integers, tie -> up ---
-__device__ __forceinline__ int decide_index(float v, int m) {
-  float f = floorf((v + (float)m) * 0.5f);
-  f = fminf(fmaxf(f, 0.0f), (float)(m - 1));
-  return (int)f;
+// floor((v + m) / 2) is computed as floor(fma(v, 1/2, m/2)): scaling by 1/2
+// is exact, so both round v + m once.  The clamp uses v_med3 directly (no
+// NaN canonicalisation of the operands).
+__device__ __forceinline__ float decide_floor(float v, int m) {
+  const float f = floorf(fmaf(v, 0.5f, 0.5f * (float)m));
+  return __builtin_amdgcn_fmed3f(f, 0.0f, (float)(m - 1));
 }
+__device__ __forceinline__ int decide_index(float v, int m) { return (int)decide_floor(v, m); }
 __device__ __forceinline__ float decide_level(float v, int m) {
-  return (float)(2 * decide_index(v, m) - (m - 1));
+  return fmaf(2.0f, decide_floor(v, m), (float)(1 - m));
 }
 
 // ---- 12-bit packed input -------------------------------------------------
