@@ -35,11 +35,13 @@ __device__ __forceinline__ void frame_codes8(const uint8_t *in, int64_t n, int64
 //  PREC 0: two planes of floats, re at [0, YPL) and im at [YPL, 2 YPL), no
 //    padding: a lane reads 24 consecutive window samples of one component
 //    as six 16-byte reads.
-//  PREC 1, 2: interleaved float2 with one float2 of padding per 32, so the
-//    8-wide A reads of one instruction (8 tiles 32 samples apart) fall on
-//    distinct banks (tile stride 66 dwords).
-template <int PREC>
-__device__ __forceinline__ int yidx(int q) { return q + (q >> 5); }
+//  PREC 1, 2: two planes of the narrow type (re, then im PS elements on),
+//    each sample rounded once when it is written, with 8 elements of padding
+//    per 32 samples: the A operand of one MFMA step (8 consecutive samples of
+//    one component) is a single aligned 16-byte read, and the eight tiles and
+//    two planes one instruction reads (tile stride 20 dwords, plane offset
+//    16 mod 64 dwords) fall on distinct banks.
+__host__ __device__ constexpr int nidx(int q) { return q + ((q >> 5) << 3); }
 
 // Matched-filter B operand (the tap matrix) and one wavefront pass of eight
 // 16-output tiles.  Lane l holds column q = l % 16 and K-row group l / 16.
@@ -86,15 +88,12 @@ template <int PREC> struct MfB {
         b[ks][j] = NT::cvt((tap >= 0 && tap <= 64) ? mf[tap] : 0.0f);
       }
   }
-  __device__ rx_f32x4 apply(const float *__restrict__ ly, int tile, int comp, int kq) const {
+  // yp: this lane's component plane; A[row][k] = plane[32 tile + k]
+  __device__ rx_f32x4 apply(const typename NT::elem *__restrict__ yp, int tile, int kq) const {
     rx_f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int ks = 0; ks < 3; ks++) {
-      typename NT::vec a;
-#pragma unroll
-      for (int j = 0; j < 8; j++) a[j] = NT::cvt(ly[2 * yidx<PREC>(32 * tile + 32 * ks + 8 * kq + j) + comp]);
-      acc = NT::mfma(a, b[ks], acc);
-    }
+    for (int ks = 0; ks < 3; ks++)
+      acc = NT::mfma(*reinterpret_cast<const typename NT::vec *>(yp + nidx(32 * (tile + ks) + 8 * kq)), b[ks], acc);
     return acc;
   }
 };
@@ -109,9 +108,16 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
   constexpr int NG = (NTILE + 7) / 8;      // eight tiles per wavefront pass
   constexpr int YPL = 32 * (8 * NG) + 64;  // y' plane length (PREC 0): every window a pass reads
   static_assert(2 * YPL <= 2 * (N + N / 16) && QN <= YPL && YPL % 4 == 0, "y' planes fit the LDS buffer");
+  // narrow forms: plane stride PS (elements, 32 mod 128) and, behind the two
+  // planes, this thread's frame-B phases parked in LDS between the frames
+  constexpr int PS = (YPL + 8 * ((YPL - 1) >> 5) - 32 + 127) / 128 * 128 + 32;
+  static_assert(PS >= nidx(YPL - 1) + 1 && (PS + QN) * 4 <= 8 * (N + N / 16), "narrow planes and phase stash fit");
   constexpr float INV2PI = 0.15915494309189535f;
   __shared__ float2 lds[N + N / 16];
   float *const ypl = reinterpret_cast<float *>(lds);   // y' planes of the FP32 filter
+  using ElemT = typename std::conditional<PREC == 0, float, typename NarrowT<PREC == 0 ? 1 : PREC>::elem>::type;
+  ElemT *const npl = reinterpret_cast<ElemT *>(lds);
+  float *const stash = reinterpret_cast<float *>(lds) + PS;
   __shared__ double red[9 * (T / 64)];
   __shared__ float htab[128];   // matched-filter taps h[i] at i + 31, zero elsewhere
 
@@ -160,17 +166,26 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
   asm volatile("" : "+s"(tw2));
   fft_forward<LOGN>(lds, tw2);
 
-  float ph[2][QPT];
+  constexpr int NPH = PREC == 0 ? 2 : 1;   // frames whose phases stay in registers
+  float ph[NPH][QPT], phb[PREC == 0 ? 1 : QPT];
 #pragma unroll
   for (int i = 0; i < QPT; i++) {
     const int q = threadIdx.x + i * T;
     if (q < QN) {
       const float2 v = lds[fpad(q + RX_KK_EDGE - RX_KK_CMF)];
       ph[0][i] = v.x * J.sgn * INV2PI;
-      ph[1][i] = -v.y * J.sgn * INV2PI;
+      if constexpr (PREC == 0) ph[NPH - 1][i] = -v.y * J.sgn * INV2PI;
+      else phb[i] = -v.y * J.sgn * INV2PI;
     }
   }
   __syncthreads();
+  if constexpr (PREC != 0) {
+#pragma unroll
+    for (int i = 0; i < QPT; i++) {
+      const int q = threadIdx.x + i * T;
+      if (q < QN) stash[q] = phb[i];   // read back by this thread only
+    }
+  }
 
   // Workgroup partial sums: the field E (carrier mean), |Z|^2, and the
   // carrier terms.  In the interior T[m] = c0 P(m)^*, P(m) = exp(+j 2 pi
@@ -210,7 +225,10 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
         if (q >= qlo && q < qhi) {
           const int o = 3 * (q + e);
           const int c = (((int)cb[o >> 1] | ((int)cb[(o >> 1) + 1] << 8)) >> (((q + e) & 1) << 2)) & 0xFFF;
-          const float2 ev = cscale(cis_rev(ph[x][i]), sqrtf((float)c + 0.5f));
+          float phv;
+          if constexpr (PREC == 0) phv = ph[x][i];
+          else phv = x == 0 ? ph[0][i] : stash[q];
+          const float2 ev = cscale(cis_rev(phv), sqrtf((float)c + 0.5f));
           yv = cmul(ev, dph);
           if (q >= RX_KK_CMF && q < RX_KK_CMF + HOP) {
             se_re += ev.x;
@@ -222,7 +240,8 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
           ypl[q] = yv.x;
           ypl[YPL + q] = yv.y;
         } else {
-          lds[yidx<PREC>(q)] = yv;
+          npl[nidx(q)] = NarrowT<PREC == 0 ? 1 : PREC>::cvt(yv.x);
+          npl[PS + nidx(q)] = NarrowT<PREC == 0 ? 1 : PREC>::cvt(yv.y);
         }
       }
       dph = cmul(dph, drot);
@@ -238,7 +257,6 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
     MfB<PREC> bmf;
     if constexpr (PREC == 0) bmf.load(htab, row, kq);
     else bmf.load(J.mf, row, kq);
-    const float *ly = reinterpret_cast<const float *>(lds);
     // P at this lane's first output of the block, exact from the FP64 phase
     const int64_t mfirst = m0 + 16 * (8 * wv + 2 * kq) + row;
     float2 pp = cis_rev(downshift_rev(J.r, 2 * mfirst));
@@ -246,7 +264,7 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
       const int tile = grp * 8 + (row >> 1);
       rx_f32x4 acc;
       if constexpr (PREC == 0) acc = bmf.apply(ypl + (row & 1) * YPL, tile, kq);
-      else acc = bmf.apply(ly, tile, row & 1, kq);
+      else acc = bmf.apply(npl + (row & 1) * PS, tile, kq);
 #pragma unroll
       for (int jj = 0; jj < 2; jj++) {
         const int t2 = grp * 8 + 2 * kq + jj;

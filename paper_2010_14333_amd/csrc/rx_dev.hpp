@@ -13,6 +13,7 @@ typedef float rx_f32x4 __attribute__((ext_vector_type(4)));
 template <int PREC> struct NarrowT;
 template <> struct NarrowT<1> {
   using vec = rx_bf16x8;
+  using elem = __bf16;
   __device__ static __bf16 cvt(float v) { return (__bf16)v; }
   __device__ static rx_f32x4 mfma(vec a, vec b, rx_f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -20,6 +21,7 @@ template <> struct NarrowT<1> {
 };
 template <> struct NarrowT<2> {
   using vec = rx_f16x8;
+  using elem = _Float16;
   __device__ static _Float16 cvt(float v) { return (_Float16)v; }
   __device__ static rx_f32x4 mfma(vec a, vec b, rx_f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
