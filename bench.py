@@ -134,6 +134,9 @@ def main():
         berr = sum(e["bit_errors"] for e in errs)
         return wall, stages, (berr / bits if bits else None)
 
+    def per_buffer(st):
+        return {k: round(v[0] / v[1] * 1e3 / a.batch, 3) for k, v in st.items()}
+
     wall, stages, ber = run_form(rx.RX_FP32, True)
     log(f"[bench] plain chain: {a.steps} steps x {a.batch} buffers in {wall:.3f}s")
     # the same chain on one stream, so that each stage's launch owns the chip
@@ -146,6 +149,9 @@ def main():
         w2, _, b2 = run_form(prec, False)
         forms[name] = {"value": round(a.batch * N / (w2 / a.steps) / 1e9, 3), "unit": "Gsamples/s",
                        "ms_per_step": round(w2 * 1e3 / a.steps, 4), "ber": b2}
+        if a.one_stream:   # isolated stage times of the form
+            _, st1, _ = run_form(prec, True, nstreams=1)
+            forms[name]["one_stream_stage_us_per_buffer"] = per_buffer(st1)
         log(f"[bench] {name} form: {forms[name]['value']} Gs/s, BER {b2}")
 
     ms_step = wall * 1e3 / a.steps
@@ -277,9 +283,6 @@ def main():
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4), "traffic": None,
                 "kernel": "kk_front<14>", "flop_per_sample": round(front_flop_per_sample(14), 2),
                 "launch_us": round(dom_ms * 1e3, 2)}
-
-    def per_buffer(st):
-        return {k: round(v[0] / v[1] * 1e3 / a.batch, 3) for k, v in st.items()}
 
     roof = roofline(stages)
     traffic = front_traffic(a.batch)

@@ -372,8 +372,15 @@ __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
 // accumulation.  A row = [Re x | Im x] of the 64-sample window of a tile of
 // 16 symbols (x = AGC'd 2-sps samples from 2(k0+s)-C), B = [[Wr, Wi],
 // [-Wi, Wr]] with W[t][q] = w0[2C + 2q - t]; 4 K-steps x 2 column tiles.
-// One wavefront per 16 tiles (256 symbols = two VV blocks), whose z^4 sums
-// it also forms.
+// A group is 16 tiles (256 symbols = two VV blocks), whose z^4 sums the
+// wavefront also forms; each wavefront takes FFE_GPW consecutive groups, so
+// the B fragments are built once per 2048 symbols and the next group's
+// window is in flight while the current one is filtered.
+#define FFE_GPW 8
+#define FFE_PL 672   // staged plane length: window positions 0..543 with 8 elements of padding per 32
+// LDS index of window position t: the 16-byte A reads of the 16 rows then
+// fall on distinct banks (row stride 20 dwords)
+__device__ __forceinline__ int ffe_idx(int t) { return t + ((t >> 5) << 3); }
 template <int PREC>
 __global__ __launch_bounds__(256) void rx_ffe_mfma(RxLaunch L) {
   using NT = NarrowT<PREC>;
@@ -381,18 +388,16 @@ __global__ __launch_bounds__(256) void rx_ffe_mfma(RxLaunch L) {
   const RxJob J = *L.job[jb];
   const int64_t n = L.n[jb], nx = n / 2, nsym = n / 4;
   const int lane = threadIdx.x & 63;
-  const int64_t grp = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (grp * 256 >= nsym) return;
+  const int64_t grp0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * FFE_GPW;
   const int K = J.ffe_taps, C = (K - 1) / 2;
-  const int s = J.sc->lag;
-  const float g = (float)J.sc->agc;
-  const float2 mean = make_float2((float)J.sc->mean_re, (float)J.sc->mean_im);
   const int row = lane & 15, kq = lane >> 4;
-  // B fragments: kk = 32 ks + 8 kq + j (t = kk % 64, part = kk / 64),
+  // B fragments, shared by the workgroup's wavefronts in LDS (wavefront ks
+  // builds step ks): kk = 32 ks + 8 kq + j (t = kk % 64, part = kk / 64),
   // column q = row of output tile ct (0: Re z, 1: Im z)
-  typename NT::vec bw[4][2];
-#pragma unroll
-  for (int ks = 0; ks < 4; ks++)
+  __shared__ __align__(16) typename NT::vec bl[8][64];
+  {
+    const int ks = threadIdx.x >> 6;
+    typename NT::vec b0, b1;
 #pragma unroll
     for (int j = 0; j < 8; j++) {
       const int kk = 32 * ks + 8 * kq + j, t = kk & 63, part = kk >> 6;
@@ -400,49 +405,112 @@ __global__ __launch_bounds__(256) void rx_ffe_mfma(RxLaunch L) {
       float2 w = make_float2(0.0f, 0.0f);
       if (i >= 0 && i < K) w = J.sc->w0[i];
       const float wr = NT::cvt(w.x), wi = NT::cvt(w.y);   // operands rounded once
-      bw[ks][0][j] = NT::cvt(part == 0 ? wr : -wi);
-      bw[ks][1][j] = NT::cvt(part == 0 ? wi : wr);
+      b0[j] = NT::cvt(part == 0 ? wr : -wi);
+      b1[j] = NT::cvt(part == 0 ? wi : wr);
     }
-  const int64_t tile = grp * 16 + row;
-  const int64_t base = 2 * (tile * 16 + s) - C;
+    bl[2 * ks][lane] = b0;
+    bl[2 * ks + 1][lane] = b1;
+  }
+  __syncthreads();
+  if (grp0 * 256 >= nsym) return;
+  const int s = J.sc->lag;
+  const float g = (float)J.sc->agc;
+  const float2 mean = make_float2((float)J.sc->mean_re, (float)J.sc->mean_im);
   const auto zin = gview(J.z);
-  float2 xv[16];
+  // The group's 16 windows cover samples base0 .. base0 + 543; they are
+  // staged once per group into this wavefront's LDS planes as u rounded to
+  // the narrow type, from coalesced 16-byte loads (pairs of samples from the
+  // even index R0 = base0 - (base0 mod 2)).  Interior samples u = g z - (g mean c0) P,
+  // P(p) = exp(-j 2 pi frac(2 r p)): one FP64 anchor per lane and group, then
+  // fixed rotations; edge samples take the exact form.
+  __shared__ __align__(16) typename NT::elem ul[4][2 * FFE_PL];
+  typename NT::elem *const ure = ul[threadIdx.x >> 6], *const uim = ure + FFE_PL;
+  const float2 Mc = cscale(cmul(mean, J.c0), g);
+  const float2 r1 = cis_rev(-downshift_rev(J.r, 2));
+  const float2 r128 = cis_rev(-downshift_rev(J.r, 2 * 128));
+  // window pairs of group grp (index clamped into the buffer; pairs outside
+  // the interior are recomputed exactly below)
+  auto load_pairs = [&](int64_t grp, float4 (&zz)[5]) {
+    const int64_t base0 = 2 * (grp * 256 + s) - C;
+    const int64_t R0 = base0 - (base0 & 1);
 #pragma unroll
-  for (int h = 0; h < 2; h++)
-#pragma unroll
-    for (int j = 0; j < 8; j++) {
-      const int64_t q = base + 32 * h + 8 * kq + j;
-      xv[8 * h + j] = kk_sample<true>(J, zin, q, n, mean, g);
+    for (int it = 0; it < 5; it++) {
+      const int64_t p = R0 + 2 * (lane + 64 * it);
+      zz[it] = gload4(J.z, (p < 0 ? 0 : (p > nx - 2 ? nx - 2 : p)) >> 1);
     }
-  rx_f32x4 zr = {0.0f, 0.0f, 0.0f, 0.0f}, zi = {0.0f, 0.0f, 0.0f, 0.0f};
+  };
+  float4 zn[5];
+  load_pairs(grp0, zn);
+  for (int gi = 0; gi < FFE_GPW; gi++) {
+    const int64_t grp = grp0 + gi;
+    if (grp * 256 >= nsym) break;
+    float4 zc[5];
 #pragma unroll
-  for (int ks = 0; ks < 4; ks++) {
-    typename NT::vec a;
+    for (int it = 0; it < 5; it++) zc[it] = zn[it];
+    if (gi + 1 < FFE_GPW && (grp + 1) * 256 < nsym) load_pairs(grp + 1, zn);   // in flight during this group
+    const int64_t base0 = 2 * (grp * 256 + s) - C;
+    const int odd = (int)(base0 & 1);
+    const int64_t R0 = base0 - odd;
+    float2 P = cis_rev(-downshift_rev(J.r, 2 * (R0 + 2 * lane)));
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");   // the previous group's reads are done
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-    for (int j = 0; j < 8; j++) {
-      const float2 v = xv[8 * (ks & 1) + j];
-      a[j] = NT::cvt(ks < 2 ? v.x : v.y);
+    for (int it = 0; it < 5; it++) {
+      const int pi = lane + 64 * it;   // pair pi: samples R0 + 2 pi, R0 + 2 pi + 1
+      if (pi < 273) {
+        const int64_t p = R0 + 2 * pi;
+        float2 u0, u1;
+        if (p >= 16 && 2 * (p + 1) + 32 < n) {
+          const float4 zz = zc[it];
+          u0 = csub(cscale(make_float2(zz.x, zz.y), g), cmul(Mc, P));
+          u1 = csub(cscale(make_float2(zz.z, zz.w), g), cmul(Mc, cmul(P, r1)));
+        } else {
+          u0 = kk_sample(J, zin, p, n, mean, g);
+          u1 = kk_sample(J, zin, p + 1, n, mean, g);
+        }
+        const int t0 = 2 * pi - odd;   // window position of sample p
+        if (t0 >= 0 && t0 < 544) {
+          ure[ffe_idx(t0)] = NT::cvt(u0.x);
+          uim[ffe_idx(t0)] = NT::cvt(u0.y);
+        }
+        if (t0 + 1 < 544) {
+          ure[ffe_idx(t0 + 1)] = NT::cvt(u1.x);
+          uim[ffe_idx(t0 + 1)] = NT::cvt(u1.y);
+        }
+      }
+      P = cmul(P, r128);
     }
-    zr = NT::mfma(a, bw[ks][0], zr);
-    zi = NT::mfma(a, bw[ks][1], zi);
-  }
-  float s4r = 0.0f, s4i = 0.0f;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");   // staged planes visible to the wavefront
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    rx_f32x4 zr = {0.0f, 0.0f, 0.0f, 0.0f}, zi = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-  for (int j = 0; j < 4; j++) {
-    const int64_t k = (grp * 16 + 4 * kq + j) * 16 + row;
-    const float2 z = make_float2(zr[j], zi[j]);
-    gstore(J.soft, k, z);
-    const float a2 = z.x * z.x - z.y * z.y, b2 = 2.0f * z.x * z.y;
-    s4r += a2 * a2 - b2 * b2;
-    s4i += 2.0f * a2 * b2;
-  }
-  // lanes 0..31 hold tiles 0..7 (block 2 grp), lanes 32..63 tiles 8..15
+    for (int ks = 0; ks < 4; ks++) {
+      // A[row][8 kq + j] = window sample 32 row + 32 (ks % 2) + 8 kq + j
+      const typename NT::elem *pl = ks < 2 ? ure : uim;
+      const typename NT::vec a = *reinterpret_cast<const typename NT::vec *>(pl + ffe_idx(32 * row + 32 * (ks & 1) + 8 * kq));
+      zr = NT::mfma(a, bl[2 * ks][lane], zr);
+      zi = NT::mfma(a, bl[2 * ks + 1][lane], zi);
+    }
+    float s4r = 0.0f, s4i = 0.0f;
 #pragma unroll
-  for (int o = 16; o > 0; o >>= 1) {
-    s4r += __shfl_xor(s4r, o, 64);
-    s4i += __shfl_xor(s4i, o, 64);
+    for (int j = 0; j < 4; j++) {
+      const int64_t k = (grp * 16 + 4 * kq + j) * 16 + row;
+      const float2 z = make_float2(zr[j], zi[j]);
+      gstore(J.soft, k, z);
+      const float a2 = z.x * z.x - z.y * z.y, b2 = 2.0f * z.x * z.y;
+      s4r += a2 * a2 - b2 * b2;
+      s4i += 2.0f * a2 * b2;
+    }
+    // lanes 0..31 hold tiles 0..7 (block 2 grp), lanes 32..63 tiles 8..15
+#pragma unroll
+    for (int o = 16; o > 0; o >>= 1) {
+      s4r += __shfl_xor(s4r, o, 64);
+      s4i += __shfl_xor(s4i, o, 64);
+    }
+    if ((lane & 31) == 0) gstore(J.s4, 2 * grp + (lane >> 5), make_float2(s4r, s4i));
   }
-  if ((lane & 31) == 0) gstore(J.s4, 2 * grp + (lane >> 5), make_float2(s4r, s4i));
 }
 
 // Decisions, Gray demapping, packing and error counting: eight consecutive
@@ -544,7 +612,8 @@ void rx_launch_eq_stage(int stage, const RxLaunch &L, int64_t maxn, int kk, int 
   if (stage == ST_PREFIX) {
     hipLaunchKernelGGL(rx_prefix, dim3(1, cnt), dim3(256), 0, s, L);
   } else if (stage == ST_BLOCKS && kk && prec != 0) {
-    dim3 gf((unsigned)((nsym / 256 + 3) / 4), cnt);
+    const int64_t ngrp = (nsym + 255) / 256;
+    dim3 gf((unsigned)((ngrp + 4 * FFE_GPW - 1) / (4 * FFE_GPW)), cnt);   // four wavefronts per workgroup
     if (prec == 1) hipLaunchKernelGGL(rx_ffe_mfma<1>, gf, dim3(256), 0, s, L);
     else hipLaunchKernelGGL(rx_ffe_mfma<2>, gf, dim3(256), 0, s, L);
   } else if (stage == ST_BLOCKS) {

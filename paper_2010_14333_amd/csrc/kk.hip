@@ -79,14 +79,12 @@ template <int PREC> struct MfB {
   // v_mfma_f32_16x16x32_{bf16,f16}: operands rounded once to the narrow type
   using NT = NarrowT<PREC>;
   typename NT::vec b[3];
-  __device__ void load(const float *__restrict__ mf, int row, int kq) {
+  // B[t][q] = h[2 q + 64 - t] = htab[2 q + 95 - t], t = 32 ks + 8 kq + j
+  __device__ void load(const float *__restrict__ htab, int row, int kq) {
 #pragma unroll
     for (int ks = 0; ks < 3; ks++)
 #pragma unroll
-      for (int j = 0; j < 8; j++) {
-        const int t = 32 * ks + 8 * kq + j, tap = 2 * row + 64 - t;
-        b[ks][j] = NT::cvt((tap >= 0 && tap <= 64) ? mf[tap] : 0.0f);
-      }
+      for (int j = 0; j < 8; j++) b[ks][j] = NT::cvt(htab[2 * row + 95 - (32 * ks + 8 * kq + j)]);
   }
   // yp: this lane's component plane; A[row][k] = plane[32 tile + k]
   __device__ rx_f32x4 apply(const typename NT::elem *__restrict__ yp, int tile, int kq) const {
@@ -255,8 +253,7 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
     //    (16x16x32 steps), both with FP32 accumulation.
     const int64_t m0 = blk[x] * (HOP / 2);
     MfB<PREC> bmf;
-    if constexpr (PREC == 0) bmf.load(htab, row, kq);
-    else bmf.load(J.mf, row, kq);
+    bmf.load(htab, row, kq);
     // P at this lane's first output of the block, exact from the FP64 phase
     const int64_t mfirst = m0 + 16 * (8 * wv + 2 * kq) + row;
     float2 pp = cis_rev(downshift_rev(J.r, 2 * mfirst));
