@@ -227,6 +227,8 @@ __global__ __launch_bounds__(256) void rx_prefix(RxLaunch L) {
 // are staged through LDS in chunks of BC steps: the workgroup loads every
 // block's next 2*BC samples with coalesced reads, each lane runs BC steps
 // from registers, and the soft outputs go back out the same way.
+// Four wavefronts per SIMD.  (Five, with 4-step chunks, is faster alone
+// but slows the chain: its workgroups keep the front end off more CUs.)
 template <bool CPLX, int K>
 __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
   constexpr int BC = 8;   // steps per staged chunk (16 measured no faster on the real chain)
@@ -520,7 +522,7 @@ __global__ __launch_bounds__(256) void rx_ffe_mfma(RxLaunch L) {
 #define DEC_SYMS 2048
 __global__ __launch_bounds__(256) void rx_decide(RxLaunch L) {
   __shared__ uint32_t wb[DEC_SYMS * 4 / 32];   // the workgroup's packed bits (up to 4 per symbol)
-  __shared__ unsigned long long red[3][4];
+  __shared__ uint32_t red[4];
   const int jb = blockIdx.y;
   const RxJob J = *L.job[jb];
   const int64_t n = L.n[jb];
@@ -535,9 +537,16 @@ __global__ __launch_bounds__(256) void rx_decide(RxLaunch L) {
   // this thread: symbols k0 .. k0 + 7 (one DD-LMS block, so one phase)
   const int64_t k0 = kbase + 8 * threadIdx.x;
   const bool valid = k0 < nsym;   // then k0 + 8 <= nsym
-  unsigned long long cs = 0, se = 0, be = 0;
+  // counted symbols, symbol errors and bit errors of this thread, packed as
+  // cs | se << 10 | be << 20: a wavefront counts at most 512 symbols and
+  // 2048 bit errors (4 bits per symbol at most), so no field overflows
+  uint32_t cnt = 0;
   uint32_t chunk = 0;   // symbol k0 + i at bits [bps i, bps (i + 1)), MSB of the symbol first
   if (valid) {
+    // counted symbols of this thread: i in [ilo, ihi)
+    const int64_t lo64 = P + RX_GUARD - k0, hi64 = nsym - RX_GUARD - k0;
+    const int ilo = (int)(lo64 < 0 ? 0 : (lo64 > 8 ? 8 : lo64)), ihi = (int)(hi64 < 0 ? 0 : (hi64 > 8 ? 8 : hi64));
+    const uint64_t zb = J.seed + (uint64_t)(k0 + 1) * RX_SM64_GAMMA;   // reference generator state of symbol k0
     float2 zv[8];
 #pragma unroll
     for (int h = 0; h < 4; h++) {
@@ -559,15 +568,11 @@ __global__ __launch_bounds__(256) void rx_decide(RxLaunch L) {
         const uint32_t gi = (uint32_t)decide_index(zv[i].x, m);
         sym = gi ^ (gi >> 1);
       }
-      uint32_t rev = 0;
-      for (int j = 0; j < bps; j++) rev |= ((sym >> (bps - 1 - j)) & 1u) << j;
-      chunk |= rev << (bps * i);
-      if (k >= P + RX_GUARD && k < nsym - RX_GUARD) {
-        const uint32_t ref = (uint32_t)(splitmix64(J.seed, (uint64_t)k) >> (64 - bps));
-        const int ne = __popc(ref ^ sym);
-        cs += 1;
-        be += (unsigned long long)ne;
-        se += ne > 0;
+      chunk |= (__builtin_bitreverse32(sym) >> (32 - bps)) << (bps * i);
+      if (i >= ilo && i < ihi) {
+        const uint32_t ref = (uint32_t)(splitmix64_mix(zb + (uint64_t)i * RX_SM64_GAMMA) >> (64 - bps));
+        const uint32_t ne = (uint32_t)__popc(ref ^ sym);
+        cnt += 1u + ((ne > 0u) << 10) + (ne << 20);
       }
     }
   }
@@ -580,19 +585,18 @@ __global__ __launch_bounds__(256) void rx_decide(RxLaunch L) {
   __syncthreads();
   const int64_t nsw = (nsym - kbase < DEC_SYMS ? nsym - kbase : DEC_SYMS) * bps / 32;
   for (int i = threadIdx.x; i < nsw; i += 256) out[kbase * bps / 32 + i] = wb[i];
-  cs = wave_sum(cs);
-  se = wave_sum(se);
-  be = wave_sum(be);
-  if ((threadIdx.x & 63) == 0) {
-    red[0][threadIdx.x >> 6] = cs;
-    red[1][threadIdx.x >> 6] = se;
-    red[2][threadIdx.x >> 6] = be;
-  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cnt;
   __syncthreads();
   if (threadIdx.x == 0) {
-    cs = red[0][0] + red[0][1] + red[0][2] + red[0][3];
-    se = red[1][0] + red[1][1] + red[1][2] + red[1][3];
-    be = red[2][0] + red[2][1] + red[2][2] + red[2][3];
+    unsigned long long cs = 0, se = 0, be = 0;
+#pragma unroll
+    for (int w = 0; w < 4; w++) {
+      cs += red[w] & 1023u;
+      se += (red[w] >> 10) & 1023u;
+      be += red[w] >> 20;
+    }
     if (cs) {
       atomicAdd(&J.sc->stats[1], cs);
       atomicAdd(&J.sc->stats[2], cs * (unsigned long long)bps);

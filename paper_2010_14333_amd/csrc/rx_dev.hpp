@@ -122,11 +122,15 @@ __device__ __forceinline__ void block_sum_n(double *v, double *scratch) {
 }
 
 // ---- reference sequence (SplitMix64, Steele, Lea & Flood 2014) -----------
-__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
-  uint64_t z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
+#define RX_SM64_GAMMA 0x9E3779B97F4A7C15ull
+// SplitMix64 output mixing of the state z = seed + (k + 1) gamma
+__device__ __forceinline__ uint64_t splitmix64_mix(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
   return z ^ (z >> 31);
+}
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
+  return splitmix64_mix(seed + (k + 1ull) * RX_SM64_GAMMA);
 }
 
 __device__ __forceinline__ uint32_t gray_inverse(uint32_t g) {
