@@ -110,6 +110,19 @@ template <int N, int R, int NS>
 __device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *__restrict__ tw) {
   constexpr int T = N / 16;
   constexpr int NB = (N / R) / T;  // butterflies per thread
+  // twiddle table reads first: their latency overlaps the LDS reads and the barrier
+  float2 tw1[NB], tw2[NB], tw4[NB], tw8[NB];
+  if constexpr (NS > 1) {
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+      const int j = threadIdx.x + b * T;
+      const int step = (j & (NS - 1)) * (N / (NS * R));
+      tw1[b] = tw[step];
+      tw2[b] = R > 2 ? tw[2 * step] : tw1[b];
+      tw4[b] = R > 4 ? tw[4 * step] : tw1[b];
+      tw8[b] = R > 8 ? tw[8 * step] : tw1[b];
+    }
+  }
   float2 v[NB][R];
 #pragma unroll
   for (int b = 0; b < NB; b++) {
@@ -122,14 +135,7 @@ __device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *__restr
   for (int b = 0; b < NB; b++) {
     const int j = threadIdx.x + b * T;
     const int k = j & (NS - 1);
-    if constexpr (NS > 1) {
-      const int step = k * (N / (NS * R));
-      const float2 w1 = tw[step];
-      const float2 w2 = R > 2 ? tw[2 * step] : w1;
-      const float2 w4 = R > 4 ? tw[4 * step] : w1;
-      const float2 w8 = R > 8 ? tw[8 * step] : w1;
-      apply_twiddles<R, 1>(v[b], w1, w2, w4, w8);
-    }
+    if constexpr (NS > 1) apply_twiddles<R, 1>(v[b], tw1[b], tw2[b], tw4[b], tw8[b]);
     dft_r<R>(v[b]);
     const int base = (j / NS) * NS * R + k;
 #pragma unroll

@@ -106,6 +106,7 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
   constexpr int NG = (NTILE + 7) / 8;      // eight tiles per wavefront pass
   constexpr int YPL = 32 * (8 * NG) + 64;  // y' plane length (PREC 0): every window a pass reads
   static_assert(2 * YPL <= 2 * (N + N / 16) && QN <= YPL && YPL % 4 == 0, "y' planes fit the LDS buffer");
+  static_assert((N / 8) % T == 0, "whole 8-sample groups per thread");
   // narrow forms: plane stride PS (elements, 32 mod 128) and, behind the two
   // planes, this thread's frame-B phases parked in LDS between the frames
   constexpr int PS = (YPL + 8 * ((YPL - 1) >> 5) - 32 + 127) / 128 * 128 + 32;
@@ -138,7 +139,9 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
   //    a small one keeps the FP32 transform accurate).
   const float off0 = 0.5f * __logf((float)read_code(in, clamp64(F[0] + N / 2, 0, n - 1)) + 0.5f);
   const float off1 = 0.5f * __logf((float)read_code(in, clamp64(F[1] + N / 2, 0, n - 1)) + 0.5f);
-  for (int g = threadIdx.x; g < N / 8; g += T) {
+#pragma unroll
+  for (int gi = 0; gi < N / 8 / T; gi++) {
+    const int g = threadIdx.x + gi * T;
     int ca[8], cb[8];
     frame_codes8(in, n, F[0] + 8 * g, ca);
     frame_codes8(in, n, F[1] + 8 * g, cb);
@@ -152,7 +155,9 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
   // 2. Hilbert filtering: Y = Z H, H = -j S; the inverse transform is done as
   //    conj(FFT(conj(Y)/N)), so the second pass leaves phiA - j phiB.
   fft_forward<LOGN>(lds, J.twid);
-  for (int k = threadIdx.x; k < N; k += T) {
+#pragma unroll 8
+  for (int i = 0; i < 16; i++) {   // unrolled: eight spectrum reads in flight together
+    const int k = threadIdx.x + i * T;
     const float2 zv = lds[fpad(k)];
     const float s = J.hspec[k];
     lds[fpad(k)] = make_float2(zv.y * s, zv.x * s);
@@ -215,14 +220,25 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
     const uint8_t *cb = in + 3 * ((nq0 - e) / 2);
     const int qlo = (int)clamp64(-nq0, 0, QN), qhi = (int)clamp64(n - nq0, 0, QN);   // t in [0, n)
     float2 dph = cis_rev(-downshift_rev(J.r, nq0 + threadIdx.x));
+    // all of this thread's code reads first (index clamped into the buffer),
+    // so their latencies overlap
+    int craw[QPT];
+    if (qhi > qlo) {
+#pragma unroll
+      for (int i = 0; i < QPT; i++) {
+        const int q = threadIdx.x + i * T;
+        const int qc = q < qlo ? qlo : (q >= qhi ? qhi - 1 : q);
+        const int o = 3 * (qc + e);
+        craw[i] = (int)cb[o >> 1] | ((int)cb[(o >> 1) + 1] << 8);
+      }
+    }
 #pragma unroll
     for (int i = 0; i < QPT; i++) {
       const int q = threadIdx.x + i * T;
       if (q < QN) {
         float2 yv = make_float2(0.0f, 0.0f);
         if (q >= qlo && q < qhi) {
-          const int o = 3 * (q + e);
-          const int c = (((int)cb[o >> 1] | ((int)cb[(o >> 1) + 1] << 8)) >> (((q + e) & 1) << 2)) & 0xFFF;
+          const int c = (craw[i] >> (((q + e) & 1) << 2)) & 0xFFF;
           float phv;
           if constexpr (PREC == 0) phv = ph[x][i];
           else phv = x == 0 ? ph[0][i] : stash[q];
