@@ -266,7 +266,7 @@ __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
     }
   };
   constexpr int LPP = 256 / (2 * BC);          // blocks staged per pass of the workgroup
-  static_assert(256 % (2 * BC) == 0 && NBW % LPP == 0, "staging assumes whole blocks per pass");
+  static_assert(256 % (2 * BC) == 0 && NBW % LPP == 0 && (NBW * 2 * BC) % 256 == 0, "staging assumes whole blocks per pass");
   const float2 Mc = cscale(cmul(mean, J.c0), g);
   const float2 rstep = cis_rev(-downshift_rev(J.r, 2 * 2 * LPP * (int64_t)blk));
   // taps 2a + h; lane 1's extra tap a = C (index K) stays zero: its update is masked
@@ -276,8 +276,43 @@ __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
   const float umask = h == 0 ? 1.0f : 0.0f;
   T xe[C + 1 + BC];   // xe[j] = sample p0 - C + 2 j - h (+ 2 BC per chunk)
   const int64_t p0 = 2 * (b * blk + s);
+  {
+    // start window: all reads first (index clamped), then formed; samples
+    // outside the interior are recomputed exactly
+    T xr0[C + 1];
 #pragma unroll
-  for (int j = 0; j <= C; j++) xe[j] = load(p0 - C + 2 * j - h);
+    for (int j = 0; j <= C; j++) {
+      const int64_t pj = p0 - C + 2 * j - h;
+      if constexpr (CPLX) xr0[j] = zin[pj < 0 ? 0 : (pj >= nx ? nx - 1 : pj)];
+      else xr0[j] = xin[pj < 0 ? 0 : (pj >= nx ? nx - 1 : pj)];
+    }
+    bool edge = false;
+    // carrier phasor P(p) = exp(-j 2 pi frac(2 r p)) at p = p0 - C - h, then
+    // one fixed rotation per step of two samples
+    float2 P = make_float2(1.0f, 0.0f), r4 = P;
+    if constexpr (CPLX) {
+      P = cis_rev(-downshift_rev(J.r, 2 * (p0 - C - h)));
+      r4 = cis_rev(-downshift_rev(J.r, 4));
+    }
+#pragma unroll
+    for (int j = 0; j <= C; j++) {
+      const int64_t pj = p0 - C + 2 * j - h;
+      if constexpr (CPLX) {
+        edge |= !kk_interior(pj, n);
+        xe[j] = csub(cscale(xr0[j], g), cmul(Mc, P));
+        P = cmul(P, r4);
+      } else {
+        xe[j] = (pj >= 0 && pj < nx) ? xr0[j] : 0.0f;
+      }
+    }
+    if (CPLX && edge) {   // a block at a buffer end
+#pragma unroll
+      for (int j = 0; j <= C; j++) {
+        const int64_t pj = p0 - C + 2 * j - h;
+        if (!kk_interior(pj, n)) xe[j] = load(pj);
+      }
+    }
+  }
   float s4r = 0.0f, s4i = 0.0f;
   const int nch = blk / BC;
   for (int ch = 0; ch < nch; ch++) {
@@ -290,20 +325,45 @@ __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
       // take the exact form).
       const int l0 = threadIdx.x / (2 * BC), jj = threadIdx.x % (2 * BC);
       const int64_t pa = 2 * ((b0 + l0) * blk + s) + C + 1 + 2 * BC * ch + jj;
-      float2 P = cis_rev(-downshift_rev(J.r, 2 * pa));
-#pragma unroll 4
+      // all reads first (index clamped into the stream) so their latencies
+      // overlap; samples outside the interior are recomputed exactly
+      float2 zr[NBW / LPP];
+#pragma unroll
       for (int i = 0; i < NBW / LPP; i++) {
         const int64_t pl = pa + (int64_t)i * 2 * LPP * blk;
-        const float2 v = (pl >= 16 && 2 * pl + 32 < n) ? csub(cscale(zin[pl], g), cmul(Mc, P))
-                                                       : load(pl);
-        sin_[(l0 + LPP * i) * (2 * BC + 1) + jj] = v;
+        zr[i] = zin[pl < 0 ? 0 : (pl >= nx ? nx - 1 : pl)];
+      }
+      float2 P = cis_rev(-downshift_rev(J.r, 2 * pa));
+      bool edge = false;
+#pragma unroll
+      for (int i = 0; i < NBW / LPP; i++) {
+        const int64_t pl = pa + (int64_t)i * 2 * LPP * blk;
+        edge |= !(pl >= 16 && 2 * pl + 32 < n);
+        sin_[(l0 + LPP * i) * (2 * BC + 1) + jj] = csub(cscale(zr[i], g), cmul(Mc, P));
         P = cmul(P, rstep);
       }
+      if (edge) {   // the few samples near the buffer ends, exact
+#pragma unroll 1
+        for (int i = 0; i < NBW / LPP; i++) {
+          const int64_t pl = pa + (int64_t)i * 2 * LPP * blk;
+          if (!(pl >= 16 && 2 * pl + 32 < n)) sin_[(l0 + LPP * i) * (2 * BC + 1) + jj] = load(pl);
+        }
+      }
     } else {
-      for (int e = threadIdx.x; e < NBW * 2 * BC; e += 256) {
+      constexpr int NE = NBW * 2 * BC / 256;
+      float xr[NE];
+#pragma unroll
+      for (int i = 0; i < NE; i++) {   // all reads first, index clamped into the stream
+        const int e = threadIdx.x + 256 * i;
+        const int64_t pl = 2 * ((b0 + e / (2 * BC)) * blk + s) + C + 1 + 2 * BC * ch + e % (2 * BC);
+        xr[i] = xin[pl < 0 ? 0 : (pl >= nx ? nx - 1 : pl)];
+      }
+#pragma unroll
+      for (int i = 0; i < NE; i++) {
+        const int e = threadIdx.x + 256 * i;
         const int l = e / (2 * BC), jj = e % (2 * BC);
         const int64_t pl = 2 * ((b0 + l) * blk + s) + C + 1 + 2 * BC * ch + jj;
-        sin_[l * (2 * BC + 1) + jj] = load(pl);
+        sin_[l * (2 * BC + 1) + jj] = (pl >= 0 && pl < nx) ? xr[i] : 0.0f;
       }
     }
     __syncthreads();
