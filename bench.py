@@ -65,7 +65,7 @@ def main():
     ap.add_argument("--streams", type=int, default=3,
                     help="consecutive batches alternate over this many HIP streams (batch pipelining)")
     ap.add_argument("--one-stream", type=int, default=1, help="also time the chain on one stream (isolated stages)")
-    ap.add_argument("--cpu-buffers", type=int, default=8)
+    ap.add_argument("--cpu-buffers", type=int, default=24)
     ap.add_argument("--copy-probe", type=int, default=1, help="run a 256 MiB device copy (counter scale)")
     ap.add_argument("--forms", default="bf16,fp16", help="precision forms timed beside the plain chain")
     ap.add_argument("--mlp", type=int, default=1, help="train and time the PAM-8 learned-equaliser form")
@@ -305,8 +305,9 @@ def main():
     if a.cpu_buffers > 0:
         import oracle
         t2 = time.perf_counter()
-        k = min(a.cpu_buffers, a.distinct)
-        for g in gens[:k]:
+        k = a.cpu_buffers   # the distinct buffers, round-robin, as on the GPU
+        for i in range(k):
+            g = gens[i % a.distinct]
             oracle.process(synth.KK_16QAM, g["packed"], N, g["seed"], want=("bits",))
         ct = time.perf_counter() - t2
         cpu = {"value": round(k * N / ct / 1e9, 5), "unit": "Gsamples/s", "cores": 1, "kind": "oracle",
