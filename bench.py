@@ -70,6 +70,7 @@ def main():
     ap.add_argument("--forms", default="bf16,fp16", help="precision forms timed beside the plain chain")
     ap.add_argument("--mlp", type=int, default=1, help="train and time the PAM-8 learned-equaliser form")
     ap.add_argument("--mixed", type=int, default=1, help="time a 64-buffer mixed-format batch (graph replay)")
+    ap.add_argument("--host", type=int, default=1, help="time the plain chain fed from pinned host memory")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the receiver path is "
@@ -158,20 +159,28 @@ def main():
     samples = a.batch * N
     gsps = samples / (ms_step * 1e-3) / 1e9
 
-    def time_handles(make_recs, bp, steps, graph, lat=False):
+    def time_handles(make_recs, bp, steps, graph, lat=False, host=False):
         """Time `steps` batches, consecutive batches alternating over the
         streams (one set of handles per stream, made by make_recs(stream));
-        with lat, each batch's latency from events on its own stream."""
+        with lat, each batch's latency from events on its own stream; with
+        host, bp are pinned host buffers and the bits come back to pinned
+        host memory (rx_process_batch_host)."""
         sets = []
         for st in streams:
             recs = make_recs(st)
-            outs = [torch.empty(r.bits_bytes(N), dtype=torch.uint8, device=dev) for r in recs]
+            if host:
+                outs = [torch.empty(r.bits_bytes(N), dtype=torch.uint8, pin_memory=True) for r in recs]
+            else:
+                outs = [torch.empty(r.bits_bytes(N), dtype=torch.uint8, device=dev) for r in recs]
             sets.append((st, recs, outs, [r.h for r in recs], [o.data_ptr() for o in outs]))
         ns = [N] * len(bp)
 
         def step(i):
             _, _, _, hs, op = sets[i % len(sets)]
-            rx.rx_process_batch(hs, bp, ns, op, graph=graph)
+            if host:
+                rx.rx_process_batch_host(hs, bp, ns, op, graph=graph)
+            else:
+                rx.rx_process_batch(hs, bp, ns, op, graph=graph)
 
         for i in range(a.warmup * len(sets)):
             step(i)
@@ -200,6 +209,22 @@ def main():
         ber = sum(e["bit_errors"] for e in errs) / bits if bits else None
         ms = sorted(e0.elapsed_time(e1) for e0, e1 in evs)
         return wall, ber, ms, errs
+
+    host_ingest = None
+    if a.host:
+        # the plain chain fed from pinned host memory: each buffer crosses PCIe
+        # in, its bits come back, on the same three streams as the kernels
+        hb = [torch.from_numpy(g["packed"]).pin_memory() for g in gens]
+        hbp = [hb[i % a.distinct].data_ptr() for i in range(a.batch)]
+        wall_h, ber_h, _, _ = time_handles(
+            lambda st: [rx.Receiver(rx.RX_KK_16QAM, gens[i % a.distinct]["seed"], max_samples=N, stream=st)
+                        for i in range(a.batch)], hbp, a.steps, False, host=True)
+        host_ingest = {"workload": f"KK-16QAM plain chain, {a.batch} x 2^22 buffers per batch from pinned host "
+                                   f"memory, bits back to pinned host memory, {len(streams)} streams",
+                       "value": round(a.steps * a.batch * N / wall_h / 1e9, 3), "unit": "Gsamples/s",
+                       "h2d_gb_per_s": round(a.steps * a.batch * N * 1.5 / wall_h / 1e9, 2), "ber": ber_h}
+        log(f"[bench] host ingest {host_ingest}")
+        del hb
 
     mlp_form = None
     if a.mlp:
@@ -329,6 +354,7 @@ def main():
         "forms": forms,
         "mlp_form": mlp_form,
         "mixed_batch": mixed,
+        "host_ingest": host_ingest,
         "stage_us_per_buffer": per_buffer(stages),
         "roofline": roof,
         "one_stream": one,

@@ -154,6 +154,28 @@ int rx_process(rx_handle h, const void *dev_buffer, size_t n_samples, void *dev_
 int rx_process_batch(const rx_handle *hs, const void *const *dev_buffers, const size_t *n_samples,
                      void *const *dev_bits, int count, int graph);
 
+/* Host-resident buffers, as the paper's receiver takes them: the ADC board
+ * writes each buffer into host memory and the host moves it to the GPU
+ * (Fig. 1a; Sec. 2, first paragraph).  Copies host_buffers[i] (n_samples[i]
+ * packed codes, 1.5 * n_samples[i] bytes) into a device staging area of
+ * handle i, runs the batch as rx_process_batch does, and copies the bits
+ * back into host_bits[i] (size as for rx_process); everything is enqueued
+ * on the FIRST handle's stream and the call returns without waiting.  The
+ * host buffers must stay valid, and host_bits must not be read, until that
+ * stream is synchronised (rx_sync or rx_errors).  Pinned host memory
+ * (hipHostMalloc) lets the copies run asynchronously and overlap work on
+ * other streams; pageable memory is accepted but its copies block the
+ * caller.  Each handle's staging area (1.5 * max_samples bytes in, the bits
+ * of max_samples out) is allocated by the library on the handle's first
+ * such call and freed by rx_destroy.  Errors: as rx_process_batch;
+ * RX_E_NOMEM if a staging area cannot be allocated; RX_E_HIP if a copy
+ * cannot be enqueued. */
+int rx_process_batch_host(const rx_handle *hs, const void *const *host_buffers, const size_t *n_samples,
+                          void *const *host_bits, int count, int graph);
+
+/* Wait for all work enqueued on the handle's stream. */
+int rx_sync(rx_handle h);
+
 /* Synchronise the handle's stream and copy the cumulative counters. */
 int rx_errors(rx_handle h, rx_stats *out);
 int rx_errors_reset(rx_handle h);

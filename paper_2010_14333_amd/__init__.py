@@ -27,7 +27,8 @@ RX_PROFILE = 0x2
 STAGES = ("kk_front", "kk_debug", "pam_sum", "pam_mf", "pam_gavg", "pam_unwrap", "pam_farrow",
           "prefix", "blocks", "kk_vv", "decide", "mlp_infer", "mlp_judge")
 RX_MLP_PARAMS = 6273
-EXPORTS = ("rx_params_default", "rx_create", "rx_process", "rx_process_batch", "rx_errors",
+EXPORTS = ("rx_params_default", "rx_create", "rx_process", "rx_process_batch", "rx_process_batch_host",
+           "rx_sync", "rx_errors",
            "rx_errors_reset", "rx_debug_fetch", "rx_train_cfg_default", "rx_mlp_param_count",
            "rx_mlp_order_multiplier", "rx_train_mlp", "rx_train_mlp_data", "rx_mlp_grad", "rx_mlp_infer",
            "rx_set_mlp", "rx_get_mlp", "rx_save_weights", "rx_load_weights", "rx_stage_times",
@@ -79,6 +80,9 @@ def lib() -> ctypes.CDLL:
         L.rx_process.argtypes = [vp, vp, sz, vp, ctypes.POINTER(sz)]
         L.rx_process_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(sz),
                                        ctypes.POINTER(vp), i32, i32]
+        L.rx_process_batch_host.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(sz),
+                                            ctypes.POINTER(vp), i32, i32]
+        L.rx_sync.argtypes = [vp]
         L.rx_errors.argtypes = [vp, ctypes.POINTER(rx_stats)]
         L.rx_errors_reset.argtypes = [vp]
         L.rx_debug_fetch.argtypes = [vp, i32, vp, sz]
@@ -145,6 +149,21 @@ def rx_process_batch(handles, dev_buffers, n_samples, dev_bits, graph: bool = Fa
     N = (ctypes.c_size_t * c)(*n_samples)
     O = (ctypes.c_void_p * c)(*dev_bits)
     return _check(lib().rx_process_batch(H, B, N, O, c, int(graph)), "rx_process_batch")
+
+
+def rx_process_batch_host(handles, host_buffers, n_samples, host_bits, graph: bool = False) -> int:
+    """Host-resident inputs and outputs (addresses of host memory, pinned for
+    asynchronous copies); returns without waiting: call rx_sync first."""
+    c = len(handles)
+    H = (ctypes.c_void_p * c)(*handles)
+    B = (ctypes.c_void_p * c)(*host_buffers)
+    N = (ctypes.c_size_t * c)(*n_samples)
+    O = (ctypes.c_void_p * c)(*host_bits)
+    return _check(lib().rx_process_batch_host(H, B, N, O, c, int(graph)), "rx_process_batch_host")
+
+
+def rx_sync(h: int) -> None:
+    _check(lib().rx_sync(h), "rx_sync")
 
 
 def rx_errors(h: int) -> dict:

@@ -118,6 +118,7 @@ struct rx_ctx {
   GraphCache graph;
   float *mlp = nullptr;   // learned-equaliser parameters (device), allocated with the handle
   bool mlp_ready = false;
+  uint8_t *hin = nullptr, *hbits = nullptr;   // host-ingest staging (device), allocated on first use
   // stage timing (RX_PROFILE): events recorded around every stage launch
   struct Pending { int stage; hipEvent_t a, b; };
   std::vector<Pending> pending;
@@ -550,6 +551,51 @@ int rx_process_batch(const rx_handle *hs, const void *const *bufs, const size_t 
   if (rc == RX_OK)
     for (int i = 0; i < count; i++) hs[i]->last_n = (int64_t)ns[i];
   return rc;
+}
+
+int rx_process_batch_host(const rx_handle *hs, const void *const *host_buffers, const size_t *ns,
+                          void *const *host_bits, int count, int graph) {
+  if (!hs || !host_buffers || !ns || !host_bits || count < 1 || count > RX_MAXB) return RX_E_INVALID;
+  const void *dbufs[RX_MAXB];
+  void *dbits[RX_MAXB];
+  for (int i = 0; i < count; i++) {
+    rx_ctx *h = hs[i];
+    if (!h || !host_buffers[i] || !host_bits[i]) return RX_E_INVALID;
+    if (h->stream != hs[0]->stream) return RX_E_INVALID;
+    for (int j = 0; j < i; j++)
+      if (hs[j] == h) return RX_E_INVALID;
+    const int rc = check_n(h, ns[i]);
+    if (rc) return rc;
+    if (!h->hin) {
+      h->hin = h->mem.get<uint8_t>(h->p.max_samples / 2 * 3);
+      h->hbits = h->mem.get<uint8_t>(h->p.max_samples / h->sps * h->bps / 8);
+      if (!h->hin || !h->hbits) {
+        h->hin = h->hbits = nullptr;
+        return RX_E_NOMEM;
+      }
+    }
+    dbufs[i] = h->hin;
+    dbits[i] = h->hbits;
+  }
+  hipStream_t s = hs[0]->stream;
+  for (int i = 0; i < count; i++) {
+    const hipError_t e = hipMemcpyAsync(hs[i]->hin, host_buffers[i], ns[i] / 2 * 3, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return fail_hip(e, "hipMemcpyAsync (buffer in)");
+  }
+  const int rc = rx_process_batch(hs, dbufs, ns, dbits, count, graph);
+  if (rc) return rc;
+  for (int i = 0; i < count; i++) {
+    const size_t nb = ns[i] / hs[i]->sps * hs[i]->bps / 8;
+    const hipError_t e = hipMemcpyAsync(host_bits[i], hs[i]->hbits, nb, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return fail_hip(e, "hipMemcpyAsync (bits out)");
+  }
+  return RX_OK;
+}
+
+int rx_sync(rx_handle h) {
+  if (!h) return RX_E_INVALID;
+  const hipError_t e = hipStreamSynchronize(h->stream);
+  return e == hipSuccess ? RX_OK : fail_hip(e, "hipStreamSynchronize");
 }
 
 int rx_errors(rx_handle h, rx_stats *out) {
