@@ -106,7 +106,7 @@ __device__ __forceinline__ void apply_twiddles(float2 *v, float2 w1, float2 w2, 
 // Butterfly j reads x[j + r N/R], twiddles by W_{NS R}^{r (j mod NS)}, and
 // writes to (j / NS) NS R + (j mod NS) + r NS.  NS is a compile-time
 // constant so the padded LDS offsets of the 16 accesses fold to immediates.
-template <int N, int R, int NS>
+template <int N, int R, int NS, bool TAIL = true>
 __device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *__restrict__ tw) {
   constexpr int T = N / 16;
   constexpr int NB = (N / R) / T;  // butterflies per thread
@@ -130,7 +130,9 @@ __device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *__restr
 #pragma unroll
     for (int r = 0; r < R; r++) v[b][r] = buf[fpad(j + r * (N / R))];
   }
-  __syncthreads();
+  // in the last pass (NS R = N) a butterfly writes back exactly the indices
+  // it read, so no thread overwrites another's input: no barrier needed
+  if constexpr (NS * R != N) __syncthreads();
 #pragma unroll
   for (int b = 0; b < NB; b++) {
     const int j = threadIdx.x + b * T;
@@ -141,26 +143,30 @@ __device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *__restr
 #pragma unroll
     for (int r = 0; r < R; r++) buf[fpad(base + r * NS)] = v[b][r];
   }
-  __syncthreads();
+  if constexpr (TAIL) __syncthreads();
 }
 
-template <int N, int NS>
+template <int N, int NS, bool TAIL>
 __device__ __forceinline__ void fft_passes(float2 *buf, const float2 *__restrict__ tw) {
-  if constexpr (NS * 16 <= N) {
+  if constexpr (NS * 16 < N) {
     stockham_pass<N, 16, NS>(buf, tw);
-    fft_passes<N, NS * 16>(buf, tw);
+    fft_passes<N, NS * 16, TAIL>(buf, tw);
+  } else if constexpr (NS * 16 == N) {
+    stockham_pass<N, 16, NS, TAIL>(buf, tw);
   } else if constexpr (NS * 8 == N) {
-    stockham_pass<N, 8, NS>(buf, tw);
+    stockham_pass<N, 8, NS, TAIL>(buf, tw);
   } else if constexpr (NS * 4 == N) {
-    stockham_pass<N, 4, NS>(buf, tw);
+    stockham_pass<N, 4, NS, TAIL>(buf, tw);
   } else if constexpr (NS * 2 == N) {
-    stockham_pass<N, 2, NS>(buf, tw);
+    stockham_pass<N, 2, NS, TAIL>(buf, tw);
   }
 }
 
 // Forward FFT of N = 2^LOGN points held in buf (padded layout), natural
-// order in and out.  tw[k] = exp(-j 2 pi k / N).
-template <int LOGN>
+// order in and out.  tw[k] = exp(-j 2 pi k / N).  The last pass writes
+// output k from thread k mod (N / 16); with TAIL = false it ends without a
+// barrier, for a caller whose threads next touch only their own outputs.
+template <int LOGN, bool TAIL = true>
 __device__ __forceinline__ void fft_forward(float2 *buf, const float2 *__restrict__ tw) {
-  fft_passes<(1 << LOGN), 1>(buf, tw);
+  fft_passes<(1 << LOGN), 1, TAIL>(buf, tw);
 }

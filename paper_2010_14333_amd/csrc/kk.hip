@@ -154,7 +154,10 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
 
   // 2. Hilbert filtering: Y = Z H, H = -j S; the inverse transform is done as
   //    conj(FFT(conj(Y)/N)), so the second pass leaves phiA - j phiB.
-  fft_forward<LOGN>(lds, J.twid);
+  // (each thread's Hilbert products and phase reads below are outputs k of
+  // the transforms with k = threadIdx.x mod T, written by this thread: no
+  // barrier after either transform)
+  fft_forward<LOGN, false>(lds, J.twid);
 #pragma unroll 8
   for (int i = 0; i < 16; i++) {   // unrolled: eight spectrum reads in flight together
     const int k = threadIdx.x + i * T;
@@ -167,7 +170,7 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
   // first they would be spilled across the Hilbert product
   const float2 *tw2 = J.twid;
   asm volatile("" : "+s"(tw2));
-  fft_forward<LOGN>(lds, tw2);
+  fft_forward<LOGN, false>(lds, tw2);
 
   constexpr int NPH = PREC == 0 ? 2 : 1;   // frames whose phases stay in registers
   float ph[NPH][QPT], phb[PREC == 0 ? 1 : QPT];
