@@ -243,8 +243,14 @@ __device__ __forceinline__ float mlp_tile(const MlpFrag &f, MNT::vec bx, int kq)
     y = fmaf(w3.z, relu_bits(d[2]), y);
     y = fmaf(w3.w, relu_bits(d[3]), y);
   }
-  y += __shfl_xor(y, 16, 64);
-  y += __shfl_xor(y, 32, 64);
+  // lanes l, l ^ 16, l ^ 32 and l ^ 48 hold the partial sums of one symbol:
+  // exchanging 16-lane rows, then 32-lane halves, and adding adds them all
+  // (the swaps move whole rows, so the sum does not depend on which rows of
+  // the two operands the instruction exchanges; one VALU instruction each)
+  const auto r16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(y), __float_as_uint(y), false, false);
+  y = __uint_as_float(r16[0]) + __uint_as_float(r16[1]);
+  const auto r32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(y), __float_as_uint(y), false, false);
+  y = __uint_as_float(r32[0]) + __uint_as_float(r32[1]);
   return y + f.b3;
 }
 
