@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--mlp", type=int, default=1, help="train and time the PAM-8 learned-equaliser form")
     ap.add_argument("--mixed", type=int, default=1, help="time a 64-buffer mixed-format batch (graph replay)")
     ap.add_argument("--host", type=int, default=1, help="time the plain chain fed from pinned host memory")
+    ap.add_argument("--sweep", type=int, default=0,
+                    help="Q-factor vs SNR of every format through the GPU chain (one 2^22 buffer per point)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the receiver path is "
@@ -226,6 +228,37 @@ def main():
         log(f"[bench] host ingest {host_ingest}")
         del hb
 
+    q_sweep = None
+    if a.sweep:
+        # BER -> Q of each format over an SNR range, one 2^22-sample buffer per
+        # point through the GPU chain; the oracle's BER beside it at one SNR
+        # per format (its decisions, so the same errors up to its rounding)
+        from scipy.special import erfcinv
+        import oracle
+
+        def q_db(ber):
+            return round(20.0 * np.log10(np.sqrt(2.0) * erfcinv(2.0 * ber)), 2) if ber and ber < 0.5 else None
+
+        names = {1: "PAM-2", 2: "PAM-4", 3: "PAM-8", 4: "KK-QPSK", 5: "KK-16QAM"}
+        snrs = [10, 12, 14, 16, 18, 20, 22, 24]
+        q_sweep = {}
+        for fmt in range(1, 6):
+            pts = []
+            for si, snr in enumerate(snrs):
+                g = synth.generate(fmt, N, synth.derive_seed(601, 16 * fmt + si), float(snr))
+                r = rx.Receiver(fmt, g["seed"], max_samples=N)
+                r.process(torch.from_numpy(g["packed"]).to(dev), N)
+                e = r.errors()
+                r.close()
+                ber = e["bit_errors"] / e["bits"] if e["bits"] else None
+                pt = {"snr_db": snr, "ber": ber, "q_db": q_db(ber)}
+                if snr == 16:
+                    o = oracle.process(fmt, g["packed"], N, g["seed"], want=("bits",))
+                    pt["oracle_ber"] = o["bit_errors"] / o["counted_bits"] if o["counted_bits"] else None
+                pts.append(pt)
+            q_sweep[names[fmt]] = pts
+            log(f"[bench] sweep {names[fmt]}: " + ", ".join(f"{p['snr_db']} dB {p['ber']:.2e}" for p in pts))
+
     mlp_form = None
     if a.mlp:
         t0 = time.time()
@@ -355,6 +388,7 @@ def main():
         "mlp_form": mlp_form,
         "mixed_batch": mixed,
         "host_ingest": host_ingest,
+        "q_vs_snr": q_sweep,
         "stage_us_per_buffer": per_buffer(stages),
         "roofline": roof,
         "one_stream": one,
