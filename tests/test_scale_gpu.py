@@ -1,0 +1,73 @@
+"""Full-scale cases through the C ABI: the largest buffer a handle accepts
+(2^26 samples) against the FP64 oracle decision by decision, and a
+64 x 2^22-sample batch in the launch configuration the benchmark times
+(distinct handles, eight distinct buffers round-robin): sampled buffers of the
+batch bit-exact against the same buffers processed alone, one of them against
+the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import parity
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2010_14333_amd as rx
+    rx.lib()
+    return rx
+
+
+def _against_oracle(fmt, g, n, bits, err):
+    o = oracle.process(fmt, g["packed"], n, g["seed"], want=("bits", "soft"))
+    kk = fmt >= 4
+    nsym = n // (4 if kk else 2)
+    nbad, tol_bits, untol = parity.compare_decisions(fmt, bits, o["bits"], o["soft"], nsym, 128 if kk else 256)
+    print(f"[scale]   mismatches {nbad}, tolerated bits {tol_bits}, bit errors {err['bit_errors']} / "
+          f"{o['bit_errors']}", flush=True)
+    assert not untol, untol[:10]
+    assert err["bits"] == o["counted_bits"]
+    assert abs(err["bit_errors"] - o["bit_errors"]) <= tol_bits
+
+
+def test_maximum_buffer_kk16qam(rx):
+    import torch
+    n = 1 << 26
+    print(f"[scale] KK-16QAM n={n}", flush=True)
+    g = synth.generate(5, n, 81, 22.0)
+    r = rx.Receiver(5, g["seed"], max_samples=n)
+    bits = r.process(torch.from_numpy(g["packed"]).to("cuda:0"), n).cpu().numpy()
+    err = r.errors()
+    r.close()
+    assert err["buffers"] == 1 and err["bit_errors"] <= 1e-4 * err["bits"]
+    _against_oracle(5, g, n, bits, err)
+
+
+def test_bench_launch_configuration(rx):
+    import torch
+    n, batch, distinct = 1 << 22, 64, 8
+    print(f"[scale] KK-16QAM batch {batch} x {n}", flush=True)
+    gens = [synth.kk_2e22(synth.KK_16QAM, index=i) for i in range(distinct)]
+    bufs = [torch.from_numpy(g["packed"]).to("cuda:0") for g in gens]
+    recs = [rx.Receiver(5, gens[i % distinct]["seed"], max_samples=n) for i in range(batch)]
+    outs = [torch.zeros(r.bits_bytes(n), dtype=torch.uint8, device="cuda:0") for r in recs]
+    rx.rx_process_batch([r.h for r in recs], [bufs[i % distinct].data_ptr() for i in range(batch)], [n] * batch,
+                        [o.data_ptr() for o in outs])
+    torch.cuda.synchronize()
+    errs = [r.errors() for r in recs]
+    for i in (0, 13, 38, 63):
+        alone = rx.Receiver(5, gens[i % distinct]["seed"], max_samples=n)
+        single = alone.process(bufs[i % distinct], n).cpu().numpy()
+        assert np.array_equal(outs[i].cpu().numpy(), single), f"buffer {i}"
+        assert alone.errors() == errs[i]
+        alone.close()
+    # the same buffer through distinct handles of the batch: identical bits
+    assert np.array_equal(outs[5].cpu().numpy(), outs[5 + distinct].cpu().numpy())
+    _against_oracle(5, gens[0], n, outs[0].cpu().numpy(), errs[0])
+    for r in recs:
+        r.close()
