@@ -276,6 +276,13 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
     // P at this lane's first output of the block, exact from the FP64 phase
     const int64_t mfirst = m0 + 16 * (8 * wv + 2 * kq) + row;
     float2 pp = cis_rev(downshift_rev(J.r, 2 * mfirst));
+    // outputs are handled by their offset mr = m - m0 < HOP / 2 in the block:
+    // valid (2 m < n) below mlim, interior (m >= 16, 2 m + 32 < n) in
+    // [mil, mih); n is even, so both limits are exact integers
+    const int mlim = (int)clamp64(n / 2 - m0, 0, HOP / 2);
+    const int mil = (int)clamp64(16 - m0, 0, HOP / 2);
+    const int mih = (int)clamp64((n - 32) / 2 - m0, 0, HOP / 2);
+    float2 *const zb = J.z + m0;
     for (int grp = wv; grp < NG; grp += NW) {
       const int tile = grp * 8 + (row >> 1);
       rx_f32x4 acc;
@@ -284,17 +291,17 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
 #pragma unroll
       for (int jj = 0; jj < 2; jj++) {
         const int t2 = grp * 8 + 2 * kq + jj;
-        const int64_t m = m0 + 16 * t2 + row;
+        const int mr = 16 * t2 + row;
         const float2 p = jj ? cmul(pp, r16) : pp;
-        if (t2 < NTILE && 2 * m < n) {
+        if (t2 < NTILE && mr < mlim) {
           const float2 zv = make_float2(acc[2 * jj], acc[2 * jj + 1]);
-          J.z[m] = zv;
+          gstore(zb, mr, zv);
           zz = fmaf(zv.x, zv.x, fmaf(zv.y, zv.y, zz));
-          if (kk_interior(m, n)) {
+          if (mr >= mil && mr < mih) {
             sp = cadd(sp, cmul(zv, p));
             nint++;
           } else {
-            const float2 te = kk_carrier_edge_inl(J.mf, J.r, m, n);
+            const float2 te = kk_carrier_edge_inl(J.mf, J.r, m0 + mr, n);
             sedge = cadd(sedge, cmulc(zv, te));
             tedge = fmaf(te.x, te.x, fmaf(te.y, te.y, tedge));
           }
