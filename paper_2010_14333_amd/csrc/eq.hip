@@ -225,10 +225,11 @@ __global__ __launch_bounds__(256) void rx_prefix(RxLaunch L) {
 // outputs.  Half the taps and half the window per lane keep the kernel at
 // four wavefronts per SIMD.  Block streams are 2*blk samples apart, so they
 // are staged through LDS in chunks of BC steps: the workgroup loads every
-// block's next 2*BC samples with coalesced reads, each lane runs BC steps
-// from registers, and the soft outputs go back out the same way.
-// Four wavefronts per SIMD.  (Five, with 4-step chunks, is faster alone
-// but slows the chain: its workgroups keep the front end off more CUs.)
+// block's next 2*BC samples with coalesced reads (all issued before any is
+// used), each lane runs BC steps from registers, and the soft outputs go
+// back out the same way.  (Five wavefronts per SIMD, with 4-step chunks, is
+// faster alone but slows the chain: its workgroups keep the front end off
+// more CUs.)
 template <bool CPLX, int K>
 __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
   constexpr int BC = 8;   // steps per staged chunk (16 measured no faster on the real chain)
@@ -435,9 +436,9 @@ __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
 // 16 symbols (x = AGC'd 2-sps samples from 2(k0+s)-C), B = [[Wr, Wi],
 // [-Wi, Wr]] with W[t][q] = w0[2C + 2q - t]; 4 K-steps x 2 column tiles.
 // A group is 16 tiles (256 symbols = two VV blocks), whose z^4 sums the
-// wavefront also forms; each wavefront takes FFE_GPW consecutive groups, so
-// the B fragments are built once per 2048 symbols and the next group's
-// window is in flight while the current one is filtered.
+// wavefront also forms; each wavefront takes FFE_GPW consecutive groups
+// (the next group's window in flight while the current one is filtered),
+// and the B fragments are built once per workgroup, in LDS.
 #define FFE_GPW 8
 #define FFE_PL 672   // staged plane length: window positions 0..543 with 8 elements of padding per 32
 // LDS index of window position t: the 16-byte A reads of the 16 rows then

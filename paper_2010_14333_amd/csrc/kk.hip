@@ -97,7 +97,7 @@ template <int PREC> struct MfB {
 };
 
 template <int LOGN, int PREC>
-__global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  // 4 waves/SIMD: two 2^13 workgroups share a CU
+__global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  // 4 waves/SIMD: one 2^14 or two 2^13 workgroups per CU
   constexpr int N = 1 << LOGN, T = N / 16;
   constexpr int HOP = (N - RX_KK_HALFV - RX_KK_EDGE - RX_KK_CMF) & ~15;
   constexpr int QN = HOP + 2 * RX_KK_CMF;   // y' samples each block needs
