@@ -75,8 +75,8 @@ def main():
                     help="Q-factor vs SNR of every format through the GPU chain (one 2^22 buffer per point)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the receiver path is "
-              "single-GPU in this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {a.gpus}): buffers are independent units, "
+              "so N GPUs would each run this single-GPU path on their share", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
