@@ -31,6 +31,25 @@ __global__ __launch_bounds__(256) void pam_sum(RxLaunch L) {
   if (threadIdx.x == 0) J.upart[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
+// The buffer mean of v = code + 0.5 from the code-sum partials, once per
+// buffer (exact integer sum, FP64 division).
+__global__ __launch_bounds__(256) void pam_mean(RxLaunch L) {
+  __shared__ unsigned long long rs[4];
+  const int jb = blockIdx.y;
+  const RxJob J = *L.job[jb];
+  const int64_t n = L.n[jb];
+  const int64_t np = (n + PAM_SUMW - 1) / PAM_SUMW;
+  unsigned long long s = 0;
+  for (int64_t i = threadIdx.x; i < np; i += 256) s += J.upart[i];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) rs[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    J.sc->mean_re = (double)(rs[0] + rs[1] + rs[2] + rs[3]) / (double)n + 0.5;
+    J.sc->mean_im = 0.0;
+  }
+}
+
 __device__ __forceinline__ int xpad(int i) { return i + (i >> 4); }
 
 // x0 = v - mean(v); y = MF(x0) (33 taps, centred, zero outside); partial
@@ -42,31 +61,12 @@ __global__ __launch_bounds__(256) void pam_mf(RxLaunch L) {
   __shared__ float xs[XN + XN / 16 + 1];
   __shared__ float ys[YN];
   __shared__ double red[4];
-  __shared__ double mean_s;
   const int jb = blockIdx.y;
   const RxJob J = *L.job[jb];
   const int64_t n = L.n[jb];
   const uint8_t *in = L.in[jb];
   if ((int64_t)blockIdx.x * PAM_MF_SUB * PAM_TS >= n) return;
-  {
-    const int64_t np = (n + PAM_SUMW - 1) / PAM_SUMW;
-    unsigned long long s = 0;
-    for (int64_t i = threadIdx.x; i < np; i += 256) s += J.upart[i];
-    s = wave_sum(s);
-    __shared__ unsigned long long rs[4];
-    if ((threadIdx.x & 63) == 0) rs[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const unsigned long long tot = rs[0] + rs[1] + rs[2] + rs[3];
-      mean_s = (double)tot / (double)n + 0.5;
-      if (blockIdx.x == 0) {   // the workgroup of tile 0
-        J.sc->mean_re = mean_s;
-        J.sc->mean_im = 0.0;
-      }
-    }
-    __syncthreads();
-  }
-  const double mv = mean_s;
+  const double mv = J.sc->mean_re;   // from pam_mean
   for (int sub = 0; sub < PAM_MF_SUB; sub++) {
     const int64_t tile = (int64_t)blockIdx.x * PAM_MF_SUB + sub;
     const int64_t t0 = tile * PAM_TS;
@@ -260,6 +260,7 @@ void rx_launch_pam_stage(int stage, const RxLaunch &L, int64_t maxn, hipStream_t
   switch (stage) {
     case ST_PAM_SUM:
       hipLaunchKernelGGL(pam_sum, dim3((unsigned)((maxn + PAM_SUMW - 1) / PAM_SUMW), cnt), dim3(256), 0, s, L);
+      hipLaunchKernelGGL(pam_mean, dim3(1, cnt), dim3(256), 0, s, L);
       break;
     case ST_PAM_MF:
       hipLaunchKernelGGL(pam_mf, dim3((unsigned)((maxn + PAM_MF_SUB * PAM_TS - 1) / (PAM_MF_SUB * PAM_TS)), cnt),
