@@ -66,19 +66,41 @@ __global__ __launch_bounds__(256) void pam_mf(RxLaunch L) {
   const int64_t n = L.n[jb];
   const uint8_t *in = L.in[jb];
   if ((int64_t)blockIdx.x * PAM_MF_SUB * PAM_TS >= n) return;
+  float hmf[33];   // the taps, read at the start (uniform: scalar registers)
+#pragma unroll
+  for (int i = 0; i < 33; i++) hmf[i] = J.mf[i];
   const double mv = J.sc->mean_re;   // from pam_mean
+  constexpr int NGR = (PAM_TS + 48) / 8, GPT = (NGR + 255) / 256;   // code groups per tile and thread
+  const int64_t gmax = n / 8 - 1;
   for (int sub = 0; sub < PAM_MF_SUB; sub++) {
     const int64_t tile = (int64_t)blockIdx.x * PAM_MF_SUB + sub;
     const int64_t t0 = tile * PAM_TS;
     if (t0 >= n) break;
     __syncthreads();   // the previous tile's readers of xs and ys are done
     // codes of [t0 - 24, t0 + TS + 24) in aligned groups of eight (t0 is a
-    // multiple of 8); xs[i] holds sample t0 - 20 + i
-    for (int g = threadIdx.x; g < (PAM_TS + 48) / 8; g += 256) {
+    // multiple of 8); xs[i] holds sample t0 - 20 + i.  Every group read is
+    // issued first (group index clamped into the buffer); groups past a
+    // buffer edge are re-read sample by sample.
+    uint32_t raw[GPT][3];
+#pragma unroll
+    for (int gi = 0; gi < GPT; gi++) {
+      const int g = threadIdx.x + 256 * gi;
+      if (g < NGR) {
+        const int64_t gg = (t0 - 24) / 8 + g;
+        const uint32_t *p = reinterpret_cast<const uint32_t *>(in + 12 * (gg < 0 ? 0 : (gg > gmax ? gmax : gg)));
+        raw[gi][0] = p[0];
+        raw[gi][1] = p[1];
+        raw[gi][2] = p[2];
+      }
+    }
+#pragma unroll
+    for (int gi = 0; gi < GPT; gi++) {
+      const int g = threadIdx.x + 256 * gi;
+      if (g >= NGR) break;
       const int64_t s0 = t0 - 24 + 8 * g;
       int c[8];
       if (s0 >= 0 && s0 + 8 <= n) {
-        read_codes8(in, s0 >> 3, c);
+        unpack_codes8(raw[gi][0], raw[gi][1], raw[gi][2], c);
       } else {
 #pragma unroll
         for (int e = 0; e < 8; e++) c[e] = (s0 + e >= 0 && s0 + e < n) ? read_code(in, s0 + e) : -1;
@@ -105,7 +127,7 @@ __global__ __launch_bounds__(256) void pam_mf(RxLaunch L) {
 #pragma unroll
         for (int o = 0; o < 16; o++) {
           const int tap = o + 32 - d;
-          if (tap >= 0 && tap <= 32) acc[o] = fmaf(J.mf[tap], v, acc[o]);
+          if (tap >= 0 && tap <= 32) acc[o] = fmaf(hmf[tap], v, acc[o]);
         }
       }
       float q2 = 0.0f;   // 16 squares in FP32, then one FP64 add
@@ -122,7 +144,8 @@ __global__ __launch_bounds__(256) void pam_mf(RxLaunch L) {
       const int l = threadIdx.x < 4 ? (int)threadIdx.x - 4 : PAM_TS + (int)threadIdx.x - 4;
       const int64_t t = t0 + l;
       float a = 0.0f;
-      for (int i = 0; i < 33; i++) a = fmaf(J.mf[i], xs[xpad(l + 36 - i)], a);
+#pragma unroll
+      for (int i = 0; i < 33; i++) a = fmaf(hmf[i], xs[xpad(l + 36 - i)], a);
       ys[l + 4] = (t >= 0 && t < n) ? a : 0.0f;
     }
     p2 = block_sum(p2, red);   // (its barriers also publish ys)

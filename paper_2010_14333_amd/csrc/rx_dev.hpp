@@ -174,10 +174,9 @@ __device__ __forceinline__ int read_code(const uint8_t *in, int64_t i) {
   return (v >> ((int)(i & 1) << 2)) & 0xFFF;
 }
 
-// Eight codes of samples 8g .. 8g+7 from three aligned 32-bit words.
-__device__ __forceinline__ void read_codes8(const uint8_t *in, int64_t g, int c[8]) {
-  const uint32_t *p = reinterpret_cast<const uint32_t *>(in + 12 * g);
-  const uint32_t w0 = p[0], w1 = p[1], w2 = p[2];
+// Eight codes of samples 8g .. 8g+7 from the three aligned 32-bit words
+// that hold them.
+__device__ __forceinline__ void unpack_codes8(uint32_t w0, uint32_t w1, uint32_t w2, int c[8]) {
   c[0] = w0 & 0xFFF;
   c[1] = (w0 >> 12) & 0xFFF;
   c[2] = (w0 >> 24) | ((w1 & 0xF) << 8);
@@ -186,6 +185,10 @@ __device__ __forceinline__ void read_codes8(const uint8_t *in, int64_t g, int c[
   c[5] = (w1 >> 28) | ((w2 & 0xFF) << 4);
   c[6] = (w2 >> 8) & 0xFFF;
   c[7] = w2 >> 20;
+}
+__device__ __forceinline__ void read_codes8(const uint8_t *in, int64_t g, int c[8]) {
+  const uint32_t *p = reinterpret_cast<const uint32_t *>(in + 12 * g);
+  unpack_codes8(p[0], p[1], p[2], c);
 }
 
 // exp(-j 2 pi frac(r n)) with the phase accumulator in FP64.
