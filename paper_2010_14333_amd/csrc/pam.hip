@@ -251,29 +251,59 @@ __global__ __launch_bounds__(256) void pam_farrow(RxLaunch L) {
   const auto dl = gptr(J.delta) + base / 512;
   const int span = (int)(n - base < FAR_SPAN ? n - base : FAR_SPAN);   // multiple of 1024
   const int lo = (int)(base < 4 ? -base : -4), hi = (int)(n - base < FAR_SPAN + 4 ? n - base : FAR_SPAN + 4);
-  for (int o2 = 0; 512 * o2 < span; o2++) {   // block o2 of the span: passes 2 o2, 2 o2 + 1
-    const float d = dl[o2];
+  constexpr int NB = FAR_SPAN / 512;   // timing blocks per span
+  const int nblk = span / 512;
+  float dv[NB];   // every block's offset first (uniform values)
+#pragma unroll
+  for (int k = 0; k < NB; k++) dv[k] = k < nblk ? dl[k] : 0.0f;
+  // block o2: its four taps i0 - 1 .. i0 + 2 of both passes, when the whole
+  // block's taps lie inside the buffer (relative to base: [lo, hi)); the
+  // next block's reads are issued before the current block is finished
+  auto fetch = [&](int o2, float (&yv)[2][4]) {
+    const int sh = (int)floorf(dv[o2]);
+    const bool inside = 512 * o2 + sh - 1 >= lo && 512 * o2 + 511 + sh + 2 < hi;
+    if (inside) {
+#pragma unroll
+      for (int h = 0; h < 2; h++) {
+        const int i0 = 512 * o2 + 256 * h + threadIdx.x + sh;
+#pragma unroll
+        for (int k = 0; k < 4; k++) yv[h][k] = y[i0 - 1 + k];
+      }
+    }
+    return inside;
+  };
+  float ya[2][4], yb[2][4];
+  bool ina = fetch(0, ya);
+#pragma unroll
+  for (int o2 = 0; o2 < NB; o2++) {   // block o2 of the span: passes 2 o2, 2 o2 + 1
+    if (o2 >= nblk) break;
+    bool inb = false;
+    if (o2 + 1 < nblk) inb = fetch(o2 + 1, yb);
+    const float d = dv[o2];
     const float fl = floorf(d), mu = d - fl;
     const int sh = (int)fl;
     const float lm1 = -mu * (mu - 1.0f) * (mu - 2.0f) * (1.0f / 6.0f);
     const float l0 = (mu + 1.0f) * (mu - 1.0f) * (mu - 2.0f) * 0.5f;
     const float l1 = -(mu + 1.0f) * mu * (mu - 2.0f) * 0.5f;
     const float l2 = (mu + 1.0f) * mu * (mu - 1.0f) * (1.0f / 6.0f);
-    // taps i0 - 1 .. i0 + 2 of the whole block inside the buffer, relative to base: [lo, hi)
-    const bool inside = 512 * o2 + sh - 1 >= lo && 512 * o2 + 511 + sh + 2 < hi;
 #pragma unroll
     for (int h = 0; h < 2; h++) {
       const int t = 512 * o2 + 256 * h + threadIdx.x;
       const int i0 = t + sh;
       float v;
-      if (inside) {
-        v = lm1 * y[i0 - 1] + l0 * y[i0] + l1 * y[i0 + 1] + l2 * y[i0 + 2];
+      if (ina) {
+        v = lm1 * ya[h][0] + l0 * ya[h][1] + l1 * ya[h][2] + l2 * ya[h][3];
       } else {
         auto yat = [&](int j) { return (base + j >= 0 && base + j < n) ? y[j] : 0.0f; };
         v = lm1 * yat(i0 - 1) + l0 * yat(i0) + l1 * yat(i0 + 1) + l2 * yat(i0 + 2);
       }
       xr[t] = g * v;
     }
+#pragma unroll
+    for (int h = 0; h < 2; h++)
+#pragma unroll
+      for (int k = 0; k < 4; k++) ya[h][k] = yb[h][k];
+    ina = inb;
   }
 }
 
