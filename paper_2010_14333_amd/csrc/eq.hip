@@ -43,19 +43,23 @@ struct PfxLane {
 #define PFX_OFF (2 * RX_LAG + RX_KMAX / 2)
 #define PFX_UL (2 * RX_PREFIX_MAX + 2 * RX_LAG + 2 * PFX_OFF)
 
-// Prefix stage, one workgroup (4 wavefronts) per buffer.
+#define PFX_T 1024
+// Prefix stage, one workgroup per buffer.  The serial loops run on one
+// wavefront; the workgroup holds a CU anyway (its LDS), so it brings
+// PFX_T / 64 wavefronts to the parallel parts (AGC sums, the sample window,
+// the candidate-delay outputs and correlations), which are latency-bound.
 //  KK : CMA over the prefix (centre-tap start), static Viterbi-Viterbi phase
 //       of the last 2048 CMA outputs, taps rotated and scaled to odd-integer
 //       units;
 //  both: delay search over [-64, 64] symbols on the known prefix (KK also
 //       picks the quadrant), then data-aided LMS over the prefix -> w0.
-__global__ __launch_bounds__(256) void rx_prefix(RxLaunch L) {
+__global__ __launch_bounds__(PFX_T) void rx_prefix(RxLaunch L) {
   __shared__ float2 u[PFX_UL];
   __shared__ float2 zp[RX_PREFIX_MAX + 2 * RX_LAG];
   __shared__ float2 ar[RX_PREFIX_MAX];
   __shared__ float2 cs[2 * RX_LAG + 1];
   __shared__ float2 w[RX_KMAX];
-  __shared__ double red[4];
+  __shared__ double red[PFX_T / 64];
   __shared__ int sel[2];
   __shared__ float th0s;
 
@@ -74,7 +78,7 @@ __global__ __launch_bounds__(256) void rx_prefix(RxLaunch L) {
   if (kk) {
     const int64_t npairs = ((n + J.hop - 1) / J.hop + 1) / 2;
     double v[6] = {0, 0, 0, 0, 0, 0};
-    for (int64_t i = threadIdx.x; i < npairs; i += 256) {
+    for (int64_t i = threadIdx.x; i < npairs; i += PFX_T) {
       const double2 a = J.part[3 * i], b = J.part[3 * i + 1], c2 = J.part[3 * i + 2];
       v[0] += a.x; v[1] += a.y; v[2] += b.x; v[3] += b.y; v[4] += c2.x; v[5] += c2.y;
     }
@@ -93,13 +97,13 @@ __global__ __launch_bounds__(256) void rx_prefix(RxLaunch L) {
   const auto zin = gview(J.z);
   const auto xin = gptr(J.xr);
 #pragma unroll 8
-  for (int idx = threadIdx.x; idx < PFX_UL; idx += 256) {
+  for (int idx = threadIdx.x; idx < PFX_UL; idx += PFX_T) {
     const int64_t j = (int64_t)idx - PFX_OFF;
     float2 v = make_float2(0.0f, 0.0f);
     if (j >= 0 && j < nx) v = kk ? kk_sample(J, zin, j, n, mean, g) : make_float2(xin[j], 0.0f);
     u[idx] = v;
   }
-  for (int k = threadIdx.x; k < P; k += 256) ar[k] = ref_symbol(J, k);
+  for (int k = threadIdx.x; k < P; k += PFX_T) ar[k] = ref_symbol(J, k);
   __syncthreads();
 
   const int tap = lane & 31;
@@ -145,7 +149,7 @@ __global__ __launch_bounds__(256) void rx_prefix(RxLaunch L) {
   __syncthreads();
 
   // FFE outputs with the start taps for every candidate delay
-  for (int jj = threadIdx.x; jj < P + 2 * RX_LAG; jj += 256) {
+  for (int jj = threadIdx.x; jj < P + 2 * RX_LAG; jj += PFX_T) {
     const int j = jj - RX_LAG;
     float2 z = make_float2(0.0f, 0.0f);
     for (int i = 0; i < K; i++) z = cadd(z, cmul(w[i], u[PFX_OFF + 2 * j + c - i]));
@@ -154,7 +158,7 @@ __global__ __launch_bounds__(256) void rx_prefix(RxLaunch L) {
   __syncthreads();
   // correlation with the known prefix, candidates in preference order
   // s = 0, -1, 1, -2, 2, ...
-  for (int t = wv; t <= 2 * RX_LAG; t += 4) {
+  for (int t = wv; t <= 2 * RX_LAG; t += PFX_T / 64) {
     const int s = (t == 0) ? 0 : ((t & 1) ? -((t + 1) / 2) : t / 2);
     float cr = 0.0f, ci = 0.0f;
     for (int k = lane; k < P; k += 64) {
@@ -675,7 +679,7 @@ void rx_launch_eq_stage(int stage, const RxLaunch &L, int64_t maxn, int kk, int 
   const unsigned cnt = (unsigned)L.count;
   const int64_t nsym = maxn / (kk ? 4 : 2);
   if (stage == ST_PREFIX) {
-    hipLaunchKernelGGL(rx_prefix, dim3(1, cnt), dim3(256), 0, s, L);
+    hipLaunchKernelGGL(rx_prefix, dim3(1, cnt), dim3(PFX_T), 0, s, L);
   } else if (stage == ST_BLOCKS && kk && prec != 0) {
     const int64_t ngrp = (nsym + 255) / 256;
     dim3 gf((unsigned)((ngrp + 4 * FFE_GPW - 1) / (4 * FFE_GPW)), cnt);   // four wavefronts per workgroup
