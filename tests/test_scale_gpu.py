@@ -71,3 +71,28 @@ def test_bench_launch_configuration(rx):
     _against_oracle(5, gens[0], n, outs[0].cpu().numpy(), errs[0])
     for r in recs:
         r.close()
+
+
+def test_every_format_full_size_in_one_batch(rx):
+    """One 2^22-sample buffer of each format, each twice, in one batched
+    launch: every buffer against the oracle, the two copies bit-exact."""
+    import torch
+    n = 1 << 22
+    fmts = [1, 2, 3, 4, 5]
+    print(f"[scale] mixed formats {fmts}, n={n}", flush=True)
+    gens = [synth.generate(f, n, 950 + f, 18.0 + f) for f in fmts]
+    bufs = [torch.from_numpy(g["packed"]).to("cuda:0") for g in gens]
+    order = list(range(len(fmts))) * 2
+    recs = [rx.Receiver(fmts[i], gens[i]["seed"], max_samples=n) for i in order]
+    outs = [torch.zeros(r.bits_bytes(n), dtype=torch.uint8, device="cuda:0") for r in recs]
+    rx.rx_process_batch([r.h for r in recs], [bufs[i].data_ptr() for i in order], [n] * len(order),
+                        [o.data_ptr() for o in outs])
+    torch.cuda.synchronize()
+    errs = [r.errors() for r in recs]
+    for j, i in enumerate(order[:len(fmts)]):
+        k = j + len(fmts)
+        assert np.array_equal(outs[j].cpu().numpy(), outs[k].cpu().numpy()) and errs[j] == errs[k]
+        print(f"[scale] format {fmts[i]}", flush=True)
+        _against_oracle(fmts[i], gens[i], n, outs[j].cpu().numpy(), errs[j])
+    for r in recs:
+        r.close()
