@@ -31,6 +31,14 @@ __device__ __forceinline__ void frame_codes8(const uint8_t *in, int64_t n, int64
   }
 }
 
+// A value that is the same in every lane, moved into scalar registers: kept
+// in vector registers it would be recomputed at each use once the
+// transforms have taken the register file.
+__device__ __forceinline__ float2 uniform2(float2 v) {
+  return make_float2(__builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v.x))),
+                     __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v.y))));
+}
+
 // LDS layout of the downshifted field y' for the matched filter.
 //  PREC 0: two planes of floats, re at [0, YPL) and im at [YPL, 2 YPL), no
 //    padding: a lane reads 24 consecutive window samples of one component
@@ -174,14 +182,17 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
 
   constexpr int NPH = PREC == 0 ? 2 : 1;   // frames whose phases stay in registers
   float ph[NPH][QPT], phb[PREC == 0 ? 1 : QPT];
+  // phase in revolutions: sgn phi / (2 pi); sgn = +-1, so one product by
+  // sgn / (2 pi) is exact against the two
+  const float sgnrev = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, J.sgn * INV2PI)));
 #pragma unroll
   for (int i = 0; i < QPT; i++) {
     const int q = threadIdx.x + i * T;
     if (q < QN) {
       const float2 v = lds[fpad(q + RX_KK_EDGE - RX_KK_CMF)];
-      ph[0][i] = v.x * J.sgn * INV2PI;
-      if constexpr (PREC == 0) ph[NPH - 1][i] = -v.y * J.sgn * INV2PI;
-      else phb[i] = -v.y * J.sgn * INV2PI;
+      ph[0][i] = v.x * sgnrev;
+      if constexpr (PREC == 0) ph[NPH - 1][i] = -v.y * sgnrev;
+      else phb[i] = -v.y * sgnrev;
     }
   }
   __syncthreads();
@@ -207,9 +218,9 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
   constexpr int NW = T / 64;
   // rotations of P between this lane's outputs: +16 (second tile) and
   // +16 * 8 * NW (next pass)
-  const float2 r16 = cis_rev(downshift_rev(J.r, 2 * 16));
-  const float2 rpass = cis_rev(downshift_rev(J.r, 2 * 16 * 8 * NW));
-  const float2 drot = cis_rev(-downshift_rev(J.r, T));   // downshift phasor step over T samples
+  const float2 r16 = uniform2(cis_rev(downshift_rev(J.r, 2 * 16)));
+  const float2 rpass = uniform2(cis_rev(downshift_rev(J.r, 2 * 16 * 8 * NW)));
+  const float2 drot = uniform2(cis_rev(-downshift_rev(J.r, T)));   // downshift phasor step over T samples
 #pragma unroll
   for (int x = 0; x < 2; x++) {
     // 3. field, carrier mean partials, downshifted field y' = E D into LDS.
@@ -245,7 +256,9 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
           float phv;
           if constexpr (PREC == 0) phv = ph[x][i];
           else phv = x == 0 ? ph[0][i] : stash[q];
-          const float2 ev = cscale(cis_rev(phv), sqrtf((float)c + 0.5f));
+          // sqrt(v): v in [0.5, 4095.5], so the hardware square root (1 ulp)
+          // needs none of the denormal or rounding fix-ups of sqrtf
+          const float2 ev = cscale(cis_rev(phv), __builtin_amdgcn_sqrtf((float)c + 0.5f));
           yv = cmul(ev, dph);
           if (q >= RX_KK_CMF && q < RX_KK_CMF + HOP) {
             se_re += ev.x;
