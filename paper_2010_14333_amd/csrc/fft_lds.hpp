@@ -140,8 +140,13 @@ __device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *__restr
     if constexpr (NS > 1) apply_twiddles<R, 1>(v[b], tw1[b], tw2[b], tw4[b], tw8[b]);
     dft_r<R>(v[b]);
     const int base = (j / NS) * NS * R + k;
+    // fpad(base + r NS) = fpad(base) + fpad(r NS): either NS is a multiple of
+    // 16, or NS = 1 and base is (R = 16), so base mod 16 + r NS mod 16 < 16;
+    // the second term is a constant, folded into the store's offset
+    static_assert(NS % 16 == 0 || (NS == 1 && R == 16), "padded write offsets split");
+    const int pb = fpad(base);
 #pragma unroll
-    for (int r = 0; r < R; r++) buf[fpad(base + r * NS)] = v[b][r];
+    for (int r = 0; r < R; r++) buf[pb + fpad(r * NS)] = v[b][r];
   }
   if constexpr (TAIL) __syncthreads();
 }

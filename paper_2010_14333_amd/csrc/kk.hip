@@ -144,9 +144,13 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
 
   // 1. l - l_ref for both frames (l_ref: the frame's centre sample; the
   //    Hilbert response is zero at DC, so any offset leaves phi unchanged and
-  //    a small one keeps the FP32 transform accurate).
-  const float off0 = 0.5f * __logf((float)read_code(in, clamp64(F[0] + N / 2, 0, n - 1)) + 0.5f);
-  const float off1 = 0.5f * __logf((float)read_code(in, clamp64(F[1] + N / 2, 0, n - 1)) + 0.5f);
+  //    a small one keeps the FP32 transform accurate).  l = ln(sqrt(v)) =
+  //    (ln 2 / 2) log2(v) with v = code + 0.5 in [0.5, 4095.5], so the
+  //    hardware log2 (1 ulp) needs none of the denormal handling of logf, and
+  //    l - l_ref = (ln 2 / 2)(log2 v - log2 v_ref).
+  constexpr float HLN2 = 0.34657359027997264f;   // ln(2) / 2
+  const float lr0 = __builtin_amdgcn_logf((float)read_code(in, clamp64(F[0] + N / 2, 0, n - 1)) + 0.5f);
+  const float lr1 = __builtin_amdgcn_logf((float)read_code(in, clamp64(F[1] + N / 2, 0, n - 1)) + 0.5f);
 #pragma unroll
   for (int gi = 0; gi < N / 8 / T; gi++) {
     const int g = threadIdx.x + gi * T;
@@ -155,8 +159,8 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
     frame_codes8(in, n, F[1] + 8 * g, cb);
 #pragma unroll
     for (int e = 0; e < 8; e++)
-      lds[fpad(8 * g + e)] = make_float2(0.5f * __logf((float)ca[e] + 0.5f) - off0,
-                                         0.5f * __logf((float)cb[e] + 0.5f) - off1);
+      lds[fpad(8 * g + e)] = make_float2(HLN2 * (__builtin_amdgcn_logf((float)ca[e] + 0.5f) - lr0),
+                                         HLN2 * (__builtin_amdgcn_logf((float)cb[e] + 0.5f) - lr1));
   }
   __syncthreads();
 
