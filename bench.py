@@ -72,7 +72,8 @@ def main():
     ap.add_argument("--mixed", type=int, default=1, help="time a 64-buffer mixed-format batch (graph replay)")
     ap.add_argument("--host", type=int, default=1, help="time the plain chain fed from pinned host memory")
     ap.add_argument("--sweep", type=int, default=0,
-                    help="Q-factor vs SNR of every format through the GPU chain (one 2^22 buffer per point)")
+                    help="Q-factor sweeps through the GPU chain, one 2^22 buffer per point: 1 = vs electrical "
+                         "SNR for every format, 2 = vs OSNR for the paper's link variants, 3 = both")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {a.gpus}): buffers are independent units, "
@@ -228,8 +229,8 @@ def main():
         log(f"[bench] host ingest {host_ingest}")
         del hb
 
-    q_sweep = None
-    if a.sweep:
+    q_sweep = q_osnr = None
+    if a.sweep & 1:
         # BER -> Q of each format over an SNR range, one 2^22-sample buffer per
         # point through the GPU chain; the oracle's BER beside it at one SNR
         # per format (its decisions, so the same errors up to its rounding)
@@ -258,6 +259,42 @@ def main():
                 pts.append(pt)
             q_sweep[names[fmt]] = pts
             log(f"[bench] sweep {names[fmt]}: " + ", ".join(f"{p['snr_db']} dB {p['ber']:.2e}" for p in pts))
+    if a.sweep & 2:
+        # Q vs OSNR with the paper's own link parameters: optical noise (ASE)
+        # before detection and no electrical noise; RRC roll-off 0.01 for the
+        # KK formats at CSPR 11 and 6 dB, 0.5 for PAM; the receiver's matched
+        # filter designed for the same roll-off; the oracle's BER at the
+        # middle point of each curve
+        from scipy.special import erfcinv
+        import oracle
+
+        def q_db2(ber):
+            return round(20.0 * np.log10(np.sqrt(2.0) * erfcinv(2.0 * ber)), 2) if ber and ber < 0.5 else None
+
+        curves = [("KK-16QAM, CSPR 11 dB, RRC 0.01", 5, {"rolloff": 0.01, "cspr_db": 11.0}, range(14, 27, 2)),
+                  ("KK-16QAM, CSPR 6 dB, RRC 0.01", 5, {"rolloff": 0.01, "cspr_db": 6.0}, range(14, 27, 2)),
+                  ("KK-QPSK, CSPR 11 dB, RRC 0.01", 4, {"rolloff": 0.01, "cspr_db": 11.0}, range(4, 15, 2)),
+                  ("KK-QPSK, CSPR 6 dB, RRC 0.01", 4, {"rolloff": 0.01, "cspr_db": 6.0}, range(4, 15, 2)),
+                  ("PAM-4, RRC 0.5", 2, {"rolloff": 0.5}, range(10, 21, 2)),
+                  ("PAM-8, RRC 0.5", 3, {"rolloff": 0.5}, range(16, 29, 2))]
+        q_osnr = {}
+        for ci, (name, fmt, gen, osnrs) in enumerate(curves):
+            osnrs = list(osnrs)
+            pts = []
+            for si, osnr in enumerate(osnrs):
+                g = synth.generate(fmt, N, synth.derive_seed(701, 16 * ci + si), None, osnr_db=float(osnr), **gen)
+                r = rx.Receiver(fmt, g["seed"], max_samples=N, rolloff=gen["rolloff"])
+                r.process(torch.from_numpy(g["packed"]).to(dev), N)
+                e = r.errors()
+                r.close()
+                ber = e["bit_errors"] / e["bits"] if e["bits"] else None
+                pt = {"osnr_db": osnr, "ber": ber, "q_db": q_db2(ber)}
+                if si == len(osnrs) // 2:
+                    o = oracle.process(fmt, g["packed"], N, g["seed"], want=("bits",), rolloff=gen["rolloff"])
+                    pt["oracle_ber"] = o["bit_errors"] / o["counted_bits"] if o["counted_bits"] else None
+                pts.append(pt)
+            q_osnr[name] = pts
+            log(f"[bench] osnr sweep {name}: " + ", ".join(f"{p['osnr_db']} dB {p['ber']:.2e}" for p in pts))
 
     mlp_form = None
     if a.mlp:
@@ -389,6 +426,7 @@ def main():
         "mixed_batch": mixed,
         "host_ingest": host_ingest,
         "q_vs_snr": q_sweep,
+        "q_vs_osnr": q_osnr,
         "stage_us_per_buffer": per_buffer(stages),
         "roofline": roof,
         "one_stream": one,

@@ -21,6 +21,12 @@ Waveforms (all synthesised circularly over exactly one buffer):
   +f_c above a carrier tone of power CSPR * E|s|^2, square-law detection.
   Its spectrum stays below 1.1 GHz, so it is synthesised at 4 Gs/s directly.
 
+Optionally, before detection, amplified spontaneous emission at a given
+OSNR (signal power over the ASE power of both polarisations in a 12.5 GHz,
+0.1 nm, reference band): complex white Gaussian noise on the optical field,
+half of it co-polarised with the signal (signal-ASE and ASE-ASE beating) and
+half orthogonal (ASE-ASE only), white over the simulation bandwidth.
+
 Then electrical AWGN (variance = var(I)/SNR at 4 Gs/s) and the 12-bit
 quantiser c = clamp(floor(I / D), 0, 4095) with D = (mean(I) + 6 std(I))/4096,
 packed two samples per three bytes, little-endian.
@@ -158,12 +164,14 @@ def generate(fmt: int, n_samples: int, seed: int, snr_db: float | None = 20.0, *
              rolloff: float = 0.1, cspr_db: float = 10.0, fc_hz: float = 0.55e9,
              drive: float = 0.3, tanh_driver: bool = False,
              beta2_l_s2: float | None = None, tau0: float | None = None,
-             theta_c: float | None = None) -> dict:
-    """One synthetic 12-bit ADC buffer.  `snr_db=None` means noiseless.
+             theta_c: float | None = None, osnr_db: float | None = None) -> dict:
+    """One synthetic 12-bit ADC buffer.  `snr_db=None` means no electrical
+    noise; `osnr_db` adds optical noise before detection (None: none).
 
     Returns a dict with 'packed' (uint8, 1.5 * n_samples), 'codes',
-    'intensity' and the drawn impairments ('tau0' in symbol periods,
-    'theta_c')."""
+    'intensity', the drawn impairments ('tau0' in symbol periods,
+    'theta_c') and, with optical noise, 'ase_var' (the per-polarisation
+    complex noise variance per simulation sample) and 'p_sig'."""
     if n_samples % 2:
         raise ValueError("n_samples must be even")
     sps = sps_of(fmt)
@@ -181,8 +189,8 @@ def generate(fmt: int, n_samples: int, seed: int, snr_db: float | None = 20.0, *
         amp = np.sqrt(10.0 ** (cspr_db / 10.0) * ps)
         n = np.arange(n_samples)
         field = amp * np.exp(1j * theta_c) + s * np.exp(2j * np.pi * fc_hz / FS * n)
-        inten = np.abs(field) ** 2
         true_field = field
+        inten, ase = _detect(field, FS, osnr_db, seed)
     else:
         m = 1 << bits_per_symbol(fmt)
         os_ = 2
@@ -194,7 +202,7 @@ def generate(fmt: int, n_samples: int, seed: int, snr_db: float | None = 20.0, *
         if beta2_l_s2 is not None:
             field = np.fft.ifft(np.fft.fft(field) *
                                 np.exp(0.5j * beta2_l_s2 * (2 * np.pi * f) ** 2))
-        i_sim = np.abs(field) ** 2
+        i_sim, ase = _detect(field, FS * os_, osnr_db, seed)
         spec = np.fft.fft(i_sim)
         spec[np.abs(f) >= FS / 2] = 0.0          # ideal 2 GHz anti-alias filter
         inten = np.fft.ifft(spec).real[::os_]
@@ -203,9 +211,31 @@ def generate(fmt: int, n_samples: int, seed: int, snr_db: float | None = 20.0, *
         sigma = np.sqrt(inten.var() / 10.0 ** (snr_db / 10.0))
         inten = inten + sigma * _rng(seed, 11).standard_normal(n_samples)
     codes = quantize12(inten)
-    return {"fmt": fmt, "seed": seed, "n_samples": n_samples, "codes": codes,
-            "packed": pack12(codes), "intensity": inten, "field": true_field, "tau0": tau0,
-            "theta_c": theta_c}
+    out = {"fmt": fmt, "seed": seed, "n_samples": n_samples, "codes": codes,
+           "packed": pack12(codes), "intensity": inten, "field": true_field, "tau0": tau0,
+           "theta_c": theta_c}
+    out.update(ase)
+    return out
+
+
+B_REF = 12.5e9   # OSNR reference bandwidth (0.1 nm at 1550 nm)
+
+
+def _detect(field: np.ndarray, fs_sim: float, osnr_db: float | None, seed: int):
+    """Square-law detection, with ASE at `osnr_db` added to the field first.
+
+    ASE power in B_REF (both polarisations) = P_sig / OSNR, white, so each
+    polarisation carries complex noise of variance P_sig fs_sim / (2 B_REF
+    OSNR) per sample at the simulation rate fs_sim."""
+    if osnr_db is None:
+        return np.abs(field) ** 2, {}
+    p_sig = float(np.mean(np.abs(field) ** 2))
+    var = p_sig * fs_sim / (2.0 * B_REF * 10.0 ** (osnr_db / 10.0))
+    r = _rng(seed, 13)
+    sd = np.sqrt(var / 2.0)   # per real component
+    n_co = sd * (r.standard_normal(field.size) + 1j * r.standard_normal(field.size))
+    n_or = sd * (r.standard_normal(field.size) + 1j * r.standard_normal(field.size))
+    return np.abs(field + n_co) ** 2 + np.abs(n_or) ** 2, {"ase_var": var, "p_sig": p_sig}
 
 
 # Named workloads (sizes and link parameters of the measured configurations).

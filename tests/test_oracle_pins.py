@@ -335,3 +335,21 @@ def test_precision_form_error_bound(oracle_lib):
         bound = 2 * u * np.convolve(np.abs(y_pre), np.abs(h), "same")[0::2] * ref["agc"]
         diff = np.abs(r["mf"] - ref["mf"])
         assert np.all(diff <= bound * 1.05 + 1e-12)
+
+
+@pytest.mark.parametrize("fmt,fs_sim", [(5, 4.0e9), (2, 8.0e9)])
+def test_synth_osnr_measured_from_detected_noise(fmt, fs_sim):
+    """The optical-noise option of the input generator (the OSNR sweeps'
+    noise model): with the same seed, noisy minus noiseless intensity is the
+    signal-ASE beat (zero mean) plus |n_co|^2 + |n_or|^2, whose mean is twice
+    the per-polarisation variance (the PAM path's 2 GHz low-pass keeps the
+    mean).  The OSNR recovered from that mean, P_sig / (ASE of both
+    polarisations in 12.5 GHz), is the one asked for."""
+    n = 1 << 20
+    for osnr in (18.0, 26.0):
+        a = synth.generate(fmt, n, 5, None, osnr_db=osnr)
+        b = synth.generate(fmt, n, 5, None)
+        var = float(np.mean(a["intensity"] - b["intensity"])) / 2.0
+        p_sig = float(np.mean(b["intensity"]))
+        ase_in_band = 2.0 * var / fs_sim * 12.5e9
+        assert 10.0 * np.log10(p_sig / ase_in_band) == pytest.approx(osnr, abs=0.25)
