@@ -15,9 +15,10 @@ FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-# Per-file additions: the MLP kernels keep MFMA results in VGPRs (they feed
-# VALU epilogues directly; the AGPR form adds a register move per value).
-EXTRA = {"mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+# Per-file additions: the MLP and precision-form FFE kernels keep MFMA
+# results in VGPRs (they feed VALU epilogues directly; the AGPR form adds a
+# register move per value, and for the MLP a quarter more registers).
+EXTRA = {"mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"], "eq.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _compile(src):

@@ -102,12 +102,25 @@ __device__ __forceinline__ void apply_twiddles(float2 *v, float2 w1, float2 w2, 
   }
 }
 
+// Where a pass puts its outputs.  begin() runs at the start of the pass,
+// before its LDS reads (a place to issue loads the outputs will need);
+// out(koff, pk, v) takes output v, with koff = its index minus threadIdx.x
+// (a constant once the loops are unrolled; meaningful in the last pass,
+// whose butterfly j = threadIdx.x + b T writes outputs j + r NS) and pk its
+// padded LDS slot.  The default writes the slot; a caller can take the last
+// pass's outputs in registers instead.
+struct LdsOut {
+  float2 *buf;
+  __device__ __forceinline__ void begin() {}
+  __device__ __forceinline__ void operator()(int, int pk, float2 v) const { buf[pk] = v; }
+};
+
 // One Stockham pass of radix R with NS = product of the previous radices.
 // Butterfly j reads x[j + r N/R], twiddles by W_{NS R}^{r (j mod NS)}, and
 // writes to (j / NS) NS R + (j mod NS) + r NS.  NS is a compile-time
 // constant so the padded LDS offsets of the 16 accesses fold to immediates.
-template <int N, int R, int NS, bool TAIL = true>
-__device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *__restrict__ tw) {
+template <int N, int R, int NS, bool TAIL = true, class Out = LdsOut>
+__device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *__restrict__ tw, Out out) {
   constexpr int T = N / 16;
   constexpr int NB = (N / R) / T;  // butterflies per thread
   // twiddle table reads first: their latency overlaps the LDS reads and the barrier
@@ -123,6 +136,7 @@ __device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *__restr
       tw8[b] = R > 8 ? tw[8 * step] : tw1[b];
     }
   }
+  out.begin();
   float2 v[NB][R];
 #pragma unroll
   for (int b = 0; b < NB; b++) {
@@ -146,32 +160,37 @@ __device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *__restr
     static_assert(NS % 16 == 0 || (NS == 1 && R == 16), "padded write offsets split");
     const int pb = fpad(base);
 #pragma unroll
-    for (int r = 0; r < R; r++) buf[pb + fpad(r * NS)] = v[b][r];
+    for (int r = 0; r < R; r++) out(b * T + r * NS, pb + fpad(r * NS), v[b][r]);
   }
   if constexpr (TAIL) __syncthreads();
 }
 
-template <int N, int NS, bool TAIL>
-__device__ __forceinline__ void fft_passes(float2 *buf, const float2 *__restrict__ tw) {
+template <int N, int NS, bool TAIL, class Out>
+__device__ __forceinline__ void fft_passes(float2 *buf, const float2 *__restrict__ tw, Out out) {
   if constexpr (NS * 16 < N) {
-    stockham_pass<N, 16, NS>(buf, tw);
-    fft_passes<N, NS * 16, TAIL>(buf, tw);
+    stockham_pass<N, 16, NS>(buf, tw, LdsOut{buf});
+    fft_passes<N, NS * 16, TAIL>(buf, tw, out);
   } else if constexpr (NS * 16 == N) {
-    stockham_pass<N, 16, NS, TAIL>(buf, tw);
+    stockham_pass<N, 16, NS, TAIL>(buf, tw, out);
   } else if constexpr (NS * 8 == N) {
-    stockham_pass<N, 8, NS, TAIL>(buf, tw);
+    stockham_pass<N, 8, NS, TAIL>(buf, tw, out);
   } else if constexpr (NS * 4 == N) {
-    stockham_pass<N, 4, NS, TAIL>(buf, tw);
+    stockham_pass<N, 4, NS, TAIL>(buf, tw, out);
   } else if constexpr (NS * 2 == N) {
-    stockham_pass<N, 2, NS, TAIL>(buf, tw);
+    stockham_pass<N, 2, NS, TAIL>(buf, tw, out);
   }
 }
 
 // Forward FFT of N = 2^LOGN points held in buf (padded layout), natural
-// order in and out.  tw[k] = exp(-j 2 pi k / N).  The last pass writes
-// output k from thread k mod (N / 16); with TAIL = false it ends without a
-// barrier, for a caller whose threads next touch only their own outputs.
+// order in.  tw[k] = exp(-j 2 pi k / N).  Output k comes from thread
+// k mod (N / 16) and goes to out (default: natural order in buf); with
+// TAIL = false the last pass ends without a barrier, for a caller whose
+// threads next touch only their own outputs.
+template <int LOGN, bool TAIL = true, class Out = LdsOut>
+__device__ __forceinline__ void fft_forward(float2 *buf, const float2 *__restrict__ tw, Out out) {
+  fft_passes<(1 << LOGN), 1, TAIL>(buf, tw, out);
+}
 template <int LOGN, bool TAIL = true>
 __device__ __forceinline__ void fft_forward(float2 *buf, const float2 *__restrict__ tw) {
-  fft_passes<(1 << LOGN), 1, TAIL>(buf, tw);
+  fft_passes<(1 << LOGN), 1, TAIL>(buf, tw, LdsOut{buf});
 }

@@ -21,15 +21,39 @@ __device__ __forceinline__ int64_t clamp64(int64_t v, int64_t lo, int64_t hi) {
   return v < lo ? lo : (v > hi ? hi : v);
 }
 
-// Codes of samples s0 .. s0+7 of a frame, replicated beyond the buffer edges.
-__device__ __forceinline__ void frame_codes8(const uint8_t *in, int64_t n, int64_t s0, int c[8]) {
-  if (s0 >= 0 && s0 + 8 <= n) {
-    read_codes8(in, s0 >> 3, c);
-  } else {
+// Last pass of the first transform: Y = Z H with H = -j S taken on the way
+// out (output k = threadIdx.x + i T of the thread, i = koff / T), the 16
+// spectrum weights read at the start of the pass.
+template <int T> struct HilbertOut {
+  float2 *buf;
+  const float *hspec;
+  float hs[16];
+  __device__ __forceinline__ void begin() {
 #pragma unroll
-    for (int e = 0; e < 8; e++) c[e] = read_code(in, clamp64(s0 + e, 0, n - 1));
+    for (int i = 0; i < 16; i++) hs[i] = hspec[threadIdx.x + i * T];
   }
-}
+  __device__ __forceinline__ void operator()(int koff, int pk, float2 z) const {
+    const float s = hs[koff / T];
+    buf[pk] = make_float2(z.y * s, z.x * s);
+  }
+};
+
+// Last pass of the second transform: outputs k = q + IOFF T (q = threadIdx.x
+// + i T, i < QPT) are the phases phiA - j phiB of the samples the field stage
+// handles; they stay in registers, in revolutions (sgn / (2 pi) applied).
+template <int T, int QPT, int IOFF> struct PhaseOut {
+  float (&pa)[QPT];
+  float (&pb)[QPT];
+  float sgnrev;
+  __device__ __forceinline__ void begin() {}
+  __device__ __forceinline__ void operator()(int koff, int, float2 v) const {
+    const int i = koff / T - IOFF;
+    if (i >= 0 && i < QPT) {
+      pa[i] = v.x * sgnrev;
+      pb[i] = -v.y * sgnrev;
+    }
+  }
+};
 
 // A value that is the same in every lane, moved into scalar registers: kept
 // in vector registers it would be recomputed at each use once the
@@ -148,63 +172,80 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
   //    (ln 2 / 2) log2(v) with v = code + 0.5 in [0.5, 4095.5], so the
   //    hardware log2 (1 ulp) needs none of the denormal handling of logf, and
   //    l - l_ref = (ln 2 / 2)(log2 v - log2 v_ref).
+  //    Taken straight into the first FFT pass (radix 16, no twiddles):
+  //    butterfly j = threadIdx.x reads samples j + r T (r < 16), so the thread
+  //    reads those codes itself, transforms them in registers and writes the
+  //    pass's outputs 16 j + r; the codes never pass through LDS.
   constexpr float HLN2 = 0.34657359027997264f;   // ln(2) / 2
   const float lr0 = __builtin_amdgcn_logf((float)read_code(in, clamp64(F[0] + N / 2, 0, n - 1)) + 0.5f);
   const float lr1 = __builtin_amdgcn_logf((float)read_code(in, clamp64(F[1] + N / 2, 0, n - 1)) + 0.5f);
+  {
+    int ca[16], cb[16];
+    if (F[0] >= 0 && F[1] + N <= n) {
+      // both frames inside the buffer: sample s0 + r T sits at byte
+      // (3 s0 >> 1) + r (3 T / 2) (T is even), in the high 12 bits of its
+      // 16-bit word when s0 is odd
+      const int64_t s0a = F[0] + threadIdx.x, s0b = F[1] + threadIdx.x;
+      const uint8_t *pa = in + ((3 * s0a) >> 1), *pb = in + ((3 * s0b) >> 1);
+      const int sha = (int)(s0a & 1) << 2, shb = (int)(s0b & 1) << 2;
 #pragma unroll
-  for (int gi = 0; gi < N / 8 / T; gi++) {
-    const int g = threadIdx.x + gi * T;
-    int ca[8], cb[8];
-    frame_codes8(in, n, F[0] + 8 * g, ca);
-    frame_codes8(in, n, F[1] + 8 * g, cb);
+      for (int r = 0; r < 16; r++) {
+        ca[r] = (int)pa[r * (3 * T / 2)] | ((int)pa[r * (3 * T / 2) + 1] << 8);
+        cb[r] = (int)pb[r * (3 * T / 2)] | ((int)pb[r * (3 * T / 2) + 1] << 8);
+      }
 #pragma unroll
-    for (int e = 0; e < 8; e++)
-      lds[fpad(8 * g + e)] = make_float2(HLN2 * (__builtin_amdgcn_logf((float)ca[e] + 0.5f) - lr0),
-                                         HLN2 * (__builtin_amdgcn_logf((float)cb[e] + 0.5f) - lr1));
+      for (int r = 0; r < 16; r++) {
+        ca[r] = (ca[r] >> sha) & 0xFFF;
+        cb[r] = (cb[r] >> shb) & 0xFFF;
+      }
+    } else {   // a frame reaches past a buffer end: samples replicated from the edge
+#pragma unroll
+      for (int r = 0; r < 16; r++) {
+        ca[r] = read_code(in, clamp64(F[0] + threadIdx.x + r * T, 0, n - 1));
+        cb[r] = read_code(in, clamp64(F[1] + threadIdx.x + r * T, 0, n - 1));
+      }
+    }
+    float2 v[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++)
+      v[r] = make_float2(HLN2 * (__builtin_amdgcn_logf((float)ca[r] + 0.5f) - lr0),
+                         HLN2 * (__builtin_amdgcn_logf((float)cb[r] + 0.5f) - lr1));
+    dft16(v);
+    const int p0 = fpad(16 * threadIdx.x);   // outputs 16 j + r: one padded run
+#pragma unroll
+    for (int r = 0; r < 16; r++) lds[p0 + r] = v[r];
   }
   __syncthreads();
 
   // 2. Hilbert filtering: Y = Z H, H = -j S; the inverse transform is done as
-  //    conj(FFT(conj(Y)/N)), so the second pass leaves phiA - j phiB.
-  // (each thread's Hilbert products and phase reads below are outputs k of
-  // the transforms with k = threadIdx.x mod T, written by this thread: no
-  // barrier after either transform)
-  fft_forward<LOGN, false>(lds, J.twid);
-#pragma unroll 8
-  for (int i = 0; i < 16; i++) {   // unrolled: eight spectrum reads in flight together
-    const int k = threadIdx.x + i * T;
-    const float2 zv = lds[fpad(k)];
-    const float s = J.hspec[k];
-    lds[fpad(k)] = make_float2(zv.y * s, zv.x * s);
-  }
+  //    conj(FFT(conj(Y)/N)), so the second pass leaves phiA - j phiB.  Each
+  //    thread's outputs of either transform (k = threadIdx.x mod T) are the
+  //    ones it multiplies by H and, after the second, the phases of the
+  //    samples it handles in the field stage (q + EDGE - CMF with q =
+  //    threadIdx.x + i T): both are taken in the last pass, in registers.
+  static_assert((RX_KK_EDGE - RX_KK_CMF) % T == 0 && QN % T == 0, "phases are the thread's own outputs");
+  fft_passes<N, 16, false>(lds, J.twid, HilbertOut<T>{lds, J.hspec, {}});   // the passes after the first
   __syncthreads();
   // the second transform recomputes its twiddle addresses: kept live from the
   // first they would be spilled across the Hilbert product
   const float2 *tw2 = J.twid;
   asm volatile("" : "+s"(tw2));
-  fft_forward<LOGN, false>(lds, tw2);
-
-  constexpr int NPH = PREC == 0 ? 2 : 1;   // frames whose phases stay in registers
-  float ph[NPH][QPT], phb[PREC == 0 ? 1 : QPT];
   // phase in revolutions: sgn phi / (2 pi); sgn = +-1, so one product by
   // sgn / (2 pi) is exact against the two
   const float sgnrev = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, J.sgn * INV2PI)));
+  float ph[2][QPT];   // frames A and B (the narrow forms park B in LDS below)
+  fft_forward<LOGN, false>(lds, tw2, PhaseOut<T, QPT, (RX_KK_EDGE - RX_KK_CMF) / T>{ph[0], ph[1], sgnrev});
+  // the phases are formed here: left to itself the compiler moves the last
+  // pass's arithmetic into the field stage, where it no longer fits the
+  // register file
 #pragma unroll
-  for (int i = 0; i < QPT; i++) {
-    const int q = threadIdx.x + i * T;
-    if (q < QN) {
-      const float2 v = lds[fpad(q + RX_KK_EDGE - RX_KK_CMF)];
-      ph[0][i] = v.x * sgnrev;
-      if constexpr (PREC == 0) ph[NPH - 1][i] = -v.y * sgnrev;
-      else phb[i] = -v.y * sgnrev;
-    }
-  }
+  for (int i = 0; i < QPT; i++) asm volatile("" : "+v"(ph[0][i]), "+v"(ph[1][i]));
   __syncthreads();
   if constexpr (PREC != 0) {
 #pragma unroll
     for (int i = 0; i < QPT; i++) {
       const int q = threadIdx.x + i * T;
-      if (q < QN) stash[q] = phb[i];   // read back by this thread only
+      stash[q] = ph[1][i];   // read back by this thread only
     }
   }
 

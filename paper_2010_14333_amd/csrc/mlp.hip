@@ -259,7 +259,8 @@ __global__ __launch_bounds__(256) void mlp_infer(RxLaunch L) {
   const RxJob J = *L.job[jb];
   if (!J.mlp) return;
   const int64_t n = L.n[jb], nsym = n / 2;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform: scalar tile bookkeeping
   const int row = lane & 15, kq = lane >> 4;
   const int s = J.sc->lag;
   const auto xr = gptr(J.xr);
@@ -267,32 +268,41 @@ __global__ __launch_bounds__(256) void mlp_infer(RxLaunch L) {
   MlpFrag f;
   mlp_load_frag(J.mlp, row, kq, cv, f);
   const int64_t tile0 = ((int64_t)blockIdx.x * 4 + wv) * TILES_PER_WAVE;
-  // window sample 8 kq + j of symbol k0 + row: x[2 (k0 + row + s) - 15 + 8 kq + j];
-  // the next tile's samples are loaded while this tile runs
-  auto load_x = [&](int64_t k0, float xv[8]) {
-    const int64_t c = 2 * (k0 + row + s) - 15 + 8 * kq;
-    if (2 * (k0 + s) - 15 >= 0 && 2 * (k0 + 15 + s) + 16 < n) {   // whole tile window inside the buffer
+  const int64_t ntl = (nsym - 16 * tile0 + 15) / 16;
+  const int nt = ntl < TILES_PER_WAVE ? (int)ntl : TILES_PER_WAVE;   // this wave's tiles (none if <= 0)
+  // window sample 8 kq + j of symbol k0 + row: x[2 (k0 + row + s) - 15 + 8 kq + j]
+  // = x[w0 + 32 tt + lo + j] with w0 = 2 (16 tile0 + s) - 15 (the wave's first
+  // window) and lo = 2 row + 8 kq < 64; the whole tile's window lies in the
+  // buffer when w0 + 32 tt >= 0 and w0 + 32 tt + 61 < n (a scalar test), and
+  // then the tile's reads are one wave-uniform pointer plus small lane
+  // offsets.  The next tile's samples are loaded while this tile runs (past
+  // the wave's last tile too: the test keeps those reads in the buffer).
+  const int64_t w0 = 2 * (16 * tile0 + s) - 15;
+  const int lo = 2 * row + 8 * kq;
+  auto load_x = [&](int tt, float xv[8]) {
+    const int64_t t0 = w0 + 32 * (int64_t)tt;
+    if (t0 >= 0 && t0 + 61 < n) {
+      const auto tp = xr + t0;
 #pragma unroll
-      for (int j = 0; j < 8; j++) xv[j] = 8 * kq + j < MI ? xr[c + j] : 0.0f;
+      for (int j = 0; j < 8; j++) xv[j] = tp[lo + j];
     } else {
 #pragma unroll
       for (int j = 0; j < 8; j++) {
-        const int64_t q = c + j;
-        xv[j] = (8 * kq + j < MI && q >= 0 && q < n) ? xr[q] : 0.0f;
+        const int64_t q = t0 + lo + j;
+        xv[j] = (q >= 0 && q < n) ? xr[q] : 0.0f;
       }
     }
   };
   float xn[8];
-  load_x(tile0 * 16, xn);
-  for (int tt = 0; tt < TILES_PER_WAVE; tt++) {
-    const int64_t k0 = (tile0 + tt) * 16;
-    if (k0 >= nsym) break;
+  load_x(0, xn);
+  for (int tt = 0; tt < nt; tt++) {
     MNT::vec bx;
 #pragma unroll
-    for (int j = 0; j < 8; j++) bx[j] = MNT::cvt(xn[j]);
-    if (tt + 1 < TILES_PER_WAVE) load_x(k0 + 16, xn);
+    for (int j = 0; j < 8; j++) bx[j] = MNT::cvt(8 * kq + j < MI ? xn[j] : 0.0f);   // column 31 is padding
+    load_x(tt + 1, xn);
     const float y = mlp_tile(f, bx, kq);
-    if (kq == 0 && k0 + row < nsym) gstore(J.soft, k0 + row, make_float2(y, 0.0f));
+    const int64_t k = (tile0 + tt) * 16 + row;
+    if (kq == 0 && k < nsym) gstore(J.soft, k, make_float2(y, 0.0f));
   }
 }
 

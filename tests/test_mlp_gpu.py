@@ -181,6 +181,40 @@ def test_mlp_stage_in_chain(rx, kind):
         assert not untol and abs(e["bit_errors"] - o["bit_errors"]) <= tol
 
 
+def test_mlp_stage_dense_window_in_chain(rx):
+    """Every window column counts: the linear network plus small seeded
+    weights on all 31 inputs.  The chain's MLP outputs are checked against
+    the oracle's forward pass on the windows the chain itself formed (its
+    timing-corrected samples x and symbol delay s: window i of symbol k is
+    x[2 (k + s) - 15 + i], zero outside the buffer), which pins the kernel's
+    window indexing and tile bookkeeping (first, interior and last tiles,
+    including the buffer edges) independently of the upstream rounding."""
+    n = 1 << 18
+    g = synth.generate(synth.PAM8, n, 913, None, drive=0.1)
+    p = _linear_net()
+    p[:64 * 31] += 1e-3 * np.random.default_rng(17).standard_normal(64 * 31)
+    p = p.astype(np.float32).astype(np.float64)
+    r = rx.Receiver(rx.RX_PAM8, g["seed"], max_samples=n, equalizer=rx.RX_EQ_MLP)
+    rx.rx_set_mlp(r.h, p)
+    r.process(_t(g["packed"]), n)
+    sc = r.fetch(rx.RX_STAGE_SCALARS, n)
+    xr = r.fetch(rx.RX_STAGE_XR, n).astype(np.float64)
+    soft = r.fetch(rx.RX_STAGE_SOFT, n).real.astype(np.float64)
+    r.close()
+    assert int(sc[6]) == 0, "the network must win on the prefix for its outputs to stand"
+    s = int(sc[4])
+    nsym = n // 2
+    idx = 2 * (np.arange(nsym)[:, None] + s) - 15 + np.arange(31)[None, :]
+    win = np.where((idx >= 0) & (idx < n), xr[np.clip(idx, 0, n - 1)], 0.0)
+    yo = oracle.mlp_forward(p, win, rounding=1)
+    rel = parity.rel_rms(soft, yo)
+    worst = int(np.argmax(np.abs(soft - yo)))
+    print(f"[mlp] dense-window chain outputs vs oracle forward on the chain's windows: rel-RMS {rel:.2e}, "
+          f"worst symbol {worst} ({soft[worst]:.6f} vs {yo[worst]:.6f})", flush=True)
+    assert rel <= 1e-4
+    assert np.max(np.abs(soft - yo)) <= 1e-2 * np.max(np.abs(yo))
+
+
 def test_untrained_mlp_runs_lms_with_warning(rx):
     import torch
     n = 1 << 17
