@@ -42,13 +42,16 @@ def run_gpu(rx, fmt, g, n, debug=True, **over):
     return out
 
 
-def check_chain(rx, fmt, n, seed, snr, **gen):
-    _log(f"[parity] fmt={fmt} n={n} seed={seed} snr={snr} {gen}")
+def check_chain(rx, fmt, n, seed, snr, rxo=None, **gen):
+    """rxo: receiver options (e.g. rolloff) given to both the HIP handle and
+    the oracle; gen: options of the input generator."""
+    rxo = rxo or {}
+    _log(f"[parity] fmt={fmt} n={n} seed={seed} snr={snr} {gen} {rxo}")
     g = synth.generate(fmt, n, seed, snr, **gen)
     kk = fmt >= 4
     want = ("bits", "soft", "taps", "mf") + (("field",) if kk else ("timing", "xr"))
-    o = oracle.process(fmt, g["packed"], n, g["seed"], want=want)
-    res = run_gpu(rx, fmt, g, n)
+    o = oracle.process(fmt, g["packed"], n, g["seed"], want=want, **rxo)
+    res = run_gpu(rx, fmt, g, n, **rxo)
     r = res["r"]
     sc = r.fetch(rx.RX_STAGE_SCALARS, n)
     report = {}
@@ -114,6 +117,25 @@ def test_parity_small(rx, fmt, n, seed, snr, gen):
 ])
 def test_parity_ragged_and_minimum(rx, fmt, n, seed, snr):
     check_chain(rx, fmt, n, seed, snr)
+
+
+# The paper's own link parameters (variants of the default workloads): RRC
+# roll-off 0.01 for the KK formats with CSPR 6 or 11 dB, roll-off 0.5 for
+# PAM, optical noise (ASE at a given OSNR) before detection instead of
+# electrical noise; the receiver's matched filter follows the roll-off.
+# OSNRs chosen for a BER near 1e-3 (many decisions near a threshold).
+PAPER_VARIANTS = [
+    (5, 1 << 18, 41, {"rolloff": 0.01, "cspr_db": 11.0, "osnr_db": 17.0}),
+    (5, 1 << 18, 42, {"rolloff": 0.01, "cspr_db": 6.0, "osnr_db": 20.0}),
+    (4, 1 << 18, 43, {"rolloff": 0.01, "cspr_db": 6.0, "osnr_db": 7.0}),
+    (2, 1 << 18, 44, {"rolloff": 0.5, "osnr_db": 15.0}),
+    (3, 1 << 18, 45, {"rolloff": 0.5, "osnr_db": 23.0}),
+]
+
+
+@pytest.mark.parametrize("fmt,n,seed,gen", PAPER_VARIANTS)
+def test_parity_paper_link_variants(rx, fmt, n, seed, gen):
+    check_chain(rx, fmt, n, seed, None, rxo={"rolloff": gen["rolloff"]}, **gen)
 
 
 def test_parity_kk16qam_full_buffer(rx):
