@@ -315,7 +315,8 @@ class Receiver:
         spec = {RX_STAGE_FIELD: (np.complex64, n_samples),
                 RX_STAGE_MF: (np.complex64, n_samples // 2) if kk else (np.float32, n_samples),
                 RX_STAGE_XR: (np.float32, n_samples), RX_STAGE_TIMING: (np.float32, n_samples // 512),
-                RX_STAGE_SOFT: (np.complex64, nsym), RX_STAGE_TAPS: (np.complex64, self.params.ffe_taps),
+                RX_STAGE_SOFT: (np.complex64, nsym) if kk else (np.float32, nsym),
+                RX_STAGE_TAPS: (np.complex64, self.params.ffe_taps),
                 RX_STAGE_PHASE: (np.float32, nsym // 128), RX_STAGE_SCALARS: (np.float64, 8)}[stage]
         dt, cnt = spec
         raw = rx_debug_fetch(self.h, stage, np.dtype(dt).itemsize * cnt)

@@ -651,7 +651,7 @@ int rx_debug_fetch(rx_handle h, int stage, void *dst, size_t bytes) {
       src = J.delta; need = (n / 512) * sizeof(float); break;
     case RX_STAGE_SOFT:
       if (h->kk && !J.debug) return RX_E_STATE;
-      src = J.soft; need = nsym * sizeof(float2); break;
+      src = J.soft; need = nsym * (h->kk ? sizeof(float2) : sizeof(float)); break;   // PAM: real
     case RX_STAGE_TAPS:
       src = reinterpret_cast<const char *>(h->dsc) + offsetof(RxScalars, w0);
       need = h->p.ffe_taps * sizeof(float2); break;

@@ -427,7 +427,7 @@ __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
       if (b0 + l < nb) {
         const T v = sout[l * (BC + 1) + kk];
         if constexpr (CPLX) gstore(soft, (b0 + l) * blk + BC * ch + kk, v);
-        else gstore(soft, (b0 + l) * blk + BC * ch + kk, make_float2(v, 0.0f));
+        else gptr(reinterpret_cast<float *>(soft))[(b0 + l) * blk + BC * ch + kk] = v;   // PAM: real soft symbols
       }
     }
   }
@@ -613,11 +613,23 @@ __global__ __launch_bounds__(256) void rx_decide(RxLaunch L) {
     const int ilo = (int)(lo64 < 0 ? 0 : (lo64 > 8 ? 8 : lo64)), ihi = (int)(hi64 < 0 ? 0 : (hi64 > 8 ? 8 : hi64));
     const uint64_t zb = J.seed + (uint64_t)(k0 + 1) * RX_SM64_GAMMA;   // reference generator state of symbol k0
     float2 zv[8];
+    if (kk) {   // complex soft symbols
 #pragma unroll
-    for (int h = 0; h < 4; h++) {
-      const float4 q = gload4(soft + k0, h);
-      zv[2 * h] = make_float2(q.x, q.y);
-      zv[2 * h + 1] = make_float2(q.z, q.w);
+      for (int h = 0; h < 4; h++) {
+        const float4 q = gload4(soft + k0, h);
+        zv[2 * h] = make_float2(q.x, q.y);
+        zv[2 * h + 1] = make_float2(q.z, q.w);
+      }
+    } else {    // PAM: real soft symbols, packed
+      const float *const sr = reinterpret_cast<const float *>(soft) + k0;
+#pragma unroll
+      for (int h = 0; h < 2; h++) {
+        const float4 q = gload4(sr, h);
+        zv[4 * h] = make_float2(q.x, 0.0f);
+        zv[4 * h + 1] = make_float2(q.y, 0.0f);
+        zv[4 * h + 2] = make_float2(q.z, 0.0f);
+        zv[4 * h + 3] = make_float2(q.w, 0.0f);
+      }
     }
     const float2 rot = kk ? cis_rev(-gptr(J.theta)[k0 / J.blk] * 0.15915494309189535f) : make_float2(1.0f, 0.0f);
 #pragma unroll

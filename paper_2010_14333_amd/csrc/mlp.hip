@@ -302,7 +302,7 @@ __global__ __launch_bounds__(256) void mlp_infer(RxLaunch L) {
     load_x(tt + 1, xn);
     const float y = mlp_tile(f, bx, kq);
     const int64_t k = (tile0 + tt) * 16 + row;
-    if (kq == 0 && k < nsym) gstore(J.soft, k, make_float2(y, 0.0f));
+    if (kq == 0 && k < nsym) gptr(reinterpret_cast<float *>(J.soft))[k] = y;   // PAM: real soft symbols
   }
 }
 
@@ -340,7 +340,7 @@ __global__ __launch_bounds__(256) void mlp_judge(RxLaunch L) {
   double em = 0.0, el = 0.0;
   for (int k = RX_GUARD + threadIdx.x; k < P; k += 256) {
     const float a = ref_symbol(J, k).x;
-    em += decide_level(J.soft[k].x, m) != a;
+    em += decide_level(reinterpret_cast<const float *>(J.soft)[k], m) != a;
     float z = 0.0f;
     for (int i = 0; i < K; i++) {
       const int64_t j = 2 * ((int64_t)k + s) + C - i;

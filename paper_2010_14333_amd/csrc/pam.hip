@@ -70,6 +70,7 @@ __global__ __launch_bounds__(256) void pam_mf(RxLaunch L) {
 #pragma unroll
   for (int i = 0; i < 33; i++) hmf[i] = J.mf[i];
   const double mv = J.sc->mean_re;   // from pam_mean
+  const float mvh = (float)(mv - 0.5);
   constexpr int NGR = (PAM_TS + 48) / 8, GPT = (NGR + 255) / 256;   // code groups per tile and thread
   const int64_t gmax = n / 8 - 1;
   for (int sub = 0; sub < PAM_MF_SUB; sub++) {
@@ -105,10 +106,22 @@ __global__ __launch_bounds__(256) void pam_mf(RxLaunch L) {
 #pragma unroll
         for (int e = 0; e < 8; e++) c[e] = (s0 + e >= 0 && s0 + e < n) ? read_code(in, s0 + e) : -1;
       }
+      // x0 = c + 0.5 - mean = c - (mean - 1/2), the latter rounded to FP32 once
+      float xv[8];
 #pragma unroll
-      for (int e = 0; e < 8; e++) {
-        const int i = 8 * g + e - 4;
-        if (i >= 0 && i < XN) xs[xpad(i)] = c[e] >= 0 ? (float)((double)c[e] + 0.5 - mv) : 0.0f;
+      for (int e = 0; e < 8; e++) xv[e] = c[e] >= 0 ? (float)c[e] - mvh : 0.0f;
+      // xs index i = ib + e, ib = 8 g - 4; xpad(i) = i + i / 16, and the run
+      // of eight crosses a pad (after e = 3) exactly when g is even
+      const int ib = 8 * g - 4;
+      if (g >= 1 && ib + 8 <= XN) {
+        float *const xp = xs + ib + (ib >> 4);
+        const int cross = (g & 1) ^ 1;
+#pragma unroll
+        for (int e = 0; e < 8; e++) xp[e + (e >= 4 ? cross : 0)] = xv[e];
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; e++)
+          if (ib + e >= 0 && ib + e < XN) xs[xpad(ib + e)] = xv[e];
       }
     }
     __syncthreads();
@@ -131,10 +144,11 @@ __global__ __launch_bounds__(256) void pam_mf(RxLaunch L) {
         }
       }
       float q2 = 0.0f;   // 16 squares in FP32, then one FP64 add
+      const int64_t rem = n - (t0 + 16 * (int64_t)threadIdx.x);
+      const int lim = rem < 0 ? 0 : (rem > 16 ? 16 : (int)rem);   // this thread's outputs inside the buffer
 #pragma unroll
       for (int o = 0; o < 16; o++) {
-        const int64_t t = t0 + 16 * threadIdx.x + o;
-        const float yv = (t < n) ? acc[o] : 0.0f;
+        const float yv = o < lim ? acc[o] : 0.0f;
         ys[16 * threadIdx.x + o + 4] = yv;
         q2 = fmaf(yv, yv, q2);
       }

@@ -41,7 +41,7 @@ struct RxJob {
   uint32_t *upart;                  // PAM code-sum partials
   float2 *gard;                     // PAM: Gardner sums per 512-sample block
   float *delta;                     // PAM: timing shift per block (samples)
-  float2 *soft;                     // soft symbols (PAM uses .x)
+  float2 *soft;                     // soft symbols: KK float2, PAM packed floats (read as float[])
   float2 *s4;                       // KK: sum z^4 per DD-LMS block
   float *theta;                     // KK: carrier phase per block
   float2 *field;                    // KK debug: reconstructed field [n] or null
