@@ -22,19 +22,19 @@ __device__ __forceinline__ int64_t clamp64(int64_t v, int64_t lo, int64_t hi) {
 }
 
 // Last pass of the first transform: Y = Z H with H = -j S taken on the way
-// out (output k = threadIdx.x + i T of the thread, i = koff / T), the 16
-// spectrum weights read at the start of the pass.
+// out into registers (output k = threadIdx.x + i T of the thread goes to
+// y[i], i = koff / T), the 16 spectrum weights read at the start of the pass.
 template <int T> struct HilbertOut {
-  float2 *buf;
   const float *hspec;
+  float2 (&y)[16];
   float hs[16];
   __device__ __forceinline__ void begin() {
 #pragma unroll
     for (int i = 0; i < 16; i++) hs[i] = hspec[threadIdx.x + i * T];
   }
-  __device__ __forceinline__ void operator()(int koff, int pk, float2 z) const {
-    const float s = hs[koff / T];
-    buf[pk] = make_float2(z.y * s, z.x * s);
+  __device__ __forceinline__ void operator()(int koff, int, float2 z) const {
+    const int i = koff / T;
+    y[i] = make_float2(z.y * hs[i], z.x * hs[i]);
   }
 };
 
@@ -223,8 +223,21 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
   //    ones it multiplies by H and, after the second, the phases of the
   //    samples it handles in the field stage (q + EDGE - CMF with q =
   //    threadIdx.x + i T): both are taken in the last pass, in registers.
+  //    The first pass of the second transform (radix 16, no twiddles) takes,
+  //    for butterfly j = threadIdx.x, inputs j + r T: the thread's own
+  //    Hilbert products, so they go from one transform to the other in
+  //    registers; the barrier only keeps the writes behind every thread's
+  //    reads of the last pass.
   static_assert((RX_KK_EDGE - RX_KK_CMF) % T == 0 && QN % T == 0, "phases are the thread's own outputs");
-  fft_passes<N, 16, false>(lds, J.twid, HilbertOut<T>{lds, J.hspec, {}});   // the passes after the first
+  {
+    float2 y[16];
+    fft_passes<N, 16, false>(lds, J.twid, HilbertOut<T>{J.hspec, y, {}});   // the passes after the first
+    dft16(y);
+    __syncthreads();
+    const int p0 = fpad(16 * threadIdx.x);   // outputs 16 j + r of the second transform's first pass
+#pragma unroll
+    for (int r = 0; r < 16; r++) lds[p0 + r] = y[r];
+  }
   __syncthreads();
   // the second transform recomputes its twiddle addresses: kept live from the
   // first they would be spilled across the Hilbert product
@@ -234,7 +247,7 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
   // sgn / (2 pi) is exact against the two
   const float sgnrev = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, J.sgn * INV2PI)));
   float ph[2][QPT];   // frames A and B (the narrow forms park B in LDS below)
-  fft_forward<LOGN, false>(lds, tw2, PhaseOut<T, QPT, (RX_KK_EDGE - RX_KK_CMF) / T>{ph[0], ph[1], sgnrev});
+  fft_passes<N, 16, false>(lds, tw2, PhaseOut<T, QPT, (RX_KK_EDGE - RX_KK_CMF) / T>{ph[0], ph[1], sgnrev});
   // the phases are formed here: left to itself the compiler moves the last
   // pass's arithmetic into the field stage, where it no longer fits the
   // register file
