@@ -155,11 +155,16 @@ def test_parity_pam4_2e20(rx):
 
 
 def test_invalid_sizes_rejected(rx):
+    """Rejected on the host before any launch: empty, not a whole number of
+    1024-sample granules (odd lengths among them), below the smallest buffer
+    a chain accepts, and above the handle's maximum."""
     import torch
-    r = rx.Receiver(5, 1, max_samples=1 << 18)
     buf = torch.zeros(3 << 17, dtype=torch.uint8, device="cuda:0")
     out = torch.zeros(1 << 16, dtype=torch.uint8, device="cuda:0")
-    for n in (1000, (1 << 18) + 1024, 0, 16384):
-        with pytest.raises(rx.RxError):
-            rx.rx_process(r.h, buf.data_ptr(), n, out.data_ptr())
-    r.close()
+    for fmt, bad in ((5, (1000, (1 << 18) + 1024, 0, 16384, 20001)),
+                     (2, (0, 9214, 20001, (1 << 18) + 2))):
+        r = rx.Receiver(fmt, 1, max_samples=1 << 18)
+        for n in bad:
+            with pytest.raises(rx.RxError):
+                rx.rx_process(r.h, buf.data_ptr(), n, out.data_ptr())
+        r.close()
