@@ -32,20 +32,33 @@ def front_flop_per_sample(log2n):
 KERNEL_SOURCES = ["kk.hip", "fft_lds.hpp", "rx_dev.hpp", "rx_shared.h"]
 
 
+def kernel_source_hash(root=None):
+    """SHA-256 of the front end's kernel sources with comments and blank
+    lines removed: what the counters were taken on is the code, so a change
+    to a comment leaves the figure valid and any change to the code does
+    not."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(root or ROOT, "paper_2010_14333_amd", "csrc", name)) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        code = "\n".join(line.rstrip() for line in text.split("\n") if line.strip())
+        h.update(code.encode())
+    return h.hexdigest()
+
+
 def front_traffic(batch):
     """HBM bytes per kk_front launch from the committed counter summary, if it
-    was taken on the kernel sources as they are now (else None)."""
-    import hashlib
+    was taken on the kernel code as it is now (else None)."""
     path = os.path.join(ROOT, "profiles", "kk_front_kk16qam_2e22_b64_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2010_14333_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
-    if t.get("source_sha256") != h.hexdigest() or t.get("buffers_per_launch") != batch:
+    if t.get("source_sha256") != kernel_source_hash() or t.get("buffers_per_launch") != batch:
         return None
     return {"bytes_per_launch": t["bytes_per_launch"], "source": os.path.relpath(path, ROOT)}
 

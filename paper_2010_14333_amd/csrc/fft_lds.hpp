@@ -1,7 +1,9 @@
 // In-LDS complex FFT for one workgroup: Stockham auto-sort, radix-16 passes
 // followed by one radix-2/4/8 pass, N = 16 * blockDim.x.  Each thread holds
 // exactly 16 values per pass: read all, barrier, butterfly, write, barrier,
-// so the transform runs in place in one padded LDS buffer.
+// so the transform runs in place in one padded LDS buffer.  The passes can
+// be entered after the first (a caller that formed the first pass itself)
+// and the last pass's outputs handed to a caller's functor instead of LDS.
 #pragma once
 #include "rx_dev.hpp"
 

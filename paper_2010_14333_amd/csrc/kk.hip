@@ -13,6 +13,11 @@
 // on y' = y + m exp(-j 2 pi r n); since the filter is linear its consumers
 // subtract m * MF(exp(...)) on load, and the AGC power of the carrier-free
 // output follows from per-workgroup sums of |Z|^2, |T|^2 and Z conj(T).
+// Wherever a thread's next inputs are its own previous outputs the data
+// stays in registers: the codes a thread reads are the inputs of its first
+// FFT butterfly, its last-pass outputs of the first transform (times H) are
+// the inputs of its first butterfly of the second, and its last-pass
+// outputs of the second are the phases of the samples it handles next.
 #include <type_traits>
 
 #include "fft_lds.hpp"

@@ -32,3 +32,25 @@ def test_traffic_figure_follows_the_sources(tmp_path, monkeypatch):
     os.symlink(os.path.join(ROOT, "paper_2010_14333_amd"), tmp_path / "paper_2010_14333_amd")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench.front_traffic(64) is None
+
+
+def test_traffic_figure_survives_comments_not_code(tmp_path, monkeypatch):
+    """The counters belong to the code: a copy of the sources with an added
+    comment keeps the figure, one with a changed constant turns it off."""
+    import shutil
+    sys.path.insert(0, ROOT)
+    import bench
+    (tmp_path / "profiles").mkdir()
+    shutil.copy(os.path.join(ROOT, "profiles", "kk_front_kk16qam_2e22_b64_traffic.json"), tmp_path / "profiles")
+    src = tmp_path / "paper_2010_14333_amd" / "csrc"
+    src.mkdir(parents=True)
+    for name in bench.KERNEL_SOURCES:
+        shutil.copy(os.path.join(ROOT, "paper_2010_14333_amd", "csrc", name), src / name)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    kk = src / "kk.hip"
+    text = kk.read_text()
+    kk.write_text("// a note for readers\n" + text.replace("\n\n", "\n\n/* and another */\n", 1))
+    assert bench.front_traffic(64) is not None
+    assert "constexpr float HLN2 = 0.34657359027997264f;" in text
+    kk.write_text(text.replace("constexpr float HLN2 = 0.34657359027997264f;", "constexpr float HLN2 = 0.3465736f;"))
+    assert bench.front_traffic(64) is None
