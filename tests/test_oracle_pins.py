@@ -353,3 +353,19 @@ def test_synth_osnr_measured_from_detected_noise(fmt, fs_sim):
         p_sig = float(np.mean(b["intensity"]))
         ase_in_band = 2.0 * var / fs_sim * 12.5e9
         assert 10.0 * np.log10(p_sig / ase_in_band) == pytest.approx(osnr, abs=0.25)
+
+
+@pytest.mark.parametrize("beta", [0.01, 0.1, 0.5])
+@pytest.mark.parametrize("k,sps", [(33, 2), (65, 4)])
+def test_rrc_taps_against_the_spectrum(oracle_lib, k, sps, beta):
+    """The oracle's matched-filter taps (closed-form impulse response) have
+    the shape of the impulse response obtained numerically from the
+    root-raised-cosine spectrum (a fine inverse FFT of the input generator's
+    closed-form spectrum), for the default roll-off and the trial's 0.01
+    (KK) and 0.5 (PAM)."""
+    h = oracle_lib.rrc_taps(k, sps, beta)
+    m, size = 16, 1 << 20
+    dt = 1.0 / (sps * m)
+    ref = np.fft.ifft(synth.rrc_spectrum(np.fft.fftfreq(size, d=dt), 1.0, beta)).real / dt
+    ref = ref[(np.arange(k) - (k - 1) // 2) * m % size]
+    assert np.max(np.abs(h / np.linalg.norm(h) - ref / np.linalg.norm(ref))) < 1e-6
