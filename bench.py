@@ -84,6 +84,9 @@ def main():
     ap.add_argument("--mlp", type=int, default=1, help="train and time the PAM-8 learned-equaliser form")
     ap.add_argument("--mixed", type=int, default=1, help="time a 64-buffer mixed-format batch (graph replay)")
     ap.add_argument("--host", type=int, default=1, help="time the plain chain fed from pinned host memory")
+    ap.add_argument("--fft-log2", type=int, default=0, choices=(0, 13, 14),
+                    help="KK overlap-save FFT size of the timed KK handles: 0 = the library's autotuner "
+                         "(2^14 on MI355X), 13 or 14 to pin it (counter runs pin 14)")
     ap.add_argument("--sweep", type=int, default=0,
                     help="Q-factor sweeps through the GPU chain, one 2^22 buffer per point: 1 = vs electrical "
                          "SNR for every format, 2 = vs OSNR for the paper's link variants, 3 = both")
@@ -111,7 +114,7 @@ def main():
         for si, st in enumerate(streams[:max(1, nstreams)]):
             recs = [rx.Receiver(rx.RX_KK_16QAM, gens[i % a.distinct]["seed"], max_samples=N, stream=st,
                                 flags=rx.RX_PROFILE if (i == 0 and profile) else 0,
-                                precision=precision) for i in range(a.batch)]
+                                precision=precision, fft_log2=a.fft_log2) for i in range(a.batch)]
             outs = [torch.empty(r.bits_bytes(N), dtype=torch.uint8, device=dev) for r in recs]
             sets.append((recs, outs, [r.h for r in recs], [o.data_ptr() for o in outs]))
         bp = [bufs[i % a.distinct].data_ptr() for i in range(a.batch)]
@@ -233,7 +236,8 @@ def main():
         hb = [torch.from_numpy(g["packed"]).pin_memory() for g in gens]
         hbp = [hb[i % a.distinct].data_ptr() for i in range(a.batch)]
         wall_h, ber_h, _, _ = time_handles(
-            lambda st: [rx.Receiver(rx.RX_KK_16QAM, gens[i % a.distinct]["seed"], max_samples=N, stream=st)
+            lambda st: [rx.Receiver(rx.RX_KK_16QAM, gens[i % a.distinct]["seed"], max_samples=N, stream=st,
+                                    fft_log2=a.fft_log2)
                         for i in range(a.batch)], hbp, a.steps, False, host=True)
         host_ingest = {"workload": f"KK-16QAM plain chain, {a.batch} x 2^22 buffers per batch from pinned host "
                                    f"memory, bits back to pinned host memory, {len(streams)} streams",
@@ -385,11 +389,12 @@ def main():
         if dom != "kk_front":
             return {"bound": "latency", "achieved": None, "peak": None, "unit": None, "frac": None,
                     "traffic": None, "kernel": dom}
-        flop = front_flop_per_sample(14) * samples
+        lg = a.fft_log2 or 14   # the autotuner's choice on MI355X when not pinned
+        flop = front_flop_per_sample(lg) * samples
         achieved = flop / (dom_ms * 1e-3) / 1e12
         return {"bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_FP32_VALU_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4), "traffic": None,
-                "kernel": "kk_front<14>", "flop_per_sample": round(front_flop_per_sample(14), 2),
+                "kernel": f"kk_front<{lg}>", "flop_per_sample": round(front_flop_per_sample(lg), 2),
                 "launch_us": round(dom_ms * 1e3, 2)}
 
     roof = roofline(stages)

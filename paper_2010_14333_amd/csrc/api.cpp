@@ -398,6 +398,13 @@ int rx_create(rx_format fmt, double baud, double fs, const rx_params *pin, rx_ha
     h->mlp = A.get<float>(rx_mlp_params());
     ok = h->mlp != nullptr;
   }
+  // reference bits of every symbol a buffer of this handle can hold, plus
+  // two words of slack for the decision stage's two-word reads
+  const int64_t nsym_max = L / (kk ? 4 : 2);
+  const int64_t ref_words = (nsym_max * J.bps + 31) / 32 + 2;
+  uint32_t *refw = ok ? A.get<uint32_t>(ref_words) : nullptr;
+  ok = ok && refw != nullptr;
+  J.refw = refw;
   h->dsc = ok ? A.get<RxScalars>(1) : nullptr;
   h->dj = ok && h->dsc ? A.get<RxJob>(1) : nullptr;
   if (!h->dj) {
@@ -410,6 +417,11 @@ int rx_create(rx_format fmt, double baud, double fs, const rx_params *pin, rx_ha
       hipMemcpy(h->dj, &J, sizeof(J), hipMemcpyHostToDevice) != hipSuccess) {
     delete h;
     return fail_hip(hipGetLastError(), "rx_create upload");
+  }
+  rx_launch_ref_fill(refw, ref_words, J.seed, J.bps, nsym_max, nullptr);
+  if (hipStreamSynchronize(nullptr) != hipSuccess) {
+    delete h;
+    return fail_hip(hipGetLastError(), "rx_create reference bits");
   }
   *out = h;
   return RX_OK;

@@ -611,7 +611,12 @@ __global__ __launch_bounds__(256) void rx_decide(RxLaunch L) {
     // counted symbols of this thread: i in [ilo, ihi)
     const int64_t lo64 = P + RX_GUARD - k0, hi64 = nsym - RX_GUARD - k0;
     const int ilo = (int)(lo64 < 0 ? 0 : (lo64 > 8 ? 8 : lo64)), ihi = (int)(hi64 < 0 ? 0 : (hi64 > 8 ? 8 : hi64));
-    const uint64_t zb = J.seed + (uint64_t)(k0 + 1) * RX_SM64_GAMMA;   // reference generator state of symbol k0
+    // the thread's reference symbols: bits [bps k0, bps (k0 + 8)) of the
+    // handle's reference stream (k0 is a multiple of 8, so they start at bit
+    // (bps k0) mod 32 of a word and end within the next)
+    const int64_t ob = (int64_t)bps * k0;
+    const auto rw = gptr(J.refw);
+    const uint32_t refc = (uint32_t)(((uint64_t)rw[ob >> 5] | ((uint64_t)rw[(ob >> 5) + 1] << 32)) >> (ob & 31));
     float2 zv[8];
     if (kk) {   // complex soft symbols
 #pragma unroll
@@ -646,9 +651,12 @@ __global__ __launch_bounds__(256) void rx_decide(RxLaunch L) {
         sym = gi ^ (gi >> 1);
       }
       chunk |= (__builtin_bitreverse32(sym) >> (32 - bps)) << (bps * i);
+    }
+    const uint32_t x = chunk ^ refc;   // differing bits, symbol i at [bps i, bps (i + 1))
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
       if (i >= ilo && i < ihi) {
-        const uint32_t ref = (uint32_t)(splitmix64_mix(zb + (uint64_t)i * RX_SM64_GAMMA) >> (64 - bps));
-        const uint32_t ne = (uint32_t)__popc(ref ^ sym);
+        const uint32_t ne = (uint32_t)__popc((x >> (bps * i)) & ((1u << bps) - 1u));
         cnt += 1u + ((ne > 0u) << 10) + (ne << 20);
       }
     }
@@ -685,6 +693,34 @@ __global__ __launch_bounds__(256) void rx_decide(RxLaunch L) {
       if (J.sc->fallback) atomicAdd(&J.sc->stats[5], 1ull);
     }
   }
+}
+
+// The handle's reference bit stream (Sec. 3: the BER is counted against
+// the known transmitted sequence): symbol k is the top bps bits of
+// SplitMix64(seed, k), stored like the decided bits (symbol k at stream
+// bits [bps k, bps (k + 1)), its most significant bit first).  Filled once
+// when the handle is created; every buffer of the handle is compared with it.
+__global__ __launch_bounds__(256) void rx_ref_fill(uint32_t *w, int64_t words, uint64_t seed, int bps, int64_t nsym) {
+  const int64_t wi = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (wi >= words) return;
+  uint32_t v = 0u;
+  int64_t kc = -1;
+  uint32_t sym = 0u;
+  for (int b = 0; b < 32; b++) {
+    const int64_t sb = 32 * wi + b, k = sb / bps;
+    if (k >= nsym) break;
+    if (k != kc) {
+      kc = k;
+      sym = (uint32_t)(splitmix64(seed, (uint64_t)k) >> (64 - bps));
+    }
+    const int j = (int)(sb - k * bps);   // bit j of the field: bit bps - 1 - j of the symbol
+    v |= ((sym >> (bps - 1 - j)) & 1u) << b;
+  }
+  w[wi] = v;
+}
+
+void rx_launch_ref_fill(uint32_t *w, int64_t words, uint64_t seed, int bps, int64_t nsym, hipStream_t s) {
+  hipLaunchKernelGGL(rx_ref_fill, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, w, words, seed, bps, nsym);
 }
 
 void rx_launch_eq_stage(int stage, const RxLaunch &L, int64_t maxn, int kk, int ffe_taps, int prec, hipStream_t s) {

@@ -47,6 +47,7 @@ struct RxJob {
   float2 *field;                    // KK debug: reconstructed field [n] or null
   float2 *udbg;                     // KK debug: AGC'd carrier-free MF output [n/2] or null
   const float *mlp;                 // PAM learned equaliser parameters (FP32) or null
+  const uint32_t *refw;             // reference bits of symbols 0 .. max_samples / sps - 1, packed as the output
   RxScalars *sc;
 };
 
@@ -80,6 +81,7 @@ void rx_launch_kk_stage(int stage, const RxLaunch &L, int64_t maxn, int log2n, i
 void rx_launch_pam_stage(int stage, const RxLaunch &L, int64_t maxn, hipStream_t s);
 void rx_launch_eq_stage(int stage, const RxLaunch &L, int64_t maxn, int kk, int ffe_taps, int prec, hipStream_t s);
 void rx_launch_mlp_stage(int stage, const RxLaunch &L, int64_t maxn, hipStream_t s);
+void rx_launch_ref_fill(uint32_t *w, int64_t words, uint64_t seed, int bps, int64_t nsym, hipStream_t s);
 void rx_mlp_windows(const RxLaunch &L, float *X, float *T, int64_t row0, hipStream_t s);
 int rx_mlp_params(void);
 void rx_mlp_step(const float *X, const float *T, int64_t ntrain, int64_t i0, int batch, int64_t mult, float *p,
