@@ -346,6 +346,30 @@ def main():
                     "value": round(res["mlp"][0], 3), "unit": "Gsamples/s", "ber": res["mlp"][1],
                     "fallbacks": res["mlp"][2], "lms_value": round(res["lms"][0], 3), "lms_ber": res["lms"][1],
                     "train_samples": 4 * N, "train_s": round(train_s, 3), "final_loss": round(loss, 5)}
+        if a.one_stream:
+            # each PAM stage alone on the chip: one stream, stage events on one handle
+            for eq in ("mlp", "lms"):
+                recs = [rx.Receiver(rx.RX_PAM8, testg[i % 4]["seed"], max_samples=N, stream=streams[0],
+                                    flags=rx.RX_PROFILE if i == 0 else 0,
+                                    equalizer=rx.RX_EQ_MLP if eq == "mlp" else rx.RX_EQ_LMS)
+                        for i in range(a.batch)]
+                if eq == "mlp":
+                    for r in recs:
+                        rx.rx_set_mlp(r.h, w)
+                outs = [torch.empty(r.bits_bytes(N), dtype=torch.uint8, device=dev) for r in recs]
+                args = ([r.h for r in recs], pbp, [N] * a.batch, [o.data_ptr() for o in outs])
+                for _ in range(2):
+                    rx.rx_process_batch(*args)
+                torch.cuda.synchronize()
+                rx.rx_stage_times(recs[0].h, reset=True)
+                for _ in range(5):
+                    rx.rx_process_batch(*args)
+                stt = rx.rx_stage_times(recs[0].h)
+                mlp_form[f"{eq}_one_stream_stage_us_per_buffer"] = {
+                    k: round(v[0] / v[1] * 1e3 / a.batch, 3) for k, v in stt.items()}
+                for r in recs:
+                    r.close()
+                del outs
         log(f"[bench] MLP form {mlp_form}")
 
     mixed = None
