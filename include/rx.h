@@ -128,7 +128,10 @@ int rx_params_default(rx_format fmt, rx_params *p);
 /* Create a receiver for one format (Sec. 1, second paragraph: the format is
  * selected in software).  baud/fs must be 2e9/4e9 (PAM) or 1e9/4e9 (KK),
  * i.e. 2 and 4 samples per symbol.  Designs the filters in FP64 on the host,
- * rounds them once, allocates the workspace for p->max_samples.
+ * rounds them once, allocates the workspace for p->max_samples, and writes
+ * the reference bits of every symbol a buffer can hold (max_samples / sps
+ * symbols of log2(M) bits, from the seed) once, on the null stream, before
+ * returning: every buffer of the handle is counted against them.
  * p may be NULL (defaults).  On success *out owns device memory. */
 int rx_create(rx_format fmt, double baud, double fs, const rx_params *p, rx_handle *out);
 
