@@ -598,7 +598,8 @@ __global__ __launch_bounds__(256) void rx_decide(RxLaunch L) {
   const auto out = gptr(reinterpret_cast<uint32_t *>(L.bits[jb]));
   float2 *const soft = J.soft;
   const int nw = DEC_SYMS * bps / 32;
-  for (int i = threadIdx.x; i < nw; i += 256) wb[i] = 0u;
+  if (bps != 4)   // 4 bits per symbol: each thread's 8 symbols are one whole output word (below)
+    for (int i = threadIdx.x; i < nw; i += 256) wb[i] = 0u;
   // this thread: symbols k0 .. k0 + 7 (one DD-LMS block, so one phase)
   const int64_t k0 = kbase + 8 * threadIdx.x;
   const bool valid = k0 < nsym;   // then k0 + 8 <= nsym
@@ -661,15 +662,19 @@ __global__ __launch_bounds__(256) void rx_decide(RxLaunch L) {
       }
     }
   }
-  __syncthreads();
-  if (valid) {
-    const int lb = 8 * bps * threadIdx.x, wi = lb >> 5, off = lb & 31;
-    atomicOr(&wb[wi], chunk << off);
-    if (off + 8 * bps > 32) atomicOr(&wb[wi + 1], chunk >> (32 - off));
+  if (bps == 4) {   // (uniform) symbols k0 .. k0 + 7 are exactly output word k0 / 8
+    if (valid) out[k0 / 8] = chunk;
+  } else {          // the workgroup's words assembled in LDS, then written whole
+    __syncthreads();
+    if (valid) {
+      const int lb = 8 * bps * threadIdx.x, wi = lb >> 5, off = lb & 31;
+      atomicOr(&wb[wi], chunk << off);
+      if (off + 8 * bps > 32) atomicOr(&wb[wi + 1], chunk >> (32 - off));
+    }
+    __syncthreads();
+    const int64_t nsw = (nsym - kbase < DEC_SYMS ? nsym - kbase : DEC_SYMS) * bps / 32;
+    for (int i = threadIdx.x; i < nsw; i += 256) out[kbase * bps / 32 + i] = wb[i];
   }
-  __syncthreads();
-  const int64_t nsw = (nsym - kbase < DEC_SYMS ? nsym - kbase : DEC_SYMS) * bps / 32;
-  for (int i = threadIdx.x; i < nsw; i += 256) out[kbase * bps / 32 + i] = wb[i];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cnt;
