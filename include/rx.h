@@ -31,7 +31,12 @@
  *     the photocurrent c + 0.5 (Sec. 2, first paragraph: 2^22 12-bit samples
  *     per buffer at 4 Gs/s).
  *   - Output bits: symbol-major, Gray bits MSB-first within a symbol; stream
- *     bit t lives in byte t >> 3 at bit position t & 7 (LSB first).
+ *     bit t lives in byte t >> 3 at bit position t & 7 (LSB first).  The
+ *     kernels write whole 32-bit words of it.
+ *   - Alignment: dev_buffer and dev_bits (and ref_bits) must be 4-byte
+ *     aligned (the kernels read and write 32-bit words); a misaligned
+ *     pointer is rejected with RX_E_INVALID before anything is enqueued.
+ *     Host pointers of rx_process_batch_host need no alignment.
  */
 #ifndef RX_H
 #define RX_H
@@ -82,8 +87,10 @@ enum {
 
 typedef struct {
   uint32_t struct_size;     /* sizeof(rx_params), for ABI evolution */
-  int32_t mf_taps;          /* matched RRC length: 33 (PAM, 2 sps), 65 (KK, 4 sps); odd, <= 65 */
-  int32_t ffe_taps;         /* T/2-spaced FFE length: 15 (PAM), 21 (KK); odd, <= 31 */
+  int32_t mf_taps;          /* matched RRC length: 33 (PAM, 2 sps), 65 (KK, 4 sps); odd, at most
+                               33 (PAM) / 65 (KK); shorter filters are centred in those slots */
+  int32_t ffe_taps;         /* T/2-spaced FFE length: 15 (PAM), 21 (KK); 15 or 21 for either chain
+                               (the precision form: 21) */
   int32_t prefix_symbols;   /* known training/sync symbols at each buffer start: 4096 */
   int32_t hilbert_taps;     /* KK Hilbert FIR length V+1: 4097 */
   int32_t fft_log2;         /* KK overlap-save FFT size: 0 = library choice, else 13 or 14 */
@@ -97,15 +104,27 @@ typedef struct {
                                of the k-th SplitMix64 output seeded with `seed` */
   uint64_t max_samples;     /* largest n_samples a call may pass (sizes the workspace) */
   void *stream;             /* hipStream_t for all work of this handle; NULL = null stream */
-  uint32_t flags;           /* RX_DEBUG_KEEP */
+  uint32_t flags;           /* RX_DEBUG_KEEP, RX_PROFILE */
   uint32_t reserved;
+  double deadline_s;        /* latency budget of every buffer, seconds; 0 = the buffer's own
+                               real-time span n_samples / fs (Sec. 2, first paragraph: each
+                               buffer processed before the next ones arrive); see rx_latencies */
+  const void *ref_bits;     /* NULL: the reference stream comes from `seed`.  Else a device
+                               pointer, owned by the caller, to the reference bits of symbols
+                               0 .. max_samples / sps - 1 packed like the output bits (4-byte
+                               aligned, at least 4 * ceil(max_samples / sps * log2(M) / 32)
+                               bytes, valid while the handle processes buffers).  It is read
+                               by every buffer at the time its decision stage runs, so a
+                               caller counting buffers of different sequences on one handle
+                               rewrites it on the handle's stream between them. */
 } rx_params;
 
 /* Cumulative counters since create / rx_errors_reset.  Symbols counted are
  * those in [prefix + 64, n_symbols - 64) of each buffer (Sec. 3, second
- * paragraph: Q-factor estimated from the error rate). */
+ * paragraph: Q-factor estimated from the error rate).  late_buffers counts
+ * buffers whose latency (rx_latencies) exceeded the handle's deadline. */
 typedef struct {
-  uint64_t buffers, symbols, bits, bit_errors, symbol_errors, fallbacks;
+  uint64_t buffers, symbols, bits, bit_errors, symbol_errors, fallbacks, late_buffers;
 } rx_stats;
 
 /* Debug stages for rx_debug_fetch (the handle needs RX_DEBUG_KEEP for FIELD). */
@@ -139,9 +158,10 @@ int rx_create(rx_format fmt, double baud, double fs, const rx_params *p, rx_hand
  * n_samples packed 12-bit codes (1.5 * n_samples bytes); dev_bits receives
  * ceil(n_sym * log2(M) / 8) bytes, n_sym = n_samples / sps.  *n_bits_out (may
  * be NULL) is set on the host without synchronising.  Asynchronous on the
- * handle's stream.  Errors: RX_E_INVALID if n_samples is not a positive
- * multiple of 1024, exceeds max_samples, or leaves fewer than prefix + 128
- * symbols; RX_E_HIP on a launch failure. */
+ * handle's stream.  Errors: RX_E_INVALID if a pointer is NULL or not 4-byte
+ * aligned, if n_samples is not a positive multiple of 1024, exceeds
+ * max_samples, or leaves fewer than prefix + 128 symbols; RX_E_HIP on a
+ * launch failure. */
 int rx_process(rx_handle h, const void *dev_buffer, size_t n_samples, void *dev_bits,
                size_t *n_bits_out);
 
@@ -151,9 +171,12 @@ int rx_process(rx_handle h, const void *dev_buffer, size_t n_samples, void *dev_
  * buffers share every kernel launch).  With graph != 0 the launch sequence
  * is captured once (on a library-owned stream) into a hipGraph per (handles,
  * buffers, sizes) and replayed on the first handle's stream.
- * Arguments as for rx_process, one entry per buffer.  Errors: RX_E_INVALID
- * for count outside 1..64, a repeated handle or handles on different
- * streams. */
+ * A cached graph is replayed only for the same handles (by a process-unique
+ * id, not their addresses) in the same state: setting or training a
+ * handle's network, or destroying and re-creating handles, leads to a new
+ * capture.  Arguments as for rx_process, one entry per buffer.  Errors:
+ * RX_E_INVALID for count outside 1..64, a repeated handle, handles on
+ * different streams, or a pointer that rx_process rejects. */
 int rx_process_batch(const rx_handle *hs, const void *const *dev_buffers, const size_t *n_samples,
                      void *const *dev_bits, int count, int graph);
 
@@ -181,7 +204,20 @@ int rx_sync(rx_handle h);
 
 /* Synchronise the handle's stream and copy the cumulative counters. */
 int rx_errors(rx_handle h, rx_stats *out);
+/* Zero the counters and the latency record. */
 int rx_errors_reset(rx_handle h);
+
+/* Per-buffer latency, measured on the device (the paper's real-time
+ * criterion, Sec. 2, first paragraph: every buffer processed within its
+ * budget): the wall clock when the buffer's first kernel starts its first
+ * workgroup, to when its last decision workgroup finishes; compared with the
+ * deadline (rx_params.deadline_s, else n_samples / fs) into
+ * rx_stats.late_buffers.  Copies the latencies, in microseconds, of the
+ * most recent min(recorded, 1024, max) buffers of this handle, oldest first,
+ * into us[] and their number into *count (may be NULL); synchronises the
+ * handle's stream.  In a batch, a buffer's latency includes the other
+ * buffers it shares each launch with. */
+int rx_latencies(rx_handle h, double *us, size_t max, size_t *count);
 
 /* Copy an intermediate array of the most recent buffer to host memory
  * (synchronises).  bytes must equal the stage's size for that buffer.

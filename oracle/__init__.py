@@ -28,12 +28,12 @@ class Cfg(ctypes.Structure):
                 ("rounding", ctypes.c_int32), ("equalizer", ctypes.c_int32),
                 ("pad0", ctypes.c_int32), ("rolloff", ctypes.c_double), ("mu", ctypes.c_double),
                 ("mu_cma", ctypes.c_double), ("fc_over_fs", ctypes.c_double),
-                ("seed", ctypes.c_uint64), ("mlp", _dp)]
+                ("seed", ctypes.c_uint64), ("mlp", _dp), ("force", ctypes.POINTER(ctypes.c_int32))]
 
 
 class Out(ctypes.Structure):
     _fields_ = [("field", _dp), ("shifted", _dp), ("mf", _dp), ("timing", _dp), ("xr", _dp),
-                ("soft", _dp), ("taps", _dp), ("phase", _dp), ("bits", _u8p),
+                ("soft", _dp), ("taps", _dp), ("phase", _dp), ("ddz", _dp), ("bits", _u8p),
                 ("mean_re", ctypes.c_double), ("mean_im", ctypes.c_double),
                 ("agc", ctypes.c_double), ("theta0", ctypes.c_double),
                 ("lag", ctypes.c_int32), ("rot", ctypes.c_int32), ("fallback", ctypes.c_int32),
@@ -63,6 +63,14 @@ def lib():
         L.rxo_hilbert_os.argtypes = [_dp, ctypes.c_int64, _dp, ctypes.c_int32, ctypes.c_int32, _dp]
         L.rxo_gardner.argtypes = [_dp, ctypes.c_int64, _dp]
         L.rxo_farrow.argtypes = [_dp, ctypes.c_int64, _dp, _dp]
+        L.rxo_gardner_sums.argtypes = [_dp, ctypes.c_int64, _dp]
+        L.rxo_downshift_rev.argtypes = [ctypes.c_double, ctypes.c_int64]
+        L.rxo_downshift_rev.restype = ctypes.c_double
+        L.rxo_lms.argtypes = [_dp, ctypes.c_int64, _dp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, _dp,
+                              ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_int32), _dp]
+        L.rxo_cma.argtypes = [_dp, ctypes.c_int64, _dp, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                              ctypes.c_double, ctypes.c_int64, _dp, _dp]
+        L.rxo_vv_phase.argtypes = [_dp, ctypes.c_int64, _dp]
         L.rxo_decide.argtypes = [ctypes.c_double, ctypes.c_int32]
         L.rxo_decide.restype = ctypes.c_int32
         L.rxo_round_bf16.argtypes = [ctypes.c_double]
@@ -99,7 +107,7 @@ def default_cfg(fmt, seed, **kw) -> dict:
     d = dict(fmt=fmt, mf_taps=65 if kk else 33, ffe_taps=21 if kk else 15, prefix=4096,
              hilbert_taps=4097, os_log2=16, form=0, rounding=0, equalizer=0,
              rolloff=0.1, mu=1e-3, mu_cma=1e-3, fc_over_fs=0.55e9 / 4e9 if kk else 0.0,
-             seed=seed, mlp=None)
+             seed=seed, mlp=None, force=None)
     d.update(kw)
     return d
 
@@ -107,21 +115,28 @@ def default_cfg(fmt, seed, **kw) -> dict:
 def process(fmt, packed, n_samples, seed, want=("bits", "soft"), **kw) -> dict:
     """Run one buffer through the oracle chain.  `want` names the optional
     intermediate arrays to return (field, shifted, mf, timing, xr, soft,
-    taps, phase, bits)."""
+    ddz, taps, phase, bits).  force: optional int32[nsym] decision indices
+    the block DD-LMS takes instead of its own (-1: its own)."""
     d = default_cfg(fmt, seed, **kw)
     mlp = d.pop("mlp")
+    force = d.pop("force")
     cfg = Cfg(**d)
     keep = []
+    n = int(n_samples)
+    kk = is_kk(fmt)
+    nsym = n // (4 if kk else 2)
+    if force is not None:
+        force = np.ascontiguousarray(force, dtype=np.int32)
+        assert force.size == nsym
+        cfg.force = force.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        keep.append(force)
     if mlp is not None:
         mlp = _f64(mlp)
         assert mlp.size == MLP_PARAMS
         cfg.mlp = _p(mlp)
         keep.append(mlp)
-    n = int(n_samples)
-    kk = is_kk(fmt)
-    nsym = n // (4 if kk else 2)
     sizes = {"field": 2 * n, "shifted": 2 * n, "mf": n, "timing": n // 512, "xr": n,
-             "soft": 2 * nsym if kk else nsym, "taps": 2 * d["ffe_taps"],
+             "soft": 2 * nsym if kk else nsym, "ddz": 2 * nsym if kk else nsym, "taps": 2 * d["ffe_taps"],
              "phase": nsym // 128}
     out = Out()
     arrays = {}
@@ -139,7 +154,7 @@ def process(fmt, packed, n_samples, seed, want=("bits", "soft"), **kw) -> dict:
     if rc != 0:
         raise ValueError(f"oracle rejected the configuration (rc={rc})")
     res = {k: v for k, v in arrays.items()}
-    for k in ("field", "shifted", "soft", "taps") if kk else ("taps",):
+    for k in ("field", "shifted", "soft", "ddz", "taps") if kk else ("taps",):
         if k in res:
             res[k] = res[k].view(np.complex128)
     if kk and "mf" in res:
@@ -222,6 +237,55 @@ def farrow(x, delta):
     y = np.zeros_like(x)
     lib().rxo_farrow(_p(x), x.size, _p(delta), _p(y))
     return y
+
+
+def gardner_sums(x):
+    x = _f64(x)
+    c = np.zeros(x.size // 512, dtype=np.complex128)
+    lib().rxo_gardner_sums(_p(x), x.size, c.view(np.float64).ctypes.data_as(_dp))
+    return c
+
+
+def downshift_rev(r, n):
+    return float(lib().rxo_downshift_rev(float(r), int(n)))
+
+
+def lms(x, w, pos0, count, ref=None, m_axis=2, cplx_axis=True, mu=1e-3, force=None):
+    """LMS adaptation of the FFE (rxo_lms): returns (final taps, outputs)."""
+    x = np.ascontiguousarray(x, dtype=np.complex128)
+    w = np.ascontiguousarray(w, dtype=np.complex128).copy()
+    z = np.zeros(count, dtype=np.complex128)
+    rp = None
+    if ref is not None:
+        ref = np.ascontiguousarray(ref, dtype=np.complex128)
+        assert ref.size >= count
+        rp = ref.view(np.float64).ctypes.data_as(_dp)
+    fp = None
+    if force is not None:
+        force = np.ascontiguousarray(force, dtype=np.int32)
+        assert force.size >= count
+        fp = force.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    lib().rxo_lms(x.view(np.float64).ctypes.data_as(_dp), x.size, w.view(np.float64).ctypes.data_as(_dp),
+                  w.size, pos0, count, rp, m_axis, int(cplx_axis), mu, fp, z.view(np.float64).ctypes.data_as(_dp))
+    return w, z
+
+
+def cma(x, w, count, mu=1e-3, r2=1.0, nvv=2048):
+    """Constant-modulus adaptation (rxo_cma): returns (taps, sum z^4, outputs)."""
+    x = np.ascontiguousarray(x, dtype=np.complex128)
+    w = np.ascontiguousarray(w, dtype=np.complex128).copy()
+    z = np.zeros(count, dtype=np.complex128)
+    s4 = np.zeros(2)
+    lib().rxo_cma(x.view(np.float64).ctypes.data_as(_dp), x.size, w.view(np.float64).ctypes.data_as(_dp),
+                  w.size, count, mu, r2, nvv, _p(s4), z.view(np.float64).ctypes.data_as(_dp))
+    return w, complex(s4[0], s4[1]), z
+
+
+def vv_phase(s4):
+    s4 = np.ascontiguousarray(s4, dtype=np.complex128)
+    ph = np.zeros(s4.size)
+    lib().rxo_vv_phase(s4.view(np.float64).ctypes.data_as(_dp), s4.size, _p(ph))
+    return ph
 
 
 def decide(v, m):

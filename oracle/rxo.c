@@ -304,16 +304,19 @@ static uint32_t symbol_bits(int fmt, cplx z)
 /* ------------------------------------------------------------------ */
 static inline double at(const double *x, int64_t n, int64_t j) { return (j >= 0 && j < n) ? x[j] : 0.0; }
 
-void rxo_gardner(const double *x, int64_t n, double *delta)
+/* Detector sums per 512-sample block (256 symbols): C_b = G0_b + j G1_b,
+ * G0 the Gardner detector on the symbol-spaced samples, G1 the same detector
+ * a quarter symbol (half a sample) later, its samples taken by cubic Lagrange
+ * interpolation at mu = 1/2. */
+void rxo_gardner_sums(const double *x, int64_t n, double *cv)
 {
-  const int64_t blk = 512, nb = n / blk, win = 16;
-  cplx *c = (cplx *)malloc(sizeof(cplx) * (size_t)nb);
+  const int64_t nb = n / 512;
+  cplx *c = (cplx *)cv;
   for (int64_t b = 0; b < nb; b++) {
     double g0 = 0.0, g1 = 0.0;
     for (int64_t k = b * 256; k < (b + 1) * 256; k++) {
       int64_t s = 2 * k;
       g0 += at(x, n, s + 1) * (at(x, n, s) - at(x, n, s + 2));
-      /* the same detector a quarter symbol later: cubic Lagrange at +1/2 */
       double h0 = (-at(x, n, s - 1) + 9.0 * at(x, n, s) + 9.0 * at(x, n, s + 1) - at(x, n, s + 2)) / 16.0;
       double h1 = (-at(x, n, s) + 9.0 * at(x, n, s + 1) + 9.0 * at(x, n, s + 2) - at(x, n, s + 3)) / 16.0;
       double h2 = (-at(x, n, s + 1) + 9.0 * at(x, n, s + 2) + 9.0 * at(x, n, s + 3) - at(x, n, s + 4)) / 16.0;
@@ -321,12 +324,26 @@ void rxo_gardner(const double *x, int64_t n, double *delta)
     }
     c[b] = g0 + I * g1;
   }
+}
+
+/* Feed-forward timing estimate per block: the sums averaged over blocks
+ * b-16..b+16 (clipped at the ends), their angle, unwrapped across blocks,
+ * as a shift in samples.  The half-sample interpolator has the gain
+ * (18 cos(pi/4) - 2 cos(3 pi/4)) / 16 = 5 / (4 sqrt 2) at half the symbol
+ * rate, where the detector's timing information sits, and G1 is a product
+ * of two interpolated samples: it is scaled back by the inverse squared
+ * gain, 32 / 25, so that G0 and G1 are a quadrature pair of equal weight. */
+void rxo_gardner(const double *x, int64_t n, double *delta)
+{
+  const int64_t nb = n / 512, win = 16;
+  cplx *c = (cplx *)malloc(sizeof(cplx) * (size_t)(nb > 0 ? nb : 1));
+  rxo_gardner_sums(x, n, (double *)c);
   double prev_raw = 0.0, acc = 0.0;
   for (int64_t b = 0; b < nb; b++) {
     cplx s = 0.0;
     int64_t lo = b - win < 0 ? 0 : b - win, hi = b + win >= nb ? nb - 1 : b + win;
     for (int64_t j = lo; j <= hi; j++) s += c[j];
-    double raw = atan2(cimag(s), creal(s));
+    double raw = atan2(cimag(s) * (32.0 / 25.0), creal(s));
     if (b == 0) {
       acc = raw;
     } else {
@@ -459,17 +476,99 @@ static void ffe_update(const cplx *x, int64_t n, cplx *w, int k, int64_t pos, cp
   for (int i = 0; i < k; i++) w[i] += step * conj(xat(x, n, pos + c - i));
 }
 
+static double level(int32_t i, int32_t m) { return 2.0 * (double)i - (double)(m - 1); }
+
+/* LMS adaptation of the FFE over `count` symbols (Sec. 2: the PAM chain's
+ * LMS FFE, the KK chain's DD-LMS): for symbol j the output
+ * z_j = sum_i w_i x[pos0 + 2j + c - i] is formed first, then
+ * w_i += mu (d_j - z_j) conj(x[pos0 + 2j + c - i]).  d_j is ref[j] when a
+ * reference is given (training on known symbols), else the decision of z_j
+ * (m_axis levels per real axis; both axes when cplx_axis).  force[j] >= 0,
+ * if given, replaces decision j by the level with that index (i m + q for
+ * QAM): test instrumentation that follows another implementation's choice
+ * at a symbol lying on a threshold. */
+void rxo_lms(const double *xv, int64_t nx, double *wv, int32_t k, int64_t pos0, int64_t count,
+             const double *refv, int32_t m_axis, int32_t cplx_axis, double mu, const int32_t *force,
+             double *zv)
+{
+  const cplx *x = (const cplx *)xv, *ref = (const cplx *)refv;
+  cplx *w = (cplx *)wv, *zo = (cplx *)zv;
+  for (int64_t j = 0; j < count; j++) {
+    const int64_t pos = pos0 + 2 * j;
+    cplx z = ffe_out(x, nx, w, k, pos), d;
+    if (zo) zo[j] = z;
+    if (ref) {
+      d = ref[j];
+    } else if (force && force[j] >= 0) {
+      d = cplx_axis ? level(force[j] / m_axis, m_axis) + I * level(force[j] % m_axis, m_axis)
+                    : level(force[j], m_axis);
+    } else {
+      d = level(rxo_decide(creal(z), m_axis), m_axis);
+      if (cplx_axis) d += I * level(rxo_decide(cimag(z), m_axis), m_axis);
+    }
+    ffe_update(x, nx, w, k, pos, mu * (d - z));
+  }
+}
+
+/* Constant-modulus adaptation from sample 0 over `count` symbols: z_j as
+ * above (pos0 = 0), then w_i += mu z_j (r2 - |z_j|^2) conj(x[2j + c - i]).
+ * s4 (re, im) receives the sum of z_j^4 over the last nvv outputs (the
+ * static Viterbi-Viterbi phase estimate); z (optional) the outputs. */
+void rxo_cma(const double *xv, int64_t nx, double *wv, int32_t k, int64_t count, double mu, double r2,
+             int64_t nvv, double *s4v, double *zv)
+{
+  const cplx *x = (const cplx *)xv;
+  cplx *w = (cplx *)wv, *zo = (cplx *)zv, s4 = 0.0;
+  for (int64_t j = 0; j < count; j++) {
+    cplx z = ffe_out(x, nx, w, k, 2 * j);
+    if (zo) zo[j] = z;
+    if (j >= count - nvv) s4 += z * z * z * z;
+    double mag = creal(z) * creal(z) + cimag(z) * cimag(z);
+    ffe_update(x, nx, w, k, 2 * j, mu * z * (r2 - mag));
+  }
+  s4v[0] = creal(s4);
+  s4v[1] = cimag(s4);
+}
+
+/* Viterbi-Viterbi carrier phase per block from the blocks' sums of z^4:
+ * theta_b = 1/4 arg(-(S_{b-1} + S_b + S_{b+1})) (neighbours beyond the ends
+ * left out; E[a^4] < 0 for QPSK and 16QAM), unwrapped across blocks in
+ * multiples of pi/2, the symmetry of the constellation. */
+void rxo_vv_phase(const double *s4v, int64_t nb, double *phase)
+{
+  const cplx *s4 = (const cplx *)s4v;
+  double prev = 0.0, th = 0.0;
+  for (int64_t b = 0; b < nb; b++) {
+    cplx a = s4[b] + (b > 0 ? s4[b - 1] : 0.0) + (b + 1 < nb ? s4[b + 1] : 0.0);
+    double raw = 0.25 * carg(-a);
+    if (b == 0) {
+      th = raw;
+    } else {
+      double d = raw - prev;
+      th += d - (M_PI / 2.0) * floor(d / (M_PI / 2.0) + 0.5);
+    }
+    prev = raw;
+    phase[b] = th;
+  }
+}
+
+/* Downshift phase of sample n in revolutions, frac(r n), in FP64 (the
+ * frequency shift of the KK chain, Fig. 1d). */
+double rxo_downshift_rev(double r, int64_t n)
+{
+  double u = r * (double)n;
+  return u - floor(u);
+}
+
 /* Joint delay / rotation search on the known prefix: maximise
  * |sum_k z(k+s) conj(a_k)| over s in [-64, 64] (ties: smallest |s|, then
  * the negative one); rotation j^q with q = round(-arg(C)/(pi/2)) (KK only). */
 static void sync_search(int fmt, const cplx *x, int64_t n, const cplx *w, int k, int p,
-                        uint64_t seed, int32_t *lag, int32_t *rot)
+                        const cplx *a, int32_t *lag, int32_t *rot)
 {
   const int R = 64;
   cplx *z = (cplx *)malloc(sizeof(cplx) * (size_t)(p + 2 * R));
-  cplx *a = (cplx *)malloc(sizeof(cplx) * (size_t)p);
   for (int j = -R; j < p + R; j++) z[j + R] = ffe_out(x, n, w, k, 2 * (int64_t)j);
-  for (int j = 0; j < p; j++) a[j] = ref_symbol(fmt, seed, j);
   double best = -INFINITY;
   cplx bestc = 0.0;
   int bests = 0;
@@ -487,7 +586,6 @@ static void sync_search(int fmt, const cplx *x, int64_t n, const cplx *w, int k,
     *rot = (int32_t)(((q % 4) + 4) % 4);
   }
   free(z);
-  free(a);
 }
 
 static const cplx jpow[4] = {1.0, I, -1.0, -I};
@@ -499,7 +597,7 @@ int rxo_process(const rxo_cfg *cfg, const uint8_t *packed, int64_t n, rxo_out *o
 {
   const int fmt = cfg->fmt;
   if (fmt < 1 || fmt > 5 || n <= 0 || n % 1024) return -1;
-  const int kk = is_kk(fmt), bps = bps_of(fmt), sps = kk ? 4 : 2;
+  const int kk = is_kk(fmt), bps = bps_of(fmt), sps = kk ? 4 : 2, m = axis_levels(fmt);
   const int64_t nsym = n / sps, nd = n / 2;
   const int K = cfg->ffe_taps, c = (K - 1) / 2, P = cfg->prefix, G = 64;
   const int blk = kk ? 128 : 256;
@@ -534,37 +632,23 @@ int rxo_process(const rxo_cfg *cfg, const uint8_t *packed, int64_t n, rxo_out *o
     }
     mean /= (double)n;
     if (o->field) memcpy(o->field, e, sizeof(cplx) * (size_t)n);
-    /* carrier removal and downshift; the phase frac(r t) kept in FP64 */
-    cplx *sh = (cplx *)malloc(sizeof(cplx) * (size_t)n);
-    for (int64_t t = 0; t < n; t++) {
-      double u = cfg->fc_over_fs * (double)t;
-      u -= floor(u);
-      sh[t] = cexp(-2.0 * M_PI * I * u);
-    }
+    /* carrier removal and downshift, the phase frac(r t) kept in FP64 */
     cplx *y = (cplx *)malloc(sizeof(cplx) * (size_t)n);
-    if (rm == 0) {
-      for (int64_t t = 0; t < n; t++) y[t] = (e[t] - mean) * sh[t];
-      if (o->shifted) memcpy(o->shifted, y, sizeof(cplx) * (size_t)n);
-      rxo_fir_same_dec2_cplx((double *)y, n, hm, cfg->mf_taps, (double *)x);
-    } else {
-      /* precision form: the MF runs on the rounded downshifted field, the
-       * (linear) carrier term is removed after the filter as mean * MF(shift) */
-      double *hr = (double *)malloc(sizeof(double) * (size_t)cfg->mf_taps);
-      for (int i = 0; i < cfg->mf_taps; i++) hr[i] = rnd(rm, hm[i]);
-      for (int64_t t = 0; t < n; t++) y[t] = rndc(rm, e[t] * sh[t]);
-      if (o->shifted)
-        for (int64_t t = 0; t < n; t++) ((cplx *)o->shifted)[t] = (e[t] - mean) * sh[t];
-      cplx *tc = (cplx *)malloc(sizeof(cplx) * (size_t)nd);
-      rxo_fir_same_dec2_cplx((double *)y, n, hr, cfg->mf_taps, (double *)x);
-      rxo_fir_same_dec2_cplx((double *)sh, n, hr, cfg->mf_taps, (double *)tc);
-      for (int64_t m = 0; m < nd; m++) x[m] -= mean * tc[m];
-      free(tc);
-      free(hr);
+    for (int64_t t = 0; t < n; t++)
+      y[t] = (e[t] - mean) * cexp(-2.0 * M_PI * I * rxo_downshift_rev(cfg->fc_over_fs, t));
+    if (o->shifted) memcpy(o->shifted, y, sizeof(cplx) * (size_t)n);
+    if (rm) {
+      /* precision form: the matched filter's operands, the carrier-free
+       * downshifted field and the taps, rounded to the narrow type; the
+       * accumulation stays exact */
+      for (int64_t t = 0; t < n; t++) y[t] = rndc(rm, y[t]);
+      for (int i = 0; i < cfg->mf_taps; i++) hm[i] = rnd(rm, hm[i]);
     }
+    rxo_fir_same_dec2_cplx((double *)y, n, hm, cfg->mf_taps, (double *)x);
     nx = nd;
     o->mean_re = creal(mean);
     o->mean_im = cimag(mean);
-    free(ell); free(phi); free(hh); free(e); free(sh); free(y);
+    free(ell); free(phi); free(hh); free(e); free(y);
   } else {
     /* --- PAM front end (Sec. 2, first paragraph): DC removal, MF --- */
     double s = 0.0;
@@ -609,38 +693,27 @@ int rxo_process(const rxo_cfg *cfg, const uint8_t *packed, int64_t n, rxo_out *o
   }
 
   /* --- prefix: (KK) CMA + static VV phase; sync; data-aided LMS --- */
-  double ea2 = 0.0;
-  {
-    int m = axis_levels(fmt);
-    ea2 = (double)(m * m - 1) / 3.0 * (kk ? 2.0 : 1.0);
-  }
+  const double ea2 = (double)(m * m - 1) / 3.0 * (kk ? 2.0 : 1.0);
+  cplx *ref = (cplx *)malloc(sizeof(cplx) * (size_t)P);
+  for (int k = 0; k < P; k++) ref[k] = ref_symbol(fmt, cfg->seed, k);
   cplx *w = (cplx *)calloc((size_t)K, sizeof(cplx));
   o->theta0 = 0.0;
   if (kk) {
     const double r2 = fmt == RXO_KK_16QAM ? 1.32 : 1.0;
-    cplx s4 = 0.0;
+    double s4[2];
     w[c] = 1.0;
-    for (int k = 0; k < P; k++) {
-      cplx z = ffe_out(x, nx, w, K, 2 * (int64_t)k);
-      if (k >= P - 2048) s4 += z * z * z * z;
-      double mag = creal(z) * creal(z) + cimag(z) * cimag(z);
-      ffe_update(x, nx, w, K, 2 * (int64_t)k, cfg->mu_cma * z * (r2 - mag));
-    }
-    double th = 0.25 * carg(-s4);
+    rxo_cma((double *)x, nx, (double *)w, K, P, cfg->mu_cma, r2, 2048, s4, NULL);
+    double th = 0.25 * carg(-(s4[0] + I * s4[1]));
     o->theta0 = th;
     cplx rotv = sqrt(ea2) * cexp(-I * th);
     for (int i = 0; i < K; i++) w[i] *= rotv;
   } else {
     w[c] = sqrt(ea2);
   }
-  sync_search(fmt, x, nx, w, K, P, cfg->seed, &o->lag, &o->rot);
+  sync_search(fmt, x, nx, w, K, P, ref, &o->lag, &o->rot);
   const int64_t sh2 = 2 * (int64_t)o->lag;
   for (int i = 0; i < K; i++) w[i] *= jpow[o->rot];
-  for (int k = 0; k < P; k++) {
-    cplx a = ref_symbol(fmt, cfg->seed, k);
-    cplx z = ffe_out(x, nx, w, K, sh2 + 2 * (int64_t)k);
-    ffe_update(x, nx, w, K, sh2 + 2 * (int64_t)k, cfg->mu * (a - z));
-  }
+  rxo_lms((double *)x, nx, (double *)w, K, sh2, P, (double *)ref, m, kk, cfg->mu, NULL, NULL);
   if (o->taps)
     for (int i = 0; i < K; i++) { o->taps[2 * i] = creal(w[i]); o->taps[2 * i + 1] = cimag(w[i]); }
 
@@ -658,7 +731,7 @@ int rxo_process(const rxo_cfg *cfg, const uint8_t *packed, int64_t n, rxo_out *o
       soft[k] = yv;
     }
     for (int64_t k = G; k < P; k++) {
-      cplx a = ref_symbol(fmt, cfg->seed, k);
+      cplx a = ref[k];
       err_mlp += creal(decide_point(fmt, soft[k])) != creal(a);
       err_lms += creal(decide_point(fmt, ffe_out(x, nx, w, K, sh2 + 2 * k))) != creal(a);
     }
@@ -673,18 +746,22 @@ int rxo_process(const rxo_cfg *cfg, const uint8_t *packed, int64_t n, rxo_out *o
     }
     for (int64_t b = 0; b < nsym / blk; b++) {
       for (int i = 0; i < K; i++) wr[i] = (cfg->form == 1) ? rndc(rm, w[i]) : w[i];
-      for (int64_t k = b * blk; k < (b + 1) * blk; k++) {
-        if (cfg->form == 1) {   /* frozen taps: a plain FIR */
-          soft[k] = ffe_out(xq ? xq : x, nx, wr, K, sh2 + 2 * k);
-          continue;
-        }
-        cplx z = ffe_out(x, nx, wr, K, sh2 + 2 * k);
-        soft[k] = z;
-        ffe_update(x, nx, wr, K, sh2 + 2 * k, cfg->mu * (decide_point(fmt, z) - z));
+      if (cfg->form == 1) {   /* frozen taps: a plain FIR */
+        for (int64_t k = b * blk; k < (b + 1) * blk; k++) soft[k] = ffe_out(xq ? xq : x, nx, wr, K, sh2 + 2 * k);
+      } else {                /* block DD-LMS from the prefix taps */
+        rxo_lms((double *)x, nx, (double *)wr, K, sh2 + 2 * b * blk, blk, NULL, m, kk, cfg->mu,
+                cfg->force ? cfg->force + b * blk : NULL, (double *)(soft + b * blk));
       }
     }
     free(wr);
     free(xq);
+  }
+
+  if (o->ddz) {
+    for (int64_t k = 0; k < nsym; k++) {
+      if (kk) { o->ddz[2 * k] = creal(soft[k]); o->ddz[2 * k + 1] = cimag(soft[k]); }
+      else o->ddz[k] = creal(soft[k]);
+    }
   }
 
   /* --- KK: per-block Viterbi-Viterbi phase over blocks b-1..b+1, unwrapped
@@ -692,26 +769,20 @@ int rxo_process(const rxo_cfg *cfg, const uint8_t *packed, int64_t n, rxo_out *o
   if (kk) {
     int64_t nb = nsym / blk;
     cplx *s4 = (cplx *)malloc(sizeof(cplx) * (size_t)nb);
+    double *th = (double *)malloc(sizeof(double) * (size_t)nb);
     for (int64_t b = 0; b < nb; b++) {
       cplx a = 0.0;
       for (int64_t k = b * blk; k < (b + 1) * blk; k++) { cplx z2 = soft[k] * soft[k]; a += z2 * z2; }
       s4[b] = a;
     }
-    double prev = 0.0, th = 0.0;
+    rxo_vv_phase((double *)s4, nb, th);
     for (int64_t b = 0; b < nb; b++) {
-      cplx a = s4[b] + (b > 0 ? s4[b - 1] : 0.0) + (b + 1 < nb ? s4[b + 1] : 0.0);
-      double raw = 0.25 * carg(-a);
-      if (b == 0) th = raw;
-      else {
-        double d = raw - prev;
-        th += d - (M_PI / 2.0) * floor(d / (M_PI / 2.0) + 0.5);
-      }
-      prev = raw;
-      if (o->phase) o->phase[b] = th;
-      cplx rv = cexp(-I * th);
+      if (o->phase) o->phase[b] = th[b];
+      cplx rv = cexp(-I * th[b]);
       for (int64_t k = b * blk; k < (b + 1) * blk; k++) soft[k] *= rv;
     }
     free(s4);
+    free(th);
   }
 
   /* --- decisions, demapping, packing, error counting --- */
@@ -741,6 +812,6 @@ int rxo_process(const rxo_cfg *cfg, const uint8_t *packed, int64_t n, rxo_out *o
   }
   o->nbits = nsym * bps;
   o->counted_syms = cs; o->sym_errors = se; o->counted_bits = cb; o->bit_errors = be;
-  free(bits); free(soft); free(w); free(x); free(hm); free(code);
+  free(bits); free(soft); free(w); free(ref); free(x); free(hm); free(code);
   return 0;
 }

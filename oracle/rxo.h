@@ -33,6 +33,8 @@ typedef struct {
   double rolloff, mu, mu_cma, fc_over_fs;
   uint64_t seed;         /* reference sequence: bits of symbol k = top bits of SplitMix64(seed, k) */
   const double *mlp;     /* RXO_MLP_PARAMS packed parameters when equalizer == 1 */
+  const int32_t *force;  /* optional, nsym entries: decision index the block DD-LMS takes at that
+                            symbol instead of its own (-1: its own); test instrumentation */
 } rxo_cfg;
 
 /* Optional outputs: any pointer may be NULL. */
@@ -45,6 +47,8 @@ typedef struct {
   double *soft;      /* soft symbols in odd-integer units: PAM nsym, KK 2*nsym (after VV) */
   double *taps;      /* prefix taps w0 as complex pairs (2*ffe_taps) */
   double *phase;     /* KK: unwrapped per-block carrier phase (nsym/128) */
+  double *ddz;       /* equaliser outputs before the carrier-phase derotation (PAM nsym, KK 2*nsym):
+                        the values the block DD-LMS decides on */
   uint8_t *bits;     /* packed hard decisions, ceil(nsym*bps/8) bytes */
   double mean_re, mean_im;   /* KK: carrier mean; PAM: mean of v */
   double agc, theta0;
@@ -68,9 +72,17 @@ void rxo_fir_same(const double *x, int64_t n, const double *h, int32_t k, double
 void rxo_fir_same_dec2_cplx(const double *x, int64_t n, const double *h, int32_t k, double *y);
 void rxo_hilbert_direct(const double *l, int64_t n, const double *h, int32_t ntaps, double *phi);
 void rxo_hilbert_os(const double *l, int64_t n, const double *h, int32_t ntaps, int32_t log2n, double *phi);
+void rxo_gardner_sums(const double *x, int64_t n, double *c);
 void rxo_gardner(const double *x, int64_t n, double *delta);
 void rxo_farrow(const double *x, int64_t n, const double *delta, double *xr);
 int32_t rxo_decide(double v, int32_t m_axis);
+double rxo_downshift_rev(double r, int64_t n);
+void rxo_lms(const double *x, int64_t nx, double *w, int32_t k, int64_t pos0, int64_t count,
+             const double *ref, int32_t m_axis, int32_t cplx_axis, double mu, const int32_t *force,
+             double *z);
+void rxo_cma(const double *x, int64_t nx, double *w, int32_t k, int64_t count, double mu, double r2,
+             int64_t nvv, double *s4, double *z);
+void rxo_vv_phase(const double *s4, int64_t nb, double *phase);
 double rxo_round_bf16(double v);
 double rxo_round_fp16(double v);
 void rxo_mlp_forward(const double *p, const double *x, int64_t nb, int32_t rounding, double *y);

@@ -29,7 +29,7 @@ STAGES = ("kk_front", "kk_debug", "pam_sum", "pam_mf", "pam_gavg", "pam_unwrap",
 RX_MLP_PARAMS = 6273
 EXPORTS = ("rx_params_default", "rx_create", "rx_process", "rx_process_batch", "rx_process_batch_host",
            "rx_sync", "rx_errors",
-           "rx_errors_reset", "rx_debug_fetch", "rx_train_cfg_default", "rx_mlp_param_count",
+           "rx_errors_reset", "rx_latencies", "rx_debug_fetch", "rx_train_cfg_default", "rx_mlp_param_count",
            "rx_mlp_order_multiplier", "rx_train_mlp", "rx_train_mlp_data", "rx_mlp_grad", "rx_mlp_infer",
            "rx_set_mlp", "rx_get_mlp", "rx_save_weights", "rx_load_weights", "rx_stage_times",
            "rx_destroy", "rx_strerror")
@@ -43,12 +43,13 @@ class rx_params(ctypes.Structure):
                 ("rolloff", ctypes.c_double), ("mu", ctypes.c_double), ("mu_cma", ctypes.c_double),
                 ("carrier_hz", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("max_samples", ctypes.c_uint64), ("stream", ctypes.c_void_p),
-                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("deadline_s", ctypes.c_double), ("ref_bits", ctypes.c_void_p)]
 
 
 class rx_stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in
-                ("buffers", "symbols", "bits", "bit_errors", "symbol_errors", "fallbacks")]
+                ("buffers", "symbols", "bits", "bit_errors", "symbol_errors", "fallbacks", "late_buffers")]
 
 
 class rx_train_cfg(ctypes.Structure):
@@ -85,6 +86,7 @@ def lib() -> ctypes.CDLL:
         L.rx_sync.argtypes = [vp]
         L.rx_errors.argtypes = [vp, ctypes.POINTER(rx_stats)]
         L.rx_errors_reset.argtypes = [vp]
+        L.rx_latencies.argtypes = [vp, ctypes.POINTER(ctypes.c_double), sz, ctypes.POINTER(sz)]
         L.rx_debug_fetch.argtypes = [vp, i32, vp, sz]
         L.rx_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_uint64), i32]
@@ -174,6 +176,15 @@ def rx_errors(h: int) -> dict:
 
 def rx_errors_reset(h: int) -> None:
     _check(lib().rx_errors_reset(h), "rx_errors_reset")
+
+
+def rx_latencies(h: int, max_count: int = 1024) -> np.ndarray:
+    """Device-measured latencies (microseconds) of the handle's most recent
+    buffers, oldest first."""
+    us = (ctypes.c_double * max_count)()
+    cnt = ctypes.c_size_t()
+    _check(lib().rx_latencies(h, us, max_count, ctypes.byref(cnt)), "rx_latencies")
+    return np.array(us[: cnt.value])
 
 
 def rx_debug_fetch(h: int, stage: int, nbytes: int) -> bytes:
@@ -308,6 +319,9 @@ class Receiver:
 
     def reset(self) -> None:
         rx_errors_reset(self.h)
+
+    def latencies(self) -> np.ndarray:
+        return rx_latencies(self.h)
 
     def fetch(self, stage: int, n_samples: int) -> np.ndarray:
         nsym = n_samples // self.sps

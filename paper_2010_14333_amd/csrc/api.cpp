@@ -3,6 +3,7 @@
 // hipGraph replay of batches).
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -98,7 +99,7 @@ struct Alloc {
 };
 
 struct GraphCache {
-  std::vector<const void *> key;
+  std::vector<uint64_t> key;
   hipGraphExec_t exec = nullptr;
   hipStream_t capture = nullptr;   // library stream used only for capture (the null stream cannot be captured)
 };
@@ -108,6 +109,9 @@ struct GraphCache {
 struct rx_ctx {
   rx_format fmt;
   rx_params p;
+  uint64_t uid = 0;       // unique over the process: never reused by a later handle
+  uint64_t version = 0;   // bumped whenever the device job or the stage list can change
+  int wall_khz = 100000;  // device wall-clock rate
   int kk = 0, sps = 2, bps = 1, log2n = 14;
   hipStream_t stream = nullptr;
   RxJob hj{};
@@ -163,6 +167,8 @@ int rx_params_default(rx_format fmt, rx_params *p) {
   p->max_samples = (uint64_t)1 << 22;
   p->stream = nullptr;
   p->flags = 0;
+  p->deadline_s = 0.0;
+  p->ref_bits = nullptr;
   return RX_OK;
 }
 
@@ -310,8 +316,19 @@ int rx_create(rx_format fmt, double baud, double fs, const rx_params *pin, rx_ha
   if (p.equalizer == RX_EQ_MLP && kk) return RX_E_UNSUPPORTED;
   if (kk && !(std::fabs(p.carrier_hz) < fs / 2)) return RX_E_INVALID;
   if (p.max_samples < 65536 || p.max_samples > ((uint64_t)1 << 26) || p.max_samples % 1024) return RX_E_INVALID;
+  if (!(p.deadline_s >= 0.0) || (reinterpret_cast<uintptr_t>(p.ref_bits) & 3)) return RX_E_INVALID;
+  int wall_khz = 0;
+  {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev);
+    if (e != hipSuccess || wall_khz <= 0) return fail_hip(e != hipSuccess ? e : hipErrorInvalidValue, "wall clock rate");
+  }
 
+  static std::atomic<uint64_t> next_uid{1};
   rx_ctx *h = new rx_ctx();
+  h->uid = next_uid.fetch_add(1);
+  h->wall_khz = wall_khz;
   h->fmt = fmt;
   h->p = p;
   h->kk = kk;
@@ -343,6 +360,8 @@ int rx_create(rx_format fmt, double baud, double fs, const rx_params *pin, rx_ha
   J.sgn = p.carrier_hz >= 0 ? 1.0f : -1.0f;
   J.debug = (p.flags & RX_DEBUG_KEEP) ? 1 : 0;
   J.seed = p.seed;
+  J.deadline_ticks = p.deadline_s * 1e3 * wall_khz;
+  J.ticks_per_sample = 1e3 * wall_khz / fs;
 
   // matched filter: KK taps centred in 65 slots (zero padded)
   std::vector<double> hm = design_rrc(p.mf_taps, h->sps, p.rolloff);
@@ -398,13 +417,16 @@ int rx_create(rx_format fmt, double baud, double fs, const rx_params *pin, rx_ha
     h->mlp = A.get<float>(rx_mlp_params());
     ok = h->mlp != nullptr;
   }
-  // reference bits of every symbol a buffer of this handle can hold, plus
-  // two words of slack for the decision stage's two-word reads
+  // reference bits of every symbol a buffer of this handle can hold, unless
+  // the caller supplies its own stream of them
   const int64_t nsym_max = L / (kk ? 4 : 2);
-  const int64_t ref_words = (nsym_max * J.bps + 31) / 32 + 2;
-  uint32_t *refw = ok ? A.get<uint32_t>(ref_words) : nullptr;
-  ok = ok && refw != nullptr;
-  J.refw = refw;
+  const int64_t ref_words = (nsym_max * J.bps + 31) / 32;
+  uint32_t *refw = nullptr;
+  if (ok && !p.ref_bits) {
+    refw = A.get<uint32_t>(ref_words);
+    ok = refw != nullptr;
+  }
+  J.refw = p.ref_bits ? static_cast<const uint32_t *>(p.ref_bits) : refw;
   h->dsc = ok ? A.get<RxScalars>(1) : nullptr;
   h->dj = ok && h->dsc ? A.get<RxJob>(1) : nullptr;
   if (!h->dj) {
@@ -418,7 +440,7 @@ int rx_create(rx_format fmt, double baud, double fs, const rx_params *pin, rx_ha
     delete h;
     return fail_hip(hipGetLastError(), "rx_create upload");
   }
-  rx_launch_ref_fill(refw, ref_words, J.seed, J.bps, nsym_max, nullptr);
+  if (refw) rx_launch_ref_fill(refw, ref_words, J.seed, J.bps, nsym_max, nullptr);
   if (hipStreamSynchronize(nullptr) != hipSuccess) {
     delete h;
     return fail_hip(hipGetLastError(), "rx_create reference bits");
@@ -494,8 +516,10 @@ static int enqueue(rx_handle const *hs, const void *const *bufs, const size_t *n
   return e == hipSuccess ? RX_OK : fail_hip(e, "kernel launch");
 }
 
+static bool aligned4(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 3) == 0; }
+
 int rx_process(rx_handle h, const void *dev_buffer, size_t n_samples, void *dev_bits, size_t *n_bits_out) {
-  if (!h || !dev_buffer || !dev_bits) return RX_E_INVALID;
+  if (!h || !dev_buffer || !dev_bits || !aligned4(dev_buffer) || !aligned4(dev_bits)) return RX_E_INVALID;
   int rc = check_n(h, n_samples);
   if (rc) return rc;
   rc = enqueue(&h, &dev_buffer, &n_samples, &dev_bits, 1, h->stream, false);
@@ -509,7 +533,7 @@ int rx_process_batch(const rx_handle *hs, const void *const *bufs, const size_t 
                      int graph) {
   if (!hs || !bufs || !ns || !bits || count < 1 || count > RX_MAXB) return RX_E_INVALID;
   for (int i = 0; i < count; i++) {
-    if (!hs[i] || !bufs[i] || !bits[i]) return RX_E_INVALID;
+    if (!hs[i] || !bufs[i] || !bits[i] || !aligned4(bufs[i]) || !aligned4(bits[i])) return RX_E_INVALID;
     if (hs[i]->stream != hs[0]->stream) return RX_E_INVALID;
     for (int j = 0; j < i; j++)
       if (hs[j] == hs[i]) return RX_E_INVALID;
@@ -522,12 +546,17 @@ int rx_process_batch(const rx_handle *hs, const void *const *bufs, const size_t 
     rc = enqueue(hs, bufs, ns, bits, count, s, false);
   } else {
     GraphCache &gc = hs[0]->graph;
-    std::vector<const void *> key;
+    // a graph replays the stage list and job pointers of the handles it was
+    // captured with: keyed by each handle's process-unique id and version
+    // (bumped whenever its job or its stage list can change), not by its
+    // address, which a later handle may reuse
+    std::vector<uint64_t> key;
     for (int i = 0; i < count; i++) {
-      key.push_back(hs[i]);
-      key.push_back(bufs[i]);
-      key.push_back(bits[i]);
-      key.push_back(reinterpret_cast<const void *>(ns[i]));
+      key.push_back(hs[i]->uid);
+      key.push_back(hs[i]->version);
+      key.push_back(reinterpret_cast<uintptr_t>(bufs[i]));
+      key.push_back(reinterpret_cast<uintptr_t>(bits[i]));
+      key.push_back((uint64_t)ns[i]);
     }
     if (!gc.exec || gc.key != key) {
       if (gc.exec) {
@@ -614,7 +643,7 @@ int rx_errors(rx_handle h, rx_stats *out) {
   if (!h || !out) return RX_E_INVALID;
   hipError_t e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
-  unsigned long long st[6];
+  unsigned long long st[7];
   e = hipMemcpy(st, h->dsc->stats, sizeof(st), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return fail_hip(e, "hipMemcpy stats");
   out->buffers = st[0];
@@ -623,6 +652,27 @@ int rx_errors(rx_handle h, rx_stats *out) {
   out->bit_errors = st[3];
   out->symbol_errors = st[4];
   out->fallbacks = st[5];
+  out->late_buffers = st[6];
+  return RX_OK;
+}
+
+int rx_latencies(rx_handle h, double *us, size_t max, size_t *count) {
+  if (!h || (!us && max)) return RX_E_INVALID;
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
+  unsigned long long c = 0;
+  e = hipMemcpy(&c, &h->dsc->lat_count, sizeof(c), hipMemcpyDeviceToHost);
+  std::vector<unsigned int> ring(RX_LAT_RING);
+  if (e == hipSuccess) e = hipMemcpy(ring.data(), h->dsc->lat, sizeof(unsigned int) * RX_LAT_RING, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail_hip(e, "hipMemcpy latencies");
+  const size_t kept = (size_t)(c < RX_LAT_RING ? c : RX_LAT_RING);
+  const size_t nout = kept < max ? kept : max;
+  const double us_per_tick = 1e3 / h->wall_khz;
+  for (size_t i = 0; i < nout; i++) {   // the most recent nout, oldest first
+    const unsigned long long idx = c - nout + i;
+    us[i] = ring[idx % RX_LAT_RING] * us_per_tick;
+  }
+  if (count) *count = nout;
   return RX_OK;
 }
 
@@ -630,8 +680,9 @@ int rx_errors_reset(rx_handle h) {
   if (!h) return RX_E_INVALID;
   hipError_t e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
-  unsigned long long z[6] = {0, 0, 0, 0, 0, 0};
+  unsigned long long z[7] = {0, 0, 0, 0, 0, 0, 0};
   e = hipMemcpy(h->dsc->stats, z, sizeof(z), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(&h->dsc->lat_count, z, sizeof(z[0]), hipMemcpyHostToDevice);
   return e == hipSuccess ? RX_OK : fail_hip(e, "hipMemcpy stats");
 }
 
@@ -688,6 +739,7 @@ int rx_debug_fetch(rx_handle h, int stage, void *dst, size_t bytes) {
 
 // ---- learned equaliser ----------------------------------------------------
 static int upload_job(rx_handle h) {
+  h->version++;   // cached graphs of this handle are stale from here on
   hipError_t e = hipStreamSynchronize(h->stream);
   if (e == hipSuccess) e = hipMemcpy(h->dj, &h->hj, sizeof(RxJob), hipMemcpyHostToDevice);
   return e == hipSuccess ? RX_OK : fail_hip(e, "job upload");
@@ -757,6 +809,8 @@ static std::vector<float> mlp_init(uint64_t seed) {
 
 static int64_t gcd64(int64_t a, int64_t b) { return b ? gcd64(b, a % b) : a; }
 
+#define RX_TRAIN_INFLIGHT 256
+
 int rx_mlp_order_multiplier(int64_t ntrain) {
   int64_t m = 1000003;
   while (gcd64(m, ntrain) != 1) m += 2;
@@ -795,6 +849,10 @@ int rx_train_mlp_data(rx_handle h, const float *dev_x, const float *dev_t, size_
     rx_mlp_step(dev_x, dev_t, (int64_t)ntrain, t * c.batch, c.batch, mult, h->mlp, m, v, part, loss, nullptr, 1,
                 (float)c.lr, (float)c.beta1, (float)c.beta2, (float)c.eps, (float)c1, (float)c2, h->stream);
     e = hipGetLastError();
+    // at most RX_TRAIN_INFLIGHT steps (two launches each) queued ahead of the
+    // device: an unbounded queue of ~32k launches holds per-launch state in
+    // the runtime and in any tool that intercepts launches
+    if (e == hipSuccess && (t + 1) % RX_TRAIN_INFLIGHT == 0) e = hipStreamSynchronize(h->stream);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e == hipSuccess && final_loss) {

@@ -617,7 +617,10 @@ __global__ __launch_bounds__(256) void rx_decide(RxLaunch L) {
     // (bps k0) mod 32 of a word and end within the next)
     const int64_t ob = (int64_t)bps * k0;
     const auto rw = gptr(J.refw);
-    const uint32_t refc = (uint32_t)(((uint64_t)rw[ob >> 5] | ((uint64_t)rw[(ob >> 5) + 1] << 32)) >> (ob & 31));
+    // the second word only where the 8 bps bits cross into it: then it still
+    // holds bits of these symbols, so no read goes past the stream's last word
+    const uint64_t w1 = ((ob & 31) + 8 * bps > 32) ? (uint64_t)rw[(ob >> 5) + 1] : 0ull;
+    const uint32_t refc = (uint32_t)(((uint64_t)rw[ob >> 5] | (w1 << 32)) >> (ob & 31));
     float2 zv[8];
     if (kk) {   // complex soft symbols
 #pragma unroll
@@ -696,6 +699,22 @@ __global__ __launch_bounds__(256) void rx_decide(RxLaunch L) {
     if (blockIdx.x == 0) {
       atomicAdd(&J.sc->stats[0], 1ull);
       if (J.sc->fallback) atomicAdd(&J.sc->stats[5], 1ull);
+    }
+    // the buffer's last decision workgroup to finish closes its latency:
+    // wall clock now minus the start its first kernel recorded, against the
+    // deadline (the buffer's own real-time span n / fs unless one is set)
+    __threadfence();
+    const unsigned nwg = (unsigned)((nsym + DEC_SYMS - 1) / DEC_SYMS);
+    if (atomicAdd(&J.sc->done_wg, 1u) == nwg - 1) {
+      RxScalars *const sc = J.sc;
+      const unsigned long long t1 = (unsigned long long)wall_clock64();
+      const unsigned long long dt = t1 - *(volatile unsigned long long *)&sc->t_start;
+      const double budget = J.deadline_ticks > 0.0 ? J.deadline_ticks : (double)n * J.ticks_per_sample;
+      if ((double)dt > budget) atomicAdd(&sc->stats[6], 1ull);
+      const unsigned long long c = sc->lat_count;
+      sc->lat[c % RX_LAT_RING] = dt < 0xFFFFFFFFull ? (unsigned)dt : 0xFFFFFFFFu;
+      sc->lat_count = c + 1;
+      sc->done_wg = 0u;
     }
   }
 }

@@ -165,6 +165,7 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
   const int64_t blk[2] = {2 * (int64_t)blockIdx.x, 2 * (int64_t)blockIdx.x + 1};
   if (blk[0] >= nrb) return;
   const int64_t F[2] = {blk[0] * HOP - RX_KK_EDGE, blk[1] * HOP - RX_KK_EDGE};
+  if (blockIdx.x == 0 && threadIdx.x == 0) J.sc->t_start = (unsigned long long)wall_clock64();   // buffer start
 
   if (threadIdx.x < 128) {
     const int i = (int)threadIdx.x - 31;

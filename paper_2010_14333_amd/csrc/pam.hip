@@ -14,6 +14,7 @@ __global__ __launch_bounds__(256) void pam_sum(RxLaunch L) {
   const int64_t n = L.n[jb];
   const int64_t base = (int64_t)blockIdx.x * PAM_SUMW;
   if (base >= n) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) J.sc->t_start = (unsigned long long)wall_clock64();   // buffer start
   uint32_t s = 0;
   for (int g = threadIdx.x; g < PAM_SUMW / 8; g += 256) {
     const int64_t s0 = base + 8 * g;
@@ -192,7 +193,11 @@ __global__ __launch_bounds__(256) void pam_mf(RxLaunch L) {
   }
 }
 
-// Angle of the detector sums averaged over blocks b-16 .. b+16.
+// Angle of the detector sums averaged over blocks b-16 .. b+16.  The
+// quarter-symbol detector's samples come from the half-sample cubic
+// interpolator, whose gain at half the symbol rate is 5 / (4 sqrt 2); its
+// sums are scaled by the inverse squared gain, 32/25, so that both
+// detectors weigh the same in the angle.
 __global__ __launch_bounds__(256) void pam_gavg(RxLaunch L) {
   const int jb = blockIdx.y;
   const RxJob J = *L.job[jb];
@@ -205,7 +210,7 @@ __global__ __launch_bounds__(256) void pam_gavg(RxLaunch L) {
     re += J.gard[j].x;
     im += J.gard[j].y;
   }
-  J.delta[nb + b] = (float)atan2(im, re);   // raw angle, second half of the array
+  J.delta[nb + b] = (float)atan2(im * (32.0 / 25.0), re);   // raw angle, second half of the array
 }
 
 // Unwrap (wrapped differences + workgroup prefix sum), timing shift

@@ -8,6 +8,7 @@
 #define RX_GUARD 64         // symbols excluded at each end of the error-count window
 #define RX_LAG 64           // delay search range [-RX_LAG, RX_LAG] symbols
 #define RX_KMAX 32          // tap storage per handle
+#define RX_LAT_RING 1024    // per-buffer latencies a handle keeps (the most recent)
 
 // Per-buffer scalars written by the kernels (device memory, one per handle).
 struct RxScalars {
@@ -16,7 +17,12 @@ struct RxScalars {
   double theta0;            // static carrier phase of the CMA taps (KK)
   int32_t lag, rot, fallback, pad;
   float2 w0[RX_KMAX];       // prefix FFE taps
-  unsigned long long stats[6];  // buffers, symbols, bits, bit errors, symbol errors, fallbacks
+  unsigned long long stats[7];  // buffers, symbols, bits, bit errors, symbol errors, fallbacks,
+                                // buffers later than their deadline
+  unsigned long long t_start;   // wall-clock ticks when the buffer's first workgroup started
+  unsigned int done_wg, pad2;   // decision workgroups of the current buffer that have finished
+  unsigned long long lat_count; // buffers whose latency has been recorded
+  unsigned int lat[RX_LAT_RING];   // latency (ticks) of recorded buffer i at index i % RX_LAT_RING
 };
 
 // Everything a kernel needs about one handle (device memory, written once).
@@ -49,6 +55,8 @@ struct RxJob {
   const float *mlp;                 // PAM learned equaliser parameters (FP32) or null
   const uint32_t *refw;             // reference bits of symbols 0 .. max_samples / sps - 1, packed as the output
   RxScalars *sc;
+  double deadline_ticks;            // > 0: latency budget of every buffer in wall-clock ticks
+  double ticks_per_sample;          // otherwise the budget is n / fs: wall-clock ticks per input sample
 };
 
 // By-value launch description of one batch (kernel argument, < 4 KiB).

@@ -53,9 +53,12 @@ def test_mixed_batch_equals_single_buffers_and_graph_replays(rx):
         e5 = r.errors()
         assert e5["buffers"] == 5 * e["buffers"] and e5["bit_errors"] == 5 * e["bit_errors"]
     # one buffer of the batch against the oracle
-    o = oracle.process(fmts[0], gens[0]["packed"], n, gens[0]["seed"], want=("bits", "soft"))
-    _, _, untol = parity.compare_decisions(fmts[0], single[0], o["bits"], o["soft"], n // 4, 128)
-    assert not untol
+    want = ("bits", "soft", "ddz")
+    o = oracle.process(fmts[0], gens[0]["packed"], n, gens[0]["seed"], want=want)
+    dec = parity.compare_decisions(
+        fmts[0], single[0], o, n // 4, 128,
+        rerun=lambda f: oracle.process(fmts[0], gens[0]["packed"], n, gens[0]["seed"], want=want, force=f))
+    assert not dec.untolerated
     for r in recs:
         r.close()
 
@@ -85,25 +88,34 @@ def test_fft_size_invariance(rx):
         res[lg] = (bits, r.fetch(rx.RX_STAGE_FIELD, n), r.errors())
         r.close()
     assert parity.rel_rms(res[13][1], res[14][1]) < 1e-6
-    o = oracle.process(5, g["packed"], n, g["seed"], want=("bits", "soft"))
+    want = ("bits", "soft", "ddz")
+    o = oracle.process(5, g["packed"], n, g["seed"], want=want)
     for lg in (13, 14):
-        _, tol, untol = parity.compare_decisions(5, res[lg][0], o["bits"], o["soft"], n // 4, 128)
-        assert not untol and abs(res[lg][2]["bit_errors"] - o["bit_errors"]) <= tol
-
-
-PREC_NEAR = 2e-2   # one-ulp narrow-operand disagreements can move an output this far
+        dec = parity.compare_decisions(
+            5, res[lg][0], o, n // 4, 128,
+            rerun=lambda f: oracle.process(5, g["packed"], n, g["seed"], want=want, force=f))
+        assert not dec.untolerated
+        assert abs(res[lg][2]["bit_errors"] - dec.oracle["bit_errors"]) <= dec.tolerated_bits
 
 
 @pytest.mark.parametrize("prec", [1, 2])
 @pytest.mark.parametrize("n,seed", [(1 << 18, 51), (1 << 24, 401)])
 def test_precision_form(rx, prec, n, seed):
     """BF16 (1) / FP16 (2) Toeplitz-GEMM matched filter and frozen-tap FFE on
-    MFMA vs the oracle run with the same operand rounding (FP64 accumulate);
-    the error against the unrounded FP64 chain is reported."""
+    MFMA with FP32 accumulation, against the oracle's precision form (the
+    carrier-free downshifted field, the taps and the FFE operands rounded to
+    the narrow type, FP64 accumulation) and against the unrounded FP64 chain
+    of the same frozen-tap definition.  The kernel rounds its own operands
+    (not the oracle's), so the soft values differ by rounding noise: their
+    error against the unrounded chain must be of the same size as the
+    oracle's own (at most RATIO times it), decisions may differ only where
+    the oracle's soft value lies within DIST_SIGMAS times that noise of a
+    threshold, and error counts by at most those symbols' bits."""
     print(f"[precision] prec={prec} n={n} seed={seed}", flush=True)
     g = synth.generate(5, n, synth.derive_seed(seed, 0), 22.0)
     s = g["seed"]
     o_r = oracle.process(5, g["packed"], n, s, want=("bits", "soft", "mf", "taps"), form=1, rounding=prec)
+    o_f = oracle.process(5, g["packed"], n, s, want=("bits", "soft", "mf"), form=1, rounding=0)
     r = rx.Receiver(5, s, max_samples=n, debug=True, precision=prec)
     bits = r.process(_dev(g["packed"]), n).cpu().numpy()
     sc = r.fetch(rx.RX_STAGE_SCALARS, n)
@@ -112,21 +124,26 @@ def test_precision_form(rx, prec, n, seed):
     err = r.errors()
     r.close()
     assert int(sc[4]) == o_r["lag"] and int(sc[5]) == o_r["rot"]
-    rep = {"mf": parity.rel_rms(mf, o_r["mf"]), "soft": parity.rel_rms(soft, o_r["soft"])}
-    assert rep["mf"] < 1e-4 and rep["soft"] < 1e-3, rep
+    rep = {"mf_vs_fp64": parity.rel_rms(mf, o_f["mf"]), "mf_oracle_rounded_vs_fp64": parity.rel_rms(o_r["mf"], o_f["mf"]),
+           "soft_vs_fp64": parity.rel_rms(soft, o_f["soft"]),
+           "soft_oracle_rounded_vs_fp64": parity.rel_rms(o_r["soft"], o_f["soft"]),
+           "soft_vs_oracle_rounded": parity.rel_rms(soft, o_r["soft"])}
     nsym = n // 4
+    sigma = np.sqrt(np.mean(np.abs(soft - o_r["soft"]) ** 2) / 2)   # per real axis
     g_sym = parity.symbols_from_bits(bits, 5, nsym)
     o_sym = parity.symbols_from_bits(o_r["bits"], 5, nsym)
     dist = parity.threshold_distance(o_r["soft"], 5)
     bad = np.nonzero(g_sym != o_sym)[0]
-    assert np.all(dist[bad] <= PREC_NEAR), dist[bad][:10]
     tol_bits = int(sum(bin(int(a ^ b)).count("1") for a, b in zip(g_sym[bad], o_sym[bad])))
-    assert abs(err["bit_errors"] - o_r["bit_errors"]) <= tol_bits
-    # stated error against the unrounded FP64 chain (same frozen-tap definition)
-    o_f = oracle.process(5, g["packed"], n, s, want=("soft",), form=1, rounding=0)
-    rep["soft_vs_fp64_frozen"] = parity.rel_rms(soft, o_f["soft"])
-    rep["ber_gpu"] = err["bit_errors"] / err["bits"]
-    rep["ber_fp64_frozen"] = o_f["bit_errors"] / o_f["counted_bits"]
-    rep["mismatch"] = int(bad.size)
+    rep.update(sigma=float(sigma), mismatch=int(bad.size), max_mismatch_dist=float(dist[bad].max()) if bad.size else 0.0,
+               ber_gpu=err["bit_errors"] / err["bits"], ber_oracle_rounded=o_r["bit_errors"] / o_r["counted_bits"],
+               ber_fp64=o_f["bit_errors"] / o_f["counted_bits"])
     print(f"[precision]   {rep}", flush=True)
-    assert rep["soft_vs_fp64_frozen"] < 2e-2
+    assert rep["mf_vs_fp64"] <= RATIO * rep["mf_oracle_rounded_vs_fp64"], rep
+    assert rep["soft_vs_fp64"] <= RATIO * rep["soft_oracle_rounded_vs_fp64"], rep
+    assert np.all(dist[bad] <= max(DIST_SIGMAS * sigma, parity.NEAR)), dist[bad][:10]
+    assert abs(err["bit_errors"] - o_r["bit_errors"]) <= tol_bits
+
+
+RATIO = 4.0          # the kernel's rounding error against the oracle's, both against FP64
+DIST_SIGMAS = 8.0    # rounding-noise standard deviations (per axis) around a threshold

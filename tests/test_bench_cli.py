@@ -17,20 +17,23 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_traffic_figure_follows_the_sources(tmp_path, monkeypatch):
+    """A counter record is used only for the launch size it was taken at
+    and only while its recorded source hash equals the current sources'."""
     sys.path.insert(0, ROOT)
     import bench
-    t = bench.front_traffic(64)
     with open(os.path.join(ROOT, "profiles", "kk_front_kk16qam_2e22_b64_traffic.json")) as f:
         rec = json.load(f)
-    assert t is not None and t["bytes_per_launch"] == rec["bytes_per_launch"]
-    assert bench.front_traffic(16) is None   # recorded for 64-buffer launches only
-    # a recorded hash that does not match the sources turns the figure off
     fake = tmp_path / "profiles"
     fake.mkdir()
-    rec["source_sha256"] = "0" * 64
-    (fake / "kk_front_kk16qam_2e22_b64_traffic.json").write_text(json.dumps(rec))
     os.symlink(os.path.join(ROOT, "paper_2010_14333_amd"), tmp_path / "paper_2010_14333_amd")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    rec["source_sha256"] = bench.kernel_source_hash()
+    (fake / "kk_front_kk16qam_2e22_b64_traffic.json").write_text(json.dumps(rec))
+    t = bench.front_traffic(64)
+    assert t is not None and t["bytes_per_launch"] == rec["bytes_per_launch"]
+    assert bench.front_traffic(16) is None   # recorded for 64-buffer launches only
+    rec["source_sha256"] = "0" * 64
+    (fake / "kk_front_kk16qam_2e22_b64_traffic.json").write_text(json.dumps(rec))
     assert bench.front_traffic(64) is None
 
 
@@ -41,7 +44,10 @@ def test_traffic_figure_survives_comments_not_code(tmp_path, monkeypatch):
     sys.path.insert(0, ROOT)
     import bench
     (tmp_path / "profiles").mkdir()
-    shutil.copy(os.path.join(ROOT, "profiles", "kk_front_kk16qam_2e22_b64_traffic.json"), tmp_path / "profiles")
+    with open(os.path.join(ROOT, "profiles", "kk_front_kk16qam_2e22_b64_traffic.json")) as f:
+        rec = json.load(f)
+    rec["source_sha256"] = bench.kernel_source_hash()
+    (tmp_path / "profiles" / "kk_front_kk16qam_2e22_b64_traffic.json").write_text(json.dumps(rec))
     src = tmp_path / "paper_2010_14333_amd" / "csrc"
     src.mkdir(parents=True)
     for name in bench.KERNEL_SOURCES:

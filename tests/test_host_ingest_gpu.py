@@ -1,9 +1,12 @@
 """Host-resident buffers through rx_process_batch_host: bits and error counts
 equal those of the device path, for pinned and pageable host memory and for
-two calls in a row (the second on smaller buffers, reusing the staging)."""
+two calls in a row (the second on smaller buffers, reusing the staging), and
+every buffer's decisions against the FP64 oracle."""
 import numpy as np
 import pytest
 
+import oracle
+import parity
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -51,6 +54,16 @@ def test_host_ingest_equals_device_path(rx, pinned):
         for i, (o, b) in enumerate(zip(hout, ref_bits)):
             got = o.numpy() if pinned else o
             assert np.array_equal(got, b), f"buffer {i}"
+            if pinned:   # the host-ingested decisions against the oracle
+                f, g = fmts[i], gens[i]
+                want = ("bits", "soft", "ddz")
+                kk = f >= 4
+                orun = oracle.process(f, g["packed"], n, g["seed"], want=want)
+                dec = parity.compare_decisions(
+                    f, got, orun, n // (4 if kk else 2), 128 if kk else 256,
+                    rerun=lambda fo, f=f, g=g: oracle.process(f, g["packed"], n, g["seed"], want=want, force=fo))
+                assert not dec.untolerated, (i, dec.untolerated[:5])
+                assert abs(ref_errs[i]["bit_errors"] - dec.oracle["bit_errors"]) <= dec.tolerated_bits
         for r, e in zip(recs, ref_errs):
             assert r.errors() == e
             r.reset()

@@ -177,8 +177,8 @@ def test_mlp_stage_in_chain(rx, kind):
         assert np.all(dist[bad] <= MLP_NEAR), dist[bad][:10]
         assert abs(e["bit_errors"] - o["bit_errors"]) <= 3 * bad.size
     else:
-        _, tol, untol = parity.compare_decisions(3, bits, o["bits"], o["soft"], nsym, 256)
-        assert not untol and abs(e["bit_errors"] - o["bit_errors"]) <= tol
+        dec = parity.compare_decisions(3, bits, o, nsym, 256)
+        assert not dec.untolerated and abs(e["bit_errors"] - o["bit_errors"]) <= dec.tolerated_bits
 
 
 def test_mlp_stage_dense_window_in_chain(rx):
@@ -246,12 +246,12 @@ def test_weights_save_load_roundtrip(rx, tmp_path):
 
 def test_trained_mlp_beats_lms_on_nonlinear_pam8(rx):
     """Train on 4 x 2^22 chain-processed PAM-8 buffers (91 km, tanh driver,
-    24 dB; 2^24 samples), test on 4 fresh buffers: the BF16 MLP must make
+    24 dB; 2^24 samples), test on 8 fresh buffers: the BF16 MLP must make
     fewer bit errors than the LMS chain on the same buffers."""
     import torch
     n = 1 << 22
     train = [synth.pam8_91km(i, seed=501) for i in range(4)]
-    test = [synth.pam8_91km(i, seed=502) for i in range(4)]
+    test = [synth.pam8_91km(i, seed=502) for i in range(8)]
     r = rx.Receiver(rx.RX_PAM8, 0, max_samples=n, equalizer=rx.RX_EQ_MLP)
     tb = [_t(g["packed"]) for g in train]
     loss = rx.rx_train_mlp(r.h, [b.data_ptr() for b in tb], [n] * 4, [g["seed"] for g in train])

@@ -2,9 +2,10 @@
 
 Bars: reconstructed KK field relative RMS <= 1e-5; decisions bit-exact except
 symbols within 1e-3 (odd-integer level units) of a threshold in the oracle
-(plus the DD-LMS cascade rule of parity.compare_decisions); error counts
-differ by at most the tolerated bits; integer results (delay, quadrant)
-exact."""
+(a block DD-LMS decision taken the other way on a threshold is followed by
+re-running the oracle with that decision forced, parity.compare_decisions);
+error counts differ by at most the tolerated bits; integer results (delay,
+quadrant) exact."""
 import sys
 
 import numpy as np
@@ -15,6 +16,16 @@ import parity
 import synth
 
 pytestmark = pytest.mark.gpu
+
+# Bars, about ten times the errors the FP32 path measured against the FP64
+# oracle on these workloads (field ~1.6e-7, MF output ~4e-7 .. 6e-7, prefix
+# taps ~2e-6, PAM timing shift ~1e-7 samples): a real regression cannot hide
+# under them.  FIELD_BAR is also the benchmark spec's bound's tenth.
+FIELD_BAR = 2e-6
+MF_BAR = 5e-6
+TAPS_BAR = 2e-5
+TIMING_BAR = 2e-6      # samples, max over the timing blocks
+XR_BAR = 1e-5
 
 
 @pytest.fixture(scope="module")
@@ -49,7 +60,7 @@ def check_chain(rx, fmt, n, seed, snr, rxo=None, **gen):
     _log(f"[parity] fmt={fmt} n={n} seed={seed} snr={snr} {gen} {rxo}")
     g = synth.generate(fmt, n, seed, snr, **gen)
     kk = fmt >= 4
-    want = ("bits", "soft", "taps", "mf") + (("field",) if kk else ("timing", "xr"))
+    want = ("bits", "soft", "ddz", "taps", "mf") + (("field",) if kk else ("timing", "xr"))
     o = oracle.process(fmt, g["packed"], n, g["seed"], want=want, **rxo)
     res = run_gpu(rx, fmt, g, n, **rxo)
     r = res["r"]
@@ -58,36 +69,40 @@ def check_chain(rx, fmt, n, seed, snr, rxo=None, **gen):
     if kk:
         field = r.fetch(rx.RX_STAGE_FIELD, n)
         report["field"] = parity.rel_rms(field, o["field"])
-        assert report["field"] <= 1e-5, report
+        assert report["field"] <= FIELD_BAR, report
         mf = r.fetch(rx.RX_STAGE_MF, n)   # already AGC'd
         report["mf"] = parity.rel_rms(mf, o["mf"])
-        assert report["mf"] <= 2e-5, report
+        assert report["mf"] <= MF_BAR, report
         assert abs(complex(sc[0], sc[1]) - complex(o["mean_re"], o["mean_im"])) <= 1e-5 * abs(
             complex(o["mean_re"], o["mean_im"]))
     else:
         mf = r.fetch(rx.RX_STAGE_MF, n) * sc[2]
         report["mf"] = parity.rel_rms(mf, o["mf"])
-        assert report["mf"] <= 1e-5, report
+        assert report["mf"] <= MF_BAR, report
         d = r.fetch(rx.RX_STAGE_TIMING, n)
         report["timing"] = float(np.max(np.abs(d - o["timing"])))
-        assert report["timing"] <= 2e-4, report
+        assert report["timing"] <= TIMING_BAR, report
         xr = r.fetch(rx.RX_STAGE_XR, n)
         report["xr"] = parity.rel_rms(xr, o["xr"])
-        assert report["xr"] <= 1e-4, report
+        assert report["xr"] <= XR_BAR, report
         assert sc[0] == pytest.approx(o["mean_re"], rel=1e-15)
     assert int(sc[4]) == o["lag"] and int(sc[5]) == o["rot"], (sc, o["lag"], o["rot"])
     taps = r.fetch(rx.RX_STAGE_TAPS, n)
     report["taps"] = parity.rel_rms(taps, o["taps"])
-    assert report["taps"] <= 1e-3, report
+    assert report["taps"] <= TAPS_BAR, report
     nsym = n // (4 if kk else 2)
     blk = 128 if kk else 256
-    nbad, tol_bits, untol = parity.compare_decisions(fmt, res["bits"], o["bits"], o["soft"], nsym, blk)
-    report.update(mismatch=nbad, tolerated_bits=tol_bits, bit_errors=(res["err"]["bit_errors"], o["bit_errors"]))
+    dec = parity.compare_decisions(
+        fmt, res["bits"], o, nsym, blk,
+        rerun=lambda f: oracle.process(fmt, g["packed"], n, g["seed"], want=("bits", "soft", "ddz"), force=f, **rxo))
+    of = dec.oracle
+    report.update(mismatch=dec.mismatch, tolerated_bits=dec.tolerated_bits, forced=dec.forced,
+                  reruns=dec.reruns, bit_errors=(res["err"]["bit_errors"], of["bit_errors"]))
     _log(f"[parity]   {report}")
-    assert not untol, (untol[:10], report)
+    assert not dec.untolerated, (dec.untolerated[:10], report)
     e = res["err"]
-    assert e["buffers"] == 1 and e["symbols"] == o["counted_syms"] and e["bits"] == o["counted_bits"]
-    assert abs(e["bit_errors"] - o["bit_errors"]) <= tol_bits
+    assert e["buffers"] == 1 and e["symbols"] == of["counted_syms"] and e["bits"] == of["counted_bits"]
+    assert abs(e["bit_errors"] - of["bit_errors"]) <= dec.tolerated_bits
     r.close()
     return report
 
@@ -136,6 +151,24 @@ PAPER_VARIANTS = [
 @pytest.mark.parametrize("fmt,n,seed,gen", PAPER_VARIANTS)
 def test_parity_paper_link_variants(rx, fmt, n, seed, gen):
     check_chain(rx, fmt, n, seed, None, rxo={"rolloff": gen["rolloff"]}, **gen)
+
+
+# Receiver configurations the library accepts besides the defaults: the
+# other FFE length on each chain, and matched filters shorter than their
+# slots (centred in them); the oracle runs the same configuration.
+OPTION_CASES = [
+    (2, 1 << 18, 51, 18.0, {"ffe_taps": 21}),
+    (3, 1 << 18, 52, 24.0, {"ffe_taps": 21, "mf_taps": 21}),
+    (5, 1 << 18, 53, 20.0, {"ffe_taps": 15}),
+    (4, 1 << 18, 54, 16.0, {"ffe_taps": 15, "mf_taps": 41}),
+    (5, 1 << 18, 55, 22.0, {"mf_taps": 33}),
+    (1, 1 << 18, 56, 14.0, {"mf_taps": 17}),
+]
+
+
+@pytest.mark.parametrize("fmt,n,seed,snr,opts", OPTION_CASES)
+def test_parity_receiver_options(rx, fmt, n, seed, snr, opts):
+    check_chain(rx, fmt, n, seed, snr, rxo=opts)
 
 
 def test_parity_kk16qam_full_buffer(rx):
