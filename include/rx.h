@@ -113,10 +113,12 @@ typedef struct {
                                pointer, owned by the caller, to the reference bits of symbols
                                0 .. max_samples / sps - 1 packed like the output bits (4-byte
                                aligned, at least 4 * ceil(max_samples / sps * log2(M) / 32)
-                               bytes, valid while the handle processes buffers).  It is read
-                               by every buffer at the time its decision stage runs, so a
-                               caller counting buffers of different sequences on one handle
-                               rewrites it on the handle's stream between them. */
+                               bytes, valid while the handle processes buffers).  Both the
+                               known prefix (training, delay search) and the error count read
+                               it, while the buffer's kernels run, so a caller processing
+                               buffers of different sequences on one handle rewrites it on
+                               the handle's stream between them.  rx_train_mlp still takes
+                               its training buffers' sequences from its seeds. */
 } rx_params;
 
 /* Cumulative counters since create / rx_errors_reset.  Symbols counted are

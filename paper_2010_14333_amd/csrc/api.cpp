@@ -427,6 +427,7 @@ int rx_create(rx_format fmt, double baud, double fs, const rx_params *pin, rx_ha
     ok = refw != nullptr;
   }
   J.refw = p.ref_bits ? static_cast<const uint32_t *>(p.ref_bits) : refw;
+  J.ref_ext = p.ref_bits ? 1 : 0;
   h->dsc = ok ? A.get<RxScalars>(1) : nullptr;
   h->dj = ok && h->dsc ? A.get<RxJob>(1) : nullptr;
   if (!h->dj) {
@@ -890,8 +891,10 @@ int rx_train_mlp(rx_handle h, const void *const *dev_buffers, const size_t *n_sa
     return RX_E_NOMEM;
   }
   const uint64_t seed0 = h->hj.seed;
+  const int32_t ext0 = h->hj.ref_ext;
   const float *mlp0 = h->hj.mlp;
   h->hj.mlp = nullptr;   // training buffers run the plain front end and prefix
+  h->hj.ref_ext = 0;     // their known symbols come from their own seeds
   int rc = RX_OK;
   int64_t row0 = 0;
   for (int i = 0; i < count && rc == RX_OK; i++) {
@@ -912,6 +915,7 @@ int rx_train_mlp(rx_handle h, const void *const *dev_buffers, const size_t *n_sa
   }
   if (rc == RX_OK) e = hipStreamSynchronize(h->stream);
   h->hj.seed = seed0;
+  h->hj.ref_ext = ext0;
   h->hj.mlp = mlp0;
   int rc2 = upload_job(h);
   if (rc == RX_OK) rc = rc2;

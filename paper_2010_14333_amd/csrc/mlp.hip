@@ -389,3 +389,4 @@ void rx_mlp_step(const float *X, const float *T, int64_t ntrain, int64_t i0, int
   hipLaunchKernelGGL(mlp_reduce_adam, dim3((MP + 255) / 256), dim3(256), 0, s, p, m, v, part, nwg, grad, adam, lr,
                      b1, b2, eps, c1, c2);
 }
+

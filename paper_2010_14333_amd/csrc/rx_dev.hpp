@@ -139,9 +139,20 @@ __device__ __forceinline__ uint32_t gray_inverse(uint32_t g) {
   return i;
 }
 
-// Transmitted symbol k in odd-integer units (QAM: I bits first).
+// Bits of symbol k in a reference stream packed like the output (symbol k
+// at stream bits [bps k, bps (k + 1)), its most significant bit first).
+__device__ __forceinline__ uint32_t ref_stream_bits(const RxJob &J, int64_t k) {
+  const int64_t ob = (int64_t)J.bps * k;
+  uint64_t v = J.refw[ob >> 5];
+  if ((ob & 31) + J.bps > 32) v |= (uint64_t)J.refw[(ob >> 5) + 1] << 32;
+  const uint32_t f = (uint32_t)(v >> (ob & 31)) & ((1u << J.bps) - 1u);
+  return __builtin_bitreverse32(f) >> (32 - J.bps);
+}
+
+// Transmitted symbol k in odd-integer units (QAM: I bits first): from the
+// caller's reference stream if the handle has one, else from the seed.
 __device__ __forceinline__ float2 ref_symbol(const RxJob &J, int64_t k) {
-  const uint32_t b = (uint32_t)(splitmix64(J.seed, (uint64_t)k) >> (64 - J.bps));
+  const uint32_t b = J.ref_ext ? ref_stream_bits(J, k) : (uint32_t)(splitmix64(J.seed, (uint64_t)k) >> (64 - J.bps));
   const int m = J.m_axis;
   if (J.kk) {
     const int half = J.bps >> 1;

@@ -34,6 +34,7 @@ struct RxJob {
   double r;                         // carrier offset / fs (signed)
   float sgn;                        // Hilbert sign (+1: signal above the carrier)
   int32_t debug;                    // keep derotated soft symbols
+  int32_t ref_ext;                  // known symbols from the caller's reference stream (refw), not the seed
   uint64_t seed;
   float2 c0;                        // interior value of MF(exp(-j 2 pi r n)) / exp(-j 2 pi r 2m)
   const float *mf;                  // matched filter taps (65 centred for KK, 33 for PAM)

@@ -73,16 +73,21 @@ def test_graph_replay_follows_network_and_new_handles(rx):
     eager_soft = m.fetch(rx.RX_STAGE_SOFT, n)
     assert np.array_equal(graph_soft, eager_soft)
     assert not np.array_equal(graph_soft, lms_soft)
-    # destroy the KK handle, create another in its place, replay with graph
-    k_bits = ok.cpu().numpy().copy()
+    # destroy the KK handle, create another in its place (another reference
+    # sequence: other training symbols, so other decisions), replay with graph
     k.close()
-    k2 = rx.Receiver(rx.RX_KK_QPSK, gk["seed"] + 1, max_samples=n)   # another reference sequence
+    k2 = rx.Receiver(rx.RX_KK_QPSK, gk["seed"] + 1, max_samples=n)
     ok.zero_()
     run([m.h, k2.h], True)
-    e2 = k2.errors()
-    assert e2["buffers"] == 1
-    assert np.array_equal(ok.cpu().numpy(), k_bits)        # same buffer, same decisions
-    assert e2["bit_errors"] > 0.3 * e2["bits"]              # counted against the new handle's sequence
+    graph_bits = ok.cpu().numpy().copy()
+    e_graph = k2.errors()
+    k2.reset()
+    ok.zero_()
+    run([m.h, k2.h], False)
+    assert e_graph["buffers"] == 1
+    assert np.array_equal(graph_bits, ok.cpu().numpy())
+    e_eager = k2.errors()
+    assert e_graph["bit_errors"] == e_eager["bit_errors"] and e_graph["bits"] == e_eager["bits"]
     m.close()
     k2.close()
 
@@ -162,7 +167,9 @@ def test_caller_reference_stream(rx, fmt):
         b2 = s.process(_dev(g["packed"]), n).cpu().numpy()
         e2 = s.errors()
         s.close()
-        assert np.array_equal(bits, b2) and e == e2
+        assert np.array_equal(bits, b2)
+        assert {k: v for k, v in e.items() if k != "late_buffers"} == \
+            {k: v for k, v in e2.items() if k != "late_buffers"}
 
 
 def test_misaligned_pointers_rejected(rx):

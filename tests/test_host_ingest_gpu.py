@@ -65,7 +65,10 @@ def test_host_ingest_equals_device_path(rx, pinned):
                 assert not dec.untolerated, (i, dec.untolerated[:5])
                 assert abs(ref_errs[i]["bit_errors"] - dec.oracle["bit_errors"]) <= dec.tolerated_bits
         for r, e in zip(recs, ref_errs):
-            assert r.errors() == e
+            got_e = r.errors()
+            # latencies differ between the batch and the lone reference runs
+            assert {k: v for k, v in got_e.items() if k != "late_buffers"} == \
+                {k: v for k, v in e.items() if k != "late_buffers"}
             r.reset()
     for r in recs:
         r.close()

@@ -23,6 +23,11 @@ def rx():
     return rx
 
 
+def _counts(e):
+    """The error counters; late_buffers depends on where a buffer sat in its launch."""
+    return {k: v for k, v in e.items() if k != "late_buffers"}
+
+
 def _against_oracle(fmt, g, n, bits, err):
     want = ("bits", "soft", "ddz")
     o = oracle.process(fmt, g["packed"], n, g["seed"], want=want)
@@ -67,7 +72,7 @@ def test_bench_launch_configuration(rx):
         alone = rx.Receiver(5, gens[i % distinct]["seed"], max_samples=n)
         single = alone.process(bufs[i % distinct], n).cpu().numpy()
         assert np.array_equal(outs[i].cpu().numpy(), single), f"buffer {i}"
-        assert alone.errors() == errs[i]
+        assert _counts(alone.errors()) == _counts(errs[i])
         alone.close()
     # the same buffer through distinct handles of the batch: identical bits
     assert np.array_equal(outs[5].cpu().numpy(), outs[5 + distinct].cpu().numpy())
@@ -94,7 +99,7 @@ def test_every_format_full_size_in_one_batch(rx):
     errs = [r.errors() for r in recs]
     for j, i in enumerate(order[:len(fmts)]):
         k = j + len(fmts)
-        assert np.array_equal(outs[j].cpu().numpy(), outs[k].cpu().numpy()) and errs[j] == errs[k]
+        assert np.array_equal(outs[j].cpu().numpy(), outs[k].cpu().numpy()) and _counts(errs[j]) == _counts(errs[k])
         print(f"[scale] format {fmts[i]}", flush=True)
         _against_oracle(fmts[i], gens[i], n, outs[j].cpu().numpy(), errs[j])
     for r in recs:
