@@ -3,8 +3,18 @@
 
 One step = one batched pass of the whole KK chain (unpack .. error count)
 over `--batch` buffers of 2^22 packed 12-bit samples (KK-16QAM, 1 GBaud,
-CSPR 10 dB, 22 dB SNR; `--distinct` seeded buffers, reused round-robin by
-distinct receiver handles), inputs resident in HBM.  Prints one JSON line.
+CSPR 10 dB, 22 dB SNR), each buffer in its own device allocation (the
+`--distinct` seeded buffers are copied into `--batch` distinct device
+buffers, 384 MiB for 64: more than the chip's caches hold), inputs resident
+in HBM.  Prints one JSON line.
+
+Beside the headline: each stage timed alone on the chip (one stream, HIP
+events on that stream) for the roofline of the dominant kernel, per-kernel
+HBM traffic from committed counter records, the BF16/FP16 precision forms,
+their error and BER against the FP64 oracle on a 2^24-sample buffer, the
+PAM-8 learned-equaliser form, a mixed-format batch with per-buffer device
+latencies, the chain fed from host memory, and the FP64 oracle timed on the
+host's cores (all of them, and one).
 """
 import argparse
 import json
@@ -16,31 +26,43 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 N = 1 << 22
-# Algorithmic work per input sample of the fused KK front end (two complex
-# N-point FFTs per 2*hop samples at 5 N log2 N flop, Hilbert product, 65-tap
-# decimating matched filter on complex samples = 130 flop), and its bytes.
+FS = 4e9
 PEAK_HBM_GBS = 8000.0
-PEAK_FP32_VALU_TFLOPS = 78.6   # 256 CU x 64 FMA/clk x 2 x 2.4 GHz (no packed FP32)
+PEAK_FP32_TFLOPS = 157.3          # published MI355X FP32 vector peak (counts packed FP32 FMA)
+PEAK_FP32_NONPACKED_TFLOPS = 78.6  # 256 CU x 64 lanes x 2 FLOP x 2.4 GHz: the kernels issue no packed FP32
+METRIC = "sustained Gsamples/s for KK-16QAM chain, plain vs BF16/MLP at matched BER"
 
 
 def front_flop_per_sample(log2n):
+    """Algorithmic FLOP per input sample of the fused KK front end: two
+    complex N-point FFTs per 2 hop samples at 5 N log2 N, the Hilbert product
+    (2 N per pair), and the 65-tap decimating matched filter on complex
+    samples (65 complex-by-real MACs per output, one output per two
+    samples: 130)."""
     n = 1 << log2n
     hop = (n - 2048 - 2080 - 32) & ~15
     return (5.0 * n * log2n + 2.0 * n) / hop + 130.0
 
 
+# Counter records (two rocprofv3 --pmc passes each, FETCH_SIZE and WRITE_SIZE)
+# and the sources whose code they were taken on.
 KERNEL_SOURCES = ["kk.hip", "fft_lds.hpp", "rx_dev.hpp", "rx_shared.h"]
+EQ_SOURCES = ["eq.hip", "rx_dev.hpp", "rx_shared.h"]
+TRAFFIC = {
+    "kk_front": ("kk_front_kk16qam_2e22_b64_traffic.json", KERNEL_SOURCES),
+    "blocks": ("rx_blocks_kk16qam_2e22_b64_traffic.json", EQ_SOURCES),
+    "decide": ("rx_decide_kk16qam_2e22_b64_traffic.json", EQ_SOURCES),
+}
 
 
-def kernel_source_hash(root=None):
-    """SHA-256 of the front end's kernel sources with comments and blank
-    lines removed: what the counters were taken on is the code, so a change
-    to a comment leaves the figure valid and any change to the code does
-    not."""
+def kernel_source_hash(root=None, sources=None):
+    """SHA-256 of the named kernel sources with comments and blank lines
+    removed: the counters were taken on the code, so a change to a comment
+    leaves a figure valid and any change to the code does not."""
     import hashlib
     import re
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in sources or KERNEL_SOURCES:
         with open(os.path.join(root or ROOT, "paper_2010_14333_amd", "csrc", name)) as f:
             text = f.read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
@@ -50,21 +72,74 @@ def kernel_source_hash(root=None):
     return h.hexdigest()
 
 
-def front_traffic(batch):
-    """HBM bytes per kk_front launch from the committed counter summary, if it
-    was taken on the kernel code as it is now (else None)."""
-    path = os.path.join(ROOT, "profiles", "kk_front_kk16qam_2e22_b64_traffic.json")
+def traffic_record(stage, batch):
+    """HBM bytes per launch of a stage from its committed counter record, if
+    it was taken at this launch size on the kernel code as it is now (else
+    None)."""
+    if stage not in TRAFFIC:
+        return None
+    fname, sources = TRAFFIC[stage]
+    path = os.path.join(ROOT, "profiles", fname)
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("source_sha256") != kernel_source_hash() or t.get("buffers_per_launch") != batch:
+    if t.get("source_sha256") != kernel_source_hash(sources=sources) or t.get("buffers_per_launch") != batch:
         return None
     return {"bytes_per_launch": t["bytes_per_launch"], "source": os.path.relpath(path, ROOT)}
 
 
+def front_traffic(batch):
+    return traffic_record("kk_front", batch)
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+# ---- input generation in worker processes (before the GPU is touched) -------
+def _gen(job):
+    import synth
+    kind, a = job
+    if kind == "kk":
+        g = synth.kk_2e22(synth.KK_16QAM, index=a)
+    elif kind == "kk24":
+        g = synth.generate(synth.KK_16QAM, 1 << 24, synth.derive_seed(401, 0), 22.0)
+    elif kind == "mixed":
+        i, fmt, snr = a
+        g = synth.generate(fmt, N, synth.derive_seed(301, i), snr)
+    elif kind == "pam8":
+        seed, i = a
+        g = synth.pam8_91km(i, seed=seed)
+    else:
+        raise ValueError(kind)
+    return {"fmt": g["fmt"], "seed": g["seed"], "n": g["n_samples"], "packed": g["packed"]}
+
+
+def _oracle_kk(item):
+    import oracle
+    import synth
+    oracle.process(synth.KK_16QAM, item["packed"], item["n"], item["seed"], want=("bits",))
+    return item["n"]
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def usable_cores():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))   # the host share of one GPU
 
 
 def main():
@@ -73,20 +148,25 @@ def main():
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=64)
-    ap.add_argument("--distinct", type=int, default=8)
+    ap.add_argument("--distinct", type=int, default=8, help="distinct seeded buffers (copied into --batch allocations)")
     ap.add_argument("--graph", type=int, default=0)
     ap.add_argument("--streams", type=int, default=3,
                     help="consecutive batches alternate over this many HIP streams (batch pipelining)")
-    ap.add_argument("--one-stream", type=int, default=1, help="also time the chain on one stream (isolated stages)")
-    ap.add_argument("--cpu-buffers", type=int, default=24)
+    ap.add_argument("--roofline", type=int, default=1,
+                    help="time every stage alone on the chip (one stream, HIP events) for the roofline")
+    ap.add_argument("--roof-steps", type=int, default=5)
+    ap.add_argument("--cpu-buffers", type=int, default=4, help="oracle buffers per host core (0: no CPU baseline)")
     ap.add_argument("--copy-probe", type=int, default=1, help="run a 256 MiB device copy (counter scale)")
     ap.add_argument("--forms", default="bf16,fp16", help="precision forms timed beside the plain chain")
+    ap.add_argument("--precision-check", type=int, default=1,
+                    help="2^24-sample KK-16QAM buffer through FP32/BF16/FP16 against the FP64 oracle")
     ap.add_argument("--mlp", type=int, default=1, help="train and time the PAM-8 learned-equaliser form")
     ap.add_argument("--mixed", type=int, default=1, help="time a 64-buffer mixed-format batch (graph replay)")
+    ap.add_argument("--latency", type=int, default=1, help="per-buffer latency of small batches on one stream")
     ap.add_argument("--host", type=int, default=1, help="time the plain chain fed from pinned host memory")
     ap.add_argument("--fft-log2", type=int, default=0, choices=(0, 13, 14),
-                    help="KK overlap-save FFT size of the timed KK handles: 0 = the library's autotuner "
-                         "(2^14 on MI355X), 13 or 14 to pin it (counter runs pin 14)")
+                    help="KK overlap-save FFT size of the timed KK handles: 0 = the library's autotuner, "
+                         "13 or 14 to pin it (profiler runs pin 14)")
     ap.add_argument("--sweep", type=int, default=0,
                     help="Q-factor sweeps through the GPU chain, one 2^22 buffer per point: 1 = vs electrical "
                          "SNR for every format, 2 = vs OSNR for the paper's link variants, 3 = both")
@@ -96,28 +176,78 @@ def main():
               "so N GPUs would each run this single-GPU path on their share", file=sys.stderr)
         sys.exit(2)
 
+    import multiprocessing as mp
+
     import numpy as np
+    import synth
+
+    # every input generated first, in worker processes, before any GPU call
+    jobs = [("kk", i) for i in range(a.distinct)]
+    plan = synth.mixed_batch_formats(a.batch, seed=301) if a.mixed else []
+    jobs += [("mixed", (i, f, snr)) for i, (f, snr) in enumerate(plan)]
+    if a.mlp:
+        jobs += [("pam8", (501, i)) for i in range(4)] + [("pam8", (502, i)) for i in range(8)]
+    if a.precision_check:
+        jobs += [("kk24", 0)]
+    cores = usable_cores()
+    t0 = time.time()
+    with mp.get_context("fork").Pool(min(cores, len(jobs))) as pool:
+        made = pool.map(_gen, jobs, chunksize=1)
+    gens = [m for j, m in zip(jobs, made) if j[0] == "kk"]
+    mixed_gens = [m for j, m in zip(jobs, made) if j[0] == "mixed"]
+    train = [m for j, m in zip(jobs, made) if j[0] == "pam8" and j[1][0] == 501]
+    testg = [m for j, m in zip(jobs, made) if j[0] == "pam8" and j[1][0] == 502]
+    big = [m for j, m in zip(jobs, made) if j[0] == "kk24"]
+    log(f"[bench] generated {len(jobs)} input buffers in {time.time() - t0:.1f}s on {cores} processes")
+
+    # the FP64 oracle on the host's cores: all of them, then one (before the
+    # GPU is touched, so the worker processes fork from a plain process)
+    cpu = None
+    if a.cpu_buffers > 0:
+        items = [gens[i % len(gens)] for i in range(a.cpu_buffers * cores)]
+        t2 = time.perf_counter()
+        with mp.get_context("fork").Pool(cores) as pool:
+            done = sum(pool.map(_oracle_kk, items, chunksize=1))
+        t_all = time.perf_counter() - t2
+        one = items[: max(2, a.cpu_buffers)]
+        t3 = time.perf_counter()
+        done1 = sum(_oracle_kk(it) for it in one)
+        t_one = time.perf_counter() - t3
+        cpu = {"value": round(done / t_all / 1e9, 5), "unit": "Gsamples/s", "cores": cores, "kind": "oracle",
+               "sample": f"{len(items)} x 2^22-sample KK-16QAM buffers (22 dB) through the FP64 oracle, one buffer "
+                         f"per process, {cores} processes, {t_all:.1f} s wall",
+               "one_core": {"value": round(done1 / t_one / 1e9, 5), "unit": "Gsamples/s", "cores": 1,
+                            "sample": f"{len(one)} buffers, one process, {t_one:.1f} s"},
+               "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+        log(f"[bench] cpu baseline {cpu['value']} Gs/s on {cores} cores, {cpu['one_core']['value']} on one")
+
     import torch
 
     import paper_2010_14333_amd as rx
-    import synth
 
     dev = torch.device("cuda:0")
-    t0 = time.time()
-    gens = [synth.kk_2e22(synth.KK_16QAM, index=i) for i in range(a.distinct)]
-    log(f"[bench] generated {a.distinct} KK-16QAM buffers in {time.time() - t0:.1f}s")
-    bufs = [torch.from_numpy(g["packed"]).to(dev) for g in gens]
+    src = [torch.from_numpy(g["packed"]).to(dev) for g in gens]
+    bufs = [src[i % a.distinct].clone() for i in range(a.batch)]   # one allocation per buffer of the batch
+    del src
+    bp = [b.data_ptr() for b in bufs]
     streams = [torch.cuda.Stream(device=dev) for _ in range(max(1, a.streams))]   # default priority
+    torch.cuda.synchronize()
 
-    def run_form(precision, profile, nstreams=a.streams, steps=a.steps):
+    def seed_of(i):
+        return gens[i % a.distinct]["seed"]
+
+    def run_kk(precision, nstreams, steps, profile=False):
+        """`steps` batches of the KK-16QAM chain, consecutive batches
+        alternating over `nstreams` streams (one set of handles each);
+        with `profile`, HIP events on the first handle of each set time
+        every stage launch on that stream."""
         sets = []
-        for si, st in enumerate(streams[:max(1, nstreams)]):
-            recs = [rx.Receiver(rx.RX_KK_16QAM, gens[i % a.distinct]["seed"], max_samples=N, stream=st,
+        for st in streams[:nstreams]:
+            recs = [rx.Receiver(rx.RX_KK_16QAM, seed_of(i), max_samples=N, stream=st,
                                 flags=rx.RX_PROFILE if (i == 0 and profile) else 0,
                                 precision=precision, fft_log2=a.fft_log2) for i in range(a.batch)]
             outs = [torch.empty(r.bits_bytes(N), dtype=torch.uint8, device=dev) for r in recs]
             sets.append((recs, outs, [r.h for r in recs], [o.data_ptr() for o in outs]))
-        bp = [bufs[i % a.distinct].data_ptr() for i in range(a.batch)]
         ns = [N] * a.batch
 
         def step(i):
@@ -127,10 +257,9 @@ def main():
         for i in range(a.warmup * len(sets)):
             step(i)
         torch.cuda.synchronize()
-        heads = [hs[0] for _, _, hs, _ in sets]   # the profiled handle of each stream
         if profile:
-            for h in heads:
-                rx.rx_stage_times(h, reset=True)
+            for _, _, hs, _ in sets:
+                rx.rx_stage_times(hs[0], reset=True)
         for recs, _, _, _ in sets:
             for r in recs:
                 r.reset()
@@ -141,9 +270,9 @@ def main():
         torch.cuda.synchronize()
         wall = time.perf_counter() - t1
         stages = {}
-        if profile:   # every timed launch, whichever stream it ran on
-            for h in heads:
-                for k, (ms, cnt) in rx.rx_stage_times(h).items():
+        if profile:
+            for _, _, hs, _ in sets:
+                for k, (ms, cnt) in rx.rx_stage_times(hs[0]).items():
                     a0, c0 = stages.get(k, (0.0, 0))
                     stages[k] = (a0 + ms, c0 + cnt)
         errs = [r.errors() for recs, _, _, _ in sets for r in recs]
@@ -157,33 +286,35 @@ def main():
     def per_buffer(st):
         return {k: round(v[0] / v[1] * 1e3 / a.batch, 3) for k, v in st.items()}
 
-    wall, stages, ber = run_form(rx.RX_FP32, True)
-    log(f"[bench] plain chain: {a.steps} steps x {a.batch} buffers in {wall:.3f}s")
-    # the same chain on one stream, so that each stage's launch owns the chip
-    if a.one_stream:
-        wall1, stages1, _ = run_form(rx.RX_FP32, True, nstreams=1)
-        log(f"[bench] plain chain, one stream: {a.steps} steps in {wall1:.3f}s")
-    forms = {}
-    for name in [f for f in a.forms.split(",") if f]:
-        prec = {"bf16": rx.RX_BF16, "fp16": rx.RX_FP16}[name]
-        w2, _, b2 = run_form(prec, False)
-        forms[name] = {"value": round(a.batch * N / (w2 / a.steps) / 1e9, 3), "unit": "Gsamples/s",
-                       "ms_per_step": round(w2 * 1e3 / a.steps, 4), "ber": b2}
-        if a.one_stream:   # isolated stage times of the form
-            _, st1, _ = run_form(prec, True, nstreams=1)
-            forms[name]["one_stream_stage_us_per_buffer"] = per_buffer(st1)
-        log(f"[bench] {name} form: {forms[name]['value']} Gs/s, BER {b2}")
-
+    # headline: no profiling events on the timed launches
+    wall, _, ber = run_kk(rx.RX_FP32, a.streams, a.steps)
     ms_step = wall * 1e3 / a.steps
     samples = a.batch * N
     gsps = samples / (ms_step * 1e-3) / 1e9
+    log(f"[bench] plain chain: {a.steps} steps x {a.batch} buffers in {wall:.3f}s: {gsps:.2f} Gs/s")
 
-    def time_handles(make_recs, bp, steps, graph, lat=False, host=False):
+    stages1 = {}
+    if a.roofline:
+        wall1, stages1, _ = run_kk(rx.RX_FP32, 1, a.roof_steps, profile=True)
+        log(f"[bench] plain chain, one stream, stage events: {per_buffer(stages1)}")
+
+    forms = {}
+    for name in [f for f in a.forms.split(",") if f]:
+        prec = {"bf16": rx.RX_BF16, "fp16": rx.RX_FP16}[name]
+        w2, _, b2 = run_kk(prec, a.streams, a.steps)
+        forms[name] = {"value": round(samples / (w2 / a.steps) / 1e9, 3), "unit": "Gsamples/s",
+                       "ms_per_step": round(w2 * 1e3 / a.steps, 4), "ber": b2}
+        if a.roofline:
+            _, st1, _ = run_kk(prec, 1, a.roof_steps, profile=True)
+            forms[name]["one_stream_stage_us_per_buffer"] = per_buffer(st1)
+        log(f"[bench] {name} form: {forms[name]['value']} Gs/s, BER {b2}")
+
+    def time_handles(make_recs, bptrs, steps, graph, host=False):
         """Time `steps` batches, consecutive batches alternating over the
         streams (one set of handles per stream, made by make_recs(stream));
-        with lat, each batch's latency from events on its own stream; with
-        host, bp are pinned host buffers and the bits come back to pinned
-        host memory (rx_process_batch_host)."""
+        with host, bptrs are pinned host buffers and the bits come back to
+        pinned host memory (rx_process_batch_host).  Returns the wall time,
+        BER, per-handle counters and every buffer's device latency (us)."""
         sets = []
         for st in streams:
             recs = make_recs(st)
@@ -192,14 +323,14 @@ def main():
             else:
                 outs = [torch.empty(r.bits_bytes(N), dtype=torch.uint8, device=dev) for r in recs]
             sets.append((st, recs, outs, [r.h for r in recs], [o.data_ptr() for o in outs]))
-        ns = [N] * len(bp)
+        ns = [N] * len(bptrs)
 
         def step(i):
             _, _, _, hs, op = sets[i % len(sets)]
             if host:
-                rx.rx_process_batch_host(hs, bp, ns, op, graph=graph)
+                rx.rx_process_batch_host(hs, bptrs, ns, op, graph=graph)
             else:
-                rx.rx_process_batch(hs, bp, ns, op, graph=graph)
+                rx.rx_process_batch(hs, bptrs, ns, op, graph=graph)
 
         for i in range(a.warmup * len(sets)):
             step(i)
@@ -207,37 +338,32 @@ def main():
         for _, recs, _, _, _ in sets:
             for r in recs:
                 r.reset()
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(steps)] if lat else []
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for i in range(steps):
-            st = sets[i % len(sets)][0]
-            if lat:
-                evs[i][0].record(st)
             step(i)
-            if lat:
-                evs[i][1].record(st)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t1
         errs = [r.errors() for _, recs, _, _, _ in sets for r in recs]
+        lat = np.concatenate([r.latencies() for _, recs, _, _, _ in sets for r in recs])
         for _, recs, _, _, _ in sets:
             for r in recs:
                 r.close()
         bits = sum(e["bits"] for e in errs)
         ber = sum(e["bit_errors"] for e in errs) / bits if bits else None
-        ms = sorted(e0.elapsed_time(e1) for e0, e1 in evs)
-        return wall, ber, ms, errs
+        return wall, ber, errs, lat
+
+    def pct(v, q):
+        return round(float(np.percentile(v, q)), 1) if len(v) else None
 
     host_ingest = None
     if a.host:
         # the plain chain fed from pinned host memory: each buffer crosses PCIe
-        # in, its bits come back, on the same three streams as the kernels
+        # in, its bits come back, on the same streams as the kernels
         hb = [torch.from_numpy(g["packed"]).pin_memory() for g in gens]
         hbp = [hb[i % a.distinct].data_ptr() for i in range(a.batch)]
         wall_h, ber_h, _, _ = time_handles(
-            lambda st: [rx.Receiver(rx.RX_KK_16QAM, gens[i % a.distinct]["seed"], max_samples=N, stream=st,
-                                    fft_log2=a.fft_log2)
+            lambda st: [rx.Receiver(rx.RX_KK_16QAM, seed_of(i), max_samples=N, stream=st, fft_log2=a.fft_log2)
                         for i in range(a.batch)], hbp, a.steps, False, host=True)
         host_ingest = {"workload": f"KK-16QAM plain chain, {a.batch} x 2^22 buffers per batch from pinned host "
                                    f"memory, bits back to pinned host memory, {len(streams)} streams",
@@ -246,110 +372,84 @@ def main():
         log(f"[bench] host ingest {host_ingest}")
         del hb
 
+    precision = None
+    if a.precision_check and big:
+        # 2^24-sample KK-16QAM buffer: each dtype's soft values and BER against
+        # the FP64 oracle (the same frozen-tap definition, unrounded and with
+        # the precision form's rounding), the FP32 field against FP64
+        import oracle
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        import parity
+        gb = big[0]
+        nb = gb["n"]
+        d = torch.from_numpy(gb["packed"]).to(dev)
+        o_plain = oracle.process(5, gb["packed"], nb, gb["seed"], want=("field",))
+        o_frozen = oracle.process(5, gb["packed"], nb, gb["seed"], want=("soft",), form=1, rounding=0)
+        precision = {"workload": "KK-16QAM, one 2^24-sample buffer (1 GBaud, CSPR 10 dB, 22 dB SNR)"}
+        r = rx.Receiver(5, gb["seed"], max_samples=nb, debug=True)
+        r.process(d, nb)
+        field = r.fetch(rx.RX_STAGE_FIELD, nb)
+        e = r.errors()
+        r.close()
+        precision["fp32"] = {"field_rel_rms_vs_fp64": parity.rel_rms(field, o_plain["field"]),
+                             "ber": e["bit_errors"] / e["bits"], "ber_fp64": o_plain["bit_errors"] / o_plain["counted_bits"]}
+        for name, prec in (("bf16", rx.RX_BF16), ("fp16", rx.RX_FP16)):
+            o_r = oracle.process(5, gb["packed"], nb, gb["seed"], want=("soft",), form=1, rounding=prec)
+            r = rx.Receiver(5, gb["seed"], max_samples=nb, debug=True, precision=prec)
+            r.process(d, nb)
+            soft = r.fetch(rx.RX_STAGE_SOFT, nb)
+            e = r.errors()
+            r.close()
+            precision[name] = {
+                "soft_rel_rms_vs_fp64": parity.rel_rms(soft, o_frozen["soft"]),
+                "oracle_rounded_soft_rel_rms_vs_fp64": parity.rel_rms(o_r["soft"], o_frozen["soft"]),
+                "soft_rel_rms_vs_oracle_rounded": parity.rel_rms(soft, o_r["soft"]),
+                "ber": e["bit_errors"] / e["bits"], "ber_fp64_frozen": o_frozen["bit_errors"] / o_frozen["counted_bits"],
+                "ber_oracle_rounded": o_r["bit_errors"] / o_r["counted_bits"],
+                "delta_ber_vs_fp64_frozen": e["bit_errors"] / e["bits"] - o_frozen["bit_errors"] / o_frozen["counted_bits"]}
+        del d
+        log(f"[bench] precision check {precision}")
+
     q_sweep = q_osnr = None
-    if a.sweep & 1:
-        # BER -> Q of each format over an SNR range, one 2^22-sample buffer per
-        # point through the GPU chain; the oracle's BER beside it at one SNR
-        # per format (its decisions, so the same errors up to its rounding)
-        from scipy.special import erfcinv
-        import oracle
-
-        def q_db(ber):
-            return round(20.0 * np.log10(np.sqrt(2.0) * erfcinv(2.0 * ber)), 2) if ber and ber < 0.5 else None
-
-        names = {1: "PAM-2", 2: "PAM-4", 3: "PAM-8", 4: "KK-QPSK", 5: "KK-16QAM"}
-        snrs = [10, 12, 14, 16, 18, 20, 22, 24]
-        q_sweep = {}
-        for fmt in range(1, 6):
-            pts = []
-            for si, snr in enumerate(snrs):
-                g = synth.generate(fmt, N, synth.derive_seed(601, 16 * fmt + si), float(snr))
-                r = rx.Receiver(fmt, g["seed"], max_samples=N)
-                r.process(torch.from_numpy(g["packed"]).to(dev), N)
-                e = r.errors()
-                r.close()
-                ber = e["bit_errors"] / e["bits"] if e["bits"] else None
-                pt = {"snr_db": snr, "ber": ber, "q_db": q_db(ber)}
-                if snr == 16:
-                    o = oracle.process(fmt, g["packed"], N, g["seed"], want=("bits",))
-                    pt["oracle_ber"] = o["bit_errors"] / o["counted_bits"] if o["counted_bits"] else None
-                pts.append(pt)
-            q_sweep[names[fmt]] = pts
-            log(f"[bench] sweep {names[fmt]}: " + ", ".join(f"{p['snr_db']} dB {p['ber']:.2e}" for p in pts))
-    if a.sweep & 2:
-        # Q vs OSNR with the paper's own link parameters: optical noise (ASE)
-        # before detection and no electrical noise; RRC roll-off 0.01 for the
-        # KK formats at CSPR 11 and 6 dB, 0.5 for PAM; the receiver's matched
-        # filter designed for the same roll-off; the oracle's BER at the
-        # middle point of each curve
-        from scipy.special import erfcinv
-        import oracle
-
-        def q_db2(ber):
-            return round(20.0 * np.log10(np.sqrt(2.0) * erfcinv(2.0 * ber)), 2) if ber and ber < 0.5 else None
-
-        curves = [("KK-16QAM, CSPR 11 dB, RRC 0.01", 5, {"rolloff": 0.01, "cspr_db": 11.0}, range(14, 27, 2)),
-                  ("KK-16QAM, CSPR 6 dB, RRC 0.01", 5, {"rolloff": 0.01, "cspr_db": 6.0}, range(14, 27, 2)),
-                  ("KK-QPSK, CSPR 11 dB, RRC 0.01", 4, {"rolloff": 0.01, "cspr_db": 11.0}, range(4, 15, 2)),
-                  ("KK-QPSK, CSPR 6 dB, RRC 0.01", 4, {"rolloff": 0.01, "cspr_db": 6.0}, range(4, 15, 2)),
-                  ("PAM-4, RRC 0.5", 2, {"rolloff": 0.5}, range(10, 21, 2)),
-                  ("PAM-8, RRC 0.5", 3, {"rolloff": 0.5}, range(16, 29, 2))]
-        q_osnr = {}
-        for ci, (name, fmt, gen, osnrs) in enumerate(curves):
-            osnrs = list(osnrs)
-            pts = []
-            for si, osnr in enumerate(osnrs):
-                g = synth.generate(fmt, N, synth.derive_seed(701, 16 * ci + si), None, osnr_db=float(osnr), **gen)
-                r = rx.Receiver(fmt, g["seed"], max_samples=N, rolloff=gen["rolloff"])
-                r.process(torch.from_numpy(g["packed"]).to(dev), N)
-                e = r.errors()
-                r.close()
-                ber = e["bit_errors"] / e["bits"] if e["bits"] else None
-                pt = {"osnr_db": osnr, "ber": ber, "q_db": q_db2(ber)}
-                if si == len(osnrs) // 2:
-                    o = oracle.process(fmt, g["packed"], N, g["seed"], want=("bits",), rolloff=gen["rolloff"])
-                    pt["oracle_ber"] = o["bit_errors"] / o["counted_bits"] if o["counted_bits"] else None
-                pts.append(pt)
-            q_osnr[name] = pts
-            log(f"[bench] osnr sweep {name}: " + ", ".join(f"{p['osnr_db']} dB {p['ber']:.2e}" for p in pts))
+    if a.sweep:
+        q_sweep, q_osnr = sweeps(a, rx, torch, dev, np, synth)
 
     mlp_form = None
     if a.mlp:
-        t0 = time.time()
-        train = [synth.pam8_91km(i, seed=501) for i in range(4)]
-        testg = [synth.pam8_91km(i, seed=502) for i in range(4)]
-        log(f"[bench] generated PAM-8 91 km buffers in {time.time() - t0:.1f}s")
         trainer = rx.Receiver(rx.RX_PAM8, 0, max_samples=N, equalizer=rx.RX_EQ_MLP)
         tb = [torch.from_numpy(g["packed"]).to(dev) for g in train]
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        loss = rx.rx_train_mlp(trainer.h, [b.data_ptr() for b in tb], [N] * 4, [g["seed"] for g in train])
+        loss = rx.rx_train_mlp(trainer.h, [b.data_ptr() for b in tb], [N] * len(tb), [g["seed"] for g in train])
         train_s = time.perf_counter() - t2
         w = rx.rx_get_mlp(trainer.h)
         trainer.close()
         del tb
-        pb = [torch.from_numpy(g["packed"]).to(dev) for g in testg]
-        pbp = [pb[i % 4].data_ptr() for i in range(a.batch)]
+        tsrc = [torch.from_numpy(g["packed"]).to(dev) for g in testg]
+        pb = [tsrc[i % len(testg)].clone() for i in range(a.batch)]
+        del tsrc
+        pbp = [b.data_ptr() for b in pb]
         res = {}
         for eq in ("mlp", "lms"):
             def make(st, eq=eq):
-                recs = [rx.Receiver(rx.RX_PAM8, testg[i % 4]["seed"], max_samples=N, stream=st,
+                recs = [rx.Receiver(rx.RX_PAM8, testg[i % len(testg)]["seed"], max_samples=N, stream=st,
                                     equalizer=rx.RX_EQ_MLP if eq == "mlp" else rx.RX_EQ_LMS)
                         for i in range(a.batch)]
                 if eq == "mlp":
                     for r in recs:
                         rx.rx_set_mlp(r.h, w)
                 return recs
-            wl, ber_f, _, errs = time_handles(make, pbp, a.steps, bool(a.graph))
+            wl, ber_f, errs, _ = time_handles(make, pbp, a.steps, bool(a.graph))
             res[eq] = (a.batch * N / (wl / a.steps) / 1e9, ber_f, sum(e["fallbacks"] for e in errs))
-        mlp_form = {"workload": "PAM-8, 2 GBaud, 91 km SSMF, tanh driver, 24 dB; 2^22-sample buffers",
+        mlp_form = {"workload": f"PAM-8, 2 GBaud, 91 km SSMF, tanh driver, 24 dB; {len(testg)} distinct 2^22-sample "
+                                f"test buffers in {a.batch} allocations per batch",
                     "value": round(res["mlp"][0], 3), "unit": "Gsamples/s", "ber": res["mlp"][1],
                     "fallbacks": res["mlp"][2], "lms_value": round(res["lms"][0], 3), "lms_ber": res["lms"][1],
-                    "train_samples": 4 * N, "train_s": round(train_s, 3), "final_loss": round(loss, 5)}
-        if a.one_stream:
+                    "train_samples": len(train) * N, "train_s": round(train_s, 3), "final_loss": round(loss, 5)}
+        if a.roofline:
             # each PAM stage alone on the chip: one stream, stage events on one handle
             for eq in ("mlp", "lms"):
-                recs = [rx.Receiver(rx.RX_PAM8, testg[i % 4]["seed"], max_samples=N, stream=streams[0],
+                recs = [rx.Receiver(rx.RX_PAM8, testg[i % len(testg)]["seed"], max_samples=N, stream=streams[0],
                                     flags=rx.RX_PROFILE if i == 0 else 0,
                                     equalizer=rx.RX_EQ_MLP if eq == "mlp" else rx.RX_EQ_LMS)
                         for i in range(a.batch)]
@@ -362,7 +462,7 @@ def main():
                     rx.rx_process_batch(*args)
                 torch.cuda.synchronize()
                 rx.rx_stage_times(recs[0].h, reset=True)
-                for _ in range(5):
+                for _ in range(a.roof_steps):
                     rx.rx_process_batch(*args)
                 stt = rx.rx_stage_times(recs[0].h)
                 mlp_form[f"{eq}_one_stream_stage_us_per_buffer"] = {
@@ -370,114 +470,184 @@ def main():
                 for r in recs:
                     r.close()
                 del outs
+        del pb
         log(f"[bench] MLP form {mlp_form}")
 
     mixed = None
     if a.mixed:
-        plan = synth.mixed_batch_formats(a.batch, seed=301)
-        per_fmt = {}
-        t0 = time.time()
-        for i, (f, snr) in enumerate(plan):
-            if len(per_fmt.setdefault(f, [])) < 2:
-                per_fmt[f].append(synth.generate(f, N, synth.derive_seed(301, i), snr))
-        log(f"[bench] generated mixed-format buffers in {time.time() - t0:.1f}s")
-        dbuf = {f: [torch.from_numpy(g["packed"]).to(dev) for g in gl] for f, gl in per_fmt.items()}
-        cnt, slot, mbp = {}, [], []
-        for f, _ in plan:
-            j = cnt.get(f, 0) % len(per_fmt[f])
-            cnt[f] = cnt.get(f, 0) + 1
-            slot.append((f, j))
-            mbp.append(dbuf[f][j].data_ptr())
+        msrc = [torch.from_numpy(g["packed"]).to(dev) for g in mixed_gens]
+        mbp = [b.data_ptr() for b in msrc]
 
         def make_mixed(st):
-            return [rx.Receiver(f, per_fmt[f][j]["seed"], max_samples=N, stream=st) for f, j in slot]
-        wl, ber_m, ms, _ = time_handles(make_mixed, mbp, a.steps, True, lat=True)
-        p50 = ms[len(ms) // 2]
-        p99 = ms[min(len(ms) - 1, int(round(0.99 * (len(ms) - 1))))]
-        mixed = {"workload": f"{a.batch} x 2^22 buffers, formats mixed per buffer (SplitMix64 % 5), "
-                             f"SNR U[14, 26] dB, one hipGraph replay per batch, consecutive batches over "
+            return [rx.Receiver(g["fmt"], g["seed"], max_samples=N, stream=st) for g in mixed_gens]
+        wl, ber_m, errs, lat = time_handles(make_mixed, mbp, a.steps, True)
+        cnt = {}
+        for g in mixed_gens:
+            cnt[synth.FORMAT_NAMES[g["fmt"]]] = cnt.get(synth.FORMAT_NAMES[g["fmt"]], 0) + 1
+        mixed = {"workload": f"{a.batch} distinct 2^22-sample buffers, format per buffer SplitMix64 % 5, SNR per "
+                             f"buffer U[14, 26] dB, one hipGraph replay per batch, consecutive batches over "
                              f"{len(streams)} streams",
-                 "value": round(a.batch * N / (wl / a.steps) / 1e9, 3), "unit": "Gsamples/s",
-                 "formats": {synth.FORMAT_NAMES[f]: c for f, c in sorted(cnt.items())},
-                 "batch_latency_ms_p50": round(p50, 3), "batch_latency_ms_p99": round(p99, 3),
-                 "realtime_budget_ms_per_batch": round(a.batch * N / 4e9 * 1e3, 3), "ber": ber_m}
+                 "value": round(a.batch * N / (wl / a.steps) / 1e9, 3), "unit": "Gsamples/s", "formats": cnt,
+                 "buffer_latency_us_p50": pct(lat, 50), "buffer_latency_us_p99": pct(lat, 99),
+                 "buffers_timed": int(lat.size), "late_buffers": int(sum(e["late_buffers"] for e in errs)),
+                 "realtime_budget_us_per_buffer": round(N / FS * 1e6, 1), "ber": ber_m}
+        del msrc
         log(f"[bench] mixed batch {mixed}")
 
+    latency = None
+    if a.latency:
+        # small batches on one stream: the latency a buffer sees when the
+        # receiver keeps up with the ADC batch by batch
+        latency = {}
+        for lb in (1, 4, 16):
+            recs = [rx.Receiver(rx.RX_KK_16QAM, seed_of(i), max_samples=N, stream=streams[0], fft_log2=a.fft_log2)
+                    for i in range(lb)]
+            outs = [torch.empty(r.bits_bytes(N), dtype=torch.uint8, device=dev) for r in recs]
+            args = ([r.h for r in recs], bp[:lb], [N] * lb, [o.data_ptr() for o in outs])
+            for _ in range(3):
+                rx.rx_process_batch(*args)
+            torch.cuda.synchronize()
+            for r in recs:
+                r.reset()
+            reps = max(8, 256 // lb)
+            t1 = time.perf_counter()
+            for _ in range(reps):
+                rx.rx_process_batch(*args)
+            torch.cuda.synchronize()
+            wl = time.perf_counter() - t1
+            lat = np.concatenate([r.latencies() for r in recs])
+            late = sum(r.errors()["late_buffers"] for r in recs)
+            latency[f"batch_{lb}"] = {"buffer_latency_us_p50": pct(lat, 50), "buffer_latency_us_p99": pct(lat, 99),
+                                      "late_buffers": int(late), "buffers": int(lat.size),
+                                      "value": round(reps * lb * N / wl / 1e9, 3), "unit": "Gsamples/s"}
+            for r in recs:
+                r.close()
+        latency["realtime_budget_us_per_buffer"] = round(N / FS * 1e6, 1)
+        latency["workload"] = "KK-16QAM plain chain, batches of 1, 4 and 16 2^22-sample buffers on one stream"
+        log(f"[bench] latency {latency}")
+
     def roofline(st):
-        if not st:   # graph replays record no per-stage events
-            return {"bound": "alu", "achieved": None, "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-                    "frac": None, "traffic": None, "kernel": "kk_front<14>"}
-        # dominant kernel: the stage with the largest total time
-        dom = max(st, key=lambda k: st[k][0])
-        dom_ms = st[dom][0] / st[dom][1]
-        if dom != "kk_front":
-            return {"bound": "latency", "achieved": None, "peak": None, "unit": None, "frac": None,
-                    "traffic": None, "kernel": dom}
+        if not st or "kk_front" not in st:
+            return {"bound": "alu", "achieved": None, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": None,
+                    "traffic": None, "kernel": "kk_front<14,0>"}
         lg = a.fft_log2 or 14   # the autotuner's choice on MI355X when not pinned
+        dom_ms = st["kk_front"][0] / st["kk_front"][1]
         flop = front_flop_per_sample(lg) * samples
         achieved = flop / (dom_ms * 1e-3) / 1e12
-        return {"bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_FP32_VALU_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4), "traffic": None,
-                "kernel": f"kk_front<{lg}>", "flop_per_sample": round(front_flop_per_sample(lg), 2),
-                "launch_us": round(dom_ms * 1e3, 2)}
+        roof = {"bound": "alu", "kernel": f"kk_front<{lg},0>", "achieved": round(achieved, 2),
+                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                "peak_nonpacked": PEAK_FP32_NONPACKED_TFLOPS,
+                "frac_nonpacked": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4),
+                "flop_per_sample": round(front_flop_per_sample(lg), 2), "samples_per_launch": samples,
+                "launch_us": round(dom_ms * 1e3, 2), "timing": "HIP events around each launch on its stream, "
+                                                              "one stream (the kernel alone on the chip)",
+                "traffic": None}
+        hbm = {}
+        for stage in ("kk_front", "blocks", "decide"):
+            t = traffic_record(stage, a.batch)
+            if stage in st and t is not None:
+                us = st[stage][0] / st[stage][1] * 1e3
+                gbs = t["bytes_per_launch"] / (us * 1e-6) / 1e9
+                hbm[stage] = {"bytes_per_launch": t["bytes_per_launch"], "launch_us": round(us, 2),
+                              "gb_per_s": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4), "source": t["source"]}
+        if "kk_front" in hbm:
+            roof["traffic"] = hbm["kk_front"]["bytes_per_launch"]
+            roof["traffic_source"] = hbm["kk_front"]["source"]
+        roof["hbm_per_kernel"] = hbm
+        return roof
 
-    roof = roofline(stages)
-    traffic = front_traffic(a.batch)
-    if traffic is not None and roof.get("kernel") == "kk_front<14>":
-        roof["traffic"] = traffic["bytes_per_launch"]
-        roof["traffic_source"] = traffic["source"]
-    one = None
-    if a.one_stream:
-        roof1 = roofline(stages1)
-        roof1["value"] = round(samples / (wall1 / a.steps) / 1e9, 3)
-        one = {"stage_us_per_buffer": per_buffer(stages1), "roofline": roof1}
-
+    roof = roofline(stages1)
     if a.copy_probe:
-        src = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
+        probe_src = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        probe_dst = torch.empty_like(probe_src)
+        probe_dst.copy_(probe_src)
         torch.cuda.synchronize()
 
-    cpu = None
-    if a.cpu_buffers > 0:
-        import oracle
-        t2 = time.perf_counter()
-        k = a.cpu_buffers   # the distinct buffers, round-robin, as on the GPU
-        for i in range(k):
-            g = gens[i % a.distinct]
-            oracle.process(synth.KK_16QAM, g["packed"], N, g["seed"], want=("bits",))
-        ct = time.perf_counter() - t2
-        cpu = {"value": round(k * N / ct / 1e9, 5), "unit": "Gsamples/s", "cores": 1, "kind": "oracle",
-               "sample": f"{k} x 2^22-sample KK-16QAM buffers (22 dB), FP64 oracle, one thread, "
-                         f"{ct:.1f} s"}
-        log(f"[bench] cpu baseline {cpu['value']} Gs/s")
-
     out = {
-        "metric": "sustained Gsamples/s for KK-16QAM chain, plain vs BF16/MLP at matched BER",
+        "metric": METRIC,
         "value": round(gsps, 3), "unit": "Gsamples/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "KK-16QAM receiver chain, plain FP32, 2^22-sample 12-bit buffers "
                                "at 4 Gs/s (1 GBaud, CSPR 10 dB, 22 dB SNR)",
-                   "buffers_per_step": a.batch, "samples_per_buffer": N, "graph": bool(a.graph),
-                   "streams": a.streams},
+                   "buffers_per_step": a.batch, "samples_per_buffer": N, "distinct_inputs": a.distinct,
+                   "input_allocations": a.batch, "graph": bool(a.graph), "streams": a.streams},
         "realtime_factor": round(gsps / 4.0, 2),
         "ber": ber,
         "forms": forms,
+        "precision_check": precision,
         "mlp_form": mlp_form,
         "mixed_batch": mixed,
+        "latency": latency,
         "host_ingest": host_ingest,
         "q_vs_snr": q_sweep,
         "q_vs_osnr": q_osnr,
-        "stage_us_per_buffer": per_buffer(stages),
+        "one_stream_stage_us_per_buffer": per_buffer(stages1) if stages1 else None,
         "roofline": roof,
-        "one_stream": one,
         # algorithmic HBM fraction of the whole chain: 1.5 B in + 0.125 B of bits out per
         # sample (KK-16QAM: 4 bits per 4 samples) at the sustained rate, over 8 TB/s
         "algorithmic_hbm_frac": round(1.625 * gsps / PEAK_HBM_GBS, 5),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def sweeps(a, rx, torch, dev, np, synth):
+    """Q against electrical SNR (every format, bit 1 of --sweep) and against
+    OSNR with the paper's link parameters (bit 2), one 2^22-sample buffer per
+    point through the GPU chain, the oracle's BER at one point per curve."""
+    from scipy.special import erfcinv
+
+    import oracle
+
+    def q_db(ber):
+        return round(20.0 * np.log10(np.sqrt(2.0) * erfcinv(2.0 * ber)), 2) if ber and ber < 0.5 else None
+
+    def point(fmt, g, **rxo):
+        r = rx.Receiver(fmt, g["seed"], max_samples=N, **rxo)
+        r.process(torch.from_numpy(g["packed"]).to(dev), N)
+        e = r.errors()
+        r.close()
+        return e["bit_errors"] / e["bits"] if e["bits"] else None
+
+    q_sweep = q_osnr = None
+    if a.sweep & 1:
+        names = {1: "PAM-2", 2: "PAM-4", 3: "PAM-8", 4: "KK-QPSK", 5: "KK-16QAM"}
+        q_sweep = {}
+        for fmt in range(1, 6):
+            pts = []
+            for si, snr in enumerate([10, 12, 14, 16, 18, 20, 22, 24]):
+                g = synth.generate(fmt, N, synth.derive_seed(601, 16 * fmt + si), float(snr))
+                ber = point(fmt, g)
+                pt = {"snr_db": snr, "ber": ber, "q_db": q_db(ber)}
+                if snr == 16:
+                    o = oracle.process(fmt, g["packed"], N, g["seed"], want=("bits",))
+                    pt["oracle_ber"] = o["bit_errors"] / o["counted_bits"] if o["counted_bits"] else None
+                pts.append(pt)
+            q_sweep[names[fmt]] = pts
+            log(f"[bench] sweep {names[fmt]}: " + ", ".join(f"{p['snr_db']} dB {p['ber']:.2e}" for p in pts))
+    if a.sweep & 2:
+        curves = [("KK-16QAM, CSPR 11 dB, RRC 0.01", 5, {"rolloff": 0.01, "cspr_db": 11.0}, range(14, 27, 2)),
+                  ("KK-16QAM, CSPR 6 dB, RRC 0.01", 5, {"rolloff": 0.01, "cspr_db": 6.0}, range(14, 27, 2)),
+                  ("KK-QPSK, CSPR 11 dB, RRC 0.01", 4, {"rolloff": 0.01, "cspr_db": 11.0}, range(4, 15, 2)),
+                  ("KK-QPSK, CSPR 6 dB, RRC 0.01", 4, {"rolloff": 0.01, "cspr_db": 6.0}, range(4, 15, 2)),
+                  ("PAM-4, RRC 0.5", 2, {"rolloff": 0.5}, range(10, 21, 2)),
+                  ("PAM-8, RRC 0.5", 3, {"rolloff": 0.5}, range(16, 29, 2))]
+        q_osnr = {}
+        for ci, (name, fmt, gen, osnrs) in enumerate(curves):
+            osnrs = list(osnrs)
+            pts = []
+            for si, osnr in enumerate(osnrs):
+                g = synth.generate(fmt, N, synth.derive_seed(701, 16 * ci + si), None, osnr_db=float(osnr), **gen)
+                ber = point(fmt, g, rolloff=gen["rolloff"])
+                pt = {"osnr_db": osnr, "ber": ber, "q_db": q_db(ber)}
+                if si == len(osnrs) // 2:
+                    o = oracle.process(fmt, g["packed"], N, g["seed"], want=("bits",), rolloff=gen["rolloff"])
+                    pt["oracle_ber"] = o["bit_errors"] / o["counted_bits"] if o["counted_bits"] else None
+                pts.append(pt)
+            q_osnr[name] = pts
+            log(f"[bench] osnr sweep {name}: " + ", ".join(f"{p['osnr_db']} dB {p['ber']:.2e}" for p in pts))
+    return q_sweep, q_osnr
 
 
 if __name__ == "__main__":
