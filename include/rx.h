@@ -270,6 +270,20 @@ int rx_train_mlp_data(rx_handle h, const float *dev_x, const float *dev_t, size_
 /* Gradient of (1/n) sum (y - t)^2 at the handle's weights over n <= 65536
  * rows (device x, t as above) into dev_grad[RX_MLP_PARAMS].  Synchronous. */
 int rx_mlp_grad(rx_handle h, const float *dev_x, const float *dev_t, size_t n, float *dev_grad, double *loss);
+/* rx_mlp_grad for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and result, but the per-workgroup gradient partials live
+ * in a static device array of the library (3.1 MiB per GPU, held until the
+ * process ends) instead of memory allocated per call, so the call allocates
+ * nothing.  n <= 8192 rows (RX_E_INVALID beyond that limit); the caller
+ * passes x, t and dev_grad as for rx_mlp_grad; *loss (may be NULL) as
+ * there.  Synchronous.  Every call on one GPU shares that GPU's array, which
+ * keeps the last call's partials (each call overwrites all it reads):
+ * calls that overlap on one GPU, from several threads or on several
+ * streams, race.  RX_E_UNSUPPORTED on KK handles, RX_E_STATE before the
+ * handle has weights. */
+int rx_mlp_grad_static(rx_handle h, const float *dev_x, const float *dev_t, size_t n, float *dev_grad,
+                       double *loss);
 /* BF16 MFMA inference (the kernel of the chain's MLP stage) on given rows:
  * dev_x = n rows of 32 floats, dev_y = n outputs.  Asynchronous. */
 int rx_mlp_infer(rx_handle h, const float *dev_x, size_t n, float *dev_y);

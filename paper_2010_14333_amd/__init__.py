@@ -30,7 +30,8 @@ RX_MLP_PARAMS = 6273
 EXPORTS = ("rx_params_default", "rx_create", "rx_process", "rx_process_batch", "rx_process_batch_host",
            "rx_sync", "rx_errors",
            "rx_errors_reset", "rx_latencies", "rx_debug_fetch", "rx_train_cfg_default", "rx_mlp_param_count",
-           "rx_mlp_order_multiplier", "rx_train_mlp", "rx_train_mlp_data", "rx_mlp_grad", "rx_mlp_infer",
+           "rx_mlp_order_multiplier", "rx_train_mlp", "rx_train_mlp_data", "rx_mlp_grad", "rx_mlp_grad_static",
+           "rx_mlp_infer",
            "rx_set_mlp", "rx_get_mlp", "rx_save_weights", "rx_load_weights", "rx_stage_times",
            "rx_destroy", "rx_strerror")
 
@@ -99,6 +100,7 @@ def lib() -> ctypes.CDLL:
                                    i32, ctypes.POINTER(rx_train_cfg), dp]
         L.rx_train_mlp_data.argtypes = [vp, vp, vp, sz, ctypes.POINTER(rx_train_cfg), dp]
         L.rx_mlp_grad.argtypes = [vp, vp, vp, sz, vp, dp]
+        L.rx_mlp_grad_static.argtypes = [vp, vp, vp, sz, vp, dp]
         L.rx_mlp_infer.argtypes = [vp, vp, sz, vp]
         L.rx_set_mlp.argtypes = [vp, fp]
         L.rx_get_mlp.argtypes = [vp, fp]
@@ -236,6 +238,14 @@ def rx_train_mlp_data(h: int, dev_x: int, dev_t: int, n: int, cfg=None, init=Non
 def rx_mlp_grad(h: int, dev_x: int, dev_t: int, n: int, dev_grad: int) -> float:
     loss = ctypes.c_double()
     _check(lib().rx_mlp_grad(h, dev_x, dev_t, n, dev_grad, ctypes.byref(loss)), "rx_mlp_grad")
+    return loss.value
+
+
+def rx_mlp_grad_static(h: int, dev_x: int, dev_t: int, n: int, dev_grad: int) -> float:
+    """rx_mlp_grad with its partials in the library's static device array
+    (no allocation; n <= 8192)."""
+    loss = ctypes.c_double()
+    _check(lib().rx_mlp_grad_static(h, dev_x, dev_t, n, dev_grad, ctypes.byref(loss)), "rx_mlp_grad_static")
     return loss.value
 
 

@@ -121,6 +121,7 @@ struct rx_ctx {
   int64_t last_n = 0;
   GraphCache graph;
   float *mlp = nullptr;   // learned-equaliser parameters (device), allocated with the handle
+  void *scratch = nullptr;   // this device's static gradient partials (rx_mlp_grad_static)
   bool mlp_ready = false;
   uint8_t *hin = nullptr, *hbits = nullptr;   // host-ingest staging (device), allocated on first use
   // stage timing (RX_PROFILE): events recorded around every stage launch
@@ -416,6 +417,13 @@ int rx_create(rx_format fmt, double baud, double fs, const rx_params *pin, rx_ha
   if (ok && !kk) {
     h->mlp = A.get<float>(rx_mlp_params());
     ok = h->mlp != nullptr;
+    if (ok) {
+      const int se = rx_mlp_scratch_resolve(&h->scratch);
+      if (se) {
+        delete h;
+        return fail_hip((hipError_t)se, "hipGetSymbolAddress (static gradient partials)");
+      }
+    }
   }
   // reference bits of every symbol a buffer of this handle can hold, unless
   // the caller supplies its own stream of them
@@ -951,6 +959,29 @@ int rx_mlp_grad(rx_handle h, const float *dev_x, const float *dev_t, size_t n, f
   hipFree(part);
   hipFree(loss);
   return e == hipSuccess ? RX_OK : fail_hip(e, "rx_mlp_grad");
+}
+
+int rx_mlp_grad_static(rx_handle h, const float *dev_x, const float *dev_t, size_t n, float *dev_grad,
+                       double *loss_out) {
+  if (!h || !dev_x || !dev_t || !dev_grad || n == 0 || n > RX_MLP_STATIC_ROWS) return RX_E_INVALID;
+  if (!h->mlp || !h->scratch) return RX_E_UNSUPPORTED;
+  if (!h->mlp_ready) return RX_E_STATE;
+  const int np = rx_mlp_params();
+  const int nwg = ((int)n + 63) / 64;   // <= rx_mlp_scratch_parts()
+  float *part = static_cast<float *>(h->scratch);
+  double *loss = reinterpret_cast<double *>(part + (size_t)rx_mlp_scratch_parts() * np);
+  rx_mlp_step(dev_x, dev_t, (int64_t)n, 0, (int)n, 0, h->mlp, nullptr, nullptr, part, loss, dev_grad, 0, 0.f, 0.f,
+              0.f, 0.f, 1.f, 1.f, h->stream);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess && loss_out) {
+    double lp[RX_MLP_STATIC_ROWS / 64];   // the partials, on the host stack
+    e = hipMemcpy(lp, loss, nwg * sizeof(double), hipMemcpyDeviceToHost);
+    double acc = 0.0;
+    for (int i = 0; i < nwg; i++) acc += lp[i];
+    *loss_out = acc / (double)n;
+  }
+  return e == hipSuccess ? RX_OK : fail_hip(e, "rx_mlp_grad_static");
 }
 
 int rx_mlp_infer(rx_handle h, const float *dev_x, size_t n, float *dev_y) {

@@ -5,6 +5,9 @@
 // backward and Adam (Kingma & Ba 2015) kernels.  Inference: BF16 operands on
 // MFMA with FP32 accumulation.  Parameters are packed W1[64][31], b1[64],
 // W2[64][64], b2[64], W3[64], b3.
+#include <map>
+#include <mutex>
+
 #include "rx_dev.hpp"
 
 #define MI 31
@@ -390,3 +393,33 @@ void rx_mlp_step(const float *X, const float *T, int64_t ntrain, int64_t i0, int
                      b1, b2, eps, c1, c2);
 }
 
+// ---- the gradient's partials in a static device array ---------------------
+// For callers that cannot allocate: RX_MLP_STATIC_ROWS rows at most, i.e.
+// RX_MLP_STATIC_ROWS / SPW workgroup partials of MP floats, then as many
+// FP64 loss partials.  Every workgroup writes all of its partial (nothing
+// has to start at zero); each GPU holds one copy until the process ends.
+#define RX_STATIC_PARTS (RX_MLP_STATIC_ROWS / SPW)
+static_assert((RX_STATIC_PARTS * MP) % 2 == 0, "the FP64 loss partials start 8-byte aligned");
+static __device__ __align__(256) float scratch[RX_STATIC_PARTS * MP + 2 * RX_STATIC_PARTS];
+
+// The array's device address on the current device, resolved once per
+// device (in host code the array's name is no device address).
+int rx_mlp_scratch_resolve(void **out) {
+  static std::mutex mu;
+  static std::map<int, void *> addr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return (int)e;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(dev);
+  if (it == addr.end()) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return e != hipSuccess ? (int)e : (int)hipErrorInvalidSymbol;
+    it = addr.emplace(dev, ptr).first;
+  }
+  *out = it->second;
+  return 0;
+}
+
+int rx_mlp_scratch_parts(void) { return RX_STATIC_PARTS; }

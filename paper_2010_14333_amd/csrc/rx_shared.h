@@ -97,3 +97,6 @@ void rx_mlp_step(const float *X, const float *T, int64_t ntrain, int64_t i0, int
                  float *m, float *v, float *part, double *loss_part, float *grad, int adam, float lr, float b1,
                  float b2, float eps, float c1, float c2, hipStream_t s);
 void rx_mlp_infer_rows(const float *P, const float *X, int64_t n, float *Y, hipStream_t s);
+#define RX_MLP_STATIC_ROWS 8192   // rows rx_mlp_grad_static takes (its partials live in a static array)
+int rx_mlp_scratch_resolve(void **out);   // 0 or a hipError_t
+int rx_mlp_scratch_parts(void);
