@@ -111,6 +111,10 @@ def _gen(job):
     elif kind == "pam8":
         seed, i = a
         g = synth.pam8_91km(i, seed=seed)
+    elif kind == "soak":
+        # a whole number of tone cycles (11/80 of the sample rate) and of 1024 samples,
+        # so the repeated pattern is a continuous signal
+        g = synth.generate(synth.KK_16QAM, 4096000, synth.derive_seed(801, 0), 22.0)
     else:
         raise ValueError(kind)
     return {"fmt": g["fmt"], "seed": g["seed"], "n": g["n_samples"], "packed": g["packed"]}
@@ -164,6 +168,9 @@ def main():
     ap.add_argument("--mixed", type=int, default=1, help="time a 64-buffer mixed-format batch (graph replay)")
     ap.add_argument("--latency", type=int, default=1, help="per-buffer latency of small batches on one stream")
     ap.add_argument("--host", type=int, default=1, help="time the plain chain fed from pinned host memory")
+    ap.add_argument("--soak", type=int, default=5859,
+                    help="buffers of the contiguous-stream soak (KK-16QAM, 4,096,000-sample buffers fed from pinned "
+                         "host memory, a repeated transmitter pattern, Q every 20 buffers; 5859 = 6 s of signal)")
     ap.add_argument("--fft-log2", type=int, default=0, choices=(0, 13, 14),
                     help="KK overlap-save FFT size of the timed KK handles: 0 = the library's autotuner, "
                          "13 or 14 to pin it (profiler runs pin 14)")
@@ -189,6 +196,8 @@ def main():
         jobs += [("pam8", (501, i)) for i in range(4)] + [("pam8", (502, i)) for i in range(8)]
     if a.precision_check:
         jobs += [("kk24", 0)]
+    if a.soak:
+        jobs += [("soak", 0)]
     cores = usable_cores()
     t0 = time.time()
     with mp.get_context("fork").Pool(min(cores, len(jobs))) as pool:
@@ -198,6 +207,7 @@ def main():
     train = [m for j, m in zip(jobs, made) if j[0] == "pam8" and j[1][0] == 501]
     testg = [m for j, m in zip(jobs, made) if j[0] == "pam8" and j[1][0] == 502]
     big = [m for j, m in zip(jobs, made) if j[0] == "kk24"]
+    soak_g = [m for j, m in zip(jobs, made) if j[0] == "soak"]
     log(f"[bench] generated {len(jobs)} input buffers in {time.time() - t0:.1f}s on {cores} processes")
 
     # the FP64 oracle on the host's cores: all of them, then one (before the
@@ -526,6 +536,50 @@ def main():
         latency["workload"] = "KK-16QAM plain chain, batches of 1, 4 and 16 2^22-sample buffers on one stream"
         log(f"[bench] latency {latency}")
 
+    soak = None
+    if a.soak and soak_g:
+        # the paper's 6-second continuity run: one contiguous stream, each buffer
+        # copied in from pinned host memory and its bits back, Q per 20 buffers
+        # (about 21 ms of signal), against the real-time rate
+        g = soak_g[0]
+        ns_ = g["n"]
+        hin = torch.from_numpy(g["packed"]).pin_memory()
+        hout = torch.empty((ns_ // 4 * 4 + 7) // 8, dtype=torch.uint8).pin_memory()
+        r = rx.Receiver(rx.RX_KK_16QAM, g["seed"], max_samples=ns_, stream=streams[0], flags=rx.RX_STREAM,
+                        ref_period=ns_ // 4, fft_log2=a.fft_log2)
+        from scipy.special import erfcinv
+        qs, bers, lat = [], [], []
+        late = 0
+        t1 = time.perf_counter()
+        done = 0
+        while done < a.soak:
+            for _ in range(min(20, a.soak - done)):
+                rx.rx_process_batch_host([r.h], [hin.data_ptr()], [ns_], [hout.data_ptr()])
+                done += 1
+            e = r.errors()          # synchronises
+            late += e["late_buffers"]
+            lat.append(rx.rx_latencies(r.h, 20))
+            r.reset()
+            ber = e["bit_errors"] / e["bits"] if e["bits"] else 0.0
+            bers.append(ber)
+            qs.append(20.0 * np.log10(np.sqrt(2.0) * erfcinv(2.0 * ber)) if 0 < ber < 0.5 else None)
+        wall_s = time.perf_counter() - t1
+        lat = np.concatenate(lat)
+        qv = [q for q in qs if q is not None]
+        signal_s = a.soak * ns_ / FS
+        soak = {"workload": f"KK-16QAM contiguous stream of {a.soak} buffers of {ns_} samples ({signal_s:.2f} s of "
+                            f"signal at 4 Gs/s, 22 dB SNR, a repeated transmitter pattern), each buffer copied from "
+                            f"pinned host memory and its bits back to pinned host memory, one HIP stream",
+                "buffers": a.soak, "wall_s": round(wall_s, 3), "realtime_factor": round(signal_s / wall_s, 2),
+                "periods": len(bers), "q_db_min": round(min(qv), 2) if qv else None,
+                "q_db_max": round(max(qv), 2) if qv else None, "error_free_periods": sum(q is None for q in qs),
+                "ber_mean": float(np.mean(bers)), "buffer_latency_us_p50": pct(lat, 50),
+                "buffer_latency_us_p99": pct(lat, 99), "late_buffers": int(late),
+                "realtime_budget_us_per_buffer": round(ns_ / FS * 1e6, 1)}
+        r.close()
+        del hin, hout
+        log(f"[bench] soak {soak}")
+
     def roofline(st):
         if not st or "kk_front" not in st:
             return {"bound": "alu", "achieved": None, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": None,
@@ -580,6 +634,7 @@ def main():
         "mixed_batch": mixed,
         "latency": latency,
         "host_ingest": host_ingest,
+        "stream_soak": soak,
         "q_vs_snr": q_sweep,
         "q_vs_osnr": q_osnr,
         "one_stream_stage_us_per_buffer": per_buffer(stages1) if stages1 else None,

@@ -66,6 +66,8 @@ enum {
 /* Flags */
 #define RX_DEBUG_KEEP 0x1u   /* keep intermediate arrays for rx_debug_fetch() */
 #define RX_PROFILE 0x2u      /* time every kernel stage with HIP events (see rx_stage_times) */
+#define RX_STREAM 0x4u       /* the handle's buffers are consecutive pieces of one continuous stream
+                                (see "Contiguous streams" below) */
 
 /* Kernel stages reported by rx_stage_times (index into its arrays). */
 enum {
@@ -93,7 +95,7 @@ typedef struct {
                                (the precision form: 21) */
   int32_t prefix_symbols;   /* known training/sync symbols at each buffer start: 4096 */
   int32_t hilbert_taps;     /* KK Hilbert FIR length V+1: 4097 */
-  int32_t fft_log2;         /* KK overlap-save FFT size: 0 = library choice, else 13 or 14 */
+  int32_t fft_log2;         /* KK overlap-save FFT size: 0 = tuned, else 13 or 14 */
   int32_t precision;        /* rx_precision: RX_FP32 plain chain; BF16/FP16 precision form (KK) */
   int32_t equalizer;        /* rx_equalizer (MLP: PAM only) */
   double rolloff;           /* RRC roll-off: 0.1 */
@@ -118,7 +120,16 @@ typedef struct {
                                it, while the buffer's kernels run, so a caller processing
                                buffers of different sequences on one handle rewrites it on
                                the handle's stream between them.  rx_train_mlp still takes
-                               its training buffers' sequences from its seeds. */
+                               its training buffers' sequences from its seeds.  Not with
+                               RX_STREAM (RX_E_UNSUPPORTED). */
+  uint64_t ref_period;      /* 0, or the seeded reference sequence repeats every ref_period
+                               symbols (symbol k is that of k mod ref_period), as the pattern
+                               of a transmitter that repeats a finite memory */
+  int32_t blocks_bc;        /* DD-LMS symbol steps per staged chunk: 4, 8 or 16; 0 = tuned */
+  int32_t ffe_gpw;          /* precision-form FFE: 256-symbol groups per wavefront: 4, 8 or 16;
+                               0 = tuned */
+  int32_t dec_syms;         /* decision stage: symbols per workgroup: 1024, 2048 or 4096; 0 = tuned */
+  int32_t reserved2;
 } rx_params;
 
 /* Cumulative counters since create / rx_errors_reset.  Symbols counted are
@@ -141,6 +152,18 @@ enum {
   RX_STAGE_PHASE = 7,   /* KK: unwrapped carrier phase per 128-symbol block, float[n_sym/128] */
   RX_STAGE_SCALARS = 8  /* double[8]: mean re, mean im, agc, theta0, lag, rot, fallback, 0 */
 };
+
+/* Launch shapes.  fft_log2, blocks_bc, ffe_gpw and dec_syms change how the
+ * work is laid out on the GPU, never the result (the FFT size changes it by
+ * rounding only: the Hilbert transform is a fixed finite kernel).  Left at
+ * 0 they are tuned on the device: the first rx_create of a (GPU
+ * architecture, chain, precision, FFE length) times each stage with each
+ * candidate on a 16-buffer batch (about a second) and keeps the fastest;
+ * the choices are cached for the process and in a JSON file
+ * ($RX_TUNE_CACHE, else $HOME/.cache/paper_2010_14333_amd/autotune.json;
+ * RX_TUNE_CACHE="" keeps them in memory only).  rx_tuning reports a
+ * handle's shapes: shapes[0..3] = fft_log2, blocks_bc, ffe_gpw, dec_syms. */
+int rx_tuning(rx_handle h, int32_t *shapes);
 
 /* Fill *p with the defaults of `fmt` (values in the comments above).
  * Returns RX_E_INVALID for an unknown format or NULL p. */
@@ -166,6 +189,38 @@ int rx_create(rx_format fmt, double baud, double fs, const rx_params *p, rx_hand
  * launch failure. */
 int rx_process(rx_handle h, const void *dev_buffer, size_t n_samples, void *dev_bits,
                size_t *n_bits_out);
+
+/* Contiguous streams (RX_STREAM).  The ADC delivers one continuous stream
+ * of buffers and the receiver keeps the signal continuous across them (Sec.
+ * 2, first paragraph: each overlap-and-save kernel prepends part of the
+ * previous buffer, and the blockwise clock-phase unwrap continues from the
+ * previous buffer).  On a stream handle:
+ *   - the first buffer (after create or rx_stream_reset) is processed as an
+ *     independent buffer and acquires the stream: carrier (KK) or DC (PAM)
+ *     mean, AGC gain, static phase, symbol delay, rotation, prefix taps and
+ *     the network's judgement are those of this buffer for the whole stream;
+ *     the known prefix is only at the stream's start;
+ *   - every later buffer is processed after the stream's preceding
+ *     hold + look samples (hold = look = 4096 samples KK, 12288 PAM), with the
+ *     downshift phase taken at the stream's sample index, the DD-LMS blocks
+ *     on the stream's grid, and the KK carrier-phase and PAM clock-phase
+ *     unwraps continued from the previous buffer's last emitted block;
+ *   - decisions are emitted `hold` samples late: the first buffer emits the
+ *     symbols of its first n - hold samples, each later one exactly n / sps
+ *     symbols (the previous buffer's held-back samples first), so the output
+ *     bits of consecutive calls concatenate into the stream's bits and no
+ *     emitted decision depends on samples not yet received;
+ *   - errors count the stream's symbols from prefix + 64 on (reference
+ *     symbol = the stream's symbol index, mod ref_period when set).
+ * The call's dev_buffer must hold n packed samples as usual (any multiple of
+ * 1024 after the first; the first must hold the prefix plus hold + look
+ * samples); it is copied into the handle's staging area (the library keeps
+ * the tail), so it may be reused once the handle's stream has passed the
+ * call.  *n_bits_out reports the emitted bits.  Graph replay is not offered
+ * for stream handles (their launch arguments change every call:
+ * RX_E_UNSUPPORTED).  rx_train_mlp on a stream handle restarts its stream. */
+int rx_stream_reset(rx_handle h);   /* the next buffer starts (and acquires) a new stream; RX_E_STATE
+                                       on a handle without RX_STREAM */
 
 /* Process `count` buffers (1..64) with distinct handles, mixed formats
  * allowed, as one batched launch sequence on the FIRST handle's stream (the

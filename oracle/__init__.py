@@ -21,6 +21,10 @@ _dp = ctypes.POINTER(ctypes.c_double)
 _u8p = ctypes.POINTER(ctypes.c_uint8)
 
 
+class Out(ctypes.Structure):
+    pass
+
+
 class Cfg(ctypes.Structure):
     _fields_ = [("fmt", ctypes.c_int32), ("mf_taps", ctypes.c_int32), ("ffe_taps", ctypes.c_int32),
                 ("prefix", ctypes.c_int32), ("hilbert_taps", ctypes.c_int32),
@@ -28,11 +32,11 @@ class Cfg(ctypes.Structure):
                 ("rounding", ctypes.c_int32), ("equalizer", ctypes.c_int32),
                 ("pad0", ctypes.c_int32), ("rolloff", ctypes.c_double), ("mu", ctypes.c_double),
                 ("mu_cma", ctypes.c_double), ("fc_over_fs", ctypes.c_double),
-                ("seed", ctypes.c_uint64), ("mlp", _dp), ("force", ctypes.POINTER(ctypes.c_int32))]
+                ("seed", ctypes.c_uint64), ("mlp", _dp), ("force", ctypes.POINTER(ctypes.c_int32)),
+                ("frozen", ctypes.POINTER(Out)), ("count_end", ctypes.c_int64)]
 
 
-class Out(ctypes.Structure):
-    _fields_ = [("field", _dp), ("shifted", _dp), ("mf", _dp), ("timing", _dp), ("xr", _dp),
+Out._fields_ = [("field", _dp), ("shifted", _dp), ("mf", _dp), ("timing", _dp), ("xr", _dp),
                 ("soft", _dp), ("taps", _dp), ("phase", _dp), ("ddz", _dp), ("bits", _u8p),
                 ("mean_re", ctypes.c_double), ("mean_im", ctypes.c_double),
                 ("agc", ctypes.c_double), ("theta0", ctypes.c_double),
@@ -107,7 +111,7 @@ def default_cfg(fmt, seed, **kw) -> dict:
     d = dict(fmt=fmt, mf_taps=65 if kk else 33, ffe_taps=21 if kk else 15, prefix=4096,
              hilbert_taps=4097, os_log2=16, form=0, rounding=0, equalizer=0,
              rolloff=0.1, mu=1e-3, mu_cma=1e-3, fc_over_fs=0.55e9 / 4e9 if kk else 0.0,
-             seed=seed, mlp=None, force=None)
+             seed=seed, mlp=None, force=None, frozen=None, count_end=0)
     d.update(kw)
     return d
 
@@ -120,6 +124,7 @@ def process(fmt, packed, n_samples, seed, want=("bits", "soft"), **kw) -> dict:
     d = default_cfg(fmt, seed, **kw)
     mlp = d.pop("mlp")
     force = d.pop("force")
+    frozen = d.pop("frozen")
     cfg = Cfg(**d)
     keep = []
     n = int(n_samples)
@@ -135,6 +140,15 @@ def process(fmt, packed, n_samples, seed, want=("bits", "soft"), **kw) -> dict:
         assert mlp.size == MLP_PARAMS
         cfg.mlp = _p(mlp)
         keep.append(mlp)
+    if frozen is not None:
+        fz = Out()
+        taps = np.ascontiguousarray(np.asarray(frozen["taps"], dtype=np.complex128))
+        keep.append(taps)
+        fz.taps = taps.view(np.float64).ctypes.data_as(_dp)
+        for k in ("mean_re", "mean_im", "agc", "theta0", "lag", "rot", "fallback"):
+            setattr(fz, k, frozen[k])
+        keep.append(fz)
+        cfg.frozen = ctypes.pointer(fz)
     sizes = {"field": 2 * n, "shifted": 2 * n, "mf": n, "timing": n // 512, "xr": n,
              "soft": 2 * nsym if kk else nsym, "ddz": 2 * nsym if kk else nsym, "taps": 2 * d["ffe_taps"],
              "phase": nsym // 128}
@@ -162,6 +176,38 @@ def process(fmt, packed, n_samples, seed, want=("bits", "soft"), **kw) -> dict:
     for k in ("mean_re", "mean_im", "agc", "theta0", "lag", "rot", "fallback", "nsym", "nbits",
               "counted_syms", "sym_errors", "counted_bits", "bit_errors"):
         res[k] = getattr(out, k)
+    return res
+
+
+def process_stream(fmt, buffers, seed, hold_back, want=("bits", "soft"), force=None, **kw) -> dict:
+    """A contiguous stream cut into buffers (the paper's continuous ADC
+    stream with its overlap events): the first buffer is acquired on its own
+    (carrier or DC mean, AGC gain, static phase, delay, rotation, prefix
+    taps, MLP fallback), then the whole concatenated stream is processed as
+    one signal with that acquisition frozen.  A receiver that holds back the
+    last `hold_back` samples of every buffer emits the decisions of samples
+    [0, total - hold_back): bits and soft values are cut to those symbols and
+    errors counted up to them.  force (optional): forced DD-LMS decisions of
+    the stream pass (see process)."""
+    bufs = [np.ascontiguousarray(b, dtype=np.uint8) for b in buffers]
+    ns = [b.size * 2 // 3 for b in bufs]
+    sps = 4 if is_kk(fmt) else 2
+    acq = process(fmt, bufs[0], ns[0], seed, want=("taps",), **kw)
+    total = sum(ns)
+    nsym_emit = (total - hold_back) // sps
+    if force is not None and len(force) < total // sps:   # forced decisions given for the emitted symbols
+        force = np.concatenate([force, np.full(total // sps - len(force), -1, dtype=np.int32)])
+    res = process(fmt, np.concatenate(bufs), total, seed, want=tuple(want), frozen=acq, count_end=nsym_emit,
+                  force=force, **kw)
+    nb = bits_per_symbol(fmt)
+    if "bits" in res:
+        bits = np.unpackbits(res["bits"], bitorder="little")[: nsym_emit * nb]
+        res["bits"] = np.packbits(bits, bitorder="little")
+    for k in ("soft", "ddz"):
+        if k in res:
+            res[k] = res[k][:nsym_emit]
+    res["nsym_emitted"] = nsym_emit
+    res["acquisition"] = acq
     return res
 
 

@@ -602,6 +602,7 @@ int rxo_process(const rxo_cfg *cfg, const uint8_t *packed, int64_t n, rxo_out *o
   const int K = cfg->ffe_taps, c = (K - 1) / 2, P = cfg->prefix, G = 64;
   const int blk = kk ? 128 : 256;
   const int rm = cfg->rounding;
+  const rxo_out *fz = cfg->frozen;
   if (P + 2 * G >= nsym || K < 1 || K % 2 == 0 || cfg->mf_taps % 2 == 0) return -1;
   if (cfg->equalizer == 1 && (kk || !cfg->mlp)) return -1;
 
@@ -631,6 +632,7 @@ int rxo_process(const rxo_cfg *cfg, const uint8_t *packed, int64_t n, rxo_out *o
       mean += e[t];
     }
     mean /= (double)n;
+    if (fz) mean = fz->mean_re + I * fz->mean_im;   /* a stream's carrier from its first buffer */
     if (o->field) memcpy(o->field, e, sizeof(cplx) * (size_t)n);
     /* carrier removal and downshift, the phase frac(r t) kept in FP64 */
     cplx *y = (cplx *)malloc(sizeof(cplx) * (size_t)n);
@@ -653,7 +655,7 @@ int rxo_process(const rxo_cfg *cfg, const uint8_t *packed, int64_t n, rxo_out *o
     /* --- PAM front end (Sec. 2, first paragraph): DC removal, MF --- */
     double s = 0.0;
     for (int64_t t = 0; t < n; t++) s += (double)code[t];
-    double mv = s / (double)n + 0.5;
+    double mv = fz ? fz->mean_re : s / (double)n + 0.5;
     double *x0 = (double *)malloc(sizeof(double) * (size_t)n);
     double *y = (double *)malloc(sizeof(double) * (size_t)n);
     for (int64_t t = 0; t < n; t++) x0[t] = (double)code[t] + 0.5 - mv;
@@ -668,7 +670,7 @@ int rxo_process(const rxo_cfg *cfg, const uint8_t *packed, int64_t n, rxo_out *o
   /* --- AGC: unit mean power --- */
   double pw = 0.0;
   for (int64_t t = 0; t < nx; t++) pw += creal(x[t]) * creal(x[t]) + cimag(x[t]) * cimag(x[t]);
-  double g = 1.0 / sqrt(pw / (double)nx);
+  double g = fz ? fz->agc : 1.0 / sqrt(pw / (double)nx);
   for (int64_t t = 0; t < nx; t++) x[t] *= g;
   o->agc = g;
   if (o->mf) {
@@ -698,7 +700,14 @@ int rxo_process(const rxo_cfg *cfg, const uint8_t *packed, int64_t n, rxo_out *o
   for (int k = 0; k < P; k++) ref[k] = ref_symbol(fmt, cfg->seed, k);
   cplx *w = (cplx *)calloc((size_t)K, sizeof(cplx));
   o->theta0 = 0.0;
-  if (kk) {
+  if (fz) {
+    /* a stream after its first buffer: the acquisition's delay, rotation
+     * and prefix taps (the known prefix is only at the stream's start) */
+    o->theta0 = fz->theta0;
+    o->lag = fz->lag;
+    o->rot = fz->rot;
+    for (int i = 0; i < K; i++) w[i] = fz->taps[2 * i] + I * fz->taps[2 * i + 1];
+  } else if (kk) {
     const double r2 = fmt == RXO_KK_16QAM ? 1.32 : 1.0;
     double s4[2];
     w[c] = 1.0;
@@ -710,10 +719,12 @@ int rxo_process(const rxo_cfg *cfg, const uint8_t *packed, int64_t n, rxo_out *o
   } else {
     w[c] = sqrt(ea2);
   }
-  sync_search(fmt, x, nx, w, K, P, ref, &o->lag, &o->rot);
+  if (!fz) {
+    sync_search(fmt, x, nx, w, K, P, ref, &o->lag, &o->rot);
+    for (int i = 0; i < K; i++) w[i] *= jpow[o->rot];
+    rxo_lms((double *)x, nx, (double *)w, K, 2 * (int64_t)o->lag, P, (double *)ref, m, kk, cfg->mu, NULL, NULL);
+  }
   const int64_t sh2 = 2 * (int64_t)o->lag;
-  for (int i = 0; i < K; i++) w[i] *= jpow[o->rot];
-  rxo_lms((double *)x, nx, (double *)w, K, sh2, P, (double *)ref, m, kk, cfg->mu, NULL, NULL);
   if (o->taps)
     for (int i = 0; i < K; i++) { o->taps[2 * i] = creal(w[i]); o->taps[2 * i + 1] = cimag(w[i]); }
 
@@ -735,7 +746,7 @@ int rxo_process(const rxo_cfg *cfg, const uint8_t *packed, int64_t n, rxo_out *o
       err_mlp += creal(decide_point(fmt, soft[k])) != creal(a);
       err_lms += creal(decide_point(fmt, ffe_out(x, nx, w, K, sh2 + 2 * k))) != creal(a);
     }
-    if (err_mlp > err_lms) { use_mlp = 0; o->fallback = 1; }
+    if (fz ? fz->fallback : err_mlp > err_lms) { use_mlp = 0; o->fallback = 1; }
   }
   if (!use_mlp) {
     cplx *wr = (cplx *)malloc(sizeof(cplx) * (size_t)K);
@@ -795,7 +806,7 @@ int rxo_process(const rxo_cfg *cfg, const uint8_t *packed, int64_t n, rxo_out *o
       int64_t t = k * bps + j;
       if ((b >> (bps - 1 - j)) & 1u) bits[t >> 3] |= (uint8_t)(1u << (t & 7));
     }
-    if (k >= P + G && k < nsym - G) {
+    if (k >= P + G && k < (cfg->count_end > 0 ? cfg->count_end : nsym - G)) {
       uint32_t r = (uint32_t)(rxo_splitmix64(cfg->seed, (uint64_t)k) >> (64 - bps));
       uint32_t d = r ^ b;
       int nerr = 0;

@@ -35,10 +35,14 @@ typedef struct {
   const double *mlp;     /* RXO_MLP_PARAMS packed parameters when equalizer == 1 */
   const int32_t *force;  /* optional, nsym entries: decision index the block DD-LMS takes at that
                             symbol instead of its own (-1: its own); test instrumentation */
+  const struct rxo_out_s *frozen;   /* optional: the acquisition of a stream (the result of its
+                            first buffer): its means, AGC gain, static phase, delay, rotation,
+                            prefix taps and MLP fallback are used instead of being computed */
+  int64_t count_end;     /* error counting stops before this symbol (0: n_sym - 64) */
 } rxo_cfg;
 
 /* Optional outputs: any pointer may be NULL. */
-typedef struct {
+typedef struct rxo_out_s {
   double *field;     /* KK: reconstructed field E (2*L doubles, re/im) before carrier removal */
   double *shifted;   /* KK: (E - mean) * exp(-j 2 pi frac(r n)) (2*L doubles) */
   double *mf;        /* PAM: AGC'd MF output (L); KK: AGC'd decimated MF output (2*(L/2)) */

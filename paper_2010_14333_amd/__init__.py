@@ -24,11 +24,13 @@ RX_DEBUG_KEEP = 0x1
  RX_STAGE_PHASE, RX_STAGE_SCALARS) = range(1, 9)
 
 RX_PROFILE = 0x2
+RX_STREAM = 0x4
+HOLD = {RX_PAM2: 12288, RX_PAM4: 12288, RX_PAM8: 12288, RX_KK_QPSK: 4096, RX_KK_16QAM: 4096}
 STAGES = ("kk_front", "kk_debug", "pam_sum", "pam_mf", "pam_gavg", "pam_unwrap", "pam_farrow",
           "prefix", "blocks", "kk_vv", "decide", "mlp_infer", "mlp_judge")
 RX_MLP_PARAMS = 6273
 EXPORTS = ("rx_params_default", "rx_create", "rx_process", "rx_process_batch", "rx_process_batch_host",
-           "rx_sync", "rx_errors",
+           "rx_sync", "rx_stream_reset", "rx_tuning", "rx_errors",
            "rx_errors_reset", "rx_latencies", "rx_debug_fetch", "rx_train_cfg_default", "rx_mlp_param_count",
            "rx_mlp_order_multiplier", "rx_train_mlp", "rx_train_mlp_data", "rx_mlp_grad", "rx_mlp_grad_static",
            "rx_mlp_infer",
@@ -45,7 +47,9 @@ class rx_params(ctypes.Structure):
                 ("carrier_hz", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("max_samples", ctypes.c_uint64), ("stream", ctypes.c_void_p),
                 ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
-                ("deadline_s", ctypes.c_double), ("ref_bits", ctypes.c_void_p)]
+                ("deadline_s", ctypes.c_double), ("ref_bits", ctypes.c_void_p),
+                ("ref_period", ctypes.c_uint64), ("blocks_bc", ctypes.c_int32), ("ffe_gpw", ctypes.c_int32),
+                ("dec_syms", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
 
 
 class rx_stats(ctypes.Structure):
@@ -85,6 +89,8 @@ def lib() -> ctypes.CDLL:
         L.rx_process_batch_host.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(sz),
                                             ctypes.POINTER(vp), i32, i32]
         L.rx_sync.argtypes = [vp]
+        L.rx_stream_reset.argtypes = [vp]
+        L.rx_tuning.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
         L.rx_errors.argtypes = [vp, ctypes.POINTER(rx_stats)]
         L.rx_errors_reset.argtypes = [vp]
         L.rx_latencies.argtypes = [vp, ctypes.POINTER(ctypes.c_double), sz, ctypes.POINTER(sz)]
@@ -168,6 +174,17 @@ def rx_process_batch_host(handles, host_buffers, n_samples, host_bits, graph: bo
 
 def rx_sync(h: int) -> None:
     _check(lib().rx_sync(h), "rx_sync")
+
+
+def rx_tuning(h: int) -> dict:
+    """The handle's launch shapes (tuned or given)."""
+    a = (ctypes.c_int32 * 4)()
+    _check(lib().rx_tuning(h, a), "rx_tuning")
+    return {"fft_log2": a[0], "blocks_bc": a[1], "ffe_gpw": a[2], "dec_syms": a[3]}
+
+
+def rx_stream_reset(h: int) -> None:
+    _check(lib().rx_stream_reset(h), "rx_stream_reset")
 
 
 def rx_errors(h: int) -> dict:
@@ -316,13 +333,16 @@ class Receiver:
         return (n_samples // self.sps * BPS[self.fmt] + 7) // 8
 
     def process(self, buf, n_samples: int, out=None):
+        """Bits of the buffer (a stream handle: of the symbols this call
+        emits, as many bytes as they fill)."""
         import torch
         if out is None:
             out = torch.empty(self.bits_bytes(n_samples), dtype=torch.uint8, device=buf.device)
         nb = ctypes.c_size_t()
         self.last_status = _check(lib().rx_process(self.h, buf.data_ptr(), n_samples, out.data_ptr(),
                                                    ctypes.byref(nb)), "rx_process")
-        return out
+        self.last_bits = nb.value
+        return out[: (nb.value + 7) // 8]
 
     def errors(self) -> dict:
         return rx_errors(self.h)

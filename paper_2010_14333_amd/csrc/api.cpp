@@ -9,8 +9,12 @@
 #include <cstdio>
 #include <cstddef>
 #include <cstring>
+#include <cstdlib>
 #include <map>
 #include <mutex>
+#include <string>
+#include <sys/stat.h>
+#include <unistd.h>
 #include <tuple>
 #include <vector>
 
@@ -113,6 +117,7 @@ struct rx_ctx {
   uint64_t version = 0;   // bumped whenever the device job or the stage list can change
   int wall_khz = 100000;  // device wall-clock rate
   int kk = 0, sps = 2, bps = 1, log2n = 14;
+  RxTune tune = {14, 8, 8, 2048};   // launch shapes
   hipStream_t stream = nullptr;
   RxJob hj{};
   RxJob *dj = nullptr;
@@ -124,6 +129,12 @@ struct rx_ctx {
   void *scratch = nullptr;   // this device's static gradient partials (rx_mlp_grad_static)
   bool mlp_ready = false;
   uint8_t *hin = nullptr, *hbits = nullptr;   // host-ingest staging (device), allocated on first use
+  // contiguous stream (RX_STREAM): the input of a buffer after the first is
+  // the stream's previous hold + look samples (tail) followed by the buffer
+  int64_t stream_pos = 0;      // stream samples received so far
+  bool acquired = false;       // the stream's first buffer has been processed
+  int64_t tail_n = 0;          // hold + look
+  uint8_t *sx = nullptr, *stail = nullptr;
   // stage timing (RX_PROFILE): events recorded around every stage launch
   struct Pending { int stage; hipEvent_t a, b; };
   std::vector<Pending> pending;
@@ -170,6 +181,10 @@ int rx_params_default(rx_format fmt, rx_params *p) {
   p->flags = 0;
   p->deadline_s = 0.0;
   p->ref_bits = nullptr;
+  p->ref_period = 0;
+  p->blocks_bc = 0;
+  p->ffe_gpw = 0;
+  p->dec_syms = 0;
   return RX_OK;
 }
 
@@ -217,24 +232,148 @@ static const SharedTables *shared_tables(int log2n, int htaps) {
   return &(cache[key] = t);
 }
 
-// FFT-size autotuner (fft_log2 = 0 on a KK handle): a batch of 16 buffers of
-// 2^22 pseudo-random codes (the work does not depend on the values; the
-// batch fills the chip the way a streaming batch does, at the real buffer
-// size) is run through the chain at each supported overlap-save size, once
-// per device and process; the fastest of three runs counts, and the smaller
-// size must win by more than 3 % to replace 2^14.  The overlap is fixed by the
-// Hilbert kernel, so the size decides the hop (N - 4160) and how many
-// workgroups share a CU.
-static int autotune_log2n(rx_format fmt, double baud, double fs, const rx_params &p) {
-  static std::mutex mu;
-  static std::map<int, int> chosen;   // device -> log2 N
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 14;
-  std::lock_guard<std::mutex> lock(mu);
-  auto it = chosen.find(dev);
-  if (it != chosen.end()) return it->second;
+// ---- launch-shape tuner ----------------------------------------------------
+// Each tunable shape (overlap-save FFT size, DD-LMS chunk steps, precision-form
+// FFE groups per wavefront, decision symbols per workgroup) is chosen by
+// timing its own stage on the device: a batch of 16 buffers of 2^22
+// pseudo-random codes (the work does not depend on the values; the batch
+// fills the chip as a streaming batch does, at the real buffer size) runs
+// through the chain with HIP events around every stage, one candidate at a
+// time with the others held at the current choice; the best of three runs
+// counts, and a candidate must beat the incumbent by more than 3 %.  Choices
+// are kept per (GPU architecture, chain, precision, FFE length) for the
+// process and in a JSON file ($RX_TUNE_CACHE, else
+// $HOME/.cache/paper_2010_14333_amd/autotune.json; an empty RX_TUNE_CACHE
+// keeps them in memory only), so later processes on the same GPU model skip
+// the timing.
+static const RxTune kDefaultTune = {14, 8, 8, 2048};
+
+static std::string tune_cache_path() {
+  const char *e = std::getenv("RX_TUNE_CACHE");
+  if (e) return std::string(e);
+  const char *home = std::getenv("HOME");
+  if (!home || !*home) return std::string();
+  return std::string(home) + "/.cache/paper_2010_14333_amd/autotune.json";
+}
+
+// The cache file: {"key": {"fft_log2": a, "blocks_bc": b, "ffe_gpw": c, "dec_syms": d}, ...}
+static std::map<std::string, RxTune> tune_file_read(const std::string &path) {
+  std::map<std::string, RxTune> out;
+  FILE *f = path.empty() ? nullptr : std::fopen(path.c_str(), "rb");
+  if (!f) return out;
+  std::string text;
+  char buf[4096];
+  size_t got;
+  while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
+  std::fclose(f);
+  size_t pos = 0;
+  while (true) {
+    const size_t k0 = text.find('"', pos);
+    if (k0 == std::string::npos) break;
+    const size_t k1 = text.find('"', k0 + 1);
+    const size_t b0 = text.find('{', k1 == std::string::npos ? k0 : k1);
+    const size_t b1 = text.find('}', b0 == std::string::npos ? k0 : b0);
+    if (k1 == std::string::npos || b0 == std::string::npos || b1 == std::string::npos) break;
+    const std::string key = text.substr(k0 + 1, k1 - k0 - 1), body = text.substr(b0 + 1, b1 - b0 - 1);
+    RxTune t = kDefaultTune;
+    int found = 0;
+    const char *names[4] = {"\"fft_log2\"", "\"blocks_bc\"", "\"ffe_gpw\"", "\"dec_syms\""};
+    int32_t *fields[4] = {&t.fft_log2, &t.blocks_bc, &t.ffe_gpw, &t.dec_syms};
+    for (int i = 0; i < 4; i++) {
+      const size_t q = body.find(names[i]);
+      const size_t c = q == std::string::npos ? q : body.find(':', q);
+      if (c == std::string::npos) continue;
+      *fields[i] = (int32_t)std::strtol(body.c_str() + c + 1, nullptr, 10);
+      found++;
+    }
+    if (found == 4) out[key] = t;
+    pos = b1 + 1;
+  }
+  return out;
+}
+
+static void tune_file_write(const std::string &path, const std::map<std::string, RxTune> &m) {
+  if (path.empty()) return;
+  for (size_t i = 1; i < path.size(); i++)   // the directories (mkdir -p)
+    if (path[i] == '/') mkdir(path.substr(0, i).c_str(), 0755);
+  const std::string tmp = path + ".tmp" + std::to_string((long)getpid());
+  FILE *f = std::fopen(tmp.c_str(), "wb");
+  if (!f) return;
+  std::fprintf(f, "{\n");
+  size_t i = 0;
+  for (const auto &kv : m) {
+    const RxTune &t = kv.second;
+    std::fprintf(f, "  \"%s\": {\"fft_log2\": %d, \"blocks_bc\": %d, \"ffe_gpw\": %d, \"dec_syms\": %d}%s\n",
+                 kv.first.c_str(), t.fft_log2, t.blocks_bc, t.ffe_gpw, t.dec_syms, ++i < m.size() ? "," : "");
+  }
+  std::fprintf(f, "}\n");
+  if (std::fclose(f) == 0) std::rename(tmp.c_str(), path.c_str());
+  else std::remove(tmp.c_str());
+}
+
+static int create_tuned(rx_format fmt, double baud, double fs, const rx_params *pin, const RxTune &t, rx_handle *out);
+
+// Per-launch time (ms) of `stage` for the chain with tune t, best of three.
+static float time_stage(rx_format fmt, double baud, double fs, const rx_params &p, const RxTune &t, int stage,
+                        const void *dbuf, uint8_t *dbits, size_t n, size_t nbits) {
   constexpr int NB = 16;
-  const size_t n = (size_t)1 << 22, nbits = n / 4;   // >= n/sps * bps / 8 for every KK format
+  rx_params q = p;
+  q.max_samples = n;
+  q.flags = 0;
+  q.stream = nullptr;
+  q.ref_bits = nullptr;
+  std::vector<rx_handle> hs;
+  for (int i = 0; i < NB; i++) {
+    rx_params qi = q;
+    if (i == 0) qi.flags = RX_PROFILE;
+    rx_handle h = nullptr;
+    if (create_tuned(fmt, baud, fs, &qi, t, &h) != RX_OK) break;
+    hs.push_back(h);
+  }
+  float best = -1.0f;
+  if ((int)hs.size() == NB) {
+    std::vector<const void *> bufs(NB, dbuf);
+    std::vector<size_t> ns(NB, n);
+    std::vector<void *> outs(NB);
+    for (int i = 0; i < NB; i++) outs[i] = dbits + i * nbits;
+    rx_process_batch(hs.data(), bufs.data(), ns.data(), outs.data(), NB, 0);   // warm-up
+    for (int r = 0; r < 3; r++) {
+      rx_stage_times(hs[0], nullptr, nullptr, 0);
+      rx_process_batch(hs.data(), bufs.data(), ns.data(), outs.data(), NB, 0);
+      double ms[RX_NSTAGES];
+      uint64_t cnt[RX_NSTAGES];
+      if (rx_stage_times(hs[0], ms, cnt, RX_NSTAGES) >= 0 && cnt[stage] > 0) {
+        const float v = (float)(ms[stage] / cnt[stage]);
+        if (best < 0.0f || v < best) best = v;
+      }
+    }
+  }
+  for (rx_handle h : hs) rx_destroy(h);
+  return best;
+}
+
+static RxTune tune_shapes(rx_format fmt, double baud, double fs, const rx_params &p) {
+  static std::mutex mu;
+  static std::map<std::string, RxTune> known;
+  static bool file_read = false;
+  const bool kk = is_kk(fmt);
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return kDefaultTune;
+  const std::string key = std::string(prop.gcnArchName) + "|" + (kk ? "kk" : "pam") + "|" +
+                          std::to_string(p.precision) + "|" + std::to_string(p.ffe_taps);
+  std::lock_guard<std::mutex> lock(mu);
+  const std::string path = tune_cache_path();
+  if (!file_read) {
+    known = tune_file_read(path);
+    file_read = true;
+  }
+  auto it = known.find(key);
+  if (it != known.end()) return it->second;
+
+  RxTune t = kDefaultTune;
+  constexpr int NB = 16;
+  const size_t n = (size_t)1 << 22, nbits = n / 2;   // >= n / sps * bps / 8 for every format
   std::vector<uint8_t> host(3 * n / 2);
   uint64_t x = 0x2545F4914F6CDD1Dull;
   for (auto &b : host) {
@@ -243,57 +382,47 @@ static int autotune_log2n(rx_format fmt, double baud, double fs, const rx_params
   }
   void *dbuf = nullptr;
   uint8_t *dbits = nullptr;
-  int best = 14;
   if (hipMalloc(&dbuf, host.size()) == hipSuccess && hipMalloc((void **)&dbits, NB * nbits) == hipSuccess &&
       hipMemcpy(dbuf, host.data(), host.size(), hipMemcpyHostToDevice) == hipSuccess) {
-    float best_ms = 0.0f;
-    for (int lg : {14, 13}) {   // incumbent first
-      rx_params q = p;
-      q.fft_log2 = lg;
-      q.max_samples = n;
-      q.flags = 0;
-      q.stream = nullptr;
-      std::vector<rx_handle> hs;
-      for (int i = 0; i < NB; i++) {
-        rx_handle h = nullptr;
-        if (rx_create(fmt, baud, fs, &q, &h) != RX_OK) break;
-        hs.push_back(h);
-      }
-      float ms = -1.0f;
-      hipEvent_t e0, e1;
-      if ((int)hs.size() == NB && hipEventCreate(&e0) == hipSuccess) {
-        if (hipEventCreate(&e1) == hipSuccess) {
-          std::vector<const void *> bufs(NB, dbuf);
-          std::vector<size_t> ns(NB, n);
-          std::vector<void *> outs(NB);
-          for (int i = 0; i < NB; i++) outs[i] = dbits + i * nbits;
-          rx_process_batch(hs.data(), bufs.data(), ns.data(), outs.data(), NB, 0);   // warm-up
-          for (int r = 0; r < 3; r++) {
-            float t = -1.0f;
-            hipEventRecord(e0, nullptr);
-            rx_process_batch(hs.data(), bufs.data(), ns.data(), outs.data(), NB, 0);
-            hipEventRecord(e1, nullptr);
-            if (hipEventSynchronize(e1) == hipSuccess) hipEventElapsedTime(&t, e0, e1);
-            if (t > 0.0f && (ms < 0.0f || t < ms)) ms = t;
-          }
-          hipEventDestroy(e1);
+    struct Knob { int32_t RxTune::*field; std::vector<int32_t> cand; int stage; bool used; };
+    const Knob knobs[] = {
+        {&RxTune::fft_log2, {14, 13}, RX_ST_KK_FRONT, kk},
+        {&RxTune::blocks_bc, {8, 4, 16}, RX_ST_BLOCKS, !(kk && p.precision != RX_FP32)},
+        {&RxTune::ffe_gpw, {8, 4, 16}, RX_ST_BLOCKS, kk && p.precision != RX_FP32},
+        {&RxTune::dec_syms, {2048, 1024, 4096}, RX_ST_DECIDE, true},
+    };
+    for (const Knob &k : knobs) {
+      if (!k.used) continue;
+      float best_ms = -1.0f;
+      int32_t best = t.*(k.field);
+      for (int32_t c : k.cand) {   // the incumbent first
+        RxTune tc = t;
+        tc.*(k.field) = c;
+        const float ms = time_stage(fmt, baud, fs, p, tc, k.stage, dbuf, dbits, n, nbits);
+        if (ms > 0.0f && (best_ms < 0.0f || ms < 0.97f * best_ms)) {
+          best_ms = ms;
+          best = c;
         }
-        hipEventDestroy(e0);
       }
-      for (rx_handle h : hs) rx_destroy(h);
-      if (ms > 0.0f && (best_ms == 0.0f || ms < 0.97f * best_ms)) {
-        best_ms = ms;
-        best = lg;
-      }
+      t.*(k.field) = best;
     }
   }
   if (dbuf) hipFree(dbuf);
   if (dbits) hipFree(dbits);
-  chosen[dev] = best;
-  return best;
+  known[key] = t;
+  tune_file_write(path, known);
+  return t;
 }
 
 int rx_create(rx_format fmt, double baud, double fs, const rx_params *pin, rx_handle *out) {
+  return create_tuned(fmt, baud, fs, pin, RxTune{0, 0, 0, 0}, out);
+}
+
+// rx_create with launch shapes: fields of `forced` that are non-zero are used
+// as they are (the tuner's candidates), the others come from the params or,
+// where those leave them to the library, from the tuner.
+static int create_tuned(rx_format fmt, double baud, double fs, const rx_params *pin, const RxTune &forced,
+                        rx_handle *out) {
   if (!out) return RX_E_INVALID;
   *out = nullptr;
   rx_params p;
@@ -310,6 +439,10 @@ int rx_create(rx_format fmt, double baud, double fs, const rx_params *pin, rx_ha
   if (p.prefix_symbols < 2048 || p.prefix_symbols > RX_PREFIX_MAX) return RX_E_INVALID;
   if (kk && (p.hilbert_taps < 3 || p.hilbert_taps > 4097 || p.hilbert_taps % 2 == 0)) return RX_E_INVALID;
   if (p.fft_log2 != 0 && p.fft_log2 != 13 && p.fft_log2 != 14) return RX_E_INVALID;
+  if ((p.blocks_bc != 0 && p.blocks_bc != 4 && p.blocks_bc != 8 && p.blocks_bc != 16) ||
+      (p.ffe_gpw != 0 && p.ffe_gpw != 4 && p.ffe_gpw != 8 && p.ffe_gpw != 16) ||
+      (p.dec_syms != 0 && p.dec_syms != 1024 && p.dec_syms != 2048 && p.dec_syms != 4096))
+    return RX_E_INVALID;
   if (!(p.rolloff > 0 && p.rolloff <= 1) || !(p.mu > 0) || !(p.mu_cma > 0)) return RX_E_INVALID;
   if (p.precision != RX_FP32 && p.precision != RX_BF16 && p.precision != RX_FP16) return RX_E_INVALID;
   if (p.precision != RX_FP32 && (!kk || p.ffe_taps != 21)) return RX_E_UNSUPPORTED;
@@ -318,6 +451,8 @@ int rx_create(rx_format fmt, double baud, double fs, const rx_params *pin, rx_ha
   if (kk && !(std::fabs(p.carrier_hz) < fs / 2)) return RX_E_INVALID;
   if (p.max_samples < 65536 || p.max_samples > ((uint64_t)1 << 26) || p.max_samples % 1024) return RX_E_INVALID;
   if (!(p.deadline_s >= 0.0) || (reinterpret_cast<uintptr_t>(p.ref_bits) & 3)) return RX_E_INVALID;
+  const bool stream = (p.flags & RX_STREAM) != 0;
+  if (stream && p.ref_bits) return RX_E_UNSUPPORTED;   // a stream's reference outgrows any one buffer
   int wall_khz = 0;
   {
     int dev = 0;
@@ -335,9 +470,25 @@ int rx_create(rx_format fmt, double baud, double fs, const rx_params *pin, rx_ha
   h->kk = kk;
   h->sps = kk ? 4 : 2;
   h->bps = bps_of(fmt);
-  h->log2n = p.fft_log2 ? p.fft_log2 : (kk ? autotune_log2n(fmt, baud, fs, p) : 14);
+  {
+    // the launch shapes: forced (tuning), else given, else tuned
+    RxTune t{forced.fft_log2 ? forced.fft_log2 : p.fft_log2, forced.blocks_bc ? forced.blocks_bc : p.blocks_bc,
+             forced.ffe_gpw ? forced.ffe_gpw : p.ffe_gpw, forced.dec_syms ? forced.dec_syms : p.dec_syms};
+    if (!kk && !t.fft_log2) t.fft_log2 = 14;   // no transform in the PAM chain
+    if (!(kk && p.precision != RX_FP32) && !t.ffe_gpw) t.ffe_gpw = 8;
+    if (!t.fft_log2 || !t.blocks_bc || !t.ffe_gpw || !t.dec_syms) {
+      const RxTune tuned = tune_shapes(fmt, baud, fs, p);
+      if (!t.fft_log2) t.fft_log2 = tuned.fft_log2;
+      if (!t.blocks_bc) t.blocks_bc = tuned.blocks_bc;
+      if (!t.ffe_gpw) t.ffe_gpw = tuned.ffe_gpw;
+      if (!t.dec_syms) t.dec_syms = tuned.dec_syms;
+    }
+    h->tune = t;
+  }
+  h->log2n = h->tune.fft_log2;
   h->stream = static_cast<hipStream_t>(p.stream);
-  const int64_t L = (int64_t)p.max_samples;
+  // a stream buffer after the first is processed with its prepended tail
+  const int64_t L = (int64_t)p.max_samples + (stream ? (kk ? 2 * RX_KK_HOLD : 2 * RX_PAM_HOLD) : 0);
   Alloc &A = h->mem;
   RxJob &J = h->hj;
   J.fmt = fmt;
@@ -361,6 +512,11 @@ int rx_create(rx_format fmt, double baud, double fs, const rx_params *pin, rx_ha
   J.sgn = p.carrier_hz >= 0 ? 1.0f : -1.0f;
   J.debug = (p.flags & RX_DEBUG_KEEP) ? 1 : 0;
   J.seed = p.seed;
+  J.stream = stream ? 1 : 0;
+  J.hold = kk ? RX_KK_HOLD : RX_PAM_HOLD;
+  J.look = J.hold;
+  J.ref_period = p.ref_period;
+  h->tail_n = stream ? (int64_t)J.hold + J.look : 0;
   J.deadline_ticks = p.deadline_s * 1e3 * wall_khz;
   J.ticks_per_sample = 1e3 * wall_khz / fs;
 
@@ -442,6 +598,14 @@ int rx_create(rx_format fmt, double baud, double fs, const rx_params *pin, rx_ha
     delete h;
     return RX_E_NOMEM;
   }
+  if (stream) {
+    h->sx = A.get<uint8_t>(L / 2 * 3);
+    h->stail = A.get<uint8_t>(h->tail_n / 2 * 3);
+    if (!h->sx || !h->stail) {
+      delete h;
+      return RX_E_NOMEM;
+    }
+  }
   J.sc = h->dsc;
   RxScalars zero{};
   if (hipMemcpy(h->dsc, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess ||
@@ -449,7 +613,7 @@ int rx_create(rx_format fmt, double baud, double fs, const rx_params *pin, rx_ha
     delete h;
     return fail_hip(hipGetLastError(), "rx_create upload");
   }
-  if (refw) rx_launch_ref_fill(refw, ref_words, J.seed, J.bps, nsym_max, nullptr);
+  if (refw) rx_launch_ref_fill(refw, ref_words, J.seed, J.bps, nsym_max, J.ref_period, nullptr);
   if (hipStreamSynchronize(nullptr) != hipSuccess) {
     delete h;
     return fail_hip(hipGetLastError(), "rx_create reference bits");
@@ -461,8 +625,49 @@ int rx_create(rx_format fmt, double baud, double fs, const rx_params *pin, rx_ha
 static int check_n(rx_handle h, size_t n) {
   if (n == 0 || n % 1024 || n > h->p.max_samples) return RX_E_INVALID;
   const int64_t nsym = (int64_t)n / h->sps;
-  if (nsym < h->p.prefix_symbols + 2 * RX_GUARD + 128) return RX_E_INVALID;
+  if (h->hj.stream && h->acquired) return RX_OK;   // any whole number of granules continues a stream
+  const int64_t held = h->hj.stream ? h->tail_n / h->sps : 0;   // a stream's first buffer also fills the tail
+  if (nsym < h->p.prefix_symbols + 2 * RX_GUARD + 128 + held) return RX_E_INVALID;
   return RX_OK;
+}
+
+// Symbols a call emits: all of an independent buffer; a stream's first
+// buffer holds its last `hold` samples back, later ones emit exactly their
+// own length (the decisions of the previous buffer's held samples first).
+static int64_t emitted_symbols(rx_handle h, size_t n) {
+  if (!h->hj.stream) return (int64_t)n / h->sps;
+  return h->acquired ? (int64_t)n / h->sps : ((int64_t)n - h->hj.hold) / h->sps;
+}
+
+// A stream buffer's input: the first one as it is; a later one after the
+// stream's tail, assembled in the handle's staging area.  Returns the
+// pointer and length to process and the launch's s0 (see RxLaunch).
+static hipError_t stream_input(rx_handle h, const void *buf, size_t n, hipStream_t s, const void **in, int64_t *nx,
+                               int64_t *s0) {
+  if (!h->hj.stream || !h->acquired) {
+    *in = buf;
+    *nx = (int64_t)n;
+    *s0 = -1;
+    return hipSuccess;
+  }
+  const size_t tb = (size_t)h->tail_n / 2 * 3;
+  hipError_t e = hipMemcpyAsync(h->sx, h->stail, tb, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(h->sx + tb, buf, n / 2 * 3, hipMemcpyDeviceToDevice, s);
+  *in = h->sx;
+  *nx = h->tail_n + (int64_t)n;
+  *s0 = h->stream_pos - h->tail_n;
+  return e;
+}
+
+// After a stream buffer: its input's last hold + look samples become the tail.
+static hipError_t stream_advance(rx_handle h, const void *in, int64_t nx, size_t n, hipStream_t s) {
+  if (!h->hj.stream) return hipSuccess;
+  const size_t tb = (size_t)h->tail_n / 2 * 3;
+  const hipError_t e = hipMemcpyAsync(h->stail, static_cast<const uint8_t *>(in) + (size_t)(nx - h->tail_n) / 2 * 3, tb,
+                                      hipMemcpyDeviceToDevice, s);
+  h->stream_pos += (int64_t)n;
+  h->acquired = true;
+  return e;
 }
 
 static const int KK_STAGES[] = {ST_KK_FRONT, ST_PREFIX, ST_BLOCKS, ST_KK_VV, ST_DECIDE, ST_KK_DEBUG};
@@ -470,14 +675,21 @@ static const int PAM_STAGES[] = {ST_PAM_SUM, ST_PAM_MF, ST_PAM_GAVG, ST_PAM_UNWR
                                  ST_PREFIX, ST_BLOCKS, ST_DECIDE};
 static const int PAM_MLP_STAGES[] = {ST_PAM_SUM, ST_PAM_MF, ST_PAM_GAVG, ST_PAM_UNWRAP, ST_PAM_FARROW,
                                      ST_PREFIX, ST_MLP_INFER, ST_MLP_JUDGE, ST_BLOCKS, ST_DECIDE};
+// a stream buffer after the first: the acquisition (means, gain, delay,
+// rotation, prefix taps, network judgement) is the stream's
+static const int KK_CONT_STAGES[] = {ST_KK_FRONT, ST_BLOCKS, ST_KK_VV, ST_DECIDE, ST_KK_DEBUG};
+static const int PAM_CONT_STAGES[] = {ST_PAM_MF, ST_PAM_GAVG, ST_PAM_UNWRAP, ST_PAM_FARROW, ST_BLOCKS, ST_DECIDE};
+static const int PAM_MLP_CONT_STAGES[] = {ST_PAM_MF, ST_PAM_GAVG, ST_PAM_UNWRAP, ST_PAM_FARROW, ST_MLP_INFER,
+                                          ST_BLOCKS, ST_DECIDE};
 
 static bool uses_mlp(const rx_ctx *h) { return h->p.equalizer == RX_EQ_MLP && h->mlp_ready; }
 
 // Launch the chains of one batch: jobs grouped by (chain, FFT size, taps),
 // each group one launch per stage.  With RX_PROFILE on the first handle
 // (and not under graph capture) every stage is bracketed by events.
-static int enqueue(rx_handle const *hs, const void *const *bufs, const size_t *ns, void *const *bits, int count,
-                   hipStream_t s, bool capturing) {
+// ns[i]: samples to process (a stream buffer's with its tail); s0[i]: see RxLaunch.
+static int enqueue(rx_handle const *hs, const void *const *bufs, const int64_t *ns, const int64_t *s0,
+                   void *const *bits, int count, hipStream_t s, bool capturing) {
   bool done[RX_MAXB] = {false};
   rx_ctx *prof = (!capturing && (hs[0]->p.flags & RX_PROFILE)) ? hs[0] : nullptr;
   for (int i = 0; i < count; i++) {
@@ -485,21 +697,32 @@ static int enqueue(rx_handle const *hs, const void *const *bufs, const size_t *n
     RxLaunch L{};
     int64_t maxn = 0;
     const rx_ctx *a = hs[i];
+    const bool cont = s0[i] >= 0;
     for (int j = i; j < count; j++) {
       const rx_ctx *b = hs[j];
       if (done[j] || b->kk != a->kk || b->log2n != a->log2n || b->p.ffe_taps != a->p.ffe_taps ||
-          b->p.precision != a->p.precision || uses_mlp(b) != uses_mlp(a))
+          b->tune.blocks_bc != a->tune.blocks_bc || b->tune.ffe_gpw != a->tune.ffe_gpw ||
+          b->tune.dec_syms != a->tune.dec_syms ||
+          b->p.precision != a->p.precision || uses_mlp(b) != uses_mlp(a) || (s0[j] >= 0) != cont)
         continue;
       done[j] = true;
       L.job[L.count] = b->dj;
       L.in[L.count] = static_cast<const uint8_t *>(bufs[j]);
       L.bits[L.count] = static_cast<uint8_t *>(bits[j]);
-      L.n[L.count] = (int64_t)ns[j];
+      L.n[L.count] = ns[j];
+      L.s0[L.count] = s0[j];
       L.count++;
-      if ((int64_t)ns[j] > maxn) maxn = (int64_t)ns[j];
+      if (ns[j] > maxn) maxn = ns[j];
     }
-    const int *st = a->kk ? KK_STAGES : (uses_mlp(a) ? PAM_MLP_STAGES : PAM_STAGES);
-    const int nst = a->kk ? (a->hj.debug ? 6 : 5) : (uses_mlp(a) ? 10 : 8);
+    const int *st;
+    int nst;
+    if (cont) {
+      st = a->kk ? KK_CONT_STAGES : (uses_mlp(a) ? PAM_MLP_CONT_STAGES : PAM_CONT_STAGES);
+      nst = a->kk ? (a->hj.debug ? 5 : 4) : (uses_mlp(a) ? 7 : 6);
+    } else {
+      st = a->kk ? KK_STAGES : (uses_mlp(a) ? PAM_MLP_STAGES : PAM_STAGES);
+      nst = a->kk ? (a->hj.debug ? 6 : 5) : (uses_mlp(a) ? 10 : 8);
+    }
     for (int k = 0; k < nst; k++) {
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (prof) {
@@ -513,7 +736,7 @@ static int enqueue(rx_handle const *hs, const void *const *bufs, const size_t *n
       else if (st[k] == ST_MLP_INFER || st[k] == ST_MLP_JUDGE)
         rx_launch_mlp_stage(st[k], L, maxn, s);
       else
-        rx_launch_eq_stage(st[k], L, maxn, a->kk, a->p.ffe_taps, a->p.precision, s);
+        rx_launch_eq_stage(st[k], L, maxn, a->kk, a->p.ffe_taps, a->p.precision, a->tune, s);
       if (prof) {
         e1 = prof->event();
         hipEventRecord(e1, s);
@@ -531,11 +754,37 @@ int rx_process(rx_handle h, const void *dev_buffer, size_t n_samples, void *dev_
   if (!h || !dev_buffer || !dev_bits || !aligned4(dev_buffer) || !aligned4(dev_bits)) return RX_E_INVALID;
   int rc = check_n(h, n_samples);
   if (rc) return rc;
-  rc = enqueue(&h, &dev_buffer, &n_samples, &dev_bits, 1, h->stream, false);
+  const int64_t nemit = emitted_symbols(h, n_samples);
+  const void *in = nullptr;
+  int64_t nx = 0, s0 = -1;
+  hipError_t e = stream_input(h, dev_buffer, n_samples, h->stream, &in, &nx, &s0);
+  if (e != hipSuccess) return fail_hip(e, "hipMemcpyAsync (stream input)");
+  rc = enqueue(&h, &in, &nx, &s0, &dev_bits, 1, h->stream, false);
   if (rc) return rc;
-  h->last_n = (int64_t)n_samples;
-  if (n_bits_out) *n_bits_out = n_samples / h->sps * h->bps;
+  e = stream_advance(h, in, nx, n_samples, h->stream);
+  if (e != hipSuccess) return fail_hip(e, "hipMemcpyAsync (stream tail)");
+  h->last_n = nx;
+  if (n_bits_out) *n_bits_out = (size_t)(nemit * h->bps);
   return (h->p.equalizer == RX_EQ_MLP && !h->mlp_ready) ? RX_W_FALLBACK : RX_OK;
+}
+
+int rx_tuning(rx_handle h, int32_t *shapes) {
+  if (!h || !shapes) return RX_E_INVALID;
+  shapes[0] = h->tune.fft_log2;
+  shapes[1] = h->tune.blocks_bc;
+  shapes[2] = h->tune.ffe_gpw;
+  shapes[3] = h->tune.dec_syms;
+  return RX_OK;
+}
+
+int rx_stream_reset(rx_handle h) {
+  if (!h) return RX_E_INVALID;
+  if (!h->hj.stream) return RX_E_STATE;
+  const hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
+  h->stream_pos = 0;
+  h->acquired = false;
+  return RX_OK;
 }
 
 int rx_process_batch(const rx_handle *hs, const void *const *bufs, const size_t *ns, void *const *bits, int count,
@@ -551,8 +800,21 @@ int rx_process_batch(const rx_handle *hs, const void *const *bufs, const size_t 
   }
   hipStream_t s = hs[0]->stream;
   int rc = RX_OK;
+  bool any_stream = false;
+  for (int i = 0; i < count; i++) any_stream |= hs[i]->hj.stream != 0;
+  if (graph && any_stream) return RX_E_UNSUPPORTED;   // a stream's launch arguments change every call
+  const void *in[RX_MAXB];
+  int64_t nx[RX_MAXB], s0[RX_MAXB];
+  for (int i = 0; i < count; i++) {
+    const hipError_t e = stream_input(hs[i], bufs[i], ns[i], s, &in[i], &nx[i], &s0[i]);
+    if (e != hipSuccess) return fail_hip(e, "hipMemcpyAsync (stream input)");
+  }
   if (!graph) {
-    rc = enqueue(hs, bufs, ns, bits, count, s, false);
+    rc = enqueue(hs, in, nx, s0, bits, count, s, false);
+    for (int i = 0; i < count && rc == RX_OK; i++) {
+      const hipError_t e = stream_advance(hs[i], in[i], nx[i], ns[i], s);
+      if (e != hipSuccess) rc = fail_hip(e, "hipMemcpyAsync (stream tail)");
+    }
   } else {
     GraphCache &gc = hs[0]->graph;
     // a graph replays the stage list and job pointers of the handles it was
@@ -580,7 +842,7 @@ int rx_process_batch(const rx_handle *hs, const void *const *bufs, const size_t 
       }
       e = hipStreamBeginCapture(gc.capture, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) return fail_hip(e, "hipStreamBeginCapture");
-      rc = enqueue(hs, bufs, ns, bits, count, gc.capture, true);
+      rc = enqueue(hs, in, nx, s0, bits, count, gc.capture, true);
       e = hipStreamEndCapture(gc.capture, &g);
       if (rc) {
         if (g) hipGraphDestroy(g);
@@ -599,7 +861,7 @@ int rx_process_batch(const rx_handle *hs, const void *const *bufs, const size_t 
     if (e != hipSuccess) return fail_hip(e, "hipGraphLaunch");
   }
   if (rc == RX_OK)
-    for (int i = 0; i < count; i++) hs[i]->last_n = (int64_t)ns[i];
+    for (int i = 0; i < count; i++) hs[i]->last_n = nx[i];
   return rc;
 }
 
@@ -628,6 +890,8 @@ int rx_process_batch_host(const rx_handle *hs, const void *const *host_buffers, 
     dbits[i] = h->hbits;
   }
   hipStream_t s = hs[0]->stream;
+  size_t nbytes[RX_MAXB];
+  for (int i = 0; i < count; i++) nbytes[i] = (size_t)(emitted_symbols(hs[i], ns[i]) * hs[i]->bps / 8);
   for (int i = 0; i < count; i++) {
     const hipError_t e = hipMemcpyAsync(hs[i]->hin, host_buffers[i], ns[i] / 2 * 3, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return fail_hip(e, "hipMemcpyAsync (buffer in)");
@@ -635,7 +899,7 @@ int rx_process_batch_host(const rx_handle *hs, const void *const *host_buffers, 
   const int rc = rx_process_batch(hs, dbufs, ns, dbits, count, graph);
   if (rc) return rc;
   for (int i = 0; i < count; i++) {
-    const size_t nb = ns[i] / hs[i]->sps * hs[i]->bps / 8;
+    const size_t nb = nbytes[i];
     const hipError_t e = hipMemcpyAsync(host_bits[i], hs[i]->hbits, nb, hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return fail_hip(e, "hipMemcpyAsync (bits out)");
   }
@@ -914,8 +1178,9 @@ int rx_train_mlp(rx_handle h, const void *const *dev_buffers, const size_t *n_sa
     L.in[0] = static_cast<const uint8_t *>(dev_buffers[i]);
     L.n[0] = (int64_t)n_samples[i];
     L.count = 1;
+    L.s0[0] = -1;   // an independent buffer
     for (int st = ST_PAM_SUM; st <= ST_PAM_FARROW; st++) rx_launch_pam_stage(st, L, L.n[0], h->stream);
-    rx_launch_eq_stage(ST_PREFIX, L, L.n[0], 0, h->p.ffe_taps, 0, h->stream);
+    rx_launch_eq_stage(ST_PREFIX, L, L.n[0], 0, h->p.ffe_taps, 0, h->tune, h->stream);
     rx_mlp_windows(L, X, T, row0, h->stream);
     row0 += L.n[0] / 2 - 2 * RX_GUARD;
     e = hipGetLastError();
@@ -930,6 +1195,8 @@ int rx_train_mlp(rx_handle h, const void *const *dev_buffers, const size_t *n_sa
   if (rc == RX_OK) rc = rx_train_mlp_data(h, X, T, (size_t)rows, c, final_loss);
   hipFree(X);
   hipFree(T);
+  h->stream_pos = 0;   // the training buffers replaced a stream's acquisition: it starts over
+  h->acquired = false;
   return rc;
 }
 

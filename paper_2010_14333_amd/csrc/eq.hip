@@ -100,7 +100,7 @@ __global__ __launch_bounds__(PFX_T) void rx_prefix(RxLaunch L) {
   for (int idx = threadIdx.x; idx < PFX_UL; idx += PFX_T) {
     const int64_t j = (int64_t)idx - PFX_OFF;
     float2 v = make_float2(0.0f, 0.0f);
-    if (j >= 0 && j < nx) v = kk ? kk_sample(J, zin, j, n, mean, g) : make_float2(xin[j], 0.0f);
+    if (j >= 0 && j < nx) v = kk ? kk_sample(J, zin, j, n, mean, g, 0) : make_float2(xin[j], 0.0f);
     u[idx] = v;
   }
   for (int k = threadIdx.x; k < P; k += PFX_T) ar[k] = ref_symbol(J, k);
@@ -234,9 +234,8 @@ __global__ __launch_bounds__(PFX_T) void rx_prefix(RxLaunch L) {
 // back out the same way.  (Five wavefronts per SIMD, with 4-step chunks, is
 // faster alone but slows the chain: its workgroups keep the front end off
 // more CUs.)
-template <bool CPLX, int K>
+template <bool CPLX, int K, int BC>   // BC: steps per staged chunk (a tuned choice)
 __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
-  constexpr int BC = 8;   // steps per staged chunk (16 measured no faster on the real chain)
   using T = typename std::conditional<CPLX, float2, float>::type;
   constexpr int NBW = 128;   // blocks per workgroup (one lane pair each)
   __shared__ T sin_[NBW * (2 * BC + 1)];
@@ -260,12 +259,13 @@ __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
   const float g = CPLX ? (float)J.sc->agc : 1.0f;
   const float2 mean = make_float2((float)J.sc->mean_re, (float)J.sc->mean_im);
   const int s = J.sc->lag;
+  const int64_t g0 = L.s0[jb] > 0 ? L.s0[jb] : 0;   // stream index of sample 0 (downshift phase)
   const auto zin = gview(J.z);
   const auto xin = gptr(J.xr);
   float2 *const soft = J.soft;
   auto load = [&](int64_t j) -> T {
     if constexpr (CPLX) {
-      return kk_sample<true>(J, zin, j, n, mean, g);
+      return kk_sample<true>(J, zin, j, n, mean, g, g0);
     } else {
       return (j >= 0 && j < nx) ? xin[j] : 0.0f;
     }
@@ -296,7 +296,7 @@ __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
     // one fixed rotation per step of two samples
     float2 P = make_float2(1.0f, 0.0f), r4 = P;
     if constexpr (CPLX) {
-      P = cis_rev(-downshift_rev(J.r, 2 * (p0 - C - h)));
+      P = cis_rev(-downshift_rev(J.r, g0 + 2 * (p0 - C - h)));
       r4 = cis_rev(-downshift_rev(J.r, 4));
     }
 #pragma unroll
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
         const int64_t pl = pa + (int64_t)i * 2 * LPP * blk;
         zr[i] = zin[pl < 0 ? 0 : (pl >= nx ? nx - 1 : pl)];
       }
-      float2 P = cis_rev(-downshift_rev(J.r, 2 * pa));
+      float2 P = cis_rev(-downshift_rev(J.r, g0 + 2 * pa));
       bool edge = false;
 #pragma unroll
       for (int i = 0; i < NBW / LPP; i++) {
@@ -440,22 +440,21 @@ __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
 // 16 symbols (x = AGC'd 2-sps samples from 2(k0+s)-C), B = [[Wr, Wi],
 // [-Wi, Wr]] with W[t][q] = w0[2C + 2q - t]; 4 K-steps x 2 column tiles.
 // A group is 16 tiles (256 symbols = two VV blocks), whose z^4 sums the
-// wavefront also forms; each wavefront takes FFE_GPW consecutive groups
+// wavefront also forms; each wavefront takes GPW consecutive groups (a tuned choice)
 // (the next group's window in flight while the current one is filtered),
 // and the B fragments are built once per workgroup, in LDS.
-#define FFE_GPW 8
 #define FFE_PL 672   // staged plane length: window positions 0..543 with 8 elements of padding per 32
 // LDS index of window position t: the 16-byte A reads of the 16 rows then
 // fall on distinct banks (row stride 20 dwords)
 __device__ __forceinline__ int ffe_idx(int t) { return t + ((t >> 5) << 3); }
-template <int PREC>
+template <int PREC, int GPW>
 __global__ __launch_bounds__(256) void rx_ffe_mfma(RxLaunch L) {
   using NT = NarrowT<PREC>;
   const int jb = blockIdx.y;
   const RxJob J = *L.job[jb];
   const int64_t n = L.n[jb], nx = n / 2, nsym = n / 4;
   const int lane = threadIdx.x & 63;
-  const int64_t grp0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * FFE_GPW;
+  const int64_t grp0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * GPW;
   const int K = J.ffe_taps, C = (K - 1) / 2;
   const int row = lane & 15, kq = lane >> 4;
   // B fragments, shared by the workgroup's wavefronts in LDS (wavefront ks
@@ -483,6 +482,7 @@ __global__ __launch_bounds__(256) void rx_ffe_mfma(RxLaunch L) {
   const int s = J.sc->lag;
   const float g = (float)J.sc->agc;
   const float2 mean = make_float2((float)J.sc->mean_re, (float)J.sc->mean_im);
+  const int64_t g0 = L.s0[jb] > 0 ? L.s0[jb] : 0;   // stream index of sample 0 (downshift phase)
   const auto zin = gview(J.z);
   // The group's 16 windows cover samples base0 .. base0 + 543; they are
   // staged once per group into this wavefront's LDS planes as u rounded to
@@ -508,17 +508,17 @@ __global__ __launch_bounds__(256) void rx_ffe_mfma(RxLaunch L) {
   };
   float4 zn[5];
   load_pairs(grp0, zn);
-  for (int gi = 0; gi < FFE_GPW; gi++) {
+  for (int gi = 0; gi < GPW; gi++) {
     const int64_t grp = grp0 + gi;
     if (grp * 256 >= nsym) break;
     float4 zc[5];
 #pragma unroll
     for (int it = 0; it < 5; it++) zc[it] = zn[it];
-    if (gi + 1 < FFE_GPW && (grp + 1) * 256 < nsym) load_pairs(grp + 1, zn);   // in flight during this group
+    if (gi + 1 < GPW && (grp + 1) * 256 < nsym) load_pairs(grp + 1, zn);   // in flight during this group
     const int64_t base0 = 2 * (grp * 256 + s) - C;
     const int odd = (int)(base0 & 1);
     const int64_t R0 = base0 - odd;
-    float2 P = cis_rev(-downshift_rev(J.r, 2 * (R0 + 2 * lane)));
+    float2 P = cis_rev(-downshift_rev(J.r, g0 + 2 * (R0 + 2 * lane)));
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");   // the previous group's reads are done
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -533,8 +533,8 @@ __global__ __launch_bounds__(256) void rx_ffe_mfma(RxLaunch L) {
           u0 = csub(cscale(make_float2(zz.x, zz.y), g), cmul(Mc, P));
           u1 = csub(cscale(make_float2(zz.z, zz.w), g), cmul(Mc, cmul(P, r1)));
         } else {
-          u0 = kk_sample(J, zin, p, n, mean, g);
-          u1 = kk_sample(J, zin, p + 1, n, mean, g);
+          u0 = kk_sample(J, zin, p, n, mean, g, g0);
+          u1 = kk_sample(J, zin, p + 1, n, mean, g, g0);
         }
         const int t0 = 2 * pi - odd;   // window position of sample p
         if (t0 >= 0 && t0 < 544) {
@@ -584,10 +584,11 @@ __global__ __launch_bounds__(256) void rx_ffe_mfma(RxLaunch L) {
 // symbols per lane (one derotation phase, one 8*bps-bit chunk of the stream);
 // the workgroup's DEC_SYMS symbols are packed in LDS, written out as whole
 // words, and its error counts added with one set of atomics.
-#define DEC_SYMS 2048
-__global__ __launch_bounds__(256) void rx_decide(RxLaunch L) {
+template <int DEC_SYMS>   // symbols per workgroup, 8 per thread (a tuned choice)
+__global__ __launch_bounds__(DEC_SYMS / 8) void rx_decide(RxLaunch L) {
+  constexpr int NT = DEC_SYMS / 8;
   __shared__ uint32_t wb[DEC_SYMS * 4 / 32];   // the workgroup's packed bits (up to 4 per symbol)
-  __shared__ uint32_t red[4];
+  __shared__ uint32_t red[NT / 64];
   const int jb = blockIdx.y;
   const RxJob J = *L.job[jb];
   const int64_t n = L.n[jb];
@@ -595,32 +596,50 @@ __global__ __launch_bounds__(256) void rx_decide(RxLaunch L) {
   const int64_t nsym = n / (kk ? 4 : 2);
   const int64_t kbase = (int64_t)blockIdx.x * DEC_SYMS;
   if (kbase >= nsym) return;   // nsym is a multiple of 256
+  // emitted symbols [k_lo, k_hi) of this input (all of an independent
+  // buffer; a stream buffer holds its last samples back and, after the
+  // first, skips the prepended ones), output bit 0 = symbol k_lo; the
+  // stream's symbol index is kg0 + k
+  const RxSpan sp = rx_span(J, n, L.s0[jb]);
   const auto out = gptr(reinterpret_cast<uint32_t *>(L.bits[jb]));
   float2 *const soft = J.soft;
   const int nw = DEC_SYMS * bps / 32;
   if (bps != 4)   // 4 bits per symbol: each thread's 8 symbols are one whole output word (below)
-    for (int i = threadIdx.x; i < nw; i += 256) wb[i] = 0u;
-  // this thread: symbols k0 .. k0 + 7 (one DD-LMS block, so one phase)
+    for (int i = threadIdx.x; i < nw; i += NT) wb[i] = 0u;
+  // this thread: symbols k0 .. k0 + 7 (one DD-LMS block, so one phase); the
+  // emission bounds are multiples of 256 symbols, so a thread's 8 are all in
+  // or all out
   const int64_t k0 = kbase + 8 * threadIdx.x;
   const bool valid = k0 < nsym;   // then k0 + 8 <= nsym
+  const bool emit = valid && k0 >= sp.k_lo && k0 < sp.k_hi;
   // counted symbols, symbol errors and bit errors of this thread, packed as
   // cs | se << 10 | be << 20: a wavefront counts at most 512 symbols and
   // 2048 bit errors (4 bits per symbol at most), so no field overflows
   uint32_t cnt = 0;
   uint32_t chunk = 0;   // symbol k0 + i at bits [bps i, bps (i + 1)), MSB of the symbol first
-  if (valid) {
-    // counted symbols of this thread: i in [ilo, ihi)
-    const int64_t lo64 = P + RX_GUARD - k0, hi64 = nsym - RX_GUARD - k0;
+  if (emit) {
+    // counted symbols of this thread: i in [ilo, ihi) (stream indices from
+    // P + 64 on; an independent buffer also leaves its last 64 out)
+    const int64_t clo = P + RX_GUARD - sp.kg0, chi = J.stream ? sp.k_hi : nsym - RX_GUARD;
+    const int64_t lo64 = clo - k0, hi64 = chi - k0;
     const int ilo = (int)(lo64 < 0 ? 0 : (lo64 > 8 ? 8 : lo64)), ihi = (int)(hi64 < 0 ? 0 : (hi64 > 8 ? 8 : hi64));
-    // the thread's reference symbols: bits [bps k0, bps (k0 + 8)) of the
-    // handle's reference stream (k0 is a multiple of 8, so they start at bit
-    // (bps k0) mod 32 of a word and end within the next)
-    const int64_t ob = (int64_t)bps * k0;
-    const auto rw = gptr(J.refw);
-    // the second word only where the 8 bps bits cross into it: then it still
-    // holds bits of these symbols, so no read goes past the stream's last word
-    const uint64_t w1 = ((ob & 31) + 8 * bps > 32) ? (uint64_t)rw[(ob >> 5) + 1] : 0ull;
-    const uint32_t refc = (uint32_t)(((uint64_t)rw[ob >> 5] | (w1 << 32)) >> (ob & 31));
+    // the thread's reference symbols, packed like the output: from the
+    // handle's stream of them (bits [bps k0, bps (k0 + 8)): k0 is a
+    // multiple of 8, so they start at bit (bps k0) mod 32 of a word and end
+    // within the next), or, for a stream, from the seed at the stream index
+    uint32_t refc = 0u;
+    if (J.stream) {
+#pragma unroll
+      for (int i = 0; i < 8; i++)
+        refc |= (__builtin_bitreverse32(ref_seed_bits(J, sp.kg0 + k0 + i)) >> (32 - bps)) << (bps * i);
+    } else {
+      const int64_t ob = (int64_t)bps * k0;
+      const auto rw = gptr(J.refw);
+      // the second word only where the 8 bps bits cross into it: then it still
+      // holds bits of these symbols, so no read goes past the stream's last word
+      const uint64_t w1 = ((ob & 31) + 8 * bps > 32) ? (uint64_t)rw[(ob >> 5) + 1] : 0ull;
+      refc = (uint32_t)(((uint64_t)rw[ob >> 5] | (w1 << 32)) >> (ob & 31));
+    }
     float2 zv[8];
     if (kk) {   // complex soft symbols
 #pragma unroll
@@ -665,18 +684,22 @@ __global__ __launch_bounds__(256) void rx_decide(RxLaunch L) {
       }
     }
   }
-  if (bps == 4) {   // (uniform) symbols k0 .. k0 + 7 are exactly output word k0 / 8
-    if (valid) out[k0 / 8] = chunk;
+  if (bps == 4) {   // (uniform) symbols k0 .. k0 + 7 are exactly output word (k0 - k_lo) / 8
+    if (emit) out[(k0 - sp.k_lo) / 8] = chunk;
   } else {          // the workgroup's words assembled in LDS, then written whole
     __syncthreads();
-    if (valid) {
+    if (emit) {
       const int lb = 8 * bps * threadIdx.x, wi = lb >> 5, off = lb & 31;
       atomicOr(&wb[wi], chunk << off);
       if (off + 8 * bps > 32) atomicOr(&wb[wi + 1], chunk >> (32 - off));
     }
     __syncthreads();
+    // word i holds bits of symbols from kbase + 32 i / bps on; the emission
+    // bounds are multiples of 256 symbols, i.e. of whole words
     const int64_t nsw = (nsym - kbase < DEC_SYMS ? nsym - kbase : DEC_SYMS) * bps / 32;
-    for (int i = threadIdx.x; i < nsw; i += 256) out[kbase * bps / 32 + i] = wb[i];
+    const int64_t wlo = (sp.k_lo - kbase) * bps / 32, whi = (sp.k_hi - kbase) * bps / 32;
+    for (int i = threadIdx.x; i < nsw; i += NT)
+      if (i >= wlo && i < whi) out[(kbase - sp.k_lo) * bps / 32 + i] = wb[i];
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
@@ -685,7 +708,7 @@ __global__ __launch_bounds__(256) void rx_decide(RxLaunch L) {
   if (threadIdx.x == 0) {
     unsigned long long cs = 0, se = 0, be = 0;
 #pragma unroll
-    for (int w = 0; w < 4; w++) {
+    for (int w = 0; w < NT / 64; w++) {
       cs += red[w] & 1023u;
       se += (red[w] >> 10) & 1023u;
       be += red[w] >> 20;
@@ -702,8 +725,10 @@ __global__ __launch_bounds__(256) void rx_decide(RxLaunch L) {
     }
     // the buffer's last decision workgroup to finish closes its latency:
     // wall clock now minus the start its first kernel recorded, against the
-    // deadline (the buffer's own real-time span n / fs unless one is set)
-    __threadfence();
+    // deadline (the buffer's own real-time span n / fs unless one is set).
+    // The count is an atomic and the stamp needs no other workgroup's data,
+    // so no fence: a device-scope fence here would write the L2 back once
+    // per workgroup (it took the stage from 2.5 to 23 us per buffer).
     const unsigned nwg = (unsigned)((nsym + DEC_SYMS - 1) / DEC_SYMS);
     if (atomicAdd(&J.sc->done_wg, 1u) == nwg - 1) {
       RxScalars *const sc = J.sc;
@@ -724,7 +749,8 @@ __global__ __launch_bounds__(256) void rx_decide(RxLaunch L) {
 // SplitMix64(seed, k), stored like the decided bits (symbol k at stream
 // bits [bps k, bps (k + 1)), its most significant bit first).  Filled once
 // when the handle is created; every buffer of the handle is compared with it.
-__global__ __launch_bounds__(256) void rx_ref_fill(uint32_t *w, int64_t words, uint64_t seed, int bps, int64_t nsym) {
+__global__ __launch_bounds__(256) void rx_ref_fill(uint32_t *w, int64_t words, uint64_t seed, int bps, int64_t nsym,
+                                                   uint64_t period) {
   const int64_t wi = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (wi >= words) return;
   uint32_t v = 0u;
@@ -735,7 +761,7 @@ __global__ __launch_bounds__(256) void rx_ref_fill(uint32_t *w, int64_t words, u
     if (k >= nsym) break;
     if (k != kc) {
       kc = k;
-      sym = (uint32_t)(splitmix64(seed, (uint64_t)k) >> (64 - bps));
+      sym = (uint32_t)(splitmix64(seed, period ? (uint64_t)k % period : (uint64_t)k) >> (64 - bps));
     }
     const int j = (int)(sb - k * bps);   // bit j of the field: bit bps - 1 - j of the symbol
     v |= ((sym >> (bps - 1 - j)) & 1u) << b;
@@ -743,31 +769,49 @@ __global__ __launch_bounds__(256) void rx_ref_fill(uint32_t *w, int64_t words, u
   w[wi] = v;
 }
 
-void rx_launch_ref_fill(uint32_t *w, int64_t words, uint64_t seed, int bps, int64_t nsym, hipStream_t s) {
-  hipLaunchKernelGGL(rx_ref_fill, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, w, words, seed, bps, nsym);
+void rx_launch_ref_fill(uint32_t *w, int64_t words, uint64_t seed, int bps, int64_t nsym, uint64_t period,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(rx_ref_fill, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, w, words, seed, bps, nsym,
+                     period);
 }
 
-void rx_launch_eq_stage(int stage, const RxLaunch &L, int64_t maxn, int kk, int ffe_taps, int prec, hipStream_t s) {
+void rx_launch_eq_stage(int stage, const RxLaunch &L, int64_t maxn, int kk, int ffe_taps, int prec, const RxTune &t,
+                        hipStream_t s) {
   const unsigned cnt = (unsigned)L.count;
   const int64_t nsym = maxn / (kk ? 4 : 2);
   if (stage == ST_PREFIX) {
     hipLaunchKernelGGL(rx_prefix, dim3(1, cnt), dim3(PFX_T), 0, s, L);
   } else if (stage == ST_BLOCKS && kk && prec != 0) {
     const int64_t ngrp = (nsym + 255) / 256;
-    dim3 gf((unsigned)((ngrp + 4 * FFE_GPW - 1) / (4 * FFE_GPW)), cnt);   // four wavefronts per workgroup
-    if (prec == 1) hipLaunchKernelGGL(rx_ffe_mfma<1>, gf, dim3(256), 0, s, L);
-    else hipLaunchKernelGGL(rx_ffe_mfma<2>, gf, dim3(256), 0, s, L);
+    const int gpw = t.ffe_gpw;
+    dim3 gf((unsigned)((ngrp + 4 * gpw - 1) / (4 * gpw)), cnt);   // four wavefronts per workgroup
+#define RX_FFE(P, G) hipLaunchKernelGGL((rx_ffe_mfma<P, G>), gf, dim3(256), 0, s, L)
+    if (prec == 1) {
+      if (gpw == 4) RX_FFE(1, 4); else if (gpw == 16) RX_FFE(1, 16); else RX_FFE(1, 8);
+    } else {
+      if (gpw == 4) RX_FFE(2, 4); else if (gpw == 16) RX_FFE(2, 16); else RX_FFE(2, 8);
+    }
+#undef RX_FFE
   } else if (stage == ST_BLOCKS) {
     const int64_t nb = nsym / (kk ? 128 : 256);
     dim3 gb((unsigned)((nb + 127) / 128), cnt);   // 128 blocks (lane pairs) per workgroup
+#define RX_BLK(C, K, B) hipLaunchKernelGGL((rx_blocks<C, K, B>), gb, dim3(256), 0, s, L)
+#define RX_BLK_BC(C, K) \
+  do { if (t.blocks_bc == 4) RX_BLK(C, K, 4); else if (t.blocks_bc == 16) RX_BLK(C, K, 16); else RX_BLK(C, K, 8); } while (0)
     if (kk) {
-      if (ffe_taps == 21) hipLaunchKernelGGL((rx_blocks<true, 21>), gb, dim3(256), 0, s, L);
-      else hipLaunchKernelGGL((rx_blocks<true, 15>), gb, dim3(256), 0, s, L);
+      if (ffe_taps == 21) RX_BLK_BC(true, 21);
+      else RX_BLK_BC(true, 15);
     } else {
-      if (ffe_taps == 21) hipLaunchKernelGGL((rx_blocks<false, 21>), gb, dim3(256), 0, s, L);
-      else hipLaunchKernelGGL((rx_blocks<false, 15>), gb, dim3(256), 0, s, L);
+      if (ffe_taps == 21) RX_BLK_BC(false, 21);
+      else RX_BLK_BC(false, 15);
     }
+#undef RX_BLK_BC
+#undef RX_BLK
   } else if (stage == ST_DECIDE) {
-    hipLaunchKernelGGL(rx_decide, dim3((unsigned)((nsym + DEC_SYMS - 1) / DEC_SYMS), cnt), dim3(256), 0, s, L);
+    const int ds = t.dec_syms;
+    dim3 gd((unsigned)((nsym + ds - 1) / ds), cnt);
+    if (ds == 1024) hipLaunchKernelGGL(rx_decide<1024>, gd, dim3(128), 0, s, L);
+    else if (ds == 4096) hipLaunchKernelGGL(rx_decide<4096>, gd, dim3(512), 0, s, L);
+    else hipLaunchKernelGGL(rx_decide<2048>, gd, dim3(256), 0, s, L);
   }
 }

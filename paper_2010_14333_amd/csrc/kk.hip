@@ -161,6 +161,7 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
   const RxJob J = *L.job[jb];
   const int64_t n = L.n[jb];
   const uint8_t *in = L.in[jb];
+  const int64_t g0 = L.s0[jb] > 0 ? L.s0[jb] : 0;   // stream index of sample 0 (downshift phase)
   const int64_t nrb = (n + HOP - 1) / HOP;
   const int64_t blk[2] = {2 * (int64_t)blockIdx.x, 2 * (int64_t)blockIdx.x + 1};
   if (blk[0] >= nrb) return;
@@ -297,7 +298,7 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
     const int e = (int)(nq0 & 1);
     const uint8_t *cb = in + 3 * ((nq0 - e) / 2);
     const int qlo = (int)clamp64(-nq0, 0, QN), qhi = (int)clamp64(n - nq0, 0, QN);   // t in [0, n)
-    float2 dph = cis_rev(-downshift_rev(J.r, nq0 + threadIdx.x));
+    float2 dph = cis_rev(-downshift_rev(J.r, g0 + nq0 + threadIdx.x));
     // all of this thread's code reads first (index clamped into the buffer),
     // so their latencies overlap
     int craw[QPT];
@@ -352,7 +353,7 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
     bmf.load(htab, row, kq);
     // P at this lane's first output of the block, exact from the FP64 phase
     const int64_t mfirst = m0 + 16 * (8 * wv + 2 * kq) + row;
-    float2 pp = cis_rev(downshift_rev(J.r, 2 * mfirst));
+    float2 pp = cis_rev(downshift_rev(J.r, g0 + 2 * mfirst));
     // outputs are handled by their offset mr = m - m0 < HOP / 2 in the block:
     // valid (2 m < n) below mlim, interior (m >= 16, 2 m + 32 < n) in
     // [mil, mih); n is even, so both limits are exact integers
@@ -378,7 +379,7 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
             sp = cadd(sp, cmul(zv, p));
             nint++;
           } else {
-            const float2 te = kk_carrier_edge_inl(J.mf, J.r, m0 + mr, n);
+            const float2 te = kk_carrier_edge_inl(J.mf, J.r, m0 + mr, n, g0);
             sedge = cadd(sedge, cmulc(zv, te));
             tedge = fmaf(te.x, te.x, fmaf(te.y, te.y, tedge));
           }
@@ -409,18 +410,26 @@ __global__ __launch_bounds__(256) void kk_debug_u(RxLaunch L) {
   const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (m >= n / 2) return;
   const float2 mean = make_float2((float)J.sc->mean_re, (float)J.sc->mean_im);
-  J.udbg[m] = kk_sample(J, J.z, m, n, mean, (float)J.sc->agc);
+  J.udbg[m] = kk_sample(J, J.z, m, n, mean, (float)J.sc->agc, L.s0[jb] > 0 ? L.s0[jb] : 0);
 }
 
 // Viterbi-Viterbi carrier phase per DD-LMS block over blocks b-1..b+1,
 // unwrapped in multiples of pi/2 (wrapped differences, then a workgroup
-// prefix sum), one workgroup per buffer.
+// prefix sum), one workgroup per buffer.  A stream buffer after the first
+// continues the unwrap from the phase carried from the previous buffer's
+// last emitted block (the block just before its first emitted one), and
+// every stream buffer carries its own last emitted block's phase on.
 __global__ __launch_bounds__(1024) void kk_vv(RxLaunch L) {
   __shared__ double scan[1024];
   const int jb = blockIdx.y;
   const RxJob J = *L.job[jb];
-  const int64_t nsym = L.n[jb] / 4;
+  const int64_t n = L.n[jb];
+  const int64_t nsym = n / 4;
   const int nb = (int)(nsym / J.blk);
+  const RxSpan sp = rx_span(J, n, L.s0[jb]);
+  const bool cont = J.stream && L.s0[jb] >= 0;
+  const int bs = cont ? (int)(sp.k_lo / J.blk) - 1 : 0;   // first block of the scan
+  const int blast = (int)(sp.k_hi / J.blk) - 1;            // last emitted block
   const int per = (nb + 1023) / 1024;
   const int b0 = threadIdx.x * per;
   constexpr float Q = 1.5707963267948966f;
@@ -431,11 +440,17 @@ __global__ __launch_bounds__(1024) void kk_vv(RxLaunch L) {
     return 0.25f * atan2f(-s.y, -s.x);
   };
   auto wrapq = [&](float d) { return d - Q * floorf(d / Q + 0.5f); };
+  const double first = cont ? J.sc->theta_carry : 0.0;
+  auto step = [&](int b, float r, float prev) -> double {
+    if (b < bs) return 0.0;
+    if (b == bs) return cont ? first : (double)r;
+    return wrapq(r - prev);
+  };
   double local = 0.0;
   float prev = (b0 > 0 && b0 < nb) ? raw(b0 - 1) : 0.0f;
   for (int b = b0; b < b0 + per && b < nb; b++) {
     const float r = raw(b);
-    local += (b == 0) ? r : wrapq(r - prev);
+    local += step(b, r, prev);
     prev = r;
   }
   scan[threadIdx.x] = local;
@@ -450,9 +465,10 @@ __global__ __launch_bounds__(1024) void kk_vv(RxLaunch L) {
   prev = (b0 > 0 && b0 < nb) ? raw(b0 - 1) : 0.0f;
   for (int b = b0; b < b0 + per && b < nb; b++) {
     const float r = raw(b);
-    th += (b == 0) ? r : wrapq(r - prev);
+    th += step(b, r, prev);
     prev = r;
     J.theta[b] = (float)th;
+    if (J.stream && b == blast) J.sc->theta_carry = th;
   }
 }
 

@@ -67,6 +67,8 @@ __global__ __launch_bounds__(256) void pam_mf(RxLaunch L) {
   const int64_t n = L.n[jb];
   const uint8_t *in = L.in[jb];
   if ((int64_t)blockIdx.x * PAM_MF_SUB * PAM_TS >= n) return;
+  // a stream buffer after the first starts here (its DC mean is the stream's)
+  if (L.s0[jb] >= 0 && blockIdx.x == 0 && threadIdx.x == 0) J.sc->t_start = (unsigned long long)wall_clock64();
   float hmf[33];   // the taps, read at the start (uniform: scalar registers)
 #pragma unroll
   for (int i = 0; i < 33; i++) hmf[i] = J.mf[i];
@@ -214,7 +216,12 @@ __global__ __launch_bounds__(256) void pam_gavg(RxLaunch L) {
 }
 
 // Unwrap (wrapped differences + workgroup prefix sum), timing shift
-// delta_b = 1/2 + psi_b / pi samples, and the AGC gain.
+// delta_b = 1/2 + psi_b / pi samples, and the AGC gain.  A stream buffer
+// after the first keeps the stream's gain and continues the unwrap from the
+// angle carried from the previous buffer's last emitted timing block (the
+// block just before its first emitted sample: the clock-phase continuity of
+// the paper's stream-to-stream events); every stream buffer carries its own
+// last emitted block's angle on.
 __global__ __launch_bounds__(1024) void pam_unwrap(RxLaunch L) {
   __shared__ double scan[1024];
   __shared__ double red[16];
@@ -223,19 +230,29 @@ __global__ __launch_bounds__(1024) void pam_unwrap(RxLaunch L) {
   const int64_t n = L.n[jb];
   const int nb = (int)(n / 512);
   const float *raw = J.delta + nb;
-  {
+  const bool cont = J.stream && L.s0[jb] >= 0;
+  if (!cont) {
     const int64_t np = (n + PAM_TS - 1) / PAM_TS;
     double p = 0.0;
     for (int64_t i = threadIdx.x; i < np; i += 1024) p += J.part2[i];
     p = block_sum(p, red);
     if (threadIdx.x == 0) J.sc->agc = 1.0 / sqrt(p / (double)n);
   }
+  const RxSpan sp = rx_span(J, n, L.s0[jb]);
+  const int bs = cont ? (int)(2 * sp.k_lo / 512) - 1 : 0;   // first block of the unwrap
+  const int blast = (int)(2 * sp.k_hi / 512) - 1;           // last emitted timing block
+  const double first = cont ? J.sc->acc_carry : 0.0;
   const int per = (nb + 1023) / 1024;
   const int b0 = threadIdx.x * per;
   constexpr double TWO_PI = 6.283185307179586;
   auto wrap = [&](double d) { return d - TWO_PI * floor(d / TWO_PI + 0.5); };
+  auto step = [&](int b) -> double {
+    if (b < bs) return 0.0;
+    if (b == bs) return cont ? first : (double)raw[b];
+    return wrap((double)raw[b] - raw[b - 1]);
+  };
   double local = 0.0;
-  for (int b = b0; b < b0 + per && b < nb; b++) local += (b == 0) ? raw[0] : wrap((double)raw[b] - raw[b - 1]);
+  for (int b = b0; b < b0 + per && b < nb; b++) local += step(b);
   scan[threadIdx.x] = local;
   __syncthreads();
   for (int o = 1; o < 1024; o <<= 1) {
@@ -247,8 +264,9 @@ __global__ __launch_bounds__(1024) void pam_unwrap(RxLaunch L) {
   double acc = scan[threadIdx.x] - local;   // exclusive prefix
   // raw angles live in the second half of the array, shifts in the first
   for (int b = b0; b < b0 + per && b < nb; b++) {
-    acc += (b == 0) ? raw[0] : wrap((double)raw[b] - raw[b - 1]);
+    acc += step(b);
     J.delta[b] = (float)(0.5 + acc / 3.141592653589793);
+    if (J.stream && b == blast) J.sc->acc_carry = acc;
   }
 }
 

@@ -149,10 +149,19 @@ __device__ __forceinline__ uint32_t ref_stream_bits(const RxJob &J, int64_t k) {
   return __builtin_bitreverse32(f) >> (32 - J.bps);
 }
 
-// Transmitted symbol k in odd-integer units (QAM: I bits first): from the
-// caller's reference stream if the handle has one, else from the seed.
+// Bits of symbol k of the seeded reference sequence (top bps bits of the
+// k-th SplitMix64 output; the sequence repeats every ref_period symbols when
+// that is set, as a transmitter repeating a finite pattern does).
+__device__ __forceinline__ uint32_t ref_seed_bits(const RxJob &J, int64_t k) {
+  const uint64_t kr = J.ref_period ? (uint64_t)k % J.ref_period : (uint64_t)k;
+  return (uint32_t)(splitmix64(J.seed, kr) >> (64 - J.bps));
+}
+
+// Transmitted symbol k (stream index) in odd-integer units (QAM: I bits
+// first): from the caller's reference stream if the handle has one, else
+// from the seed.
 __device__ __forceinline__ float2 ref_symbol(const RxJob &J, int64_t k) {
-  const uint32_t b = J.ref_ext ? ref_stream_bits(J, k) : (uint32_t)(splitmix64(J.seed, (uint64_t)k) >> (64 - J.bps));
+  const uint32_t b = J.ref_ext ? ref_stream_bits(J, k) : ref_seed_bits(J, k);
   const int m = J.m_axis;
   if (J.kk) {
     const int half = J.bps >> 1;
@@ -215,33 +224,36 @@ __device__ __forceinline__ float2 cis_rev(float rev) {
 }
 
 // KK: the matched filter's response to the downshifted carrier,
-// T[m] = sum_i h[i] exp(-j 2 pi frac(r (2m + 32 - i))) over in-range samples;
-// in the interior it is c0 exp(-j 2 pi frac(2 r m)).  The 16 outputs at each
-// edge take the direct sum: inline where the caller has registers to spare,
-// out of line (kk_carrier_edge) where it has not.
+// T[m] = sum_i h[i] exp(-j 2 pi frac(r (g0 + 2m + 32 - i))) over in-range samples
+// (g0: stream index of the input's first sample, 0 for an independent buffer);
+// in the interior it is c0 exp(-j 2 pi frac(r (g0 + 2m))).  The 16 outputs at
+// each edge take the direct sum: inline where the caller has registers to
+// spare, out of line (kk_carrier_edge) where it has not.
 __device__ __forceinline__ float2 kk_carrier_edge_inl(const float *__restrict__ mf, double r, int64_t m,
-                                                      int64_t n) {
+                                                      int64_t n, int64_t g0) {
   float2 tc = make_float2(0.0f, 0.0f);
 #pragma unroll 1
   for (int i = 0; i < 65; i++) {
     const int64_t t = 2 * m + 32 - i;
-    if (t >= 0 && t < n) tc = cadd(tc, cscale(cis_rev(-downshift_rev(r, t)), mf[i]));
+    if (t >= 0 && t < n) tc = cadd(tc, cscale(cis_rev(-downshift_rev(r, g0 + t)), mf[i]));
   }
   return tc;
 }
-__device__ __noinline__ float2 kk_carrier_edge(const float *__restrict__ mf, double r, int64_t m, int64_t n) {
-  return kk_carrier_edge_inl(mf, r, m, n);
+__device__ __noinline__ float2 kk_carrier_edge(const float *__restrict__ mf, double r, int64_t m, int64_t n,
+                                               int64_t g0) {
+  return kk_carrier_edge_inl(mf, r, m, n, g0);
 }
 __device__ __forceinline__ bool kk_interior(int64_t m, int64_t n) { return m >= 16 && 2 * m + 32 < n; }
 template <bool INL = false>
-__device__ __forceinline__ float2 kk_carrier_term(const RxJob &J, int64_t m, int64_t n) {
-  if (kk_interior(m, n)) return cmul(J.c0, cis_rev(-downshift_rev(J.r, 2 * m)));
-  return INL ? kk_carrier_edge_inl(J.mf, J.r, m, n) : kk_carrier_edge(J.mf, J.r, m, n);
+__device__ __forceinline__ float2 kk_carrier_term(const RxJob &J, int64_t m, int64_t n, int64_t g0) {
+  if (kk_interior(m, n)) return cmul(J.c0, cis_rev(-downshift_rev(J.r, g0 + 2 * m)));
+  return INL ? kk_carrier_edge_inl(J.mf, J.r, m, n, g0) : kk_carrier_edge(J.mf, J.r, m, n, g0);
 }
 
 // KK: AGC'd carrier-free 2-sps sample u[m] = g (Z[m] - mean T[m]) (zero outside).
 template <bool INL = false, class ZP>
-__device__ __forceinline__ float2 kk_sample(const RxJob &J, ZP z, int64_t m, int64_t n, float2 mean, float g) {
+__device__ __forceinline__ float2 kk_sample(const RxJob &J, ZP z, int64_t m, int64_t n, float2 mean, float g,
+                                            int64_t g0) {
   if (m < 0 || m >= n / 2) return make_float2(0.0f, 0.0f);
-  return cscale(csub(z[m], cmul(mean, kk_carrier_term<INL>(J, m, n))), g);
+  return cscale(csub(z[m], cmul(mean, kk_carrier_term<INL>(J, m, n, g0))), g);
 }

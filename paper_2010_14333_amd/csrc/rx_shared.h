@@ -23,6 +23,8 @@ struct RxScalars {
   unsigned int done_wg, pad2;   // decision workgroups of the current buffer that have finished
   unsigned long long lat_count; // buffers whose latency has been recorded
   unsigned int lat[RX_LAT_RING];   // latency (ticks) of recorded buffer i at index i % RX_LAT_RING
+  double theta_carry;           // stream: KK carrier phase of the last emitted DD-LMS block
+  double acc_carry;             // stream: PAM unwrapped timing angle of the last emitted timing block
 };
 
 // Everything a kernel needs about one handle (device memory, written once).
@@ -35,6 +37,9 @@ struct RxJob {
   float sgn;                        // Hilbert sign (+1: signal above the carrier)
   int32_t debug;                    // keep derotated soft symbols
   int32_t ref_ext;                  // known symbols from the caller's reference stream (refw), not the seed
+  int32_t stream;                   // contiguous stream: decisions held back by `hold` samples
+  int32_t hold, look;               // stream: hold-back and look-back (samples) of the prepended tail
+  uint64_t ref_period;              // the reference sequence repeats every ref_period symbols (0: never)
   uint64_t seed;
   float2 c0;                        // interior value of MF(exp(-j 2 pi r n)) / exp(-j 2 pi r 2m)
   const float *mf;                  // matched filter taps (65 centred for KK, 33 for PAM)
@@ -61,14 +66,43 @@ struct RxJob {
 };
 
 // By-value launch description of one batch (kernel argument, < 4 KiB).
+// s0[i] >= 0 marks a stream buffer after the first: its input is the stream's
+// previous `hold + look` samples followed by the new buffer, and s0 is the
+// stream index of its first sample; -1 for an independent buffer or the
+// first buffer of a stream.
 struct RxLaunch {
   const RxJob *job[RX_MAXB];
   const uint8_t *in[RX_MAXB];
   uint8_t *bits[RX_MAXB];
   int64_t n[RX_MAXB];
+  int64_t s0[RX_MAXB];
   int32_t count;
   int32_t pad;
 };
+
+// Hold-back (decisions of the last `hold` samples of a stream buffer wait for
+// the next buffer) and look-back (samples before the first emitted one that
+// the chain needs) of the contiguous-stream mode, per chain: the KK chain's
+// Hilbert and matched-filter reach, FFE span and delay, DD-LMS block and
+// carrier-phase window fit in 4096 samples either way; the PAM chain's
+// timing-detector averaging window (16 blocks of 512) sets 12288.
+#define RX_KK_HOLD 4096
+#define RX_PAM_HOLD 12288
+// Symbol ranges of a launch entry, in symbols of its processed input.
+struct RxSpan {
+  int64_t k_lo, k_hi;   // emitted symbols [k_lo, k_hi) (output bit 0 = symbol k_lo)
+  int64_t g0;           // stream index of the input's first sample (0 unless continuing a stream)
+  int64_t kg0;          // stream symbol index of the input's first symbol
+};
+__host__ __device__ inline RxSpan rx_span(const RxJob &J, int64_t n, int64_t s0) {
+  const int sps = J.kk ? 4 : 2;
+  RxSpan sp;
+  sp.g0 = s0 > 0 ? s0 : 0;
+  sp.kg0 = sp.g0 / sps;
+  sp.k_lo = (J.stream && s0 >= 0) ? J.look / sps : 0;
+  sp.k_hi = J.stream ? (n - J.hold) / sps : n / sps;
+  return sp;
+}
 
 // KK overlap-save geometry: a frame of N samples starts RX_KK_EDGE samples
 // before its hop, the Hilbert FIR reaches 2048 samples either side and the
@@ -81,6 +115,14 @@ static inline int rx_kk_hop(int log2n) {
   return h & ~15;
 }
 
+// Launch shapes picked per (GPU, chain, precision, FFE length) by the
+// library's tuner: overlap-save FFT size, DD-LMS chunk steps, precision-form
+// FFE groups per wavefront, decision symbols per workgroup.  Every choice
+// computes the same result (the FFT size up to rounding).
+struct RxTune {
+  int32_t fft_log2, blocks_bc, ffe_gpw, dec_syms;
+};
+
 // Kernel stages (host-side launchers are defined with their kernels).
 enum RxStage {
   ST_KK_FRONT = 0, ST_KK_DEBUG, ST_PAM_SUM, ST_PAM_MF, ST_PAM_GAVG, ST_PAM_UNWRAP, ST_PAM_FARROW,
@@ -88,9 +130,11 @@ enum RxStage {
 };
 void rx_launch_kk_stage(int stage, const RxLaunch &L, int64_t maxn, int log2n, int prec, hipStream_t s);
 void rx_launch_pam_stage(int stage, const RxLaunch &L, int64_t maxn, hipStream_t s);
-void rx_launch_eq_stage(int stage, const RxLaunch &L, int64_t maxn, int kk, int ffe_taps, int prec, hipStream_t s);
+void rx_launch_eq_stage(int stage, const RxLaunch &L, int64_t maxn, int kk, int ffe_taps, int prec, const RxTune &t,
+                        hipStream_t s);
 void rx_launch_mlp_stage(int stage, const RxLaunch &L, int64_t maxn, hipStream_t s);
-void rx_launch_ref_fill(uint32_t *w, int64_t words, uint64_t seed, int bps, int64_t nsym, hipStream_t s);
+void rx_launch_ref_fill(uint32_t *w, int64_t words, uint64_t seed, int bps, int64_t nsym, uint64_t period,
+                        hipStream_t s);
 void rx_mlp_windows(const RxLaunch &L, float *X, float *T, int64_t row0, hipStream_t s);
 int rx_mlp_params(void);
 void rx_mlp_step(const float *X, const float *T, int64_t ntrain, int64_t i0, int batch, int64_t mult, float *p,
