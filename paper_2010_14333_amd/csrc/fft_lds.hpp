@@ -125,17 +125,21 @@ template <int N, int R, int NS, bool TAIL = true, class Out = LdsOut>
 __device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *__restrict__ tw, Out out) {
   constexpr int T = N / 16;
   constexpr int NB = (N / R) / T;  // butterflies per thread
-  // twiddle table reads first: their latency overlaps the LDS reads and the barrier
+  // twiddle table reads first: their latency overlaps the LDS reads and the
+  // barrier.  They go through a global-memory view: as flat accesses they
+  // would also count against the LDS wait counter, and the wait for this
+  // pass's LDS reads would wait for them too.
   float2 tw1[NB], tw2[NB], tw4[NB], tw8[NB];
   if constexpr (NS > 1) {
+    const GView2 tg = gview(tw);
 #pragma unroll
     for (int b = 0; b < NB; b++) {
       const int j = threadIdx.x + b * T;
       const int step = (j & (NS - 1)) * (N / (NS * R));
-      tw1[b] = tw[step];
-      tw2[b] = R > 2 ? tw[2 * step] : tw1[b];
-      tw4[b] = R > 4 ? tw[4 * step] : tw1[b];
-      tw8[b] = R > 8 ? tw[8 * step] : tw1[b];
+      tw1[b] = tg[step];
+      tw2[b] = R > 2 ? tg[2 * step] : tw1[b];
+      tw4[b] = R > 4 ? tg[4 * step] : tw1[b];
+      tw8[b] = R > 8 ? tg[8 * step] : tw1[b];
     }
   }
   out.begin();

@@ -35,7 +35,7 @@ template <int T> struct HilbertOut {
   float hs[16];
   __device__ __forceinline__ void begin() {
 #pragma unroll
-    for (int i = 0; i < 16; i++) hs[i] = hspec[threadIdx.x + i * T];
+    for (int i = 0; i < 16; i++) hs[i] = gptr(hspec)[threadIdx.x + i * T];
   }
   __device__ __forceinline__ void operator()(int koff, int, float2 z) const {
     const int i = koff / T;
@@ -68,63 +68,83 @@ __device__ __forceinline__ float2 uniform2(float2 v) {
                      __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v.y))));
 }
 
-// LDS layout of the downshifted field y' for the matched filter.
-//  PREC 0: two planes of floats, re at [0, YPL) and im at [YPL, 2 YPL), no
-//    padding: a lane reads 24 consecutive window samples of one component
-//    as six 16-byte reads.
+// LDS layout of the downshifted field y' for the matched filter: planes of
+// 16-bit elements with 8 elements of padding per 32 samples, so that the A
+// operand of one MFMA step (8 consecutive samples of one component) is a
+// single aligned 16-byte read, and the eight tiles and two planes one
+// instruction reads (tile stride 20 dwords, plane offset 16 mod 64 dwords)
+// fall on distinct banks.
+//  PREC 0: four planes, re and im of hi = fp16(y') at 0 and PS, re and im of
+//    lo = fp16(y' - hi) at 2 PS and 3 PS (the lo pair 32 mod 64 dwords on).
 //  PREC 1, 2: two planes of the narrow type (re, then im PS elements on),
-//    each sample rounded once when it is written, with 8 elements of padding
-//    per 32 samples: the A operand of one MFMA step (8 consecutive samples of
-//    one component) is a single aligned 16-byte read, and the eight tiles and
-//    two planes one instruction reads (tile stride 20 dwords, plane offset
-//    16 mod 64 dwords) fall on distinct banks.
+//    each sample rounded once when it is written.
 __host__ __device__ constexpr int nidx(int q) { return q + ((q >> 5) << 3); }
 
 // Matched-filter B operand (the tap matrix) and one wavefront pass of eight
-// 16-output tiles.  Lane l holds column q = l % 16 and K-row group l / 16.
+// 16-output tiles on v_mfma_f32_16x16x32_{f16,bf16}.  Lane l holds column
+// q = l % 16 and K-row group l / 16; B[t][q] = h[2 q + 64 - t] =
+// htab[2 q + 95 - t] (taps h[i] at index i + 31 of a zero-padded copy in
+// LDS), t = 32 ks + 8 kq + j; A[row][t] = plane[32 tile + t].
 template <int PREC> struct MfB;
+// The plain form keeps FP32 accuracy on the FP16 matrix pipe: each operand
+// is carried as hi + lo, two FP16 values holding 22 significant bits (the
+// lo part is exact: v - hi needs no rounding in FP32), and the product is
+// taken as a_lo b_hi + a_hi b_lo + a_hi b_hi.  Every FP16 product is exact
+// in the FP32 accumulator; the dropped a_lo b_lo is below 2^-22 of the
+// term, and the split itself leaves at most 2^-22 of each operand behind,
+// a few times the FP32 rounding of the sums and far below the field's own
+// FP32 error.  Nine 16-cycle instructions replace the 24 32-cycle FP32
+// 16x16x4 steps of the same tile pass.
 template <> struct MfB<0> {
-  // v_mfma_f32_16x16x4_f32: lane l supplies A[l % 16][l / 16], B[l / 16][l % 16].
-  // The GEMM's K index is taken as k = 24 kq + ks (step ks, lane group kq), so
-  // lane group kq covers window samples 24 kq .. 24 kq + 23 in order.
-  // B[k][q] = h[2 q + 64 - k] = htab[2 q + 95 - k] from a zero-padded copy of
-  // the taps in LDS (h[i] at index i + 31).
-  const float *hb;
-  __device__ void load(const float *__restrict__ htab, int row, int kq) { hb = htab + 2 * row + 95 - 24 * kq; }
-  // yp: this lane's component plane; A[row][k] = plane[32 tile + k]
-  __device__ rx_f32x4 apply(const float *__restrict__ yp, int tile, int kq) const {
-    const float4 *a4 = reinterpret_cast<const float4 *>(yp + 32 * tile + 24 * kq);   // 16-byte aligned
-    float av[24];
+  // the lane's B vectors sit in LDS (kept in registers they would not fit
+  // beside the frame-B phases): hi of step ks at bt[64 ks + lane], lo at
+  // bt[192 + 64 ks + lane]; filled once per workgroup by fill()
+  const rx_f16x8 *bt;
+  __device__ static void fill(rx_f16x8 *tab, const float *__restrict__ mf) {
+    if (threadIdx.x < 192) {
+      const int ks = threadIdx.x >> 6, lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
+      rx_f16x8 hv, lv;
 #pragma unroll
-    for (int h = 0; h < 6; h++) {
-      const float4 v = a4[h];
-      av[4 * h] = v.x;
-      av[4 * h + 1] = v.y;
-      av[4 * h + 2] = v.z;
-      av[4 * h + 3] = v.w;
+      for (int j = 0; j < 8; j++) {
+        const int i = 2 * row + 64 - (32 * ks + 8 * kq + j);
+        const float h = (i >= 0 && i <= 64) ? mf[i] : 0.0f;
+        const _Float16 hi = (_Float16)h;
+        hv[j] = hi;
+        lv[j] = (_Float16)(h - (float)hi);
+      }
+      tab[threadIdx.x] = hv;
+      tab[192 + threadIdx.x] = lv;
     }
+  }
+  __device__ void load(const rx_f16x8 *tab) { bt = tab + (threadIdx.x & 63); }
+  // yp: this lane's component plane of hi; its lo plane is `lo` elements on
+  __device__ rx_f32x4 apply(const _Float16 *__restrict__ yp, int lo, int tile, int kq) const {
     rx_f32x4 c0 = {0.0f, 0.0f, 0.0f, 0.0f}, c1 = c0;
 #pragma unroll
-    for (int ks = 0; ks < 24; ks += 2) {
-      c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks], hb[-ks], c0, 0, 0, 0);
-      c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks + 1], hb[-ks - 1], c1, 0, 0, 0);
+    for (int ks = 0; ks < 3; ks++) {
+      const int o = nidx(32 * (tile + ks) + 8 * kq);
+      const rx_f16x8 ah = *reinterpret_cast<const rx_f16x8 *>(yp + o);
+      const rx_f16x8 al = *reinterpret_cast<const rx_f16x8 *>(yp + lo + o);
+      const rx_f16x8 bh = bt[64 * ks], bl = bt[192 + 64 * ks];
+      c1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh, c1, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl, c1, 0, 0, 0);
+      c0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh, c0, 0, 0, 0);
     }
     return c0 + c1;
   }
 };
 template <int PREC> struct MfB {
-  // v_mfma_f32_16x16x32_{bf16,f16}: operands rounded once to the narrow type
+  // precision form: operands rounded once to the narrow type
   using NT = NarrowT<PREC>;
   typename NT::vec b[3];
-  // B[t][q] = h[2 q + 64 - t] = htab[2 q + 95 - t], t = 32 ks + 8 kq + j
   __device__ void load(const float *__restrict__ htab, int row, int kq) {
 #pragma unroll
     for (int ks = 0; ks < 3; ks++)
 #pragma unroll
       for (int j = 0; j < 8; j++) b[ks][j] = NT::cvt(htab[2 * row + 95 - (32 * ks + 8 * kq + j)]);
   }
-  // yp: this lane's component plane; A[row][k] = plane[32 tile + k]
-  __device__ rx_f32x4 apply(const typename NT::elem *__restrict__ yp, int tile, int kq) const {
+  // yp: this lane's component plane
+  __device__ rx_f32x4 apply(const typename NT::elem *__restrict__ yp, int, int tile, int kq) const {
     rx_f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int ks = 0; ks < 3; ks++)
@@ -133,7 +153,10 @@ template <int PREC> struct MfB {
   }
 };
 
-template <int LOGN, int PREC>
+// FIELD: the debug instantiation, which only writes the reconstructed field
+// E of the buffers that keep it (RX_DEBUG_KEEP) and does no filtering; the
+// production kernel never stores E, which keeps its registers free.
+template <int LOGN, int PREC, bool FIELD = false>
 __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  // 4 waves/SIMD: one 2^14 or two 2^13 workgroups per CU
   constexpr int N = 1 << LOGN, T = N / 16;
   constexpr int HOP = (N - RX_KK_HALFV - RX_KK_EDGE - RX_KK_CMF) & ~15;
@@ -141,21 +164,22 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
   constexpr int QPT = (QN + T - 1) / T;
   constexpr int NTILE = HOP / 32;          // 16-output matched-filter tiles per block
   constexpr int NG = (NTILE + 7) / 8;      // eight tiles per wavefront pass
-  constexpr int YPL = 32 * (8 * NG) + 64;  // y' plane length (PREC 0): every window a pass reads
-  static_assert(2 * YPL <= 2 * (N + N / 16) && QN <= YPL && YPL % 4 == 0, "y' planes fit the LDS buffer");
+  constexpr int YPL = 32 * (8 * NG) + 64;  // y' samples every window of a pass reads
+  static_assert(QN <= YPL && YPL % 4 == 0, "every y' sample inside the planes");
   static_assert((N / 8) % T == 0, "whole 8-sample groups per thread");
-  // narrow forms: plane stride PS (elements, 32 mod 128) and, behind the two
-  // planes, this thread's frame-B phases parked in LDS between the frames
+  // plane stride PS (16-bit elements, 32 mod 128); behind the narrow forms'
+  // two planes, this thread's frame-B phases parked in LDS between the frames
   constexpr int PS = (YPL + 8 * ((YPL - 1) >> 5) - 32 + 127) / 128 * 128 + 32;
   static_assert(PS >= nidx(YPL - 1) + 1 && (PS + QN) * 4 <= 8 * (N + N / 16), "narrow planes and phase stash fit");
+  static_assert(4 * PS * 2 <= 8 * (N + N / 16), "the plain form's four planes fit");
   constexpr float INV2PI = 0.15915494309189535f;
   __shared__ float2 lds[N + N / 16];
-  float *const ypl = reinterpret_cast<float *>(lds);   // y' planes of the FP32 filter
-  using ElemT = typename std::conditional<PREC == 0, float, typename NarrowT<PREC == 0 ? 1 : PREC>::elem>::type;
-  ElemT *const npl = reinterpret_cast<ElemT *>(lds);
+  using ElemT = typename std::conditional<PREC == 0, _Float16, typename NarrowT<PREC == 0 ? 1 : PREC>::elem>::type;
+  ElemT *const npl = reinterpret_cast<ElemT *>(lds);   // y' planes
   float *const stash = reinterpret_cast<float *>(lds) + PS;
   __shared__ double red[9 * (T / 64)];
   __shared__ float htab[128];   // matched-filter taps h[i] at i + 31, zero elsewhere
+  __shared__ rx_f16x8 btab[PREC == 0 ? 384 : 1];   // the plain form's split tap operands
 
   const int jb = blockIdx.y;
   const RxJob J = *L.job[jb];
@@ -164,11 +188,13 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
   const int64_t g0 = L.s0[jb] > 0 ? L.s0[jb] : 0;   // stream index of sample 0 (downshift phase)
   const int64_t nrb = (n + HOP - 1) / HOP;
   const int64_t blk[2] = {2 * (int64_t)blockIdx.x, 2 * (int64_t)blockIdx.x + 1};
-  if (blk[0] >= nrb) return;
+  if (blk[0] >= nrb || (FIELD && !J.field)) return;
   const int64_t F[2] = {blk[0] * HOP - RX_KK_EDGE, blk[1] * HOP - RX_KK_EDGE};
-  if (blockIdx.x == 0 && threadIdx.x == 0) J.sc->t_start = (unsigned long long)wall_clock64();   // buffer start
+  if (!FIELD && blockIdx.x == 0 && threadIdx.x == 0) J.sc->t_start = (unsigned long long)wall_clock64();   // buffer start
 
-  if (threadIdx.x < 128) {
+  if constexpr (PREC == 0) {
+    MfB<0>::fill(btab, J.mf);
+  } else if (threadIdx.x < 128) {
     const int i = (int)threadIdx.x - 31;
     htab[threadIdx.x] = (i >= 0 && i <= 64) ? J.mf[i] : 0.0f;
   }
@@ -299,58 +325,71 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
     const uint8_t *cb = in + 3 * ((nq0 - e) / 2);
     const int qlo = (int)clamp64(-nq0, 0, QN), qhi = (int)clamp64(n - nq0, 0, QN);   // t in [0, n)
     float2 dph = cis_rev(-downshift_rev(J.r, g0 + nq0 + threadIdx.x));
-    // all of this thread's code reads first (index clamped into the buffer),
-    // so their latencies overlap
-    int craw[QPT];
-    if (qhi > qlo) {
+    float2 *const fbase = J.field + nq0;   // FIELD only
+    // the thread's code reads are issued a batch at a time (index clamped
+    // into the buffer), so their latencies overlap; the plain form, whose
+    // split planes take more registers, issues its 12 in three batches
+    constexpr int QB = PREC == 0 ? (QPT + 2) / 3 : QPT;
 #pragma unroll
-      for (int i = 0; i < QPT; i++) {
-        const int q = threadIdx.x + i * T;
-        const int qc = q < qlo ? qlo : (q >= qhi ? qhi - 1 : q);
-        const int o = 3 * (qc + e);
-        craw[i] = (int)cb[o >> 1] | ((int)cb[(o >> 1) + 1] << 8);
+    for (int i0 = 0; i0 < QPT; i0 += QB) {
+      int craw[QB];
+      if (qhi > qlo) {
+#pragma unroll
+        for (int u = 0; u < QB && i0 + u < QPT; u++) {
+          const int q = threadIdx.x + (i0 + u) * T;
+          const int qc = q < qlo ? qlo : (q >= qhi ? qhi - 1 : q);
+          const int o = 3 * (qc + e);
+          craw[u] = (int)cb[o >> 1] | ((int)cb[(o >> 1) + 1] << 8);
+        }
       }
-    }
 #pragma unroll
-    for (int i = 0; i < QPT; i++) {
-      const int q = threadIdx.x + i * T;
-      if (q < QN) {
-        float2 yv = make_float2(0.0f, 0.0f);
-        if (q >= qlo && q < qhi) {
-          const int c = (craw[i] >> (((q + e) & 1) << 2)) & 0xFFF;
-          float phv;
-          if constexpr (PREC == 0) phv = ph[x][i];
-          else phv = x == 0 ? ph[0][i] : stash[q];
-          // sqrt(v): v in [0.5, 4095.5], so the hardware square root (1 ulp)
-          // needs none of the denormal or rounding fix-ups of sqrtf
-          const float2 ev = cscale(cis_rev(phv), __builtin_amdgcn_sqrtf((float)c + 0.5f));
-          yv = cmul(ev, dph);
-          if (q >= RX_KK_CMF && q < RX_KK_CMF + HOP) {
-            se_re += ev.x;
-            se_im += ev.y;
-            if (J.field) J.field[nq0 + q] = ev;
+      for (int u = 0; u < QB && i0 + u < QPT; u++) {
+        const int i = i0 + u;
+        const int q = threadIdx.x + i * T;
+        if (q < QN) {
+          float2 yv = make_float2(0.0f, 0.0f);
+          if (q >= qlo && q < qhi) {
+            const int c = (craw[u] >> (((q + e) & 1) << 2)) & 0xFFF;
+            float phv;
+            if constexpr (PREC == 0) phv = ph[x][i];
+            else phv = x == 0 ? ph[0][i] : stash[q];
+            // sqrt(v): v in [0.5, 4095.5], so the hardware square root (1 ulp)
+            // needs none of the denormal or rounding fix-ups of sqrtf
+            const float2 ev = cscale(cis_rev(phv), __builtin_amdgcn_sqrtf((float)c + 0.5f));
+            yv = cmul(ev, dph);
+            if (q >= RX_KK_CMF && q < RX_KK_CMF + HOP) {
+              se_re += ev.x;
+              se_im += ev.y;
+              if constexpr (FIELD) gstore(fbase, q, ev);
+            }
+          }
+          if constexpr (FIELD) {
+          } else if constexpr (PREC == 0) {
+            const _Float16 rh = (_Float16)yv.x, ih = (_Float16)yv.y;
+            npl[nidx(q)] = rh;
+            npl[PS + nidx(q)] = ih;
+            npl[2 * PS + nidx(q)] = (_Float16)(yv.x - (float)rh);
+            npl[3 * PS + nidx(q)] = (_Float16)(yv.y - (float)ih);
+          } else {
+            npl[nidx(q)] = NarrowT<PREC == 0 ? 1 : PREC>::cvt(yv.x);
+            npl[PS + nidx(q)] = NarrowT<PREC == 0 ? 1 : PREC>::cvt(yv.y);
           }
         }
-        if constexpr (PREC == 0) {
-          ypl[q] = yv.x;
-          ypl[YPL + q] = yv.y;
-        } else {
-          npl[nidx(q)] = NarrowT<PREC == 0 ? 1 : PREC>::cvt(yv.x);
-          npl[PS + nidx(q)] = NarrowT<PREC == 0 ? 1 : PREC>::cvt(yv.y);
-        }
+        dph = cmul(dph, drot);
       }
-      dph = cmul(dph, drot);
     }
+    if constexpr (FIELD) continue;
     __syncthreads();
     // 4. decimating matched filter Z[m] = sum_i h[i] y'[2m + 32 - i] as a
     //    Toeplitz GEMM on MFMA: a row of A is one real component (re or im)
     //    of the 96-sample window of a tile of 16 outputs, B[t][q] =
-    //    h[2q + 64 - t]; eight tiles (16 rows) per wavefront pass.  PREC 0
-    //    takes FP32 operands (16x16x4 steps), the precision form narrow ones
-    //    (16x16x32 steps), both with FP32 accumulation.
+    //    h[2q + 64 - t]; eight tiles (16 rows) per wavefront pass, 16x16x32
+    //    steps with FP32 accumulation: PREC 0 on split (hi + lo) FP16
+    //    operands, the precision form on operands rounded to the narrow type.
     const int64_t m0 = blk[x] * (HOP / 2);
     MfB<PREC> bmf;
-    bmf.load(htab, row, kq);
+    if constexpr (PREC == 0) bmf.load(btab);
+    else bmf.load(htab, row, kq);
     // P at this lane's first output of the block, exact from the FP64 phase
     const int64_t mfirst = m0 + 16 * (8 * wv + 2 * kq) + row;
     float2 pp = cis_rev(downshift_rev(J.r, g0 + 2 * mfirst));
@@ -364,8 +403,7 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
     for (int grp = wv; grp < NG; grp += NW) {
       const int tile = grp * 8 + (row >> 1);
       rx_f32x4 acc;
-      if constexpr (PREC == 0) acc = bmf.apply(ypl + (row & 1) * YPL, tile, kq);
-      else acc = bmf.apply(npl + (row & 1) * PS, tile, kq);
+      acc = bmf.apply(npl + (row & 1) * PS, 2 * PS, tile, kq);
 #pragma unroll
       for (int jj = 0; jj < 2; jj++) {
         const int t2 = grp * 8 + 2 * kq + jj;
@@ -389,6 +427,7 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
     }
     __syncthreads();
   }
+  if constexpr (FIELD) return;
   double v[9] = {se_re, se_im, zz, tedge, (double)nint, sp.x, sp.y, sedge.x, sedge.y};
   block_sum_n<9>(v, red);
   if (threadIdx.x == 0) {
@@ -472,13 +511,13 @@ __global__ __launch_bounds__(1024) void kk_vv(RxLaunch L) {
   }
 }
 
-template <int LOGN, int PREC>
+template <int LOGN, int PREC, bool FIELD = false>
 static void launch_front(const RxLaunch &L, int64_t maxn, hipStream_t s) {
   constexpr int N = 1 << LOGN;
   const int hop = rx_kk_hop(LOGN);
   const int64_t nrb = (maxn + hop - 1) / hop;
   dim3 grid((unsigned)((nrb + 1) / 2), (unsigned)L.count);
-  hipLaunchKernelGGL((kk_front<LOGN, PREC>), grid, dim3(N / 16), 0, s, L);
+  hipLaunchKernelGGL((kk_front<LOGN, PREC, FIELD>), grid, dim3(N / 16), 0, s, L);
 }
 
 void rx_launch_kk_stage(int stage, const RxLaunch &L, int64_t maxn, int log2n, int prec, hipStream_t s) {
@@ -494,6 +533,9 @@ void rx_launch_kk_stage(int stage, const RxLaunch &L, int64_t maxn, int log2n, i
       else launch_front<14, 0>(L, maxn, s);
     }
   } else if (stage == ST_KK_DEBUG) {
+    // the field E (the same FP32 arithmetic in every form), then u
+    if (log2n == 13) launch_front<13, 0, true>(L, maxn, s);
+    else launch_front<14, 0, true>(L, maxn, s);
     const int64_t nd = maxn / 2;
     hipLaunchKernelGGL(kk_debug_u, dim3((unsigned)((nd + 255) / 256), cnt), dim3(256), 0, s, L);
   } else if (stage == ST_KK_VV) {
