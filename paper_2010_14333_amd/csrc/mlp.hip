@@ -203,58 +203,76 @@ __device__ __forceinline__ void mlp_load_frag(const float *__restrict__ P, int r
 // so max(bits, 0) is max(x, +0) in one integer instruction.
 __device__ __forceinline__ float relu_bits(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
 
-// One tile of 16 symbols; bx = this lane's B fragment of layer 1 (window
-// samples 8 kq .. 8 kq + 7 of symbol `row`).  Every lane returns the output
-// of symbol `row`.  Registers, LDS reads of the per-unit vectors and two
-// cross-lane shuffles only.
-__device__ __forceinline__ float mlp_tile(const MlpFrag &f, MNT::vec bx, int kq) {
+// NT tiles of 16 symbols at once (their dependent MFMA -> VALU chains
+// interleave, which one tile's chain alone leaves the SIMD idle waiting
+// on); bx[i] = this lane's B fragment of layer 1 for tile i (window samples
+// 8 kq .. 8 kq + 7 of symbol `row`).  Every lane returns in y[i] the output
+// of symbol `row` of tile i.  Registers, LDS reads of the per-unit vectors
+// and two cross-lane shuffles per tile only.
+template <int NT>
+__device__ __forceinline__ void mlp_tiles(const MlpFrag &f, const MNT::vec (&bx)[NT], int kq, float (&y)[NT]) {
   const float4 *cv4 = reinterpret_cast<const float4 *>(f.cv) + kq;   // units 16 t + 4 kq .. + 3
-  rx_f32x4 d1[4];
+  rx_f32x4 d1[NT][4];
 #pragma unroll
   for (int t = 0; t < 4; t++) {
     const float4 b = cv4[4 * t];
-    d1[t] = MNT::mfma(f.a1[t], bx, rx_f32x4{b.x, b.y, b.z, b.w});
+#pragma unroll
+    for (int i = 0; i < NT; i++) d1[i][t] = MNT::mfma(f.a1[t], bx[i], rx_f32x4{b.x, b.y, b.z, b.w});
   }
   // layer-1 activations: round pairs to BF16, then ReLU as a packed 16-bit
   // integer max with 0 (a BF16 with the sign bit set is a negative int16;
   // rounding and ReLU commute)
-  MNT::vec bh[2];
+  MNT::vec bh[NT][2];
 #pragma unroll
-  for (int ks = 0; ks < 2; ks++) {
-    typedef short s16x2 __attribute__((ext_vector_type(2)));
-    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  for (int i = 0; i < NT; i++)
 #pragma unroll
-    for (int jp = 0; jp < 4; jp++) {
-      const int t = 2 * ks + (2 * jp) / 4, j = (2 * jp) % 4;
-      typedef float f32x2 __attribute__((ext_vector_type(2)));
-      bf16x2 pr = __builtin_convertvector((f32x2){d1[t][j], d1[t][j + 1]}, bf16x2);
-      s16x2 bits = __builtin_bit_cast(s16x2, pr);
-      bits = __builtin_elementwise_max(bits, (s16x2){0, 0});
-      pr = __builtin_bit_cast(bf16x2, bits);
-      bh[ks][2 * jp] = pr[0];
-      bh[ks][2 * jp + 1] = pr[1];
+    for (int ks = 0; ks < 2; ks++) {
+      typedef short s16x2 __attribute__((ext_vector_type(2)));
+      typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+      for (int jp = 0; jp < 4; jp++) {
+        const int t = 2 * ks + (2 * jp) / 4, j = (2 * jp) % 4;
+        typedef float f32x2 __attribute__((ext_vector_type(2)));
+        bf16x2 pr = __builtin_convertvector((f32x2){d1[i][t][j], d1[i][t][j + 1]}, bf16x2);
+        s16x2 bits = __builtin_bit_cast(s16x2, pr);
+        bits = __builtin_elementwise_max(bits, (s16x2){0, 0});
+        pr = __builtin_bit_cast(bf16x2, bits);
+        bh[i][ks][2 * jp] = pr[0];
+        bh[i][ks][2 * jp + 1] = pr[1];
+      }
     }
-  }
-  float y = 0.0f;
+  // layer 2 and the output layer; each tile's output sum in four partials
+  // (one per 16-unit row tile), so the FMAs do not form one serial chain
+  float yp[NT][4];
 #pragma unroll
   for (int t = 0; t < 4; t++) {
     const float4 b = cv4[16 + 4 * t], w3 = cv4[32 + 4 * t];
-    rx_f32x4 d = MNT::mfma(f.a2[t][0], bh[0], rx_f32x4{b.x, b.y, b.z, b.w});
-    d = MNT::mfma(f.a2[t][1], bh[1], d);
-    y = fmaf(w3.x, relu_bits(d[0]), y);
-    y = fmaf(w3.y, relu_bits(d[1]), y);
-    y = fmaf(w3.z, relu_bits(d[2]), y);
-    y = fmaf(w3.w, relu_bits(d[3]), y);
+    rx_f32x4 d[NT];
+#pragma unroll
+    for (int i = 0; i < NT; i++) d[i] = MNT::mfma(f.a2[t][0], bh[i][0], rx_f32x4{b.x, b.y, b.z, b.w});
+#pragma unroll
+    for (int i = 0; i < NT; i++) d[i] = MNT::mfma(f.a2[t][1], bh[i][1], d[i]);
+#pragma unroll
+    for (int i = 0; i < NT; i++) {
+      float v = w3.x * relu_bits(d[i][0]);
+      v = fmaf(w3.y, relu_bits(d[i][1]), v);
+      v = fmaf(w3.z, relu_bits(d[i][2]), v);
+      yp[i][t] = fmaf(w3.w, relu_bits(d[i][3]), v);
+    }
   }
   // lanes l, l ^ 16, l ^ 32 and l ^ 48 hold the partial sums of one symbol:
   // exchanging 16-lane rows, then 32-lane halves, and adding adds them all
   // (the swaps move whole rows, so the sum does not depend on which rows of
   // the two operands the instruction exchanges; one VALU instruction each)
-  const auto r16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(y), __float_as_uint(y), false, false);
-  y = __uint_as_float(r16[0]) + __uint_as_float(r16[1]);
-  const auto r32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(y), __float_as_uint(y), false, false);
-  y = __uint_as_float(r32[0]) + __uint_as_float(r32[1]);
-  return y + f.b3;
+#pragma unroll
+  for (int i = 0; i < NT; i++) {
+    float v = (yp[i][0] + yp[i][1]) + (yp[i][2] + yp[i][3]);
+    const auto r16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = __uint_as_float(r16[0]) + __uint_as_float(r16[1]);
+    const auto r32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = __uint_as_float(r32[0]) + __uint_as_float(r32[1]);
+    y[i] = v + f.b3;
+  }
 }
 
 __global__ __launch_bounds__(256) void mlp_infer(RxLaunch L) {
@@ -296,16 +314,26 @@ __global__ __launch_bounds__(256) void mlp_infer(RxLaunch L) {
       }
     }
   };
-  float xn[8];
-  load_x(0, xn);
-  for (int tt = 0; tt < nt; tt++) {
-    MNT::vec bx;
+  // two tiles per step (the second past the wave's last tile is computed on
+  // in-buffer samples and not stored)
+  float xn[2][8];
+  load_x(0, xn[0]);
+  load_x(1, xn[1]);
+  for (int tt = 0; tt < nt; tt += 2) {
+    MNT::vec bx[2];
 #pragma unroll
-    for (int j = 0; j < 8; j++) bx[j] = MNT::cvt(8 * kq + j < MI ? xn[j] : 0.0f);   // column 31 is padding
-    load_x(tt + 1, xn);
-    const float y = mlp_tile(f, bx, kq);
-    const int64_t k = (tile0 + tt) * 16 + row;
-    if (kq == 0 && k < nsym) gptr(reinterpret_cast<float *>(J.soft))[k] = y;   // PAM: real soft symbols
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+      for (int j = 0; j < 8; j++) bx[i][j] = MNT::cvt(8 * kq + j < MI ? xn[i][j] : 0.0f);   // column 31 is padding
+    load_x(tt + 2, xn[0]);
+    load_x(tt + 3, xn[1]);
+    float y[2];
+    mlp_tiles<2>(f, bx, kq, y);
+#pragma unroll
+    for (int i = 0; i < 2; i++) {
+      const int64_t k = (tile0 + tt + i) * 16 + row;
+      if (kq == 0 && tt + i < nt && k < nsym) gptr(reinterpret_cast<float *>(J.soft))[k] = y[i];   // PAM: real soft symbols
+    }
   }
 }
 
@@ -321,11 +349,12 @@ __global__ __launch_bounds__(256) void mlp_infer_rows(const float *__restrict__ 
   for (int tt = 0; tt < TILES_PER_WAVE; tt++) {
     const int64_t r = (tile0 + tt) * 16 + row;
     if ((tile0 + tt) * 16 >= nrows) break;
-    MNT::vec bx;
+    MNT::vec bx[1];
 #pragma unroll
-    for (int j = 0; j < 8; j++) bx[j] = MNT::cvt((8 * kq + j < MI && r < nrows) ? X[r * 32 + 8 * kq + j] : 0.0f);
-    const float y = mlp_tile(f, bx, kq);
-    if (kq == 0 && r < nrows) Y[r] = y;
+    for (int j = 0; j < 8; j++) bx[0][j] = MNT::cvt((8 * kq + j < MI && r < nrows) ? X[r * 32 + 8 * kq + j] : 0.0f);
+    float y[1];
+    mlp_tiles<1>(f, bx, kq, y);
+    if (kq == 0 && r < nrows) Y[r] = y[0];
   }
 }
 
