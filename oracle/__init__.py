@@ -30,7 +30,7 @@ class Cfg(ctypes.Structure):
                 ("prefix", ctypes.c_int32), ("hilbert_taps", ctypes.c_int32),
                 ("os_log2", ctypes.c_int32), ("form", ctypes.c_int32),
                 ("rounding", ctypes.c_int32), ("equalizer", ctypes.c_int32),
-                ("pad0", ctypes.c_int32), ("rolloff", ctypes.c_double), ("mu", ctypes.c_double),
+                ("front", ctypes.c_int32), ("rolloff", ctypes.c_double), ("mu", ctypes.c_double),
                 ("mu_cma", ctypes.c_double), ("fc_over_fs", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("mlp", _dp), ("force", ctypes.POINTER(ctypes.c_int32)),
                 ("frozen", ctypes.POINTER(Out)), ("count_end", ctypes.c_int64)]
@@ -65,6 +65,8 @@ def lib():
         L.rxo_fir_same_dec2_cplx.argtypes = [_dp, ctypes.c_int64, _dp, ctypes.c_int32, _dp]
         L.rxo_hilbert_direct.argtypes = [_dp, ctypes.c_int64, _dp, ctypes.c_int32, _dp]
         L.rxo_hilbert_os.argtypes = [_dp, ctypes.c_int64, _dp, ctypes.c_int32, ctypes.c_int32, _dp]
+        L.rxo_hilbert_fd.argtypes = [_dp, ctypes.c_int64, _dp]
+        L.rxo_fd_eq_dec2.argtypes = [_dp, ctypes.c_int64, _dp, ctypes.c_int32, _dp]
         L.rxo_gardner.argtypes = [_dp, ctypes.c_int64, _dp]
         L.rxo_farrow.argtypes = [_dp, ctypes.c_int64, _dp, _dp]
         L.rxo_gardner_sums.argtypes = [_dp, ctypes.c_int64, _dp]
@@ -110,7 +112,7 @@ def default_cfg(fmt, seed, **kw) -> dict:
     kk = is_kk(fmt)
     d = dict(fmt=fmt, mf_taps=65 if kk else 33, ffe_taps=21 if kk else 15, prefix=4096,
              hilbert_taps=4097, os_log2=16, form=0, rounding=0, equalizer=0,
-             rolloff=0.1, mu=1e-3, mu_cma=1e-3, fc_over_fs=0.55e9 / 4e9 if kk else 0.0,
+             front=0, rolloff=0.1, mu=1e-3, mu_cma=1e-3, fc_over_fs=0.55e9 / 4e9 if kk else 0.0,
              seed=seed, mlp=None, force=None, frozen=None, count_end=0)
     d.update(kw)
     return d
@@ -269,6 +271,28 @@ def hilbert_os(l, h, log2n):
     y = np.zeros_like(l)
     lib().rxo_hilbert_os(_p(l), l.size, _p(h), h.size, log2n, _p(y))
     return y
+
+
+def hilbert_fd(l):
+    """The paper's block-circular Hilbert transform (1024-point blocks at hop 512)."""
+    l = _f64(l)
+    y = np.zeros_like(l)
+    lib().rxo_hilbert_fd(_p(l), l.size, _p(y))
+    return y
+
+
+def fd_eq_dec2(y, h):
+    """Frequency-domain static equaliser h and 512-point IFFT decimation to
+    half rate over 1024-point blocks at hop 512 (complex y -> complex y.size / 2)."""
+    y = np.ascontiguousarray(y, dtype=np.complex128)
+    h = _f64(h)
+    x = np.zeros(y.size // 2, dtype=np.complex128)
+    lib().rxo_fd_eq_dec2(y.view(np.float64).ctypes.data_as(_dp), y.size, _p(h), h.size,
+                         x.view(np.float64).ctypes.data_as(_dp))
+    return x
+
+
+FD_EQ_TAPS = 203
 
 
 def gardner(x):

@@ -219,6 +219,67 @@ void rxo_hilbert_os(const double *l, int64_t n, const double *h, int32_t ntaps, 
   free(buf);
 }
 
+/* The paper's frequency-domain forms (Sec. 2, first and second paragraphs:
+ * 1024-point transforms over blocks that advance by 512 samples, "100 %
+ * overlap", 8192 blocks per 2^22-sample buffer).  Block b covers samples
+ * 512 b - 256 .. 512 b + 767 and yields the 512 samples at its centre,
+ * 512 b .. 512 b + 511. */
+#define FD_N 1024
+#define FD_HOP 512
+#define FD_GUARD 256
+
+/* Hilbert transform by the block-circular -j sgn(k) on each block's
+ * 1024-point spectrum (sgn = 0 at DC and at N/2); samples before the buffer
+ * repeat its first one and samples after it its last one. */
+void rxo_hilbert_fd(const double *l, int64_t n, double *phi)
+{
+  cplx *buf = (cplx *)malloc(sizeof(cplx) * FD_N);
+  for (int64_t b = 0; b * FD_HOP < n; b++) {
+    const int64_t t0 = b * FD_HOP - FD_GUARD;
+    for (int t = 0; t < FD_N; t++) buf[t] = edge(l, n, t0 + t);
+    rxo_fft((double *)buf, FD_N, 0);
+    for (int k = 0; k < FD_N; k++) {
+      const double sg = (k == 0 || k == FD_N / 2) ? 0.0 : (k < FD_N / 2 ? 1.0 : -1.0);
+      buf[k] *= -I * sg;
+    }
+    rxo_fft((double *)buf, FD_N, 1);
+    for (int u = 0; u < FD_HOP && b * FD_HOP + u < n; u++) phi[b * FD_HOP + u] = creal(buf[FD_GUARD + u]) / FD_N;
+  }
+  free(buf);
+}
+
+/* Static equaliser and decimation to 2 samples per symbol in the frequency
+ * domain: each block's 1024-point spectrum (samples outside the buffer are
+ * zero) times the response of the ntaps-tap filter h (centred: tap i at
+ * offset i - (ntaps - 1) / 2, taken circularly), then the 512 bins of
+ * |f| < fs / 4 (k < 256 and k >= 768) through a 512-point inverse transform
+ * (scaled 1 / 1024), whose outputs are the filtered block at every second
+ * sample; the block's central 256 outputs are kept.  y, x: complex, n and
+ * n / 2 values. */
+void rxo_fd_eq_dec2(const double *yv, int64_t n, const double *h, int32_t ntaps, double *xv)
+{
+  const cplx *y = (const cplx *)yv;
+  cplx *x = (cplx *)xv;
+  cplx *buf = (cplx *)malloc(sizeof(cplx) * FD_N), *hf = (cplx *)calloc(FD_N, sizeof(cplx));
+  cplx *z = (cplx *)malloc(sizeof(cplx) * FD_N / 2);
+  const int32_t c = (ntaps - 1) / 2;
+  for (int32_t i = 0; i < ntaps; i++) hf[((i - c) % FD_N + FD_N) % FD_N] += h[i];
+  rxo_fft((double *)hf, FD_N, 0);
+  for (int64_t b = 0; b * FD_HOP < n; b++) {
+    const int64_t t0 = b * FD_HOP - FD_GUARD;
+    for (int t = 0; t < FD_N; t++) buf[t] = (t0 + t >= 0 && t0 + t < n) ? y[t0 + t] : 0.0;
+    rxo_fft((double *)buf, FD_N, 0);
+    for (int k = 0; k < FD_N / 2; k++) {
+      const int kk = k < FD_N / 4 ? k : k + FD_N / 2;
+      z[k] = buf[kk] * hf[kk];
+    }
+    rxo_fft((double *)z, FD_N / 2, 1);
+    for (int u = 0; u < FD_HOP / 2 && b * FD_HOP + 2 * u < n; u++)
+      x[b * (FD_HOP / 2) + u] = z[FD_GUARD / 2 + u] / FD_N;
+  }
+  free(buf); free(hf); free(z);
+}
+
 /* ------------------------------------------------------------------ */
 /* Rounding to the narrow operand formats of the precision form          */
 /* (round to nearest, ties to even).                                     */
@@ -605,6 +666,7 @@ int rxo_process(const rxo_cfg *cfg, const uint8_t *packed, int64_t n, rxo_out *o
   const rxo_out *fz = cfg->frozen;
   if (P + 2 * G >= nsym || K < 1 || K % 2 == 0 || cfg->mf_taps % 2 == 0) return -1;
   if (cfg->equalizer == 1 && (kk || !cfg->mlp)) return -1;
+  if (cfg->front == 1 && (!kk || rm || fz)) return -1;   /* the FD front end: KK, FP64, one buffer */
 
   int32_t *code = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
   rxo_unpack12(packed, n, code);
@@ -623,7 +685,8 @@ int rxo_process(const rxo_cfg *cfg, const uint8_t *packed, int64_t n, rxo_out *o
     for (int64_t t = 0; t < n; t++) ell[t] = 0.5 * log((double)code[t] + 0.5);
     double *hh = (double *)malloc(sizeof(double) * (size_t)cfg->hilbert_taps);
     rxo_hilbert_taps(cfg->hilbert_taps, hh);
-    rxo_hilbert_os(ell, n, hh, cfg->hilbert_taps, cfg->os_log2, phi);
+    if (cfg->front == 1) rxo_hilbert_fd(ell, n, phi);
+    else rxo_hilbert_os(ell, n, hh, cfg->hilbert_taps, cfg->os_log2, phi);
     const double sg = cfg->fc_over_fs >= 0 ? 1.0 : -1.0;
     cplx *e = (cplx *)malloc(sizeof(cplx) * (size_t)n);
     cplx mean = 0.0;
@@ -646,7 +709,16 @@ int rxo_process(const rxo_cfg *cfg, const uint8_t *packed, int64_t n, rxo_out *o
       for (int64_t t = 0; t < n; t++) y[t] = rndc(rm, y[t]);
       for (int i = 0; i < cfg->mf_taps; i++) hm[i] = rnd(rm, hm[i]);
     }
-    rxo_fir_same_dec2_cplx((double *)y, n, hm, cfg->mf_taps, (double *)x);
+    if (cfg->front == 1) {
+      /* the paper's static equaliser: 203 taps on the 1024-point blocks,
+       * here the matched RRC of the same roll-off (its link-specific part
+       * is the identity for a back-to-back link) */
+      double heq[RXO_FD_EQ_TAPS];
+      rxo_rrc_taps(RXO_FD_EQ_TAPS, (double)sps, cfg->rolloff, heq);
+      rxo_fd_eq_dec2((double *)y, n, heq, RXO_FD_EQ_TAPS, (double *)x);
+    } else {
+      rxo_fir_same_dec2_cplx((double *)y, n, hm, cfg->mf_taps, (double *)x);
+    }
     nx = nd;
     o->mean_re = creal(mean);
     o->mean_im = cimag(mean);

@@ -29,7 +29,10 @@ typedef struct {
   int32_t form;          /* 0: block-parallel DD-LMS FFE; 1: FFE frozen at the prefix taps */
   int32_t rounding;      /* 0: none; 1: BF16; 2: FP16 operands (MF + FFE, or the MLP) */
   int32_t equalizer;     /* 0: LMS FFE; 1: MLP (PAM only) */
-  int32_t pad0;
+  int32_t front;         /* KK front end: 0, a finite Hilbert FIR by overlap-save and the matched
+                            FIR; 1, the paper's frequency-domain form (rxo_hilbert_fd,
+                            rxo_fd_eq_dec2: 1024-point blocks at hop 512, block-circular
+                            Hilbert, 203-tap static equaliser, 512-point IFFT to 2 sps) */
   double rolloff, mu, mu_cma, fc_over_fs;
   uint64_t seed;         /* reference sequence: bits of symbol k = top bits of SplitMix64(seed, k) */
   const double *mlp;     /* RXO_MLP_PARAMS packed parameters when equalizer == 1 */
@@ -60,6 +63,7 @@ typedef struct rxo_out_s {
   int64_t nsym, nbits, counted_syms, sym_errors, counted_bits, bit_errors;
 } rxo_out;
 
+#define RXO_FD_EQ_TAPS 203   /* the paper's KK static equaliser length */
 #define RXO_MLP_IN 31
 #define RXO_MLP_H 64
 #define RXO_MLP_PARAMS (RXO_MLP_H * RXO_MLP_IN + RXO_MLP_H + RXO_MLP_H * RXO_MLP_H + RXO_MLP_H + RXO_MLP_H + 1)
@@ -76,6 +80,8 @@ void rxo_fir_same(const double *x, int64_t n, const double *h, int32_t k, double
 void rxo_fir_same_dec2_cplx(const double *x, int64_t n, const double *h, int32_t k, double *y);
 void rxo_hilbert_direct(const double *l, int64_t n, const double *h, int32_t ntaps, double *phi);
 void rxo_hilbert_os(const double *l, int64_t n, const double *h, int32_t ntaps, int32_t log2n, double *phi);
+void rxo_hilbert_fd(const double *l, int64_t n, double *phi);
+void rxo_fd_eq_dec2(const double *y, int64_t n, const double *h, int32_t ntaps, double *x);
 void rxo_gardner_sums(const double *x, int64_t n, double *c);
 void rxo_gardner(const double *x, int64_t n, double *delta);
 void rxo_farrow(const double *x, int64_t n, const double *delta, double *xr);

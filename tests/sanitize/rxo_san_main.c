@@ -6,7 +6,8 @@
  * documents, so a write past a documented size is an ASan report.  The run
  * covers one buffer through the full chain, the stream-continuation form
  * (the acquisition frozen from the first pass, a shortened counting window,
- * forced decisions) and the exported building blocks with odd sizes.
+ * forced decisions), the KK frequency-domain front end and the exported
+ * building blocks with odd sizes.
  *
  * Input file: int32 fmt, rounding, form, equalizer; int64 n; uint64 seed;
  * then, when equalizer == 1, RXO_MLP_PARAMS doubles; then n*3/2 packed bytes.
@@ -111,6 +112,20 @@ int main(int argc, char **argv) {
   cfg.count_end = nsym - 1000;
   if (rxo_process(&cfg, packed, n, &o2) != 0) { fprintf(stderr, "rejected (stream form)\n"); return 3; }
 
+  /* KK: the frequency-domain front end (plain arithmetic only) */
+  if (kk && cfg.rounding == 0) {
+    rxo_out o3;
+    memset(&o3, 0, sizeof o3);
+    o3.bits = take(nbytes);
+    o3.mf = take(sizeof(double) * 2 * (size_t)(n / 2));
+    cfg.front = 1;
+    cfg.frozen = NULL;
+    cfg.force = NULL;
+    cfg.count_end = 0;
+    if (rxo_process(&cfg, packed, n, &o3) != 0) { fprintf(stderr, "rejected (FD front end)\n"); return 3; }
+    free(o3.bits); free(o3.mf);
+  }
+
   /* building blocks at odd sizes */
   {
     double h[7], t[2 * 37], y[2 * 37];
@@ -127,6 +142,10 @@ int main(int argc, char **argv) {
     for (int i = 0; i < 1000; i++) l[i] = 0.001 * (double)((i * 37) % 101);
     rxo_hilbert_direct(l, 1000, hh, 65, phi);
     rxo_hilbert_os(l, 1000, hh, 65, 8, phi);
+    rxo_hilbert_fd(l, 1000, phi);
+    double yc[2 * 1000], xc[1000];
+    for (int i = 0; i < 2000; i++) yc[i] = 0.01 * (double)((i * 17) % 23);
+    rxo_fd_eq_dec2(yc, 1000, hh, 65, xc);
     double x[1536], d[3], xr[1536], c[6];
     for (int i = 0; i < 1536; i++) x[i] = (double)((i * 13) % 7) - 3.0;
     rxo_gardner_sums(x, 1536, c);
