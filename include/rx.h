@@ -52,6 +52,18 @@ typedef struct rx_ctx *rx_handle;
 typedef enum { RX_PAM2 = 1, RX_PAM4 = 2, RX_PAM8 = 3, RX_KK_QPSK = 4, RX_KK_16QAM = 5 } rx_format;
 typedef enum { RX_FP32 = 0, RX_BF16 = 1, RX_FP16 = 2 } rx_precision;
 typedef enum { RX_EQ_LMS = 0, RX_EQ_MLP = 1 } rx_equalizer;
+/* KK front end.  RX_FRONT_OS: a finite 4097-tap Hilbert FIR applied by
+ * overlap-save FFTs and the 65-tap matched filter on MFMA.  RX_FRONT_FD: the
+ * paper's own frequency-domain form (Sec. 2, second paragraph, with the first
+ * paragraph's 1024-point "100 % overlap" blocks): 1024-point blocks advancing
+ * by 512 samples, the Hilbert transform as -j sgn(k) on each block's
+ * spectrum, field and FP64-phase downshift with the carrier mean removed,
+ * the 203-tap static equaliser on the 1024-point spectrum (the matched RRC:
+ * the paper's taps are unpublished and their link-specific part is the
+ * identity back to back), the 512 bins of |f| < fs/4 through a 512-point
+ * inverse transform to 2 samples per symbol.  FP32, independent buffers
+ * only; mf_taps, hilbert_taps and fft_log2 do not apply to it. */
+typedef enum { RX_FRONT_OS = 0, RX_FRONT_FD = 1 } rx_front;
 
 enum {
   RX_OK = 0,
@@ -129,7 +141,9 @@ typedef struct {
   int32_t ffe_gpw;          /* precision-form FFE: 256-symbol groups per wavefront: 4, 8 or 16;
                                0 = tuned */
   int32_t dec_syms;         /* decision stage: symbols per workgroup: 1024, 2048 or 4096; 0 = tuned */
-  int32_t reserved2;
+  int32_t front;            /* rx_front (KK): RX_FRONT_OS (default) or RX_FRONT_FD; RX_FRONT_FD
+                               with a PAM format, a precision form or RX_STREAM:
+                               RX_E_UNSUPPORTED */
 } rx_params;
 
 /* Cumulative counters since create / rx_errors_reset.  Symbols counted are

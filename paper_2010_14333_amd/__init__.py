@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "librx.so")
 RX_PAM2, RX_PAM4, RX_PAM8, RX_KK_QPSK, RX_KK_16QAM = 1, 2, 3, 4, 5
 RX_FP32, RX_BF16, RX_FP16 = 0, 1, 2
 RX_EQ_LMS, RX_EQ_MLP = 0, 1
+RX_FRONT_OS, RX_FRONT_FD = 0, 1
 RX_OK, RX_E_INVALID, RX_E_UNSUPPORTED, RX_E_NOMEM, RX_E_HIP, RX_E_STATE = 0, -1, -2, -3, -4, -5
 RX_W_FALLBACK = 1
 RX_DEBUG_KEEP = 0x1
@@ -49,7 +50,7 @@ class rx_params(ctypes.Structure):
                 ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
                 ("deadline_s", ctypes.c_double), ("ref_bits", ctypes.c_void_p),
                 ("ref_period", ctypes.c_uint64), ("blocks_bc", ctypes.c_int32), ("ffe_gpw", ctypes.c_int32),
-                ("dec_syms", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
+                ("dec_syms", ctypes.c_int32), ("front", ctypes.c_int32)]
 
 
 class rx_stats(ctypes.Structure):

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librx.so")
-SOURCES = ["kk.hip", "eq.hip", "pam.hip", "mlp.hip", "api.cpp"]
+SOURCES = ["kk.hip", "fd.hip", "eq.hip", "pam.hip", "mlp.hip", "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-Wall",
          # packed FP32 instructions are kept out of every kernel

@@ -185,6 +185,7 @@ int rx_params_default(rx_format fmt, rx_params *p) {
   p->blocks_bc = 0;
   p->ffe_gpw = 0;
   p->dec_syms = 0;
+  p->front = RX_FRONT_OS;
   return RX_OK;
 }
 
@@ -224,6 +225,43 @@ static const SharedTables *shared_tables(int log2n, int htaps) {
   if (hipMalloc((void **)&t.hspec, n * sizeof(float)) != hipSuccess) return nullptr;
   if (hipMalloc((void **)&t.twid, tw.size() * sizeof(float2)) != hipSuccess ||
       hipMemcpy(t.hspec, hs.data(), n * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(t.twid, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) {
+    hipFree(t.hspec);
+    if (t.twid) hipFree(t.twid);
+    return nullptr;
+  }
+  return &(cache[key] = t);
+}
+
+// Tables of the frequency-domain front end, one copy per (device, roll-off):
+// hspec holds S[k] = sgn(k) / 1024 (block-circular Hilbert: -j S, zero at DC
+// and N/2) and then the static equaliser's response over the 1024 bins,
+// divided by 1024 (the 203-tap matched RRC, centred, so real); twid holds
+// the 1024-point twiddles and then the 512-point ones.
+static const SharedTables *fd_tables(double rolloff) {
+  static std::mutex mu;
+  static std::map<std::pair<int, double>, SharedTables> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  const auto key = std::make_pair(dev, rolloff);
+  auto it = cache.find(key);
+  if (it != cache.end()) return &it->second;
+  constexpr int N = 1 << RX_KK_FD_LOG2, EQ = 203;
+  std::vector<float> hs(2 * N);
+  for (int k = 0; k < N; k++) hs[k] = (k == 0 || k == N / 2) ? 0.0f : (k < N / 2 ? 1.0f : -1.0f) / N;
+  const std::vector<double> heq = design_rrc(EQ, 4.0, rolloff);
+  for (int k = 0; k < N; k++) {
+    double acc = 0.0;
+    for (int i = 0; i < EQ; i++) acc += heq[i] * std::cos(2.0 * M_PI * (double)(((int64_t)k * (i - EQ / 2)) % N + N) / N);
+    hs[N + k] = (float)(acc / N);
+  }
+  std::vector<float2> tw = design_twiddles(RX_KK_FD_LOG2), tw2 = design_twiddles(RX_KK_FD_LOG2 - 1);
+  tw.insert(tw.end(), tw2.begin(), tw2.end());
+  SharedTables t{nullptr, nullptr};
+  if (hipMalloc((void **)&t.hspec, hs.size() * sizeof(float)) != hipSuccess) return nullptr;
+  if (hipMalloc((void **)&t.twid, tw.size() * sizeof(float2)) != hipSuccess ||
+      hipMemcpy(t.hspec, hs.data(), hs.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(t.twid, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) {
     hipFree(t.hspec);
     if (t.twid) hipFree(t.twid);
@@ -361,7 +399,8 @@ static RxTune tune_shapes(rx_format fmt, double baud, double fs, const rx_params
   hipDeviceProp_t prop{};
   if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return kDefaultTune;
   const std::string key = std::string(prop.gcnArchName) + "|" + (kk ? "kk" : "pam") + "|" +
-                          std::to_string(p.precision) + "|" + std::to_string(p.ffe_taps);
+                          std::to_string(p.precision) + "|" + std::to_string(p.ffe_taps) +
+                          (p.front == RX_FRONT_FD ? "|fd" : "");
   std::lock_guard<std::mutex> lock(mu);
   const std::string path = tune_cache_path();
   if (!file_read) {
@@ -386,7 +425,7 @@ static RxTune tune_shapes(rx_format fmt, double baud, double fs, const rx_params
       hipMemcpy(dbuf, host.data(), host.size(), hipMemcpyHostToDevice) == hipSuccess) {
     struct Knob { int32_t RxTune::*field; std::vector<int32_t> cand; int stage; bool used; };
     const Knob knobs[] = {
-        {&RxTune::fft_log2, {14, 13}, RX_ST_KK_FRONT, kk},
+        {&RxTune::fft_log2, {14, 13}, RX_ST_KK_FRONT, kk && p.front != RX_FRONT_FD},
         {&RxTune::blocks_bc, {8, 4, 16}, RX_ST_BLOCKS, !(kk && p.precision != RX_FP32)},
         {&RxTune::ffe_gpw, {8, 4, 16}, RX_ST_BLOCKS, kk && p.precision != RX_FP32},
         {&RxTune::dec_syms, {2048, 1024, 4096}, RX_ST_DECIDE, true},
@@ -453,6 +492,9 @@ static int create_tuned(rx_format fmt, double baud, double fs, const rx_params *
   if (!(p.deadline_s >= 0.0) || (reinterpret_cast<uintptr_t>(p.ref_bits) & 3)) return RX_E_INVALID;
   const bool stream = (p.flags & RX_STREAM) != 0;
   if (stream && p.ref_bits) return RX_E_UNSUPPORTED;   // a stream's reference outgrows any one buffer
+  if (p.front != RX_FRONT_OS && p.front != RX_FRONT_FD) return RX_E_INVALID;
+  const bool fd = p.front == RX_FRONT_FD;
+  if (fd && (!kk || p.precision != RX_FP32 || stream)) return RX_E_UNSUPPORTED;
   int wall_khz = 0;
   {
     int dev = 0;
@@ -475,6 +517,7 @@ static int create_tuned(rx_format fmt, double baud, double fs, const rx_params *
     RxTune t{forced.fft_log2 ? forced.fft_log2 : p.fft_log2, forced.blocks_bc ? forced.blocks_bc : p.blocks_bc,
              forced.ffe_gpw ? forced.ffe_gpw : p.ffe_gpw, forced.dec_syms ? forced.dec_syms : p.dec_syms};
     if (!kk && !t.fft_log2) t.fft_log2 = 14;   // no transform in the PAM chain
+    if (fd) t.fft_log2 = RX_KK_FD_LOG2;         // the paper's 1024-point blocks
     if (!(kk && p.precision != RX_FP32) && !t.ffe_gpw) t.ffe_gpw = 8;
     if (!t.fft_log2 || !t.blocks_bc || !t.ffe_gpw || !t.dec_syms) {
       const RxTune tuned = tune_shapes(fmt, baud, fs, p);
@@ -500,7 +543,10 @@ static int create_tuned(rx_format fmt, double baud, double fs, const rx_params *
   J.prefix = p.prefix_symbols;
   J.precision = p.precision;
   J.fft_log2 = h->log2n;
-  J.hop = rx_kk_hop(h->log2n);
+  // the frequency-domain front end writes one set of sums per 512-sample
+  // block, which is what the prefix stage's count of ceil(ceil(n / hop) / 2)
+  // gives with hop 256
+  J.hop = fd ? 256 : rx_kk_hop(h->log2n);
   J.blk = kk ? 128 : 256;
   J.equalizer = p.equalizer;
   J.mu = (float)p.mu;
@@ -535,6 +581,7 @@ static int create_tuned(rx_format fmt, double baud, double fs, const rx_params *
     if (p.precision == RX_BF16) hf[i] = (float)(__bf16)hf[i];
     else if (p.precision == RX_FP16) hf[i] = (float)(_Float16)hf[i];
   }
+  if (fd) std::fill(hf.begin(), hf.end(), 0.0f);   // no carrier term: the FD output is carrier-free
   float *dmf = A.get<float>(slots);
   bool ok = dmf != nullptr;
   if (ok) ok = hipMemcpy(dmf, hf.data(), slots * sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
@@ -544,7 +591,7 @@ static int create_tuned(rx_format fmt, double baud, double fs, const rx_params *
     std::complex<double> c0 = 0.0;
     for (int i = 0; i < 65; i++) c0 += (double)hf[i] * std::exp(std::complex<double>(0.0, -2.0 * M_PI * J.r * (32 - i)));
     J.c0 = make_float2((float)c0.real(), (float)c0.imag());
-    const SharedTables *t = shared_tables(h->log2n, p.hilbert_taps);
+    const SharedTables *t = fd ? fd_tables(p.rolloff) : shared_tables(h->log2n, p.hilbert_taps);
     ok = t != nullptr;
     if (ok) {
       J.hspec = t->hspec;
@@ -560,6 +607,11 @@ static int create_tuned(rx_format fmt, double baud, double fs, const rx_params *
     J.field = J.debug ? A.get<float2>(L) : nullptr;
     J.udbg = J.debug ? A.get<float2>(nd) : nullptr;
     ok = ok && J.z && J.part && J.soft && J.s4 && J.theta && (!J.debug || (J.field && J.udbg));
+    if (fd) {
+      J.phi = A.get<float>(L);
+      J.fdpart = A.get<double2>(L / 1024 + 1);
+      ok = ok && J.phi && J.fdpart;
+    }
   } else if (ok) {
     J.y = A.get<float>(L);
     J.xr = A.get<float>(L);

@@ -1,7 +1,8 @@
 // In-LDS complex FFT for one workgroup: Stockham auto-sort, radix-16 passes
-// followed by one radix-2/4/8 pass, N = 16 * blockDim.x.  Each thread holds
-// exactly 16 values per pass: read all, barrier, butterfly, write, barrier,
-// so the transform runs in place in one padded LDS buffer.  The passes can
+// followed by one radix-2/4/8 pass, N = 16 * blockDim.x (or radix-8 passes,
+// N = 8 * blockDim.x).  Each thread holds exactly 16 (8) values per pass:
+// read all, barrier, butterfly, write, barrier, so the transform runs in
+// place in one padded LDS buffer.  The passes can
 // be entered after the first (a caller that formed the first pass itself)
 // and the last pass's outputs handed to a caller's functor instead of LDS.
 #pragma once
@@ -120,10 +121,10 @@ struct LdsOut {
 // One Stockham pass of radix R with NS = product of the previous radices.
 // Butterfly j reads x[j + r N/R], twiddles by W_{NS R}^{r (j mod NS)}, and
 // writes to (j / NS) NS R + (j mod NS) + r NS.  NS is a compile-time
-// constant so the padded LDS offsets of the 16 accesses fold to immediates.
-template <int N, int R, int NS, bool TAIL = true, class Out = LdsOut>
+// constant so the padded LDS offsets of the VPT accesses fold to immediates.
+template <int N, int R, int NS, bool TAIL = true, class Out = LdsOut, int VPT = 16>
 __device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *__restrict__ tw, Out out) {
-  constexpr int T = N / 16;
+  constexpr int T = N / VPT;
   constexpr int NB = (N / R) / T;  // butterflies per thread
   // twiddle table reads first: their latency overlaps the LDS reads and the
   // barrier.  They go through a global-memory view: as flat accesses they
@@ -161,14 +162,28 @@ __device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *__restr
     dft_r<R>(v[b]);
     const int base = (j / NS) * NS * R + k;
     // fpad(base + r NS) = fpad(base) + fpad(r NS): either NS is a multiple of
-    // 16, or NS = 1 and base is (R = 16), so base mod 16 + r NS mod 16 < 16;
+    // 16, or base mod 16 + r NS mod 16 < 16 (NS = 1, R = 16: base mod 16 = 0;
+    // NS = 1 or 8, R = 8: base mod 16 < 8 and r NS mod 16 in {0, 8} or < 8);
     // the second term is a constant, folded into the store's offset
-    static_assert(NS % 16 == 0 || (NS == 1 && R == 16), "padded write offsets split");
+    static_assert(NS % 16 == 0 || (NS == 1 && (R == 16 || R == 8)) || (NS == 8 && R == 8),
+                  "padded write offsets split");
     const int pb = fpad(base);
 #pragma unroll
     for (int r = 0; r < R; r++) out(b * T + r * NS, pb + fpad(r * NS), v[b][r]);
   }
   if constexpr (TAIL) __syncthreads();
+}
+
+// Radix-8 passes only, 8 values per thread (N = 8 * blockDim.x, N a power of 8).
+template <int N, int NS, bool TAIL, class Out>
+__device__ __forceinline__ void fft_passes8(float2 *buf, const float2 *__restrict__ tw, Out out) {
+  if constexpr (NS * 8 < N) {
+    stockham_pass<N, 8, NS, true, LdsOut, 8>(buf, tw, LdsOut{buf});
+    fft_passes8<N, NS * 8, TAIL>(buf, tw, out);
+  } else {
+    static_assert(NS * 8 == N, "N is a power of 8");
+    stockham_pass<N, 8, NS, TAIL, Out, 8>(buf, tw, out);
+  }
 }
 
 template <int N, int NS, bool TAIL, class Out>

@@ -523,7 +523,9 @@ static void launch_front(const RxLaunch &L, int64_t maxn, hipStream_t s) {
 void rx_launch_kk_stage(int stage, const RxLaunch &L, int64_t maxn, int log2n, int prec, hipStream_t s) {
   const unsigned cnt = (unsigned)L.count;
   if (stage == ST_KK_FRONT) {
-    if (log2n == 13) {
+    if (log2n == RX_KK_FD_LOG2) {
+      rx_launch_kkfd(L, maxn, s);
+    } else if (log2n == 13) {
       if (prec == 1) launch_front<13, 1>(L, maxn, s);
       else if (prec == 2) launch_front<13, 2>(L, maxn, s);
       else launch_front<13, 0>(L, maxn, s);
@@ -533,9 +535,10 @@ void rx_launch_kk_stage(int stage, const RxLaunch &L, int64_t maxn, int log2n, i
       else launch_front<14, 0>(L, maxn, s);
     }
   } else if (stage == ST_KK_DEBUG) {
-    // the field E (the same FP32 arithmetic in every form), then u
+    // the field E (the same FP32 arithmetic in every form; the
+    // frequency-domain front end writes it itself), then u
     if (log2n == 13) launch_front<13, 0, true>(L, maxn, s);
-    else launch_front<14, 0, true>(L, maxn, s);
+    else if (log2n == 14) launch_front<14, 0, true>(L, maxn, s);
     const int64_t nd = maxn / 2;
     hipLaunchKernelGGL(kk_debug_u, dim3((unsigned)((nd + 255) / 256), cnt), dim3(256), 0, s, L);
   } else if (stage == ST_KK_VV) {

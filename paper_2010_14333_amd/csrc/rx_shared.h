@@ -58,6 +58,8 @@ struct RxJob {
   float *theta;                     // KK: carrier phase per block
   float2 *field;                    // KK debug: reconstructed field [n] or null
   float2 *udbg;                     // KK debug: AGC'd carrier-free MF output [n/2] or null
+  float *phi;                       // KK frequency-domain front end: phase (revolutions) [n]
+  double2 *fdpart;                  // KK frequency-domain front end: field sums per block pair
   const float *mlp;                 // PAM learned equaliser parameters (FP32) or null
   const uint32_t *refw;             // reference bits of symbols 0 .. max_samples / sps - 1, packed as the output
   RxScalars *sc;
@@ -129,6 +131,9 @@ enum RxStage {
   ST_PREFIX, ST_BLOCKS, ST_KK_VV, ST_DECIDE, ST_MLP_INFER, ST_MLP_JUDGE, ST_COUNT
 };
 void rx_launch_kk_stage(int stage, const RxLaunch &L, int64_t maxn, int log2n, int prec, hipStream_t s);
+// the paper's frequency-domain KK front end (jobs with fft_log2 == RX_KK_FD_LOG2)
+#define RX_KK_FD_LOG2 10
+void rx_launch_kkfd(const RxLaunch &L, int64_t maxn, hipStream_t s);
 void rx_launch_pam_stage(int stage, const RxLaunch &L, int64_t maxn, hipStream_t s);
 void rx_launch_eq_stage(int stage, const RxLaunch &L, int64_t maxn, int kk, int ffe_taps, int prec, const RxTune &t,
                         hipStream_t s);

@@ -201,3 +201,29 @@ def test_invalid_sizes_rejected(rx):
             with pytest.raises(rx.RxError):
                 rx.rx_process(r.h, buf.data_ptr(), n, out.data_ptr())
         r.close()
+
+
+# The paper's own frequency-domain KK front end (1024-point blocks at hop
+# 512, block-circular Hilbert, 203-tap static equaliser, 512-point IFFT to 2
+# samples per symbol) against the oracle's, through the same chain after it.
+@pytest.mark.parametrize("fmt,n,seed,snr,gen", [
+    (5, 1 << 18, 51, 22.0, {}),
+    (5, 1 << 18, 52, 16.0, {}),
+    (4, 1 << 18, 53, 22.0, {}),
+    (4, 1 << 18, 54, None, {"theta_c": 2.0}),
+    (5, (1 << 18) + 3 * 1024, 55, 22.0, {}),   # ragged
+    (5, 17408, 56, 22.0, {}),                  # smallest KK buffer
+])
+def test_parity_fd_front(rx, fmt, n, seed, snr, gen):
+    check_chain(rx, fmt, n, seed, snr, rxo={"front": 1}, **gen)
+
+
+def test_fd_front_rejects_what_it_does_not_cover(rx):
+    for fmt, over in ((5, {"precision": 1}), (5, {"flags": 0x4}), (2, {})):
+        p = rx.rx_params_default(fmt)
+        p.front = 1
+        for k, v in over.items():
+            setattr(p, k, v)
+        with pytest.raises(rx.RxError) as e:
+            rx.rx_create(fmt, *((1e9,) if fmt >= 4 else (2e9,)), 4e9, p)
+        assert e.value.code == rx.RX_E_UNSUPPORTED
