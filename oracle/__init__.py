@@ -67,6 +67,8 @@ def lib():
         L.rxo_hilbert_os.argtypes = [_dp, ctypes.c_int64, _dp, ctypes.c_int32, ctypes.c_int32, _dp]
         L.rxo_hilbert_fd.argtypes = [_dp, ctypes.c_int64, _dp]
         L.rxo_fd_eq_dec2.argtypes = [_dp, ctypes.c_int64, _dp, ctypes.c_int32, _dp]
+        L.rxo_fd_fir.argtypes = [_dp, ctypes.c_int64, _dp, ctypes.c_int32, _dp]
+        L.rxo_fd_delay.argtypes = [_dp, ctypes.c_int64, _dp, _dp]
         L.rxo_gardner.argtypes = [_dp, ctypes.c_int64, _dp]
         L.rxo_farrow.argtypes = [_dp, ctypes.c_int64, _dp, _dp]
         L.rxo_gardner_sums.argtypes = [_dp, ctypes.c_int64, _dp]
@@ -293,6 +295,24 @@ def fd_eq_dec2(y, h):
 
 
 FD_EQ_TAPS = 203
+FD_PAM_EQ_TAPS = 503
+
+
+def fd_fir(x, h):
+    """Real FIR h on the frequency-domain blocks (central outputs kept)."""
+    x, h = _f64(x), _f64(h)
+    y = np.zeros_like(x)
+    lib().rxo_fd_fir(_p(x), x.size, _p(h), h.size, _p(y))
+    return y
+
+
+def fd_delay(x, delta):
+    """Block b's central samples resampled at t + delta[b] in the frequency domain."""
+    x, d = _f64(x), _f64(delta)
+    assert d.size >= (x.size + 511) // 512
+    y = np.zeros_like(x)
+    lib().rxo_fd_delay(_p(x), x.size, _p(d), _p(y))
+    return y
 
 
 def gardner(x):

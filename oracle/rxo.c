@@ -169,6 +169,9 @@ static inline double edge(const double *l, int64_t n, int64_t j)
   return l[j < 0 ? 0 : (j >= n ? n - 1 : j)];
 }
 
+/* x[j] inside the buffer, zero outside */
+static inline double at(const double *x, int64_t n, int64_t j) { return (j >= 0 && j < n) ? x[j] : 0.0; }
+
 /* Hilbert FIR applied directly, input replicated beyond the buffer edges:
  * phi[t] = sum_m h(m) l[t - m]. */
 void rxo_hilbert_direct(const double *l, int64_t n, const double *h, int32_t ntaps, double *phi)
@@ -280,6 +283,51 @@ void rxo_fd_eq_dec2(const double *yv, int64_t n, const double *h, int32_t ntaps,
   free(buf); free(hf); free(z);
 }
 
+/* A real FIR in the frequency domain on the same blocks: each block's
+ * spectrum (samples outside the buffer are zero) times the response of the
+ * centred ntaps-tap filter, back, central 512 samples kept.  For ntaps up to
+ * 2 * 256 + 1 no central output wraps around the block, so this is the
+ * "same" convolution with zeros outside the buffer, by another route. */
+void rxo_fd_fir(const double *x, int64_t n, const double *h, int32_t ntaps, double *y)
+{
+  cplx *buf = (cplx *)malloc(sizeof(cplx) * FD_N), *hf = (cplx *)calloc(FD_N, sizeof(cplx));
+  const int32_t c = (ntaps - 1) / 2;
+  for (int32_t i = 0; i < ntaps; i++) hf[((i - c) % FD_N + FD_N) % FD_N] += h[i];
+  rxo_fft((double *)hf, FD_N, 0);
+  for (int64_t b = 0; b * FD_HOP < n; b++) {
+    const int64_t t0 = b * FD_HOP - FD_GUARD;
+    for (int t = 0; t < FD_N; t++) buf[t] = at(x, n, t0 + t);
+    rxo_fft((double *)buf, FD_N, 0);
+    for (int k = 0; k < FD_N; k++) buf[k] *= hf[k];
+    rxo_fft((double *)buf, FD_N, 1);
+    for (int u = 0; u < FD_HOP && b * FD_HOP + u < n; u++) y[b * FD_HOP + u] = creal(buf[FD_GUARD + u]) / FD_N;
+  }
+  free(buf); free(hf);
+}
+
+/* Timing correction in the frequency domain: block b's central samples are
+ * the block resampled at t + delta[b] (delta in samples, one per 512-sample
+ * block, as rxo_gardner gives it), i.e. its spectrum times exp(+j 2 pi k d /
+ * N) for the signed bin index k in (-N/2, N/2) and cos(pi d) at N/2 (the
+ * real part of either sign, so the result stays real). */
+void rxo_fd_delay(const double *x, int64_t n, const double *delta, double *xr)
+{
+  cplx *buf = (cplx *)malloc(sizeof(cplx) * FD_N);
+  for (int64_t b = 0; b * FD_HOP < n; b++) {
+    const int64_t t0 = b * FD_HOP - FD_GUARD;
+    const double d = delta[b];
+    for (int t = 0; t < FD_N; t++) buf[t] = at(x, n, t0 + t);
+    rxo_fft((double *)buf, FD_N, 0);
+    for (int k = 0; k < FD_N; k++) {
+      if (k == FD_N / 2) buf[k] *= cos(M_PI * d);
+      else buf[k] *= cexp(2.0 * M_PI * I * (double)(k < FD_N / 2 ? k : k - FD_N) * d / FD_N);
+    }
+    rxo_fft((double *)buf, FD_N, 1);
+    for (int u = 0; u < FD_HOP && b * FD_HOP + u < n; u++) xr[b * FD_HOP + u] = creal(buf[FD_GUARD + u]) / FD_N;
+  }
+  free(buf);
+}
+
 /* ------------------------------------------------------------------ */
 /* Rounding to the narrow operand formats of the precision form          */
 /* (round to nearest, ties to even).                                     */
@@ -363,7 +411,6 @@ static uint32_t symbol_bits(int fmt, cplx z)
 /* clock-phase estimation, unwrapping, clock recovery), as feed-forward  */
 /* Gardner estimation per 256-symbol block.                              */
 /* ------------------------------------------------------------------ */
-static inline double at(const double *x, int64_t n, int64_t j) { return (j >= 0 && j < n) ? x[j] : 0.0; }
 
 /* Detector sums per 512-sample block (256 symbols): C_b = G0_b + j G1_b,
  * G0 the Gardner detector on the symbol-spaced samples, G1 the same detector
@@ -666,7 +713,7 @@ int rxo_process(const rxo_cfg *cfg, const uint8_t *packed, int64_t n, rxo_out *o
   const rxo_out *fz = cfg->frozen;
   if (P + 2 * G >= nsym || K < 1 || K % 2 == 0 || cfg->mf_taps % 2 == 0) return -1;
   if (cfg->equalizer == 1 && (kk || !cfg->mlp)) return -1;
-  if (cfg->front == 1 && (!kk || rm || fz)) return -1;   /* the FD front end: KK, FP64, one buffer */
+  if (cfg->front == 1 && (rm || fz || cfg->equalizer == 1)) return -1;   /* the FD front end: FP64, one buffer, LMS */
 
   int32_t *code = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
   rxo_unpack12(packed, n, code);
@@ -731,7 +778,15 @@ int rxo_process(const rxo_cfg *cfg, const uint8_t *packed, int64_t n, rxo_out *o
     double *x0 = (double *)malloc(sizeof(double) * (size_t)n);
     double *y = (double *)malloc(sizeof(double) * (size_t)n);
     for (int64_t t = 0; t < n; t++) x0[t] = (double)code[t] + 0.5 - mv;
-    rxo_fir_same(x0, n, hm, cfg->mf_taps, y);
+    if (cfg->front == 1) {
+      /* the paper's 503-tap static equaliser on the 1024-point blocks (Sec. 2,
+       * first paragraph), here the matched RRC of the same roll-off */
+      double heq[RXO_FD_PAM_EQ_TAPS];
+      rxo_rrc_taps(RXO_FD_PAM_EQ_TAPS, (double)sps, cfg->rolloff, heq);
+      rxo_fd_fir(x0, n, heq, RXO_FD_PAM_EQ_TAPS, y);
+    } else {
+      rxo_fir_same(x0, n, hm, cfg->mf_taps, y);
+    }
     o->mean_re = mv;
     o->mean_im = 0.0;
     for (int64_t t = 0; t < n; t++) x[t] = y[t];
@@ -759,7 +814,8 @@ int rxo_process(const rxo_cfg *cfg, const uint8_t *packed, int64_t n, rxo_out *o
     double *dl = (double *)malloc(sizeof(double) * (size_t)(n / 512));
     for (int64_t t = 0; t < n; t++) xs[t] = creal(x[t]);
     rxo_gardner(xs, n, dl);
-    rxo_farrow(xs, n, dl, xr);
+    if (cfg->front == 1) rxo_fd_delay(xs, n, dl, xr);   /* FD clock recovery (Sec. 2, first paragraph) */
+    else rxo_farrow(xs, n, dl, xr);
     if (o->timing) memcpy(o->timing, dl, sizeof(double) * (size_t)(n / 512));
     if (o->xr) memcpy(o->xr, xr, sizeof(double) * (size_t)n);
     for (int64_t t = 0; t < n; t++) x[t] = xr[t];

@@ -29,10 +29,14 @@ typedef struct {
   int32_t form;          /* 0: block-parallel DD-LMS FFE; 1: FFE frozen at the prefix taps */
   int32_t rounding;      /* 0: none; 1: BF16; 2: FP16 operands (MF + FFE, or the MLP) */
   int32_t equalizer;     /* 0: LMS FFE; 1: MLP (PAM only) */
-  int32_t front;         /* KK front end: 0, a finite Hilbert FIR by overlap-save and the matched
-                            FIR; 1, the paper's frequency-domain form (rxo_hilbert_fd,
-                            rxo_fd_eq_dec2: 1024-point blocks at hop 512, block-circular
-                            Hilbert, 203-tap static equaliser, 512-point IFFT to 2 sps) */
+  int32_t front;         /* 0: the time-domain front end (KK: a finite Hilbert FIR by
+                            overlap-save and the matched FIR; PAM: the matched FIR and cubic
+                            Farrow timing correction).  1: the paper's frequency-domain form
+                            on 1024-point blocks at hop 512 (KK: rxo_hilbert_fd, block-circular
+                            Hilbert, and rxo_fd_eq_dec2, 203-tap static equaliser and
+                            512-point IFFT to 2 sps; PAM: rxo_fd_fir, 503-tap static
+                            equaliser, and rxo_fd_delay, timing correction in the frequency
+                            domain).  FP64 arithmetic, one buffer, no learned equaliser */
   double rolloff, mu, mu_cma, fc_over_fs;
   uint64_t seed;         /* reference sequence: bits of symbol k = top bits of SplitMix64(seed, k) */
   const double *mlp;     /* RXO_MLP_PARAMS packed parameters when equalizer == 1 */
@@ -64,6 +68,7 @@ typedef struct rxo_out_s {
 } rxo_out;
 
 #define RXO_FD_EQ_TAPS 203   /* the paper's KK static equaliser length */
+#define RXO_FD_PAM_EQ_TAPS 503   /* the paper's PAM static equaliser length */
 #define RXO_MLP_IN 31
 #define RXO_MLP_H 64
 #define RXO_MLP_PARAMS (RXO_MLP_H * RXO_MLP_IN + RXO_MLP_H + RXO_MLP_H * RXO_MLP_H + RXO_MLP_H + RXO_MLP_H + 1)
@@ -82,6 +87,8 @@ void rxo_hilbert_direct(const double *l, int64_t n, const double *h, int32_t nta
 void rxo_hilbert_os(const double *l, int64_t n, const double *h, int32_t ntaps, int32_t log2n, double *phi);
 void rxo_hilbert_fd(const double *l, int64_t n, double *phi);
 void rxo_fd_eq_dec2(const double *y, int64_t n, const double *h, int32_t ntaps, double *x);
+void rxo_fd_fir(const double *x, int64_t n, const double *h, int32_t ntaps, double *y);
+void rxo_fd_delay(const double *x, int64_t n, const double *delta, double *xr);
 void rxo_gardner_sums(const double *x, int64_t n, double *c);
 void rxo_gardner(const double *x, int64_t n, double *delta);
 void rxo_farrow(const double *x, int64_t n, const double *delta, double *xr);

@@ -6,7 +6,7 @@
  * documents, so a write past a documented size is an ASan report.  The run
  * covers one buffer through the full chain, the stream-continuation form
  * (the acquisition frozen from the first pass, a shortened counting window,
- * forced decisions), the KK frequency-domain front end and the exported
+ * forced decisions), the frequency-domain front ends and the exported
  * building blocks with odd sizes.
  *
  * Input file: int32 fmt, rounding, form, equalizer; int64 n; uint64 seed;
@@ -112,18 +112,22 @@ int main(int argc, char **argv) {
   cfg.count_end = nsym - 1000;
   if (rxo_process(&cfg, packed, n, &o2) != 0) { fprintf(stderr, "rejected (stream form)\n"); return 3; }
 
-  /* KK: the frequency-domain front end (plain arithmetic only) */
-  if (kk && cfg.rounding == 0) {
+  /* the frequency-domain front end (plain arithmetic, LMS only) */
+  if (cfg.rounding == 0 && cfg.equalizer == 0) {
     rxo_out o3;
     memset(&o3, 0, sizeof o3);
     o3.bits = take(nbytes);
-    o3.mf = take(sizeof(double) * 2 * (size_t)(n / 2));
+    o3.mf = take(sizeof(double) * (kk ? 2 * (size_t)(n / 2) : (size_t)n));
+    if (!kk) {
+      o3.xr = take(sizeof(double) * (size_t)n);
+      o3.timing = take(sizeof(double) * (size_t)(n / 512));
+    }
     cfg.front = 1;
     cfg.frozen = NULL;
     cfg.force = NULL;
     cfg.count_end = 0;
     if (rxo_process(&cfg, packed, n, &o3) != 0) { fprintf(stderr, "rejected (FD front end)\n"); return 3; }
-    free(o3.bits); free(o3.mf);
+    free(o3.bits); free(o3.mf); free(o3.xr); free(o3.timing);
   }
 
   /* building blocks at odd sizes */
@@ -146,6 +150,9 @@ int main(int argc, char **argv) {
     double yc[2 * 1000], xc[1000];
     for (int i = 0; i < 2000; i++) yc[i] = 0.01 * (double)((i * 17) % 23);
     rxo_fd_eq_dec2(yc, 1000, hh, 65, xc);
+    double dd[2] = {0.3, -1.2}, xd[1000];
+    rxo_fd_fir(l, 1000, hh, 65, xd);
+    rxo_fd_delay(l, 1000, dd, xd);
     double x[1536], d[3], xr[1536], c[6];
     for (int i = 0; i < 1536; i++) x[i] = (double)((i * 13) % 7) - 3.0;
     rxo_gardner_sums(x, 1536, c);

@@ -1,8 +1,10 @@
-"""Pins of the oracle's frequency-domain KK front end, the paper's own form
-(Sec. 2, second paragraph): 1024-point blocks advancing by 512 samples,
-the Hilbert transform as -j sgn(k) on each block's spectrum, and the 203-tap
-static equaliser on the 1024-point spectrum with a 512-point inverse
-transform to 2 samples per symbol.  Each pin is fixed by the mathematics,
+"""Pins of the oracle's frequency-domain front ends, the paper's own forms
+(Sec. 2): 1024-point blocks advancing by 512 samples; for KK (second
+paragraph) the Hilbert transform as -j sgn(k) on each block's spectrum and
+the 203-tap static equaliser on the 1024-point spectrum with a 512-point
+inverse transform to 2 samples per symbol; for PAM (first paragraph) the
+503-tap static equaliser on the blocks and the clock recovery as a delay
+applied to each block's spectrum.  Each pin is fixed by the mathematics,
 not by retyping the oracle: exact transforms of tones that are periodic in
 a block, equality with the (separately pinned) time-domain FIR, and which
 input samples an output may depend on."""
@@ -138,6 +140,89 @@ def test_fd_front_rejects_what_it_does_not_cover():
     for kw in ({"rounding": 1}, ):
         with pytest.raises(ValueError):
             oracle.process(5, g["packed"], 1 << 16, g["seed"], front=1, **kw)
-    g2 = synth.generate(2, 1 << 16, seed=47, snr_db=20.0)
+    g2 = synth.generate(3, 1 << 16, seed=47, snr_db=20.0)
     with pytest.raises(ValueError):
-        oracle.process(2, g2["packed"], 1 << 16, g2["seed"], front=1)
+        oracle.process(3, g2["packed"], 1 << 16, g2["seed"], front=1, equalizer=1,
+                       mlp=np.zeros(oracle.MLP_PARAMS))
+
+
+# ---- the PAM frequency-domain forms (Sec. 2, first paragraph: 503-tap static
+# equaliser on the 1024-point blocks, frequency-domain clock recovery) ----
+def _rrc2(k):
+    h = np.zeros(k)
+    oracle.lib().rxo_rrc_taps(k, 2.0, 0.1, h.ctypes.data_as(oracle._dp))
+    return h
+
+
+def _fir_same(x, h):
+    y = np.zeros_like(x)
+    oracle.lib().rxo_fir_same(x.ctypes.data_as(oracle._dp), x.size, h.ctypes.data_as(oracle._dp), h.size,
+                              y.ctypes.data_as(oracle._dp))
+    return y
+
+
+def test_fd_fir_is_the_same_convolution():
+    """503 taps fit inside the 256-sample guards, so no central output wraps
+    around its block: the block filter equals the time-domain convolution
+    with zeros outside the buffer everywhere, edges included."""
+    rng = np.random.default_rng(6)
+    x = rng.normal(size=N + 1024)
+    for h in (_rrc2(oracle.FD_PAM_EQ_TAPS), rng.normal(size=oracle.FD_PAM_EQ_TAPS), rng.normal(size=33)):
+        assert np.abs(oracle.fd_fir(x, h) - _fir_same(x, h)).max() < 1e-12 * np.abs(x).max() * np.abs(h).sum()
+
+
+@pytest.mark.parametrize("k0", [3, 100, 511])
+def test_fd_delay_shifts_a_bin_tone_by_each_blocks_delay(k0):
+    rng = np.random.default_rng(k0)
+    d = rng.uniform(-1.5, 1.5, N // 512)
+    xr = oracle.fd_delay(np.cos(2 * np.pi * k0 * t / 1024 + 0.4), d)
+    ref = np.cos(2 * np.pi * k0 * (t + np.repeat(d, 512)) / 1024 + 0.4)
+    assert np.abs(xr - ref)[INNER].max() < 1e-10
+
+
+def test_fd_delay_at_half_the_rate_keeps_the_signal_real():
+    """The bin at N/2 takes cos(pi d): (-1)^t resampled at t + d is
+    (-1)^t cos(pi d), with no imaginary part to discard."""
+    d = np.linspace(-1.0, 1.0, N // 512)
+    xr = oracle.fd_delay((-1.0) ** t, d)
+    assert np.abs(xr - (-1.0) ** t * np.cos(np.pi * np.repeat(d, 512)))[INNER].max() < 1e-10
+
+
+def test_fd_delay_zero_and_integer_delays():
+    rng = np.random.default_rng(7)
+    x = rng.normal(size=N)
+    assert np.abs(oracle.fd_delay(x, np.zeros(N // 512)) - x).max() < 1e-12
+    # an integer delay of a block-periodic signal is an exact shift
+    per = rng.normal(size=1024)
+    xp = np.tile(per, N // 1024)
+    assert np.abs(oracle.fd_delay(xp, np.full(N // 512, 3.0)) - np.roll(xp, -3))[INNER].max() < 1e-10
+
+
+def test_fd_delay_approaches_band_limited_interpolation():
+    """On a band-limited signal (not periodic in the blocks) the block-circular
+    delay differs from the exact shift only by the wrap-around of the block
+    edges, attenuated across the 256-sample guards."""
+    rng = np.random.default_rng(8)
+    f = np.fft.rfftfreq(4 * N)
+    spec = (rng.normal(size=f.size) + 1j * rng.normal(size=f.size)) * (f < 0.3)
+    d = 0.37
+
+    def sig(shift):
+        return np.fft.irfft(spec * np.exp(2j * np.pi * f * shift), 4 * N)[:N]
+    xr = oracle.fd_delay(sig(0.0), np.full(N // 512, d))
+    err = np.abs(xr - sig(d))[INNER]
+    assert err.max() < 2e-2 * np.abs(sig(0.0)).max() and np.sqrt(np.mean(err ** 2)) < 2e-3 * np.std(sig(0.0))
+
+
+@pytest.mark.parametrize("fmt", [1, 2, 3])
+def test_pam_fd_chain_noiseless_is_error_free(fmt):
+    g = synth.generate(fmt, 1 << 18, seed=60 + fmt, snr_db=None, drive=0.1)
+    r = oracle.process(fmt, g["packed"], 1 << 18, g["seed"], want=("bits",), front=1)
+    assert r["counted_bits"] > 100000 and r["bit_errors"] == 0
+
+
+def test_pam_fd_chain_agrees_with_the_time_domain_chain():
+    g = synth.generate(3, 1 << 18, seed=63, snr_db=20.0)
+    fd = oracle.process(3, g["packed"], 1 << 18, g["seed"], want=("bits",), front=1)
+    td = oracle.process(3, g["packed"], 1 << 18, g["seed"], want=("bits",))
+    assert abs(fd["bit_errors"] - td["bit_errors"]) < 0.1 * td["bit_errors"]
