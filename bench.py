@@ -443,10 +443,13 @@ def main():
         del tsrc
         pbp = [b.data_ptr() for b in pb]
         res = {}
-        for eq in ("mlp", "lms"):
+        # the learned equaliser, LMS, and LMS behind the paper's frequency-domain
+        # front end (503-tap static equaliser, clock recovery on the spectra)
+        for eq in ("mlp", "lms", "lms_fd"):
             def make(st, eq=eq):
                 recs = [rx.Receiver(rx.RX_PAM8, testg[i % len(testg)]["seed"], max_samples=N, stream=st,
-                                    equalizer=rx.RX_EQ_MLP if eq == "mlp" else rx.RX_EQ_LMS)
+                                    equalizer=rx.RX_EQ_MLP if eq == "mlp" else rx.RX_EQ_LMS,
+                                    front=rx.RX_FRONT_FD if eq == "lms_fd" else rx.RX_FRONT_OS)
                         for i in range(a.batch)]
                 if eq == "mlp":
                     for r in recs:
@@ -458,13 +461,15 @@ def main():
                                 f"test buffers in {a.batch} allocations per batch",
                     "value": round(res["mlp"][0], 3), "unit": "Gsamples/s", "ber": res["mlp"][1],
                     "fallbacks": res["mlp"][2], "lms_value": round(res["lms"][0], 3), "lms_ber": res["lms"][1],
+                    "lms_fd_value": round(res["lms_fd"][0], 3), "lms_fd_ber": res["lms_fd"][1],
                     "train_samples": len(train) * N, "train_s": round(train_s, 3), "final_loss": round(loss, 5)}
         if a.roofline:
             # each PAM stage alone on the chip: one stream, stage events on one handle
-            for eq in ("mlp", "lms"):
+            for eq in ("mlp", "lms", "lms_fd"):
                 recs = [rx.Receiver(rx.RX_PAM8, testg[i % len(testg)]["seed"], max_samples=N, stream=streams[0],
                                     flags=rx.RX_PROFILE if i == 0 else 0,
-                                    equalizer=rx.RX_EQ_MLP if eq == "mlp" else rx.RX_EQ_LMS)
+                                    equalizer=rx.RX_EQ_MLP if eq == "mlp" else rx.RX_EQ_LMS,
+                                    front=rx.RX_FRONT_FD if eq == "lms_fd" else rx.RX_FRONT_OS)
                         for i in range(a.batch)]
                 if eq == "mlp":
                     for r in recs:

@@ -233,24 +233,26 @@ static const SharedTables *shared_tables(int log2n, int htaps) {
   return &(cache[key] = t);
 }
 
-// Tables of the frequency-domain front end, one copy per (device, roll-off):
-// hspec holds S[k] = sgn(k) / 1024 (block-circular Hilbert: -j S, zero at DC
-// and N/2) and then the static equaliser's response over the 1024 bins,
-// divided by 1024 (the 203-tap matched RRC, centred, so real); twid holds
-// the 1024-point twiddles and then the 512-point ones.
-static const SharedTables *fd_tables(double rolloff) {
+// Tables of the frequency-domain front ends, one copy per (device, roll-off,
+// chain): hspec holds S[k] = sgn(k) / 1024 (block-circular Hilbert: -j S,
+// zero at DC and N/2) and then the static equaliser's response over the 1024
+// bins, divided by 1024 (the matched RRC, 203 taps at 4 sps for KK, 503 at
+// 2 sps for PAM, centred, so real); twid holds the 1024-point twiddles and
+// then the 512-point ones.
+static const SharedTables *fd_tables(double rolloff, bool kk) {
   static std::mutex mu;
-  static std::map<std::pair<int, double>, SharedTables> cache;
+  static std::map<std::tuple<int, double, bool>, SharedTables> cache;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return nullptr;
   std::lock_guard<std::mutex> lock(mu);
-  const auto key = std::make_pair(dev, rolloff);
+  const auto key = std::make_tuple(dev, rolloff, kk);
   auto it = cache.find(key);
   if (it != cache.end()) return &it->second;
-  constexpr int N = 1 << RX_KK_FD_LOG2, EQ = 203;
+  constexpr int N = 1 << RX_KK_FD_LOG2;
+  const int EQ = kk ? 203 : 503;   // the paper's static equaliser lengths (KK, PAM)
   std::vector<float> hs(2 * N);
   for (int k = 0; k < N; k++) hs[k] = (k == 0 || k == N / 2) ? 0.0f : (k < N / 2 ? 1.0f : -1.0f) / N;
-  const std::vector<double> heq = design_rrc(EQ, 4.0, rolloff);
+  const std::vector<double> heq = design_rrc(EQ, kk ? 4.0 : 2.0, rolloff);
   for (int k = 0; k < N; k++) {
     double acc = 0.0;
     for (int i = 0; i < EQ; i++) acc += heq[i] * std::cos(2.0 * M_PI * (double)(((int64_t)k * (i - EQ / 2)) % N + N) / N);
@@ -494,7 +496,7 @@ static int create_tuned(rx_format fmt, double baud, double fs, const rx_params *
   if (stream && p.ref_bits) return RX_E_UNSUPPORTED;   // a stream's reference outgrows any one buffer
   if (p.front != RX_FRONT_OS && p.front != RX_FRONT_FD) return RX_E_INVALID;
   const bool fd = p.front == RX_FRONT_FD;
-  if (fd && (!kk || p.precision != RX_FP32 || stream)) return RX_E_UNSUPPORTED;
+  if (fd && (p.precision != RX_FP32 || stream || p.equalizer != RX_EQ_LMS)) return RX_E_UNSUPPORTED;
   int wall_khz = 0;
   {
     int dev = 0;
@@ -516,7 +518,7 @@ static int create_tuned(rx_format fmt, double baud, double fs, const rx_params *
     // the launch shapes: forced (tuning), else given, else tuned
     RxTune t{forced.fft_log2 ? forced.fft_log2 : p.fft_log2, forced.blocks_bc ? forced.blocks_bc : p.blocks_bc,
              forced.ffe_gpw ? forced.ffe_gpw : p.ffe_gpw, forced.dec_syms ? forced.dec_syms : p.dec_syms};
-    if (!kk && !t.fft_log2) t.fft_log2 = 14;   // no transform in the PAM chain
+    if (!kk && !t.fft_log2) t.fft_log2 = 14;   // no overlap-save transform in the PAM chain
     if (fd) t.fft_log2 = RX_KK_FD_LOG2;         // the paper's 1024-point blocks
     if (!(kk && p.precision != RX_FP32) && !t.ffe_gpw) t.ffe_gpw = 8;
     if (!t.fft_log2 || !t.blocks_bc || !t.ffe_gpw || !t.dec_syms) {
@@ -591,7 +593,7 @@ static int create_tuned(rx_format fmt, double baud, double fs, const rx_params *
     std::complex<double> c0 = 0.0;
     for (int i = 0; i < 65; i++) c0 += (double)hf[i] * std::exp(std::complex<double>(0.0, -2.0 * M_PI * J.r * (32 - i)));
     J.c0 = make_float2((float)c0.real(), (float)c0.imag());
-    const SharedTables *t = fd ? fd_tables(p.rolloff) : shared_tables(h->log2n, p.hilbert_taps);
+    const SharedTables *t = fd ? fd_tables(p.rolloff, true) : shared_tables(h->log2n, p.hilbert_taps);
     ok = t != nullptr;
     if (ok) {
       J.hspec = t->hspec;
@@ -616,11 +618,19 @@ static int create_tuned(rx_format fmt, double baud, double fs, const rx_params *
     J.y = A.get<float>(L);
     J.xr = A.get<float>(L);
     J.upart = A.get<uint32_t>(L / 16384 + 1);
-    J.part2 = A.get<double>(L / 4096 + 1);
+    J.part2 = A.get<double>(L / 1024 + 1);   // per 4096-sample tile, or per 1024-sample FD block pair
     J.gard = A.get<float2>(L / 512);
     J.delta = A.get<float>(2 * (L / 512));
     J.soft = A.get<float2>(L / 2);
     ok = J.y && J.xr && J.upart && J.part2 && J.gard && J.delta && J.soft;
+    if (ok && fd) {
+      const SharedTables *t = fd_tables(p.rolloff, false);
+      ok = t != nullptr;
+      if (ok) {
+        J.hspec = t->hspec;
+        J.twid = t->twid;
+      }
+    }
   }
   if (ok && !kk) {
     h->mlp = A.get<float>(rx_mlp_params());
@@ -784,7 +794,7 @@ static int enqueue(rx_handle const *hs, const void *const *bufs, const int64_t *
       if (st[k] == ST_KK_FRONT || st[k] == ST_KK_DEBUG || st[k] == ST_KK_VV)
         rx_launch_kk_stage(st[k], L, maxn, a->log2n, a->p.precision, s);
       else if (st[k] >= ST_PAM_SUM && st[k] <= ST_PAM_FARROW)
-        rx_launch_pam_stage(st[k], L, maxn, s);
+        rx_launch_pam_stage(st[k], L, maxn, a->log2n, s);
       else if (st[k] == ST_MLP_INFER || st[k] == ST_MLP_JUDGE)
         rx_launch_mlp_stage(st[k], L, maxn, s);
       else
@@ -1231,7 +1241,7 @@ int rx_train_mlp(rx_handle h, const void *const *dev_buffers, const size_t *n_sa
     L.n[0] = (int64_t)n_samples[i];
     L.count = 1;
     L.s0[0] = -1;   // an independent buffer
-    for (int st = ST_PAM_SUM; st <= ST_PAM_FARROW; st++) rx_launch_pam_stage(st, L, L.n[0], h->stream);
+    for (int st = ST_PAM_SUM; st <= ST_PAM_FARROW; st++) rx_launch_pam_stage(st, L, L.n[0], h->log2n, h->stream);
     rx_launch_eq_stage(ST_PREFIX, L, L.n[0], 0, h->p.ffe_taps, 0, h->tune, h->stream);
     rx_mlp_windows(L, X, T, row0, h->stream);
     row0 += L.n[0] / 2 - 2 * RX_GUARD;

@@ -246,3 +246,198 @@ void rx_launch_kkfd(const RxLaunch &L, int64_t maxn, hipStream_t s) {
   hipLaunchKernelGGL(kkfd_mean, dim3(1, cnt), dim3(256), 0, s, L);
   hipLaunchKernelGGL(kkfd_eq, dim3((unsigned)nb, cnt), dim3(FT), 0, s, L);
 }
+
+// ---- PAM (Sec. 2, first paragraph): the 503-tap static equaliser on the
+// 1024-point blocks and the clock recovery in the frequency domain.  Two
+// real blocks per complex transform again (A real, B imaginary).
+namespace {
+// Last pass of the forward transform: conj(Z H) with the real response H
+// (1/N folded in) into registers, the inverse's input.
+struct RealEqOut {
+  const float *hq;
+  float2 (&y)[16];
+  float w[16];
+  __device__ __forceinline__ void begin() {
+#pragma unroll
+    for (int i = 0; i < 16; i++) w[i] = gptr(hq)[threadIdx.x + i * FT];
+  }
+  __device__ __forceinline__ void operator()(int koff, int, float2 z) const {
+    const int i = koff / FT;
+    y[i] = make_float2(z.x * w[i], -z.y * w[i]);
+  }
+};
+// Last pass of the inverse: block sample k = threadIdx.x + i T of A and B.
+struct PairOut {
+  float (&a)[16];
+  float (&b)[16];
+  __device__ __forceinline__ void begin() {}
+  __device__ __forceinline__ void operator()(int koff, int, float2 v) const {
+    const int i = koff / FT;
+    a[i] = v.x;
+    b[i] = -v.y;
+  }
+};
+}   // namespace
+
+// y = the static equaliser's output at every central sample (written, before
+// the AGC gain), the power partial of the pair, and each block's Gardner
+// detector sums (the detector reads y up to 4 samples past the block, which
+// the transform's outputs cover: a 503-tap output is exact up to 251 samples
+// from the block's ends).
+__global__ __launch_bounds__(FT) void pamfd_eq(RxLaunch L) {
+  __shared__ float2 lds[FN + FN / 16];
+  const int jb = blockIdx.y;
+  const RxJob J = *L.job[jb];
+  const int64_t n = L.n[jb];
+  const int64_t b0 = 2 * (int64_t)blockIdx.x;
+  if (b0 * FHOP >= n) return;
+  const uint8_t *in = L.in[jb];
+  const int64_t F[2] = {b0 * FHOP - FGUARD, (b0 + 1) * FHOP - FGUARD};
+  const int j = threadIdx.x;
+  const float off = (float)(J.sc->mean_re - 0.5);   // x0 = code - (mean - 1/2)
+  {
+    float2 v[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+      const int64_t ta = F[0] + j + FT * r, tb = F[1] + j + FT * r;
+      v[r] = make_float2(ta >= 0 && ta < n ? (float)read_code(in, ta) - off : 0.0f,
+                         tb >= 0 && tb < n ? (float)read_code(in, tb) - off : 0.0f);
+    }
+    dft16(v);
+    const int p0 = fpad(16 * j);
+#pragma unroll
+    for (int r = 0; r < 16; r++) lds[p0 + r] = v[r];
+  }
+  __syncthreads();
+  {
+    float2 y[16];
+    fft_passes<FN, 16, false>(lds, J.twid, RealEqOut{J.hspec + FN, y, {}});
+    dft16(y);
+    __syncthreads();
+    const int p0 = fpad(16 * j);
+#pragma unroll
+    for (int r = 0; r < 16; r++) lds[p0 + r] = y[r];
+  }
+  __syncthreads();
+  float ya[16], yb[16];
+  fft_passes<FN, 16, false>(lds, J.twid, PairOut{ya, yb});
+  __syncthreads();
+  // y of block samples 192 .. 831 of both blocks into LDS (zero outside the
+  // buffer, as the detector takes it), the central ones to HBM
+  float *ys = reinterpret_cast<float *>(lds);
+  constexpr int YLO = 3 * FT, YN = 10 * FT;
+  float p2 = 0.0f;
+#pragma unroll
+  for (int x = 0; x < 2; x++) {
+#pragma unroll
+    for (int i = 3; i < 13; i++) {
+      const int64_t t = F[x] + j + FT * i;
+      const float yv = (t >= 0 && t < n) ? (x ? yb[i] : ya[i]) : 0.0f;
+      ys[x * YN + j + FT * i - YLO] = yv;
+      if (i >= FGUARD / FT && i < (FGUARD + FHOP) / FT && t < n) {
+        gptr(J.y)[t] = yv;
+        p2 = fmaf(yv, yv, p2);
+      }
+    }
+  }
+  __syncthreads();
+  // Gardner sums of each block: its 256 symbols, 4 per lane; symbol sample
+  // s = 2 k sits at block sample 2 k - 512 b + 256
+#pragma unroll
+  for (int x = 0; x < 2; x++) {
+    float g0 = 0.0f, g1 = 0.0f;
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      const int s = x * YN + FGUARD + 2 * (4 * j + e) - YLO;
+      const float ym = ys[s - 1], y0 = ys[s], y1 = ys[s + 1], y2 = ys[s + 2], y3 = ys[s + 3], y4 = ys[s + 4];
+      g0 += y1 * (y0 - y2);
+      const float h0 = (-ym + 9.0f * y0 + 9.0f * y1 - y2) * 0.0625f;
+      const float h1 = (-y0 + 9.0f * y1 + 9.0f * y2 - y3) * 0.0625f;
+      const float h2 = (-y1 + 9.0f * y2 + 9.0f * y3 - y4) * 0.0625f;
+      g1 += h1 * (h0 - h2);
+    }
+    g0 = wave_sum(g0);
+    g1 = wave_sum(g1);
+    if (threadIdx.x == 0 && (b0 + x) * FHOP < n) J.gard[b0 + x] = make_float2(g0, g1);
+  }
+  const float ps = wave_sum(p2);
+  if (threadIdx.x == 0) J.part2[blockIdx.x] = (double)ps;
+}
+
+// xr = g y(t + delta_b) for the central samples of block b: the pair's
+// spectrum Z = A + j B is split into the two blocks' spectra, A[k] =
+// (Z[k] + conj Z[N-k]) / 2 and B[k] = (Z[k] - conj Z[N-k]) / 2j, each takes
+// its own block's delay exp(+j 2 pi k delta / N) (signed k; cos(pi delta)
+// at N/2, so both stay real), and A' + j B' goes back.
+__global__ __launch_bounds__(FT) void pamfd_clock(RxLaunch L) {
+  __shared__ float2 lds[FN + FN / 16];
+  const int jb = blockIdx.y;
+  const RxJob J = *L.job[jb];
+  const int64_t n = L.n[jb];
+  const int64_t b0 = 2 * (int64_t)blockIdx.x;
+  if (b0 * FHOP >= n) return;
+  const int64_t F[2] = {b0 * FHOP - FGUARD, (b0 + 1) * FHOP - FGUARD};
+  const int j = threadIdx.x;
+  const auto yin = gptr(J.y);
+  {
+    float2 v[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+      const int64_t ta = F[0] + j + FT * r, tb = F[1] + j + FT * r;
+      v[r] = make_float2(ta >= 0 && ta < n ? yin[ta] : 0.0f, tb >= 0 && tb < n ? yin[tb] : 0.0f);
+    }
+    dft16(v);
+    const int p0 = fpad(16 * j);
+#pragma unroll
+    for (int r = 0; r < 16; r++) lds[p0 + r] = v[r];
+  }
+  __syncthreads();
+  fft_passes<FN, 16, true>(lds, J.twid, LdsOut{lds});   // Z in natural order
+  const float da = J.delta[b0], db = (b0 + 1) * FHOP < n ? J.delta[b0 + 1] : 0.0f;
+  const float g = (float)J.sc->agc * (1.0f / FN);
+  float2 w[16];
+#pragma unroll
+  for (int i = 0; i < 16; i++) {
+    const int k = j + FT * i;
+    const float2 zk = lds[fpad(k)], zm = lds[fpad((FN - k) & (FN - 1))];
+    const float2 a = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));   // A[k]
+    const float2 bb = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));  // B[k]
+    float2 ra, rb;
+    if (k == FN / 2) {
+      ra = make_float2(__builtin_amdgcn_cosf(0.5f * da), 0.0f);
+      rb = make_float2(__builtin_amdgcn_cosf(0.5f * db), 0.0f);
+    } else {
+      const float ks = (float)(k < FN / 2 ? k : k - FN) * (1.0f / FN);
+      ra = cis_rev(ks * da);
+      rb = cis_rev(ks * db);
+    }
+    const float2 pa = cmul(a, ra), pb = cmul(bb, rb);
+    // W = A' + j B', conjugated (the inverse runs forward) and scaled by g / N
+    w[i] = make_float2(g * (pa.x - pb.y), -g * (pa.y + pb.x));
+  }
+  dft16(w);   // the inverse's first pass: its inputs j + r T are this lane's bins
+  __syncthreads();
+  {
+    const int p0 = fpad(16 * j);
+#pragma unroll
+    for (int r = 0; r < 16; r++) lds[p0 + r] = w[r];
+  }
+  __syncthreads();
+  float xa[16], xb[16];
+  fft_passes<FN, 16, false>(lds, J.twid, PairOut{xa, xb});
+#pragma unroll
+  for (int x = 0; x < 2; x++) {
+#pragma unroll
+    for (int i = FGUARD / FT; i < (FGUARD + FHOP) / FT; i++) {
+      const int64_t t = F[x] + j + FT * i;
+      if (t < n) gptr(J.xr)[t] = x ? xb[i] : xa[i];
+    }
+  }
+}
+
+void rx_launch_pamfd(int stage, const RxLaunch &L, int64_t maxn, hipStream_t s) {
+  const unsigned cnt = (unsigned)L.count;
+  const int64_t npair = (maxn + 2 * FHOP - 1) / (2 * FHOP);
+  if (stage == ST_PAM_MF) hipLaunchKernelGGL(pamfd_eq, dim3((unsigned)npair, cnt), dim3(FT), 0, s, L);
+  else hipLaunchKernelGGL(pamfd_clock, dim3((unsigned)npair, cnt), dim3(FT), 0, s, L);
+}

@@ -232,7 +232,10 @@ __global__ __launch_bounds__(1024) void pam_unwrap(RxLaunch L) {
   const float *raw = J.delta + nb;
   const bool cont = J.stream && L.s0[jb] >= 0;
   if (!cont) {
-    const int64_t np = (n + PAM_TS - 1) / PAM_TS;
+    // power partials: one per matched-filter tile, or per pair of
+    // 512-sample blocks from the frequency-domain equaliser
+    const int64_t pt = J.fft_log2 == RX_KK_FD_LOG2 ? 1024 : PAM_TS;
+    const int64_t np = (n + pt - 1) / pt;
     double p = 0.0;
     for (int64_t i = threadIdx.x; i < np; i += 1024) p += J.part2[i];
     p = block_sum(p, red);
@@ -344,8 +347,12 @@ __global__ __launch_bounds__(256) void pam_farrow(RxLaunch L) {
   }
 }
 
-void rx_launch_pam_stage(int stage, const RxLaunch &L, int64_t maxn, hipStream_t s) {
+void rx_launch_pam_stage(int stage, const RxLaunch &L, int64_t maxn, int log2n, hipStream_t s) {
   const unsigned cnt = (unsigned)L.count;
+  if (log2n == RX_KK_FD_LOG2 && (stage == ST_PAM_MF || stage == ST_PAM_FARROW)) {
+    rx_launch_pamfd(stage, L, maxn, s);
+    return;
+  }
   const int64_t nb = maxn / 512;
   switch (stage) {
     case ST_PAM_SUM:

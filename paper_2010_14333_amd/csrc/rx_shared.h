@@ -134,7 +134,10 @@ void rx_launch_kk_stage(int stage, const RxLaunch &L, int64_t maxn, int log2n, i
 // the paper's frequency-domain KK front end (jobs with fft_log2 == RX_KK_FD_LOG2)
 #define RX_KK_FD_LOG2 10
 void rx_launch_kkfd(const RxLaunch &L, int64_t maxn, hipStream_t s);
-void rx_launch_pam_stage(int stage, const RxLaunch &L, int64_t maxn, hipStream_t s);
+// the paper's frequency-domain PAM static equaliser (stage ST_PAM_MF) and
+// clock recovery (ST_PAM_FARROW), for jobs with fft_log2 == RX_KK_FD_LOG2
+void rx_launch_pamfd(int stage, const RxLaunch &L, int64_t maxn, hipStream_t s);
+void rx_launch_pam_stage(int stage, const RxLaunch &L, int64_t maxn, int log2n, hipStream_t s);
 void rx_launch_eq_stage(int stage, const RxLaunch &L, int64_t maxn, int kk, int ffe_taps, int prec, const RxTune &t,
                         hipStream_t s);
 void rx_launch_mlp_stage(int stage, const RxLaunch &L, int64_t maxn, hipStream_t s);

@@ -203,9 +203,11 @@ def test_invalid_sizes_rejected(rx):
         r.close()
 
 
-# The paper's own frequency-domain KK front end (1024-point blocks at hop
-# 512, block-circular Hilbert, 203-tap static equaliser, 512-point IFFT to 2
-# samples per symbol) against the oracle's, through the same chain after it.
+# The paper's own frequency-domain front ends against the oracle's, through
+# the same chain after them: KK (1024-point blocks at hop 512, block-circular
+# Hilbert, 203-tap static equaliser, 512-point IFFT to 2 samples per symbol)
+# and PAM (503-tap static equaliser on the blocks, clock recovery as a delay
+# on each block's spectrum).
 @pytest.mark.parametrize("fmt,n,seed,snr,gen", [
     (5, 1 << 18, 51, 22.0, {}),
     (5, 1 << 18, 52, 16.0, {}),
@@ -213,13 +215,19 @@ def test_invalid_sizes_rejected(rx):
     (4, 1 << 18, 54, None, {"theta_c": 2.0}),
     (5, (1 << 18) + 3 * 1024, 55, 22.0, {}),   # ragged
     (5, 17408, 56, 22.0, {}),                  # smallest KK buffer
+    (2, 1 << 18, 57, 20.0, {}),
+    (1, 1 << 18, 58, 16.0, {}),
+    (3, 1 << 18, 59, 24.0, {}),
+    (3, 1 << 18, 60, None, {"drive": 0.1}),
+    (2, (1 << 18) + 5 * 1024, 61, 20.0, {}),   # ragged
+    (2, 9216, 62, 20.0, {}),                   # smallest PAM buffer
 ])
 def test_parity_fd_front(rx, fmt, n, seed, snr, gen):
     check_chain(rx, fmt, n, seed, snr, rxo={"front": 1}, **gen)
 
 
 def test_fd_front_rejects_what_it_does_not_cover(rx):
-    for fmt, over in ((5, {"precision": 1}), (5, {"flags": 0x4}), (2, {})):
+    for fmt, over in ((5, {"precision": 1}), (5, {"flags": 0x4}), (2, {"flags": 0x4}), (3, {"equalizer": 1})):
         p = rx.rx_params_default(fmt)
         p.front = 1
         for k, v in over.items():
