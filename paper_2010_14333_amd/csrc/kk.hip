@@ -303,7 +303,11 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
   float se_re = 0.0f, se_im = 0.0f, zz = 0.0f;
   float2 sp = make_float2(0.0f, 0.0f), sedge = make_float2(0.0f, 0.0f);
   float tedge = 0.0f;
+  // interior outputs of the workgroup's two blocks (a count fixed by the
+  // geometry), and whether it has edge outputs (only the buffer's first and
+  // last workgroups): both workgroup-uniform
   int nint = 0;
+  bool edge_wg = false;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int row = lane & 15, kq = lane >> 4;
   constexpr int NW = T / 64;
@@ -399,6 +403,8 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
     const int mlim = (int)clamp64(n / 2 - m0, 0, HOP / 2);
     const int mil = (int)clamp64(16 - m0, 0, HOP / 2);
     const int mih = (int)clamp64((n - 32) / 2 - m0, 0, HOP / 2);
+    nint += mih > mil ? mih - mil : 0;
+    edge_wg = edge_wg || mil > 0 || mih < mlim;
     float2 *const zb = J.z + m0;
     for (int grp = wv; grp < NG; grp += NW) {
       const int tile = grp * 8 + (row >> 1);
@@ -415,7 +421,6 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
           zz = fmaf(zv.x, zv.x, fmaf(zv.y, zv.y, zz));
           if (mr >= mil && mr < mih) {
             sp = cadd(sp, cmul(zv, p));
-            nint++;
           } else {
             const float2 te = kk_carrier_edge_inl(J.mf, J.r, m0 + mr, n, g0);
             sedge = cadd(sedge, cmulc(zv, te));
@@ -428,14 +433,36 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
     __syncthreads();
   }
   if constexpr (FIELD) return;
-  double v[9] = {se_re, se_im, zz, tedge, (double)nint, sp.x, sp.y, sedge.x, sedge.y};
-  block_sum_n<9>(v, red);
-  if (threadIdx.x == 0) {
-    const double c0r = J.c0.x, c0i = J.c0.y;
-    J.part[3 * blockIdx.x] = make_double2(v[0], v[1]);                          // sum of the field E
-    J.part[3 * blockIdx.x + 1] = make_double2(v[2], v[3] + v[4] * (c0r * c0r + c0i * c0i));  // |Z|^2, |T|^2
-    J.part[3 * blockIdx.x + 2] = make_double2(c0r * v[5] + c0i * v[6] + v[7],    // sum Z conj(T)
-                                              c0r * v[6] - c0i * v[5] + v[8]);
+  // FP64 workgroup sums: each wavefront's (DPP), then lane k < 9 of the
+  // first wavefront adds variable k over the wavefronts in wavefront order
+  // and thread 0 collects them; only thread 0 needs them.  The edge sums
+  // are zero outside the edge workgroups, the interior count is nint.
+  double v[9] = {se_re, se_im, zz, tedge, 0.0, sp.x, sp.y, sedge.x, sedge.y};
+#pragma unroll
+  for (int k = 0; k < 9; k++) {
+    if (k == 4) continue;
+    if ((k == 3 || k == 7 || k == 8) && !edge_wg) continue;
+    v[k] = wave_sum(v[k]);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < 9; k++) red[k * NW + wv] = v[k];
+  }
+  __syncthreads();
+  if (wv == 0) {
+    double sk = 0.0;
+    if (lane < 9)
+      for (int i = 0; i < NW; i++) sk += red[lane * NW + i];
+#pragma unroll
+    for (int k = 0; k < 9; k++) v[k] = __shfl(sk, k);
+    v[4] = (double)nint;
+    if (lane == 0) {
+      const double c0r = J.c0.x, c0i = J.c0.y;
+      J.part[3 * blockIdx.x] = make_double2(v[0], v[1]);                          // sum of the field E
+      J.part[3 * blockIdx.x + 1] = make_double2(v[2], v[3] + v[4] * (c0r * c0r + c0i * c0i));  // |Z|^2, |T|^2
+      J.part[3 * blockIdx.x + 2] = make_double2(c0r * v[5] + c0i * v[6] + v[7],    // sum Z conj(T)
+                                                c0r * v[6] - c0i * v[5] + v[8]);
+    }
   }
 }
 
