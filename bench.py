@@ -103,8 +103,9 @@ def _gen(job):
     kind, a = job
     if kind == "kk":
         g = synth.kk_2e22(synth.KK_16QAM, index=a)
-    elif kind == "kk24":
-        g = synth.generate(synth.KK_16QAM, 1 << 24, synth.derive_seed(401, 0), 22.0)
+    elif kind == "kk24":   # the precision workload at its SNR (22 dB) and at 16 dB (BER near 1e-3)
+        g = synth.generate(synth.KK_16QAM, 1 << 24, synth.derive_seed(401, 0 if a == 22.0 else 1), a)
+        g["snr_db"] = a
     elif kind == "mixed":
         i, fmt, snr = a
         g = synth.generate(fmt, N, synth.derive_seed(301, i), snr)
@@ -117,7 +118,8 @@ def _gen(job):
         g = synth.generate(synth.KK_16QAM, 4096000, synth.derive_seed(801, 0), 22.0)
     else:
         raise ValueError(kind)
-    return {"fmt": g["fmt"], "seed": g["seed"], "n": g["n_samples"], "packed": g["packed"]}
+    return {"fmt": g["fmt"], "seed": g["seed"], "n": g["n_samples"], "packed": g["packed"],
+            "snr_db": g.get("snr_db")}
 
 
 def _oracle_kk(item):
@@ -165,7 +167,7 @@ def main():
                     help="forms timed beside the plain chain: bf16, fp16 (precision forms), fd (the paper's "
                          "frequency-domain front end)")
     ap.add_argument("--precision-check", type=int, default=1,
-                    help="2^24-sample KK-16QAM buffer through FP32/BF16/FP16 against the FP64 oracle")
+                    help="2^24-sample KK-16QAM buffers (22 and 16 dB) through FP32/BF16/FP16 against the FP64 oracle")
     ap.add_argument("--mlp", type=int, default=1, help="train and time the PAM-8 learned-equaliser form")
     ap.add_argument("--mixed", type=int, default=1, help="time a 64-buffer mixed-format batch (graph replay)")
     ap.add_argument("--latency", type=int, default=1, help="per-buffer latency of small batches on one stream")
@@ -197,7 +199,7 @@ def main():
     if a.mlp:
         jobs += [("pam8", (501, i)) for i in range(4)] + [("pam8", (502, i)) for i in range(8)]
     if a.precision_check:
-        jobs += [("kk24", 0)]
+        jobs += [("kk24", 22.0), ("kk24", 16.0)]
     if a.soak:
         jobs += [("soak", 0)]
     cores = usable_cores()
@@ -387,40 +389,52 @@ def main():
 
     precision = None
     if a.precision_check and big:
-        # 2^24-sample KK-16QAM buffer: each dtype's soft values and BER against
-        # the FP64 oracle (the same frozen-tap definition, unrounded and with
-        # the precision form's rounding), the FP32 field against FP64
+        # 2^24-sample KK-16QAM buffers at 22 dB (the workload) and 16 dB (a
+        # BER near 1e-3, so the BERs are paired over thousands of errors):
+        # each dtype's soft values and BER against the FP64 oracle (the same
+        # frozen-tap definition, unrounded and with the precision form's
+        # rounding), the FP32 field against FP64
         import oracle
         sys.path.insert(0, os.path.join(ROOT, "tests"))
         import parity
-        gb = big[0]
-        nb = gb["n"]
-        d = torch.from_numpy(gb["packed"]).to(dev)
-        o_plain = oracle.process(5, gb["packed"], nb, gb["seed"], want=("field",))
-        o_frozen = oracle.process(5, gb["packed"], nb, gb["seed"], want=("soft",), form=1, rounding=0)
-        precision = {"workload": "KK-16QAM, one 2^24-sample buffer (1 GBaud, CSPR 10 dB, 22 dB SNR)"}
-        r = rx.Receiver(5, gb["seed"], max_samples=nb, debug=True)
-        r.process(d, nb)
-        field = r.fetch(rx.RX_STAGE_FIELD, nb)
-        e = r.errors()
-        r.close()
-        precision["fp32"] = {"field_rel_rms_vs_fp64": parity.rel_rms(field, o_plain["field"]),
-                             "ber": e["bit_errors"] / e["bits"], "ber_fp64": o_plain["bit_errors"] / o_plain["counted_bits"]}
-        for name, prec in (("bf16", rx.RX_BF16), ("fp16", rx.RX_FP16)):
-            o_r = oracle.process(5, gb["packed"], nb, gb["seed"], want=("soft",), form=1, rounding=prec)
-            r = rx.Receiver(5, gb["seed"], max_samples=nb, debug=True, precision=prec)
+
+        def check(gb):
+            nb = gb["n"]
+            d = torch.from_numpy(gb["packed"]).to(dev)
+            o_plain = oracle.process(5, gb["packed"], nb, gb["seed"], want=("field",))
+            o_frozen = oracle.process(5, gb["packed"], nb, gb["seed"], want=("soft",), form=1, rounding=0)
+            res = {"workload": f"KK-16QAM, one 2^24-sample buffer (1 GBaud, CSPR 10 dB, {gb['snr_db']:g} dB SNR)"}
+            r = rx.Receiver(5, gb["seed"], max_samples=nb, debug=True)
             r.process(d, nb)
-            soft = r.fetch(rx.RX_STAGE_SOFT, nb)
+            field = r.fetch(rx.RX_STAGE_FIELD, nb)
             e = r.errors()
             r.close()
-            precision[name] = {
-                "soft_rel_rms_vs_fp64": parity.rel_rms(soft, o_frozen["soft"]),
-                "oracle_rounded_soft_rel_rms_vs_fp64": parity.rel_rms(o_r["soft"], o_frozen["soft"]),
-                "soft_rel_rms_vs_oracle_rounded": parity.rel_rms(soft, o_r["soft"]),
-                "ber": e["bit_errors"] / e["bits"], "ber_fp64_frozen": o_frozen["bit_errors"] / o_frozen["counted_bits"],
-                "ber_oracle_rounded": o_r["bit_errors"] / o_r["counted_bits"],
-                "delta_ber_vs_fp64_frozen": e["bit_errors"] / e["bits"] - o_frozen["bit_errors"] / o_frozen["counted_bits"]}
-        del d
+            res["fp32"] = {"field_rel_rms_vs_fp64": parity.rel_rms(field, o_plain["field"]),
+                           "ber": e["bit_errors"] / e["bits"], "bit_errors": e["bit_errors"],
+                           "ber_fp64": o_plain["bit_errors"] / o_plain["counted_bits"],
+                           "bit_errors_fp64": o_plain["bit_errors"]}
+            for name, prec in (("bf16", rx.RX_BF16), ("fp16", rx.RX_FP16)):
+                o_r = oracle.process(5, gb["packed"], nb, gb["seed"], want=("soft",), form=1, rounding=prec)
+                r = rx.Receiver(5, gb["seed"], max_samples=nb, debug=True, precision=prec)
+                r.process(d, nb)
+                soft = r.fetch(rx.RX_STAGE_SOFT, nb)
+                e = r.errors()
+                r.close()
+                res[name] = {
+                    "soft_rel_rms_vs_fp64": parity.rel_rms(soft, o_frozen["soft"]),
+                    "oracle_rounded_soft_rel_rms_vs_fp64": parity.rel_rms(o_r["soft"], o_frozen["soft"]),
+                    "soft_rel_rms_vs_oracle_rounded": parity.rel_rms(soft, o_r["soft"]),
+                    "ber": e["bit_errors"] / e["bits"], "bit_errors": e["bit_errors"],
+                    "ber_fp64_frozen": o_frozen["bit_errors"] / o_frozen["counted_bits"],
+                    "bit_errors_fp64_frozen": o_frozen["bit_errors"],
+                    "ber_oracle_rounded": o_r["bit_errors"] / o_r["counted_bits"],
+                    "delta_ber_vs_fp64_frozen": e["bit_errors"] / e["bits"] - o_frozen["bit_errors"] / o_frozen["counted_bits"]}
+            del d
+            return res
+
+        precision = check(big[0])
+        if len(big) > 1:
+            precision["at_16db"] = check(big[1])
         log(f"[bench] precision check {precision}")
 
     q_sweep = q_osnr = None

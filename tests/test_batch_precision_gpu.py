@@ -24,12 +24,16 @@ def _dev(a):
     return torch.from_numpy(a).to("cuda:0")
 
 
-def test_mixed_batch_equals_single_buffers_and_graph_replays(rx):
+@pytest.mark.parametrize("fronts", [(0, 0, 0, 0, 0, 0), (1, 1, 0, 0, 1, 0)], ids=["os", "fd_and_os"])
+def test_mixed_batch_equals_single_buffers_and_graph_replays(rx, fronts):
+    """fronts: per buffer, the time-domain front end (0) or the paper's
+    frequency-domain one (1); a batch mixing them launches each group's
+    kernels separately and must equal the buffers processed alone."""
     import torch
     n = 1 << 18
     fmts = [5, 1, 4, 3, 2, 5]
     gens = [synth.generate(f, n, 700 + i, 18.0 + i) for i, f in enumerate(fmts)]
-    recs = [rx.Receiver(f, g["seed"], max_samples=n) for f, g in zip(fmts, gens)]
+    recs = [rx.Receiver(f, g["seed"], max_samples=n, front=fr) for f, g, fr in zip(fmts, gens, fronts)]
     bufs = [_dev(g["packed"]) for g in gens]
     single = [r.process(b, n).cpu().numpy() for r, b in zip(recs, bufs)]
     torch.cuda.synchronize()
@@ -54,10 +58,11 @@ def test_mixed_batch_equals_single_buffers_and_graph_replays(rx):
         assert e5["buffers"] == 5 * e["buffers"] and e5["bit_errors"] == 5 * e["bit_errors"]
     # one buffer of the batch against the oracle
     want = ("bits", "soft", "ddz")
-    o = oracle.process(fmts[0], gens[0]["packed"], n, gens[0]["seed"], want=want)
+    o = oracle.process(fmts[0], gens[0]["packed"], n, gens[0]["seed"], want=want, front=fronts[0])
     dec = parity.compare_decisions(
         fmts[0], single[0], o, n // 4, 128,
-        rerun=lambda f: oracle.process(fmts[0], gens[0]["packed"], n, gens[0]["seed"], want=want, force=f))
+        rerun=lambda f: oracle.process(fmts[0], gens[0]["packed"], n, gens[0]["seed"], want=want, force=f,
+                                       front=fronts[0]))
     assert not dec.untolerated
     for r in recs:
         r.close()
