@@ -33,7 +33,8 @@ class Cfg(ctypes.Structure):
                 ("front", ctypes.c_int32), ("rolloff", ctypes.c_double), ("mu", ctypes.c_double),
                 ("mu_cma", ctypes.c_double), ("fc_over_fs", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("mlp", _dp), ("force", ctypes.POINTER(ctypes.c_int32)),
-                ("frozen", ctypes.POINTER(Out)), ("count_end", ctypes.c_int64)]
+                ("frozen", ctypes.POINTER(Out)), ("count_end", ctypes.c_int64),
+                ("dd_phase", ctypes.c_int32), ("pad2", ctypes.c_int32)]
 
 
 Out._fields_ = [("field", _dp), ("shifted", _dp), ("mf", _dp), ("timing", _dp), ("xr", _dp),
@@ -115,7 +116,7 @@ def default_cfg(fmt, seed, **kw) -> dict:
     d = dict(fmt=fmt, mf_taps=65 if kk else 33, ffe_taps=21 if kk else 15, prefix=4096,
              hilbert_taps=4097, os_log2=16, form=0, rounding=0, equalizer=0,
              front=0, rolloff=0.1, mu=1e-3, mu_cma=1e-3, fc_over_fs=0.55e9 / 4e9 if kk else 0.0,
-             seed=seed, mlp=None, force=None, frozen=None, count_end=0)
+             seed=seed, mlp=None, force=None, frozen=None, count_end=0, dd_phase=0, pad2=0)
     d.update(kw)
     return d
 

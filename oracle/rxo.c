@@ -711,7 +711,8 @@ int rxo_process(const rxo_cfg *cfg, const uint8_t *packed, int64_t n, rxo_out *o
   const int blk = kk ? 128 : 256;
   const int rm = cfg->rounding;
   const rxo_out *fz = cfg->frozen;
-  if (P + 2 * G >= nsym || K < 1 || K % 2 == 0 || cfg->mf_taps % 2 == 0) return -1;
+  if (P + 2 * G >= nsym || K < 1 || (K % 2 == 0 && K != 4) || cfg->mf_taps % 2 == 0) return -1;
+  if (cfg->dd_phase && !kk) return -1;
   if (cfg->equalizer == 1 && (kk || !cfg->mlp)) return -1;
   if (cfg->front == 1 && (rm || fz || cfg->equalizer == 1)) return -1;   /* the FD front end: FP64, one buffer, LMS */
 
@@ -904,8 +905,9 @@ int rxo_process(const rxo_cfg *cfg, const uint8_t *packed, int64_t n, rxo_out *o
   }
 
   /* --- KK: per-block Viterbi-Viterbi phase over blocks b-1..b+1, unwrapped
-   *     in multiples of pi/2, then derotation --- */
-  if (kk) {
+   *     in multiples of pi/2, then derotation (unless the DD-LMS taps carry
+   *     the phase) --- */
+  if (kk && !cfg->dd_phase) {
     int64_t nb = nsym / blk;
     cplx *s4 = (cplx *)malloc(sizeof(cplx) * (size_t)nb);
     double *th = (double *)malloc(sizeof(double) * (size_t)nb);

@@ -22,7 +22,8 @@ enum { RXO_PAM2 = 1, RXO_PAM4, RXO_PAM8, RXO_KK_QPSK, RXO_KK_16QAM };
 typedef struct {
   int32_t fmt;           /* RXO_* */
   int32_t mf_taps;       /* matched RRC length: 33 (PAM, 2 sps) / 65 (KK, 4 sps) */
-  int32_t ffe_taps;      /* T/2-spaced FFE length: 15 (PAM) / 21 (KK) */
+  int32_t ffe_taps;      /* T/2-spaced FFE length: 15 (PAM) / 21 (KK), or 4 (the paper's KK
+                            DD-LMS); tap i multiplies x[2k + (K - 1) / 2 - i] (integer division) */
   int32_t prefix;        /* known training/sync symbols at the buffer start */
   int32_t hilbert_taps;  /* odd: V+1 */
   int32_t os_log2;       /* FFT size of the oracle's own overlap-save (any >= log2(2V)) */
@@ -46,6 +47,10 @@ typedef struct {
                             first buffer): its means, AGC gain, static phase, delay, rotation,
                             prefix taps and MLP fallback are used instead of being computed */
   int64_t count_end;     /* error counting stops before this symbol (0: n_sym - 64) */
+  int32_t dd_phase;      /* KK: 0, Viterbi-Viterbi carrier phase per block after the DD-LMS; 1, none:
+                            the DD-LMS taps track the phase (the paper's short DD-LMS doing clock-
+                            and symbol-phase recovery, Sec. 2 second paragraph) */
+  int32_t pad2;
 } rxo_cfg;
 
 /* Optional outputs: any pointer may be NULL. */

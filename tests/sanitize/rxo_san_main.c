@@ -126,6 +126,10 @@ int main(int argc, char **argv) {
     cfg.frozen = NULL;
     cfg.force = NULL;
     cfg.count_end = 0;
+    if (kk) {   /* with the paper's 4-tap DD-LMS carrying the phase */
+      cfg.ffe_taps = 4;
+      cfg.dd_phase = 1;
+    }
     if (rxo_process(&cfg, packed, n, &o3) != 0) { fprintf(stderr, "rejected (FD front end)\n"); return 3; }
     free(o3.bits); free(o3.mf); free(o3.xr); free(o3.timing);
   }

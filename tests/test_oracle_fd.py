@@ -226,3 +226,46 @@ def test_pam_fd_chain_agrees_with_the_time_domain_chain():
     fd = oracle.process(3, g["packed"], 1 << 18, g["seed"], want=("bits",), front=1)
     td = oracle.process(3, g["packed"], 1 << 18, g["seed"], want=("bits",))
     assert abs(fd["bit_errors"] - td["bit_errors"]) < 0.1 * td["bit_errors"]
+
+
+# ---- the paper's short KK DD-LMS (Sec. 2, second paragraph: a 4-tap
+# decision-directed LMS equaliser doing clock- and symbol-phase recovery):
+# 4 T/2-spaced taps, the carrier phase carried by the taps (no
+# Viterbi-Viterbi stage) ----
+def test_four_tap_ffe_alignment():
+    """An even tap count keeps the centring c = (K - 1) / 2 = 1: tap i
+    multiplies x[2k + 1 - i], so a unit tap 1 passes the symbol sample and a
+    unit tap 0 the sample after it."""
+    rng = np.random.default_rng(9)
+    x = rng.normal(size=400) + 1j * rng.normal(size=400)
+    for tap, off in ((1, 0), (0, 1), (2, -1), (3, -2)):
+        w = np.zeros(4, complex)
+        w[tap] = 1.0
+        _, z = oracle.lms(x, w, 10, 100, mu=0.0)
+        assert np.allclose(z, x[10 + 2 * np.arange(100) + off])
+
+
+@pytest.mark.parametrize("theta", [0.0, 1.0, 2.2, -2.0])
+def test_four_tap_dd_phase_chain_is_error_free_for_every_quadrant(theta):
+    """Noiseless KK-16QAM through the paper's front end and its 4-tap
+    DD-LMS without a separate phase stage: the prefix acquisition (CMA,
+    static phase, quadrant) and the taps carry any carrier phase."""
+    g = synth.generate(5, 1 << 18, seed=90, snr_db=None, theta_c=theta)
+    r = oracle.process(5, g["packed"], 1 << 18, g["seed"], want=("bits",), front=1, ffe_taps=4, dd_phase=1)
+    assert r["counted_bits"] > 200000 and r["bit_errors"] == 0
+
+
+def test_four_tap_dd_phase_chain_at_22_db():
+    for fmt in (4, 5):
+        g = synth.generate(fmt, 1 << 18, seed=91 + fmt, snr_db=22.0)
+        r = oracle.process(fmt, g["packed"], 1 << 18, g["seed"], want=("bits",), front=1, ffe_taps=4, dd_phase=1)
+        assert r["bit_errors"] <= 2, r["bit_errors"]
+
+
+def test_dd_phase_and_even_taps_are_limited_to_what_is_defined():
+    g = synth.generate(2, 1 << 16, seed=95, snr_db=20.0)
+    with pytest.raises(ValueError):
+        oracle.process(2, g["packed"], 1 << 16, g["seed"], dd_phase=1)
+    g = synth.generate(5, 1 << 16, seed=96, snr_db=20.0)
+    with pytest.raises(ValueError):
+        oracle.process(5, g["packed"], 1 << 16, g["seed"], ffe_taps=6)
