@@ -163,9 +163,10 @@ def main():
     ap.add_argument("--roof-steps", type=int, default=5)
     ap.add_argument("--cpu-buffers", type=int, default=4, help="oracle buffers per host core (0: no CPU baseline)")
     ap.add_argument("--copy-probe", type=int, default=1, help="run a 256 MiB device copy (counter scale)")
-    ap.add_argument("--forms", default="bf16,fp16,fd",
+    ap.add_argument("--forms", default="bf16,fp16,fd,paper",
                     help="forms timed beside the plain chain: bf16, fp16 (precision forms), fd (the paper's "
-                         "frequency-domain front end)")
+                         "frequency-domain front end), paper (that front end with the paper's 4-tap DD-LMS "
+                         "carrying the carrier phase)")
     ap.add_argument("--precision-check", type=int, default=1,
                     help="2^24-sample KK-16QAM buffers (22 and 16 dB) through FP32/BF16/FP16 against the FP64 oracle")
     ap.add_argument("--mlp", type=int, default=1, help="train and time the PAM-8 learned-equaliser form")
@@ -250,7 +251,7 @@ def main():
     def seed_of(i):
         return gens[i % a.distinct]["seed"]
 
-    def run_kk(precision, nstreams, steps, profile=False, front=0):
+    def run_kk(precision, nstreams, steps, profile=False, front=0, taps=21, dd_phase=False):
         """`steps` batches of the KK-16QAM chain, consecutive batches
         alternating over `nstreams` streams (one set of handles each);
         with `profile`, HIP events on the first handle of each set time
@@ -259,7 +260,8 @@ def main():
         for st in streams[:nstreams]:
             recs = [rx.Receiver(rx.RX_KK_16QAM, seed_of(i), max_samples=N, stream=st,
                                 flags=rx.RX_PROFILE if (i == 0 and profile) else 0,
-                                precision=precision, fft_log2=0 if front else a.fft_log2, front=front)
+                                precision=precision, fft_log2=0 if front else a.fft_log2, front=front,
+                                ffe_taps=taps, dd_phase=dd_phase)
                     for i in range(a.batch)]
             outs = [torch.empty(r.bits_bytes(N), dtype=torch.uint8, device=dev) for r in recs]
             sets.append((recs, outs, [r.h for r in recs], [o.data_ptr() for o in outs]))
@@ -315,12 +317,14 @@ def main():
 
     forms = {}
     for name in [f for f in a.forms.split(",") if f]:
-        prec, front = {"bf16": (rx.RX_BF16, 0), "fp16": (rx.RX_FP16, 0), "fd": (rx.RX_FP32, rx.RX_FRONT_FD)}[name]
-        w2, _, b2 = run_kk(prec, a.streams, a.steps, front=front)
+        prec, front, taps, ddp = {"bf16": (rx.RX_BF16, 0, 21, False), "fp16": (rx.RX_FP16, 0, 21, False),
+                                  "fd": (rx.RX_FP32, rx.RX_FRONT_FD, 21, False),
+                                  "paper": (rx.RX_FP32, rx.RX_FRONT_FD, 4, True)}[name]
+        w2, _, b2 = run_kk(prec, a.streams, a.steps, front=front, taps=taps, dd_phase=ddp)
         forms[name] = {"value": round(samples / (w2 / a.steps) / 1e9, 3), "unit": "Gsamples/s",
                        "ms_per_step": round(w2 * 1e3 / a.steps, 4), "ber": b2}
         if a.roofline:
-            _, st1, _ = run_kk(prec, 1, a.roof_steps, profile=True, front=front)
+            _, st1, _ = run_kk(prec, 1, a.roof_steps, profile=True, front=front, taps=taps, dd_phase=ddp)
             forms[name]["one_stream_stage_us_per_buffer"] = per_buffer(st1)
         log(f"[bench] {name} form: {forms[name]['value']} Gs/s, BER {b2}")
 

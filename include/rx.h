@@ -80,6 +80,11 @@ enum {
 #define RX_PROFILE 0x2u      /* time every kernel stage with HIP events (see rx_stage_times) */
 #define RX_STREAM 0x4u       /* the handle's buffers are consecutive pieces of one continuous stream
                                 (see "Contiguous streams" below) */
+#define RX_DD_PHASE 0x8u     /* KK: no Viterbi-Viterbi carrier-phase stage; the block DD-LMS taps,
+                                started from the prefix acquisition, carry the carrier phase (the
+                                paper's short DD-LMS doing clock- and symbol-phase recovery, Sec. 2,
+                                second paragraph; with ffe_taps = 4 its 4-tap form).  PAM:
+                                RX_E_UNSUPPORTED */
 
 /* Kernel stages reported by rx_stage_times (index into its arrays). */
 enum {
@@ -103,8 +108,10 @@ typedef struct {
   uint32_t struct_size;     /* sizeof(rx_params), for ABI evolution */
   int32_t mf_taps;          /* matched RRC length: 33 (PAM, 2 sps), 65 (KK, 4 sps); odd, at most
                                33 (PAM) / 65 (KK); shorter filters are centred in those slots */
-  int32_t ffe_taps;         /* T/2-spaced FFE length: 15 (PAM), 21 (KK); 15 or 21 for either chain
-                               (the precision form: 21) */
+  int32_t ffe_taps;         /* T/2-spaced FFE length: 15 (PAM), 21 (KK); 15 or 21 for either chain,
+                               or 4 for KK (the paper's 4-tap DD-LMS; tap i multiplies sample
+                               2k + (K - 1) / 2 - i of symbol k, integer division); the precision
+                               form: 21 */
   int32_t prefix_symbols;   /* known training/sync symbols at each buffer start: 4096 */
   int32_t hilbert_taps;     /* KK Hilbert FIR length V+1: 4097 */
   int32_t fft_log2;         /* KK overlap-save FFT size: 0 = tuned, else 13 or 14 */

@@ -26,6 +26,7 @@ RX_DEBUG_KEEP = 0x1
 
 RX_PROFILE = 0x2
 RX_STREAM = 0x4
+RX_DD_PHASE = 0x8
 HOLD = {RX_PAM2: 12288, RX_PAM4: 12288, RX_PAM8: 12288, RX_KK_QPSK: 4096, RX_KK_16QAM: 4096}
 STAGES = ("kk_front", "kk_debug", "pam_sum", "pam_mf", "pam_gavg", "pam_unwrap", "pam_farrow",
           "prefix", "blocks", "kk_vv", "decide", "mlp_infer", "mlp_judge")
@@ -317,15 +318,17 @@ class Receiver:
     """One rx handle; buffers and bit outputs are torch uint8 device tensors."""
 
     def __init__(self, fmt: int, seed: int, max_samples: int = 1 << 22, debug: bool = False,
-                 stream=None, **overrides):
+                 stream=None, dd_phase: bool = False, **overrides):
         self.fmt = fmt
         self.baud, self.sps = FMT_RATE[fmt]
         p = rx_params_default(fmt)
         p.seed = seed
         p.max_samples = max_samples
-        p.flags = RX_DEBUG_KEEP if debug else 0
+        p.flags = (RX_DEBUG_KEEP if debug else 0) | (RX_DD_PHASE if dd_phase else 0)
         p.stream = stream.cuda_stream if stream is not None else None
         for k, v in overrides.items():
+            if not any(k == f[0] for f in rx_params._fields_):
+                raise TypeError(f"rx_params has no field {k!r}")
             setattr(p, k, v)
         self.params = p
         self.h = rx_create(fmt, self.baud, 4e9, p)

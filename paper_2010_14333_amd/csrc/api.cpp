@@ -476,7 +476,8 @@ static int create_tuned(rx_format fmt, double baud, double fs, const rx_params *
   const double sps = fs / baud;
   if (!(baud > 0) || !(fs > 0) || std::fabs(sps - (kk ? 4.0 : 2.0)) > 1e-9) return RX_E_UNSUPPORTED;
   if (p.mf_taps < 1 || p.mf_taps % 2 == 0 || p.mf_taps > (kk ? 65 : 33)) return RX_E_INVALID;
-  if (p.ffe_taps != 15 && p.ffe_taps != 21) return RX_E_UNSUPPORTED;
+  if (p.ffe_taps != 15 && p.ffe_taps != 21 && !(kk && p.ffe_taps == 4)) return RX_E_UNSUPPORTED;
+  if ((p.flags & RX_DD_PHASE) && !kk) return RX_E_UNSUPPORTED;
   if (p.prefix_symbols < 2048 || p.prefix_symbols > RX_PREFIX_MAX) return RX_E_INVALID;
   if (kk && (p.hilbert_taps < 3 || p.hilbert_taps > 4097 || p.hilbert_taps % 2 == 0)) return RX_E_INVALID;
   if (p.fft_log2 != 0 && p.fft_log2 != 13 && p.fft_log2 != 14) return RX_E_INVALID;
@@ -561,6 +562,7 @@ static int create_tuned(rx_format fmt, double baud, double fs, const rx_params *
   J.debug = (p.flags & RX_DEBUG_KEEP) ? 1 : 0;
   J.seed = p.seed;
   J.stream = stream ? 1 : 0;
+  J.dd_phase = (p.flags & RX_DD_PHASE) ? 1 : 0;
   J.hold = kk ? RX_KK_HOLD : RX_PAM_HOLD;
   J.look = J.hold;
   J.ref_period = p.ref_period;

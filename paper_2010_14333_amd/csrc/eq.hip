@@ -278,7 +278,9 @@ __global__ __launch_bounds__(256) void rx_blocks(RxLaunch L) {
   float2 w[C + 1];
 #pragma unroll
   for (int a = 0; a <= C; a++) w[a] = (2 * a + h < K) ? J.sc->w0[2 * a + h] : make_float2(0.0f, 0.0f);
-  const float umask = h == 0 ? 1.0f : 0.0f;
+  // lane h's last tap, 2 C + h, exists for lane 0 always and for lane 1 only
+  // with an even tap count (the paper's 4 taps)
+  const float umask = 2 * C + h < K ? 1.0f : 0.0f;
   T xe[C + 1 + BC];   // xe[j] = sample p0 - C + 2 j - h (+ 2 BC per chunk)
   const int64_t p0 = 2 * (b * blk + s);
   {
@@ -800,6 +802,7 @@ void rx_launch_eq_stage(int stage, const RxLaunch &L, int64_t maxn, int kk, int 
   do { if (t.blocks_bc == 4) RX_BLK(C, K, 4); else if (t.blocks_bc == 16) RX_BLK(C, K, 16); else RX_BLK(C, K, 8); } while (0)
     if (kk) {
       if (ffe_taps == 21) RX_BLK_BC(true, 21);
+      else if (ffe_taps == 4) RX_BLK_BC(true, 4);
       else RX_BLK_BC(true, 15);
     } else {
       if (ffe_taps == 21) RX_BLK_BC(false, 21);

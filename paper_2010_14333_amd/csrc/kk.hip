@@ -492,6 +492,10 @@ __global__ __launch_bounds__(1024) void kk_vv(RxLaunch L) {
   const int64_t n = L.n[jb];
   const int64_t nsym = n / 4;
   const int nb = (int)(nsym / J.blk);
+  if (J.dd_phase) {   // the DD-LMS taps carry the phase: no derotation
+    for (int b = threadIdx.x; b < nb; b += 1024) J.theta[b] = 0.0f;
+    return;
+  }
   const RxSpan sp = rx_span(J, n, L.s0[jb]);
   const bool cont = J.stream && L.s0[jb] >= 0;
   const int bs = cont ? (int)(sp.k_lo / J.blk) - 1 : 0;   // first block of the scan

@@ -60,6 +60,8 @@ struct RxJob {
   float2 *udbg;                     // KK debug: AGC'd carrier-free MF output [n/2] or null
   float *phi;                       // KK frequency-domain front end: phase (revolutions) [n]
   double2 *fdpart;                  // KK frequency-domain front end: field sums per block pair
+  int32_t dd_phase;                 // KK: the DD-LMS taps carry the carrier phase (no VV stage)
+  int32_t pad_dd;
   const float *mlp;                 // PAM learned equaliser parameters (FP32) or null
   const uint32_t *refw;             // reference bits of symbols 0 .. max_samples / sps - 1, packed as the output
   RxScalars *sc;

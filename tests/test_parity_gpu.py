@@ -45,7 +45,8 @@ def _log(msg):
 def run_gpu(rx, fmt, g, n, debug=True, **over):
     import torch
     dev = torch.device("cuda:0")
-    r = rx.Receiver(fmt, g["seed"], max_samples=max(n, 1 << 16), debug=debug, **over)
+    r = rx.Receiver(fmt, g["seed"], max_samples=max(n, 1 << 16), debug=debug,
+                    dd_phase=bool(over.pop("dd_phase", 0)), **over)
     buf = torch.from_numpy(g["packed"]).to(dev)
     bits = r.process(buf, n)
     torch.cuda.synchronize()
@@ -224,6 +225,20 @@ def test_invalid_sizes_rejected(rx):
 ])
 def test_parity_fd_front(rx, fmt, n, seed, snr, gen):
     check_chain(rx, fmt, n, seed, snr, rxo={"front": 1}, **gen)
+
+
+# The paper's KK chain as a whole: the frequency-domain front end and its
+# 4-tap DD-LMS carrying the carrier phase (no Viterbi-Viterbi stage); and the
+# 4-tap DD-LMS behind the overlap-save front end.
+@pytest.mark.parametrize("fmt,n,seed,snr,gen,front", [
+    (5, 1 << 18, 71, 22.0, {}, 1),
+    (5, 1 << 18, 72, 16.0, {}, 1),
+    (4, 1 << 18, 73, 20.0, {"theta_c": -2.0}, 1),
+    (5, (1 << 18) + 3 * 1024, 74, 22.0, {}, 1),
+    (5, 1 << 18, 75, 18.0, {}, 0),
+])
+def test_parity_paper_four_tap_dd_lms(rx, fmt, n, seed, snr, gen, front):
+    check_chain(rx, fmt, n, seed, snr, rxo={"front": front, "ffe_taps": 4, "dd_phase": 1}, **gen)
 
 
 def test_fd_front_rejects_what_it_does_not_cover(rx):
