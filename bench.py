@@ -608,9 +608,9 @@ def main():
             late += e["late_buffers"]
             lat.append(rx.rx_latencies(r.h, 20))
             r.reset()
-            ber = e["bit_errors"] / e["bits"] if e["bits"] else 0.0
-            bers.append(ber)
-            qs.append(20.0 * np.log10(np.sqrt(2.0) * erfcinv(2.0 * ber)) if 0 < ber < 0.5 else None)
+            ber_p = e["bit_errors"] / e["bits"] if e["bits"] else 0.0
+            bers.append(ber_p)
+            qs.append(20.0 * np.log10(np.sqrt(2.0) * erfcinv(2.0 * ber_p)) if 0 < ber_p < 0.5 else None)
         torch.cuda.synchronize()
         wall_s = time.perf_counter() - t1
         lat = np.concatenate(lat)
