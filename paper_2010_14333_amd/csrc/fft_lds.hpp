@@ -8,9 +8,20 @@
 #pragma once
 #include "rx_dev.hpp"
 
+// threadIdx.x as a value the compiler cannot treat as loop-invariant: in a
+// kernel that loops over work items, the per-thread addresses of each pass
+// are then formed inside the iteration instead of being hoisted out of the
+// loop and held in registers (or scratch) across all of it.
+__device__ __forceinline__ int tid_local() {
+  unsigned t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  __builtin_assume(t < 1024u);   // the range the compiler knew of threadIdx.x
+  return (int)t;
+}
+
 // LDS index with one float2 of padding every 16: stride-16 writes of the
 // first pass then spread over all banks.
-__device__ __forceinline__ int fpad(int p) { return p + (p >> 4); }
+__host__ __device__ constexpr int fpad(int p) { return p + (p >> 4); }
 
 __device__ __forceinline__ float2 mul_mj(float2 a) { return make_float2(a.y, -a.x); }  // -j * a
 
@@ -126,6 +137,7 @@ template <int N, int R, int NS, bool TAIL = true, class Out = LdsOut, int VPT = 
 __device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *__restrict__ tw, Out out) {
   constexpr int T = N / VPT;
   constexpr int NB = (N / R) / T;  // butterflies per thread
+  const int tx = tid_local();
   // twiddle table reads first: their latency overlaps the LDS reads and the
   // barrier.  They go through a global-memory view: as flat accesses they
   // would also count against the LDS wait counter, and the wait for this
@@ -135,28 +147,38 @@ __device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *__restr
     const GView2 tg = gview(tw);
 #pragma unroll
     for (int b = 0; b < NB; b++) {
-      const int j = threadIdx.x + b * T;
-      const int step = (j & (NS - 1)) * (N / (NS * R));
-      tw1[b] = tg[step];
-      tw2[b] = R > 2 ? tg[2 * step] : tw1[b];
-      tw4[b] = R > 4 ? tg[4 * step] : tw1[b];
-      tw8[b] = R > 8 ? tg[8 * step] : tw1[b];
+      const int j = tx + b * T;
+      const unsigned step = (unsigned)(j & (NS - 1)) * (N / (NS * R));
+      tw1[b] = tg.at(step);
+      tw2[b] = R > 2 ? tg.at(2 * step) : tw1[b];
+      tw4[b] = R > 4 ? tg.at(4 * step) : tw1[b];
+      tw8[b] = R > 8 ? tg.at(8 * step) : tw1[b];
     }
   }
   out.begin();
   float2 v[NB][R];
+  // N / R is a multiple of 16, so fpad(j + r N/R) = fpad(j) + fpad(r N/R):
+  // one address per butterfly, the rest immediate offsets
+  static_assert((N / R) % 16 == 0, "padded read offsets split");
+  // (the reads past 64 KiB of the first take a second base: the offset
+  // field of an LDS read holds 16 bits)
+  constexpr int RH = R / 2, OH = fpad(RH * (N / R));
 #pragma unroll
   for (int b = 0; b < NB; b++) {
-    const int j = threadIdx.x + b * T;
+    const int pj = fpad(tx + b * T);
+    int pj1 = pj + OH;
+    asm volatile("" : "+v"(pj1));   // kept as its own base, not refolded into pj
+    const float2 *b0 = buf + pj, *b1 = buf + pj1;
 #pragma unroll
-    for (int r = 0; r < R; r++) v[b][r] = buf[fpad(j + r * (N / R))];
+    for (int r = 0; r < R; r++)
+      v[b][r] = (r < RH || R < 8) ? b0[fpad(r * (N / R))] : b1[fpad(r * (N / R)) - OH];
   }
   // in the last pass (NS R = N) a butterfly writes back exactly the indices
   // it read, so no thread overwrites another's input: no barrier needed
   if constexpr (NS * R != N) __syncthreads();
 #pragma unroll
   for (int b = 0; b < NB; b++) {
-    const int j = threadIdx.x + b * T;
+    const int j = tx + b * T;
     const int k = j & (NS - 1);
     if constexpr (NS > 1) apply_twiddles<R, 1>(v[b], tw1[b], tw2[b], tw4[b], tw8[b]);
     dft_r<R>(v[b]);

@@ -18,6 +18,7 @@
 // FFT butterfly, its last-pass outputs of the first transform (times H) are
 // the inputs of its first butterfly of the second, and its last-pass
 // outputs of the second are the phases of the samples it handles next.
+#include <algorithm>
 #include <type_traits>
 
 #include "fft_lds.hpp"
@@ -34,8 +35,9 @@ template <int T> struct HilbertOut {
   float2 (&y)[16];
   float hs[16];
   __device__ __forceinline__ void begin() {
+    const int tx = tid_local();
 #pragma unroll
-    for (int i = 0; i < 16; i++) hs[i] = gptr(hspec)[threadIdx.x + i * T];
+    for (int i = 0; i < 16; i++) hs[i] = gload_u32(hspec, (unsigned)(tx + i * T));
   }
   __device__ __forceinline__ void operator()(int koff, int, float2 z) const {
     const int i = koff / T;
@@ -101,8 +103,9 @@ template <> struct MfB<0> {
   // bt[192 + 64 ks + lane]; filled once per workgroup by fill()
   const rx_f16x8 *bt;
   __device__ static void fill(rx_f16x8 *tab, const float *__restrict__ mf) {
-    if (threadIdx.x < 192) {
-      const int ks = threadIdx.x >> 6, lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
+    const int tx = tid_local();
+    if (tx < 192) {
+      const int ks = tx >> 6, lane = tx & 63, row = lane & 15, kq = lane >> 4;
       rx_f16x8 hv, lv;
 #pragma unroll
       for (int j = 0; j < 8; j++) {
@@ -112,11 +115,11 @@ template <> struct MfB<0> {
         hv[j] = hi;
         lv[j] = (_Float16)(h - (float)hi);
       }
-      tab[threadIdx.x] = hv;
-      tab[192 + threadIdx.x] = lv;
+      tab[tx] = hv;
+      tab[192 + tx] = lv;
     }
   }
-  __device__ void load(const rx_f16x8 *tab) { bt = tab + (threadIdx.x & 63); }
+  __device__ void load(const rx_f16x8 *tab) { bt = tab + (tid_local() & 63); }
   // yp: this lane's component plane of hi; its lo plane is `lo` elements on
   __device__ rx_f32x4 apply(const _Float16 *__restrict__ yp, int lo, int tile, int kq) const {
     rx_f32x4 c0 = {0.0f, 0.0f, 0.0f, 0.0f}, c1 = c0;
@@ -156,8 +159,39 @@ template <int PREC> struct MfB {
 // FIELD: the debug instantiation, which only writes the reconstructed field
 // E of the buffers that keep it (RX_DEBUG_KEEP) and does no filtering; the
 // production kernel never stores E, which keeps its registers free.
+//
+// Work items: item w = jb pmax + p is block pair p of launch entry jb (pairs
+// past the end of a shorter buffer are skipped).  The production kernel is
+// persistent: its grid is as many workgroups as the chip holds at once, each
+// takes item blockIdx.x and then one item at a time from a counter in the
+// scalars of launch entry 0, so a CU goes from one pair to the next without
+// a workgroup dispatch in between, and workgroups that start late (their CUs
+// busy with another stream's kernels) take fewer items.  The workgroup that
+// finds the queue empty last resets the counters for the next launch.  The
+// debug instantiation runs one workgroup per item.
+// A job description read through the constant address space (its loads stay
+// scalar even where the kernel has stored to global memory before them).
+__device__ __forceinline__ RxJob load_job_const(const RxJob *p) {
+  static_assert(sizeof(RxJob) % 4 == 0, "whole words");
+  typedef const __attribute__((address_space(4))) int cword;
+  const cword *src = (const cword *)p;
+  RxJob j;
+  int *dst = reinterpret_cast<int *>(&j);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(RxJob) / 4); i++) dst[i] = src[i];
+  return j;
+}
+
+// Hands out a workgroup's next item: thread 0 publishes it before a barrier
+// that every thread passes before reading the slot; the two parity slots keep
+// the write of the item after next clear of the reads of this one.
+template <bool FIELD>
+__device__ __forceinline__ void front_take_next(int *nxt, int it, RxScalars *q0) {
+  if (!FIELD && threadIdx.x == 0) nxt[it & 1] = (int)gridDim.x + (int)atomicAdd(&q0->kk_next, 1u);
+}
+
 template <int LOGN, int PREC, bool FIELD = false>
-__global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  // 4 waves/SIMD: one 2^14 or two 2^13 workgroups per CU
+__global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L, int pmax) {  // 4 waves/SIMD: one 2^14 or two 2^13 workgroups per CU
   constexpr int N = 1 << LOGN, T = N / 16;
   constexpr int HOP = (N - RX_KK_HALFV - RX_KK_EDGE - RX_KK_CMF) & ~15;
   constexpr int QN = HOP + 2 * RX_KK_CMF;   // y' samples each block needs
@@ -180,23 +214,35 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
   __shared__ double red[9 * (T / 64)];
   __shared__ float htab[128];   // matched-filter taps h[i] at i + 31, zero elsewhere
   __shared__ rx_f16x8 btab[PREC == 0 ? 384 : 1];   // the plain form's split tap operands
+  __shared__ int nxt[2];   // the workgroup's next item, by iteration parity
 
-  const int jb = blockIdx.y;
-  const RxJob J = *L.job[jb];
+  const int total = L.count * pmax;
+  RxScalars *const q0 = FIELD ? nullptr : L.job[0]->sc;
+  int it = 0;
+  for (int item = blockIdx.x; item < total; it++) {
+  const int jb = item / pmax;
+  const int64_t pidx = item - (int64_t)jb * pmax;   // block pair of the buffer
+  // the job description is never written by a kernel: read through the
+  // constant address space it stays in scalar registers, although the loop
+  // stores to global memory between its reads
+  const RxJob J = load_job_const(L.job[jb]);
   const int64_t n = L.n[jb];
   const uint8_t *in = L.in[jb];
   const int64_t g0 = L.s0[jb] > 0 ? L.s0[jb] : 0;   // stream index of sample 0 (downshift phase)
   const int64_t nrb = (n + HOP - 1) / HOP;
-  const int64_t blk[2] = {2 * (int64_t)blockIdx.x, 2 * (int64_t)blockIdx.x + 1};
-  if (blk[0] >= nrb || (FIELD && !J.field)) return;
+  const int64_t blk[2] = {2 * pidx, 2 * pidx + 1};
+  if (blk[0] >= nrb || (FIELD && !J.field)) {
+    front_take_next<FIELD>(nxt, it, q0);
+    __syncthreads();
+  } else {
   const int64_t F[2] = {blk[0] * HOP - RX_KK_EDGE, blk[1] * HOP - RX_KK_EDGE};
-  if (!FIELD && blockIdx.x == 0 && threadIdx.x == 0) J.sc->t_start = (unsigned long long)wall_clock64();   // buffer start
+  if (!FIELD && pidx == 0 && threadIdx.x == 0) J.sc->t_start = (unsigned long long)wall_clock64();   // buffer start
 
   if constexpr (PREC == 0) {
     MfB<0>::fill(btab, J.mf);
-  } else if (threadIdx.x < 128) {
-    const int i = (int)threadIdx.x - 31;
-    htab[threadIdx.x] = (i >= 0 && i <= 64) ? J.mf[i] : 0.0f;
+  } else if (tid_local() < 128) {
+    const int tx = tid_local(), i = tx - 31;
+    htab[tx] = (i >= 0 && i <= 64) ? J.mf[i] : 0.0f;
   }
 
   // 1. l - l_ref for both frames (l_ref: the frame's centre sample; the
@@ -213,12 +259,13 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
   const float lr0 = __builtin_amdgcn_logf((float)read_code(in, clamp64(F[0] + N / 2, 0, n - 1)) + 0.5f);
   const float lr1 = __builtin_amdgcn_logf((float)read_code(in, clamp64(F[1] + N / 2, 0, n - 1)) + 0.5f);
   {
+    const int tx = tid_local();
     int ca[16], cb[16];
     if (F[0] >= 0 && F[1] + N <= n) {
       // both frames inside the buffer: sample s0 + r T sits at byte
       // (3 s0 >> 1) + r (3 T / 2) (T is even), in the high 12 bits of its
       // 16-bit word when s0 is odd
-      const int64_t s0a = F[0] + threadIdx.x, s0b = F[1] + threadIdx.x;
+      const int64_t s0a = F[0] + tx, s0b = F[1] + tx;
       const uint8_t *pa = in + ((3 * s0a) >> 1), *pb = in + ((3 * s0b) >> 1);
       const int sha = (int)(s0a & 1) << 2, shb = (int)(s0b & 1) << 2;
 #pragma unroll
@@ -234,8 +281,8 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
     } else {   // a frame reaches past a buffer end: samples replicated from the edge
 #pragma unroll
       for (int r = 0; r < 16; r++) {
-        ca[r] = read_code(in, clamp64(F[0] + threadIdx.x + r * T, 0, n - 1));
-        cb[r] = read_code(in, clamp64(F[1] + threadIdx.x + r * T, 0, n - 1));
+        ca[r] = read_code(in, clamp64(F[0] + tx + r * T, 0, n - 1));
+        cb[r] = read_code(in, clamp64(F[1] + tx + r * T, 0, n - 1));
       }
     }
     float2 v[16];
@@ -243,8 +290,9 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
     for (int r = 0; r < 16; r++)
       v[r] = make_float2(HLN2 * (__builtin_amdgcn_logf((float)ca[r] + 0.5f) - lr0),
                          HLN2 * (__builtin_amdgcn_logf((float)cb[r] + 0.5f) - lr1));
+    front_take_next<FIELD>(nxt, it, q0);   // its latency overlaps the code reads
     dft16(v);
-    const int p0 = fpad(16 * threadIdx.x);   // outputs 16 j + r: one padded run
+    const int p0 = fpad(16 * tx);   // outputs 16 j + r: one padded run
 #pragma unroll
     for (int r = 0; r < 16; r++) lds[p0 + r] = v[r];
   }
@@ -267,7 +315,7 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
     fft_passes<N, 16, false>(lds, J.twid, HilbertOut<T>{J.hspec, y, {}});   // the passes after the first
     dft16(y);
     __syncthreads();
-    const int p0 = fpad(16 * threadIdx.x);   // outputs 16 j + r of the second transform's first pass
+    const int p0 = fpad(16 * tid_local());   // outputs 16 j + r of the second transform's first pass
 #pragma unroll
     for (int r = 0; r < 16; r++) lds[p0 + r] = y[r];
   }
@@ -288,9 +336,10 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
   for (int i = 0; i < QPT; i++) asm volatile("" : "+v"(ph[0][i]), "+v"(ph[1][i]));
   __syncthreads();
   if constexpr (PREC != 0) {
+    const int tx = tid_local();
 #pragma unroll
     for (int i = 0; i < QPT; i++) {
-      const int q = threadIdx.x + i * T;
+      const int q = tx + i * T;
       stash[q] = ph[1][i];   // read back by this thread only
     }
   }
@@ -308,7 +357,7 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
   // last workgroups): both workgroup-uniform
   int nint = 0;
   bool edge_wg = false;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = tid_local() & 63, wv = tid_local() >> 6;
   const int row = lane & 15, kq = lane >> 4;
   constexpr int NW = T / 64;
   // rotations of P between this lane's outputs: +16 (second tile) and
@@ -328,19 +377,35 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
     const int e = (int)(nq0 & 1);
     const uint8_t *cb = in + 3 * ((nq0 - e) / 2);
     const int qlo = (int)clamp64(-nq0, 0, QN), qhi = (int)clamp64(n - nq0, 0, QN);   // t in [0, n)
-    float2 dph = cis_rev(-downshift_rev(J.r, g0 + nq0 + threadIdx.x));
+    const int tx = tid_local();
+    float2 dph = cis_rev(-downshift_rev(J.r, g0 + nq0 + tx));
     float2 *const fbase = J.field + nq0;   // FIELD only
-    // the thread's code reads are issued a batch at a time (index clamped
-    // into the buffer), so their latencies overlap; the plain form, whose
-    // split planes take more registers, issues its 12 in three batches
+    // interior frames (all samples inside the buffer: every block pair but
+    // a buffer's first and last) read the thread's codes at immediate
+    // offsets from one address; the others clamp each index into the buffer
+    const bool inner = qlo == 0 && qhi == QN;
+    const int sh = ((tx + e) & 1) << 2;   // T is even: one nibble position for all q of the thread
+    // plane index of q = tx + i T: nidx(tx) + nidx(i T), T a multiple of 32
+    static_assert(T % 32 == 0, "plane offsets split");
+    const int nq = nidx(tx);
+    // the thread's code reads are issued a batch at a time, so their
+    // latencies overlap; the plain form, whose split planes take more
+    // registers, issues its 12 in three batches
     constexpr int QB = PREC == 0 ? (QPT + 2) / 3 : QPT;
 #pragma unroll
     for (int i0 = 0; i0 < QPT; i0 += QB) {
       int craw[QB];
-      if (qhi > qlo) {
+      if (inner) {
+        const uint8_t *ct = cb + ((3 * (tx + e)) >> 1);
 #pragma unroll
         for (int u = 0; u < QB && i0 + u < QPT; u++) {
-          const int q = threadIdx.x + (i0 + u) * T;
+          const int o = (i0 + u) * (3 * T / 2);
+          craw[u] = (int)ct[o] | ((int)ct[o + 1] << 8);
+        }
+      } else if (qhi > qlo) {
+#pragma unroll
+        for (int u = 0; u < QB && i0 + u < QPT; u++) {
+          const int q = tx + (i0 + u) * T;
           const int qc = q < qlo ? qlo : (q >= qhi ? qhi - 1 : q);
           const int o = 3 * (qc + e);
           craw[u] = (int)cb[o >> 1] | ((int)cb[(o >> 1) + 1] << 8);
@@ -349,11 +414,11 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
 #pragma unroll
       for (int u = 0; u < QB && i0 + u < QPT; u++) {
         const int i = i0 + u;
-        const int q = threadIdx.x + i * T;
-        if (q < QN) {
+        const int q = tx + i * T;   // < QN: QN is a multiple of T
+        {
           float2 yv = make_float2(0.0f, 0.0f);
-          if (q >= qlo && q < qhi) {
-            const int c = (craw[u] >> (((q + e) & 1) << 2)) & 0xFFF;
+          if (inner || (q >= qlo && q < qhi)) {
+            const int c = (craw[u] >> sh) & 0xFFF;
             float phv;
             if constexpr (PREC == 0) phv = ph[x][i];
             else phv = x == 0 ? ph[0][i] : stash[q];
@@ -367,16 +432,17 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
               if constexpr (FIELD) gstore(fbase, q, ev);
             }
           }
+          const int pq = nq + nidx(i * T);
           if constexpr (FIELD) {
           } else if constexpr (PREC == 0) {
             const _Float16 rh = (_Float16)yv.x, ih = (_Float16)yv.y;
-            npl[nidx(q)] = rh;
-            npl[PS + nidx(q)] = ih;
-            npl[2 * PS + nidx(q)] = (_Float16)(yv.x - (float)rh);
-            npl[3 * PS + nidx(q)] = (_Float16)(yv.y - (float)ih);
+            npl[pq] = rh;
+            npl[PS + pq] = ih;
+            npl[2 * PS + pq] = (_Float16)(yv.x - (float)rh);
+            npl[3 * PS + pq] = (_Float16)(yv.y - (float)ih);
           } else {
-            npl[nidx(q)] = NarrowT<PREC == 0 ? 1 : PREC>::cvt(yv.x);
-            npl[PS + nidx(q)] = NarrowT<PREC == 0 ? 1 : PREC>::cvt(yv.y);
+            npl[pq] = NarrowT<PREC == 0 ? 1 : PREC>::cvt(yv.x);
+            npl[PS + pq] = NarrowT<PREC == 0 ? 1 : PREC>::cvt(yv.y);
           }
         }
         dph = cmul(dph, drot);
@@ -432,7 +498,7 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
     }
     __syncthreads();
   }
-  if constexpr (FIELD) return;
+  if constexpr (!FIELD) {
   // FP64 workgroup sums: each wavefront's (DPP), then lane k < 9 of the
   // first wavefront adds variable k over the wavefronts in wavefront order
   // and thread 0 collects them; only thread 0 needs them.  The edge sums
@@ -458,11 +524,22 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L) {  /
     v[4] = (double)nint;
     if (lane == 0) {
       const double c0r = J.c0.x, c0i = J.c0.y;
-      J.part[3 * blockIdx.x] = make_double2(v[0], v[1]);                          // sum of the field E
-      J.part[3 * blockIdx.x + 1] = make_double2(v[2], v[3] + v[4] * (c0r * c0r + c0i * c0i));  // |Z|^2, |T|^2
-      J.part[3 * blockIdx.x + 2] = make_double2(c0r * v[5] + c0i * v[6] + v[7],    // sum Z conj(T)
-                                                c0r * v[6] - c0i * v[5] + v[8]);
+      J.part[3 * pidx] = make_double2(v[0], v[1]);                          // sum of the field E
+      J.part[3 * pidx + 1] = make_double2(v[2], v[3] + v[4] * (c0r * c0r + c0i * c0i));  // |Z|^2, |T|^2
+      J.part[3 * pidx + 2] = make_double2(c0r * v[5] + c0i * v[6] + v[7],    // sum Z conj(T)
+                                          c0r * v[6] - c0i * v[5] + v[8]);
     }
+  }
+  }
+  }
+  if constexpr (FIELD) break;
+  item = __builtin_amdgcn_readfirstlane(nxt[it & 1]);
+  }
+  // every workgroup's last take came back empty before it counts itself
+  // here, so the last one to count resets the queue for the next launch
+  if (!FIELD && threadIdx.x == 0 && atomicAdd(&q0->kk_done, 1u) == gridDim.x - 1) {
+    atomicExch(&q0->kk_next, 0u);
+    atomicExch(&q0->kk_done, 0u);
   }
 }
 
@@ -542,13 +619,32 @@ __global__ __launch_bounds__(1024) void kk_vv(RxLaunch L) {
   }
 }
 
+// The persistent grid: as many workgroups as the device holds at once.
+template <int LOGN, int PREC>
+static int front_resident() {
+  static int resident = 0;   // one device type per process
+  if (resident == 0) {
+    int dev = 0, ncu = 0, occ = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kk_front<LOGN, PREC, false>, (1 << LOGN) / 16, 0) !=
+            hipSuccess)
+      return 256;
+    resident = ncu * (occ > 0 ? occ : 1);
+  }
+  return resident;
+}
+
 template <int LOGN, int PREC, bool FIELD = false>
 static void launch_front(const RxLaunch &L, int64_t maxn, hipStream_t s) {
   constexpr int N = 1 << LOGN;
   const int hop = rx_kk_hop(LOGN);
   const int64_t nrb = (maxn + hop - 1) / hop;
-  dim3 grid((unsigned)((nrb + 1) / 2), (unsigned)L.count);
-  hipLaunchKernelGGL((kk_front<LOGN, PREC, FIELD>), grid, dim3(N / 16), 0, s, L);
+  const int pmax = (int)((nrb + 1) / 2);
+  const int64_t total = (int64_t)pmax * L.count;
+  if (total <= 0) return;
+  const int64_t grid = FIELD ? total : std::min<int64_t>(total, front_resident<LOGN, PREC>());
+  hipLaunchKernelGGL((kk_front<LOGN, PREC, FIELD>), dim3((unsigned)grid), dim3(N / 16), 0, s, L, pmax);
 }
 
 void rx_launch_kk_stage(int stage, const RxLaunch &L, int64_t maxn, int log2n, int prec, hipStream_t s) {

@@ -42,10 +42,22 @@ typedef float rx_v2 __attribute__((ext_vector_type(2)));
 typedef float rx_v4 __attribute__((ext_vector_type(4)));
 template <class T>
 __device__ __forceinline__ RX_GLOBAL T *gptr(T *p) { return (RX_GLOBAL T *)p; }
+// Element i (i < 2^32 / sizeof(T)) of a global array with a uniform base:
+// a 32-bit unsigned byte offset lets the load take the base in scalar
+// registers and one vector register of offset, with no 64-bit address
+// arithmetic per thread.
+template <class T>
+__device__ __forceinline__ T gload_u32(const T *base, unsigned i) {
+  return *(const RX_GLOBAL T *)((const RX_GLOBAL char *)base + i * (unsigned)sizeof(T));
+}
 struct GView2 {   // read-only global view of a float2 array
   const RX_GLOBAL rx_v2 *p;
   __device__ float2 operator[](int64_t i) const {
     const rx_v2 v = p[i];
+    return make_float2(v.x, v.y);
+  }
+  __device__ float2 at(unsigned i) const {   // i < 2^29, as gload_u32
+    const rx_v2 v = *(const RX_GLOBAL rx_v2 *)((const RX_GLOBAL char *)p + i * 8u);
     return make_float2(v.x, v.y);
   }
 };

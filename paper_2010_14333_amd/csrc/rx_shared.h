@@ -20,7 +20,9 @@ struct RxScalars {
   unsigned long long stats[7];  // buffers, symbols, bits, bit errors, symbol errors, fallbacks,
                                 // buffers later than their deadline
   unsigned long long t_start;   // wall-clock ticks when the buffer's first workgroup started
-  unsigned int done_wg, pad2;   // decision workgroups of the current buffer that have finished
+  unsigned int done_wg;         // decision workgroups of the current buffer that have finished
+  unsigned int kk_next;         // KK front end: work items handed out beyond the first grid (launch job 0)
+  unsigned int kk_done, pad2;   // KK front end: workgroups that found the queue empty (launch job 0)
   unsigned long long lat_count; // buffers whose latency has been recorded
   unsigned int lat[RX_LAT_RING];   // latency (ticks) of recorded buffer i at index i % RX_LAT_RING
   double theta_carry;           // stream: KK carrier phase of the last emitted DD-LMS block
