@@ -221,10 +221,21 @@ static const SharedTables *shared_tables(int log2n, int htaps) {
   const int n = 1 << log2n;
   std::vector<float> hs = design_hilbert_spectrum(htaps, log2n);
   std::vector<float2> tw = design_twiddles(log2n);
+  // the 2^14-point front end runs its transforms as 16 x 1024: behind the
+  // N-point twiddles the 1024-point ones, and behind the spectrum a copy in
+  // the order its 1024-point transforms hand their outputs over (entry
+  // 1024 k1 + 64 i + l is bin k = k1 + 16 (l + 64 i))
+  const std::vector<float2> tw1k = design_twiddles(10);
+  tw.insert(tw.end(), tw1k.begin(), tw1k.end());
+  hs.resize(2 * (size_t)n, 0.0f);
+  if (log2n == 14)
+    for (int k1 = 0; k1 < 16; k1++)
+      for (int i = 0; i < 16; i++)
+        for (int l = 0; l < 64; l++) hs[n + 1024 * k1 + 64 * i + l] = hs[k1 + 16 * (l + 64 * i)];
   SharedTables t{nullptr, nullptr};
-  if (hipMalloc((void **)&t.hspec, n * sizeof(float)) != hipSuccess) return nullptr;
+  if (hipMalloc((void **)&t.hspec, hs.size() * sizeof(float)) != hipSuccess) return nullptr;
   if (hipMalloc((void **)&t.twid, tw.size() * sizeof(float2)) != hipSuccess ||
-      hipMemcpy(t.hspec, hs.data(), n * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(t.hspec, hs.data(), hs.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(t.twid, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) {
     hipFree(t.hspec);
     if (t.twid) hipFree(t.twid);

@@ -19,6 +19,15 @@ __device__ __forceinline__ int tid_local() {
   return (int)t;
 }
 
+// Orders one wavefront's LDS accesses across lanes: its DS instructions
+// execute in program order, so a fence that keeps the compiler from moving
+// accesses across it is all that a wavefront-local exchange needs.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // LDS index with one float2 of padding every 16: stride-16 writes of the
 // first pass then spread over all banks.
 __host__ __device__ constexpr int fpad(int p) { return p + (p >> 4); }
@@ -133,26 +142,42 @@ struct LdsOut {
 // Butterfly j reads x[j + r N/R], twiddles by W_{NS R}^{r (j mod NS)}, and
 // writes to (j / NS) NS R + (j mod NS) + r NS.  NS is a compile-time
 // constant so the padded LDS offsets of the VPT accesses fold to immediates.
-template <int N, int R, int NS, bool TAIL = true, class Out = LdsOut, int VPT = 16>
+// TWL: every twiddle W^r read from the table (R - 1 loads a butterfly and no
+// products), else W, W^2, W^4, W^8 read and the others formed as their
+// products.  With the table in natural order the R - 1 loads of a wavefront
+// touch about four times the cache lines of the four (lane stride 8 r NS'
+// bytes), which costs the 2^14-point front end far more than the products
+// it saves; it stays off there.
+// WV: a transform of one wavefront (T = 64 lanes, buf its own LDS region),
+// synchronised by wave_sync instead of workgroup barriers.
+template <int N, int R, int NS, bool TAIL = true, class Out = LdsOut, int VPT = 16, bool TWL = false,
+          bool WV = false>
 __device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *__restrict__ tw, Out out) {
   constexpr int T = N / VPT;
   constexpr int NB = (N / R) / T;  // butterflies per thread
-  const int tx = tid_local();
+  static_assert(!WV || T == 64, "a wavefront transform has one butterfly column per lane");
+  const int tx = WV ? (tid_local() & 63) : tid_local();
   // twiddle table reads first: their latency overlaps the LDS reads and the
   // barrier.  They go through a global-memory view: as flat accesses they
   // would also count against the LDS wait counter, and the wait for this
   // pass's LDS reads would wait for them too.
   float2 tw1[NB], tw2[NB], tw4[NB], tw8[NB];
+  float2 twr[TWL ? NB : 1][TWL ? R : 1];
   if constexpr (NS > 1) {
     const GView2 tg = gview(tw);
 #pragma unroll
     for (int b = 0; b < NB; b++) {
       const int j = tx + b * T;
-      const unsigned step = (unsigned)(j & (NS - 1)) * (N / (NS * R));
-      tw1[b] = tg.at(step);
-      tw2[b] = R > 2 ? tg.at(2 * step) : tw1[b];
-      tw4[b] = R > 4 ? tg.at(4 * step) : tw1[b];
-      tw8[b] = R > 8 ? tg.at(8 * step) : tw1[b];
+      const unsigned step = (unsigned)(j & (NS - 1)) * (N / (NS * R));   // r step < N
+      if constexpr (TWL) {
+#pragma unroll
+        for (int r = 1; r < R; r++) twr[b][r] = tg.at(r * step);
+      } else {
+        tw1[b] = tg.at(step);
+        tw2[b] = R > 2 ? tg.at(2 * step) : tw1[b];
+        tw4[b] = R > 4 ? tg.at(4 * step) : tw1[b];
+        tw8[b] = R > 8 ? tg.at(8 * step) : tw1[b];
+      }
     }
   }
   out.begin();
@@ -162,25 +187,33 @@ __device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *__restr
   static_assert((N / R) % 16 == 0, "padded read offsets split");
   // (the reads past 64 KiB of the first take a second base: the offset
   // field of an LDS read holds 16 bits)
-  constexpr int RH = R / 2, OH = fpad(RH * (N / R));
+  constexpr bool TWO = 8 * fpad((R - 1) * (N / R)) >= 65536;
+  constexpr int RH = TWO ? R / 2 : R, OH = fpad(RH * (N / R));
 #pragma unroll
   for (int b = 0; b < NB; b++) {
     const int pj = fpad(tx + b * T);
     int pj1 = pj + OH;
-    asm volatile("" : "+v"(pj1));   // kept as its own base, not refolded into pj
+    if constexpr (TWO) asm volatile("" : "+v"(pj1));   // kept as its own base, not refolded into pj
     const float2 *b0 = buf + pj, *b1 = buf + pj1;
 #pragma unroll
-    for (int r = 0; r < R; r++)
-      v[b][r] = (r < RH || R < 8) ? b0[fpad(r * (N / R))] : b1[fpad(r * (N / R)) - OH];
+    for (int r = 0; r < R; r++) v[b][r] = r < RH ? b0[fpad(r * (N / R))] : b1[fpad(r * (N / R)) - OH];
   }
   // in the last pass (NS R = N) a butterfly writes back exactly the indices
   // it read, so no thread overwrites another's input: no barrier needed
-  if constexpr (NS * R != N) __syncthreads();
+  if constexpr (NS * R != N) {
+    if constexpr (WV) wave_sync();
+    else __syncthreads();
+  }
 #pragma unroll
   for (int b = 0; b < NB; b++) {
     const int j = tx + b * T;
     const int k = j & (NS - 1);
-    if constexpr (NS > 1) apply_twiddles<R, 1>(v[b], tw1[b], tw2[b], tw4[b], tw8[b]);
+    if constexpr (NS > 1 && TWL) {
+#pragma unroll
+      for (int r = 1; r < R; r++) v[b][r] = cmul(v[b][r], twr[b][r]);
+    } else if constexpr (NS > 1) {
+      apply_twiddles<R, 1>(v[b], tw1[b], tw2[b], tw4[b], tw8[b]);
+    }
     dft_r<R>(v[b]);
     const int base = (j / NS) * NS * R + k;
     // fpad(base + r NS) = fpad(base) + fpad(r NS): either NS is a multiple of
@@ -193,7 +226,10 @@ __device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *__restr
 #pragma unroll
     for (int r = 0; r < R; r++) out(b * T + r * NS, pb + fpad(r * NS), v[b][r]);
   }
-  if constexpr (TAIL) __syncthreads();
+  if constexpr (TAIL) {
+    if constexpr (WV) wave_sync();
+    else __syncthreads();
+  }
 }
 
 // Radix-8 passes only, 8 values per thread (N = 8 * blockDim.x, N a power of 8).
@@ -208,19 +244,19 @@ __device__ __forceinline__ void fft_passes8(float2 *buf, const float2 *__restric
   }
 }
 
-template <int N, int NS, bool TAIL, class Out>
+template <int N, int NS, bool TAIL, class Out, bool TWL = false, bool WV = false>
 __device__ __forceinline__ void fft_passes(float2 *buf, const float2 *__restrict__ tw, Out out) {
   if constexpr (NS * 16 < N) {
-    stockham_pass<N, 16, NS>(buf, tw, LdsOut{buf});
-    fft_passes<N, NS * 16, TAIL>(buf, tw, out);
+    stockham_pass<N, 16, NS, true, LdsOut, 16, TWL, WV>(buf, tw, LdsOut{buf});
+    fft_passes<N, NS * 16, TAIL, Out, TWL, WV>(buf, tw, out);
   } else if constexpr (NS * 16 == N) {
-    stockham_pass<N, 16, NS, TAIL>(buf, tw, out);
+    stockham_pass<N, 16, NS, TAIL, Out, 16, TWL, WV>(buf, tw, out);
   } else if constexpr (NS * 8 == N) {
-    stockham_pass<N, 8, NS, TAIL>(buf, tw, out);
+    stockham_pass<N, 8, NS, TAIL, Out, 16, TWL, WV>(buf, tw, out);
   } else if constexpr (NS * 4 == N) {
-    stockham_pass<N, 4, NS, TAIL>(buf, tw, out);
+    stockham_pass<N, 4, NS, TAIL, Out, 16, TWL, WV>(buf, tw, out);
   } else if constexpr (NS * 2 == N) {
-    stockham_pass<N, 2, NS, TAIL>(buf, tw, out);
+    stockham_pass<N, 2, NS, TAIL, Out, 16, TWL, WV>(buf, tw, out);
   }
 }
 

@@ -62,6 +62,32 @@ template <int T, int QPT, int IOFF> struct PhaseOut {
   }
 };
 
+// The 2^14-point transforms run as 16 x 1024 (see kk_front): a wavefront's
+// 1024-point transform of column k1 = its wave index hands over output
+// k2 = lane + koff (slot i = koff / 64), bin k = k1 + 16 k2.
+// Last pass of the first transform: times H = -j S on the way out, as
+// HilbertOut, the weights read in the transform's own order.
+struct HilbertOutW {
+  const float *hs2;   // the column's 1024 weights, entry 64 i + lane for slot i
+  float2 (&y)[16];
+  float hs[16];
+  __device__ __forceinline__ void begin() {
+    const int lane = tid_local() & 63;
+#pragma unroll
+    for (int i = 0; i < 16; i++) hs[i] = gload_u32(hs2, (unsigned)(64 * i + lane));
+  }
+  __device__ __forceinline__ void operator()(int koff, int, float2 z) const {
+    const int i = koff / 64;
+    y[i] = make_float2(z.y * hs[i], z.x * hs[i]);
+  }
+};
+// Last pass of the second transform: outputs kept in registers by slot.
+struct RegOutW {
+  float2 (&c)[16];
+  __device__ __forceinline__ void begin() {}
+  __device__ __forceinline__ void operator()(int koff, int, float2 v) const { c[koff / 64] = v; }
+};
+
 // A value that is the same in every lane, moved into scalar registers: kept
 // in vector registers it would be recomputed at each use once the
 // transforms have taken the register file.
@@ -123,11 +149,13 @@ template <> struct MfB<0> {
   // yp: this lane's component plane of hi; its lo plane is `lo` elements on
   __device__ rx_f32x4 apply(const _Float16 *__restrict__ yp, int lo, int tile, int kq) const {
     rx_f32x4 c0 = {0.0f, 0.0f, 0.0f, 0.0f}, c1 = c0;
+    // nidx(32 (tile + ks) + 8 kq) = 40 (tile + ks) + 8 kq (8 kq < 32): one
+    // address, the steps at immediate offsets
+    const _Float16 *const a0 = yp + 40 * tile + 8 * kq;
 #pragma unroll
     for (int ks = 0; ks < 3; ks++) {
-      const int o = nidx(32 * (tile + ks) + 8 * kq);
-      const rx_f16x8 ah = *reinterpret_cast<const rx_f16x8 *>(yp + o);
-      const rx_f16x8 al = *reinterpret_cast<const rx_f16x8 *>(yp + lo + o);
+      const rx_f16x8 ah = *reinterpret_cast<const rx_f16x8 *>(a0 + 40 * ks);
+      const rx_f16x8 al = *reinterpret_cast<const rx_f16x8 *>(a0 + lo + 40 * ks);
       const rx_f16x8 bh = bt[64 * ks], bl = bt[192 + 64 * ks];
       c1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh, c1, 0, 0, 0);
       c1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl, c1, 0, 0, 0);
@@ -149,9 +177,10 @@ template <int PREC> struct MfB {
   // yp: this lane's component plane
   __device__ rx_f32x4 apply(const typename NT::elem *__restrict__ yp, int, int tile, int kq) const {
     rx_f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    const typename NT::elem *const a0 = yp + 40 * tile + 8 * kq;   // as MfB<0>::apply
 #pragma unroll
     for (int ks = 0; ks < 3; ks++)
-      acc = NT::mfma(*reinterpret_cast<const typename NT::vec *>(yp + nidx(32 * (tile + ks) + 8 * kq)), b[ks], acc);
+      acc = NT::mfma(*reinterpret_cast<const typename NT::vec *>(a0 + 40 * ks), b[ks], acc);
     return acc;
   }
 };
@@ -207,6 +236,11 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L, int 
   static_assert(PS >= nidx(YPL - 1) + 1 && (PS + QN) * 4 <= 8 * (N + N / 16), "narrow planes and phase stash fit");
   static_assert(4 * PS * 2 <= 8 * (N + N / 16), "the plain form's four planes fit");
   constexpr float INV2PI = 0.15915494309189535f;
+  // 2^14 points: the transforms as 16 x 1024, one 1024-point column per
+  // wavefront in its own region of RG = fpad(1024) entries
+  constexpr bool FOUR = LOGN == 14;
+  constexpr int RG = fpad(1024);
+  static_assert(!FOUR || 16 * RG == N + N / 16, "sixteen column regions fill the buffer");
   __shared__ float2 lds[N + N / 16];
   using ElemT = typename std::conditional<PREC == 0, _Float16, typename NarrowT<PREC == 0 ? 1 : PREC>::elem>::type;
   ElemT *const npl = reinterpret_cast<ElemT *>(lds);   // y' planes
@@ -285,6 +319,14 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L, int 
         cb[r] = read_code(in, clamp64(F[1] + tx + r * T, 0, n - 1));
       }
     }
+    float2 w1, w2, w4, w8;   // W^(j r) of the 16 x 1024 form's first step, read beside the codes
+    if constexpr (FOUR) {
+      const GView2 tg = gview(J.twid);
+      w1 = tg.at(tx);
+      w2 = tg.at(2 * tx);
+      w4 = tg.at(4 * tx);
+      w8 = tg.at(8 * tx);
+    }
     float2 v[16];
 #pragma unroll
     for (int r = 0; r < 16; r++)
@@ -292,9 +334,16 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L, int 
                          HLN2 * (__builtin_amdgcn_logf((float)cb[r] + 0.5f) - lr1));
     front_take_next<FIELD>(nxt, it, q0);   // its latency overlaps the code reads
     dft16(v);
-    const int p0 = fpad(16 * tx);   // outputs 16 j + r: one padded run
+    if constexpr (FOUR) {
+      // output k1 = r, times W_N^(j k1), to column k1: G[k1][j] at k1 RG + j
+      apply_twiddles<16, 1>(v, w1, w2, w4, w8);
 #pragma unroll
-    for (int r = 0; r < 16; r++) lds[p0 + r] = v[r];
+      for (int r = 0; r < 16; r++) lds[r * RG + tx] = v[r];
+    } else {
+      const int p0 = fpad(16 * tx);   // outputs 16 j + r: one padded run
+#pragma unroll
+      for (int r = 0; r < 16; r++) lds[p0 + r] = v[r];
+    }
   }
   __syncthreads();
 
@@ -310,25 +359,84 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L, int 
   //    registers; the barrier only keeps the writes behind every thread's
   //    reads of the last pass.
   static_assert((RX_KK_EDGE - RX_KK_CMF) % T == 0 && QN % T == 0, "phases are the thread's own outputs");
-  {
-    float2 y[16];
-    fft_passes<N, 16, false>(lds, J.twid, HilbertOut<T>{J.hspec, y, {}});   // the passes after the first
-    dft16(y);
-    __syncthreads();
-    const int p0 = fpad(16 * tid_local());   // outputs 16 j + r of the second transform's first pass
-#pragma unroll
-    for (int r = 0; r < 16; r++) lds[p0 + r] = y[r];
-  }
-  __syncthreads();
-  // the second transform recomputes its twiddle addresses: kept live from the
-  // first they would be spilled across the Hilbert product
-  const float2 *tw2 = J.twid;
-  asm volatile("" : "+s"(tw2));
+  constexpr int IOFF = (RX_KK_EDGE - RX_KK_CMF) / T;
   // phase in revolutions: sgn phi / (2 pi); sgn = +-1, so one product by
   // sgn / (2 pi) is exact against the two
   const float sgnrev = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, J.sgn * INV2PI)));
   float ph[2][QPT];   // frames A and B (the narrow forms park B in LDS below)
-  fft_passes<N, 16, false>(lds, tw2, PhaseOut<T, QPT, (RX_KK_EDGE - RX_KK_CMF) / T>{ph[0], ph[1], sgnrev});
+  if constexpr (FOUR) {
+    // 16 x 1024: X[k1 + 16 k2] = sum_j W_1024^(j k2) W_N^(j k1) sum_r x[j + T r]
+    // W_16^(r k1).  The inner sums and twiddles are done (thread j, above);
+    // wavefront k1 now takes column k1 (lane l: j = l + 64 m) and
+    // transforms it in its own LDS region, with wavefront-local exchanges
+    // only.  The second transform runs the same steps in reverse order:
+    // Z[m2 + T m1] = sum_k1 W_16^(m1 k1) W_N^(m2 k1) sum_k2 c[k1 + 16 k2]
+    // W_1024^(m2 k2), with c = conj(Y) the column's own products, so only
+    // its last step (thread m2 = j, all k1) needs the workgroup again.
+    static_assert(N == 16 * 1024 && T == 1024 && QPT + IOFF <= 16, "16 x 1024 geometry");
+    const int lane = tid_local() & 63, wv = tid_local() >> 6;
+    float2 *const wb = lds + wv * RG;
+    const float2 *const tw1k = J.twid + N;
+    float2 y[16];
+    {
+      float2 x[16];
+#pragma unroll
+      for (int m = 0; m < 16; m++) x[m] = wb[64 * m + lane];
+      wave_sync();
+      dft16(x);   // first pass of the column transform (radix 16, no twiddles)
+      const int p0 = fpad(16 * lane);
+#pragma unroll
+      for (int r = 0; r < 16; r++) wb[p0 + r] = x[r];
+    }
+    wave_sync();
+    fft_passes<1024, 16, false, HilbertOutW, false, true>(wb, tw1k, HilbertOutW{J.hspec + N + 1024 * wv, y, {}});
+    // second transform: the column's products are its first pass's inputs
+    // (slot m' = element lane + 64 m')
+    dft16(y);
+    wave_sync();
+    {
+      const int p0 = fpad(16 * lane);
+#pragma unroll
+      for (int r = 0; r < 16; r++) wb[p0 + r] = y[r];
+    }
+    wave_sync();
+    float2 c[16];
+    fft_passes<1024, 16, false, RegOutW, false, true>(wb, tw1k, RegOutW{c});
+    // element m2 = lane + 64 m of column k1 = wv to thread m2: G[m][wv][lane]
+    const int tx = tid_local();
+    const GView2 tg = gview(J.twid);
+    const float2 u1 = tg.at(tx), u2 = tg.at(2 * tx), u4 = tg.at(4 * tx), u8 = tg.at(8 * tx);
+    __syncthreads();   // every wavefront is done with its region
+#pragma unroll
+    for (int m = 0; m < 16; m++) lds[m * RG + 64 * wv + lane] = c[m];
+    __syncthreads();
+    float2 z[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 16; k1++) z[k1] = lds[wv * RG + 64 * k1 + lane];
+    apply_twiddles<16, 1>(z, u1, u2, u4, u8);   // W_N^(j k1)
+    dft16(z);   // z[m1] = output j + T m1
+#pragma unroll
+    for (int i = 0; i < QPT; i++) {
+      ph[0][i] = z[i + IOFF].x * sgnrev;
+      ph[1][i] = -z[i + IOFF].y * sgnrev;
+    }
+  } else {
+    {
+      float2 y[16];
+      fft_passes<N, 16, false>(lds, J.twid, HilbertOut<T>{J.hspec, y, {}});   // the passes after the first
+      dft16(y);
+      __syncthreads();
+      const int p0 = fpad(16 * tid_local());   // outputs 16 j + r of the second transform's first pass
+#pragma unroll
+      for (int r = 0; r < 16; r++) lds[p0 + r] = y[r];
+    }
+    __syncthreads();
+    // the second transform recomputes its twiddle addresses: kept live from
+    // the first they would be spilled across the Hilbert product
+    const float2 *tw2 = J.twid;
+    asm volatile("" : "+s"(tw2));
+    fft_passes<N, 16, false>(lds, tw2, PhaseOut<T, QPT, IOFF>{ph[0], ph[1], sgnrev});
+  }
   // the phases are formed here: left to itself the compiler moves the last
   // pass's arithmetic into the field stage, where it no longer fits the
   // register file
@@ -435,11 +543,16 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L, int 
           const int pq = nq + nidx(i * T);
           if constexpr (FIELD) {
           } else if constexpr (PREC == 0) {
-            const _Float16 rh = (_Float16)yv.x, ih = (_Float16)yv.y;
-            npl[pq] = rh;
-            npl[PS + pq] = ih;
-            npl[2 * PS + pq] = (_Float16)(yv.x - (float)rh);
-            npl[3 * PS + pq] = (_Float16)(yv.y - (float)ih);
+            // both components converted as one pair (the same rounding as
+            // one at a time)
+            const rx_f32x2 y2 = {yv.x, yv.y};
+            const rx_f16x2 hi = __builtin_convertvector(y2, rx_f16x2);
+            const rx_f32x2 back = __builtin_convertvector(hi, rx_f32x2);
+            const rx_f16x2 lo = __builtin_convertvector(rx_f32x2{y2.x - back.x, y2.y - back.y}, rx_f16x2);
+            npl[pq] = hi.x;
+            npl[PS + pq] = hi.y;
+            npl[2 * PS + pq] = lo.x;
+            npl[3 * PS + pq] = lo.y;
           } else {
             npl[pq] = NarrowT<PREC == 0 ? 1 : PREC>::cvt(yv.x);
             npl[PS + pq] = NarrowT<PREC == 0 ? 1 : PREC>::cvt(yv.y);
@@ -483,7 +596,7 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L, int 
         const float2 p = jj ? cmul(pp, r16) : pp;
         if (t2 < NTILE && mr < mlim) {
           const float2 zv = make_float2(acc[2 * jj], acc[2 * jj + 1]);
-          gstore(zb, mr, zv);
+          gstore_u32(zb, (unsigned)mr, zv);
           zz = fmaf(zv.x, zv.x, fmaf(zv.y, zv.y, zz));
           if (mr >= mil && mr < mih) {
             sp = cadd(sp, cmul(zv, p));

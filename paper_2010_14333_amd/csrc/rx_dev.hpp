@@ -7,6 +7,8 @@
 typedef __bf16 rx_bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 rx_f16x8 __attribute__((ext_vector_type(8)));
 typedef float rx_f32x4 __attribute__((ext_vector_type(4)));
+typedef float rx_f32x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 rx_f16x2 __attribute__((ext_vector_type(2)));
 
 // Narrow operand type of the precision form (PREC 1: BF16, 2: FP16), with
 // round-to-nearest-even conversion from FP32.
@@ -64,6 +66,9 @@ struct GView2 {   // read-only global view of a float2 array
 __device__ __forceinline__ GView2 gview(const float2 *p) { return GView2{(const RX_GLOBAL rx_v2 *)p}; }
 __device__ __forceinline__ void gstore(float2 *p, int64_t i, float2 v) {
   ((RX_GLOBAL rx_v2 *)p)[i] = rx_v2{v.x, v.y};
+}
+__device__ __forceinline__ void gstore_u32(float2 *p, unsigned i, float2 v) {   // i < 2^29, as gload_u32
+  *(RX_GLOBAL rx_v2 *)((RX_GLOBAL char *)p + i * 8u) = rx_v2{v.x, v.y};
 }
 __device__ __forceinline__ float4 gload4(const void *p, int64_t i) {   // i-th 16-byte element
   const rx_v4 v = ((const RX_GLOBAL rx_v4 *)p)[i];
