@@ -290,6 +290,13 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L, int 
   //    reads those codes itself, transforms them in registers and writes the
   //    pass's outputs 16 j + r; the codes never pass through LDS.
   constexpr float HLN2 = 0.34657359027997264f;   // ln(2) / 2
+  // The field stage's samples t = F + EDGE - CMF + q, q = j + i T, are this
+  // thread's first-pass samples r = i + IOFF of the same frame: their codes
+  // stay in registers (both frames' 12-bit codes packed in one word).
+  static_assert((RX_KK_EDGE - RX_KK_CMF) % T == 0 && QN % T == 0, "phases are the thread's own outputs");
+  constexpr int IOFF = (RX_KK_EDGE - RX_KK_CMF) / T;
+  static_assert(QPT + IOFF <= 16, "the field stage's codes are first-pass codes");
+  int cpk[QPT];
   const float lr0 = __builtin_amdgcn_logf((float)read_code(in, clamp64(F[0] + N / 2, 0, n - 1)) + 0.5f);
   const float lr1 = __builtin_amdgcn_logf((float)read_code(in, clamp64(F[1] + N / 2, 0, n - 1)) + 0.5f);
   {
@@ -332,6 +339,8 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L, int 
     for (int r = 0; r < 16; r++)
       v[r] = make_float2(HLN2 * (__builtin_amdgcn_logf((float)ca[r] + 0.5f) - lr0),
                          HLN2 * (__builtin_amdgcn_logf((float)cb[r] + 0.5f) - lr1));
+#pragma unroll
+    for (int i = 0; i < QPT; i++) cpk[i] = ca[i + IOFF] | (cb[i + IOFF] << 16);
     front_take_next<FIELD>(nxt, it, q0);   // its latency overlaps the code reads
     dft16(v);
     if constexpr (FOUR) {
@@ -358,8 +367,6 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L, int 
   //    Hilbert products, so they go from one transform to the other in
   //    registers; the barrier only keeps the writes behind every thread's
   //    reads of the last pass.
-  static_assert((RX_KK_EDGE - RX_KK_CMF) % T == 0 && QN % T == 0, "phases are the thread's own outputs");
-  constexpr int IOFF = (RX_KK_EDGE - RX_KK_CMF) / T;
   // phase in revolutions: sgn phi / (2 pi); sgn = +-1, so one product by
   // sgn / (2 pi) is exact against the two
   const float sgnrev = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, J.sgn * INV2PI)));
@@ -479,87 +486,61 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L, int 
     //    This thread's samples t = nq0 + q, q = threadIdx + i T, are T apart,
     //    so the downshift phasor D(t) = exp(-j 2 pi frac(r t)) starts from an
     //    FP64 anchor and advances by the fixed rotation D(T) per sample.
-    //    Codes: t = nq0 + q sits at byte 3t/2 = base + 3(q + e)/2 with
-    //    e = nq0 mod 2 and base = 3(nq0 - e)/2, all offsets 32-bit.
+    //    Their codes are the first pass's (clamped into the buffer there;
+    //    samples outside it give y' = 0 here).
     const int64_t nq0 = F[x] + RX_KK_EDGE - RX_KK_CMF;   // sample index of q = 0
-    const int e = (int)(nq0 & 1);
-    const uint8_t *cb = in + 3 * ((nq0 - e) / 2);
     const int qlo = (int)clamp64(-nq0, 0, QN), qhi = (int)clamp64(n - nq0, 0, QN);   // t in [0, n)
+    // interior frames (all samples inside the buffer: every block pair but
+    // a buffer's first and last) skip the range masks
+    const bool inner = qlo == 0 && qhi == QN;
     const int tx = tid_local();
     float2 dph = cis_rev(-downshift_rev(J.r, g0 + nq0 + tx));
     float2 *const fbase = J.field + nq0;   // FIELD only
-    // interior frames (all samples inside the buffer: every block pair but
-    // a buffer's first and last) read the thread's codes at immediate
-    // offsets from one address; the others clamp each index into the buffer
-    const bool inner = qlo == 0 && qhi == QN;
-    const int sh = ((tx + e) & 1) << 2;   // T is even: one nibble position for all q of the thread
     // plane index of q = tx + i T: nidx(tx) + nidx(i T), T a multiple of 32
     static_assert(T % 32 == 0, "plane offsets split");
     const int nq = nidx(tx);
-    // the thread's code reads are issued a batch at a time, so their
-    // latencies overlap; the plain form, whose split planes take more
-    // registers, issues its 12 in three batches
-    constexpr int QB = PREC == 0 ? (QPT + 2) / 3 : QPT;
 #pragma unroll
-    for (int i0 = 0; i0 < QPT; i0 += QB) {
-      int craw[QB];
-      if (inner) {
-        const uint8_t *ct = cb + ((3 * (tx + e)) >> 1);
-#pragma unroll
-        for (int u = 0; u < QB && i0 + u < QPT; u++) {
-          const int o = (i0 + u) * (3 * T / 2);
-          craw[u] = (int)ct[o] | ((int)ct[o + 1] << 8);
-        }
-      } else if (qhi > qlo) {
-#pragma unroll
-        for (int u = 0; u < QB && i0 + u < QPT; u++) {
-          const int q = tx + (i0 + u) * T;
-          const int qc = q < qlo ? qlo : (q >= qhi ? qhi - 1 : q);
-          const int o = 3 * (qc + e);
-          craw[u] = (int)cb[o >> 1] | ((int)cb[(o >> 1) + 1] << 8);
+    for (int i = 0; i < QPT; i++) {
+      const int q = tx + i * T;   // < QN: QN is a multiple of T
+      const int c = x == 0 ? (cpk[i] & 0xFFF) : (cpk[i] >> 16);
+      float phv;
+      if constexpr (PREC == 0) phv = ph[x][i];
+      else phv = x == 0 ? ph[0][i] : stash[q];
+      // sqrt(v): v in [0.5, 4095.5], so the hardware square root (1 ulp)
+      // needs none of the denormal or rounding fix-ups of sqrtf
+      float2 ev = cscale(cis_rev(phv), __builtin_amdgcn_sqrtf((float)c + 0.5f));
+      float2 yv = cmul(ev, dph);
+      if (!inner) {
+        if (q < qlo || q >= qhi) {
+          ev = make_float2(0.0f, 0.0f);
+          yv = ev;
         }
       }
-#pragma unroll
-      for (int u = 0; u < QB && i0 + u < QPT; u++) {
-        const int i = i0 + u;
-        const int q = tx + i * T;   // < QN: QN is a multiple of T
-        {
-          float2 yv = make_float2(0.0f, 0.0f);
-          if (inner || (q >= qlo && q < qhi)) {
-            const int c = (craw[u] >> sh) & 0xFFF;
-            float phv;
-            if constexpr (PREC == 0) phv = ph[x][i];
-            else phv = x == 0 ? ph[0][i] : stash[q];
-            // sqrt(v): v in [0.5, 4095.5], so the hardware square root (1 ulp)
-            // needs none of the denormal or rounding fix-ups of sqrtf
-            const float2 ev = cscale(cis_rev(phv), __builtin_amdgcn_sqrtf((float)c + 0.5f));
-            yv = cmul(ev, dph);
-            if (q >= RX_KK_CMF && q < RX_KK_CMF + HOP) {
-              se_re += ev.x;
-              se_im += ev.y;
-              if constexpr (FIELD) gstore(fbase, q, ev);
-            }
-          }
-          const int pq = nq + nidx(i * T);
-          if constexpr (FIELD) {
-          } else if constexpr (PREC == 0) {
-            // both components converted as one pair (the same rounding as
-            // one at a time)
-            const rx_f32x2 y2 = {yv.x, yv.y};
-            const rx_f16x2 hi = __builtin_convertvector(y2, rx_f16x2);
-            const rx_f32x2 back = __builtin_convertvector(hi, rx_f32x2);
-            const rx_f16x2 lo = __builtin_convertvector(rx_f32x2{y2.x - back.x, y2.y - back.y}, rx_f16x2);
-            npl[pq] = hi.x;
-            npl[PS + pq] = hi.y;
-            npl[2 * PS + pq] = lo.x;
-            npl[3 * PS + pq] = lo.y;
-          } else {
-            npl[pq] = NarrowT<PREC == 0 ? 1 : PREC>::cvt(yv.x);
-            npl[PS + pq] = NarrowT<PREC == 0 ? 1 : PREC>::cvt(yv.y);
-          }
+      if (q >= RX_KK_CMF && q < RX_KK_CMF + HOP) {
+        se_re += ev.x;
+        se_im += ev.y;
+        if constexpr (FIELD) {
+          if (q >= qlo && q < qhi) gstore(fbase, q, ev);
         }
-        dph = cmul(dph, drot);
       }
+      const int pq = nq + nidx(i * T);
+      if constexpr (FIELD) {
+      } else if constexpr (PREC == 0) {
+        // both components converted as one pair (the same rounding as
+        // one at a time)
+        const rx_f32x2 y2 = {yv.x, yv.y};
+        const rx_f16x2 hi = __builtin_convertvector(y2, rx_f16x2);
+        const rx_f32x2 back = __builtin_convertvector(hi, rx_f32x2);
+        const rx_f16x2 lo = __builtin_convertvector(rx_f32x2{y2.x - back.x, y2.y - back.y}, rx_f16x2);
+        npl[pq] = hi.x;
+        npl[PS + pq] = hi.y;
+        npl[2 * PS + pq] = lo.x;
+        npl[3 * PS + pq] = lo.y;
+      } else {
+        npl[pq] = NarrowT<PREC == 0 ? 1 : PREC>::cvt(yv.x);
+        npl[PS + pq] = NarrowT<PREC == 0 ? 1 : PREC>::cvt(yv.y);
+      }
+      dph = cmul(dph, drot);
     }
     if constexpr (FIELD) continue;
     __syncthreads();
@@ -609,7 +590,9 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L, int 
       }
       pp = cmul(pp, rpass);
     }
-    __syncthreads();
+    // the second frame's reads of the planes are kept from the next pair's
+    // writes by the barrier of the workgroup sums below
+    if (x == 0) __syncthreads();
   }
   if constexpr (!FIELD) {
   // FP64 workgroup sums: each wavefront's (DPP), then lane k < 9 of the
