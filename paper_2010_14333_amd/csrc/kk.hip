@@ -211,6 +211,21 @@ __device__ __forceinline__ RxJob load_job_const(const RxJob *p) {
   return j;
 }
 
+// The 16-bit words holding a thread's first-pass codes of two frames, for
+// samples s0a + r T and s0b + r T (r < 16) inside the buffer: sample s sits
+// at byte 3s/2 (in the high 12 bits of its word when s is odd); T is even,
+// so one base per frame and immediate offsets r 3T/2.
+template <int T>
+__device__ __forceinline__ void front_code_words(const uint8_t *in, int64_t s0a, int64_t s0b, int (&ca)[16],
+                                                 int (&cb)[16]) {
+  const uint8_t *pa = in + ((3 * s0a) >> 1), *pb = in + ((3 * s0b) >> 1);
+#pragma unroll
+  for (int r = 0; r < 16; r++) {
+    ca[r] = (int)pa[r * (3 * T / 2)] | ((int)pa[r * (3 * T / 2) + 1] << 8);
+    cb[r] = (int)pb[r * (3 * T / 2)] | ((int)pb[r * (3 * T / 2) + 1] << 8);
+  }
+}
+
 // Hands out a workgroup's next item: thread 0 publishes it before a barrier
 // that every thread passes before reading the slot; the two parity slots keep
 // the write of the item after next clear of the reads of this one.
@@ -307,13 +322,8 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L, int 
       // (3 s0 >> 1) + r (3 T / 2) (T is even), in the high 12 bits of its
       // 16-bit word when s0 is odd
       const int64_t s0a = F[0] + tx, s0b = F[1] + tx;
-      const uint8_t *pa = in + ((3 * s0a) >> 1), *pb = in + ((3 * s0b) >> 1);
       const int sha = (int)(s0a & 1) << 2, shb = (int)(s0b & 1) << 2;
-#pragma unroll
-      for (int r = 0; r < 16; r++) {
-        ca[r] = (int)pa[r * (3 * T / 2)] | ((int)pa[r * (3 * T / 2) + 1] << 8);
-        cb[r] = (int)pb[r * (3 * T / 2)] | ((int)pb[r * (3 * T / 2) + 1] << 8);
-      }
+      front_code_words<T>(in, s0a, s0b, ca, cb);
 #pragma unroll
       for (int r = 0; r < 16; r++) {
         ca[r] = (ca[r] >> sha) & 0xFFF;
@@ -550,6 +560,26 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L, int 
     //    h[2q + 64 - t]; eight tiles (16 rows) per wavefront pass, 16x16x32
     //    steps with FP32 accumulation: PREC 0 on split (hi + lo) FP16
     //    operands, the precision form on operands rounded to the narrow type.
+    // the next item (published before this pair's first barrier): one read
+    // per 128-byte line of its input brings that into this CU's L2 while
+    // this matched filter runs, so the next pair's first reads hit there
+    unsigned warm = 0;
+    if constexpr (!FIELD) {
+      if (x == 1) {
+        const int nit = __builtin_amdgcn_readfirstlane(nxt[it & 1]);
+        if (nit < total) {
+          const int njb = nit / pmax;
+          const int64_t np = nit - (int64_t)njb * pmax, nn = L.n[njb];
+          const int64_t nF0 = 2 * np * HOP - RX_KK_EDGE;
+          if (2 * np < (nn + HOP - 1) / HOP) {
+            // samples [lo, hi) of its two frames inside the buffer (all even)
+            const int64_t lo = nF0 > 0 ? nF0 : 0, hi = nF0 + HOP + N < nn ? nF0 + HOP + N : nn;
+            const int64_t b0 = (3 * lo / 2) & ~(int64_t)3, off = b0 + 128 * (int64_t)tid_local();
+            if (off + 4 <= 3 * hi / 2) warm = *gptr(reinterpret_cast<const uint32_t *>(L.in[njb] + off));
+          }
+        }
+      }
+    }
     const int64_t m0 = blk[x] * (HOP / 2);
     MfB<PREC> bmf;
     if constexpr (PREC == 0) bmf.load(btab);
@@ -590,6 +620,7 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L, int 
       }
       pp = cmul(pp, rpass);
     }
+    asm volatile("" : : "v"(warm));   // the warming read has landed by now
     // the second frame's reads of the planes are kept from the next pair's
     // writes by the barrier of the workgroup sums below
     if (x == 0) __syncthreads();
