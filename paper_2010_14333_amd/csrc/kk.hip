@@ -635,7 +635,7 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L, int 
   for (int k = 0; k < 9; k++) {
     if (k == 4) continue;
     if ((k == 3 || k == 7 || k == 8) && !edge_wg) continue;
-    v[k] = wave_sum(v[k]);
+    v[k] = wave_sum_dpp(v[k]);
   }
   if (lane == 0) {
 #pragma unroll

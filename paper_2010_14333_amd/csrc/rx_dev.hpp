@@ -96,6 +96,28 @@ __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, RX_WAVE);
   return v;
 }
+// A double from another lane of the same row of 16, by DPP: each 32-bit
+// half moves as a VALU operand, without the LDS crossbar of a shuffle.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+// Sum of a double over the wavefront, every lane getting it: within each row
+// of 16 lanes by DPP (partners lane ^ 1, lane ^ 2 (quad permutes), then the
+// half-row and row mirrors, which pair the two sums formed so far), across
+// rows by two shuffles.
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_f64<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+  v += dpp_f64<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+  v += dpp_f64<0x141>(v);   // row_half_mirror
+  v += dpp_f64<0x140>(v);   // row_mirror
+  v += __shfl_xor(v, 16, RX_WAVE);
+  v += __shfl_xor(v, 32, RX_WAVE);
+  return v;
+}
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, RX_WAVE);
