@@ -174,26 +174,47 @@ using MNT = NarrowT<1>;
 struct MlpFrag {
   MNT::vec a1[4], a2[4][2];   // A fragments: W1 row tiles, W2 row tiles x 2 K-steps (permuted)
   const float *cv;            // LDS: b1[64], b2[64], W3[64] (per-unit vectors read per tile)
+  const MNT::vec *a2l;        // or the W2 fragments in LDS, [t][ks][lane] (then a2 is unused)
   float b3;
 };
 
-// Every thread of the workgroup calls this (it fills the LDS vectors).
-__device__ __forceinline__ void mlp_load_frag(const float *__restrict__ P, int row, int kq, float *cv, MlpFrag &f) {
+// Every thread of the workgroup calls this (it fills the LDS vectors, and
+// the W2 fragments into a2l when that is given).
+__device__ __forceinline__ void mlp_load_frag(const float *__restrict__ P, int row, int kq, float *cv, MlpFrag &f,
+                                              MNT::vec *a2l = nullptr) {
+  const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int t = 0; t < 4; t++)
 #pragma unroll
     for (int jj = 0; jj < 8; jj++) {
       const int i = 8 * kq + jj;
       f.a1[t][jj] = MNT::cvt(i < MI ? P[(16 * t + row) * MI + i] : 0.0f);
+      if (!a2l) {
 #pragma unroll
-      for (int ks = 0; ks < 2; ks++) {
-        const int u = 16 * (2 * ks + jj / 4) + 4 * kq + jj % 4;
-        f.a2[t][ks][jj] = MNT::cvt(P[OFF_W2 + (16 * t + row) * MH + u]);
+        for (int ks = 0; ks < 2; ks++) {
+          const int u = 16 * (2 * ks + jj / 4) + 4 * kq + jj % 4;
+          f.a2[t][ks][jj] = MNT::cvt(P[OFF_W2 + (16 * t + row) * MH + u]);
+        }
       }
     }
+  if (a2l && threadIdx.x < 64) {
+#pragma unroll
+    for (int t = 0; t < 4; t++)
+#pragma unroll
+      for (int ks = 0; ks < 2; ks++) {
+        MNT::vec v;
+#pragma unroll
+        for (int jj = 0; jj < 8; jj++) {
+          const int u = 16 * (2 * ks + jj / 4) + 4 * kq + jj % 4;
+          v[jj] = MNT::cvt(P[OFF_W2 + (16 * t + row) * MH + u]);
+        }
+        a2l[(2 * t + ks) * 64 + lane] = v;
+      }
+  }
   for (int i = threadIdx.x; i < 3 * MH; i += blockDim.x)
     cv[i] = P[i < MH ? OFF_B1 + i : i < 2 * MH ? OFF_B2 + i - MH : OFF_W3 + i - 2 * MH];
   f.cv = cv;
+  f.a2l = a2l;
   f.b3 = P[OFF_B3];
   __syncthreads();
 }
@@ -209,8 +230,10 @@ __device__ __forceinline__ float relu_bits(float x) { return __int_as_float(max(
 // 8 kq .. 8 kq + 7 of symbol `row`).  Every lane returns in y[i] the output
 // of symbol `row` of tile i.  Registers, LDS reads of the per-unit vectors
 // and two cross-lane shuffles per tile only.
-template <int NT>
-__device__ __forceinline__ void mlp_tiles(const MlpFrag &f, const MNT::vec (&bx)[NT], int kq, float (&y)[NT]) {
+// A2L: the W2 fragments from LDS (f.a2l) at lane index a2i, read per call.
+template <int NT, bool A2L = false>
+__device__ __forceinline__ void mlp_tiles(const MlpFrag &f, const MNT::vec (&bx)[NT], int kq, float (&y)[NT],
+                                          int a2i = 0) {
   const float4 *cv4 = reinterpret_cast<const float4 *>(f.cv) + kq;   // units 16 t + 4 kq .. + 3
   rx_f32x4 d1[NT][4];
 #pragma unroll
@@ -248,10 +271,12 @@ __device__ __forceinline__ void mlp_tiles(const MlpFrag &f, const MNT::vec (&bx)
   for (int t = 0; t < 4; t++) {
     const float4 b = cv4[16 + 4 * t], w3 = cv4[32 + 4 * t];
     rx_f32x4 d[NT];
+    const MNT::vec w20 = A2L ? f.a2l[(2 * t) * 64 + a2i] : f.a2[t][0];
+    const MNT::vec w21 = A2L ? f.a2l[(2 * t + 1) * 64 + a2i] : f.a2[t][1];
 #pragma unroll
-    for (int i = 0; i < NT; i++) d[i] = MNT::mfma(f.a2[t][0], bh[i][0], rx_f32x4{b.x, b.y, b.z, b.w});
+    for (int i = 0; i < NT; i++) d[i] = MNT::mfma(w20, bh[i][0], rx_f32x4{b.x, b.y, b.z, b.w});
 #pragma unroll
-    for (int i = 0; i < NT; i++) d[i] = MNT::mfma(f.a2[t][1], bh[i][1], d[i]);
+    for (int i = 0; i < NT; i++) d[i] = MNT::mfma(w21, bh[i][1], d[i]);
 #pragma unroll
     for (int i = 0; i < NT; i++) {
       float v = w3.x * relu_bits(d[i][0]);
@@ -286,8 +311,11 @@ __global__ __launch_bounds__(256) void mlp_infer(RxLaunch L) {
   const int s = J.sc->lag;
   const auto xr = gptr(J.xr);
   __shared__ __attribute__((aligned(16))) float cv[3 * MH];
+  // the W2 fragments in LDS, read per tile pair: held in registers they kept
+  // the kernel at three wavefronts per SIMD
+  __shared__ MNT::vec a2l[8 * 64];
   MlpFrag f;
-  mlp_load_frag(J.mlp, row, kq, cv, f);
+  mlp_load_frag(J.mlp, row, kq, cv, f, a2l);
   const int64_t tile0 = ((int64_t)blockIdx.x * 4 + wv) * TILES_PER_WAVE;
   const int64_t ntl = (nsym - 16 * tile0 + 15) / 16;
   const int nt = ntl < TILES_PER_WAVE ? (int)ntl : TILES_PER_WAVE;   // this wave's tiles (none if <= 0)
@@ -328,7 +356,11 @@ __global__ __launch_bounds__(256) void mlp_infer(RxLaunch L) {
     load_x(tt + 2, xn[0]);
     load_x(tt + 3, xn[1]);
     float y[2];
-    mlp_tiles<2>(f, bx, kq, y);
+    // the fragment index is re-formed each iteration, so the reads are
+    // not hoisted out of the loop into registers
+    int a2i = lane;
+    asm volatile("" : "+v"(a2i));
+    mlp_tiles<2, true>(f, bx, kq, y, a2i);
 #pragma unroll
     for (int i = 0; i < 2; i++) {
       const int64_t k = (tile0 + tt + i) * 16 + row;
