@@ -68,6 +68,43 @@ def test_mixed_batch_equals_single_buffers_and_graph_replays(rx, fronts):
         r.close()
 
 
+def test_kk_batch_of_unequal_buffers_through_the_work_queue(rx):
+    """Eight KK buffers of unequal lengths in one launch group (both formats,
+    lengths multiples of 1024 but not of the front end's block pair): 344
+    work items (eight buffers of the longest one's 43 block pairs), more than
+    the persistent front end's grid holds at once, so workgroups take items
+    from its queue; the 85 items past a shorter buffer's end are skipped.  Each buffer's bits must equal the buffer
+    processed alone, on two eager batches in a row (the queue resets itself
+    between launches) and on graph replays."""
+    import torch
+    lens = [1 << 20, (1 << 20) - 25 * 1024, 600 * 1024, (1 << 19) + 7 * 1024, 1 << 20, 24 * 1024,
+            900 * 1024, (1 << 20) - 1024]
+    fmts = [5, 4, 5, 4, 4, 5, 5, 4]
+    gens = [synth.generate(f, n, 1400 + i, 20.0) for i, (f, n) in enumerate(zip(fmts, lens))]
+    recs = [rx.Receiver(f, g["seed"], max_samples=1 << 20) for f, g in zip(fmts, gens)]
+    bufs = [_dev(g["packed"]) for g in gens]
+    single = [r.process(b, n).cpu().numpy() for r, b, n in zip(recs, bufs, lens)]
+    torch.cuda.synchronize()
+    outs = [torch.zeros(r.bits_bytes(n), dtype=torch.uint8, device="cuda:0") for r, n in zip(recs, lens)]
+    args = ([r.h for r in recs], [b.data_ptr() for b in bufs], lens, [o.data_ptr() for o in outs])
+    for rep in range(2):
+        for o in outs:
+            o.zero_()
+        rx.rx_process_batch(*args, graph=False)
+        torch.cuda.synchronize()
+        for i, (o, s) in enumerate(zip(outs, single)):
+            assert np.array_equal(o.cpu().numpy(), s), f"eager batch {rep}, buffer {i} (n = {lens[i]})"
+    for rep in range(2):
+        for o in outs:
+            o.zero_()
+        rx.rx_process_batch(*args, graph=True)
+        torch.cuda.synchronize()
+        for i, (o, s) in enumerate(zip(outs, single)):
+            assert np.array_equal(o.cpu().numpy(), s), f"graph replay {rep}, buffer {i} (n = {lens[i]})"
+    for r in recs:
+        r.close()
+
+
 def test_batch_rejects_repeated_handle_and_bad_count(rx):
     import torch
     n = 1 << 16
