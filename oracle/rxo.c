@@ -483,8 +483,10 @@ void rxo_farrow(const double *x, int64_t n, const double *delta, double *xr)
 /* ------------------------------------------------------------------ */
 /* Small MLP equaliser: 31 -> 64 ReLU -> 64 ReLU -> 1.                  */
 /* Parameters packed W1[64][31], b1, W2[64][64], b2, W3[64], b3.        */
-/* rounding 1/2: layer-1 and layer-2 operands (inputs, weights, hidden  */
-/* layer-1 activations) rounded to BF16/FP16; biases and layer 3 exact. */
+/* rounding 1/2: the operands of all three layers (inputs, weights,     */
+/* hidden activations) rounded to BF16/FP16, products summed in FP64,   */
+/* biases exact: inference on narrow matrix operands with a wide        */
+/* accumulator throughout.                                              */
 /* ------------------------------------------------------------------ */
 #define H RXO_MLP_H
 #define NI RXO_MLP_IN
@@ -504,7 +506,7 @@ static void mlp_one(const double *p, const double *x, int rm, double *h1, double
     h2[o] = a > 0.0 ? a : 0.0;
   }
   double a = b3[0];
-  for (int i = 0; i < H; i++) a += w3[i] * h2[i];
+  for (int i = 0; i < H; i++) a += rnd(rm, w3[i]) * rnd(rm, h2[i]);
   *y = a;
 }
 

@@ -167,13 +167,19 @@ __global__ __launch_bounds__(256) void mlp_windows(RxLaunch L, float *__restrict
 //            u(ks, kq, jj) = 16 (2 ks + jj / 4) + 4 kq + jj % 4 (W2's columns
 //            permuted to match) and the ReLU'd layer-1 outputs become its B
 //            operand without leaving the registers;
-//   layer 3: y = W3 . H2 + b3 in FP32 (lane partials + two shuffles).
-#define TILES_PER_WAVE 64   // amortises loading the network into registers
+//   layer 3: y = W3 . H2 + b3: 2 MFMA with W3 in row 0 of A (the other
+//            rows zero) and the ReLU'd layer-2 outputs as B in the same K
+//            order, so lane l < 16 receives y of symbol l.
+#define TILES_PER_WAVE 64   // amortises loading the network into registers (training-side rows)
+// the chain's inference: a wavefront's set-up (the network's fragments
+// converted into registers and LDS) is paid once per this many tiles
+#define MLP_INFER_TPW 256
 using MNT = NarrowT<1>;
 
 struct MlpFrag {
   MNT::vec a1[4], a2[4][2];   // A fragments: W1 row tiles, W2 row tiles x 2 K-steps (permuted)
-  const float *cv;            // LDS: b1[64], b2[64], W3[64] (per-unit vectors read per tile)
+  MNT::vec a3[2];             // W3 in row 0 (lanes l % 16 == 0), 2 K-steps in layer 2's order
+  const float *cv;            // LDS: b1[64], b2[64] (the biases, read per tile)
   const MNT::vec *a2l;        // or the W2 fragments in LDS, [t][ks][lane] (then a2 is unused)
   float b3;
 };
@@ -197,6 +203,13 @@ __device__ __forceinline__ void mlp_load_frag(const float *__restrict__ P, int r
         }
       }
     }
+#pragma unroll
+  for (int ks = 0; ks < 2; ks++)
+#pragma unroll
+    for (int jj = 0; jj < 8; jj++) {
+      const int u = 16 * (2 * ks + jj / 4) + 4 * kq + jj % 4;
+      f.a3[ks][jj] = MNT::cvt(row == 0 ? P[OFF_W3 + u] : 0.0f);
+    }
   if (a2l && threadIdx.x < 64) {
 #pragma unroll
     for (int t = 0; t < 4; t++)
@@ -211,8 +224,7 @@ __device__ __forceinline__ void mlp_load_frag(const float *__restrict__ P, int r
         a2l[(2 * t + ks) * 64 + lane] = v;
       }
   }
-  for (int i = threadIdx.x; i < 3 * MH; i += blockDim.x)
-    cv[i] = P[i < MH ? OFF_B1 + i : i < 2 * MH ? OFF_B2 + i - MH : OFF_W3 + i - 2 * MH];
+  for (int i = threadIdx.x; i < 2 * MH; i += blockDim.x) cv[i] = P[i < MH ? OFF_B1 + i : OFF_B2 + i - MH];
   f.cv = cv;
   f.a2l = a2l;
   f.b3 = P[OFF_B3];
@@ -224,12 +236,33 @@ __device__ __forceinline__ void mlp_load_frag(const float *__restrict__ P, int r
 // so max(bits, 0) is max(x, +0) in one integer instruction.
 __device__ __forceinline__ float relu_bits(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
 
+// One K-step of the next layer's B operand from two 16-unit row tiles of
+// this layer's accumulators (lane: units 16 t + 4 kq + j of its symbol, t =
+// 2 ks, 2 ks + 1): each pair rounded to BF16, then ReLU as a packed 16-bit
+// integer max with 0.
+__device__ __forceinline__ void mlp_handover(const rx_f32x4 &da, const rx_f32x4 &db, MNT::vec &out) {
+  typedef short s16x2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+  for (int jp = 0; jp < 4; jp++) {
+    const rx_f32x4 &d = jp < 2 ? da : db;
+    const int j = (2 * jp) % 4;
+    bf16x2 pr = __builtin_convertvector((f32x2){d[j], d[j + 1]}, bf16x2);
+    s16x2 bits = __builtin_bit_cast(s16x2, pr);
+    bits = __builtin_elementwise_max(bits, (s16x2){0, 0});
+    pr = __builtin_bit_cast(bf16x2, bits);
+    out[2 * jp] = pr[0];
+    out[2 * jp + 1] = pr[1];
+  }
+}
+
 // NT tiles of 16 symbols at once (their dependent MFMA -> VALU chains
 // interleave, which one tile's chain alone leaves the SIMD idle waiting
 // on); bx[i] = this lane's B fragment of layer 1 for tile i (window samples
-// 8 kq .. 8 kq + 7 of symbol `row`).  Every lane returns in y[i] the output
-// of symbol `row` of tile i.  Registers, LDS reads of the per-unit vectors
-// and two cross-lane shuffles per tile only.
+// 8 kq .. 8 kq + 7 of symbol `row`).  Lanes with kq == 0 return in y[i]
+// the output of symbol `row` of tile i (the other lanes hold b3).  Registers
+// and LDS reads of the bias vectors only; no cross-lane traffic.
 // A2L: the W2 fragments from LDS (f.a2l) at lane index a2i, read per call.
 template <int NT, bool A2L = false>
 __device__ __forceinline__ void mlp_tiles(const MlpFrag &f, const MNT::vec (&bx)[NT], int kq, float (&y)[NT],
@@ -244,59 +277,38 @@ __device__ __forceinline__ void mlp_tiles(const MlpFrag &f, const MNT::vec (&bx)
   }
   // layer-1 activations: round pairs to BF16, then ReLU as a packed 16-bit
   // integer max with 0 (a BF16 with the sign bit set is a negative int16;
-  // rounding and ReLU commute)
+  // rounding and ReLU commute); the same hand-over takes layer 2's outputs
+  // to layer 3
   MNT::vec bh[NT][2];
 #pragma unroll
   for (int i = 0; i < NT; i++)
 #pragma unroll
-    for (int ks = 0; ks < 2; ks++) {
-      typedef short s16x2 __attribute__((ext_vector_type(2)));
-      typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    for (int ks = 0; ks < 2; ks++) mlp_handover(d1[i][2 * ks], d1[i][2 * ks + 1], bh[i][ks]);
+  // layer 2, two 16-unit row tiles at a time (one K-step of layer 3's B)
+  MNT::vec bh2[NT][2];
 #pragma unroll
-      for (int jp = 0; jp < 4; jp++) {
-        const int t = 2 * ks + (2 * jp) / 4, j = (2 * jp) % 4;
-        typedef float f32x2 __attribute__((ext_vector_type(2)));
-        bf16x2 pr = __builtin_convertvector((f32x2){d1[i][t][j], d1[i][t][j + 1]}, bf16x2);
-        s16x2 bits = __builtin_bit_cast(s16x2, pr);
-        bits = __builtin_elementwise_max(bits, (s16x2){0, 0});
-        pr = __builtin_bit_cast(bf16x2, bits);
-        bh[i][ks][2 * jp] = pr[0];
-        bh[i][ks][2 * jp + 1] = pr[1];
-      }
+  for (int ks = 0; ks < 2; ks++) {
+    rx_f32x4 d[NT][2];
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+      const int t = 2 * ks + h;
+      const float4 b = cv4[16 + 4 * t];
+      const MNT::vec w20 = A2L ? f.a2l[(2 * t) * 64 + a2i] : f.a2[t][0];
+      const MNT::vec w21 = A2L ? f.a2l[(2 * t + 1) * 64 + a2i] : f.a2[t][1];
+#pragma unroll
+      for (int i = 0; i < NT; i++) d[i][h] = MNT::mfma(w20, bh[i][0], rx_f32x4{b.x, b.y, b.z, b.w});
+#pragma unroll
+      for (int i = 0; i < NT; i++) d[i][h] = MNT::mfma(w21, bh[i][1], d[i][h]);
     }
-  // layer 2 and the output layer; each tile's output sum in four partials
-  // (one per 16-unit row tile), so the FMAs do not form one serial chain
-  float yp[NT][4];
 #pragma unroll
-  for (int t = 0; t < 4; t++) {
-    const float4 b = cv4[16 + 4 * t], w3 = cv4[32 + 4 * t];
-    rx_f32x4 d[NT];
-    const MNT::vec w20 = A2L ? f.a2l[(2 * t) * 64 + a2i] : f.a2[t][0];
-    const MNT::vec w21 = A2L ? f.a2l[(2 * t + 1) * 64 + a2i] : f.a2[t][1];
-#pragma unroll
-    for (int i = 0; i < NT; i++) d[i] = MNT::mfma(w20, bh[i][0], rx_f32x4{b.x, b.y, b.z, b.w});
-#pragma unroll
-    for (int i = 0; i < NT; i++) d[i] = MNT::mfma(w21, bh[i][1], d[i]);
-#pragma unroll
-    for (int i = 0; i < NT; i++) {
-      float v = w3.x * relu_bits(d[i][0]);
-      v = fmaf(w3.y, relu_bits(d[i][1]), v);
-      v = fmaf(w3.z, relu_bits(d[i][2]), v);
-      yp[i][t] = fmaf(w3.w, relu_bits(d[i][3]), v);
-    }
+    for (int i = 0; i < NT; i++) mlp_handover(d[i][0], d[i][1], bh2[i][ks]);
   }
-  // lanes l, l ^ 16, l ^ 32 and l ^ 48 hold the partial sums of one symbol:
-  // exchanging 16-lane rows, then 32-lane halves, and adding adds them all
-  // (the swaps move whole rows, so the sum does not depend on which rows of
-  // the two operands the instruction exchanges; one VALU instruction each)
+  // layer 3: lane l < 16 gets y of symbol l in element 0
 #pragma unroll
   for (int i = 0; i < NT; i++) {
-    float v = (yp[i][0] + yp[i][1]) + (yp[i][2] + yp[i][3]);
-    const auto r16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-    v = __uint_as_float(r16[0]) + __uint_as_float(r16[1]);
-    const auto r32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-    v = __uint_as_float(r32[0]) + __uint_as_float(r32[1]);
-    y[i] = v + f.b3;
+    rx_f32x4 o = MNT::mfma(f.a3[0], bh2[i][0], rx_f32x4{0.0f, 0.0f, 0.0f, 0.0f});
+    o = MNT::mfma(f.a3[1], bh2[i][1], o);
+    y[i] = o[0] + f.b3;
   }
 }
 
@@ -310,15 +322,15 @@ __global__ __launch_bounds__(256) void mlp_infer(RxLaunch L) {
   const int row = lane & 15, kq = lane >> 4;
   const int s = J.sc->lag;
   const auto xr = gptr(J.xr);
-  __shared__ __attribute__((aligned(16))) float cv[3 * MH];
+  __shared__ __attribute__((aligned(16))) float cv[2 * MH];
   // the W2 fragments in LDS, read per tile pair: held in registers they kept
   // the kernel at three wavefronts per SIMD
   __shared__ MNT::vec a2l[8 * 64];
   MlpFrag f;
   mlp_load_frag(J.mlp, row, kq, cv, f, a2l);
-  const int64_t tile0 = ((int64_t)blockIdx.x * 4 + wv) * TILES_PER_WAVE;
+  const int64_t tile0 = ((int64_t)blockIdx.x * 4 + wv) * MLP_INFER_TPW;
   const int64_t ntl = (nsym - 16 * tile0 + 15) / 16;
-  const int nt = ntl < TILES_PER_WAVE ? (int)ntl : TILES_PER_WAVE;   // this wave's tiles (none if <= 0)
+  const int nt = ntl < MLP_INFER_TPW ? (int)ntl : MLP_INFER_TPW;   // this wave's tiles (none if <= 0)
   // window sample 8 kq + j of symbol k0 + row: x[2 (k0 + row + s) - 15 + 8 kq + j]
   // = x[w0 + 32 tt + lo + j] with w0 = 2 (16 tile0 + s) - 15 (the wave's first
   // window) and lo = 2 row + 8 kq < 64; the whole tile's window lies in the
@@ -374,7 +386,7 @@ __global__ __launch_bounds__(256) void mlp_infer_rows(const float *__restrict__ 
                                                       int64_t nrows, float *__restrict__ Y) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int row = lane & 15, kq = lane >> 4;
-  __shared__ __attribute__((aligned(16))) float cv[3 * MH];
+  __shared__ __attribute__((aligned(16))) float cv[2 * MH];
   MlpFrag f;
   mlp_load_frag(P, row, kq, cv, f);
   const int64_t tile0 = ((int64_t)blockIdx.x * 4 + wv) * TILES_PER_WAVE;
@@ -423,7 +435,7 @@ void rx_launch_mlp_stage(int stage, const RxLaunch &L, int64_t maxn, hipStream_t
   const int64_t nsym = maxn / 2;
   if (stage == ST_MLP_INFER) {
     const int64_t tiles = (nsym + 15) / 16;
-    const int64_t wgs = (tiles + 4 * TILES_PER_WAVE - 1) / (4 * TILES_PER_WAVE);
+    const int64_t wgs = (tiles + 4 * MLP_INFER_TPW - 1) / (4 * MLP_INFER_TPW);
     hipLaunchKernelGGL(mlp_infer, dim3((unsigned)wgs, cnt), dim3(256), 0, s, L);
   } else if (stage == ST_MLP_JUDGE) {
     hipLaunchKernelGGL(mlp_judge, dim3(1, cnt), dim3(256), 0, s, L);

@@ -405,12 +405,13 @@ def test_mlp_forward_hand_network(oracle_lib):
 
 
 def test_mlp_forward_bf16_hand_network(oracle_lib):
-    """rounding=1 rounds the layer-1 and layer-2 operands to BF16 (inputs,
-    weights, layer-1 activations) and keeps biases and layer 3 exact.  With
-    x = 1 + 2^-8 (a tie: rounds to 1), W1 = 1 + 3 2^-8 (a tie: rounds up to
-    1 + 2^-6) and b1 = 2^-9: h1 = 1 + 2^-6 + 2^-9, which rounds to 1 + 2^-6;
-    W2 = 1 + 2^-9 rounds to 1, b2 = 2^-12 exact: h2 = 1 + 2^-6 + 2^-12;
-    W3 = 1 + 2^-20 and b3 = 2^-30 are applied exactly."""
+    """rounding=1 rounds every layer's operands to BF16 (inputs, weights,
+    hidden activations) and keeps the biases exact.  With x = 1 + 2^-8 (a
+    tie: rounds to 1), W1 = 1 + 3 2^-8 (a tie: rounds up to 1 + 2^-6) and
+    b1 = 2^-9: h1 = 1 + 2^-6 + 2^-9, which rounds to 1 + 2^-6; W2 = 1 + 2^-9
+    rounds to 1, b2 = 2^-12 exact: h2 = 1 + 2^-6 + 2^-12, which rounds to
+    1 + 2^-6 (2^-12 is below half an ulp, 2^-8); W3 = 1 + 2^-20 rounds to 1;
+    b3 = 2^-30 is added exactly."""
     p = np.zeros(oracle_lib_params())
     p[15] = 1 + 3 * 2.0 ** -8                    # W1[0][15]
     p[64 * 31] = 2.0 ** -9                       # b1[0]
@@ -421,17 +422,17 @@ def test_mlp_forward_bf16_hand_network(oracle_lib):
     p[-1] = 2.0 ** -30                           # b3
     x = np.zeros((1, 31))
     x[0, 15] = 1 + 2.0 ** -8
-    h2 = 1 + 2.0 ** -6 + 2.0 ** -12
-    want = h2 * (1 + 2.0 ** -20) + 2.0 ** -30
+    want = (1 + 2.0 ** -6) * 1.0 + 2.0 ** -30
     assert oracle_lib.mlp_forward(p, x, rounding=1)[0] == want
     # unrounded: every term exact in FP64
     h1 = (1 + 3 * 2.0 ** -8) * (1 + 2.0 ** -8) + 2.0 ** -9
     exact = (h1 * (1 + 2.0 ** -9) + 2.0 ** -12) * (1 + 2.0 ** -20) + 2.0 ** -30
     assert oracle_lib.mlp_forward(p, x, rounding=0)[0] == exact
     # FP16 (11 significant bits) holds x, W1 and W2 exactly; h1 = 1 + 2^-6 + 2^-9 + 3 2^-16
-    # rounds to 1 + 2^-6 + 2^-9 (3 2^-16 is below half an ulp, 2^-11)
-    h1_16 = 1 + 2.0 ** -6 + 2.0 ** -9
-    want16 = (h1_16 * (1 + 2.0 ** -9) + 2.0 ** -12) * (1 + 2.0 ** -20) + 2.0 ** -30
+    # rounds to 1 + 2^-6 + 2^-9 (3 2^-16 is below half an ulp, 2^-11); then
+    # h2 = (1 + 2^-6 + 2^-9)(1 + 2^-9) + 2^-12 = 1 + 2^-6 + 2^-8 + 2^-12 + 2^-15 + 2^-18
+    # rounds to 1 + 2^-6 + 2^-8 (the rest is below 2^-11), and W3 rounds to 1
+    want16 = (1 + 2.0 ** -6 + 2.0 ** -8) * 1.0 + 2.0 ** -30
     assert oracle_lib.mlp_forward(p, x, rounding=2)[0] == want16
 
 
