@@ -8,7 +8,7 @@
 #include <map>
 #include <mutex>
 
-#include "rx_dev.hpp"
+#include "fft_lds.hpp"   // rx_dev.hpp and wave_sync
 
 #define MI 31
 #define MH 64
@@ -312,7 +312,9 @@ __device__ __forceinline__ void mlp_tiles(const MlpFrag &f, const MNT::vec (&bx)
   }
 }
 
-__global__ __launch_bounds__(256) void mlp_infer(RxLaunch L) {
+// Five wavefronts per SIMD (at most 102 VGPRs; it needs 88): the loop waits
+// on its LDS and MFMA results, and a fifth wavefront hides more of that.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void mlp_infer(RxLaunch L) {
   const int jb = blockIdx.y;
   const RxJob J = *L.job[jb];
   if (!J.mlp) return;
@@ -331,45 +333,58 @@ __global__ __launch_bounds__(256) void mlp_infer(RxLaunch L) {
   const int64_t tile0 = ((int64_t)blockIdx.x * 4 + wv) * MLP_INFER_TPW;
   const int64_t ntl = (nsym - 16 * tile0 + 15) / 16;
   const int nt = ntl < MLP_INFER_TPW ? (int)ntl : MLP_INFER_TPW;   // this wave's tiles (none if <= 0)
-  // window sample 8 kq + j of symbol k0 + row: x[2 (k0 + row + s) - 15 + 8 kq + j]
+  // Window sample 8 kq + j of symbol k0 + row is x[2 (k0 + row + s) - 15 + 8 kq + j]
   // = x[w0 + 32 tt + lo + j] with w0 = 2 (16 tile0 + s) - 15 (the wave's first
-  // window) and lo = 2 row + 8 kq < 64; the whole tile's window lies in the
-  // buffer when w0 + 32 tt >= 0 and w0 + 32 tt + 61 < n (a scalar test), and
-  // then the tile's reads are one wave-uniform pointer plus small lane
-  // offsets.  The next tile's samples are loaded while this tile runs (past
-  // the wave's last tile too: the test keeps those reads in the buffer).
+  // window) and lo = 2 row + 8 kq < 64.  A step (two tiles, tt and tt + 1)
+  // reads samples w0 + 32 tt + [0, 94): the wave loads 128 of them (two per
+  // lane, one read per sample instead of one per window it falls in),
+  // rounds each pair to BF16 once and parks the pairs in its own LDS
+  // staging area, from which every lane reads its B fragments.  Copy 0
+  // holds pair p (samples 2p, 2p + 1) at dword p, copy 1 at dword p - 1, so
+  // a lane's four dwords p0 = row + 4 kq + 16 i .. p0 + 3 start 8-byte
+  // aligned in copy row & 1.  Two areas alternate by step; the next step's
+  // samples load while a step runs.  Samples outside the buffer read as 0
+  // (only near its ends: a wave-uniform test picks the guarded path).
   const int64_t w0 = 2 * (16 * tile0 + s) - 15;
-  const int lo = 2 * row + 8 * kq;
-  auto load_x = [&](int tt, float xv[8]) {
+  __shared__ __attribute__((aligned(16))) uint32_t xs[4][2][2][64];   // [wave][area][copy][dword]
+  uint32_t(*const xw)[2][64] = xs[wv];
+  auto load_x = [&](int tt, float (&xv)[2]) {
     const int64_t t0 = w0 + 32 * (int64_t)tt;
-    if (t0 >= 0 && t0 + 61 < n) {
+    if (t0 >= 0 && t0 + 127 < n) {
       const auto tp = xr + t0;
-#pragma unroll
-      for (int j = 0; j < 8; j++) xv[j] = tp[lo + j];
+      xv[0] = tp[2 * lane];
+      xv[1] = tp[2 * lane + 1];
     } else {
 #pragma unroll
-      for (int j = 0; j < 8; j++) {
-        const int64_t q = t0 + lo + j;
-        xv[j] = (q >= 0 && q < n) ? xr[q] : 0.0f;
+      for (int e = 0; e < 2; e++) {
+        const int64_t q = t0 + 2 * lane + e;
+        xv[e] = (q >= 0 && q < n) ? xr[q] : 0.0f;
       }
     }
   };
+  auto stage = [&](int area, const float (&xv)[2]) {
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    const uint32_t pr = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){xv[0], xv[1]}, bf16x2));
+    xw[area][0][lane] = pr;
+    xw[area][1][(lane + 63) & 63] = pr;   // lane 0's copy-1 slot (dword 63) is never read
+  };
+  const int rpar = row & 1, p0 = row - rpar + 4 * kq;   // this lane's first dword, even
   // two tiles per step (the second past the wave's last tile is computed on
-  // in-buffer samples and not stored)
-  float xn[2][8];
-  load_x(0, xn[0]);
-  load_x(1, xn[1]);
-  for (int tt = 0; tt < nt; tt += 2) {
+  // in-buffer samples and not stored); the loop takes two steps per
+  // iteration, so the staging area of each is a constant
+  auto step = [&](int tt, int area, float (&xv)[2]) {
     MNT::vec bx[2];
 #pragma unroll
-    for (int i = 0; i < 2; i++)
-#pragma unroll
-      for (int j = 0; j < 8; j++) bx[i][j] = MNT::cvt(8 * kq + j < MI ? xn[i][j] : 0.0f);   // column 31 is padding
-    load_x(tt + 2, xn[0]);
-    load_x(tt + 3, xn[1]);
+    for (int i = 0; i < 2; i++) {
+      const uint2 *src = reinterpret_cast<const uint2 *>(&xw[area][rpar][p0 + 16 * i]);
+      const uint2 u = src[0], v = src[1];
+      bx[i] = __builtin_bit_cast(MNT::vec, (uint4){u.x, u.y, v.x, v.y});
+    }
+    load_x(tt + 2, xv);   // the next step's samples, in flight during this one
     float y[2];
-    // the fragment index is re-formed each iteration, so the reads are
-    // not hoisted out of the loop into registers
+    // the fragment index is re-formed each step, so the reads are not
+    // hoisted out of the loop into registers
     int a2i = lane;
     asm volatile("" : "+v"(a2i));
     mlp_tiles<2, true>(f, bx, kq, y, a2i);
@@ -378,6 +393,22 @@ __global__ __launch_bounds__(256) void mlp_infer(RxLaunch L) {
       const int64_t k = (tile0 + tt + i) * 16 + row;
       if (kq == 0 && tt + i < nt && k < nsym) gptr(reinterpret_cast<float *>(J.soft))[k] = y[i];   // PAM: real soft symbols
     }
+    // the other area takes the next step's pairs; a wavefront's LDS
+    // accesses run in program order, so only the compiler needs the fence
+    stage(area ^ 1, xv);
+    wave_sync();
+  };
+  {
+    float xv[2];
+    load_x(0, xv);
+    stage(0, xv);
+    wave_sync();
+  }
+  float xv[2];
+  for (int tt = 0; tt < nt; tt += 4) {
+    step(tt, 0, xv);
+    if (tt + 2 >= nt) break;
+    step(tt + 2, 1, xv);
   }
 }
 
