@@ -62,7 +62,7 @@ std::vector<double> design_rrc(int k, double sps, double beta) {
 // Hilbert FIR h(m), |m| <= V/2: (2/(pi m)) Blackman(m) for odd m, else 0;
 // returned for m = 1..V/2 (odd symmetric).  Its N-point DFT is -j S[k] with
 // S[k] = 2 sum_{m>0} h(m) sin(2 pi k m / N).
-std::vector<float> design_hilbert_spectrum(int ntaps, int log2n) {
+std::vector<float> design_hilbert_spectrum(int ntaps, int log2n, double scale = 1.0) {
   const int v = ntaps - 1, half = v / 2, n = 1 << log2n;
   std::vector<double> h(half + 1, 0.0);
   for (int m = 1; m <= half; m += 2) {
@@ -75,7 +75,7 @@ std::vector<float> design_hilbert_spectrum(int ntaps, int log2n) {
   for (int k = 0; k < n; k++) {
     double acc = 0.0;
     for (int m = 1; m <= half; m += 2) acc += h[m] * sn[(int)(((int64_t)k * m) % n)];
-    s[k] = (float)(2.0 * acc / n);
+    s[k] = (float)(scale * 2.0 * acc / n);
   }
   return s;
 }
@@ -219,7 +219,10 @@ static const SharedTables *shared_tables(int log2n, int htaps) {
   auto it = cache.find(key);
   if (it != cache.end()) return &it->second;
   const int n = 1 << log2n;
-  std::vector<float> hs = design_hilbert_spectrum(htaps, log2n);
+  // the front end transforms log2 v, not ln sqrt v = (ln 2 / 2) log2 v, and
+  // takes the phase in revolutions: the spectrum carries both factors
+  const double rev = 0.5 * std::log(2.0) / (2.0 * M_PI);
+  std::vector<float> hs = design_hilbert_spectrum(htaps, log2n, rev);
   std::vector<float2> tw = design_twiddles(log2n);
   // the 2^14-point front end runs its transforms as 16 x 1024: behind the
   // N-point twiddles the 1024-point ones, and behind the spectrum a copy in
@@ -232,6 +235,9 @@ static const SharedTables *shared_tables(int log2n, int htaps) {
     for (int k1 = 0; k1 < 16; k1++)
       for (int i = 0; i < 16; i++)
         for (int l = 0; l < 64; l++) hs[n + 1024 * k1 + 64 * i + l] = hs[k1 + 16 * (l + 64 * i)];
+  // then the same 2N entries negated, for the other sideband (sgn = -1)
+  hs.resize(4 * (size_t)n);
+  for (size_t k = 0; k < 2 * (size_t)n; k++) hs[2 * (size_t)n + k] = -hs[k];
   SharedTables t{nullptr, nullptr};
   if (hipMalloc((void **)&t.hspec, hs.size() * sizeof(float)) != hipSuccess) return nullptr;
   if (hipMalloc((void **)&t.twid, tw.size() * sizeof(float2)) != hipSuccess ||
@@ -609,7 +615,8 @@ static int create_tuned(rx_format fmt, double baud, double fs, const rx_params *
     const SharedTables *t = fd ? fd_tables(p.rolloff, true) : shared_tables(h->log2n, p.hilbert_taps);
     ok = t != nullptr;
     if (ok) {
-      J.hspec = t->hspec;
+      // the overlap-save front end's spectrum copy for this sideband
+      J.hspec = t->hspec + (!fd && J.sgn < 0.0f ? 2 * ((size_t)1 << h->log2n) : 0);
       J.twid = t->twid;
     }
     const int64_t nd = L / 2;

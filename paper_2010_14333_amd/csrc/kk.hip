@@ -47,17 +47,17 @@ template <int T> struct HilbertOut {
 
 // Last pass of the second transform: outputs k = q + IOFF T (q = threadIdx.x
 // + i T, i < QPT) are the phases phiA - j phiB of the samples the field stage
-// handles; they stay in registers, in revolutions (sgn / (2 pi) applied).
+// handles; they stay in registers, in revolutions (the spectrum carries
+// sgn / (2 pi)).
 template <int T, int QPT, int IOFF> struct PhaseOut {
   float (&pa)[QPT];
   float (&pb)[QPT];
-  float sgnrev;
   __device__ __forceinline__ void begin() {}
   __device__ __forceinline__ void operator()(int koff, int, float2 v) const {
     const int i = koff / T - IOFF;
     if (i >= 0 && i < QPT) {
-      pa[i] = v.x * sgnrev;
-      pb[i] = -v.y * sgnrev;
+      pa[i] = v.x;
+      pb[i] = -v.y;
     }
   }
 };
@@ -234,6 +234,47 @@ __device__ __forceinline__ void front_take_next(int *nxt, int it, RxScalars *q0)
   if (!FIELD && threadIdx.x == 0) nxt[it & 1] = (int)gridDim.x + (int)atomicAdd(&q0->kk_next, 1u);
 }
 
+// Eight per-lane doubles summed over the wavefront together: lane l returns
+// the sum of variable l / 8.  Each step hands half of what a lane carries to
+// a partner and adds the partner's matching half: across the two 32-lane
+// halves (v[k] and v[k + 4] swapped by permlane32_swap: the low half keeps
+// variable k, the high half k + 4), across pairs of 16-lane rows (the same
+// with permlane16_swap), across the two 8-lane halves of a row (a DPP
+// rotation by 8, one variable left), then within 8 lanes by DPP (partners
+// l ^ 1, l ^ 2 and the half-row mirror).  A swap returns both registers
+// rearranged; only their sum is used, which the order of the pair returned
+// does not change.
+template <bool ROW16>
+__device__ __forceinline__ double swap_sum(double a, double b) {
+  const unsigned long long ua = __builtin_bit_cast(unsigned long long, a), ub = __builtin_bit_cast(unsigned long long, b);
+  const unsigned alo = (unsigned)ua, ahi = (unsigned)(ua >> 32), blo = (unsigned)ub, bhi = (unsigned)(ub >> 32);
+  unsigned lo0, lo1, hi0, hi1;
+  if constexpr (ROW16) {
+    const auto l = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
+    lo0 = l[0]; lo1 = l[1]; hi0 = h[0]; hi1 = h[1];
+  } else {
+    const auto l = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
+    lo0 = l[0]; lo1 = l[1]; hi0 = h[0]; hi1 = h[1];
+  }
+  return __builtin_bit_cast(double, ((unsigned long long)hi0 << 32) | lo0) +
+         __builtin_bit_cast(double, ((unsigned long long)hi1 << 32) | lo1);
+}
+__device__ __forceinline__ double wave_sum8(const double (&v)[8], int lane) {
+  double w[4], u[2];
+#pragma unroll
+  for (int k = 0; k < 4; k++) w[k] = swap_sum<false>(v[k], v[k + 4]);   // row R < 2: k, R >= 2: k + 4
+#pragma unroll
+  for (int k = 0; k < 2; k++) u[k] = swap_sum<true>(w[k], w[k + 2]);    // row R: variable 2 R + k
+  const bool odd = (lane & 8) != 0;   // keeps variable 2 R + 1
+  double r = (odd ? u[1] : u[0]) + dpp_f64<0x128>(odd ? u[0] : u[1]);   // row_ror:8
+  r += dpp_f64<0xB1>(r);    // quad_perm [1, 0, 3, 2]
+  r += dpp_f64<0x4E>(r);    // quad_perm [2, 3, 0, 1]
+  r += dpp_f64<0x141>(r);   // row_half_mirror
+  return r;
+}
+
 template <int LOGN, int PREC, bool FIELD = false>
 __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L, int pmax) {  // 4 waves/SIMD: one 2^14 or two 2^13 workgroups per CU
   constexpr int N = 1 << LOGN, T = N / 16;
@@ -250,7 +291,6 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L, int 
   constexpr int PS = (YPL + 8 * ((YPL - 1) >> 5) - 32 + 127) / 128 * 128 + 32;
   static_assert(PS >= nidx(YPL - 1) + 1 && (PS + QN) * 4 <= 8 * (N + N / 16), "narrow planes and phase stash fit");
   static_assert(4 * PS * 2 <= 8 * (N + N / 16), "the plain form's four planes fit");
-  constexpr float INV2PI = 0.15915494309189535f;
   // 2^14 points: the transforms as 16 x 1024, one 1024-point column per
   // wavefront in its own region of RG = fpad(1024) entries
   constexpr bool FOUR = LOGN == 14;
@@ -294,17 +334,17 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L, int 
     htab[tx] = (i >= 0 && i <= 64) ? J.mf[i] : 0.0f;
   }
 
-  // 1. l - l_ref for both frames (l_ref: the frame's centre sample; the
-  //    Hilbert response is zero at DC, so any offset leaves phi unchanged and
-  //    a small one keeps the FP32 transform accurate).  l = ln(sqrt(v)) =
-  //    (ln 2 / 2) log2(v) with v = code + 0.5 in [0.5, 4095.5], so the
-  //    hardware log2 (1 ulp) needs none of the denormal handling of logf, and
-  //    l - l_ref = (ln 2 / 2)(log2 v - log2 v_ref).
+  // 1. log2 v - log2 v_ref for both frames (v_ref: the frame's centre
+  //    sample; the Hilbert response is zero at DC, so any offset leaves phi
+  //    unchanged and a small one keeps the FP32 transform accurate), with
+  //    v = code + 0.5 in [0.5, 4095.5], so the hardware log2 (1 ulp) needs
+  //    none of the denormal handling of logf.  l = ln(sqrt(v)) is
+  //    (ln 2 / 2) log2 v: the transforms are linear, so that factor (and
+  //    1 / (2 pi) for a phase in revolutions) rides in the spectrum weights.
   //    Taken straight into the first FFT pass (radix 16, no twiddles):
   //    butterfly j = threadIdx.x reads samples j + r T (r < 16), so the thread
   //    reads those codes itself, transforms them in registers and writes the
   //    pass's outputs 16 j + r; the codes never pass through LDS.
-  constexpr float HLN2 = 0.34657359027997264f;   // ln(2) / 2
   // The field stage's samples t = F + EDGE - CMF + q, q = j + i T, are this
   // thread's first-pass samples r = i + IOFF of the same frame: their codes
   // stay in registers (both frames' 12-bit codes packed in one word).
@@ -347,8 +387,8 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L, int 
     float2 v[16];
 #pragma unroll
     for (int r = 0; r < 16; r++)
-      v[r] = make_float2(HLN2 * (__builtin_amdgcn_logf((float)ca[r] + 0.5f) - lr0),
-                         HLN2 * (__builtin_amdgcn_logf((float)cb[r] + 0.5f) - lr1));
+      v[r] = make_float2(__builtin_amdgcn_logf((float)ca[r] + 0.5f) - lr0,
+                         __builtin_amdgcn_logf((float)cb[r] + 0.5f) - lr1);
 #pragma unroll
     for (int i = 0; i < QPT; i++) cpk[i] = ca[i + IOFF] | (cb[i + IOFF] << 16);
     front_take_next<FIELD>(nxt, it, q0);   // its latency overlaps the code reads
@@ -377,9 +417,8 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L, int 
   //    Hilbert products, so they go from one transform to the other in
   //    registers; the barrier only keeps the writes behind every thread's
   //    reads of the last pass.
-  // phase in revolutions: sgn phi / (2 pi); sgn = +-1, so one product by
-  // sgn / (2 pi) is exact against the two
-  const float sgnrev = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, J.sgn * INV2PI)));
+  // the phases come out as sgn phi / (2 pi), in revolutions: the spectrum
+  // weights carry sgn (ln 2 / 2) / (2 pi)
   float ph[2][QPT];   // frames A and B (the narrow forms park B in LDS below)
   if constexpr (FOUR) {
     // 16 x 1024: X[k1 + 16 k2] = sum_j W_1024^(j k2) W_N^(j k1) sum_r x[j + T r]
@@ -434,8 +473,8 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L, int 
     dft16(z);   // z[m1] = output j + T m1
 #pragma unroll
     for (int i = 0; i < QPT; i++) {
-      ph[0][i] = z[i + IOFF].x * sgnrev;
-      ph[1][i] = -z[i + IOFF].y * sgnrev;
+      ph[0][i] = z[i + IOFF].x;
+      ph[1][i] = -z[i + IOFF].y;
     }
   } else {
     {
@@ -452,7 +491,7 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L, int 
     // the first they would be spilled across the Hilbert product
     const float2 *tw2 = J.twid;
     asm volatile("" : "+s"(tw2));
-    fft_passes<N, 16, false>(lds, tw2, PhaseOut<T, QPT, IOFF>{ph[0], ph[1], sgnrev});
+    fft_passes<N, 16, false>(lds, tw2, PhaseOut<T, QPT, IOFF>{ph[0], ph[1]});
   }
   // the phases are formed here: left to itself the compiler moves the last
   // pass's arithmetic into the field stage, where it no longer fits the
@@ -478,10 +517,8 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L, int 
   float2 sp = make_float2(0.0f, 0.0f), sedge = make_float2(0.0f, 0.0f);
   float tedge = 0.0f;
   // interior outputs of the workgroup's two blocks (a count fixed by the
-  // geometry), and whether it has edge outputs (only the buffer's first and
-  // last workgroups): both workgroup-uniform
+  // geometry, workgroup-uniform)
   int nint = 0;
-  bool edge_wg = false;
   const int lane = tid_local() & 63, wv = tid_local() >> 6;
   const int row = lane & 15, kq = lane >> 4;
   constexpr int NW = T / 64;
@@ -537,11 +574,15 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L, int 
       if constexpr (FIELD) {
       } else if constexpr (PREC == 0) {
         // both components converted as one pair (the same rounding as
-        // one at a time)
+        // one at a time); lo = y - hi, exact in FP32, rounded once to FP16
+        // by a mixed-precision FMA (hi as its FP16 operand, -1, y)
         const rx_f32x2 y2 = {yv.x, yv.y};
         const rx_f16x2 hi = __builtin_convertvector(y2, rx_f16x2);
-        const rx_f32x2 back = __builtin_convertvector(hi, rx_f32x2);
-        const rx_f16x2 lo = __builtin_convertvector(rx_f32x2{y2.x - back.x, y2.y - back.y}, rx_f16x2);
+        const unsigned hb = __builtin_bit_cast(unsigned, hi);
+        unsigned lb;
+        asm("v_fma_mixlo_f16 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]" : "=v"(lb) : "v"(hb), "v"(y2.x));
+        asm("v_fma_mixhi_f16 %0, %1, -1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "+v"(lb) : "v"(hb), "v"(y2.y));
+        const rx_f16x2 lo = __builtin_bit_cast(rx_f16x2, lb);
         npl[pq] = hi.x;
         npl[PS + pq] = hi.y;
         npl[2 * PS + pq] = lo.x;
@@ -594,7 +635,6 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L, int 
     const int mil = (int)clamp64(16 - m0, 0, HOP / 2);
     const int mih = (int)clamp64((n - 32) / 2 - m0, 0, HOP / 2);
     nint += mih > mil ? mih - mil : 0;
-    edge_wg = edge_wg || mil > 0 || mih < mlim;
     float2 *const zb = J.z + m0;
     for (int grp = wv; grp < NG; grp += NW) {
       const int tile = grp * 8 + (row >> 1);
@@ -626,35 +666,28 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L, int 
     if (x == 0) __syncthreads();
   }
   if constexpr (!FIELD) {
-  // FP64 workgroup sums: each wavefront's (DPP), then lane k < 9 of the
-  // first wavefront adds variable k over the wavefronts in wavefront order
+  // FP64 workgroup sums of eight variables: each wavefront's at once
+  // (wave_sum8: variable s in lanes 8 s .. 8 s + 7), then lane s < 8 of the
+  // first wavefront adds variable s over the wavefronts in wavefront order
   // and thread 0 collects them; only thread 0 needs them.  The edge sums
   // are zero outside the edge workgroups, the interior count is nint.
-  double v[9] = {se_re, se_im, zz, tedge, 0.0, sp.x, sp.y, sedge.x, sedge.y};
-#pragma unroll
-  for (int k = 0; k < 9; k++) {
-    if (k == 4) continue;
-    if ((k == 3 || k == 7 || k == 8) && !edge_wg) continue;
-    v[k] = wave_sum_dpp(v[k]);
-  }
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < 9; k++) red[k * NW + wv] = v[k];
-  }
+  const double w8[8] = {se_re, se_im, zz, tedge, sp.x, sp.y, sedge.x, sedge.y};
+  const double ws = wave_sum8(w8, lane);
+  if ((lane & 7) == 0) red[(lane >> 3) * NW + wv] = ws;
   __syncthreads();
   if (wv == 0) {
     double sk = 0.0;
-    if (lane < 9)
+    if (lane < 8)
       for (int i = 0; i < NW; i++) sk += red[lane * NW + i];
+    double v[8];
 #pragma unroll
-    for (int k = 0; k < 9; k++) v[k] = __shfl(sk, k);
-    v[4] = (double)nint;
+    for (int k = 0; k < 8; k++) v[k] = __shfl(sk, k);
     if (lane == 0) {
       const double c0r = J.c0.x, c0i = J.c0.y;
       J.part[3 * pidx] = make_double2(v[0], v[1]);                          // sum of the field E
-      J.part[3 * pidx + 1] = make_double2(v[2], v[3] + v[4] * (c0r * c0r + c0i * c0i));  // |Z|^2, |T|^2
-      J.part[3 * pidx + 2] = make_double2(c0r * v[5] + c0i * v[6] + v[7],    // sum Z conj(T)
-                                          c0r * v[6] - c0i * v[5] + v[8]);
+      J.part[3 * pidx + 1] = make_double2(v[2], v[3] + (double)nint * (c0r * c0r + c0i * c0i));  // |Z|^2, |T|^2
+      J.part[3 * pidx + 2] = make_double2(c0r * v[4] + c0i * v[5] + v[6],    // sum Z conj(T)
+                                          c0r * v[5] - c0i * v[4] + v[7]);
     }
   }
   }

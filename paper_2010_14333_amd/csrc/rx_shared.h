@@ -45,8 +45,9 @@ struct RxJob {
   uint64_t seed;
   float2 c0;                        // interior value of MF(exp(-j 2 pi r n)) / exp(-j 2 pi r 2m)
   const float *mf;                  // matched filter taps (65 centred for KK, 33 for PAM)
-  const float *hspec;               // KK: Hilbert spectrum S[k]/N (H = -j S), N entries, then (N = 2^14) the
-                                    //   same in the 16 x 1024 transform's order, N entries
+  const float *hspec;               // KK: Hilbert spectrum sgn S[k] c / N (H = -j S; c = (ln 2 / 2) / (2 pi):
+                                    //   the transforms take log2 v and give the phase in revolutions), N
+                                    //   entries, then (N = 2^14) the same in the 16 x 1024 transform's order
   const float2 *twid;               // KK: exp(-j 2 pi k / N), N entries, then exp(-j 2 pi k / 1024), 1024
   float2 *z;                        // KK: MF output / carrier-free field at 2 sps [n/2]
   float *y;                         // PAM: MF output [n]

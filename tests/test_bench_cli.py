@@ -57,6 +57,6 @@ def test_traffic_figure_survives_comments_not_code(tmp_path, monkeypatch):
     text = kk.read_text()
     kk.write_text("// a note for readers\n" + text.replace("\n\n", "\n\n/* and another */\n", 1))
     assert bench.front_traffic(64) is not None
-    assert "constexpr float HLN2 = 0.34657359027997264f;" in text
-    kk.write_text(text.replace("constexpr float HLN2 = 0.34657359027997264f;", "constexpr float HLN2 = 0.3465736f;"))
+    assert "constexpr int RG = fpad(1024);" in text
+    kk.write_text(text.replace("constexpr int RG = fpad(1024);", "constexpr int RG = fpad(1024) + 2;"))
     assert bench.front_traffic(64) is None
