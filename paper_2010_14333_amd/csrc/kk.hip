@@ -539,13 +539,17 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L, int 
     const int qlo = (int)clamp64(-nq0, 0, QN), qhi = (int)clamp64(n - nq0, 0, QN);   // t in [0, n)
     // interior frames (all samples inside the buffer: every block pair but
     // a buffer's first and last) skip the range masks
-    const bool inner = qlo == 0 && qhi == QN;
+    const bool inner = __builtin_amdgcn_readfirstlane((int)(qlo == 0 && qhi == QN)) != 0;
     const int tx = tid_local();
     float2 dph = cis_rev(-downshift_rev(J.r, g0 + nq0 + tx));
     float2 *const fbase = J.field + nq0;   // FIELD only
     // plane index of q = tx + i T: nidx(tx) + nidx(i T), T a multiple of 32
     static_assert(T % 32 == 0, "plane offsets split");
     const int nq = nidx(tx);
+    // the LDS offset field holds 16 bits: the two lo planes take bases of
+    // their own, formed once, with the sample's offset as the immediate
+    int nq2 = nq + 2 * PS, nq3 = nq + 3 * PS;
+    asm volatile("" : "+v"(nq2), "+v"(nq3));
 #pragma unroll
     for (int i = 0; i < QPT; i++) {
       const int q = tx + i * T;   // < QN: QN is a multiple of T
@@ -585,8 +589,8 @@ __global__ __launch_bounds__((1 << LOGN) / 16, 4) void kk_front(RxLaunch L, int 
         const rx_f16x2 lo = __builtin_bit_cast(rx_f16x2, lb);
         npl[pq] = hi.x;
         npl[PS + pq] = hi.y;
-        npl[2 * PS + pq] = lo.x;
-        npl[3 * PS + pq] = lo.y;
+        npl[nq2 + nidx(i * T)] = lo.x;
+        npl[nq3 + nidx(i * T)] = lo.y;
       } else {
         npl[pq] = NarrowT<PREC == 0 ? 1 : PREC>::cvt(yv.x);
         npl[PS + pq] = NarrowT<PREC == 0 ? 1 : PREC>::cvt(yv.y);
