@@ -181,15 +181,16 @@ def test_mlp_stage_in_chain(rx, kind):
         assert not dec.untolerated and abs(e["bit_errors"] - o["bit_errors"]) <= dec.tolerated_bits
 
 
-def test_mlp_stage_dense_window_in_chain(rx):
+@pytest.mark.parametrize("n", [1 << 18, (1 << 18) + 3 * 1024])
+def test_mlp_stage_dense_window_in_chain(rx, n):
     """Every window column counts: the linear network plus small seeded
     weights on all 31 inputs.  The chain's MLP outputs are checked against
     the oracle's forward pass on the windows the chain itself formed (its
     timing-corrected samples x and symbol delay s: window i of symbol k is
     x[2 (k + s) - 15 + i], zero outside the buffer), which pins the kernel's
     window indexing and tile bookkeeping (first, interior and last tiles,
-    including the buffer edges) independently of the upstream rounding."""
-    n = 1 << 18
+    including the buffer edges) independently of the upstream rounding.
+    The ragged length leaves the last wavefront 96 of its 256 tiles."""
     g = synth.generate(synth.PAM8, n, 913, None, drive=0.1)
     p = _linear_net()
     p[:64 * 31] += 1e-3 * np.random.default_rng(17).standard_normal(64 * 31)
