@@ -361,7 +361,10 @@ int rx_mlp_grad(rx_handle h, const float *dev_x, const float *dev_t, size_t n, f
 int rx_mlp_grad_static(rx_handle h, const float *dev_x, const float *dev_t, size_t n, float *dev_grad,
                        double *loss);
 /* BF16 MFMA inference (the kernel of the chain's MLP stage) on given rows:
- * dev_x = n rows of 32 floats, dev_y = n outputs.  Asynchronous. */
+ * dev_x = n rows of 32 floats (column 31 ignored), dev_y = n outputs.  All
+ * three layers' operands (inputs, weights, ReLU'd hidden activations) are
+ * rounded to BF16 and their products summed in FP32; biases are added in
+ * FP32.  Asynchronous. */
 int rx_mlp_infer(rx_handle h, const float *dev_x, size_t n, float *dev_y);
 /* Copy weights in/out (host memory), or to/from a file ("RXMLP001", uint32
  * count, float32 little-endian). */
